@@ -1,0 +1,197 @@
+#!/usr/bin/env python
+"""Benchmark: RVE homogenisations per second on one MI355X.
+
+Workload (default "c1"): the synthetic plain-weave RVE on a 24^3 Kuhn lattice
+(82,944 tets), order-2 hierarchic basis (352,947 elastic DOFs), homogenised
+under each of the three boundary conditions (linear Dirichlet, periodic,
+uniform traction), 6 mechanical + 3 thermal + 3 moisture load cases each,
+FP32 operator with FP64 CG reductions, constraint projection, refinement
+residual and volume average.  One step = the three homogenisations.  The mesh,
+tags and element data are resident on the GPU before timing starts.
+
+Also reported (outside the timed region):
+  * the error of the timed results against the FP64 GPU path on the same RVE
+    (the FP64 path is checked against the CPU oracle at smaller sizes by tests);
+  * the roofline record of the dominant kernel (the FP32 mechanical operator):
+    HIP-event timing of its launches, algorithmic bytes/flops per launch;
+  * the CPU oracle timed on the host on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
+FP32_VEC_PEAK = 157.3e12   # flop/s, MI355X FP32 vector (published)
+FP64_VEC_PEAK = 78.6e12
+
+WORKLOADS = {
+    "c1": dict(n=24, bcs=("dirichlet", "periodic", "neumann"), precision="fp32_refined",
+               desc="24^3 Kuhn plain-weave RVE (82,944 tets), p=2 (352,947 elastic DOFs), "
+                    "Dirichlet+periodic+Neumann, 6+3+3 load cases each, FP32 operator + FP64 refinement"),
+    "c0": dict(n=8, bcs=("dirichlet",), precision="fp64",
+               desc="8^3 Kuhn plain-weave RVE (3,072 tets), p=2, linear Dirichlet, 6+3+3 load cases, FP64"),
+}
+
+
+def algorithmic_mech(n, nprob, fp32):
+    """Bytes and flops of one mechanical operator launch (6 load cases) per the
+    survey's definition: bytes = sum_RHS 2 ndof s + T (conn + n_A s),
+    flops = T n_RHS 2 n_e^2, with conn = 40 B, n_A = 45, n_e = 30 at p = 2."""
+    s = 4 if fp32 else 8
+    T = 6 * n ** 3
+    ndof = 3 * (2 * n + 1) ** 3
+    bytes_ = 6 * 2 * ndof * s + T * (40 + 45 * s)
+    flops = T * 6 * 2 * 30 ** 2
+    return bytes_ * nprob, flops * nprob
+
+
+CPU_SAMPLE_CODE = r"""
+import sys, time, json
+sys.path.insert(0, {root!r})
+import chom_inputs as ci
+from oracle import fem, mesh
+n = {n}
+params = ci.draw_factors_only(0, 1)[0]
+c, t, ph, ax = mesh.plain_weave(n)
+t0 = time.perf_counter()
+count = 0
+for bc in (fem.BC_DIRICHLET, fem.BC_PERIODIC, fem.BC_NEUMANN):
+    fem.homogenise(c, t, ph, ax, 2, bc, ci.BASE_MATERIALS, params)
+    count += 1
+dt = time.perf_counter() - t0
+print(json.dumps(dict(count=count, seconds=dt)))
+"""
+
+
+def cpu_baseline(n_sample=8):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               CUDA_VISIBLE_DEVICES="", HIP_VISIBLE_DEVICES="")
+    code = CPU_SAMPLE_CODE.format(root=ROOT, n=n_sample)
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if res.returncode != 0:
+        return None
+    rec = json.loads(res.stdout.strip().splitlines()[-1])
+    return dict(value=rec["count"] / rec["seconds"], unit="homogenisations/s", cores=1, kind="oracle",
+                sample=(f"CPU FP64 oracle (Lagrange P2, SuperLU saddle point, factorised once per BC and "
+                        f"physics) on the {n_sample}^3 plain-weave RVE, Dirichlet+periodic+Neumann x 12 load "
+                        f"cases = {rec['count']} homogenisations in {rec['seconds']:.1f} s on 1 thread; the "
+                        f"24^3 RVE is not run (about 40 min per mechanical factorisation), so this rate "
+                        f"overstates the oracle's rate on the benchmark RVE"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--op-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (the RVE batches shard across GPUs without "
+              f"communication, but no multi-GPU path is built); got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import chom_inputs as ci
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+
+    if not torch.cuda.is_available():
+        print("bench.py: needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    wl = WORKLOADS[args.workload]
+    n = wl["n"]
+    params = ci.draw_factors_only(0, 1)
+    mesh = generate_plain_weave(n, device="cuda:0")
+    rves = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision=wl["precision"], rtol=1e-10, max_iter=50000)
+            for bc in wl["bcs"]]
+
+    def step():
+        out = []
+        for r in rves:
+            out.append(r.homogenise(params))
+        return out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    homs = len(rves) * args.steps
+    value = homs / dt
+    for bc, (C, K, D, rep) in zip(wl["bcs"], res):
+        print(f"[bench] {bc}: iters={rep[0]['iters']} refine={rep[0]['refine_steps']} "
+              f"resid_max={max(rep[0]['resid']):.1e} asym={rep[0]['asym']:.1e}", file=sys.stderr)
+
+    # accuracy against the FP64 GPU path (same RVE, same parameters)
+    err = None
+    if not args.no_accuracy and wl["precision"] != "fp64":
+        errs = []
+        for bc, (C, K, D, _) in zip(wl["bcs"], res):
+            ref = RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision="fp64", rtol=1e-12, max_iter=50000)
+            Cr, Kr, Dr, _ = ref.homogenise(params)
+            errs.append(max(np.linalg.norm(C - Cr) / np.linalg.norm(Cr), np.linalg.norm(K - Kr) / np.linalg.norm(Kr),
+                            np.linalg.norm(D - Dr) / np.linalg.norm(Dr)))
+            ref.close()
+        err = float(max(errs))
+
+    # dominant kernel: the mechanical operator of the first (full-lattice) RVE
+    ms, tets, nprob = rves[0].time_operator(0, args.op_reps)
+    fp32 = wl["precision"] != "fp64"
+    bytes_, flops = algorithmic_mech(n, nprob, fp32)
+    t = ms * 1e-3
+    peak_alu = FP32_VEC_PEAK if fp32 else FP64_VEC_PEAK
+    t_hbm, t_alu = bytes_ / HBM_PEAK, flops / peak_alu
+    if t_alu >= t_hbm:
+        roof = dict(bound="alu", achieved=flops / t / 1e12, peak=peak_alu / 1e12, unit="TFLOP/s",
+                    frac=(flops / t) / peak_alu, traffic=None)
+    else:
+        roof = dict(bound="hbm", achieved=bytes_ / t / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=(bytes_ / t) / HBM_PEAK, traffic=None)
+    roof.update(kernel=("op_p2_kernel<float,3,6>" if fp32 else "op_p2_kernel<double,3,6>"),
+                avg_launch_us=ms * 1e3, algorithmic_bytes=bytes_, algorithmic_flops=flops)
+    print(f"[bench] operator: {ms * 1e3:.1f} us/launch, {bytes_ / t / 1e9:.0f} GB/s algorithmic, "
+          f"{flops / t / 1e12:.2f} TFLOP/s algorithmic", file=sys.stderr)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    line = {
+        "metric": "RVE homogenisations/s (12 load cases) @ stated C_hom error",
+        "value": value,
+        "unit": "homogenisations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if fp32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "path": "plain", "rves_per_step": len(rves),
+                   "c_hom_rel_err_vs_fp64_gpu": err},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

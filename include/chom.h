@@ -1,0 +1,218 @@
+/*
+ * chom.h -- C ABI of the MI355X RVE computational-homogenisation library.
+ *
+ * The library computes, for a representative volume element (RVE) of a
+ * plain-weave composite, the homogenised stiffness C_bar (6x6), conductivity
+ * K_bar (3x3) and diffusivity D_bar (3x3) of first-order computational
+ * homogenisation (paper Sec. 2): for each unit macro strain (6 load cases,
+ * Eq. Eq_C_stress) and each unit macro gradient of temperature and moisture
+ * (3 + 3 load cases, Eqs. eq_RVE_disc_Eqs_field, eq_homo_flux) it solves the
+ * micro equilibrium problem (Eq. RVE_Eq_var_final) on the RVE under linear
+ * Dirichlet, periodic or uniform-traction (Neumann) constraints (Sec. 2,
+ * items 1-3; Eqs. eq_RVE_disc_Eqs, eq_mat_C_and_D) and volume-averages the
+ * micro stress / flux (Eq. macro_stress).  Matrix stiffness is degraded with
+ * the temperature-moisture-time law of Sec. 4 (Eq. Eq_Model_final1), applied
+ * to the matrix only (Sec. 5).
+ *
+ * Conventions
+ *   - Every function returns an int status (CHOM_OK = 0 or a negative code).
+ *     No exception crosses the ABI.  chom_last_error() gives a message for the
+ *     last failing call on the calling thread.
+ *   - Voigt order [11, 22, 33, 12, 23, 31], strains with engineering shear
+ *     (paper Sec. 2, definition of the macro-strain vector); stresses without.
+ *   - C_hom is returned as its 21 upper-triangle entries, row-major
+ *     (C[0][0], C[0][1], ..., C[0][5], C[1][1], ...), where column j of the
+ *     unsymmetrised C_bar is the homogenised stress of unit strain j.
+ *     K_hom and D_hom are returned as [xx, yy, zz, xy, yz, xz] of the upper
+ *     triangle.  Units pass through (moduli in the units of the inputs).
+ *   - Inputs are borrowed for the duration of the call and copied; handles are
+ *     owned by the caller and released with the matching *_destroy.  Output
+ *     buffers are allocated by the caller.
+ *   - Pointers are host pointers unless a flag says they are device pointers
+ *     (chom_mesh.on_device, chom_options.device_ptrs).  Device pointers must be
+ *     on the current HIP device.  Work is queued on chom_options.hip_stream (or
+ *     the null stream); chom_homogenise returns after the results are written.
+ */
+#ifndef CHOM_H
+#define CHOM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+enum {
+    CHOM_OK = 0,
+    CHOM_EINVAL = -1,     /* bad argument (null pointer, size, option)            */
+    CHOM_EMESH = -2,      /* mesh not a supported lattice, or degenerate tet       */
+    CHOM_EMATERIAL = -3,  /* material not positive definite after factors/damage  */
+    CHOM_ENOCONV = -4,    /* results written, some load case did not converge     */
+    CHOM_EDEVICE = -5,    /* HIP runtime error or no device                        */
+    CHOM_ENOMEM = -6      /* device allocation failed                              */
+};
+
+enum { CHOM_BC_DIRICHLET = 0, CHOM_BC_PERIODIC = 1, CHOM_BC_NEUMANN = 2 };
+enum { CHOM_FP64 = 0, CHOM_FP32_REFINED = 1 };
+enum { CHOM_PRECOND_BLOCK_JACOBI = 0 };
+
+typedef struct chom_rve chom_rve;
+
+/* RVE mesh.  Supported meshes: the Kuhn split of an n x n x n cell grid of the
+ * box [lo, hi] -- (n+1)^3 vertices numbered i + (n+1)(j + (n+1)k), 6 n^3 tets,
+ * cell-major, the six tets of a cell in the axis-permutation order
+ * (0,1,2),(0,2,1),(1,0,2),(1,2,0),(2,0,1),(2,1,0), each tet
+ * (v0, v0+e_a, v0+e_a+e_b, v0+(1,1,1)) in any vertex order.  Vertex
+ * coordinates may be moved (distorted meshes) as long as every tet keeps the
+ * orientation of its undistorted shape and boundary vertices stay on their
+ * faces; periodic BCs additionally need matching opposite faces.  Other meshes
+ * are rejected with CHOM_EMESH.
+ * phase: 0 = matrix, 1..4 = yarn; fibre_axis: unit vector per tet (ignored
+ * for matrix tets). */
+typedef struct {
+    int32_t n_vertices;
+    int32_t n_tets;
+    const double *coords;      /* [n_vertices][3]                        */
+    const int32_t *tets;       /* [n_tets][4]                            */
+    const int8_t *phase;       /* [n_tets]                               */
+    const double *fibre_axis;  /* [n_tets][3]                            */
+    double lo[3], hi[3];
+    int32_t on_device;         /* 1: the four arrays are device pointers */
+} chom_mesh;
+
+/* Base constituent properties.  Matrix: isotropic (E, nu), conductivity k,
+ * diffusivity D.  Yarn: transversely isotropic about the fibre axis: E1 along
+ * the fibre, E2 = E3 across, G12 = G13, major Poisson ratio nu12
+ * (S12 = -nu12/E1), nu23 with G23 = E2 / (2 (1 + nu23)); conductivity and
+ * diffusivity k1, D1 along and k2, D2 across the fibre. */
+typedef struct {
+    double E, nu, k, D;
+    double E1, E2, G12, nu12, nu23, k1, k2, D1, D2;
+} chom_materials;
+
+/* One macro Gauss point: exposure temperature (deg C), moisture (wt%),
+ * exposure time (years) and eight property factors multiplying the groups
+ * matrix {E}, {nu}, {k}, {D}, yarn {E1, E2, G12}, {nu12, nu23}, {k1, k2},
+ * {D1, D2}.  The matrix modulus is further multiplied by
+ * (1 - omega) = exp(-gamma(c) alpha(T) t): alpha(T) = beta ln(1 - T/T_g) with
+ * absolute temperatures, beta = -0.001682 per day, T_g = 126 C (Sec. 4, Eqs.
+ * Eq_alphaT, Eq_alphaT_LSF), gamma(c) = c / c_sat (Eq. Eq_Model3), t in days
+ * (365.25 per year). */
+typedef struct {
+    double T_celsius, c_wt, t_years, factor[8];
+} chom_params;
+
+typedef struct {
+    int32_t precision;     /* CHOM_FP64 or CHOM_FP32_REFINED                           */
+    int32_t precond;       /* CHOM_PRECOND_BLOCK_JACOBI                                */
+    int32_t max_iter;      /* CG iteration cap per solve (per inner solve when refined) */
+    int32_t max_refine;    /* refinement steps cap (CHOM_FP32_REFINED)                 */
+    double rtol;           /* stop when r.M^-1 r <= rtol^2 * (linear-field energy)    */
+    double inner_rtol;     /* FP32 inner solves: reduce r.M^-1 r by inner_rtol^2       */
+    double c_sat;          /* moisture content (wt%) with gamma = 1                    */
+    int32_t degrade_yarn;  /* 1: the damage factor also scales the yarn moduli         */
+    int32_t device_ptrs;   /* 1: params and outputs of chom_homogenise are on device  */
+    void *hip_stream;      /* hipStream_t to queue work on (NULL: null stream)        */
+} chom_options;
+
+typedef struct {
+    int32_t iters[12];        /* CG iterations per load case: 6 mech, 3 thermal, 3 moisture */
+    int32_t refine_steps[3];  /* refinement steps (mech, thermal, moisture)                 */
+    int32_t status;           /* CHOM_OK or CHOM_ENOCONV                                    */
+    double resid[12];         /* final sqrt(r.M^-1 r / linear-field energy) per load case    */
+    double asym;              /* ||C - C^T||_F / ||C||_F of the unsymmetrised C_bar           */
+    double omega_keep;        /* (1 - omega) applied to the matrix modulus                   */
+} chom_report;
+
+/* Fill *opt with defaults: FP64, block Jacobi, max_iter 20000, max_refine 30,
+ * rtol 1e-12, inner_rtol 1e-4, c_sat 1.5, no yarn damage, host pointers,
+ * null stream.  Always succeeds for non-null opt. */
+int chom_default_options(chom_options *opt);
+
+/* Sizes of the n x n x n plain-weave mesh: (n+1)^3 vertices, 6 n^3 tets.
+ * Errors: CHOM_EINVAL for n < 1 or n > 1024 or null outputs. */
+int chom_mesh_sizes(int32_t n, int32_t *n_vertices, int32_t *n_tets);
+
+/* Generate the synthetic plain-weave RVE on the GPU into caller-allocated
+ * device buffers (sizes from chom_mesh_sizes) on the unit cube: the Kuhn
+ * lattice above, coordinates i/n, and the yarn tags.  A tet is yarn j if its
+ * centroid lies in yarn j's elliptical section (semi-axes 0.2 in-plane, 0.06
+ * in z), first hit wins in the order warp y=0.25, warp y=0.75, weft x=0.25,
+ * weft x=0.75; warp centrelines z = 0.5 + 0.12 sin(2 pi x + phi), weft
+ * z = 0.5 - 0.12 sin(2 pi y + phi), phi = 0, pi.  The fibre axis is the unit
+ * centreline tangent at the centroid's abscissa, zero for matrix tets.  The
+ * paper models elliptical yarn sections on spline paths (Sec. 1, Table 1);
+ * this analytic weave is the synthetic workload geometry.
+ * Errors: CHOM_EINVAL (n out of range, null buffer), CHOM_EDEVICE. */
+int chom_generate_plain_weave(int32_t n, double *coords, int32_t *tets, int8_t *phase,
+                              double *fibre_axis, void *hip_stream);
+
+/* Create an RVE handle: copies the mesh to the device, checks it (CHOM_EMESH),
+ * tabulates the order-p hierarchic basis (p = 2 supported), precomputes
+ * element geometry and the constraint rows of bc_type.  opt may be NULL
+ * (defaults).  *out receives a caller-owned handle.  Errors: CHOM_EINVAL,
+ * CHOM_EMESH, CHOM_EDEVICE, CHOM_ENOMEM. */
+int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc_type,
+                    int32_t order, const chom_options *opt, chom_rve **out);
+
+/* Homogenise the RVE for `batch` parameter records: 6 mechanical + 3 thermal
+ * + 3 moisture load cases each.  Outputs: C_hom [batch][21], K_hom [batch][6],
+ * D_hom [batch][6], rep [batch] (rep may be NULL; rep is always host memory).
+ * Returns CHOM_ENOCONV (results written, rep.status set) if a load case hit the
+ * iteration cap, CHOM_EMATERIAL if a record gives a non-positive-definite
+ * material, CHOM_EINVAL / CHOM_EDEVICE / CHOM_ENOMEM otherwise. */
+int chom_homogenise(chom_rve *rve, const chom_params *params, int32_t batch,
+                    double *C_hom, double *K_hom, double *D_hom, chom_report *rep);
+
+/* Time the matrix-free operator kernel that chom_homogenise launches for
+ * `physics` (0: mechanical, 6 load cases; 1: thermal + moisture, 3 load cases
+ * each) at the handle's precision (FP32 operator when CHOM_FP32_REFINED):
+ * `reps` back-to-back launches with the same grid and problem table as the last
+ * chom_homogenise call, on the handle's stream, between two HIP events; the
+ * operands are that call's workspace vectors (their contents are overwritten).
+ * Outputs: average milliseconds per launch, tets processed per launch (tets x
+ * problems) and problems per launch (either pointer may be NULL).
+ * Errors: CHOM_EINVAL (no prior chom_homogenise, bad argument), CHOM_EDEVICE. */
+int chom_time_operator(chom_rve *rve, int32_t physics, int32_t reps, double *ms_per_launch,
+                       int64_t *tets_per_launch, int32_t *problems_per_launch);
+
+/* Release a handle (NULL is ignored). */
+void chom_rve_destroy(chom_rve *rve);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *chom_last_error(void);
+
+/* ---------------------------------------------------------------- host-only helpers
+ * These run on the CPU and need no GPU; they expose the library's own host
+ * arithmetic for inspection. */
+
+/* Material constants of one record as used by the kernels.  out_mech[10]:
+ * per phase (matrix, yarn) the five transversely isotropic invariants
+ * (lambda, mu_T, alpha, mu_L - mu_T, beta) of
+ *   sigma = lambda tr(e) I + 2 mu_T e + alpha ((a.e.a) I + tr(e) A)
+ *         + 2 (mu_L - mu_T)(A e + e A) + beta (a.e.a) A,   A = a a^T;
+ * out_therm[4], out_moist[4]: per phase (k_T, k_L - k_T) of k_T I + (k_L - k_T) A;
+ * *omega_keep: the matrix damage factor.  params may be NULL (no factors, no
+ * damage).  Errors: CHOM_EINVAL, CHOM_EMATERIAL. */
+int chom_material_constants(const chom_materials *mat, const chom_params *params, double c_sat,
+                            int32_t degrade_yarn, double *out_mech, double *out_therm,
+                            double *out_moist, double *omega_keep);
+
+/* One element of the order-2 operator evaluated on the host with the same code
+ * the kernels run: y = K_e u for a tet with barycentric-coordinate gradients
+ * grad_lam [4][3], volume vol, fibre axis [3] and the five invariants inv5 of
+ * chom_material_constants (ncomp = 3; for ncomp = 1 inv5[0..1] = (k_T, k_L - k_T)).
+ * u, y: [10][ncomp], DOFs ordered vertices 0..3 then edges (01, 02, 03, 12,
+ * 13, 23); vertex functions lam_a, edge functions 4 lam_a lam_b.
+ * Errors: CHOM_EINVAL. */
+int chom_element_apply_host(int32_t ncomp, const double *grad_lam, double vol, const double *axis,
+                            const double *inv5, const double *u, double *y);
+
+/* Library version string. */
+const char *chom_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHOM_H */

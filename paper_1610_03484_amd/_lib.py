@@ -1,0 +1,100 @@
+"""ctypes view of include/chom.h (argument marshalling only).
+
+Loading fails loudly when libchom.so has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libchom.so")
+
+CHOM_OK, CHOM_EINVAL, CHOM_EMESH, CHOM_EMATERIAL, CHOM_ENOCONV, CHOM_EDEVICE, CHOM_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "CHOM_OK", -1: "CHOM_EINVAL", -2: "CHOM_EMESH", -3: "CHOM_EMATERIAL",
+                -4: "CHOM_ENOCONV", -5: "CHOM_EDEVICE", -6: "CHOM_ENOMEM"}
+BC = {"dirichlet": 0, "periodic": 1, "neumann": 2}
+PRECISION = {"fp64": 0, "fp32_refined": 1}
+
+
+class ChomMesh(ct.Structure):
+    _fields_ = [("n_vertices", ct.c_int32), ("n_tets", ct.c_int32),
+                ("coords", ct.c_void_p), ("tets", ct.c_void_p), ("phase", ct.c_void_p),
+                ("fibre_axis", ct.c_void_p), ("lo", ct.c_double * 3), ("hi", ct.c_double * 3),
+                ("on_device", ct.c_int32)]
+
+
+class ChomMaterials(ct.Structure):
+    _fields_ = [(k, ct.c_double) for k in
+                ("E", "nu", "k", "D", "E1", "E2", "G12", "nu12", "nu23", "k1", "k2", "D1", "D2")]
+
+
+class ChomParams(ct.Structure):
+    _fields_ = [("T_celsius", ct.c_double), ("c_wt", ct.c_double), ("t_years", ct.c_double),
+                ("factor", ct.c_double * 8)]
+
+
+class ChomOptions(ct.Structure):
+    _fields_ = [("precision", ct.c_int32), ("precond", ct.c_int32), ("max_iter", ct.c_int32),
+                ("max_refine", ct.c_int32), ("rtol", ct.c_double), ("inner_rtol", ct.c_double),
+                ("c_sat", ct.c_double), ("degrade_yarn", ct.c_int32), ("device_ptrs", ct.c_int32),
+                ("hip_stream", ct.c_void_p)]
+
+
+class ChomReport(ct.Structure):
+    _fields_ = [("iters", ct.c_int32 * 12), ("refine_steps", ct.c_int32 * 3), ("status", ct.c_int32),
+                ("resid", ct.c_double * 12), ("asym", ct.c_double), ("omega_keep", ct.c_double)]
+
+
+# every exported symbol of include/chom.h with its ctypes signature
+SIGNATURES = {
+    "chom_default_options": (ct.c_int, [ct.POINTER(ChomOptions)]),
+    "chom_mesh_sizes": (ct.c_int, [ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]),
+    "chom_generate_plain_weave": (ct.c_int, [ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                             ct.c_void_p]),
+    "chom_rve_create": (ct.c_int, [ct.POINTER(ChomMesh), ct.POINTER(ChomMaterials), ct.c_int32, ct.c_int32,
+                                   ct.POINTER(ChomOptions), ct.POINTER(ct.c_void_p)]),
+    "chom_homogenise": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                   ct.POINTER(ChomReport)]),
+    "chom_rve_destroy": (None, [ct.c_void_p]),
+    "chom_last_error": (ct.c_char_p, []),
+    "chom_material_constants": (ct.c_int, [ct.POINTER(ChomMaterials), ct.POINTER(ChomParams), ct.c_double,
+                                           ct.c_int32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
+                                           ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]),
+    "chom_version": (ct.c_char_p, []),
+    "chom_time_operator": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_double),
+                                      ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)]),
+    "chom_element_apply_host": (ct.c_int, [ct.c_int32, ct.c_void_p, ct.c_double, ct.c_void_p, ct.c_void_p,
+                                           ct.c_void_p, ct.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the HIP library is required; there is no fallback path)")
+        L = ct.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class ChomError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib().chom_last_error().decode()
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status, where):
+    if status != CHOM_OK:
+        raise ChomError(status, where)
+    return status

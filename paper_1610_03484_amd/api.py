@@ -1,0 +1,168 @@
+"""Python binding of the C ABI (same names; marshalling only).
+
+Device memory and streams come from PyTorch; every arithmetic step of the
+homogenisation runs in libchom's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+
+import numpy as np
+
+from . import _lib as L
+
+
+def default_options(**kw) -> L.ChomOptions:
+    o = L.ChomOptions()
+    L.check(L.lib().chom_default_options(ct.byref(o)), "chom_default_options")
+    if "precision" in kw and isinstance(kw["precision"], str):
+        kw["precision"] = L.PRECISION[kw["precision"]]
+    for k, v in kw.items():
+        if k == "hip_stream":
+            v = ct.c_void_p(v)
+        setattr(o, k, v)
+    return o
+
+
+def materials_struct(m: dict) -> L.ChomMaterials:
+    s = L.ChomMaterials()
+    for k, _ in L.ChomMaterials._fields_:
+        setattr(s, k, float(m[k]))
+    return s
+
+
+def params_array(p: np.ndarray):
+    p = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(-1, 11))
+    arr = (L.ChomParams * len(p))()
+    ct.memmove(arr, p.ctypes.data, p.nbytes)
+    return arr
+
+
+def mesh_sizes(n: int):
+    nv, nt = ct.c_int32(), ct.c_int32()
+    L.check(L.lib().chom_mesh_sizes(n, ct.byref(nv), ct.byref(nt)), "chom_mesh_sizes")
+    return nv.value, nt.value
+
+
+def generate_plain_weave(n: int, device="cuda"):
+    """Device tensors (coords [V,3] f64, tets [T,4] i32, phase [T] i8, axis [T,3] f64)."""
+    import torch
+    nv, nt = mesh_sizes(n)
+    coords = torch.empty((nv, 3), dtype=torch.float64, device=device)
+    tets = torch.empty((nt, 4), dtype=torch.int32, device=device)
+    phase = torch.empty((nt,), dtype=torch.int8, device=device)
+    axis = torch.empty((nt, 3), dtype=torch.float64, device=device)
+    stream = torch.cuda.current_stream(coords.device).cuda_stream
+    L.check(L.lib().chom_generate_plain_weave(n, ct.c_void_p(coords.data_ptr()), ct.c_void_p(tets.data_ptr()),
+                                              ct.c_void_p(phase.data_ptr()), ct.c_void_p(axis.data_ptr()),
+                                              ct.c_void_p(stream)), "chom_generate_plain_weave")
+    return coords, tets, phase, axis
+
+
+def material_constants(materials: dict, params=None, c_sat=1.5, degrade_yarn=0):
+    """Host-only: (mech[10], therm[4], moist[4], omega_keep) as the kernels use them."""
+    m = materials_struct(materials)
+    mech = (ct.c_double * 10)()
+    th = (ct.c_double * 4)()
+    mo = (ct.c_double * 4)()
+    keep = ct.c_double()
+    pp = None
+    if params is not None:
+        pp = params_array(params)
+    L.check(L.lib().chom_material_constants(ct.byref(m), pp, c_sat, degrade_yarn, mech, th, mo, ct.byref(keep)),
+            "chom_material_constants")
+    return np.array(mech[:]), np.array(th[:]), np.array(mo[:]), keep.value
+
+
+class RVE:
+    """Handle of chom_rve_create; homogenise() wraps chom_homogenise."""
+
+    def __init__(self, coords, tets, phase, axis, materials: dict, bc="periodic", order=2,
+                 lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), **options):
+        self._h = ct.c_void_p()
+        self.options = default_options(**options)
+        mesh = L.ChomMesh()
+        keep = []
+        if hasattr(coords, "is_cuda") and coords.is_cuda:
+            arrs = [coords.contiguous(), tets.contiguous(), phase.contiguous(), axis.contiguous()]
+            keep = arrs
+            mesh.on_device = 1
+            ptrs = [a.data_ptr() for a in arrs]
+            nv, nt = arrs[0].shape[0], arrs[1].shape[0]
+        else:
+            arrs = [np.ascontiguousarray(coords, np.float64), np.ascontiguousarray(tets, np.int32),
+                    np.ascontiguousarray(phase, np.int8), np.ascontiguousarray(axis, np.float64)]
+            keep = arrs
+            mesh.on_device = 0
+            ptrs = [a.ctypes.data for a in arrs]
+            nv, nt = arrs[0].shape[0], arrs[1].shape[0]
+        mesh.n_vertices, mesh.n_tets = nv, nt
+        mesh.coords, mesh.tets, mesh.phase, mesh.fibre_axis = ptrs
+        mesh.lo[:] = lo
+        mesh.hi[:] = hi
+        bc_id = L.BC[bc] if isinstance(bc, str) else int(bc)
+        self.bc = bc_id
+        self.materials = dict(materials)
+        st = L.lib().chom_rve_create(ct.byref(mesh), ct.byref(materials_struct(materials)), bc_id, order,
+                                     ct.byref(self.options), ct.byref(self._h))
+        del keep
+        L.check(st, "chom_rve_create")
+
+    def homogenise(self, params, allow_noconv=False):
+        """params [B, 11] -> (C21 [B,21], K6 [B,6], D6 [B,6], reports list)."""
+        p = np.asarray(params, dtype=np.float64).reshape(-1, 11)
+        B = len(p)
+        C = np.zeros((B, 21))
+        K = np.zeros((B, 6))
+        D = np.zeros((B, 6))
+        reps = (L.ChomReport * B)()
+        st = L.lib().chom_homogenise(self._h, params_array(p), B, ct.c_void_p(C.ctypes.data),
+                                     ct.c_void_p(K.ctypes.data), ct.c_void_p(D.ctypes.data), reps)
+        if not (st == L.CHOM_OK or (allow_noconv and st == L.CHOM_ENOCONV)):
+            L.check(st, "chom_homogenise")
+        return C, K, D, [report_dict(r) for r in reps]
+
+    def time_operator(self, physics=0, reps=50):
+        """(ms per launch, tets per launch, problems per launch) of the operator kernel."""
+        ms = ct.c_double()
+        nt = ct.c_int64()
+        npb = ct.c_int32()
+        L.check(L.lib().chom_time_operator(self._h, physics, reps, ct.byref(ms), ct.byref(nt), ct.byref(npb)),
+                "chom_time_operator")
+        return ms.value, nt.value, npb.value
+
+    def close(self):
+        if self._h:
+            L.lib().chom_rve_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def report_dict(r: L.ChomReport) -> dict:
+    return dict(iters=list(r.iters), refine_steps=list(r.refine_steps), status=r.status,
+                resid=list(r.resid), asym=r.asym, omega_keep=r.omega_keep)
+
+
+def upper21_to_matrix(c21):
+    """Upper-triangle vector (row-major) -> symmetric 6x6 (mirror of the upper triangle)."""
+    c21 = np.asarray(c21)
+    M = np.zeros(c21.shape[:-1] + (6, 6))
+    iu = np.triu_indices(6)
+    M[..., iu[0], iu[1]] = c21
+    M[..., iu[1], iu[0]] = c21
+    return M
+
+
+def upper6_to_matrix(k6):
+    k6 = np.asarray(k6)
+    M = np.zeros(k6.shape[:-1] + (3, 3))
+    idx = [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)]
+    for q, (i, j) in enumerate(idx):
+        M[..., i, j] = k6[..., q]
+        M[..., j, i] = k6[..., q]
+    return M

@@ -1,0 +1,825 @@
+// C ABI of libchom: argument checking, mesh validation, material constants,
+// workspaces and the host side of the solver (PCG loop, refinement loop).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace chom {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+#define CHOM_HIP(...)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (__VA_ARGS__);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #__VA_ARGS__); \
+            return e_ == hipErrorOutOfMemory ? CHOM_ENOMEM : CHOM_EDEVICE;               \
+        }                                                                                \
+    } while (0)
+
+// Device buffer owned by a handle.
+template <typename T> struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t ensure(size_t count) {
+        if (count <= n && p) return hipSuccess;
+        release();
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc((void **)&p, sizeof(T) * count);
+        if (e == hipSuccess) n = count;
+        return e;
+    }
+};
+
+// ------------------------------------------------------------------ materials
+static const double kBeta = -0.001682;     // per day (Sec. 4, Eq. Eq_alphaT_LSF)
+static const double kTgC = 126.0;          // glass transition (Sec. 4)
+static const double kKelvin = 273.15;
+static const double kDaysPerYear = 365.25;
+
+// Degradation factor (1 - omega) = exp(-gamma(c) alpha(T) t), Eq. Eq_Model_final1.
+static bool damage_factor(const chom_params *pr, double c_sat, double *keep) {
+    if (!pr) { *keep = 1.0; return true; }
+    const double TK = pr->T_celsius + kKelvin, TgK = kTgC + kKelvin;
+    const double arg = 1.0 - TK / TgK;
+    if (!(arg > 0.0) || !(c_sat > 0.0) || pr->c_wt < 0.0 || pr->t_years < 0.0) return false;
+    const double alpha = kBeta * std::log(arg);
+    const double gamma = pr->c_wt / c_sat;
+    *keep = std::exp(-gamma * alpha * pr->t_years * kDaysPerYear);
+    return std::isfinite(*keep) && *keep > 0.0;
+}
+
+// Local transversely isotropic stiffness (fibre along e1) -> the five invariants.
+static bool transiso_invariants(double E1, double E2, double G12, double nu12, double nu23, double out[5]) {
+    if (!(E1 > 0 && E2 > 0 && G12 > 0)) return false;
+    // normal compliance block (e1, e2, e3)
+    const double s11 = 1.0 / E1, s22 = 1.0 / E2, s12 = -nu12 / E1, s23 = -nu23 / E2;
+    const double S[3][3] = {{s11, s12, s12}, {s12, s22, s23}, {s12, s23, s22}};
+    const double det = S[0][0] * (S[1][1] * S[2][2] - S[1][2] * S[2][1]) -
+                       S[0][1] * (S[1][0] * S[2][2] - S[1][2] * S[2][0]) +
+                       S[0][2] * (S[1][0] * S[2][1] - S[1][1] * S[2][0]);
+    const double m2 = S[0][0] * S[1][1] - S[0][1] * S[1][0];
+    if (!(S[0][0] > 0 && m2 > 0 && det > 0)) return false;
+    const double C11 = (S[1][1] * S[2][2] - S[1][2] * S[2][1]) / det;
+    const double C12 = -(S[1][0] * S[2][2] - S[1][2] * S[2][0]) / det;
+    const double C22 = (S[0][0] * S[2][2] - S[0][2] * S[2][0]) / det;
+    const double C23 = -(S[0][0] * S[2][1] - S[0][1] * S[2][0]) / det;
+    const double lam = C23;
+    const double muT = 0.5 * (C22 - C23);
+    const double alpha = C12 - lam;
+    const double muL = G12;
+    const double beta = C11 - lam - 2.0 * muT - 2.0 * alpha - 4.0 * (muL - muT);
+    if (!(muT > 0)) return false;
+    out[0] = lam;
+    out[1] = muT;
+    out[2] = alpha;
+    out[3] = muL - muT;
+    out[4] = beta;
+    return true;
+}
+
+static int material_constants(const chom_materials *m, const chom_params *pr, double c_sat,
+                              int degrade_yarn, double mech[10], double therm[4], double moist[4],
+                              double *keep_out) {
+    double f[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+    if (pr)
+        for (int i = 0; i < 8; ++i) f[i] = pr->factor[i];
+    for (int i = 0; i < 8; ++i)
+        if (!(f[i] > 0) || !std::isfinite(f[i])) {
+            set_error("property factors must be positive and finite");
+            return CHOM_EMATERIAL;
+        }
+    double keep;
+    if (!damage_factor(pr, c_sat, &keep)) {
+        set_error("exposure parameters outside the degradation law's domain (T < T_g, c, t >= 0)");
+        return CHOM_EMATERIAL;
+    }
+    const double E = m->E * f[0] * keep, nu = m->nu * f[1];
+    if (!(E > 0) || !(nu > -1.0 && nu < 0.5)) {
+        set_error("matrix stiffness not positive definite");
+        return CHOM_EMATERIAL;
+    }
+    const double lam = E * nu / ((1 + nu) * (1 - 2 * nu)), mu = E / (2 * (1 + nu));
+    mech[0] = lam; mech[1] = mu; mech[2] = 0; mech[3] = 0; mech[4] = 0;
+    const double ys = degrade_yarn ? keep : 1.0;
+    if (!transiso_invariants(m->E1 * f[4] * ys, m->E2 * f[4] * ys, m->G12 * f[4] * ys, m->nu12 * f[5],
+                             m->nu23 * f[5], mech + 5)) {
+        set_error("yarn stiffness not positive definite");
+        return CHOM_EMATERIAL;
+    }
+    const double km = m->k * f[2], Dm = m->D * f[3];
+    const double k1 = m->k1 * f[6], k2 = m->k2 * f[6], D1 = m->D1 * f[7], D2 = m->D2 * f[7];
+    if (!(km > 0 && Dm > 0 && k1 > 0 && k2 > 0 && D1 > 0 && D2 > 0)) {
+        set_error("conductivity/diffusivity not positive");
+        return CHOM_EMATERIAL;
+    }
+    therm[0] = km; therm[1] = 0; therm[2] = k2; therm[3] = k1 - k2;
+    moist[0] = Dm; moist[1] = 0; moist[2] = D2; moist[3] = D1 - D2;
+    if (keep_out) *keep_out = keep;
+    return CHOM_OK;
+}
+
+// ------------------------------------------------------------------ workspaces
+template <int C, int R> struct ClassWS {
+    static constexpr int MS = (C == 3) ? 6 : 1;
+    int nprob = 0;
+    long long vpp = 0;
+    int nwg_vec = 0, nwg_op = 0, nwg_gram = 0, nwg_avg = 0;
+    DevBuf<Prob> probs;
+    DevBuf<double> b, x64, r64, q64;
+    DevBuf<double> xd, rd, zd, pd, qd;
+    DevBuf<float> xf, rf, zf, pf, qf, r32;
+    DevBuf<double> diag, minv64, ginv64, ginv32, ycoef;
+    DevBuf<float> minv32;
+    DevBuf<ColState> cols, cols_outer;
+    DevBuf<int> active, active_outer, bad;
+    DevBuf<double> partial, avg_out;
+    std::vector<ColState> h_cols, h_cols_outer;
+    std::vector<int> h_active;
+    std::vector<int> refine_steps;  // per problem
+};
+
+}  // namespace chom
+
+using namespace chom;
+
+struct chom_rve {
+    int n = 0, bc = 0, order = 2;
+    double lo[3], hi[3];
+    chom_materials mat;
+    chom_options opt;
+    Geo geo;
+    DevBuf<double4> elem64;
+    DevBuf<float4> elem32;
+    DevBuf<double> geo64;
+    DevBuf<float> geo32;
+    DevBuf<double> rows;
+    ClassWS<3, 6> mech;
+    ClassWS<1, 3> scal;
+};
+
+namespace chom {
+
+static hipStream_t stream_of(const chom_rve *r) { return (hipStream_t)r->opt.hip_stream; }
+
+template <int C, int R>
+static int ensure_ws(chom_rve *rve, ClassWS<C, R> &W, int nprob) {
+    const Geo &G = rve->geo;
+    constexpr int MS = ClassWS<C, R>::MS;
+    W.nprob = nprob;
+    W.vpp = G.npts * R * C;
+    const size_t nv = (size_t)W.vpp * nprob;
+    const size_t nq = (size_t)operator_tiles(G) * BOXPTS * R * C * nprob;  // tile-box operator output
+    W.nwg_vec = (int)std::min<long long>(std::max<long long>((G.npts + 127) / 128, 1), 1024);
+    W.nwg_op = operator_tiles(G);   // partial p.Kp records per load case
+    W.nwg_gram = (int)std::min<long long>(std::max<long long>((G.npts + 4095) / 4096, 1), 256);
+    const long long nt = 6LL * G.n * G.n * G.n;
+    W.nwg_avg = (int)std::min<long long>(std::max<long long>((nt + 1023) / 1024, 1), 256);
+    const bool fp32 = rve->opt.precision == CHOM_FP32_REFINED;
+    CHOM_HIP(W.probs.ensure(nprob));
+    CHOM_HIP(W.b.ensure(nv));
+    CHOM_HIP(W.q64.ensure(nq));
+    if (fp32) {
+        CHOM_HIP(W.x64.ensure(nv));
+        CHOM_HIP(W.r64.ensure(nv));
+        CHOM_HIP(W.xf.ensure(nv));
+        CHOM_HIP(W.rf.ensure(nv));
+        CHOM_HIP(W.zf.ensure(nv));
+        CHOM_HIP(W.pf.ensure(nv));
+        CHOM_HIP(W.qf.ensure(nq));
+        CHOM_HIP(W.r32.ensure(nv));
+    } else {
+        CHOM_HIP(W.xd.ensure(nv));
+        CHOM_HIP(W.rd.ensure(nv));
+        CHOM_HIP(W.zd.ensure(nv));
+        CHOM_HIP(W.pd.ensure(nv));
+        CHOM_HIP(W.qd.ensure(nq));
+    }
+    CHOM_HIP(W.diag.ensure((size_t)G.npts * MS * nprob));
+    CHOM_HIP(W.minv64.ensure((size_t)G.npts * MS * nprob));
+    CHOM_HIP(W.minv32.ensure((size_t)G.npts * MS * nprob));
+    const int S = C * 4;
+    CHOM_HIP(W.ginv64.ensure((size_t)S * S * nprob));
+    CHOM_HIP(W.ginv32.ensure((size_t)S * S * nprob));
+    CHOM_HIP(W.ycoef.ensure((size_t)R * S * nprob));
+    CHOM_HIP(W.cols.ensure((size_t)R * nprob));
+    CHOM_HIP(W.cols_outer.ensure((size_t)R * nprob));
+    CHOM_HIP(W.active.ensure(nprob));
+    CHOM_HIP(W.active_outer.ensure(nprob));
+    CHOM_HIP(W.bad.ensure(1));
+    const int NC = (C == 3) ? 6 : 3;
+    size_t part = 0;
+    part = std::max(part, (size_t)nprob * W.nwg_vec * R * (2 + C * 4));
+    part = std::max(part, (size_t)nprob * W.nwg_op * R);
+    part = std::max(part, (size_t)nprob * W.nwg_gram * 2 * 60);
+    part = std::max(part, (size_t)nprob * W.nwg_avg * R * NC);
+    part = std::max(part, (size_t)nprob * W.nwg_vec * R * C * 4 + (size_t)nprob * R * C * 4);
+    CHOM_HIP(W.partial.ensure(part));
+    CHOM_HIP(W.avg_out.ensure((size_t)nprob * R * NC));
+    W.h_cols.resize((size_t)R * nprob);
+    W.h_cols_outer.resize((size_t)R * nprob);
+    W.h_active.resize(nprob);
+    W.refine_steps.assign(nprob, 0);
+    return CHOM_OK;
+}
+
+// PCG on one class of problems: b -> x (vectors of precision T).
+template <typename T, int C, int R>
+static int pcg(chom_rve *rve, ClassWS<C, R> &W, const T *b, T *x, T *r, T *z, T *p, T *q,
+               const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask,
+               const Prob *probs_dev) {
+    const Geo &G = rve->geo;
+    hipStream_t s = stream_of(rve);
+    const int nprob = W.nprob;
+    CHOM_HIP(launch_cg_init<T, C, R>(G, nprob, W.vpp, b, x, r, z, minv, W.partial.p, W.nwg_vec, s));
+    if (mask)
+        CHOM_HIP((launch_finish_beta_masked<C, R>(nprob, G.nrow, W.partial.p, W.nwg_vec, ginv, W.ycoef.p,
+                                                  W.cols.p, W.active.p, rtol2, mask, s)));
+    else
+        CHOM_HIP((launch_finish_beta<C, R>(nprob, G.nrow, W.partial.p, W.nwg_vec, ginv, W.ycoef.p, W.cols.p,
+                                           W.active.p, 1, rtol2, use_init, s)));
+    const int max_iter = rve->opt.max_iter;
+    const int check = 8;
+    for (int it = 0; it < max_iter; ++it) {
+        if (it % check == 0) {
+            CHOM_HIP(hipMemcpyAsync(W.h_active.data(), W.active.p, sizeof(int) * nprob, hipMemcpyDeviceToHost, s));
+            CHOM_HIP(hipStreamSynchronize(s));
+            int act = 0;
+            for (int i = 0; i < nprob; ++i) act += W.h_active[i];
+            if (act == 0) break;
+        }
+        CHOM_HIP((launch_cg_dir<T, C, R>(G, nprob, W.vpp, r, z, p, q, minv, W.ycoef.p, W.cols.p, W.active.p,
+                                         W.nwg_vec, s)));
+        CHOM_HIP((launch_operator<T, C, R>(G, probs_dev, nprob, p, q, W.partial.p, W.active.p, s)));
+        CHOM_HIP((launch_finish_alpha<C, R>(nprob, W.partial.p, W.nwg_op, W.cols.p, s)));
+        CHOM_HIP((launch_cg_update<T, C, R>(G, nprob, W.vpp, x, r, z, p, q, minv, W.cols.p, W.partial.p,
+                                            W.active.p, W.nwg_vec, s)));
+        CHOM_HIP((launch_finish_beta<C, R>(nprob, G.nrow, W.partial.p, W.nwg_vec, ginv, W.ycoef.p, W.cols.p,
+                                           W.active.p, 0, rtol2, use_init, s)));
+    }
+    return CHOM_OK;
+}
+
+// Solve one class (mechanical or scalar) for all its problems.  Result: W.avg_out.
+template <int C, int R>
+static int run_class(chom_rve *rve, ClassWS<C, R> &W, const std::vector<Prob> &hprobs) {
+    const Geo &G = rve->geo;
+    hipStream_t s = stream_of(rve);
+    const int nprob = (int)hprobs.size();
+    int st = ensure_ws<C, R>(rve, W, nprob);
+    if (st != CHOM_OK) return st;
+    const size_t nv = (size_t)W.vpp * nprob;
+    CHOM_HIP(hipMemcpyAsync(W.probs.p, hprobs.data(), sizeof(Prob) * nprob, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipMemsetAsync(W.cols.p, 0, sizeof(ColState) * R * nprob, s));
+    CHOM_HIP(hipMemsetAsync(W.bad.p, 0, sizeof(int), s));
+    CHOM_HIP((launch_precond<C>(G, W.probs.p, nprob, W.diag.p, W.minv64.p, W.minv32.p, s)));
+    CHOM_HIP((launch_gram<C>(G, nprob, W.minv64.p, W.minv32.p, W.partial.p, W.nwg_gram, W.ginv64.p, W.ginv32.p,
+                             W.bad.p, s)));
+    CHOM_HIP((launch_rhs<C, R>(G, W.probs.p, nprob, W.vpp, W.b.p, W.cols.p, s)));
+    const double rtol2 = rve->opt.rtol * rve->opt.rtol;
+    double *x64 = nullptr;
+    if (rve->opt.precision == CHOM_FP64) {
+        st = pcg<double, C, R>(rve, W, W.b.p, W.xd.p, W.rd.p, W.zd.p, W.pd.p, W.qd.p, W.minv64.p, W.ginv64.p,
+                               rtol2, 0, nullptr, W.probs.p);
+        if (st != CHOM_OK) return st;
+        x64 = W.xd.p;
+    } else {
+        const double irtol2 = rve->opt.inner_rtol * rve->opt.inner_rtol;
+        CHOM_HIP(hipMemsetAsync(W.x64.p, 0, sizeof(double) * nv, s));
+        CHOM_HIP((launch_residual64<C, R>(G, nprob, W.vpp, W.b.p, nullptr, W.r64.p, W.r32.p, s)));
+        CHOM_HIP(hipMemcpyAsync(W.cols_outer.p, W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToDevice, s));
+        for (int i = 0; i < nprob; ++i) W.refine_steps[i] = 0;
+        for (int step = 0; step <= rve->opt.max_refine; ++step) {
+            // outer residual norm in FP64: r64 . P M^-1 r64 against the linear-field energy
+            CHOM_HIP((launch_cg_init<double, C, R>(G, nprob, W.vpp, W.r64.p, nullptr, nullptr, nullptr, W.minv64.p,
+                                                   W.partial.p, W.nwg_vec, s)));
+            CHOM_HIP((launch_finish_beta<C, R>(nprob, G.nrow, W.partial.p, W.nwg_vec, W.ginv64.p, W.ycoef.p,
+                                               W.cols_outer.p, W.active_outer.p, 1, rtol2, 0, s)));
+            if (G.nrow > 0) {
+                // project the residual vector, then measure it again
+                CHOM_HIP((launch_proj_resid<C, R>(G, nprob, W.vpp, W.r64.p, W.r32.p, W.minv64.p, W.ycoef.p,
+                                                  W.partial.p, W.nwg_vec, s)));
+                CHOM_HIP((launch_finish_beta<C, R>(nprob, G.nrow, W.partial.p, W.nwg_vec, W.ginv64.p, W.ycoef.p,
+                                                   W.cols_outer.p, W.active_outer.p, 1, rtol2, 0, s)));
+            }
+            CHOM_HIP(hipMemcpyAsync(W.h_active.data(), W.active_outer.p, sizeof(int) * nprob, hipMemcpyDeviceToHost, s));
+            CHOM_HIP(hipStreamSynchronize(s));
+            int act = 0;
+            for (int i = 0; i < nprob; ++i) {
+                act += W.h_active[i];
+                if (W.h_active[i]) W.refine_steps[i] = step;
+            }
+            if (act == 0 || step == rve->opt.max_refine) break;
+            st = pcg<float, C, R>(rve, W, W.r32.p, W.xf.p, W.rf.p, W.zf.p, W.pf.p, W.qf.p, W.minv32.p, W.ginv32.p,
+                                  irtol2, 1, W.cols_outer.p, W.probs.p);
+            if (st != CHOM_OK) return st;
+            CHOM_HIP((launch_axpy_x64<C, R>(nprob, W.vpp, W.x64.p, W.xf.p, s)));
+            CHOM_HIP((launch_operator<double, C, R>(G, W.probs.p, nprob, W.x64.p, W.q64.p, W.partial.p, nullptr, s)));
+            CHOM_HIP((launch_residual64<C, R>(G, nprob, W.vpp, W.b.p, W.q64.p, W.r64.p, W.r32.p, s)));
+        }
+        x64 = W.x64.p;
+    }
+    CHOM_HIP((launch_project<C, R>(G, nprob, W.vpp, x64, W.minv64.p, W.ginv64.p, W.partial.p, W.nwg_vec, s)));
+    CHOM_HIP((launch_average<C, R>(G, W.probs.p, nprob, W.vpp, x64, W.partial.p, W.nwg_avg, W.avg_out.p, s)));
+    CHOM_HIP(hipMemcpyAsync(W.h_cols.data(), W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToHost, s));
+    if (rve->opt.precision == CHOM_FP32_REFINED)
+        CHOM_HIP(hipMemcpyAsync(W.h_cols_outer.data(), W.cols_outer.p, sizeof(ColState) * R * nprob,
+                                hipMemcpyDeviceToHost, s));
+    int hbad = 0;
+    CHOM_HIP(hipMemcpyAsync(&hbad, W.bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipStreamSynchronize(s));
+    if (hbad) {
+        set_error("constraint Gram matrix singular");
+        return CHOM_EDEVICE;
+    }
+    return CHOM_OK;
+}
+
+// ------------------------------------------------------------------ mesh checks
+static int64_t kuhn_vertex(int i, int j, int k, int n) { return i + (int64_t)(n + 1) * (j + (int64_t)(n + 1) * k); }
+
+}  // namespace chom
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *chom_last_error(void) { return chom::g_last_error.c_str(); }
+const char *chom_version(void) { return "chom 0.1 (gfx950, p=2 lattice operator)"; }
+
+int chom_default_options(chom_options *opt) {
+    if (!opt) return CHOM_EINVAL;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = CHOM_FP64;
+    opt->precond = CHOM_PRECOND_BLOCK_JACOBI;
+    opt->max_iter = 20000;
+    opt->max_refine = 30;
+    opt->rtol = 1e-12;
+    opt->inner_rtol = 1e-4;
+    opt->c_sat = 1.5;
+    return CHOM_OK;
+}
+
+int chom_mesh_sizes(int32_t n, int32_t *nv, int32_t *nt) {
+    if (n < 1 || n > 1024 || !nv || !nt) {
+        set_error("chom_mesh_sizes: n must be in [1, 1024] and outputs non-null");
+        return CHOM_EINVAL;
+    }
+    const int64_t v = (int64_t)(n + 1) * (n + 1) * (n + 1), t = 6LL * n * n * n;
+    if (t > INT32_MAX) {
+        set_error("chom_mesh_sizes: mesh too large for 32-bit tet counts");
+        return CHOM_EINVAL;
+    }
+    *nv = (int32_t)v;
+    *nt = (int32_t)t;
+    return CHOM_OK;
+}
+
+int chom_generate_plain_weave(int32_t n, double *coords, int32_t *tets, int8_t *phase, double *axis,
+                              void *stream) {
+    int32_t nv, nt;
+    int st = chom_mesh_sizes(n, &nv, &nt);
+    if (st != CHOM_OK) return st;
+    if (!coords || !tets || !phase || !axis) {
+        set_error("chom_generate_plain_weave: null output buffer");
+        return CHOM_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    CHOM_HIP(launch_generate(n, coords, tets, phase, axis, s));
+    CHOM_HIP(hipStreamSynchronize(s));
+    return CHOM_OK;
+}
+
+int chom_material_constants(const chom_materials *mat, const chom_params *params, double c_sat,
+                            int32_t degrade_yarn, double *out_mech, double *out_therm, double *out_moist,
+                            double *omega_keep) {
+    if (!mat || !out_mech || !out_therm || !out_moist) {
+        set_error("chom_material_constants: null argument");
+        return CHOM_EINVAL;
+    }
+    return material_constants(mat, params, c_sat, degrade_yarn, out_mech, out_therm, out_moist, omega_keep);
+}
+
+int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc, int32_t order,
+                    const chom_options *opt, chom_rve **out) {
+    if (!mesh || !mat || !out) {
+        set_error("chom_rve_create: null argument");
+        return CHOM_EINVAL;
+    }
+    *out = nullptr;
+    if (bc < 0 || bc > 2) {
+        set_error("chom_rve_create: bc_type must be 0 (Dirichlet), 1 (periodic) or 2 (Neumann)");
+        return CHOM_EINVAL;
+    }
+    if (order != 2) {
+        set_error("chom_rve_create: only order 2 is supported by this build");
+        return CHOM_EINVAL;
+    }
+    chom_options o;
+    chom_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision != CHOM_FP64 && o.precision != CHOM_FP32_REFINED) {
+        set_error("chom_rve_create: unknown precision");
+        return CHOM_EINVAL;
+    }
+    if (!(o.rtol > 0) || !(o.inner_rtol > 0) || o.max_iter < 1 || o.max_refine < 0 || !(o.c_sat > 0)) {
+        set_error("chom_rve_create: bad tolerances or caps");
+        return CHOM_EINVAL;
+    }
+    // --- mesh size: (n+1)^3 vertices, 6 n^3 tets
+    int n = (int)std::lround(std::cbrt((double)mesh->n_tets / 6.0));
+    if (n < 1 || 6LL * n * n * n != mesh->n_tets || (int64_t)(n + 1) * (n + 1) * (n + 1) != mesh->n_vertices) {
+        set_error("chom_rve_create: mesh is not a Kuhn lattice (need (n+1)^3 vertices and 6 n^3 tets)");
+        return CHOM_EMESH;
+    }
+    if (!mesh->coords || !mesh->tets || !mesh->phase || !mesh->fibre_axis) {
+        set_error("chom_rve_create: null mesh array");
+        return CHOM_EINVAL;
+    }
+    for (int d = 0; d < 3; ++d)
+        if (!(mesh->hi[d] > mesh->lo[d])) {
+            set_error("chom_rve_create: box must have hi > lo");
+            return CHOM_EMESH;
+        }
+    const int64_t nv = mesh->n_vertices, nt = mesh->n_tets;
+    // --- host copies for validation
+    std::vector<double> hc(3 * nv), hax(3 * nt);
+    std::vector<int32_t> ht(4 * nt);
+    std::vector<int8_t> hph(nt);
+    if (mesh->on_device) {
+        CHOM_HIP(hipMemcpy(hc.data(), mesh->coords, sizeof(double) * 3 * nv, hipMemcpyDeviceToHost));
+        CHOM_HIP(hipMemcpy(ht.data(), mesh->tets, sizeof(int32_t) * 4 * nt, hipMemcpyDeviceToHost));
+        CHOM_HIP(hipMemcpy(hph.data(), mesh->phase, nt, hipMemcpyDeviceToHost));
+        CHOM_HIP(hipMemcpy(hax.data(), mesh->fibre_axis, sizeof(double) * 3 * nt, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(hc.data(), mesh->coords, sizeof(double) * 3 * nv);
+        std::memcpy(ht.data(), mesh->tets, sizeof(int32_t) * 4 * nt);
+        std::memcpy(hph.data(), mesh->phase, nt);
+        std::memcpy(hax.data(), mesh->fibre_axis, sizeof(double) * 3 * nt);
+    }
+    for (int64_t e = 0; e < nt; ++e) {
+        const int t = (int)(e % 6);
+        const int64_t cell = e / 6;
+        const int ci = (int)(cell % n), cj = (int)((cell / n) % n), ck = (int)(cell / ((int64_t)n * n));
+        int p0, p1;
+        kuhn_perm(t, p0, p1);
+        int v[4][3] = {{ci, cj, ck}, {ci, cj, ck}, {ci, cj, ck}, {ci + 1, cj + 1, ck + 1}};
+        v[1][p0] += 1;
+        v[2][p0] += 1;
+        v[2][p1] += 1;
+        int64_t want[4], got[4];
+        for (int a = 0; a < 4; ++a) {
+            want[a] = kuhn_vertex(v[a][0], v[a][1], v[a][2], n);
+            got[a] = ht[4 * e + a];
+        }
+        std::sort(got, got + 4);
+        for (int a = 0; a < 4; ++a)
+            if (want[a] != got[a]) {
+                set_error("chom_rve_create: tet " + std::to_string(e) + " does not match the Kuhn lattice");
+                return CHOM_EMESH;
+            }
+        if (hph[e] < 0 || hph[e] > 4) {
+            set_error("chom_rve_create: phase must be in 0..4");
+            return CHOM_EMESH;
+        }
+        if (hph[e] > 0) {
+            const double nr = std::sqrt(hax[3 * e] * hax[3 * e] + hax[3 * e + 1] * hax[3 * e + 1] +
+                                        hax[3 * e + 2] * hax[3 * e + 2]);
+            if (!(std::fabs(nr - 1.0) < 1e-6)) {
+                set_error("chom_rve_create: yarn fibre axis must be a unit vector");
+                return CHOM_EMESH;
+            }
+        }
+    }
+    // boundary vertices on their faces; uniform grid detection; periodic face matching
+    bool uniform = true;
+    double h[3];
+    for (int d = 0; d < 3; ++d) h[d] = (mesh->hi[d] - mesh->lo[d]) / n;
+    const double scale = std::max(mesh->hi[0] - mesh->lo[0], std::max(mesh->hi[1] - mesh->lo[1], mesh->hi[2] - mesh->lo[2]));
+    const double tol = 1e-12 * scale;
+    for (int k = 0; k <= n; ++k)
+        for (int j = 0; j <= n; ++j)
+            for (int i = 0; i <= n; ++i) {
+                const int64_t v = kuhn_vertex(i, j, k, n);
+                const int ijk[3] = {i, j, k};
+                for (int d = 0; d < 3; ++d) {
+                    const double ref = (ijk[d] == n) ? mesh->hi[d] : mesh->lo[d] + (mesh->hi[d] - mesh->lo[d]) * ((double)ijk[d] / n);
+                    const double x = hc[3 * v + d];
+                    if (std::fabs(x - ref) > tol) uniform = false;
+                    if ((ijk[d] == 0 && std::fabs(x - mesh->lo[d]) > tol) || (ijk[d] == n && std::fabs(x - mesh->hi[d]) > tol)) {
+                        set_error("chom_rve_create: boundary vertex off its face");
+                        return CHOM_EMESH;
+                    }
+                }
+                if (bc == CHOM_BC_PERIODIC) {
+                    for (int d = 0; d < 3; ++d) {
+                        if (ijk[d] != n) continue;
+                        int m[3] = {i, j, k};
+                        m[d] = 0;
+                        const int64_t w = kuhn_vertex(m[0], m[1], m[2], n);
+                        for (int d2 = 0; d2 < 3; ++d2)
+                            if (d2 != d && std::fabs(hc[3 * v + d2] - hc[3 * w + d2]) > tol) {
+                                set_error("chom_rve_create: periodic faces do not match");
+                                return CHOM_EMESH;
+                            }
+                    }
+                }
+            }
+    std::unique_ptr<chom_rve> R(new chom_rve());
+    R->n = n;
+    R->bc = bc;
+    R->order = order;
+    for (int d = 0; d < 3; ++d) {
+        R->lo[d] = mesh->lo[d];
+        R->hi[d] = mesh->hi[d];
+    }
+    R->mat = *mat;
+    R->opt = o;
+    {
+        double m10[10], t4[4], d4[4];
+        if (material_constants(mat, nullptr, o.c_sat, o.degrade_yarn, m10, t4, d4, nullptr) != CHOM_OK)
+            return CHOM_EMATERIAL;
+    }
+    Geo &G = R->geo;
+    std::memset(&G, 0, sizeof(G));
+    G.n = n;
+    G.bc = bc;
+    G.uniform = uniform ? 1 : 0;
+    G.Lw = (bc == CHOM_BC_PERIODIC) ? 2 * n : 2 * n + 1;
+    G.npts = (long long)G.Lw * G.Lw * G.Lw;
+    G.volume = (mesh->hi[0] - mesh->lo[0]) * (mesh->hi[1] - mesh->lo[1]) * (mesh->hi[2] - mesh->lo[2]);
+    G.nrow = (bc == CHOM_BC_DIRICHLET) ? 0 : (bc == CHOM_BC_PERIODIC ? 1 : 4);
+    G.tiles_x = (n + TX - 1) / TX;
+    G.tiles_y = (n + TY - 1) / TY;
+    G.tiles_z = (n + TZ - 1) / TZ;
+    // uniform geometry per tet type
+    for (int t = 0; t < 6; ++t) {
+        int p0, p1;
+        kuhn_perm(t, p0, p1);
+        double v1[3] = {0, 0, 0}, v2[3] = {0, 0, 0}, v3[3] = {h[0], h[1], h[2]};
+        v1[p0] = h[p0];
+        v2[p0] = h[p0];
+        v2[p1] = h[p1];
+        const double J[3][3] = {{v1[0], v2[0], v3[0]}, {v1[1], v2[1], v3[1]}, {v1[2], v2[2], v3[2]}};
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        const double id = 1.0 / det;
+        const double Ji[3][3] = {
+            {(J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id, (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id, (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id},
+            {(J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id, (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id, (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id},
+            {(J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id, (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id, (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id}};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                G.tg64[t][3 * i + j] = Ji[i][j];
+                G.tg32[t][3 * i + j] = (float)Ji[i][j];
+            }
+        G.tg64[t][9] = std::fabs(det) / 6.0;
+        G.tg32[t][9] = (float)(std::fabs(det) / 6.0);
+    }
+    hipStream_t s = (hipStream_t)o.hip_stream;
+    CHOM_HIP(R->elem64.ensure(nt));
+    CHOM_HIP(R->elem32.ensure(nt));
+    if (!uniform) {
+        CHOM_HIP(R->geo64.ensure(10 * nt));
+        CHOM_HIP(R->geo32.ensure(10 * nt));
+    }
+    CHOM_HIP(R->rows.ensure(4 * G.npts));
+    // device copies of coords / phase / axis
+    DevBuf<double> dc, dax;
+    DevBuf<int8_t> dph;
+    DevBuf<int> dbad;
+    CHOM_HIP(dc.ensure(3 * nv));
+    CHOM_HIP(dax.ensure(3 * nt));
+    CHOM_HIP(dph.ensure(nt));
+    CHOM_HIP(dbad.ensure(1));
+    CHOM_HIP(hipMemcpyAsync(dc.p, hc.data(), sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipMemcpyAsync(dax.p, hax.data(), sizeof(double) * 3 * nt, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipMemcpyAsync(dph.p, hph.data(), nt, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipMemsetAsync(dbad.p, 0, sizeof(int), s));
+    G.elem64 = R->elem64.p;
+    G.elem32 = R->elem32.p;
+    G.geo64 = uniform ? nullptr : R->geo64.p;
+    G.geo32 = uniform ? nullptr : R->geo32.p;
+    G.rows = R->rows.p;
+    CHOM_HIP(launch_element_setup(G, dc.p, nullptr, dph.p, dax.p, R->elem64.p, R->elem32.p, G.geo64 ? R->geo64.p : nullptr,
+                                  G.geo32 ? R->geo32.p : nullptr, dbad.p, s));
+    CHOM_HIP(launch_rows(G, R->rows.p, s));
+    int hbad = 0;
+    CHOM_HIP(hipMemcpyAsync(&hbad, dbad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipStreamSynchronize(s));
+    if (hbad) {
+        set_error("chom_rve_create: " + std::to_string(hbad) + " tets are degenerate or inverted");
+        return CHOM_EMESH;
+    }
+    *out = R.release();
+    return CHOM_OK;
+}
+
+void chom_rve_destroy(chom_rve *rve) { delete rve; }
+
+int chom_time_operator(chom_rve *rve, int32_t physics, int32_t reps, double *ms_per_launch,
+                       int64_t *tets_per_launch, int32_t *problems_per_launch) {
+    if (!rve || !ms_per_launch || reps < 1 || (physics != 0 && physics != 1)) {
+        set_error("chom_time_operator: bad argument");
+        return CHOM_EINVAL;
+    }
+    const Geo &G = rve->geo;
+    hipStream_t s = stream_of(rve);
+    const bool f32 = rve->opt.precision == CHOM_FP32_REFINED;
+    const int nprob = physics == 0 ? rve->mech.nprob : rve->scal.nprob;
+    if (nprob == 0) {
+        set_error("chom_time_operator: call chom_homogenise first (the timing reuses its workspace)");
+        return CHOM_EINVAL;
+    }
+    hipEvent_t e0, e1;
+    CHOM_HIP(hipEventCreate(&e0));
+    CHOM_HIP(hipEventCreate(&e1));
+    CHOM_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) {
+        if (physics == 0) {
+            if (f32)
+                CHOM_HIP((launch_operator<float, 3, 6>(G, rve->mech.probs.p, nprob, rve->mech.pf.p, rve->mech.qf.p,
+                                                      rve->mech.partial.p, nullptr, s)));
+            else
+                CHOM_HIP((launch_operator<double, 3, 6>(G, rve->mech.probs.p, nprob, rve->mech.pd.p, rve->mech.qd.p,
+                                                       rve->mech.partial.p, nullptr, s)));
+        } else {
+            if (f32)
+                CHOM_HIP((launch_operator<float, 1, 3>(G, rve->scal.probs.p, nprob, rve->scal.pf.p, rve->scal.qf.p,
+                                                      rve->scal.partial.p, nullptr, s)));
+            else
+                CHOM_HIP((launch_operator<double, 1, 3>(G, rve->scal.probs.p, nprob, rve->scal.pd.p, rve->scal.qd.p,
+                                                       rve->scal.partial.p, nullptr, s)));
+        }
+    }
+    CHOM_HIP(hipEventRecord(e1, s));
+    CHOM_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    CHOM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_launch = (double)ms / reps;
+    if (tets_per_launch) *tets_per_launch = 6LL * G.n * G.n * G.n * nprob;
+    if (problems_per_launch) *problems_per_launch = nprob;
+    return CHOM_OK;
+}
+
+int chom_element_apply_host(int32_t ncomp, const double *grad_lam, double vol, const double *axis,
+                            const double *inv5, const double *u, double *y) {
+    if (!grad_lam || !axis || !inv5 || !u || !y || (ncomp != 1 && ncomp != 3)) {
+        set_error("chom_element_apply_host: bad argument");
+        return CHOM_EINVAL;
+    }
+    double g[4][3], a[3] = {axis[0], axis[1], axis[2]}, m[5];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 3; ++j) g[i][j] = grad_lam[3 * i + j];
+    for (int k = 0; k < 5; ++k) m[k] = inv5[k];
+    if (ncomp == 3) {
+        double uu[10][3], yy[10][3];
+        for (int k = 0; k < 10; ++k)
+            for (int c = 0; c < 3; ++c) uu[k][c] = u[3 * k + c];
+        p2_apply<double, 3>(g, vol, a, m, uu, yy);
+        for (int k = 0; k < 10; ++k)
+            for (int c = 0; c < 3; ++c) y[3 * k + c] = yy[k][c];
+    } else {
+        double uu[10][1], yy[10][1];
+        for (int k = 0; k < 10; ++k) uu[k][0] = u[k];
+        p2_apply<double, 1>(g, vol, a, m, uu, yy);
+        for (int k = 0; k < 10; ++k) y[k] = yy[k][0];
+    }
+    return CHOM_OK;
+}
+
+int chom_homogenise(chom_rve *rve, const chom_params *params, int32_t batch, double *C_hom, double *K_hom,
+                    double *D_hom, chom_report *rep) {
+    if (!rve || !params || !C_hom || !K_hom || !D_hom || batch < 1) {
+        set_error("chom_homogenise: null argument or batch < 1");
+        return CHOM_EINVAL;
+    }
+    hipStream_t s = stream_of(rve);
+    std::vector<chom_params> hp(batch);
+    if (rve->opt.device_ptrs)
+        CHOM_HIP(hipMemcpy(hp.data(), params, sizeof(chom_params) * batch, hipMemcpyDeviceToHost));
+    else
+        std::memcpy(hp.data(), params, sizeof(chom_params) * batch);
+    std::vector<Prob> pm(batch), ps(2 * batch);
+    std::vector<double> keep(batch);
+    for (int i = 0; i < batch; ++i) {
+        double m10[10], t4[4], d4[4];
+        const int st = material_constants(&rve->mat, &hp[i], rve->opt.c_sat, rve->opt.degrade_yarn, m10, t4, d4, &keep[i]);
+        if (st != CHOM_OK) {
+            set_error(std::string("chom_homogenise: record ") + std::to_string(i) + ": " + g_last_error);
+            return st;
+        }
+        std::memset(&pm[i], 0, sizeof(Prob));
+        std::memset(&ps[i], 0, sizeof(Prob));
+        std::memset(&ps[batch + i], 0, sizeof(Prob));
+        for (int ph = 0; ph < 2; ++ph)
+            for (int k = 0; k < 5; ++k) {
+                pm[i].mat64[ph][k] = m10[5 * ph + k];
+                pm[i].mat32[ph][k] = (float)m10[5 * ph + k];
+            }
+        for (int ph = 0; ph < 2; ++ph)
+            for (int k = 0; k < 2; ++k) {
+                ps[i].mat64[ph][k] = t4[2 * ph + k];
+                ps[i].mat32[ph][k] = (float)t4[2 * ph + k];
+                ps[batch + i].mat64[ph][k] = d4[2 * ph + k];
+                ps[batch + i].mat32[ph][k] = (float)d4[2 * ph + k];
+            }
+    }
+    const Geo &G = rve->geo;
+    for (int i = 0; i < batch; ++i) {
+        pm[i].voff = (long long)i * G.npts * 18;
+        pm[i].doff = (long long)i * G.npts;
+    }
+    for (int i = 0; i < 2 * batch; ++i) {
+        ps[i].voff = (long long)i * G.npts * 3;
+        ps[i].doff = (long long)i * G.npts;
+    }
+    int st = run_class<3, 6>(rve, rve->mech, pm);
+    if (st != CHOM_OK) return st;
+    st = run_class<1, 3>(rve, rve->scal, ps);
+    if (st != CHOM_OK) return st;
+    // gather results
+    std::vector<double> cm((size_t)batch * 36), cs((size_t)2 * batch * 9);
+    CHOM_HIP(hipMemcpyAsync(cm.data(), rve->mech.avg_out.p, sizeof(double) * cm.size(), hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipMemcpyAsync(cs.data(), rve->scal.avg_out.p, sizeof(double) * cs.size(), hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipStreamSynchronize(s));
+    std::vector<double> oc((size_t)batch * 21), ok((size_t)batch * 6), od((size_t)batch * 6);
+    int overall = CHOM_OK;
+    const bool refined = rve->opt.precision == CHOM_FP32_REFINED;
+    for (int i = 0; i < batch; ++i) {
+        const double *Cm = &cm[(size_t)i * 36];
+        int q = 0;
+        double fro = 0, asym = 0;
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) {
+                if (b >= a) oc[(size_t)i * 21 + q++] = Cm[a * 6 + b];
+                fro += Cm[a * 6 + b] * Cm[a * 6 + b];
+                const double dlt = Cm[a * 6 + b] - Cm[b * 6 + a];
+                asym += dlt * dlt;
+            }
+        const double *Kt = &cs[(size_t)i * 9], *Dt = &cs[(size_t)(batch + i) * 9];
+        const int ui[6] = {0, 4, 8, 1, 5, 2};
+        for (int k = 0; k < 6; ++k) {
+            ok[(size_t)i * 6 + k] = Kt[ui[k]];
+            od[(size_t)i * 6 + k] = Dt[ui[k]];
+        }
+        chom_report R;
+        std::memset(&R, 0, sizeof(R));
+        R.status = CHOM_OK;
+        R.asym = fro > 0 ? std::sqrt(asym / fro) : 0.0;
+        R.omega_keep = keep[i];
+        for (int c = 0; c < 12; ++c) {
+            const ColState *cs_in, *cs_out;
+            int ridx;
+            if (c < 6) {
+                cs_in = &rve->mech.h_cols[(size_t)i * 6 + c];
+                cs_out = refined ? &rve->mech.h_cols_outer[(size_t)i * 6 + c] : cs_in;
+            } else {
+                const int pidx = (c < 9) ? i : batch + i;
+                ridx = (c < 9) ? c - 6 : c - 9;
+                cs_in = &rve->scal.h_cols[(size_t)pidx * 3 + ridx];
+                cs_out = refined ? &rve->scal.h_cols_outer[(size_t)pidx * 3 + ridx] : cs_in;
+            }
+            R.iters[c] = cs_in->iters;
+            R.resid[c] = cs_out->eref > 0 ? std::sqrt(cs_out->rz / cs_out->eref) : 0.0;
+            const bool conv = (cs_out->done == 1) || (cs_out->rz <= rve->opt.rtol * rve->opt.rtol * cs_out->eref);
+            if (!conv) R.status = CHOM_ENOCONV;
+        }
+        if (refined) {
+            R.refine_steps[0] = rve->mech.refine_steps[i];
+            R.refine_steps[1] = rve->scal.refine_steps[i];
+            R.refine_steps[2] = rve->scal.refine_steps[batch + i];
+        }
+        if (R.status != CHOM_OK) overall = CHOM_ENOCONV;
+        if (rep) rep[i] = R;
+    }
+    if (rve->opt.device_ptrs) {
+        CHOM_HIP(hipMemcpyAsync(C_hom, oc.data(), sizeof(double) * oc.size(), hipMemcpyHostToDevice, s));
+        CHOM_HIP(hipMemcpyAsync(K_hom, ok.data(), sizeof(double) * ok.size(), hipMemcpyHostToDevice, s));
+        CHOM_HIP(hipMemcpyAsync(D_hom, od.data(), sizeof(double) * od.size(), hipMemcpyHostToDevice, s));
+        CHOM_HIP(hipStreamSynchronize(s));
+    } else {
+        std::memcpy(C_hom, oc.data(), sizeof(double) * oc.size());
+        std::memcpy(K_hom, ok.data(), sizeof(double) * ok.size());
+        std::memcpy(D_hom, od.data(), sizeof(double) * od.size());
+    }
+    if (overall != CHOM_OK) set_error("chom_homogenise: some load case did not converge");
+    return overall;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Homogenisation average (paper Sec. 2, Eq. macro_stress and Eq. Eq_C_stress;
+// Eq. eq_homo_flux for the scalar fields): for load case k,
+//   sigma_bar_k = (1/V) sum_e C_e (eps_k |e| + int_e sym grad(u~_k) dV),
+// accumulated in FP64 from the FP64 fluctuation.  Column k of C_bar is
+// sigma_bar_k; K_bar and D_bar likewise with fluxes k_e (e_k |e| + int grad psi~).
+#include "common.h"
+#include "internal.h"
+
+namespace chom {
+
+template <int C, int R>
+__global__ void average_kernel(Geo G, const Prob *probs, long long vpp, const double *x, double *partial) {
+    constexpr int NC = (C == 3) ? 6 : 3;
+    const int prob = blockIdx.y;
+    const Prob P = probs[prob];
+    const double *xp = x + (long long)prob * vpp;
+    const long long nt = 6LL * G.n * G.n * G.n;
+    double acc[R * NC];
+    for (int k = 0; k < R * NC; ++k) acc[k] = 0.0;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int n = G.n;
+        const int t = (int)(e % 6);
+        const long long cell = e / 6;
+        const int ci = (int)(cell % n), cj = (int)((cell / n) % n), ck = (int)(cell / ((long long)n * n));
+        int off[10][3];
+        p2_dof_offsets(t, off);
+        double g[4][3], vol, a[3];
+        int ph;
+        GeoSel<double>::get(G, e, t, g, vol);
+        GeoSel<double>::elem(G, e, a, ph);
+        const double *m = P.mat64[ph ? 1 : 0];
+        long long idx[10];
+        double w[10][3];
+        for (int k = 0; k < 10; ++k) {
+            idx[k] = lat_index(G, 2 * ci + off[k][0], 2 * cj + off[k][1], 2 * ck + off[k][2]);
+            if (k < 4) {
+                for (int d = 0; d < 3; ++d) w[k][d] = vol * g[k][d];
+            } else {
+                int a2, b2;
+                edge_verts(k - 4, a2, b2);
+                for (int d = 0; d < 3; ++d) w[k][d] = vol * (g[a2][d] + g[b2][d]);
+            }
+        }
+        for (int r = 0; r < R; ++r) {
+            double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // int grad(u~) dV
+            for (int k = 0; k < 10; ++k)
+                for (int c = 0; c < C; ++c) {
+                    const double u = xp[(idx[k] * R + r) * C + c];
+                    for (int d = 0; d < 3; ++d) H[c][d] += u * w[k][d];
+                }
+            if constexpr (C == 3) {
+                double eps[6] = {H[0][0], H[1][1], H[2][2], 0.5 * (H[0][1] + H[1][0]),
+                                 0.5 * (H[1][2] + H[2][1]), 0.5 * (H[2][0] + H[0][2])};
+                if (r < 3) eps[r] += vol; else eps[r] += 0.5 * vol;
+                double s[6];
+                stress_ti<double>(eps, a, m, s);
+                for (int k = 0; k < 6; ++k) acc[r * NC + k] += s[k];
+            } else {
+                double gr[3] = {H[0][0], H[0][1], H[0][2]};
+                gr[r] += vol;
+                double q[3];
+                flux_ti<double>(gr, a, m, q);
+                for (int k = 0; k < 3; ++k) acc[r * NC + k] += q[k];
+            }
+        }
+    }
+    __shared__ double red[R * NC][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < R * NC; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) red[k][wv] = v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < R * NC; k += blockDim.x) {
+        double s = 0.0;
+        for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) s += red[k][w2];
+        partial[((long long)prob * gridDim.x + blockIdx.x) * R * NC + k] = s;
+    }
+}
+
+// out[prob][i][j] = (1/V) sum of partials: row i = stress/flux component, column j = load case.
+template <int C, int R>
+__global__ void average_finish_kernel(int nwg, const double *partial, double volume, double *out) {
+    constexpr int NC = (C == 3) ? 6 : 3;
+    const int prob = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (int k = 0; k < R * NC; ++k) {
+        double s = 0.0;
+        for (int w = lane; w < nwg; w += 64) s += partial[((long long)prob * nwg + w) * R * NC + k];
+        s = wave_sum(s);
+        if (lane == 0) {
+            const int r = k / NC, i = k % NC;   // load case r, component i
+            out[(long long)prob * NC * R + i * R + r] = s / volume;
+        }
+    }
+}
+
+template <int C, int R>
+hipError_t launch_average(const Geo &G, const Prob *probs, int nprob, long long vpp,
+                          const double *x64, double *partial, int nwg, double *out, hipStream_t s) {
+    dim3 grid(nwg, nprob);
+    average_kernel<C, R><<<grid, 256, 0, s>>>(G, probs, vpp, x64, partial);
+    average_finish_kernel<C, R><<<nprob, FIN_BS, 0, s>>>(nwg, partial, G.volume, out);
+    return hipGetLastError();
+}
+template hipError_t launch_average<3, 6>(const Geo &, const Prob *, int, long long, const double *, double *, int, double *, hipStream_t);
+template hipError_t launch_average<1, 3>(const Geo &, const Prob *, int, long long, const double *, double *, int, double *, hipStream_t);
+
+}  // namespace chom

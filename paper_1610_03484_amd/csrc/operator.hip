@@ -1,0 +1,187 @@
+// Matrix-free stiffness / conductivity operator Y = K X for the order-2
+// hierarchic space on the Kuhn lattice (K is the standard FE matrix of Sec. 2,
+// Eq. eq_RVE_disc_Eqs, and its scalar analogue, Eq. eq_RVE_disc_Eqs_field).
+//
+// One workgroup owns a tile of TX x TY x TZ cells (6 tets each).  It stages the
+// (2T+1)^3 DOF box of its tile from HBM into LDS with coalesced loads, applies
+// every tet of the tile for every load case (element data: fibre axis + phase,
+// 16/32 bytes; the stiffness is evaluated on the fly from five invariants),
+// accumulates the element results in a second LDS box with LDS atomics, and
+// stores the whole box, contiguous, to its slot of the tile-box output (no
+// global atomics, no zeroing pass); consumers sum the copies of points on
+// shared tile faces.  The element energies x_e . K_e x_e of all tets are
+// summed on the fly in FP64, giving p.Kp for CG without another sweep.
+#include "common.h"
+#include "internal.h"
+
+#include <type_traits>
+
+namespace chom {
+
+int operator_tiles(const Geo &G) { return G.tiles_x * G.tiles_y * G.tiles_z; }
+
+// Load cases are split into NG = R / RG groups; a workgroup handles one tile
+// and one group (grid.x = tiles * NG), with one thread per tet.  The LDS
+// accumulator is FP64 (LDS FP64 atomic adds are markedly faster than FP32 ones
+// on gfx950) and the per-point strides are padded by one element to spread
+// LDS banks.  Output layout: [prob][tile][group][box point][RG * C].
+template <typename T, int C, int R, int RG>
+__global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(Geo G, const Prob *probs, const T *__restrict__ x,
+                                                          T *__restrict__ y, double *partial_pq,
+                                                          const int *prob_active) {
+    constexpr int NG = R / RG;
+    constexpr int RC = R * C;
+    constexpr int RCg = RG * C;
+    constexpr int PS = RCg + 1;
+    constexpr int NBOX = BOXPTS * RCg;
+    constexpr int NST = (NBOX + TILE_TETS - 1) / TILE_TETS;
+    constexpr int NCELL = TX * TY * TZ;
+    constexpr int NW = TILE_TETS / 64;
+    using V4 = typename std::conditional<std::is_same<T, double>::value, double4, float4>::type;
+    __shared__ T xs[BOXPTS * PS];
+    __shared__ double ys[BOXPTS * PS];
+    __shared__ V4 se[TILE_TETS];
+    __shared__ T sg[6][10];
+    __shared__ double red[RG][NW];
+    const int prob = blockIdx.y;
+    const int tile = blockIdx.x / NG, grp = blockIdx.x - (blockIdx.x / NG) * NG;
+    const int ntiles = gridDim.x / NG;
+    const int tt = threadIdx.x;
+    if (prob_active != nullptr && prob_active[prob] == 0) {
+        if (tt < RG) partial_pq[((long long)prob * R + grp * RG + tt) * ntiles + tile] = 0.0;
+        return;
+    }
+    const Prob P = probs[prob];
+    const int n = G.n, m2 = 2 * n;
+    const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, tz = tile / (G.tiles_x * G.tiles_y);
+    const int cx0 = tx * TX, cy0 = ty * TY, cz0 = tz * TZ;
+    const int X0 = 2 * cx0, Y0 = 2 * cy0, Z0 = 2 * cz0;
+    const int hx = min(X0 + 2 * TX, m2), hy = min(Y0 + 2 * TY, m2), hz = min(Z0 + 2 * TZ, m2);
+    const T *xp = x + P.voff + grp * RCg;
+
+    // ---- stage the DOF box (this group's values), element data, geometry;
+    // all loads of a thread are issued before the LDS stores.
+    T tmp[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+        const int i = tt + TILE_TETS * k;
+        T val = T(0);
+        if (i < NBOX) {
+            const int pt = i / RCg, v = i - pt * RCg;
+            const int bx = pt % BX, by = (pt / BX) % BY, bz = pt / (BX * BY);
+            const int X = X0 + bx, Y = Y0 + by, Z = Z0 + bz;
+            if (X <= hx && Y <= hy && Z <= hz) val = xp[lat_index(G, X, Y, Z) * RC + v];
+        }
+        tmp[k] = val;
+    }
+    const int type = tt / NCELL, lc = tt - (tt / NCELL) * NCELL;
+    const int lcx = lc % TX, lcy = (lc / TX) % TY, lcz = lc / (TX * TY);
+    const int ci = cx0 + lcx, cj = cy0 + lcy, ck = cz0 + lcz;
+    const bool live = (ci < n && cj < n && ck < n);
+    const long long tet = ((long long)ci + (long long)n * (cj + (long long)n * ck)) * 6 + type;
+    V4 ev;
+    if (live) {
+        if constexpr (std::is_same<T, double>::value) ev = G.elem64[tet]; else ev = G.elem32[tet];
+    }
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+        const int i = tt + TILE_TETS * k;
+        if (i < NBOX) {
+            const int pt = i / RCg, v = i - pt * RCg;
+            xs[pt * PS + v] = tmp[k];
+        }
+    }
+    for (int i = tt; i < BOXPTS * PS; i += TILE_TETS) ys[i] = 0.0;
+    if (tt < 60 && G.uniform) {
+        if constexpr (std::is_same<T, double>::value) sg[tt / 10][tt % 10] = G.tg64[tt / 10][tt % 10];
+        else sg[tt / 10][tt % 10] = G.tg32[tt / 10][tt % 10];
+    }
+    __syncthreads();
+
+    // ---- element work: one tet per thread, the group's load cases in turn
+    double pq[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) pq[r] = 0.0;
+    if (live) {
+        T g[4][3], vol, a[3];
+        if (G.uniform) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) g[i + 1][j] = sg[type][3 * i + j];
+            vol = sg[type][9];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
+        } else {
+            GeoSel<T>::get(G, tet, type, g, vol);
+        }
+        a[0] = ev.x; a[1] = ev.y; a[2] = ev.z;
+        const T *mt = prob_mat<T>(P, (int)ev.w);
+        T mloc[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) mloc[k] = mt[k];
+        int off[10][3];
+        p2_dof_offsets(type, off);
+        int lp[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            lp[k] = ((2 * lcx + off[k][0]) + BX * ((2 * lcy + off[k][1]) + BY * (2 * lcz + off[k][2]))) * PS;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            T u[10][C], yv[10][C];
+#pragma unroll
+            for (int k = 0; k < 10; ++k)
+#pragma unroll
+                for (int c = 0; c < C; ++c) u[k][c] = xs[lp[k] + r * C + c];
+            p2_apply<T, C>(g, vol, a, mloc, u, yv);
+            double en = 0.0;
+#pragma unroll
+            for (int k = 0; k < 10; ++k)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    en += (double)u[k][c] * (double)yv[k][c];
+                    atomicAdd(&ys[lp[k] + r * C + c], (double)yv[k][c]);
+                }
+            pq[r] = en;
+        }
+    }
+    __syncthreads();
+
+    // ---- write this group's tile box (contiguous, coalesced)
+    T *qt = y + (((long long)prob * ntiles + tile) * NG + grp) * NBOX;
+    for (int i = tt; i < NBOX; i += TILE_TETS) {
+        const int pt = i / RCg, v = i - pt * RCg;
+        qt[i] = (T)ys[pt * PS + v];
+    }
+
+    // ---- element-energy partial sums (layout [prob][load case][tile])
+    const int lane = tt & 63, wv = tt >> 6;
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+        const double s = wave_sum(pq[r]);
+        if (lane == 0) red[r][wv] = s;
+    }
+    __syncthreads();
+    if (tt < RG) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += red[tt][w];
+        partial_pq[((long long)prob * R + grp * RG + tt) * ntiles + tile] = s;
+    }
+}
+
+template <typename T, int C, int R>
+hipError_t launch_operator(const Geo &G, const Prob *probs, int nprob, const T *x, T *y,
+                           double *partial_pq, const int *prob_active, hipStream_t s) {
+    constexpr int RG = OpGroup<C, R>::RG;
+    dim3 grid(operator_tiles(G) * (R / RG), nprob);
+    op_p2_kernel<T, C, R, RG><<<grid, TILE_TETS, 0, s>>>(G, probs, x, y, partial_pq, prob_active);
+    return hipGetLastError();
+}
+
+template hipError_t launch_operator<double, 3, 6>(const Geo &, const Prob *, int, const double *, double *, double *, const int *, hipStream_t);
+template hipError_t launch_operator<float, 3, 6>(const Geo &, const Prob *, int, const float *, float *, double *, const int *, hipStream_t);
+template hipError_t launch_operator<double, 1, 3>(const Geo &, const Prob *, int, const double *, double *, double *, const int *, hipStream_t);
+template hipError_t launch_operator<float, 1, 3>(const Geo &, const Prob *, int, const float *, float *, double *, const int *, hipStream_t);
+
+}  // namespace chom

@@ -1,0 +1,492 @@
+// Per-RVE and per-problem setup kernels: element data, constraint rows,
+// block-Jacobi preconditioner, Gram matrices of the constraint projection and
+// the load vectors of the unit macro strains / gradients.
+#include "common.h"
+#include "internal.h"
+
+namespace chom {
+
+static inline int grid_for(long long work, int bs, int cap = 16384) {
+    long long g = (work + bs - 1) / bs;
+    if (g < 1) g = 1;
+    return (int)(g < cap ? g : cap);
+}
+
+// ------------------------------------------------------------------ element data
+__global__ void element_setup_kernel(Geo G, const double *coords, const int8_t *phase,
+                                     const double *axis, double4 *elem64, float4 *elem32,
+                                     double *geo64, float *geo32, int *bad) {
+    const int n = G.n, n1 = n + 1;
+    const long long nt = 6LL * n * n * n;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int ph = phase[e];
+        double a[3] = {axis[3 * e], axis[3 * e + 1], axis[3 * e + 2]};
+        if (ph == 0) a[0] = a[1] = a[2] = 0.0;
+        elem64[e] = make_double4(a[0], a[1], a[2], (double)ph);
+        elem32[e] = make_float4((float)a[0], (float)a[1], (float)a[2], (float)ph);
+        if (geo64 == nullptr) continue;
+        const int t = (int)(e % 6);
+        const long long cell = e / 6;
+        const int ci = (int)(cell % n), cj = (int)((cell / n) % n), ck = (int)(cell / ((long long)n * n));
+        int p0, p1;
+        kuhn_perm(t, p0, p1);
+        int v[4][3] = {{ci, cj, ck}, {ci, cj, ck}, {ci, cj, ck}, {ci + 1, cj + 1, ck + 1}};
+        v[1][p0] += 1;
+        v[2][p0] += 1;
+        v[2][p1] += 1;
+        double x[4][3];
+        for (int k = 0; k < 4; ++k) {
+            const long long id = v[k][0] + (long long)n1 * (v[k][1] + (long long)n1 * v[k][2]);
+            for (int d = 0; d < 3; ++d) x[k][d] = coords[3 * id + d];
+        }
+        double J[3][3];  // columns x1-x0, x2-x0, x3-x0
+        for (int c = 0; c < 3; ++c)
+            for (int d = 0; d < 3; ++d) J[d][c] = x[c + 1][d] - x[0][d];
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        // expected orientation: sign of the axis permutation (even: t = 0, 3, 4)
+        const double sgn = (t == 0 || t == 3 || t == 4) ? 1.0 : -1.0;
+        if (!(det * sgn > 0.0)) atomicAdd(bad, 1);
+        const double id = 1.0 / det;
+        // rows of J^-1 are the gradients of lam_1..3
+        double Ji[3][3];
+        Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+        Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+        Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+        double *g64 = geo64 + e * 10;
+        float *g32 = geo32 + e * 10;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                g64[3 * i + j] = Ji[i][j];
+                g32[3 * i + j] = (float)Ji[i][j];
+            }
+        g64[9] = fabs(det) / 6.0;
+        g32[9] = (float)(fabs(det) / 6.0);
+    }
+}
+
+hipError_t launch_element_setup(const Geo &G, const double *coords, const int32_t *,
+                                const int8_t *phase, const double *axis, double4 *elem64,
+                                float4 *elem32, double *geo64, float *geo32, int *bad_count,
+                                hipStream_t s) {
+    const long long nt = 6LL * G.n * G.n * G.n;
+    element_setup_kernel<<<grid_for(nt, 256), 256, 0, s>>>(G, coords, phase, axis, elem64, elem32,
+                                                           geo64, geo32, bad_count);
+    return hipGetLastError();
+}
+
+// Decode tet id -> (cell coords, type) and the 10 DOF lattice points.
+__device__ inline void tet_points(const Geo &G, long long e, int &t, int P[10][3]) {
+    const int n = G.n;
+    t = (int)(e % 6);
+    const long long cell = e / 6;
+    const int ci = (int)(cell % n), cj = (int)((cell / n) % n), ck = (int)(cell / ((long long)n * n));
+    int off[10][3];
+    p2_dof_offsets(t, off);
+    for (int k = 0; k < 10; ++k) {
+        P[k][0] = 2 * ci + off[k][0];
+        P[k][1] = 2 * cj + off[k][1];
+        P[k][2] = 2 * ck + off[k][2];
+    }
+}
+
+// ------------------------------------------------------------------ constraint rows
+// Per DOF: int grad(phi) dV (3) and int phi dV (1).  For interior DOFs the
+// gradient integral vanishes; for boundary DOFs it is the surface moment
+// int phi n dS of the uniform-traction rows (divergence theorem).
+__global__ void rows_kernel(Geo G, double *rows) {
+    const long long nt = 6LL * G.n * G.n * G.n;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
+         e += (long long)gridDim.x * blockDim.x) {
+        int t, P[10][3];
+        tet_points(G, e, t, P);
+        double g[4][3], vol;
+        GeoSel<double>::get(G, e, t, g, vol);
+        for (int k = 0; k < 10; ++k) {
+            double m[3], w;
+            if (k < 4) {
+                for (int d = 0; d < 3; ++d) m[d] = vol * g[k][d];
+                w = 0.25 * vol;
+            } else {
+                int a, b;
+                edge_verts(k - 4, a, b);
+                for (int d = 0; d < 3; ++d) m[d] = vol * (g[a][d] + g[b][d]);
+                w = 0.2 * vol;
+            }
+            const long long idx = lat_index(G, P[k][0], P[k][1], P[k][2]);
+            for (int d = 0; d < 3; ++d) atomicAdd(&rows[4 * idx + d], m[d]);
+            atomicAdd(&rows[4 * idx + 3], w);
+        }
+    }
+}
+
+hipError_t launch_rows(const Geo &G, double *rows, hipStream_t s) {
+    hipError_t err = hipMemsetAsync(rows, 0, sizeof(double) * 4 * G.npts, s);
+    if (err != hipSuccess) return err;
+    const long long nt = 6LL * G.n * G.n * G.n;
+    rows_kernel<<<grid_for(nt, 256), 256, 0, s>>>(G, rows);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ preconditioner
+// Acoustic tensor Q(w)_cd = sum_kl C_ckdl w_k w_l from the stress law.
+__device__ inline void acoustic(const double w[3], const double a[3], const double *m, double Q[3][3]) {
+    for (int d = 0; d < 3; ++d) {
+        double e[6] = {0, 0, 0, 0, 0, 0};
+        // sym(e_d (x) w)
+        double G3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int l = 0; l < 3; ++l) G3[d][l] = w[l];
+        e[0] = G3[0][0];
+        e[1] = G3[1][1];
+        e[2] = G3[2][2];
+        e[3] = 0.5 * (G3[0][1] + G3[1][0]);
+        e[4] = 0.5 * (G3[1][2] + G3[2][1]);
+        e[5] = 0.5 * (G3[2][0] + G3[0][2]);
+        double s[6];
+        stress_ti<double>(e, a, m, s);
+        Q[0][d] = s[0] * w[0] + s[3] * w[1] + s[5] * w[2];
+        Q[1][d] = s[3] * w[0] + s[1] * w[1] + s[4] * w[2];
+        Q[2][d] = s[5] * w[0] + s[4] * w[1] + s[2] * w[2];
+    }
+}
+
+template <int C>
+__global__ void diag_kernel(Geo G, const Prob *probs, double *diag) {
+    constexpr int MS = (C == 3) ? 6 : 1;
+    const Prob P = probs[blockIdx.y];
+    double *D = diag + (long long)blockIdx.y * G.npts * MS;
+    const long long nt = 6LL * G.n * G.n * G.n;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
+         e += (long long)gridDim.x * blockDim.x) {
+        int t, Pt[10][3];
+        tet_points(G, e, t, Pt);
+        double g[4][3], vol, a[3];
+        int ph;
+        GeoSel<double>::get(G, e, t, g, vol);
+        GeoSel<double>::elem(G, e, a, ph);
+        const double *m = P.mat64[ph ? 1 : 0];
+        for (int k = 0; k < 10; ++k) {
+            if (dirichlet_boundary(G, Pt[k][0], Pt[k][1], Pt[k][2])) continue;
+            const long long idx = lat_index(G, Pt[k][0], Pt[k][1], Pt[k][2]);
+            // decomposition sum_m c_m w_m w_m^T of int grad(phi) grad(phi)^T
+            double ws[3][3], cs[3];
+            int nw;
+            if (k < 4) {
+                nw = 1;
+                for (int d = 0; d < 3; ++d) ws[0][d] = g[k][d];
+                cs[0] = vol;
+            } else {
+                int a2, b2;
+                edge_verts(k - 4, a2, b2);
+                nw = 3;
+                for (int d = 0; d < 3; ++d) {
+                    ws[0][d] = g[a2][d] + g[b2][d];
+                    ws[1][d] = g[a2][d];
+                    ws[2][d] = g[b2][d];
+                }
+                cs[0] = cs[1] = cs[2] = 0.8 * vol;
+            }
+            if constexpr (C == 3) {
+                double acc[6] = {0, 0, 0, 0, 0, 0};
+                for (int q = 0; q < nw; ++q) {
+                    double Q[3][3];
+                    acoustic(ws[q], a, m, Q);
+                    acc[0] += cs[q] * Q[0][0];
+                    acc[1] += cs[q] * Q[1][1];
+                    acc[2] += cs[q] * Q[2][2];
+                    acc[3] += cs[q] * Q[0][1];
+                    acc[4] += cs[q] * Q[1][2];
+                    acc[5] += cs[q] * Q[0][2];
+                }
+                for (int c = 0; c < 6; ++c) atomicAdd(&D[6 * idx + c], acc[c]);
+            } else {
+                double acc = 0.0;
+                for (int q = 0; q < nw; ++q) {
+                    double fl[3];
+                    flux_ti<double>(ws[q], a, m, fl);
+                    acc += cs[q] * (fl[0] * ws[q][0] + fl[1] * ws[q][1] + fl[2] * ws[q][2]);
+                }
+                atomicAdd(&D[idx], acc);
+            }
+        }
+    }
+}
+
+template <int C>
+__global__ void invert_diag_kernel(Geo G, int nprob, const double *diag, double *minv64, float *minv32) {
+    constexpr int MS = (C == 3) ? 6 : 1;
+    const long long total = (long long)nprob * G.npts;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double *d = diag + i * MS;
+        double *o = minv64 + i * MS;
+        float *o32 = minv32 + i * MS;
+        if constexpr (C == 3) {
+            const double a = d[0], b = d[1], c = d[2], xy = d[3], yz = d[4], xz = d[5];
+            const double c00 = b * c - yz * yz, c11 = a * c - xz * xz, c22 = a * b - xy * xy;
+            const double c01 = xz * yz - xy * c, c12 = xy * xz - a * yz, c02 = xy * yz - b * xz;
+            const double det = a * c00 + xy * c01 + xz * c02;
+            double r[6] = {0, 0, 0, 0, 0, 0};
+            if (det > 0.0) {
+                const double id = 1.0 / det;
+                r[0] = c00 * id; r[1] = c11 * id; r[2] = c22 * id;
+                r[3] = c01 * id; r[4] = c12 * id; r[5] = c02 * id;
+            }
+            for (int k = 0; k < 6; ++k) {
+                o[k] = r[k];
+                o32[k] = (float)r[k];
+            }
+        } else {
+            const double r = d[0] > 0.0 ? 1.0 / d[0] : 0.0;
+            o[0] = r;
+            o32[0] = (float)r;
+        }
+    }
+}
+
+template <int C>
+hipError_t launch_precond(const Geo &G, const Prob *probs, int nprob, double *diag,
+                          double *minv64, float *minv32, hipStream_t s) {
+    constexpr int MS = (C == 3) ? 6 : 1;
+    hipError_t err = hipMemsetAsync(diag, 0, sizeof(double) * MS * G.npts * nprob, s);
+    if (err != hipSuccess) return err;
+    const long long nt = 6LL * G.n * G.n * G.n;
+    dim3 grid(grid_for(nt, 256, 2048), nprob);
+    diag_kernel<C><<<grid, 256, 0, s>>>(G, probs, diag);
+    invert_diag_kernel<C><<<grid_for(G.npts * nprob, 256), 256, 0, s>>>(G, nprob, diag, minv64, minv32);
+    return hipGetLastError();
+}
+template hipError_t launch_precond<3>(const Geo &, const Prob *, int, double *, double *, float *, hipStream_t);
+template hipError_t launch_precond<1>(const Geo &, const Prob *, int, double *, double *, float *, hipStream_t);
+
+// ------------------------------------------------------------------ Gram matrices
+// G[(i,a),(j,b)] = sum_pt row_a(pt) row_b(pt) Minv_pt[i][j] for the rows of the
+// boundary condition (periodic: int phi; Neumann: int grad(phi), int phi), with
+// the FP64 and with the FP32 preconditioner.  Unique sums: sym(Minv) x sym(rows).
+constexpr int GRAM_CHUNK = 256;
+
+template <int C>
+__global__ void gram_partial_kernel(Geo G, const double *minv64, const float *minv32, double *partial) {
+    constexpr int MS = (C == 3) ? 6 : 1;
+    const int nrow = G.nrow;
+    const int rfirst = (nrow == 1) ? 3 : 0;  // periodic uses only int phi
+    const int nRs = nrow * (nrow + 1) / 2;
+    const int nU = MS * nRs;
+    __shared__ double sm64[GRAM_CHUNK][MS];
+    __shared__ double sm32[GRAM_CHUNK][MS];
+    __shared__ double sr[GRAM_CHUNK][4];
+    const int prob = blockIdx.y;
+    const double *M64 = minv64 + (long long)prob * G.npts * MS;
+    const float *M32 = minv32 + (long long)prob * G.npts * MS;
+    // each thread owns unique sum u (two precisions)
+    const int u = threadIdx.x;
+    int mi = 0, ra = 0, rb = 0;
+    if (u < nU) {
+        mi = u / nRs;
+        int rr = u % nRs;
+        for (ra = 0; ra < nrow; ++ra) {
+            if (rr < nrow - ra) { rb = ra + rr; break; }
+            rr -= nrow - ra;
+        }
+    }
+    double acc64 = 0.0, acc32 = 0.0;
+    const long long per = (G.npts + gridDim.x - 1) / gridDim.x;
+    const long long p0 = blockIdx.x * per;
+    const long long p1 = (p0 + per < G.npts) ? p0 + per : G.npts;
+    for (long long base = p0; base < p1; base += GRAM_CHUNK) {
+        __syncthreads();
+        const long long pt = base + threadIdx.x;
+        if (threadIdx.x < GRAM_CHUNK) {
+            if (pt < p1) {
+                for (int k = 0; k < MS; ++k) {
+                    sm64[threadIdx.x][k] = M64[pt * MS + k];
+                    sm32[threadIdx.x][k] = (double)M32[pt * MS + k];
+                }
+                for (int k = 0; k < 4; ++k) sr[threadIdx.x][k] = G.rows[4 * pt + k];
+            } else {
+                for (int k = 0; k < MS; ++k) sm64[threadIdx.x][k] = sm32[threadIdx.x][k] = 0.0;
+                for (int k = 0; k < 4; ++k) sr[threadIdx.x][k] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (u < nU) {
+            for (int q = 0; q < GRAM_CHUNK; ++q) {
+                const double rp = sr[q][rfirst + ra] * sr[q][rfirst + rb];
+                acc64 += rp * sm64[q][mi];
+                acc32 += rp * sm32[q][mi];
+            }
+        }
+    }
+    if (u < nU) {
+        double *out = partial + ((long long)prob * gridDim.x + blockIdx.x) * 2 * nU;
+        out[u] = acc64;
+        out[nU + u] = acc32;
+    }
+}
+
+// Expand the unique sums of one problem, invert (Gauss-Jordan, pivoted), store.
+template <int C>
+__global__ void gram_finish_kernel(int nprob, int nrow, int nwg, const double *partial,
+                                   double *ginv64, double *ginv32, int *bad) {
+    constexpr int MS = (C == 3) ? 6 : 1;
+    const int prob = blockIdx.x * blockDim.x + threadIdx.x;
+    if (prob >= nprob || nrow == 0) return;
+    const int nRs = nrow * (nrow + 1) / 2;
+    const int nU = MS * nRs;
+    const int S = C * nrow;
+    for (int which = 0; which < 2; ++which) {
+        double A[12][24];
+        for (int I = 0; I < S; ++I)
+            for (int J = 0; J < S; ++J) {
+                const int i = I / nrow, a = I % nrow, j = J / nrow, b = J % nrow;
+                int mi;
+                if (C == 3) {
+                    const int lo = i < j ? i : j, hi = i < j ? j : i;
+                    mi = (lo == hi) ? lo : (lo == 0 && hi == 1 ? 3 : (lo == 1 && hi == 2 ? 4 : 5));
+                } else {
+                    mi = 0;
+                }
+                const int ra = a < b ? a : b, rb = a < b ? b : a;
+                int ri = 0;
+                for (int q = 0; q < ra; ++q) ri += nrow - q;
+                ri += rb - ra;
+                const int u = mi * nRs + ri;
+                double s = 0.0;
+                for (int w = 0; w < nwg; ++w) s += partial[((long long)prob * nwg + w) * 2 * nU + which * nU + u];
+                A[I][J] = s;
+                A[I][S + J] = (I == J) ? 1.0 : 0.0;
+            }
+        int ok = 1;
+        for (int c = 0; c < S; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < S; ++r)
+                if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+            if (!(fabs(A[piv][c]) > 0.0)) { ok = 0; break; }
+            if (piv != c)
+                for (int k = 0; k < 2 * S; ++k) { double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
+            const double ip = 1.0 / A[c][c];
+            for (int k = 0; k < 2 * S; ++k) A[c][k] *= ip;
+            for (int r = 0; r < S; ++r) {
+                if (r == c) continue;
+                const double f = A[r][c];
+                if (f != 0.0)
+                    for (int k = 0; k < 2 * S; ++k) A[r][k] -= f * A[c][k];
+            }
+        }
+        if (!ok) atomicAdd(bad, 1);
+        double *out = (which == 0 ? ginv64 : ginv32) + (long long)prob * S * S;
+        for (int I = 0; I < S; ++I)
+            for (int J = 0; J < S; ++J) out[I * S + J] = ok ? A[I][S + J] : 0.0;
+    }
+}
+
+template <int C>
+hipError_t launch_gram(const Geo &G, int nprob, const double *minv64, const float *minv32,
+                       double *gram_partial, int nwg, double *ginv64, double *ginv32, int *bad,
+                       hipStream_t s) {
+    if (G.nrow == 0) return hipSuccess;
+    dim3 grid(nwg, nprob);
+    gram_partial_kernel<C><<<grid, GRAM_CHUNK, 0, s>>>(G, minv64, minv32, gram_partial);
+    gram_finish_kernel<C><<<(nprob + 63) / 64, 64, 0, s>>>(nprob, G.nrow, nwg, gram_partial, ginv64, ginv32, bad);
+    return hipGetLastError();
+}
+template hipError_t launch_gram<3>(const Geo &, int, const double *, const float *, double *, int, double *, double *, int *, hipStream_t);
+template hipError_t launch_gram<1>(const Geo &, int, const double *, const float *, double *, int, double *, double *, int *, hipStream_t);
+
+// ------------------------------------------------------------------ load vectors
+// b_i = - int grad(phi_i) : C eps_k dV for the unit strains (or - int grad(phi_i) . k e_k
+// for unit gradients), i.e. minus the stiffness times the interpolated linear
+// field; also the energy of the linear field eps_k : C_e eps_k |e| (reference
+// scale of the stopping test).
+template <int C, int R>
+__global__ void rhs_kernel(Geo G, const Prob *probs, long long vpp, double *b, ColState *cols) {
+    const int prob = blockIdx.y;
+    const Prob P = probs[prob];
+    double *bp = b + (long long)prob * vpp;
+    const long long nt = 6LL * G.n * G.n * G.n;
+    double eref[R];
+    for (int k = 0; k < R; ++k) eref[k] = 0.0;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
+         e += (long long)gridDim.x * blockDim.x) {
+        int t, Pt[10][3];
+        tet_points(G, e, t, Pt);
+        double g[4][3], vol, a[3];
+        int ph;
+        GeoSel<double>::get(G, e, t, g, vol);
+        GeoSel<double>::elem(G, e, a, ph);
+        const double *m = P.mat64[ph ? 1 : 0];
+        for (int k = 0; k < R; ++k) {
+            double sig[3][3];
+            if constexpr (C == 3) {
+                double eps[6] = {0, 0, 0, 0, 0, 0};
+                if (k < 3) eps[k] = 1.0; else eps[k] = 0.5;  // engineering shear 1
+                double s[6];
+                stress_ti<double>(eps, a, m, s);
+                sig[0][0] = s[0]; sig[1][1] = s[1]; sig[2][2] = s[2];
+                sig[0][1] = sig[1][0] = s[3];
+                sig[1][2] = sig[2][1] = s[4];
+                sig[2][0] = sig[0][2] = s[5];
+                eref[k] += vol * s[k];
+            } else {
+                double gk[3] = {0, 0, 0};
+                gk[k] = 1.0;
+                double q[3];
+                flux_ti<double>(gk, a, m, q);
+                sig[0][0] = q[0]; sig[0][1] = q[1]; sig[0][2] = q[2];
+                eref[k] += vol * q[k];
+            }
+            for (int kk = 0; kk < 10; ++kk) {
+                if (dirichlet_boundary(G, Pt[kk][0], Pt[kk][1], Pt[kk][2])) continue;
+                double w[3];
+                if (kk < 4) {
+                    for (int d = 0; d < 3; ++d) w[d] = vol * g[kk][d];
+                } else {
+                    int a2, b2;
+                    edge_verts(kk - 4, a2, b2);
+                    for (int d = 0; d < 3; ++d) w[d] = vol * (g[a2][d] + g[b2][d]);
+                }
+                const long long idx = lat_index(G, Pt[kk][0], Pt[kk][1], Pt[kk][2]);
+                for (int c = 0; c < C; ++c) {
+                    const double v = -(sig[c][0] * w[0] + sig[c][1] * w[1] + sig[c][2] * w[2]);
+                    atomicAdd(&bp[(idx * R + k) * C + c], v);
+                }
+            }
+        }
+    }
+    // block reduction of eref, one atomic per block and load case
+    __shared__ double red[R][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < R; ++k) {
+        const double v = wave_sum(eref[k]);
+        if (lane == 0) red[k][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[threadIdx.x][w];
+        atomicAdd(&cols[prob * R + threadIdx.x].eref, s);
+    }
+}
+
+template <int C, int R>
+hipError_t launch_rhs(const Geo &G, const Prob *probs, int nprob, long long vpp, double *b,
+                      ColState *cols, hipStream_t s) {
+    hipError_t err = hipMemsetAsync(b, 0, sizeof(double) * vpp * nprob, s);
+    if (err != hipSuccess) return err;
+    const long long nt = 6LL * G.n * G.n * G.n;
+    dim3 grid(grid_for(nt, 256, 2048), nprob);
+    rhs_kernel<C, R><<<grid, 256, 0, s>>>(G, probs, vpp, b, cols);
+    return hipGetLastError();
+}
+template hipError_t launch_rhs<3, 6>(const Geo &, const Prob *, int, long long, double *, ColState *, hipStream_t);
+template hipError_t launch_rhs<1, 3>(const Geo &, const Prob *, int, long long, double *, ColState *, hipStream_t);
+
+}  // namespace chom

@@ -1,0 +1,108 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Sizes are chosen so the oracle finishes in seconds while the operator still
+spans several tiles (4 x 4 x 2 cells) and a ragged tail (n = 5, 9).
+Tolerances: FP64 path 1e-9 relative Frobenius error on C_bar, K_bar, D_bar;
+FP32 operator with FP64 refinement 1e-6 (the targets of the workload).
+"""
+import numpy as np
+import pytest
+
+import chom_inputs as ci
+from oracle import fem as ofem, mesh as omesh
+
+from gpu_util import banner, rel, require_gpu, upper21, upper6
+
+pytestmark = pytest.mark.gpu
+
+BCS = ["dirichlet", "periodic", "neumann"]
+BC_ID = {"dirichlet": ofem.BC_DIRICHLET, "periodic": ofem.BC_PERIODIC, "neumann": ofem.BC_NEUMANN}
+_ORACLE_CACHE = {}
+
+
+def oracle_result(n, bc, params, key):
+    k = (n, bc, key)
+    if k not in _ORACLE_CACHE:
+        c, t, ph, ax = omesh.plain_weave(n)
+        _ORACLE_CACHE[k] = ofem.homogenise(c, t, ph, ax, 2, BC_ID[bc], ci.BASE_MATERIALS, params)
+    return _ORACLE_CACHE[k]
+
+
+def gpu_rve(n, bc, **opts):
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    coords, tets, phase, axis = generate_plain_weave(n, device="cuda")
+    return RVE(coords, tets, phase, axis, ci.BASE_MATERIALS, bc=bc, **opts)
+
+
+def errors(C, K, D, ref):
+    return (rel(C, upper21(ref["C"])), rel(K, upper6(ref["K"])), rel(D, upper6(ref["D"])))
+
+
+def test_generator_matches_oracle():
+    torch = require_gpu()
+    from paper_1610_03484_amd import generate_plain_weave
+    for n in (3, 8, 24):
+        banner(f"generator n={n}")
+        coords, tets, phase, axis = (t.cpu().numpy() for t in generate_plain_weave(n, device="cuda"))
+        oc, ot, oph, oax = omesh.plain_weave(n)
+        assert np.array_equal(coords, oc)
+        assert np.array_equal(tets, ot)
+        cen = omesh.centroids(oc, ot)
+        near = omesh.yarn_margin(cen[:, 0], cen[:, 1], cen[:, 2]) < 1e-12
+        assert np.array_equal(phase[~near], oph[~near])
+        assert np.allclose(axis[~near], oax[~near], rtol=0, atol=1e-14)
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [3, 5])
+@pytest.mark.parametrize("bc", BCS)
+def test_parity_fp64_degraded(n, bc):
+    require_gpu()
+    params = ci.draw_params(11, 1)[0]
+    banner(f"fp64 n={n} bc={bc} params={np.round(params[:3], 3)}")
+    rve = gpu_rve(n, bc, precision="fp64")
+    C, K, D, rep = rve.homogenise(params[None])
+    ref = oracle_result(n, bc, params, "deg11")
+    eC, eK, eD = errors(C[0], K[0], D[0], ref)
+    banner(f"  errors C={eC:.2e} K={eK:.2e} D={eD:.2e} iters={rep[0]['iters']}")
+    assert rep[0]["status"] == 0
+    assert max(eC, eK, eD) < 1e-9
+
+
+def test_parity_c0_config_fp64():
+    """8^3 cells, p = 2, linear Dirichlet, FP64, 12 load cases, factors only."""
+    require_gpu()
+    params = ci.draw_factors_only(0, 1)[0]
+    banner("c0 fp64 n=8 dirichlet")
+    rve = gpu_rve(8, "dirichlet", precision="fp64")
+    C, K, D, rep = rve.homogenise(params[None])
+    ref = oracle_result(8, "dirichlet", params, "f0")
+    eC, eK, eD = errors(C[0], K[0], D[0], ref)
+    banner(f"  errors C={eC:.2e} K={eK:.2e} D={eD:.2e} iters={rep[0]['iters']}")
+    assert max(eC, eK, eD) < 1e-9
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_parity_fp32_refined(bc):
+    require_gpu()
+    n = 5
+    params = ci.draw_params(11, 1)[0]
+    banner(f"fp32-refined n={n} bc={bc}")
+    rve = gpu_rve(n, bc, precision="fp32_refined", rtol=1e-10)
+    C, K, D, rep = rve.homogenise(params[None])
+    ref = oracle_result(n, bc, params, "deg11")
+    eC, eK, eD = errors(C[0], K[0], D[0], ref)
+    banner(f"  errors C={eC:.2e} K={eK:.2e} D={eD:.2e} refine={rep[0]['refine_steps']} iters={rep[0]['iters']}")
+    assert rep[0]["status"] == 0
+    assert max(eC, eK, eD) < 1e-6
+
+
+def test_batch_equals_single_calls():
+    require_gpu()
+    params = ci.draw_params(5, 3)
+    banner("batch of 3 vs single")
+    rve = gpu_rve(4, "periodic", precision="fp64")
+    Cb, Kb, Db, _ = rve.homogenise(params)
+    for i in range(3):
+        C, K, D, _ = rve.homogenise(params[i:i + 1])
+        assert rel(Cb[i], C[0]) < 1e-12 and rel(Kb[i], K[0]) < 1e-12 and rel(Db[i], D[0]) < 1e-12

@@ -1,0 +1,213 @@
+"""CPU tests of libchom's host side: exports, material constants, element operator, checks.
+
+None of these needs a GPU: they call host-only functions of the library or
+exercise argument checks that fail before any device work.
+"""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import chom_inputs as ci
+from oracle import fem, materials as M, mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1610_03484_amd import _lib
+    return _lib
+
+
+def test_library_exports_every_header_symbol(L):
+    header = open(os.path.join(ROOT, "include", "chom.h")).read()
+    names = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(chom_\w+)\s*\(", header, re.M))
+    assert {"chom_rve_create", "chom_homogenise", "chom_generate_plain_weave"} <= names
+    lib = L.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert names <= set(L.SIGNATURES)
+
+
+def test_struct_layouts_match_c_compiler(L, tmp_path):
+    """ctypes structs of the binding have the layout gcc gives the header's structs."""
+    structs = {"chom_mesh": L.ChomMesh, "chom_materials": L.ChomMaterials, "chom_params": L.ChomParams,
+               "chom_options": L.ChomOptions, "chom_report": L.ChomReport}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "chom.h"', 'int main(void){']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append('return 0;}')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, field, val = line.split()
+        py = structs[cname]
+        if field == "size":
+            assert ct.sizeof(py) == int(val), cname
+        else:
+            assert getattr(py, field).offset == int(val), (cname, field)
+
+
+def _voigt_from_invariants(m, a):
+    """6x6 Voigt stiffness by applying the library's invariant law (via the element
+    operator's constitutive part is not exported, so rebuild from the 5 constants)."""
+    lam, muT, alpha, dmu, beta = m
+    A = np.outer(a, a)
+    C = np.zeros((6, 6))
+    for J, (k, l) in enumerate(M.VOIGT_PAIRS):
+        e = np.zeros((3, 3))
+        if k == l:
+            e[k, k] = 1.0
+        else:
+            e[k, l] = e[l, k] = 0.5
+        w = e @ a
+        aea = a @ w
+        s = (lam * np.trace(e) * np.eye(3) + 2 * muT * e + alpha * (aea * np.eye(3) + np.trace(e) * A)
+             + 2 * dmu * (np.outer(a, w) + np.outer(w, a)) + beta * aea * A)
+        for I, (p, q) in enumerate(M.VOIGT_PAIRS):
+            C[I, J] = s[p, q]
+    return C
+
+
+def test_material_invariants_match_oracle_stiffness():
+    from paper_1610_03484_amd import material_constants
+    base = ci.BASE_MATERIALS
+    params = ci.draw_params(3, 4)
+    for p in params:
+        mech, th, mo, keep = material_constants(base, p)
+        m, y, keep_o = M.phase_materials(base, p)
+        assert np.isclose(keep, keep_o, rtol=1e-14)
+        a = np.array([0.3, -0.4, 0.85])
+        a /= np.linalg.norm(a)
+        Cy = M.rotate_stiffness(M.transiso_stiffness_local(y["E1"], y["E2"], y["G12"], y["nu12"], y["nu23"]), a)
+        assert np.allclose(_voigt_from_invariants(mech[5:], a), Cy, rtol=1e-12, atol=1e-12 * np.abs(Cy).max())
+        Cm = M.isotropic_stiffness(m["E"], m["nu"])
+        assert np.allclose(_voigt_from_invariants(mech[:5], a), Cm, rtol=1e-12, atol=1e-12 * np.abs(Cm).max())
+        kt = M.transverse_tensor(y["k1"], y["k2"], a)
+        assert np.allclose(th[2] * np.eye(3) + th[3] * np.outer(a, a), kt)
+        assert np.isclose(th[0], m["k"]) and th[1] == 0.0 and np.isclose(mo[0], m["D"])
+
+
+def test_material_constants_reject_bad_records(L):
+    from paper_1610_03484_amd import material_constants
+    p = ci.draw_factors_only(0, 1)[0].copy()
+    p[0] = 130.0                       # above the glass transition
+    with pytest.raises(L.ChomError) as e:
+        material_constants(ci.BASE_MATERIALS, p)
+    assert e.value.status == L.CHOM_EMATERIAL
+    p = ci.draw_factors_only(0, 1)[0].copy()
+    p[4] = 1.6                          # nu factor -> nu > 0.5
+    with pytest.raises(L.ChomError):
+        material_constants(ci.BASE_MATERIALS, p)
+
+
+def _hier_to_lagrange_p2(d):
+    """Matrix T with v_Lagrange = T c_hierarchic for one P2 tet of the oracle."""
+    alphas = d.ref["nodes"]
+    T = np.zeros((10, 10))
+    edges = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    for node_local, al in enumerate(alphas):
+        row = d.e2n[0, node_local]
+        nz = [i for i in range(4) if al[i]]
+        if len(nz) == 1:                        # vertex node
+            T[row, nz[0]] = 1.0
+        else:                                   # edge midpoint: (c_a + c_b)/2 + 4 * 1/4 * c_ab
+            a, b = nz
+            T[row, a] = T[row, b] = 0.5
+            T[row, 4 + edges.index((a, b))] = 1.0
+    return T
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_element_operator_matches_oracle_element_matrix(L, seed):
+    rng_u = ci.uniform01(seed, np.arange(40)[:, None], np.arange(3)[None, :])
+    X = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [1, 1, 1]], float) * 0.3 + 0.1 * rng_u[:4]
+    d = fem.Discretisation(X, np.array([[0, 1, 2, 3]]), 2)
+    g = d.grad[0]                     # [4, 3]
+    vol = d.vol[0]
+    a = np.array([0.2, 0.9, -0.3])
+    a /= np.linalg.norm(a)
+    from paper_1610_03484_amd import material_constants
+    mech, th, mo, _ = material_constants(ci.BASE_MATERIALS)
+    C = _voigt_from_invariants(mech[5:], a)
+    K = d.stiffness_mech(C[None]).toarray()       # Lagrange, DOF 3*node + c
+    T = _hier_to_lagrange_p2(d)
+    T3 = np.kron(T, np.eye(3))
+    Kh = T3.T @ K @ T3
+    u = rng_u[10:20].reshape(-1) - 0.5
+    y = np.zeros(30)
+    gl = np.ascontiguousarray(g)
+    st = L.lib().chom_element_apply_host(3, gl.ctypes.data, vol, a.ctypes.data, mech[5:].copy().ctypes.data,
+                                         u.ctypes.data, y.ctypes.data)
+    assert st == 0
+    assert np.allclose(y, Kh @ u, rtol=1e-12, atol=1e-12 * np.abs(Kh @ u).max())
+    # scalar operator with a transversely isotropic conductivity
+    kt = th[2] * np.eye(3) + th[3] * np.outer(a, a)
+    Ks = d.stiffness_scalar(kt[None]).toarray()
+    Khs = T.T @ Ks @ T
+    us = u[:10].copy()
+    ys = np.zeros(10)
+    inv = np.array([th[2], th[3], 0, 0, 0])
+    st = L.lib().chom_element_apply_host(1, gl.ctypes.data, vol, a.ctypes.data, inv.ctypes.data,
+                                         us.ctypes.data, ys.ctypes.data)
+    assert st == 0
+    assert np.allclose(ys, Khs @ us, rtol=1e-12, atol=1e-12 * np.abs(Khs @ us).max())
+
+
+def _host_mesh_rve(coords, tets, phase, axis, bc="periodic"):
+    from paper_1610_03484_amd import RVE
+    return RVE(coords, tets, phase, axis, ci.BASE_MATERIALS, bc=bc)
+
+
+def test_rve_create_rejects_non_lattice_meshes(L):
+    coords, tets, phase, axis = mesh.plain_weave(2)
+    bad = tets.copy()
+    bad[5, 2] = bad[5, 3]
+    with pytest.raises(L.ChomError) as e:
+        _host_mesh_rve(coords, bad, phase, axis)
+    assert e.value.status == L.CHOM_EMESH
+    with pytest.raises(L.ChomError) as e:
+        _host_mesh_rve(coords[:-1], tets, phase, axis)
+    assert e.value.status == L.CHOM_EMESH
+    ax = axis.copy()
+    yarn = np.nonzero(phase > 0)[0]
+    if len(yarn):
+        ax[yarn[0]] *= 2.0
+        with pytest.raises(L.ChomError) as e:
+            _host_mesh_rve(coords, tets, phase, ax)
+        assert e.value.status == L.CHOM_EMESH
+    c2 = coords.copy()
+    c2[0, 0] = 0.01                     # boundary vertex off its face
+    with pytest.raises(L.ChomError) as e:
+        _host_mesh_rve(c2, tets, phase, axis)
+    assert e.value.status == L.CHOM_EMESH
+
+
+def test_rve_create_rejects_bad_arguments(L):
+    coords, tets, phase, axis = mesh.plain_weave(1)
+    with pytest.raises(L.ChomError) as e:
+        _host_mesh_rve(coords, tets, phase, axis, bc=7)
+    assert e.value.status == L.CHOM_EINVAL
+    from paper_1610_03484_amd import RVE
+    with pytest.raises(L.ChomError) as e:
+        RVE(coords, tets, phase, axis, ci.BASE_MATERIALS, order=3)
+    assert e.value.status == L.CHOM_EINVAL
+    with pytest.raises(L.ChomError) as e:
+        RVE(coords, tets, phase, axis, ci.BASE_MATERIALS, rtol=-1.0)
+    assert e.value.status == L.CHOM_EINVAL
+
+
+def test_mesh_sizes(L):
+    from paper_1610_03484_amd import mesh_sizes
+    assert mesh_sizes(24) == (25 ** 3, 6 * 24 ** 3)
+    with pytest.raises(L.ChomError):
+        mesh_sizes(0)
