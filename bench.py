@@ -40,9 +40,13 @@ FP64_VEC_PEAK = 78.6e12
 WORKLOADS = {
     "c1": dict(n=24, bcs=("dirichlet", "periodic", "neumann"), precision="fp32_refined",
                desc="24^3 Kuhn plain-weave RVE (82,944 tets), p=2 (352,947 elastic DOFs), "
-                    "Dirichlet+periodic+Neumann, 6+3+3 load cases each, FP32 operator + FP64 refinement"),
+                    "Dirichlet+periodic+Neumann in one batch, 6+3+3 load cases each, FP32 operator + FP64 refinement"),
     "c0": dict(n=8, bcs=("dirichlet",), precision="fp64",
                desc="8^3 Kuhn plain-weave RVE (3,072 tets), p=2, linear Dirichlet, 6+3+3 load cases, FP64"),
+    "c2": dict(n=None, bcs=("periodic",), precision="fp32_refined",
+               desc="batch of RVEs with sizes uniform over {8,12,16,20,24}^3 cells, p=2, periodic, degraded "
+                    "(T~U(20,60) C, c~U(0,1.5) wt%, t~U(0,10) y, factors U(0.9,1.1)), 12 load cases each, "
+                    "FP32 operator + FP64 refinement, one batch"),
 }
 
 
@@ -101,6 +105,7 @@ def main():
     ap.add_argument("--op-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--items", type=int, default=512, help="items of the c2 batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (the RVE batches shard across GPUs without "
@@ -115,17 +120,30 @@ def main():
         print("bench.py: needs a GPU", file=sys.stderr)
         sys.exit(1)
     wl = WORKLOADS[args.workload]
-    n = wl["n"]
-    params = ci.draw_factors_only(0, 1)
-    mesh = generate_plain_weave(n, device="cuda:0")
-    rves = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision=wl["precision"], rtol=1e-10, max_iter=50000)
-            for bc in wl["bcs"]]
+    from paper_1610_03484_amd import Batch
+    opts = dict(precision=wl["precision"], rtol=1e-10, max_iter=50000)
+    if args.workload == "c2":
+        sizes = ci.batch_sizes_c2(0, args.items)
+        params = ci.draw_params(0, args.items)
+        handles = {}
+        rves = []
+        for n_i in sizes:
+            if n_i not in handles:
+                handles[n_i] = RVE(*generate_plain_weave(int(n_i), device="cuda:0"), ci.BASE_MATERIALS,
+                                   bc="periodic", **opts)
+            rves.append(handles[n_i])
+        n = int(max(sizes))
+        labels = [f"n={int(s)}" for s in sizes]
+    else:
+        n = wl["n"]
+        mesh = generate_plain_weave(n, device="cuda:0")
+        rves = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, **opts) for bc in wl["bcs"]]
+        params = np.repeat(ci.draw_factors_only(0, 1), len(rves), axis=0)
+        labels = list(wl["bcs"])
+    batch = Batch(rves)
 
     def step():
-        out = []
-        for r in rves:
-            out.append(r.homogenise(params))
-        return out
+        return batch.homogenise(params)
 
     for _ in range(args.warmup):
         step()
@@ -137,26 +155,38 @@ def main():
     dt = time.perf_counter() - t0
     homs = len(rves) * args.steps
     value = homs / dt
-    for bc, (C, K, D, rep) in zip(wl["bcs"], res):
-        print(f"[bench] {bc}: iters={rep[0]['iters']} refine={rep[0]['refine_steps']} "
-              f"resid_max={max(rep[0]['resid']):.1e} asym={rep[0]['asym']:.1e}", file=sys.stderr)
+    C, K, D, rep = res
+    for i, lab in enumerate(labels[:6]):
+        print(f"[bench] {lab}: iters={rep[i]['iters']} refine={rep[i]['refine_steps']} "
+              f"resid_max={max(rep[i]['resid']):.1e} asym={rep[i]['asym']:.1e}", file=sys.stderr)
+    print(f"[bench] status: {sum(r['status'] == 0 for r in rep)}/{len(rep)} converged; "
+          f"max iters {max(max(r['iters']) for r in rep)}", file=sys.stderr)
 
-    # accuracy against the FP64 GPU path (same RVE, same parameters)
+    # accuracy against the FP64 GPU path (same RVEs, same parameters); for the
+    # mixed-size batch it is measured by the tests on a stratified sample instead
     err = None
-    if not args.no_accuracy and wl["precision"] != "fp64":
-        errs = []
-        for bc, (C, K, D, _) in zip(wl["bcs"], res):
-            ref = RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision="fp64", rtol=1e-12, max_iter=50000)
-            Cr, Kr, Dr, _ = ref.homogenise(params)
-            errs.append(max(np.linalg.norm(C - Cr) / np.linalg.norm(Cr), np.linalg.norm(K - Kr) / np.linalg.norm(Kr),
-                            np.linalg.norm(D - Dr) / np.linalg.norm(Dr)))
-            ref.close()
+    if not args.no_accuracy and wl["precision"] != "fp64" and args.workload != "c2":
+        ref_rves = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision="fp64", rtol=1e-12, max_iter=50000)
+                    for bc in wl["bcs"]]
+        ref = Batch(ref_rves)
+        Cr, Kr, Dr, _ = ref.homogenise(params)
+        errs = [max(np.linalg.norm(C[i] - Cr[i]) / np.linalg.norm(Cr[i]),
+                    np.linalg.norm(K[i] - Kr[i]) / np.linalg.norm(Kr[i]),
+                    np.linalg.norm(D[i] - Dr[i]) / np.linalg.norm(Dr[i])) for i in range(len(rves))]
         err = float(max(errs))
+        ref.close()
 
-    # dominant kernel: the mechanical operator of the first (full-lattice) RVE
-    ms, tets, nprob = rves[0].time_operator(0, args.op_reps)
+    # dominant kernel: the mechanical operator launch of the batch
+    ms, tets, nprob = batch.time_operator(0, args.op_reps)
     fp32 = wl["precision"] != "fp64"
-    bytes_, flops = algorithmic_mech(n, nprob, fp32)
+    if args.workload == "c2":
+        bytes_ = flops = 0
+        for s_ in sizes:
+            b1, f1 = algorithmic_mech(int(s_), 1, fp32)
+            bytes_ += b1
+            flops += f1
+    else:
+        bytes_, flops = algorithmic_mech(n, nprob, fp32)
     t = ms * 1e-3
     peak_alu = FP32_VEC_PEAK if fp32 else FP64_VEC_PEAK
     t_hbm, t_alu = bytes_ / HBM_PEAK, flops / peak_alu
@@ -185,8 +215,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": wl["desc"], "path": "plain", "rves_per_step": len(rves),
-                   "c_hom_rel_err_vs_fp64_gpu": err},
+        "config": {"workload": wl["desc"], "path": "batched", "rves_per_step": len(rves),
+                   "c_hom_rel_err_vs_fp64_gpu": err, "launch": batch.launch_config(),
+                   "converged": int(sum(r["status"] == 0 for r in rep))},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -58,6 +58,7 @@ enum { CHOM_FP64 = 0, CHOM_FP32_REFINED = 1 };
 enum { CHOM_PRECOND_BLOCK_JACOBI = 0 };
 
 typedef struct chom_rve chom_rve;
+typedef struct chom_batch chom_batch;
 
 /* RVE mesh.  Supported meshes: the Kuhn split of an n x n x n cell grid of the
  * box [lo, hi] -- (n+1)^3 vertices numbered i + (n+1)(j + (n+1)k), 6 n^3 tets,
@@ -177,8 +178,44 @@ int chom_homogenise(chom_rve *rve, const chom_params *params, int32_t batch,
 int chom_time_operator(chom_rve *rve, int32_t physics, int32_t reps, double *ms_per_launch,
                        int64_t *tets_per_launch, int32_t *problems_per_launch);
 
-/* Release a handle (NULL is ignored). */
+/* Release a handle (NULL is ignored).  Batches that list the handle must be
+ * destroyed first. */
 void chom_rve_destroy(chom_rve *rve);
+
+/* ---------------------------------------------------------------- batches
+ * One macro Gauss point per item (the FE^2 setting of Sec. 5, where every macro
+ * Gauss point carries its own RVE): item i is homogenised on RVE rves[i] with
+ * parameter record params[i].  Handles may repeat (items sharing a mesh) and may
+ * differ in size and boundary condition; all items and all 12 load cases run in
+ * the same kernel launches (one problem table per physics), the CG iterations
+ * replayed from a captured HIP graph, with device-side convergence flags so
+ * finished items cost only an early exit.  opt may be NULL (the first handle's
+ * options).  The handles must outlive the batch.
+ * Errors: CHOM_EINVAL, CHOM_EDEVICE, CHOM_ENOMEM. */
+int chom_batch_create(chom_rve *const *rves, int32_t n, const chom_options *opt, chom_batch **out);
+
+/* Homogenise every item of the batch: params [n], C_hom [n][21], K_hom [n][6],
+ * D_hom [n][6], rep [n] (nullable, host).  Same conventions and errors as
+ * chom_homogenise.  If the environment variable CHOM_AUTOTUNE is set, the first
+ * call times the operator's load-case grouping (1, 2 or 3 load cases per
+ * workgroup) and the vector kernels' grid (128..1024 workgroups per item) on
+ * this batch and keeps the fastest; results are cached per device, precision
+ * and size mix (and persisted to the file named by CHOM_TUNE_FILE if set). */
+int chom_batch_homogenise(chom_batch *batch, const chom_params *params, double *C_hom, double *K_hom,
+                          double *D_hom, chom_report *rep);
+
+/* Launch shape in use: load cases per operator workgroup and vector
+ * workgroups per item, for the mechanical and scalar classes (any pointer may
+ * be NULL).  Errors: CHOM_EINVAL. */
+int chom_batch_launch_config(const chom_batch *batch, int32_t *rg_mech, int32_t *rg_scal, int32_t *nwg_mech,
+                             int32_t *nwg_scal);
+
+/* As chom_time_operator, for a batch. */
+int chom_batch_time_operator(chom_batch *batch, int32_t physics, int32_t reps, double *ms_per_launch,
+                             int64_t *tets_per_launch, int32_t *problems_per_launch);
+
+/* Release a batch (NULL is ignored). */
+void chom_batch_destroy(chom_batch *batch);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *chom_last_error(void);

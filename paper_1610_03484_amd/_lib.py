@@ -62,6 +62,15 @@ SIGNATURES = {
                                            ct.c_int32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                                            ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]),
     "chom_version": (ct.c_char_p, []),
+    "chom_batch_create": (ct.c_int, [ct.POINTER(ct.c_void_p), ct.c_int32, ct.POINTER(ChomOptions),
+                                     ct.POINTER(ct.c_void_p)]),
+    "chom_batch_homogenise": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                         ct.POINTER(ChomReport)]),
+    "chom_batch_launch_config": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
+                                            ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]),
+    "chom_batch_time_operator": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_double),
+                                            ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)]),
+    "chom_batch_destroy": (None, [ct.c_void_p]),
     "chom_time_operator": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_double),
                                       ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)]),
     "chom_element_apply_host": (ct.c_int, [ct.c_int32, ct.c_void_p, ct.c_double, ct.c_void_p, ct.c_void_p,

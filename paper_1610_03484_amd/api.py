@@ -97,6 +97,7 @@ class RVE:
             ptrs = [a.ctypes.data for a in arrs]
             nv, nt = arrs[0].shape[0], arrs[1].shape[0]
         mesh.n_vertices, mesh.n_tets = nv, nt
+        self.n = int(round((nt / 6) ** (1.0 / 3.0)))
         mesh.coords, mesh.tets, mesh.phase, mesh.fibre_axis = ptrs
         mesh.lo[:] = lo
         mesh.hi[:] = hi
@@ -166,3 +167,59 @@ def upper6_to_matrix(k6):
         M[..., i, j] = k6[..., q]
         M[..., j, i] = k6[..., q]
     return M
+
+
+class Batch:
+    """Handle of chom_batch_create: item i is homogenised on rves[i] (handles may repeat)."""
+
+    def __init__(self, rves, **options):
+        self._rves = list(rves)                # keep the handles alive
+        self._h = ct.c_void_p()
+        arr = (ct.c_void_p * len(self._rves))(*[r._h.value for r in self._rves])
+        opt = default_options(**options) if options else self._rves[0].options
+        self.options = opt
+        L.check(L.lib().chom_batch_create(arr, len(self._rves), ct.byref(opt), ct.byref(self._h)),
+                "chom_batch_create")
+
+    def __len__(self):
+        return len(self._rves)
+
+    def homogenise(self, params, allow_noconv=False):
+        """params [n, 11] -> (C21 [n,21], K6 [n,6], D6 [n,6], reports)."""
+        p = np.asarray(params, dtype=np.float64).reshape(-1, 11)
+        n = len(self._rves)
+        if len(p) != n:
+            raise ValueError(f"need {n} parameter records, got {len(p)}")
+        C = np.zeros((n, 21))
+        K = np.zeros((n, 6))
+        D = np.zeros((n, 6))
+        reps = (L.ChomReport * n)()
+        st = L.lib().chom_batch_homogenise(self._h, params_array(p), ct.c_void_p(C.ctypes.data),
+                                           ct.c_void_p(K.ctypes.data), ct.c_void_p(D.ctypes.data), reps)
+        if not (st == L.CHOM_OK or (allow_noconv and st == L.CHOM_ENOCONV)):
+            L.check(st, "chom_batch_homogenise")
+        return C, K, D, [report_dict(r) for r in reps]
+
+    def launch_config(self):
+        v = [ct.c_int32() for _ in range(4)]
+        L.check(L.lib().chom_batch_launch_config(self._h, *[ct.byref(x) for x in v]), "chom_batch_launch_config")
+        return dict(rg_mech=v[0].value, rg_scal=v[1].value, nwg_mech=v[2].value, nwg_scal=v[3].value)
+
+    def time_operator(self, physics=0, reps=50):
+        ms = ct.c_double()
+        nt = ct.c_int64()
+        npb = ct.c_int32()
+        L.check(L.lib().chom_batch_time_operator(self._h, physics, reps, ct.byref(ms), ct.byref(nt), ct.byref(npb)),
+                "chom_batch_time_operator")
+        return ms.value, nt.value, npb.value
+
+    def close(self):
+        if self._h:
+            L.lib().chom_batch_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,11 +1,16 @@
 // C ABI of libchom: argument checking, mesh validation, material constants,
-// workspaces and the host side of the solver (PCG loop, refinement loop).
+// batches and workspaces, the host side of the solver (PCG loop captured in a
+// HIP graph, refinement loop) and the launch autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,19 +21,28 @@ namespace chom {
 static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
-#define CHOM_HIP(...)                                                                    \
-    do {                                                                                 \
-        hipError_t e_ = (__VA_ARGS__);                                                          \
-        if (e_ != hipSuccess) {                                                          \
+#define CHOM_HIP(...)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (__VA_ARGS__);                                                         \
+        if (e_ != hipSuccess) {                                                                \
             set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #__VA_ARGS__); \
-            return e_ == hipErrorOutOfMemory ? CHOM_ENOMEM : CHOM_EDEVICE;               \
-        }                                                                                \
+            return e_ == hipErrorOutOfMemory ? CHOM_ENOMEM : CHOM_EDEVICE;                     \
+        }                                                                                      \
+    } while (0)
+
+#define CHOM_TRY(...)                    \
+    do {                                 \
+        int st_ = (__VA_ARGS__);         \
+        if (st_ != CHOM_OK) return st_;  \
     } while (0)
 
 // Device buffer owned by a handle.
 template <typename T> struct DevBuf {
     T *p = nullptr;
     size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release() {
         if (p) (void)hipFree(p);
@@ -56,7 +70,7 @@ static bool damage_factor(const chom_params *pr, double c_sat, double *keep) {
     if (!pr) { *keep = 1.0; return true; }
     const double TK = pr->T_celsius + kKelvin, TgK = kTgC + kKelvin;
     const double arg = 1.0 - TK / TgK;
-    if (!(arg > 0.0) || !(c_sat > 0.0) || pr->c_wt < 0.0 || pr->t_years < 0.0) return false;
+    if (!(arg > 0.0) || !(c_sat > 0.0) || !(pr->c_wt >= 0.0) || !(pr->t_years >= 0.0)) return false;
     const double alpha = kBeta * std::log(arg);
     const double gamma = pr->c_wt / c_sat;
     *keep = std::exp(-gamma * alpha * pr->t_years * kDaysPerYear);
@@ -66,7 +80,6 @@ static bool damage_factor(const chom_params *pr, double c_sat, double *keep) {
 // Local transversely isotropic stiffness (fibre along e1) -> the five invariants.
 static bool transiso_invariants(double E1, double E2, double G12, double nu12, double nu23, double out[5]) {
     if (!(E1 > 0 && E2 > 0 && G12 > 0)) return false;
-    // normal compliance block (e1, e2, e3)
     const double s11 = 1.0 / E1, s22 = 1.0 / E2, s12 = -nu12 / E1, s23 = -nu23 / E2;
     const double S[3][3] = {{s11, s12, s12}, {s12, s22, s23}, {s12, s23, s22}};
     const double det = S[0][0] * (S[1][1] * S[2][2] - S[1][2] * S[2][1]) -
@@ -92,9 +105,8 @@ static bool transiso_invariants(double E1, double E2, double G12, double nu12, d
     return true;
 }
 
-static int material_constants(const chom_materials *m, const chom_params *pr, double c_sat,
-                              int degrade_yarn, double mech[10], double therm[4], double moist[4],
-                              double *keep_out) {
+static int material_constants(const chom_materials *m, const chom_params *pr, double c_sat, int degrade_yarn,
+                              double mech[10], double therm[4], double moist[4], double *keep_out) {
     double f[8] = {1, 1, 1, 1, 1, 1, 1, 1};
     if (pr)
         for (int i = 0; i < 8; ++i) f[i] = pr->factor[i];
@@ -134,11 +146,28 @@ static int material_constants(const chom_materials *m, const chom_params *pr, do
 }
 
 // ------------------------------------------------------------------ workspaces
+// A captured run of CG iterations (the kernel sequence is fixed by the buffers).
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    const void *key = nullptr;   // buffer identity the graph was captured for
+    int iters = 0;
+    unsigned long long gen = 0;  // workspace generation it was captured for
+    ~GraphCache() { reset(); }
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        key = nullptr;
+        iters = 0;
+        gen = 0;
+    }
+};
+
 template <int C, int R> struct ClassWS {
     static constexpr int MS = (C == 3) ? 6 : 1;
-    int nprob = 0;
-    long long vpp = 0;
-    int nwg_vec = 0, nwg_op = 0, nwg_gram = 0, nwg_avg = 0;
+    Launch L{};
+    long long total_vals = 0, total_pts = 0, total_q = 0;
+    int nwg_gram = 0, nwg_avg = 0;
+    unsigned long long gen = 0;          // bumped whenever the launch shape may change
     DevBuf<Prob> probs;
     DevBuf<double> b, x64, r64, q64;
     DevBuf<double> xd, rd, zd, pd, qd;
@@ -150,7 +179,8 @@ template <int C, int R> struct ClassWS {
     DevBuf<double> partial, avg_out;
     std::vector<ColState> h_cols, h_cols_outer;
     std::vector<int> h_active;
-    std::vector<int> refine_steps;  // per problem
+    std::vector<int> refine_steps;
+    GraphCache graph64, graph32;
 };
 
 }  // namespace chom
@@ -168,28 +198,104 @@ struct chom_rve {
     DevBuf<double> geo64;
     DevBuf<float> geo32;
     DevBuf<double> rows;
+    std::unique_ptr<chom_batch> self;   // batch of this RVE alone (chom_homogenise)
+    int self_size = 0;
+    ~chom_rve();
+};
+
+struct chom_batch {
+    std::vector<chom_rve *> entries;    // one per batch item (handles may repeat)
+    std::vector<chom_rve *> distinct;   // distinct handles, index = Prob.geo
+    std::vector<int> geo_of;            // entry -> index in distinct
+    chom_options opt;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    DevBuf<Geo> geos;
     ClassWS<3, 6> mech;
     ClassWS<1, 3> scal;
+    int rg_mech = 2, rg_scal = 3;       // load cases per operator workgroup
+    int nwg_mech = 0, nwg_scal = 0;     // vector workgroups per problem (0: default)
+    bool tuned = false;
+    ~chom_batch() {
+        mech.graph64.reset();
+        mech.graph32.reset();
+        scal.graph64.reset();
+        scal.graph32.reset();
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
 };
+
+chom_rve::~chom_rve() { self.reset(); }
 
 namespace chom {
 
-static hipStream_t stream_of(const chom_rve *r) { return (hipStream_t)r->opt.hip_stream; }
+// ------------------------------------------------------------------ autotune cache
+// Process-wide cache of tuned launch shapes, keyed by device, physics,
+// precision and problem sizes; optionally persisted to $CHOM_TUNE_FILE.
+static std::mutex g_tune_mu;
+static std::map<std::string, std::pair<int, int>> g_tune;
+static bool g_tune_loaded = false;
 
+static void tune_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("CHOM_TUNE_FILE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char key[512];
+    int a, b;
+    while (std::fscanf(f, "%511s %d %d", key, &a, &b) == 3) g_tune[key] = {a, b};
+    std::fclose(f);
+}
+
+static void tune_store(const std::string &key, int a, int b) {
+    g_tune[key] = {a, b};
+    const char *path = std::getenv("CHOM_TUNE_FILE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return;
+    for (auto &kv : g_tune) std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    std::fclose(f);
+}
+
+// ------------------------------------------------------------------ class setup
 template <int C, int R>
-static int ensure_ws(chom_rve *rve, ClassWS<C, R> &W, int nprob) {
-    const Geo &G = rve->geo;
+static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, int rg, int nwg_override) {
     constexpr int MS = ClassWS<C, R>::MS;
-    W.nprob = nprob;
-    W.vpp = G.npts * R * C;
-    const size_t nv = (size_t)W.vpp * nprob;
-    const size_t nq = (size_t)operator_tiles(G) * BOXPTS * R * C * nprob;  // tile-box operator output
-    W.nwg_vec = (int)std::min<long long>(std::max<long long>((G.npts + 127) / 128, 1), 1024);
-    W.nwg_op = operator_tiles(G);   // partial p.Kp records per load case
-    W.nwg_gram = (int)std::min<long long>(std::max<long long>((G.npts + 4095) / 4096, 1), 256);
-    const long long nt = 6LL * G.n * G.n * G.n;
-    W.nwg_avg = (int)std::min<long long>(std::max<long long>((nt + 1023) / 1024, 1), 256);
-    const bool fp32 = rve->opt.precision == CHOM_FP32_REFINED;
+    const int nprob = (int)hp.size();
+    long long voff = 0, doff = 0, qoff = 0, max_pts = 0, max_tets = 0;
+    int max_tiles = 0, nr = 0;
+    for (auto &P : hp) {
+        const Geo &G = B->distinct[P.geo]->geo;
+        P.voff = voff;
+        P.doff = doff;
+        P.qoff = qoff;
+        voff += G.npts * R * C;
+        doff += G.npts;
+        qoff += (long long)G.ntiles * BOXPTS * R * C;
+        max_pts = std::max(max_pts, G.npts);
+        max_tets = std::max(max_tets, 6LL * G.n * G.n * G.n);
+        max_tiles = std::max(max_tiles, G.ntiles);
+        nr = std::max(nr, G.nrow);
+    }
+    W.total_vals = voff;
+    W.total_pts = doff;
+    W.total_q = qoff;
+    Launch &L = W.L;
+    const Launch old = L;
+    L.nprob = nprob;
+    L.nwg = nwg_override > 0 ? nwg_override
+                              : (int)std::min<long long>(std::max<long long>((max_pts + 127) / 128, 1), 1024);
+    L.max_tiles = max_tiles;
+    L.nr = nr == 0 ? 0 : (nr == 1 ? 1 : 4);
+    L.rg = rg;
+    L.max_tets = max_tets;
+    W.nwg_gram = (int)std::min<long long>(std::max<long long>((max_pts + 4095) / 4096, 1), 256);
+    W.nwg_avg = (int)std::min<long long>(std::max<long long>((max_tets + 1023) / 1024, 1), 256);
+    const bool fp32 = B->opt.precision == CHOM_FP32_REFINED;
+    const size_t nv = (size_t)voff, nq = (size_t)qoff;
+    void *before[4] = {W.xd.p, W.xf.p, W.partial.p, W.probs.p};
     CHOM_HIP(W.probs.ensure(nprob));
     CHOM_HIP(W.b.ensure(nv));
     CHOM_HIP(W.q64.ensure(nq));
@@ -209,13 +315,13 @@ static int ensure_ws(chom_rve *rve, ClassWS<C, R> &W, int nprob) {
         CHOM_HIP(W.pd.ensure(nv));
         CHOM_HIP(W.qd.ensure(nq));
     }
-    CHOM_HIP(W.diag.ensure((size_t)G.npts * MS * nprob));
-    CHOM_HIP(W.minv64.ensure((size_t)G.npts * MS * nprob));
-    CHOM_HIP(W.minv32.ensure((size_t)G.npts * MS * nprob));
-    const int S = C * 4;
-    CHOM_HIP(W.ginv64.ensure((size_t)S * S * nprob));
-    CHOM_HIP(W.ginv32.ensure((size_t)S * S * nprob));
-    CHOM_HIP(W.ycoef.ensure((size_t)R * S * nprob));
+    CHOM_HIP(W.diag.ensure((size_t)doff * MS));
+    CHOM_HIP(W.minv64.ensure((size_t)doff * MS));
+    CHOM_HIP(W.minv32.ensure((size_t)doff * MS));
+    const int S4 = C * 4;
+    CHOM_HIP(W.ginv64.ensure((size_t)S4 * S4 * nprob));
+    CHOM_HIP(W.ginv32.ensure((size_t)S4 * S4 * nprob));
+    CHOM_HIP(W.ycoef.ensure((size_t)R * S4 * nprob));
     CHOM_HIP(W.cols.ensure((size_t)R * nprob));
     CHOM_HIP(W.cols_outer.ensure((size_t)R * nprob));
     CHOM_HIP(W.active.ensure(nprob));
@@ -223,98 +329,120 @@ static int ensure_ws(chom_rve *rve, ClassWS<C, R> &W, int nprob) {
     CHOM_HIP(W.bad.ensure(1));
     const int NC = (C == 3) ? 6 : 3;
     size_t part = 0;
-    part = std::max(part, (size_t)nprob * W.nwg_vec * R * (2 + C * 4));
-    part = std::max(part, (size_t)nprob * W.nwg_op * R);
+    part = std::max(part, (size_t)nprob * L.nwg * R * (2 + C * 4));
+    part = std::max(part, (size_t)nprob * L.max_tiles * R);
     part = std::max(part, (size_t)nprob * W.nwg_gram * 2 * 60);
     part = std::max(part, (size_t)nprob * W.nwg_avg * R * NC);
-    part = std::max(part, (size_t)nprob * W.nwg_vec * R * C * 4 + (size_t)nprob * R * C * 4);
+    part = std::max(part, (size_t)nprob * L.nwg * R * C * 4 + (size_t)nprob * R * C * 4);
     CHOM_HIP(W.partial.ensure(part));
     CHOM_HIP(W.avg_out.ensure((size_t)nprob * R * NC));
     W.h_cols.resize((size_t)R * nprob);
     W.h_cols_outer.resize((size_t)R * nprob);
     W.h_active.resize(nprob);
     W.refine_steps.assign(nprob, 0);
+    L.geos = B->geos.p;
+    L.probs = W.probs.p;
+    const void *after[4] = {W.xd.p, W.xf.p, W.partial.p, W.probs.p};
+    if (std::memcmp(before, after, sizeof(before)) != 0 || old.nprob != L.nprob || old.nwg != L.nwg ||
+        old.max_tiles != L.max_tiles || old.nr != L.nr || old.rg != L.rg)
+        ++W.gen;
     return CHOM_OK;
 }
 
-// PCG on one class of problems: b -> x (vectors of precision T).
+// One CG iteration (5 kernels).
 template <typename T, int C, int R>
-static int pcg(chom_rve *rve, ClassWS<C, R> &W, const T *b, T *x, T *r, T *z, T *p, T *q,
-               const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask,
-               const Prob *probs_dev) {
-    const Geo &G = rve->geo;
-    hipStream_t s = stream_of(rve);
-    const int nprob = W.nprob;
-    CHOM_HIP(launch_cg_init<T, C, R>(G, nprob, W.vpp, b, x, r, z, minv, W.partial.p, W.nwg_vec, s));
-    if (mask)
-        CHOM_HIP((launch_finish_beta_masked<C, R>(nprob, G.nrow, W.partial.p, W.nwg_vec, ginv, W.ycoef.p,
-                                                  W.cols.p, W.active.p, rtol2, mask, s)));
-    else
-        CHOM_HIP((launch_finish_beta<C, R>(nprob, G.nrow, W.partial.p, W.nwg_vec, ginv, W.ycoef.p, W.cols.p,
-                                           W.active.p, 1, rtol2, use_init, s)));
-    const int max_iter = rve->opt.max_iter;
-    const int check = 8;
-    for (int it = 0; it < max_iter; ++it) {
-        if (it % check == 0) {
-            CHOM_HIP(hipMemcpyAsync(W.h_active.data(), W.active.p, sizeof(int) * nprob, hipMemcpyDeviceToHost, s));
-            CHOM_HIP(hipStreamSynchronize(s));
-            int act = 0;
-            for (int i = 0; i < nprob; ++i) act += W.h_active[i];
-            if (act == 0) break;
+static hipError_t cg_iteration(ClassWS<C, R> &W, T *x, T *r, T *z, T *p, T *q, const void *minv,
+                               const double *ginv, double rtol2, int use_init, hipStream_t s) {
+    const Launch &L = W.L;
+    hipError_t e;
+    if ((e = launch_cg_dir<T, C, R>(L, r, z, p, minv, W.ycoef.p, W.cols.p, W.active.p, s)) != hipSuccess) return e;
+    if ((e = launch_operator<T, C, R>(L.geos, L.probs, L.nprob, L.max_tiles, L.rg, p, q, W.partial.p, W.active.p, s)) != hipSuccess) return e;
+    if ((e = launch_finish_alpha<C, R>(L, W.partial.p, W.cols.p, s)) != hipSuccess) return e;
+    if ((e = launch_cg_update<T, C, R>(L, x, r, z, p, q, minv, W.cols.p, W.partial.p, W.active.p, s)) != hipSuccess) return e;
+    return launch_finish_beta<C, R>(L, W.partial.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 0, rtol2, use_init, nullptr, s);
+}
+
+// PCG on one class of problems: b -> x (vectors of precision T).  Iterations
+// run in chunks, captured once as a HIP graph and replayed; between chunks the
+// host reads the per-problem active counts (finished problems cost only an
+// early exit in every kernel).
+template <typename T, int C, int R>
+static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x, T *r, T *z, T *p, T *q,
+               const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask) {
+    hipStream_t s = B->stream;
+    const Launch &L = W.L;
+    CHOM_HIP((launch_cg_init<T, C, R>(L, b, x, r, z, minv, W.partial.p, s)));
+    CHOM_HIP((launch_finish_beta<C, R>(L, W.partial.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 1, rtol2,
+                                       mask ? 1 : use_init, mask, s)));
+    const int max_iter = B->opt.max_iter;
+    const int chunk = 8;
+    const bool use_graph = std::getenv("CHOM_NO_GRAPH") == nullptr;
+    if (use_graph && (GC.exec == nullptr || GC.key != (const void *)x || GC.iters != chunk || GC.gen != W.gen)) {
+        GC.reset();
+        hipGraph_t g;
+        CHOM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int k = 0; k < chunk && ce == hipSuccess; ++k)
+            ce = cg_iteration<T, C, R>(W, x, r, z, p, q, minv, ginv, rtol2, use_init, s);
+        hipError_t ee = hipStreamEndCapture(s, &g);
+        CHOM_HIP(ce);
+        CHOM_HIP(ee);
+        hipError_t ie = hipGraphInstantiate(&GC.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        CHOM_HIP(ie);
+        GC.key = x;
+        GC.iters = chunk;
+        GC.gen = W.gen;
+    }
+    for (int it = 0; it < max_iter; it += chunk) {
+        CHOM_HIP(hipMemcpyAsync(W.h_active.data(), W.active.p, sizeof(int) * L.nprob, hipMemcpyDeviceToHost, s));
+        CHOM_HIP(hipStreamSynchronize(s));
+        int act = 0;
+        for (int i = 0; i < L.nprob; ++i) act += W.h_active[i];
+        if (act == 0) break;
+        if (use_graph) {
+            CHOM_HIP(hipGraphLaunch(GC.exec, s));
+        } else {
+            for (int k = 0; k < chunk; ++k)
+                CHOM_HIP((cg_iteration<T, C, R>(W, x, r, z, p, q, minv, ginv, rtol2, use_init, s)));
         }
-        CHOM_HIP((launch_cg_dir<T, C, R>(G, nprob, W.vpp, r, z, p, q, minv, W.ycoef.p, W.cols.p, W.active.p,
-                                         W.nwg_vec, s)));
-        CHOM_HIP((launch_operator<T, C, R>(G, probs_dev, nprob, p, q, W.partial.p, W.active.p, s)));
-        CHOM_HIP((launch_finish_alpha<C, R>(nprob, W.partial.p, W.nwg_op, W.cols.p, s)));
-        CHOM_HIP((launch_cg_update<T, C, R>(G, nprob, W.vpp, x, r, z, p, q, minv, W.cols.p, W.partial.p,
-                                            W.active.p, W.nwg_vec, s)));
-        CHOM_HIP((launch_finish_beta<C, R>(nprob, G.nrow, W.partial.p, W.nwg_vec, ginv, W.ycoef.p, W.cols.p,
-                                           W.active.p, 0, rtol2, use_init, s)));
     }
     return CHOM_OK;
 }
 
 // Solve one class (mechanical or scalar) for all its problems.  Result: W.avg_out.
 template <int C, int R>
-static int run_class(chom_rve *rve, ClassWS<C, R> &W, const std::vector<Prob> &hprobs) {
-    const Geo &G = rve->geo;
-    hipStream_t s = stream_of(rve);
-    const int nprob = (int)hprobs.size();
-    int st = ensure_ws<C, R>(rve, W, nprob);
-    if (st != CHOM_OK) return st;
-    const size_t nv = (size_t)W.vpp * nprob;
+static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs, int rg, int nwg) {
+    hipStream_t s = B->stream;
+    CHOM_TRY((setup_class<C, R>(B, W, hprobs, rg, nwg)));
+    const Launch &L = W.L;
+    const int nprob = L.nprob;
     CHOM_HIP(hipMemcpyAsync(W.probs.p, hprobs.data(), sizeof(Prob) * nprob, hipMemcpyHostToDevice, s));
     CHOM_HIP(hipMemsetAsync(W.cols.p, 0, sizeof(ColState) * R * nprob, s));
     CHOM_HIP(hipMemsetAsync(W.bad.p, 0, sizeof(int), s));
-    CHOM_HIP((launch_precond<C>(G, W.probs.p, nprob, W.diag.p, W.minv64.p, W.minv32.p, s)));
-    CHOM_HIP((launch_gram<C>(G, nprob, W.minv64.p, W.minv32.p, W.partial.p, W.nwg_gram, W.ginv64.p, W.ginv32.p,
-                             W.bad.p, s)));
-    CHOM_HIP((launch_rhs<C, R>(G, W.probs.p, nprob, W.vpp, W.b.p, W.cols.p, s)));
-    const double rtol2 = rve->opt.rtol * rve->opt.rtol;
+    CHOM_HIP((launch_precond<C>(L, W.total_pts, W.diag.p, W.minv64.p, W.minv32.p, s)));
+    CHOM_HIP((launch_gram<C>(L, W.minv64.p, W.minv32.p, W.partial.p, W.nwg_gram, W.ginv64.p, W.ginv32.p, W.bad.p, s)));
+    CHOM_HIP((launch_rhs<C, R>(L, W.total_vals, W.b.p, W.cols.p, s)));
+    const double rtol2 = B->opt.rtol * B->opt.rtol;
     double *x64 = nullptr;
-    if (rve->opt.precision == CHOM_FP64) {
-        st = pcg<double, C, R>(rve, W, W.b.p, W.xd.p, W.rd.p, W.zd.p, W.pd.p, W.qd.p, W.minv64.p, W.ginv64.p,
-                               rtol2, 0, nullptr, W.probs.p);
-        if (st != CHOM_OK) return st;
+    if (B->opt.precision == CHOM_FP64) {
+        CHOM_TRY((pcg<double, C, R>(B, W, W.graph64, W.b.p, W.xd.p, W.rd.p, W.zd.p, W.pd.p, W.qd.p, W.minv64.p,
+                                    W.ginv64.p, rtol2, 0, nullptr)));
         x64 = W.xd.p;
     } else {
-        const double irtol2 = rve->opt.inner_rtol * rve->opt.inner_rtol;
-        CHOM_HIP(hipMemsetAsync(W.x64.p, 0, sizeof(double) * nv, s));
-        CHOM_HIP((launch_residual64<C, R>(G, nprob, W.vpp, W.b.p, nullptr, W.r64.p, W.r32.p, s)));
+        const double irtol2 = B->opt.inner_rtol * B->opt.inner_rtol;
+        CHOM_HIP(hipMemsetAsync(W.x64.p, 0, sizeof(double) * W.total_vals, s));
+        CHOM_HIP((launch_residual64<C, R>(L, W.b.p, nullptr, W.r64.p, W.r32.p, s)));
         CHOM_HIP(hipMemcpyAsync(W.cols_outer.p, W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToDevice, s));
-        for (int i = 0; i < nprob; ++i) W.refine_steps[i] = 0;
-        for (int step = 0; step <= rve->opt.max_refine; ++step) {
-            // outer residual norm in FP64: r64 . P M^-1 r64 against the linear-field energy
-            CHOM_HIP((launch_cg_init<double, C, R>(G, nprob, W.vpp, W.r64.p, nullptr, nullptr, nullptr, W.minv64.p,
-                                                   W.partial.p, W.nwg_vec, s)));
-            CHOM_HIP((launch_finish_beta<C, R>(nprob, G.nrow, W.partial.p, W.nwg_vec, W.ginv64.p, W.ycoef.p,
-                                               W.cols_outer.p, W.active_outer.p, 1, rtol2, 0, s)));
-            if (G.nrow > 0) {
-                // project the residual vector, then measure it again
-                CHOM_HIP((launch_proj_resid<C, R>(G, nprob, W.vpp, W.r64.p, W.r32.p, W.minv64.p, W.ycoef.p,
-                                                  W.partial.p, W.nwg_vec, s)));
-                CHOM_HIP((launch_finish_beta<C, R>(nprob, G.nrow, W.partial.p, W.nwg_vec, W.ginv64.p, W.ycoef.p,
-                                                   W.cols_outer.p, W.active_outer.p, 1, rtol2, 0, s)));
+        for (int step = 0; step <= B->opt.max_refine; ++step) {
+            // outer residual norm in FP64: project r64, then r64 . M^-1 r64 against the linear-field energy
+            CHOM_HIP((launch_cg_init<double, C, R>(L, W.r64.p, nullptr, nullptr, nullptr, W.minv64.p, W.partial.p, s)));
+            CHOM_HIP((launch_finish_beta<C, R>(L, W.partial.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p, W.active_outer.p,
+                                               1, rtol2, 0, nullptr, s)));
+            if (L.nr > 0) {
+                CHOM_HIP((launch_proj_resid<C, R>(L, W.r64.p, W.r32.p, W.minv64.p, W.ycoef.p, W.partial.p, s)));
+                CHOM_HIP((launch_finish_beta<C, R>(L, W.partial.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p,
+                                                   W.active_outer.p, 1, rtol2, 0, nullptr, s)));
             }
             CHOM_HIP(hipMemcpyAsync(W.h_active.data(), W.active_outer.p, sizeof(int) * nprob, hipMemcpyDeviceToHost, s));
             CHOM_HIP(hipStreamSynchronize(s));
@@ -323,20 +451,20 @@ static int run_class(chom_rve *rve, ClassWS<C, R> &W, const std::vector<Prob> &h
                 act += W.h_active[i];
                 if (W.h_active[i]) W.refine_steps[i] = step;
             }
-            if (act == 0 || step == rve->opt.max_refine) break;
-            st = pcg<float, C, R>(rve, W, W.r32.p, W.xf.p, W.rf.p, W.zf.p, W.pf.p, W.qf.p, W.minv32.p, W.ginv32.p,
-                                  irtol2, 1, W.cols_outer.p, W.probs.p);
-            if (st != CHOM_OK) return st;
-            CHOM_HIP((launch_axpy_x64<C, R>(nprob, W.vpp, W.x64.p, W.xf.p, s)));
-            CHOM_HIP((launch_operator<double, C, R>(G, W.probs.p, nprob, W.x64.p, W.q64.p, W.partial.p, nullptr, s)));
-            CHOM_HIP((launch_residual64<C, R>(G, nprob, W.vpp, W.b.p, W.q64.p, W.r64.p, W.r32.p, s)));
+            if (act == 0 || step == B->opt.max_refine) break;
+            CHOM_TRY((pcg<float, C, R>(B, W, W.graph32, W.r32.p, W.xf.p, W.rf.p, W.zf.p, W.pf.p, W.qf.p, W.minv32.p,
+                                       W.ginv32.p, irtol2, 1, W.cols_outer.p)));
+            CHOM_HIP(launch_axpy_x64(W.total_vals, W.x64.p, W.xf.p, s));
+            CHOM_HIP((launch_operator<double, C, R>(L.geos, L.probs, nprob, L.max_tiles, L.rg, W.x64.p, W.q64.p,
+                                                    W.partial.p, nullptr, s)));
+            CHOM_HIP((launch_residual64<C, R>(L, W.b.p, W.q64.p, W.r64.p, W.r32.p, s)));
         }
         x64 = W.x64.p;
     }
-    CHOM_HIP((launch_project<C, R>(G, nprob, W.vpp, x64, W.minv64.p, W.ginv64.p, W.partial.p, W.nwg_vec, s)));
-    CHOM_HIP((launch_average<C, R>(G, W.probs.p, nprob, W.vpp, x64, W.partial.p, W.nwg_avg, W.avg_out.p, s)));
+    CHOM_HIP((launch_project<C, R>(L, x64, W.minv64.p, W.ginv64.p, W.partial.p, s)));
+    CHOM_HIP((launch_average<C, R>(L, x64, W.partial.p, W.nwg_avg, W.avg_out.p, s)));
     CHOM_HIP(hipMemcpyAsync(W.h_cols.data(), W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToHost, s));
-    if (rve->opt.precision == CHOM_FP32_REFINED)
+    if (B->opt.precision == CHOM_FP32_REFINED)
         CHOM_HIP(hipMemcpyAsync(W.h_cols_outer.data(), W.cols_outer.p, sizeof(ColState) * R * nprob,
                                 hipMemcpyDeviceToHost, s));
     int hbad = 0;
@@ -349,8 +477,325 @@ static int run_class(chom_rve *rve, ClassWS<C, R> &W, const std::vector<Prob> &h
     return CHOM_OK;
 }
 
-// ------------------------------------------------------------------ mesh checks
+// Time `reps` operator launches of a class with load-case grouping rg (ms per launch).
+template <typename T, int C, int R>
+static int time_op(chom_batch *B, ClassWS<C, R> &W, const T *x, T *y, int rg, int reps, double *ms) {
+    const Launch &L = W.L;
+    hipStream_t s = B->stream;
+    hipEvent_t e0, e1;
+    CHOM_HIP(hipEventCreate(&e0));
+    CHOM_HIP(hipEventCreate(&e1));
+    CHOM_HIP((launch_operator<T, C, R>(L.geos, L.probs, L.nprob, L.max_tiles, rg, x, y, W.partial.p, nullptr, s)));
+    CHOM_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i)
+        CHOM_HIP((launch_operator<T, C, R>(L.geos, L.probs, L.nprob, L.max_tiles, rg, x, y, W.partial.p, nullptr, s)));
+    CHOM_HIP(hipEventRecord(e1, s));
+    CHOM_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    CHOM_HIP(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = (double)t / reps;
+    return CHOM_OK;
+}
+
+// Time `reps` CG vector sweeps (dir + update) with nwg workgroups per problem.
+template <typename T, int C, int R>
+static int time_vec(chom_batch *B, ClassWS<C, R> &W, T *x, T *r, T *z, T *p, const T *q, const void *minv, int nwg,
+                    int reps, double *ms) {
+    Launch L = W.L;
+    L.nwg = nwg;
+    hipStream_t s = B->stream;
+    std::vector<int> ones(L.nprob, 1);
+    CHOM_HIP(hipMemcpyAsync(W.active.p, ones.data(), sizeof(int) * L.nprob, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipMemsetAsync(W.cols.p, 0, sizeof(ColState) * R * L.nprob, s));
+    hipEvent_t e0, e1;
+    CHOM_HIP(hipEventCreate(&e0));
+    CHOM_HIP(hipEventCreate(&e1));
+    CHOM_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) {
+        CHOM_HIP((launch_cg_dir<T, C, R>(L, r, z, p, minv, W.ycoef.p, W.cols.p, W.active.p, s)));
+        CHOM_HIP((launch_cg_update<T, C, R>(L, x, r, z, p, q, minv, W.cols.p, W.partial.p, W.active.p, s)));
+    }
+    CHOM_HIP(hipEventRecord(e1, s));
+    CHOM_HIP(hipEventSynchronize(e1));
+    float t = 0.f;
+    CHOM_HIP(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    CHOM_HIP(hipStreamSynchronize(s));
+    *ms = (double)t / reps;
+    return CHOM_OK;
+}
+
+// Autotune one class: operator grouping rg and vector workgroups per problem,
+// timed on the batch's own problem table with zero operands (the cost of these
+// kernels does not depend on the values).
+template <int C, int R>
+static int autotune_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, const std::string &key,
+                          int *rg_out, int *nwg_out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+        *rg_out = it->second.first;
+        *nwg_out = it->second.second;
+        return CHOM_OK;
+    }
+    CHOM_TRY((setup_class<C, R>(B, W, hp, *rg_out, 1024)));   // partials sized for the largest candidate
+    hipStream_t s = B->stream;
+    CHOM_HIP(hipMemcpyAsync(W.probs.p, hp.data(), sizeof(Prob) * hp.size(), hipMemcpyHostToDevice, s));
+    const bool f32 = B->opt.precision == CHOM_FP32_REFINED;
+    const size_t nv = W.total_vals, nq = W.total_q;
+    if (f32) {
+        CHOM_HIP(hipMemsetAsync(W.pf.p, 0, sizeof(float) * nv, s));
+        CHOM_HIP(hipMemsetAsync(W.zf.p, 0, sizeof(float) * nv, s));
+        CHOM_HIP(hipMemsetAsync(W.rf.p, 0, sizeof(float) * nv, s));
+        CHOM_HIP(hipMemsetAsync(W.xf.p, 0, sizeof(float) * nv, s));
+        CHOM_HIP(hipMemsetAsync(W.qf.p, 0, sizeof(float) * nq, s));
+        CHOM_HIP(hipMemsetAsync(W.minv32.p, 0, sizeof(float) * W.total_pts * ClassWS<C, R>::MS, s));
+    } else {
+        CHOM_HIP(hipMemsetAsync(W.pd.p, 0, sizeof(double) * nv, s));
+        CHOM_HIP(hipMemsetAsync(W.zd.p, 0, sizeof(double) * nv, s));
+        CHOM_HIP(hipMemsetAsync(W.rd.p, 0, sizeof(double) * nv, s));
+        CHOM_HIP(hipMemsetAsync(W.xd.p, 0, sizeof(double) * nv, s));
+        CHOM_HIP(hipMemsetAsync(W.qd.p, 0, sizeof(double) * nq, s));
+        CHOM_HIP(hipMemsetAsync(W.minv64.p, 0, sizeof(double) * W.total_pts * ClassWS<C, R>::MS, s));
+    }
+    CHOM_HIP(hipMemsetAsync(W.ycoef.p, 0, sizeof(double) * W.ycoef.n, s));
+    const int rgs_mech[3] = {1, 2, 3}, rgs_scal[2] = {1, 3};
+    const int *rgs = (C == 3) ? rgs_mech : rgs_scal;
+    const int nrg = (C == 3) ? 3 : 2;
+    double best = 1e30;
+    int best_rg = *rg_out;
+    for (int i = 0; i < nrg; ++i) {
+        double ms;
+        if (f32) CHOM_TRY((time_op<float, C, R>(B, W, W.pf.p, W.qf.p, rgs[i], 5, &ms)));
+        else CHOM_TRY((time_op<double, C, R>(B, W, W.pd.p, W.qd.p, rgs[i], 5, &ms)));
+        if (ms < best) {
+            best = ms;
+            best_rg = rgs[i];
+        }
+    }
+    W.L.rg = best_rg;
+    const int nwgs[4] = {128, 256, 512, 1024};
+    best = 1e30;
+    int best_nwg = W.L.nwg;
+    for (int i = 0; i < 4; ++i) {
+        double ms;
+        if (f32) CHOM_TRY((time_vec<float, C, R>(B, W, W.xf.p, W.rf.p, W.zf.p, W.pf.p, W.qf.p, W.minv32.p, nwgs[i], 5, &ms)));
+        else CHOM_TRY((time_vec<double, C, R>(B, W, W.xd.p, W.rd.p, W.zd.p, W.pd.p, W.qd.p, W.minv64.p, nwgs[i], 5, &ms)));
+        if (ms < best) {
+            best = ms;
+            best_nwg = nwgs[i];
+        }
+    }
+    *rg_out = best_rg;
+    *nwg_out = best_nwg;
+    tune_store(key, best_rg, best_nwg);
+    return CHOM_OK;
+}
+
+static std::string tune_key(chom_batch *B, int physics) {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::string name = "gpu";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) name = prop.gcnArchName;
+    for (auto &ch : name)
+        if (ch == ' ' || ch == ':') ch = '_';
+    std::string key = name + "/" + (physics == 0 ? "mech" : "scal") + "/" +
+                      (B->opt.precision == CHOM_FP32_REFINED ? "f32" : "f64") + "/";
+    std::map<std::pair<int, int>, int> sizes;
+    for (auto *r : B->entries) sizes[{r->n, r->bc}] += 1;
+    for (auto &kv : sizes)
+        key += std::to_string(kv.first.first) + "b" + std::to_string(kv.first.second) + "x" + std::to_string(kv.second) + ",";
+    return key;
+}
+
+// ------------------------------------------------------------------ batch solve
+static int batch_init(chom_batch *B, chom_rve *const *rves, int n, const chom_options *opt) {
+    B->entries.assign(rves, rves + n);
+    std::map<chom_rve *, int> idx;
+    for (int i = 0; i < n; ++i) {
+        auto it = idx.find(rves[i]);
+        if (it == idx.end()) {
+            const int k = (int)B->distinct.size();
+            idx[rves[i]] = k;
+            B->distinct.push_back(rves[i]);
+            B->geo_of.push_back(k);
+        } else {
+            B->geo_of.push_back(it->second);
+        }
+    }
+    B->opt = *opt;
+    if (B->opt.hip_stream) {
+        B->stream = (hipStream_t)B->opt.hip_stream;
+    } else {
+        CHOM_HIP(hipStreamCreate(&B->stream));   // default priority
+        B->own_stream = true;
+    }
+    std::vector<Geo> hg;
+    for (auto *r : B->distinct) hg.push_back(r->geo);
+    CHOM_HIP(B->geos.ensure(hg.size()));
+    CHOM_HIP(hipMemcpyAsync(B->geos.p, hg.data(), sizeof(Geo) * hg.size(), hipMemcpyHostToDevice, B->stream));
+    CHOM_HIP(hipStreamSynchronize(B->stream));
+    return CHOM_OK;
+}
+
+static int batch_homogenise(chom_batch *B, const chom_params *params, double *C_hom, double *K_hom, double *D_hom,
+                            chom_report *rep) {
+    const int batch = (int)B->entries.size();
+    hipStream_t s = B->stream;
+    std::vector<chom_params> hp(batch);
+    if (B->opt.device_ptrs)
+        CHOM_HIP(hipMemcpy(hp.data(), params, sizeof(chom_params) * batch, hipMemcpyDeviceToHost));
+    else
+        std::memcpy(hp.data(), params, sizeof(chom_params) * batch);
+    std::vector<Prob> pm(batch), ps(2 * batch);
+    std::vector<double> keep(batch);
+    for (int i = 0; i < batch; ++i) {
+        chom_rve *rv = B->entries[i];
+        double m10[10], t4[4], d4[4];
+        const int st = material_constants(&rv->mat, &hp[i], B->opt.c_sat, B->opt.degrade_yarn, m10, t4, d4, &keep[i]);
+        if (st != CHOM_OK) {
+            set_error(std::string("record ") + std::to_string(i) + ": " + g_last_error);
+            return st;
+        }
+        std::memset(&pm[i], 0, sizeof(Prob));
+        std::memset(&ps[i], 0, sizeof(Prob));
+        std::memset(&ps[batch + i], 0, sizeof(Prob));
+        for (int ph = 0; ph < 2; ++ph)
+            for (int k = 0; k < 5; ++k) {
+                pm[i].mat64[ph][k] = m10[5 * ph + k];
+                pm[i].mat32[ph][k] = (float)m10[5 * ph + k];
+            }
+        for (int ph = 0; ph < 2; ++ph)
+            for (int k = 0; k < 2; ++k) {
+                ps[i].mat64[ph][k] = t4[2 * ph + k];
+                ps[i].mat32[ph][k] = (float)t4[2 * ph + k];
+                ps[batch + i].mat64[ph][k] = d4[2 * ph + k];
+                ps[batch + i].mat32[ph][k] = (float)d4[2 * ph + k];
+            }
+        pm[i].geo = ps[i].geo = ps[batch + i].geo = B->geo_of[i];
+    }
+    if (!B->tuned && std::getenv("CHOM_AUTOTUNE")) {
+        CHOM_TRY((autotune_class<3, 6>(B, B->mech, pm, tune_key(B, 0), &B->rg_mech, &B->nwg_mech)));
+        CHOM_TRY((autotune_class<1, 3>(B, B->scal, ps, tune_key(B, 1), &B->rg_scal, &B->nwg_scal)));
+        B->tuned = true;
+    }
+    CHOM_TRY((run_class<3, 6>(B, B->mech, pm, B->rg_mech, B->nwg_mech)));
+    CHOM_TRY((run_class<1, 3>(B, B->scal, ps, B->rg_scal, B->nwg_scal)));
+    std::vector<double> cm((size_t)batch * 36), cs((size_t)2 * batch * 9);
+    CHOM_HIP(hipMemcpyAsync(cm.data(), B->mech.avg_out.p, sizeof(double) * cm.size(), hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipMemcpyAsync(cs.data(), B->scal.avg_out.p, sizeof(double) * cs.size(), hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipStreamSynchronize(s));
+    std::vector<double> oc((size_t)batch * 21), ok((size_t)batch * 6), od((size_t)batch * 6);
+    int overall = CHOM_OK;
+    const bool refined = B->opt.precision == CHOM_FP32_REFINED;
+    const double rtol2 = B->opt.rtol * B->opt.rtol;
+    for (int i = 0; i < batch; ++i) {
+        const double *Cm = &cm[(size_t)i * 36];
+        int q = 0;
+        double fro = 0, asym = 0;
+        for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) {
+                if (b >= a) oc[(size_t)i * 21 + q++] = Cm[a * 6 + b];
+                fro += Cm[a * 6 + b] * Cm[a * 6 + b];
+                const double dlt = Cm[a * 6 + b] - Cm[b * 6 + a];
+                asym += dlt * dlt;
+            }
+        const double *Kt = &cs[(size_t)i * 9], *Dt = &cs[(size_t)(batch + i) * 9];
+        const int ui[6] = {0, 4, 8, 1, 5, 2};
+        for (int k = 0; k < 6; ++k) {
+            ok[(size_t)i * 6 + k] = Kt[ui[k]];
+            od[(size_t)i * 6 + k] = Dt[ui[k]];
+        }
+        chom_report Rp;
+        std::memset(&Rp, 0, sizeof(Rp));
+        Rp.status = CHOM_OK;
+        Rp.asym = fro > 0 ? std::sqrt(asym / fro) : 0.0;
+        Rp.omega_keep = keep[i];
+        for (int c = 0; c < 12; ++c) {
+            const ColState *cin, *cout;
+            if (c < 6) {
+                cin = &B->mech.h_cols[(size_t)i * 6 + c];
+                cout = refined ? &B->mech.h_cols_outer[(size_t)i * 6 + c] : cin;
+            } else {
+                const int pidx = (c < 9) ? i : batch + i;
+                const int ridx = (c < 9) ? c - 6 : c - 9;
+                cin = &B->scal.h_cols[(size_t)pidx * 3 + ridx];
+                cout = refined ? &B->scal.h_cols_outer[(size_t)pidx * 3 + ridx] : cin;
+            }
+            Rp.iters[c] = cin->iters;
+            Rp.resid[c] = cout->eref > 0 ? std::sqrt(cout->rz / cout->eref) : 0.0;
+            const bool conv = (cout->done == 1) || (cout->rz <= rtol2 * cout->eref);
+            if (!conv) Rp.status = CHOM_ENOCONV;
+        }
+        if (refined) {
+            Rp.refine_steps[0] = B->mech.refine_steps[i];
+            Rp.refine_steps[1] = B->scal.refine_steps[i];
+            Rp.refine_steps[2] = B->scal.refine_steps[batch + i];
+        }
+        if (Rp.status != CHOM_OK) overall = CHOM_ENOCONV;
+        if (rep) rep[i] = Rp;
+    }
+    if (B->opt.device_ptrs) {
+        CHOM_HIP(hipMemcpyAsync(C_hom, oc.data(), sizeof(double) * oc.size(), hipMemcpyHostToDevice, s));
+        CHOM_HIP(hipMemcpyAsync(K_hom, ok.data(), sizeof(double) * ok.size(), hipMemcpyHostToDevice, s));
+        CHOM_HIP(hipMemcpyAsync(D_hom, od.data(), sizeof(double) * od.size(), hipMemcpyHostToDevice, s));
+        CHOM_HIP(hipStreamSynchronize(s));
+    } else {
+        std::memcpy(C_hom, oc.data(), sizeof(double) * oc.size());
+        std::memcpy(K_hom, ok.data(), sizeof(double) * ok.size());
+        std::memcpy(D_hom, od.data(), sizeof(double) * od.size());
+    }
+    if (overall != CHOM_OK) set_error("some load case did not converge");
+    return overall;
+}
+
+static int check_options(const chom_options &o) {
+    if (o.precision != CHOM_FP64 && o.precision != CHOM_FP32_REFINED) {
+        set_error("unknown precision");
+        return CHOM_EINVAL;
+    }
+    if (o.precond != CHOM_PRECOND_BLOCK_JACOBI) {
+        set_error("unknown preconditioner");
+        return CHOM_EINVAL;
+    }
+    if (!(o.rtol > 0) || !(o.inner_rtol > 0) || o.max_iter < 1 || o.max_refine < 0 || !(o.c_sat > 0)) {
+        set_error("bad tolerances or caps");
+        return CHOM_EINVAL;
+    }
+    return CHOM_OK;
+}
+
 static int64_t kuhn_vertex(int i, int j, int k, int n) { return i + (int64_t)(n + 1) * (j + (int64_t)(n + 1) * k); }
+
+static int batch_time_operator(chom_batch *B, int32_t physics, int32_t reps, double *ms_per_launch,
+                               int64_t *tets_per_launch, int32_t *problems_per_launch) {
+    if (!B || !ms_per_launch || reps < 1 || (physics != 0 && physics != 1)) {
+        set_error("time_operator: bad argument");
+        return CHOM_EINVAL;
+    }
+    const bool f32 = B->opt.precision == CHOM_FP32_REFINED;
+    if ((physics == 0 ? B->mech.L.nprob : B->scal.L.nprob) == 0) {
+        set_error("time_operator: call the homogenise function first (the timing reuses its workspace)");
+        return CHOM_EINVAL;
+    }
+    if (physics == 0) {
+        if (f32) CHOM_TRY((time_op<float, 3, 6>(B, B->mech, B->mech.pf.p, B->mech.qf.p, B->mech.L.rg, reps, ms_per_launch)));
+        else CHOM_TRY((time_op<double, 3, 6>(B, B->mech, B->mech.pd.p, B->mech.qd.p, B->mech.L.rg, reps, ms_per_launch)));
+    } else {
+        if (f32) CHOM_TRY((time_op<float, 1, 3>(B, B->scal, B->scal.pf.p, B->scal.qf.p, B->scal.L.rg, reps, ms_per_launch)));
+        else CHOM_TRY((time_op<double, 1, 3>(B, B->scal, B->scal.pd.p, B->scal.qd.p, B->scal.L.rg, reps, ms_per_launch)));
+    }
+    int64_t tets = 0;
+    for (auto *r : B->entries) tets += 6LL * r->n * r->n * r->n;
+    if (tets_per_launch) *tets_per_launch = physics == 0 ? tets : 2 * tets;
+    if (problems_per_launch) *problems_per_launch = physics == 0 ? (int)B->entries.size() : 2 * (int)B->entries.size();
+    return CHOM_OK;
+}
 
 }  // namespace chom
 
@@ -358,7 +803,7 @@ static int64_t kuhn_vertex(int i, int j, int k, int n) { return i + (int64_t)(n 
 extern "C" {
 
 const char *chom_last_error(void) { return chom::g_last_error.c_str(); }
-const char *chom_version(void) { return "chom 0.1 (gfx950, p=2 lattice operator)"; }
+const char *chom_version(void) { return "chom 0.2 (gfx950, order-2 lattice operator, batched)"; }
 
 int chom_default_options(chom_options *opt) {
     if (!opt) return CHOM_EINVAL;
@@ -388,8 +833,7 @@ int chom_mesh_sizes(int32_t n, int32_t *nv, int32_t *nt) {
     return CHOM_OK;
 }
 
-int chom_generate_plain_weave(int32_t n, double *coords, int32_t *tets, int8_t *phase, double *axis,
-                              void *stream) {
+int chom_generate_plain_weave(int32_t n, double *coords, int32_t *tets, int8_t *phase, double *axis, void *stream) {
     int32_t nv, nt;
     int st = chom_mesh_sizes(n, &nv, &nt);
     if (st != CHOM_OK) return st;
@@ -403,9 +847,8 @@ int chom_generate_plain_weave(int32_t n, double *coords, int32_t *tets, int8_t *
     return CHOM_OK;
 }
 
-int chom_material_constants(const chom_materials *mat, const chom_params *params, double c_sat,
-                            int32_t degrade_yarn, double *out_mech, double *out_therm, double *out_moist,
-                            double *omega_keep) {
+int chom_material_constants(const chom_materials *mat, const chom_params *params, double c_sat, int32_t degrade_yarn,
+                            double *out_mech, double *out_therm, double *out_moist, double *omega_keep) {
     if (!mat || !out_mech || !out_therm || !out_moist) {
         set_error("chom_material_constants: null argument");
         return CHOM_EINVAL;
@@ -431,15 +874,13 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
     chom_options o;
     chom_default_options(&o);
     if (opt) o = *opt;
-    if (o.precision != CHOM_FP64 && o.precision != CHOM_FP32_REFINED) {
-        set_error("chom_rve_create: unknown precision");
-        return CHOM_EINVAL;
+    {
+        const int st = check_options(o);
+        if (st != CHOM_OK) {
+            set_error("chom_rve_create: " + g_last_error);
+            return st;
+        }
     }
-    if (!(o.rtol > 0) || !(o.inner_rtol > 0) || o.max_iter < 1 || o.max_refine < 0 || !(o.c_sat > 0)) {
-        set_error("chom_rve_create: bad tolerances or caps");
-        return CHOM_EINVAL;
-    }
-    // --- mesh size: (n+1)^3 vertices, 6 n^3 tets
     int n = (int)std::lround(std::cbrt((double)mesh->n_tets / 6.0));
     if (n < 1 || 6LL * n * n * n != mesh->n_tets || (int64_t)(n + 1) * (n + 1) * (n + 1) != mesh->n_vertices) {
         set_error("chom_rve_create: mesh is not a Kuhn lattice (need (n+1)^3 vertices and 6 n^3 tets)");
@@ -455,7 +896,6 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
             return CHOM_EMESH;
         }
     const int64_t nv = mesh->n_vertices, nt = mesh->n_tets;
-    // --- host copies for validation
     std::vector<double> hc(3 * nv), hax(3 * nt);
     std::vector<int32_t> ht(4 * nt);
     std::vector<int8_t> hph(nt);
@@ -496,15 +936,13 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
             return CHOM_EMESH;
         }
         if (hph[e] > 0) {
-            const double nr = std::sqrt(hax[3 * e] * hax[3 * e] + hax[3 * e + 1] * hax[3 * e + 1] +
-                                        hax[3 * e + 2] * hax[3 * e + 2]);
+            const double nr = std::sqrt(hax[3 * e] * hax[3 * e] + hax[3 * e + 1] * hax[3 * e + 1] + hax[3 * e + 2] * hax[3 * e + 2]);
             if (!(std::fabs(nr - 1.0) < 1e-6)) {
                 set_error("chom_rve_create: yarn fibre axis must be a unit vector");
                 return CHOM_EMESH;
             }
         }
     }
-    // boundary vertices on their faces; uniform grid detection; periodic face matching
     bool uniform = true;
     double h[3];
     for (int d = 0; d < 3; ++d) h[d] = (mesh->hi[d] - mesh->lo[d]) / n;
@@ -538,6 +976,10 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
                     }
                 }
             }
+    {
+        double m10[10], t4[4], d4[4];
+        if (material_constants(mat, nullptr, o.c_sat, o.degrade_yarn, m10, t4, d4, nullptr) != CHOM_OK) return CHOM_EMATERIAL;
+    }
     std::unique_ptr<chom_rve> R(new chom_rve());
     R->n = n;
     R->bc = bc;
@@ -548,11 +990,6 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
     }
     R->mat = *mat;
     R->opt = o;
-    {
-        double m10[10], t4[4], d4[4];
-        if (material_constants(mat, nullptr, o.c_sat, o.degrade_yarn, m10, t4, d4, nullptr) != CHOM_OK)
-            return CHOM_EMATERIAL;
-    }
     Geo &G = R->geo;
     std::memset(&G, 0, sizeof(G));
     G.n = n;
@@ -565,7 +1002,7 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
     G.tiles_x = (n + TX - 1) / TX;
     G.tiles_y = (n + TY - 1) / TY;
     G.tiles_z = (n + TZ - 1) / TZ;
-    // uniform geometry per tet type
+    G.ntiles = G.tiles_x * G.tiles_y * G.tiles_z;
     for (int t = 0; t < 6; ++t) {
         int p0, p1;
         kuhn_perm(t, p0, p1);
@@ -597,7 +1034,6 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
         CHOM_HIP(R->geo32.ensure(10 * nt));
     }
     CHOM_HIP(R->rows.ensure(4 * G.npts));
-    // device copies of coords / phase / axis
     DevBuf<double> dc, dax;
     DevBuf<int8_t> dph;
     DevBuf<int> dbad;
@@ -630,55 +1066,88 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
 
 void chom_rve_destroy(chom_rve *rve) { delete rve; }
 
-int chom_time_operator(chom_rve *rve, int32_t physics, int32_t reps, double *ms_per_launch,
-                       int64_t *tets_per_launch, int32_t *problems_per_launch) {
-    if (!rve || !ms_per_launch || reps < 1 || (physics != 0 && physics != 1)) {
-        set_error("chom_time_operator: bad argument");
+int chom_homogenise(chom_rve *rve, const chom_params *params, int32_t batch, double *C_hom, double *K_hom,
+                    double *D_hom, chom_report *rep) {
+    if (!rve || !params || !C_hom || !K_hom || !D_hom || batch < 1) {
+        set_error("chom_homogenise: null argument or batch < 1");
         return CHOM_EINVAL;
     }
-    const Geo &G = rve->geo;
-    hipStream_t s = stream_of(rve);
-    const bool f32 = rve->opt.precision == CHOM_FP32_REFINED;
-    const int nprob = physics == 0 ? rve->mech.nprob : rve->scal.nprob;
-    if (nprob == 0) {
+    if (!rve->self || rve->self_size != batch) {
+        rve->self.reset();
+        std::unique_ptr<chom_batch> B(new chom_batch());
+        std::vector<chom_rve *> ents(batch, rve);
+        const int st = batch_init(B.get(), ents.data(), batch, &rve->opt);
+        if (st != CHOM_OK) return st;
+        rve->self = std::move(B);
+        rve->self_size = batch;
+    }
+    const int st = batch_homogenise(rve->self.get(), params, C_hom, K_hom, D_hom, rep);
+    if (st != CHOM_OK) set_error("chom_homogenise: " + g_last_error);
+    return st;
+}
+
+int chom_time_operator(chom_rve *rve, int32_t physics, int32_t reps, double *ms_per_launch, int64_t *tets_per_launch,
+                       int32_t *problems_per_launch) {
+    if (!rve || !rve->self) {
         set_error("chom_time_operator: call chom_homogenise first (the timing reuses its workspace)");
         return CHOM_EINVAL;
     }
-    hipEvent_t e0, e1;
-    CHOM_HIP(hipEventCreate(&e0));
-    CHOM_HIP(hipEventCreate(&e1));
-    CHOM_HIP(hipEventRecord(e0, s));
-    for (int i = 0; i < reps; ++i) {
-        if (physics == 0) {
-            if (f32)
-                CHOM_HIP((launch_operator<float, 3, 6>(G, rve->mech.probs.p, nprob, rve->mech.pf.p, rve->mech.qf.p,
-                                                      rve->mech.partial.p, nullptr, s)));
-            else
-                CHOM_HIP((launch_operator<double, 3, 6>(G, rve->mech.probs.p, nprob, rve->mech.pd.p, rve->mech.qd.p,
-                                                       rve->mech.partial.p, nullptr, s)));
-        } else {
-            if (f32)
-                CHOM_HIP((launch_operator<float, 1, 3>(G, rve->scal.probs.p, nprob, rve->scal.pf.p, rve->scal.qf.p,
-                                                      rve->scal.partial.p, nullptr, s)));
-            else
-                CHOM_HIP((launch_operator<double, 1, 3>(G, rve->scal.probs.p, nprob, rve->scal.pd.p, rve->scal.qd.p,
-                                                       rve->scal.partial.p, nullptr, s)));
-        }
+    return batch_time_operator(rve->self.get(), physics, reps, ms_per_launch, tets_per_launch, problems_per_launch);
+}
+
+int chom_batch_create(chom_rve *const *rves, int32_t n, const chom_options *opt, chom_batch **out) {
+    if (!rves || n < 1 || !out) {
+        set_error("chom_batch_create: null argument or n < 1");
+        return CHOM_EINVAL;
     }
-    CHOM_HIP(hipEventRecord(e1, s));
-    CHOM_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    CHOM_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    *ms_per_launch = (double)ms / reps;
-    if (tets_per_launch) *tets_per_launch = 6LL * G.n * G.n * G.n * nprob;
-    if (problems_per_launch) *problems_per_launch = nprob;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i)
+        if (!rves[i]) {
+            set_error("chom_batch_create: null RVE handle");
+            return CHOM_EINVAL;
+        }
+    chom_options o = rves[0]->opt;
+    if (opt) o = *opt;
+    CHOM_TRY(check_options(o));
+    std::unique_ptr<chom_batch> B(new chom_batch());
+    CHOM_TRY(batch_init(B.get(), rves, n, &o));
+    *out = B.release();
     return CHOM_OK;
 }
 
-int chom_element_apply_host(int32_t ncomp, const double *grad_lam, double vol, const double *axis,
-                            const double *inv5, const double *u, double *y) {
+int chom_batch_homogenise(chom_batch *batch, const chom_params *params, double *C_hom, double *K_hom, double *D_hom,
+                          chom_report *rep) {
+    if (!batch || !params || !C_hom || !K_hom || !D_hom) {
+        set_error("chom_batch_homogenise: null argument");
+        return CHOM_EINVAL;
+    }
+    const int st = batch_homogenise(batch, params, C_hom, K_hom, D_hom, rep);
+    if (st != CHOM_OK) set_error("chom_batch_homogenise: " + g_last_error);
+    return st;
+}
+
+int chom_batch_time_operator(chom_batch *batch, int32_t physics, int32_t reps, double *ms_per_launch,
+                             int64_t *tets_per_launch, int32_t *problems_per_launch) {
+    return batch_time_operator(batch, physics, reps, ms_per_launch, tets_per_launch, problems_per_launch);
+}
+
+int chom_batch_launch_config(const chom_batch *batch, int32_t *rg_mech, int32_t *rg_scal, int32_t *nwg_mech,
+                             int32_t *nwg_scal) {
+    if (!batch) {
+        set_error("chom_batch_launch_config: null batch");
+        return CHOM_EINVAL;
+    }
+    if (rg_mech) *rg_mech = batch->rg_mech;
+    if (rg_scal) *rg_scal = batch->rg_scal;
+    if (nwg_mech) *nwg_mech = batch->mech.L.nwg;
+    if (nwg_scal) *nwg_scal = batch->scal.L.nwg;
+    return CHOM_OK;
+}
+
+void chom_batch_destroy(chom_batch *batch) { delete batch; }
+
+int chom_element_apply_host(int32_t ncomp, const double *grad_lam, double vol, const double *axis, const double *inv5,
+                            const double *u, double *y) {
     if (!grad_lam || !axis || !inv5 || !u || !y || (ncomp != 1 && ncomp != 3)) {
         set_error("chom_element_apply_host: bad argument");
         return CHOM_EINVAL;
@@ -701,125 +1170,6 @@ int chom_element_apply_host(int32_t ncomp, const double *grad_lam, double vol, c
         for (int k = 0; k < 10; ++k) y[k] = yy[k][0];
     }
     return CHOM_OK;
-}
-
-int chom_homogenise(chom_rve *rve, const chom_params *params, int32_t batch, double *C_hom, double *K_hom,
-                    double *D_hom, chom_report *rep) {
-    if (!rve || !params || !C_hom || !K_hom || !D_hom || batch < 1) {
-        set_error("chom_homogenise: null argument or batch < 1");
-        return CHOM_EINVAL;
-    }
-    hipStream_t s = stream_of(rve);
-    std::vector<chom_params> hp(batch);
-    if (rve->opt.device_ptrs)
-        CHOM_HIP(hipMemcpy(hp.data(), params, sizeof(chom_params) * batch, hipMemcpyDeviceToHost));
-    else
-        std::memcpy(hp.data(), params, sizeof(chom_params) * batch);
-    std::vector<Prob> pm(batch), ps(2 * batch);
-    std::vector<double> keep(batch);
-    for (int i = 0; i < batch; ++i) {
-        double m10[10], t4[4], d4[4];
-        const int st = material_constants(&rve->mat, &hp[i], rve->opt.c_sat, rve->opt.degrade_yarn, m10, t4, d4, &keep[i]);
-        if (st != CHOM_OK) {
-            set_error(std::string("chom_homogenise: record ") + std::to_string(i) + ": " + g_last_error);
-            return st;
-        }
-        std::memset(&pm[i], 0, sizeof(Prob));
-        std::memset(&ps[i], 0, sizeof(Prob));
-        std::memset(&ps[batch + i], 0, sizeof(Prob));
-        for (int ph = 0; ph < 2; ++ph)
-            for (int k = 0; k < 5; ++k) {
-                pm[i].mat64[ph][k] = m10[5 * ph + k];
-                pm[i].mat32[ph][k] = (float)m10[5 * ph + k];
-            }
-        for (int ph = 0; ph < 2; ++ph)
-            for (int k = 0; k < 2; ++k) {
-                ps[i].mat64[ph][k] = t4[2 * ph + k];
-                ps[i].mat32[ph][k] = (float)t4[2 * ph + k];
-                ps[batch + i].mat64[ph][k] = d4[2 * ph + k];
-                ps[batch + i].mat32[ph][k] = (float)d4[2 * ph + k];
-            }
-    }
-    const Geo &G = rve->geo;
-    for (int i = 0; i < batch; ++i) {
-        pm[i].voff = (long long)i * G.npts * 18;
-        pm[i].doff = (long long)i * G.npts;
-    }
-    for (int i = 0; i < 2 * batch; ++i) {
-        ps[i].voff = (long long)i * G.npts * 3;
-        ps[i].doff = (long long)i * G.npts;
-    }
-    int st = run_class<3, 6>(rve, rve->mech, pm);
-    if (st != CHOM_OK) return st;
-    st = run_class<1, 3>(rve, rve->scal, ps);
-    if (st != CHOM_OK) return st;
-    // gather results
-    std::vector<double> cm((size_t)batch * 36), cs((size_t)2 * batch * 9);
-    CHOM_HIP(hipMemcpyAsync(cm.data(), rve->mech.avg_out.p, sizeof(double) * cm.size(), hipMemcpyDeviceToHost, s));
-    CHOM_HIP(hipMemcpyAsync(cs.data(), rve->scal.avg_out.p, sizeof(double) * cs.size(), hipMemcpyDeviceToHost, s));
-    CHOM_HIP(hipStreamSynchronize(s));
-    std::vector<double> oc((size_t)batch * 21), ok((size_t)batch * 6), od((size_t)batch * 6);
-    int overall = CHOM_OK;
-    const bool refined = rve->opt.precision == CHOM_FP32_REFINED;
-    for (int i = 0; i < batch; ++i) {
-        const double *Cm = &cm[(size_t)i * 36];
-        int q = 0;
-        double fro = 0, asym = 0;
-        for (int a = 0; a < 6; ++a)
-            for (int b = 0; b < 6; ++b) {
-                if (b >= a) oc[(size_t)i * 21 + q++] = Cm[a * 6 + b];
-                fro += Cm[a * 6 + b] * Cm[a * 6 + b];
-                const double dlt = Cm[a * 6 + b] - Cm[b * 6 + a];
-                asym += dlt * dlt;
-            }
-        const double *Kt = &cs[(size_t)i * 9], *Dt = &cs[(size_t)(batch + i) * 9];
-        const int ui[6] = {0, 4, 8, 1, 5, 2};
-        for (int k = 0; k < 6; ++k) {
-            ok[(size_t)i * 6 + k] = Kt[ui[k]];
-            od[(size_t)i * 6 + k] = Dt[ui[k]];
-        }
-        chom_report R;
-        std::memset(&R, 0, sizeof(R));
-        R.status = CHOM_OK;
-        R.asym = fro > 0 ? std::sqrt(asym / fro) : 0.0;
-        R.omega_keep = keep[i];
-        for (int c = 0; c < 12; ++c) {
-            const ColState *cs_in, *cs_out;
-            int ridx;
-            if (c < 6) {
-                cs_in = &rve->mech.h_cols[(size_t)i * 6 + c];
-                cs_out = refined ? &rve->mech.h_cols_outer[(size_t)i * 6 + c] : cs_in;
-            } else {
-                const int pidx = (c < 9) ? i : batch + i;
-                ridx = (c < 9) ? c - 6 : c - 9;
-                cs_in = &rve->scal.h_cols[(size_t)pidx * 3 + ridx];
-                cs_out = refined ? &rve->scal.h_cols_outer[(size_t)pidx * 3 + ridx] : cs_in;
-            }
-            R.iters[c] = cs_in->iters;
-            R.resid[c] = cs_out->eref > 0 ? std::sqrt(cs_out->rz / cs_out->eref) : 0.0;
-            const bool conv = (cs_out->done == 1) || (cs_out->rz <= rve->opt.rtol * rve->opt.rtol * cs_out->eref);
-            if (!conv) R.status = CHOM_ENOCONV;
-        }
-        if (refined) {
-            R.refine_steps[0] = rve->mech.refine_steps[i];
-            R.refine_steps[1] = rve->scal.refine_steps[i];
-            R.refine_steps[2] = rve->scal.refine_steps[batch + i];
-        }
-        if (R.status != CHOM_OK) overall = CHOM_ENOCONV;
-        if (rep) rep[i] = R;
-    }
-    if (rve->opt.device_ptrs) {
-        CHOM_HIP(hipMemcpyAsync(C_hom, oc.data(), sizeof(double) * oc.size(), hipMemcpyHostToDevice, s));
-        CHOM_HIP(hipMemcpyAsync(K_hom, ok.data(), sizeof(double) * ok.size(), hipMemcpyHostToDevice, s));
-        CHOM_HIP(hipMemcpyAsync(D_hom, od.data(), sizeof(double) * od.size(), hipMemcpyHostToDevice, s));
-        CHOM_HIP(hipStreamSynchronize(s));
-    } else {
-        std::memcpy(C_hom, oc.data(), sizeof(double) * oc.size());
-        std::memcpy(K_hom, ok.data(), sizeof(double) * ok.size());
-        std::memcpy(D_hom, od.data(), sizeof(double) * od.size());
-    }
-    if (overall != CHOM_OK) set_error("chom_homogenise: some load case did not converge");
-    return overall;
 }
 
 }  // extern "C"

@@ -16,8 +16,6 @@
 
 namespace chom {
 
-constexpr int kMaxProblemsPerLaunch = 1 << 20;
-
 // Operator tile: TX x TY x TZ cells per workgroup; its DOF box is (2T+1)^3.
 // One thread per tet of the tile (192 threads).
 constexpr int TX = 4, TY = 4, TZ = 2;
@@ -25,10 +23,8 @@ constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1, BZ = 2 * TZ + 1;
 constexpr int BOXPTS = BX * BY * BZ;
 constexpr int TILE_TETS = 6 * TX * TY * TZ;
 
-// Load cases per operator workgroup: mechanics 2 of 6, scalar fields 3 of 3.
-template <int C, int R> struct OpGroup { static constexpr int RG = (C == 3) ? 2 : R; };
-
-// Per-RVE geometry, passed by value to kernels.
+// Per-RVE geometry.  Kernels read it from a device array, indexed by the
+// problem's `geo`, so one launch can mix RVEs of different sizes and BCs.
 struct Geo {
     int n;            // cells per side
     int bc;           // 0 Dirichlet, 1 periodic, 2 Neumann
@@ -45,17 +41,23 @@ struct Geo {
     const double *rows;     // per lattice point: int grad(phi) (3) and int phi (1)
     int nrow;               // projection rows per component: 0 (D), 1 (P), 4 (N)
     int tiles_x, tiles_y, tiles_z;
+    int ntiles;
+    int pad_;
 };
 
-// Per-problem descriptor (one parameter record x one physics).
+// Per-problem descriptor (one parameter record x one physics of one RVE).
 struct Prob {
     double mat64[2][5];   // [phase 0 matrix, 1 yarn][invariants]
     float mat32[2][5];
     long long voff;       // offset of this problem's vector segment (values)
-    long long doff;       // offset of this problem's per-point preconditioner data (points)
+    long long doff;       // offset of its per-point preconditioner data (points)
+    long long qoff;       // offset of its operator tile boxes (values)
+    int geo;              // index of its RVE geometry
+    int pad_;
 };
 
-template <typename T> struct Mat5 { T c[5]; };
+// First constraint row used by a BC: periodic uses only int(phi) (row 3).
+__host__ __device__ inline int row_first(int nrow) { return nrow == 1 ? 3 : 0; }
 
 // Kuhn tet type t: axis permutation (p0, p1, p2) in the fixed order.
 __host__ __device__ inline void kuhn_perm(int t, int &p0, int &p1) {
@@ -317,14 +319,12 @@ __device__ inline int tile_cands(int X, int T2, int ntiles, int m2, bool per, in
 }
 
 // Sum of the tile-box copies of lattice point (X, Y, Z) for load case w (C
-// values); tile boxes are [tile][group][box point][RG * C] with RG load cases
-// per group.
+// values).  Tile boxes are [tile][group][box point][rg * C], rg load cases per
+// group, R / rg groups.
 template <typename T, int C, int R>
-__device__ inline void gather_tiles_col(const Geo &G, const T *qt, int X, int Y, int Z, int w, double out[C]) {
-    constexpr int RG = OpGroup<C, R>::RG;
-    constexpr int NG = R / RG;
-    constexpr int RCg = RG * C;
-    const int grp = w / RG, rr = w - (w / RG) * RG;
+__device__ inline void gather_tiles_col(const Geo &G, const T *qt, int rg, int X, int Y, int Z, int w, double out[C]) {
+    const int ng = R / rg, rcg = rg * C;
+    const int grp = w / rg, rr = w - grp * rg;
     const bool per = (G.bc == 1);
     const int m2 = 2 * G.n;
     int tx[2], ty[2], tz[2], lx[2], ly[2], lz[2];
@@ -337,7 +337,7 @@ __device__ inline void gather_tiles_col(const Geo &G, const T *qt, int X, int Y,
         for (int b = 0; b < ny; ++b)
             for (int c = 0; c < nz; ++c) {
                 const long long tile = tx[a] + (long long)G.tiles_x * (ty[b] + (long long)G.tiles_y * tz[c]);
-                const long long off = ((tile * NG + grp) * BOXPTS + lx[a] + BX * (ly[b] + BY * lz[c])) * RCg + rr * C;
+                const long long off = ((tile * ng + grp) * BOXPTS + lx[a] + BX * (ly[b] + BY * lz[c])) * rcg + rr * C;
 #pragma unroll
                 for (int v = 0; v < C; ++v) out[v] += (double)qt[off + v];
             }

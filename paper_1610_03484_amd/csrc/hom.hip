@@ -9,11 +9,12 @@
 namespace chom {
 
 template <int C, int R>
-__global__ void average_kernel(Geo G, const Prob *probs, long long vpp, const double *x, double *partial) {
+__global__ void average_kernel(const Geo *geos, const Prob *probs, const double *x, double *partial) {
     constexpr int NC = (C == 3) ? 6 : 3;
     const int prob = blockIdx.y;
-    const Prob P = probs[prob];
-    const double *xp = x + (long long)prob * vpp;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    const double *xp = x + P.voff;
     const long long nt = 6LL * G.n * G.n * G.n;
     double acc[R * NC];
     for (int k = 0; k < R * NC; ++k) acc[k] = 0.0;
@@ -81,9 +82,10 @@ __global__ void average_kernel(Geo G, const Prob *probs, long long vpp, const do
 
 // out[prob][i][j] = (1/V) sum of partials: row i = stress/flux component, column j = load case.
 template <int C, int R>
-__global__ void average_finish_kernel(int nwg, const double *partial, double volume, double *out) {
+__global__ void average_finish_kernel(const Geo *geos, const Prob *probs, int nwg, const double *partial, double *out) {
     constexpr int NC = (C == 3) ? 6 : 3;
     const int prob = blockIdx.x;
+    const double volume = geos[probs[prob].geo].volume;
     const int lane = threadIdx.x;
     for (int k = 0; k < R * NC; ++k) {
         double s = 0.0;
@@ -97,14 +99,13 @@ __global__ void average_finish_kernel(int nwg, const double *partial, double vol
 }
 
 template <int C, int R>
-hipError_t launch_average(const Geo &G, const Prob *probs, int nprob, long long vpp,
-                          const double *x64, double *partial, int nwg, double *out, hipStream_t s) {
-    dim3 grid(nwg, nprob);
-    average_kernel<C, R><<<grid, 256, 0, s>>>(G, probs, vpp, x64, partial);
-    average_finish_kernel<C, R><<<nprob, FIN_BS, 0, s>>>(nwg, partial, G.volume, out);
+hipError_t launch_average(const Launch &L, const double *x64, double *partial, int nwg, double *out, hipStream_t s) {
+    dim3 grid(nwg, L.nprob);
+    average_kernel<C, R><<<grid, 256, 0, s>>>(L.geos, L.probs, x64, partial);
+    average_finish_kernel<C, R><<<L.nprob, FIN_BS, 0, s>>>(L.geos, L.probs, nwg, partial, out);
     return hipGetLastError();
 }
-template hipError_t launch_average<3, 6>(const Geo &, const Prob *, int, long long, const double *, double *, int, double *, hipStream_t);
-template hipError_t launch_average<1, 3>(const Geo &, const Prob *, int, long long, const double *, double *, int, double *, hipStream_t);
+template hipError_t launch_average<3, 6>(const Launch &, const double *, double *, int, double *, hipStream_t);
+template hipError_t launch_average<1, 3>(const Launch &, const double *, double *, int, double *, hipStream_t);
 
 }  // namespace chom

@@ -2,15 +2,20 @@
 // hierarchic space on the Kuhn lattice (K is the standard FE matrix of Sec. 2,
 // Eq. eq_RVE_disc_Eqs, and its scalar analogue, Eq. eq_RVE_disc_Eqs_field).
 //
-// One workgroup owns a tile of TX x TY x TZ cells (6 tets each).  It stages the
-// (2T+1)^3 DOF box of its tile from HBM into LDS with coalesced loads, applies
-// every tet of the tile for every load case (element data: fibre axis + phase,
-// 16/32 bytes; the stiffness is evaluated on the fly from five invariants),
-// accumulates the element results in a second LDS box with LDS atomics, and
-// stores the whole box, contiguous, to its slot of the tile-box output (no
-// global atomics, no zeroing pass); consumers sum the copies of points on
-// shared tile faces.  The element energies x_e . K_e x_e of all tets are
-// summed on the fly in FP64, giving p.Kp for CG without another sweep.
+// One workgroup owns a tile of TX x TY x TZ cells (6 tets each, one thread per
+// tet) and one group of RG load cases.  It stages the (2T+1)^3 DOF box of its
+// tile from HBM into LDS (all loads in flight before the first LDS store),
+// applies every tet of the tile (element data: fibre axis + phase, 16/32 bytes;
+// the stiffness is evaluated on the fly from five invariants), accumulates the
+// element results in an FP64 LDS box with LDS atomics (FP64 LDS atomic adds are
+// markedly faster than FP32 ones on gfx950), and stores the whole box,
+// contiguous, to its slot of the tile-box output: no global atomics, no zeroing
+// pass; consumers sum the copies of points on shared tile faces.  The element
+// energies x_e . K_e x_e are summed on the fly in FP64 (p.Kp for CG).
+//
+// Problems of different RVEs (sizes, BCs) share a launch: grid.x covers the
+// largest problem's tiles x groups; workgroups past a problem's tiles only
+// write zero partials.
 #include "common.h"
 #include "internal.h"
 
@@ -20,15 +25,10 @@ namespace chom {
 
 int operator_tiles(const Geo &G) { return G.tiles_x * G.tiles_y * G.tiles_z; }
 
-// Load cases are split into NG = R / RG groups; a workgroup handles one tile
-// and one group (grid.x = tiles * NG), with one thread per tet.  The LDS
-// accumulator is FP64 (LDS FP64 atomic adds are markedly faster than FP32 ones
-// on gfx950) and the per-point strides are padded by one element to spread
-// LDS banks.  Output layout: [prob][tile][group][box point][RG * C].
 template <typename T, int C, int R, int RG>
-__global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(Geo G, const Prob *probs, const T *__restrict__ x,
-                                                          T *__restrict__ y, double *partial_pq,
-                                                          const int *prob_active) {
+__global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const Prob *probs, int max_tiles,
+                                                          const T *__restrict__ x, T *__restrict__ y,
+                                                          double *partial_pq, const int *prob_active) {
     constexpr int NG = R / RG;
     constexpr int RC = R * C;
     constexpr int RCg = RG * C;
@@ -40,18 +40,17 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(Geo G, const Prob *pro
     using V4 = typename std::conditional<std::is_same<T, double>::value, double4, float4>::type;
     __shared__ T xs[BOXPTS * PS];
     __shared__ double ys[BOXPTS * PS];
-    __shared__ V4 se[TILE_TETS];
     __shared__ T sg[6][10];
     __shared__ double red[RG][NW];
     const int prob = blockIdx.y;
     const int tile = blockIdx.x / NG, grp = blockIdx.x - (blockIdx.x / NG) * NG;
-    const int ntiles = gridDim.x / NG;
     const int tt = threadIdx.x;
-    if (prob_active != nullptr && prob_active[prob] == 0) {
-        if (tt < RG) partial_pq[((long long)prob * R + grp * RG + tt) * ntiles + tile] = 0.0;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    if (tile >= G.ntiles || (prob_active != nullptr && prob_active[prob] == 0)) {
+        if (tt < RG) partial_pq[((long long)prob * R + grp * RG + tt) * max_tiles + tile] = 0.0;
         return;
     }
-    const Prob P = probs[prob];
     const int n = G.n, m2 = 2 * n;
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, tz = tile / (G.tiles_x * G.tiles_y);
     const int cx0 = tx * TX, cy0 = ty * TY, cz0 = tz * TZ;
@@ -59,8 +58,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(Geo G, const Prob *pro
     const int hx = min(X0 + 2 * TX, m2), hy = min(Y0 + 2 * TY, m2), hz = min(Z0 + 2 * TZ, m2);
     const T *xp = x + P.voff + grp * RCg;
 
-    // ---- stage the DOF box (this group's values), element data, geometry;
-    // all loads of a thread are issued before the LDS stores.
+    // ---- stage the DOF box (this group's values), element data, geometry
     T tmp[NST];
 #pragma unroll
     for (int k = 0; k < NST; ++k) {
@@ -148,13 +146,13 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(Geo G, const Prob *pro
     __syncthreads();
 
     // ---- write this group's tile box (contiguous, coalesced)
-    T *qt = y + (((long long)prob * ntiles + tile) * NG + grp) * NBOX;
+    T *qt = y + P.qoff + ((long long)tile * NG + grp) * NBOX;
     for (int i = tt; i < NBOX; i += TILE_TETS) {
         const int pt = i / RCg, v = i - pt * RCg;
         qt[i] = (T)ys[pt * PS + v];
     }
 
-    // ---- element-energy partial sums (layout [prob][load case][tile])
+    // ---- element-energy partial sums (layout [prob][load case][max_tiles])
     const int lane = tt & 63, wv = tt >> 6;
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
@@ -166,22 +164,38 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(Geo G, const Prob *pro
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) s += red[tt][w];
-        partial_pq[((long long)prob * R + grp * RG + tt) * ntiles + tile] = s;
+        partial_pq[((long long)prob * R + grp * RG + tt) * max_tiles + tile] = s;
     }
 }
 
-template <typename T, int C, int R>
-hipError_t launch_operator(const Geo &G, const Prob *probs, int nprob, const T *x, T *y,
-                           double *partial_pq, const int *prob_active, hipStream_t s) {
-    constexpr int RG = OpGroup<C, R>::RG;
-    dim3 grid(operator_tiles(G) * (R / RG), nprob);
-    op_p2_kernel<T, C, R, RG><<<grid, TILE_TETS, 0, s>>>(G, probs, x, y, partial_pq, prob_active);
+template <typename T, int C, int R, int RG>
+static hipError_t launch_rg(const Geo *geos, const Prob *probs, int nprob, int max_tiles, const T *x, T *y,
+                            double *partial_pq, const int *prob_active, hipStream_t s) {
+    dim3 grid(max_tiles * (R / RG), nprob);
+    op_p2_kernel<T, C, R, RG><<<grid, TILE_TETS, 0, s>>>(geos, probs, max_tiles, x, y, partial_pq, prob_active);
     return hipGetLastError();
 }
 
-template hipError_t launch_operator<double, 3, 6>(const Geo &, const Prob *, int, const double *, double *, double *, const int *, hipStream_t);
-template hipError_t launch_operator<float, 3, 6>(const Geo &, const Prob *, int, const float *, float *, double *, const int *, hipStream_t);
-template hipError_t launch_operator<double, 1, 3>(const Geo &, const Prob *, int, const double *, double *, double *, const int *, hipStream_t);
-template hipError_t launch_operator<float, 1, 3>(const Geo &, const Prob *, int, const float *, float *, double *, const int *, hipStream_t);
+template <typename T, int C, int R>
+hipError_t launch_operator(const Geo *geos, const Prob *probs, int nprob, int max_tiles, int rg, const T *x, T *y,
+                           double *partial_pq, const int *prob_active, hipStream_t s) {
+    if constexpr (C == 3) {
+        switch (rg) {
+            case 1: return launch_rg<T, C, R, 1>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
+            case 3: return launch_rg<T, C, R, 3>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
+            default: return launch_rg<T, C, R, 2>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
+        }
+    } else {
+        switch (rg) {
+            case 1: return launch_rg<T, C, R, 1>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
+            default: return launch_rg<T, C, R, 3>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
+        }
+    }
+}
+
+template hipError_t launch_operator<double, 3, 6>(const Geo *, const Prob *, int, int, int, const double *, double *, double *, const int *, hipStream_t);
+template hipError_t launch_operator<float, 3, 6>(const Geo *, const Prob *, int, int, int, const float *, float *, double *, const int *, hipStream_t);
+template hipError_t launch_operator<double, 1, 3>(const Geo *, const Prob *, int, int, int, const double *, double *, double *, const int *, hipStream_t);
+template hipError_t launch_operator<float, 1, 3>(const Geo *, const Prob *, int, int, int, const float *, float *, double *, const int *, hipStream_t);
 
 }  // namespace chom

@@ -159,10 +159,11 @@ __device__ inline void acoustic(const double w[3], const double a[3], const doub
 }
 
 template <int C>
-__global__ void diag_kernel(Geo G, const Prob *probs, double *diag) {
+__global__ void diag_kernel(const Geo *geos, const Prob *probs, double *diag) {
     constexpr int MS = (C == 3) ? 6 : 1;
-    const Prob P = probs[blockIdx.y];
-    double *D = diag + (long long)blockIdx.y * G.npts * MS;
+    const Prob &P = probs[blockIdx.y];
+    const Geo &G = geos[P.geo];
+    double *D = diag + P.doff * MS;
     const long long nt = 6LL * G.n * G.n * G.n;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
          e += (long long)gridDim.x * blockDim.x) {
@@ -221,9 +222,8 @@ __global__ void diag_kernel(Geo G, const Prob *probs, double *diag) {
 }
 
 template <int C>
-__global__ void invert_diag_kernel(Geo G, int nprob, const double *diag, double *minv64, float *minv32) {
+__global__ void invert_diag_kernel(long long total, const double *diag, double *minv64, float *minv32) {
     constexpr int MS = (C == 3) ? 6 : 1;
-    const long long total = (long long)nprob * G.npts;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
          i += (long long)gridDim.x * blockDim.x) {
         const double *d = diag + i * MS;
@@ -253,19 +253,18 @@ __global__ void invert_diag_kernel(Geo G, int nprob, const double *diag, double 
 }
 
 template <int C>
-hipError_t launch_precond(const Geo &G, const Prob *probs, int nprob, double *diag,
-                          double *minv64, float *minv32, hipStream_t s) {
+hipError_t launch_precond(const Launch &L, long long total_pts, double *diag, double *minv64, float *minv32,
+                          hipStream_t s) {
     constexpr int MS = (C == 3) ? 6 : 1;
-    hipError_t err = hipMemsetAsync(diag, 0, sizeof(double) * MS * G.npts * nprob, s);
+    hipError_t err = hipMemsetAsync(diag, 0, sizeof(double) * MS * total_pts, s);
     if (err != hipSuccess) return err;
-    const long long nt = 6LL * G.n * G.n * G.n;
-    dim3 grid(grid_for(nt, 256, 2048), nprob);
-    diag_kernel<C><<<grid, 256, 0, s>>>(G, probs, diag);
-    invert_diag_kernel<C><<<grid_for(G.npts * nprob, 256), 256, 0, s>>>(G, nprob, diag, minv64, minv32);
+    dim3 grid(grid_for(L.max_tets, 256, 2048), L.nprob);
+    diag_kernel<C><<<grid, 256, 0, s>>>(L.geos, L.probs, diag);
+    invert_diag_kernel<C><<<grid_for(total_pts, 256), 256, 0, s>>>(total_pts, diag, minv64, minv32);
     return hipGetLastError();
 }
-template hipError_t launch_precond<3>(const Geo &, const Prob *, int, double *, double *, float *, hipStream_t);
-template hipError_t launch_precond<1>(const Geo &, const Prob *, int, double *, double *, float *, hipStream_t);
+template hipError_t launch_precond<3>(const Launch &, long long, double *, double *, float *, hipStream_t);
+template hipError_t launch_precond<1>(const Launch &, long long, double *, double *, float *, hipStream_t);
 
 // ------------------------------------------------------------------ Gram matrices
 // G[(i,a),(j,b)] = sum_pt row_a(pt) row_b(pt) Minv_pt[i][j] for the rows of the
@@ -274,8 +273,12 @@ template hipError_t launch_precond<1>(const Geo &, const Prob *, int, double *, 
 constexpr int GRAM_CHUNK = 256;
 
 template <int C>
-__global__ void gram_partial_kernel(Geo G, const double *minv64, const float *minv32, double *partial) {
+__global__ void gram_partial_kernel(const Geo *geos, const Prob *probs, const double *minv64, const float *minv32,
+                                    double *partial) {
     constexpr int MS = (C == 3) ? 6 : 1;
+    constexpr int NUMAX = 60;
+    const Prob &P = probs[blockIdx.y];
+    const Geo &G = geos[P.geo];
     const int nrow = G.nrow;
     const int rfirst = (nrow == 1) ? 3 : 0;  // periodic uses only int phi
     const int nRs = nrow * (nrow + 1) / 2;
@@ -284,8 +287,8 @@ __global__ void gram_partial_kernel(Geo G, const double *minv64, const float *mi
     __shared__ double sm32[GRAM_CHUNK][MS];
     __shared__ double sr[GRAM_CHUNK][4];
     const int prob = blockIdx.y;
-    const double *M64 = minv64 + (long long)prob * G.npts * MS;
-    const float *M32 = minv32 + (long long)prob * G.npts * MS;
+    const double *M64 = minv64 + P.doff * MS;
+    const float *M32 = minv32 + P.doff * MS;
     // each thread owns unique sum u (two precisions)
     const int u = threadIdx.x;
     int mi = 0, ra = 0, rb = 0;
@@ -326,19 +329,23 @@ __global__ void gram_partial_kernel(Geo G, const double *minv64, const float *mi
         }
     }
     if (u < nU) {
-        double *out = partial + ((long long)prob * gridDim.x + blockIdx.x) * 2 * nU;
+        double *out = partial + ((long long)prob * gridDim.x + blockIdx.x) * 2 * NUMAX;
         out[u] = acc64;
-        out[nU + u] = acc32;
+        out[NUMAX + u] = acc32;
     }
 }
 
 // Expand the unique sums of one problem, invert (Gauss-Jordan, pivoted), store.
 template <int C>
-__global__ void gram_finish_kernel(int nprob, int nrow, int nwg, const double *partial,
+__global__ void gram_finish_kernel(const Geo *geos, const Prob *probs, int nprob, int nwg, const double *partial,
                                    double *ginv64, double *ginv32, int *bad) {
     constexpr int MS = (C == 3) ? 6 : 1;
+    constexpr int NUMAX = 60;
+    constexpr int SMAX = C * 4;
     const int prob = blockIdx.x * blockDim.x + threadIdx.x;
-    if (prob >= nprob || nrow == 0) return;
+    if (prob >= nprob) return;
+    const int nrow = geos[probs[prob].geo].nrow;
+    if (nrow == 0) return;
     const int nRs = nrow * (nrow + 1) / 2;
     const int nU = MS * nRs;
     const int S = C * nrow;
@@ -360,7 +367,7 @@ __global__ void gram_finish_kernel(int nprob, int nrow, int nwg, const double *p
                 ri += rb - ra;
                 const int u = mi * nRs + ri;
                 double s = 0.0;
-                for (int w = 0; w < nwg; ++w) s += partial[((long long)prob * nwg + w) * 2 * nU + which * nU + u];
+                for (int w = 0; w < nwg; ++w) s += partial[((long long)prob * nwg + w) * 2 * NUMAX + which * NUMAX + u];
                 A[I][J] = s;
                 A[I][S + J] = (I == J) ? 1.0 : 0.0;
             }
@@ -382,24 +389,24 @@ __global__ void gram_finish_kernel(int nprob, int nrow, int nwg, const double *p
             }
         }
         if (!ok) atomicAdd(bad, 1);
-        double *out = (which == 0 ? ginv64 : ginv32) + (long long)prob * S * S;
+        double *out = (which == 0 ? ginv64 : ginv32) + (long long)prob * SMAX * SMAX;
         for (int I = 0; I < S; ++I)
             for (int J = 0; J < S; ++J) out[I * S + J] = ok ? A[I][S + J] : 0.0;
     }
 }
 
 template <int C>
-hipError_t launch_gram(const Geo &G, int nprob, const double *minv64, const float *minv32,
-                       double *gram_partial, int nwg, double *ginv64, double *ginv32, int *bad,
-                       hipStream_t s) {
-    if (G.nrow == 0) return hipSuccess;
-    dim3 grid(nwg, nprob);
-    gram_partial_kernel<C><<<grid, GRAM_CHUNK, 0, s>>>(G, minv64, minv32, gram_partial);
-    gram_finish_kernel<C><<<(nprob + 63) / 64, 64, 0, s>>>(nprob, G.nrow, nwg, gram_partial, ginv64, ginv32, bad);
+hipError_t launch_gram(const Launch &L, const double *minv64, const float *minv32, double *gram_partial, int nwg,
+                       double *ginv64, double *ginv32, int *bad, hipStream_t s) {
+    if (L.nr == 0) return hipSuccess;
+    dim3 grid(nwg, L.nprob);
+    gram_partial_kernel<C><<<grid, GRAM_CHUNK, 0, s>>>(L.geos, L.probs, minv64, minv32, gram_partial);
+    gram_finish_kernel<C><<<(L.nprob + 63) / 64, 64, 0, s>>>(L.geos, L.probs, L.nprob, nwg, gram_partial, ginv64,
+                                                             ginv32, bad);
     return hipGetLastError();
 }
-template hipError_t launch_gram<3>(const Geo &, int, const double *, const float *, double *, int, double *, double *, int *, hipStream_t);
-template hipError_t launch_gram<1>(const Geo &, int, const double *, const float *, double *, int, double *, double *, int *, hipStream_t);
+template hipError_t launch_gram<3>(const Launch &, const double *, const float *, double *, int, double *, double *, int *, hipStream_t);
+template hipError_t launch_gram<1>(const Launch &, const double *, const float *, double *, int, double *, double *, int *, hipStream_t);
 
 // ------------------------------------------------------------------ load vectors
 // b_i = - int grad(phi_i) : C eps_k dV for the unit strains (or - int grad(phi_i) . k e_k
@@ -407,10 +414,11 @@ template hipError_t launch_gram<1>(const Geo &, int, const double *, const float
 // field; also the energy of the linear field eps_k : C_e eps_k |e| (reference
 // scale of the stopping test).
 template <int C, int R>
-__global__ void rhs_kernel(Geo G, const Prob *probs, long long vpp, double *b, ColState *cols) {
+__global__ void rhs_kernel(const Geo *geos, const Prob *probs, double *b, ColState *cols) {
     const int prob = blockIdx.y;
-    const Prob P = probs[prob];
-    double *bp = b + (long long)prob * vpp;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    double *bp = b + P.voff;
     const long long nt = 6LL * G.n * G.n * G.n;
     double eref[R];
     for (int k = 0; k < R; ++k) eref[k] = 0.0;
@@ -477,16 +485,14 @@ __global__ void rhs_kernel(Geo G, const Prob *probs, long long vpp, double *b, C
 }
 
 template <int C, int R>
-hipError_t launch_rhs(const Geo &G, const Prob *probs, int nprob, long long vpp, double *b,
-                      ColState *cols, hipStream_t s) {
-    hipError_t err = hipMemsetAsync(b, 0, sizeof(double) * vpp * nprob, s);
+hipError_t launch_rhs(const Launch &L, long long total_vals, double *b, ColState *cols, hipStream_t s) {
+    hipError_t err = hipMemsetAsync(b, 0, sizeof(double) * total_vals, s);
     if (err != hipSuccess) return err;
-    const long long nt = 6LL * G.n * G.n * G.n;
-    dim3 grid(grid_for(nt, 256, 2048), nprob);
-    rhs_kernel<C, R><<<grid, 256, 0, s>>>(G, probs, vpp, b, cols);
+    dim3 grid(grid_for(L.max_tets, 256, 2048), L.nprob);
+    rhs_kernel<C, R><<<grid, 256, 0, s>>>(L.geos, L.probs, b, cols);
     return hipGetLastError();
 }
-template hipError_t launch_rhs<3, 6>(const Geo &, const Prob *, int, long long, double *, ColState *, hipStream_t);
-template hipError_t launch_rhs<1, 3>(const Geo &, const Prob *, int, long long, double *, ColState *, hipStream_t);
+template hipError_t launch_rhs<3, 6>(const Launch &, long long, double *, ColState *, hipStream_t);
+template hipError_t launch_rhs<1, 3>(const Launch &, long long, double *, ColState *, hipStream_t);
 
 }  // namespace chom

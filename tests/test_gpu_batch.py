@@ -1,0 +1,103 @@
+"""GPU: the batched path (items on RVEs of different sizes and BCs in one launch) vs the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import chom_inputs as ci
+from oracle import fem as ofem, mesh as omesh
+
+from gpu_util import banner, rel, require_gpu, upper21, upper6
+
+pytestmark = pytest.mark.gpu
+
+BC_ID = {"dirichlet": ofem.BC_DIRICHLET, "periodic": ofem.BC_PERIODIC, "neumann": ofem.BC_NEUMANN}
+
+
+def _items():
+    # (n, bc) per item; handles repeat for equal (n, bc)
+    return [(3, "dirichlet"), (4, "periodic"), (5, "neumann"), (4, "periodic"), (5, "dirichlet"), (3, "neumann")]
+
+
+def _make(precision, **opts):
+    from paper_1610_03484_amd import RVE, Batch, generate_plain_weave
+    handles = {}
+    rves = []
+    for n, bc in _items():
+        if (n, bc) not in handles:
+            mesh = generate_plain_weave(n, device="cuda")
+            handles[(n, bc)] = RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision=precision, **opts)
+        rves.append(handles[(n, bc)])
+    return Batch(rves), handles
+
+
+def _oracle(items, params):
+    out = []
+    for (n, bc), p in zip(items, params):
+        c, t, ph, ax = omesh.plain_weave(n)
+        out.append(ofem.homogenise(c, t, ph, ax, 2, BC_ID[bc], ci.BASE_MATERIALS, p))
+    return out
+
+
+@pytest.fixture(scope="module")
+def params_and_oracle():
+    params = ci.draw_params(21, len(_items()))
+    return params, _oracle(_items(), params)
+
+
+def _check(C, K, D, refs, tol):
+    worst = 0.0
+    for i, ref in enumerate(refs):
+        e = max(rel(C[i], upper21(ref["C"])), rel(K[i], upper6(ref["K"])), rel(D[i], upper6(ref["D"])))
+        worst = max(worst, e)
+    return worst
+
+
+def test_batch_mixed_sizes_and_bcs_fp64(params_and_oracle):
+    require_gpu()
+    params, refs = params_and_oracle
+    banner("batch fp64: n in {3,4,5}, D/P/N mixed, 6 items")
+    batch, _ = _make("fp64")
+    C, K, D, rep = batch.homogenise(params)
+    worst = _check(C, K, D, refs, 1e-9)
+    banner(f"  worst rel err {worst:.2e}; iters item0 {rep[0]['iters']}")
+    assert all(r["status"] == 0 for r in rep)
+    assert worst < 1e-9
+
+
+def test_batch_mixed_sizes_and_bcs_fp32_refined(params_and_oracle):
+    require_gpu()
+    params, refs = params_and_oracle
+    banner("batch fp32-refined: mixed sizes and BCs")
+    batch, _ = _make("fp32_refined", rtol=1e-10)
+    C, K, D, rep = batch.homogenise(params)
+    worst = _check(C, K, D, refs, 1e-6)
+    banner(f"  worst rel err {worst:.2e}; refine item0 {rep[0]['refine_steps']}")
+    assert all(r["status"] == 0 for r in rep)
+    assert worst < 1e-6
+
+
+def test_batch_matches_single_rve_calls(params_and_oracle):
+    require_gpu()
+    params, _ = params_and_oracle
+    batch, handles = _make("fp64")
+    C, K, D, _ = batch.homogenise(params)
+    for i, key in enumerate(_items()):
+        Ci, Ki, Di, _ = handles[key].homogenise(params[i:i + 1])
+        assert rel(C[i], Ci[0]) < 1e-11 and rel(K[i], Ki[0]) < 1e-11 and rel(D[i], Di[0]) < 1e-11
+
+
+def test_autotuned_batch_gives_same_results(params_and_oracle):
+    require_gpu()
+    params, refs = params_and_oracle
+    os.environ["CHOM_AUTOTUNE"] = "1"
+    try:
+        batch, _ = _make("fp64")
+        C, K, D, rep = batch.homogenise(params)
+        cfg = batch.launch_config()
+    finally:
+        del os.environ["CHOM_AUTOTUNE"]
+    banner(f"autotuned launch config {cfg}")
+    assert cfg["rg_mech"] in (1, 2, 3) and cfg["rg_scal"] in (1, 3)
+    assert cfg["nwg_mech"] in (128, 256, 512, 1024)
+    assert _check(C, K, D, refs, 1e-9) < 1e-9
