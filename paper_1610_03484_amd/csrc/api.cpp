@@ -176,7 +176,7 @@ template <int C, int R> struct ClassWS {
     DevBuf<float> minv32;
     DevBuf<ColState> cols, cols_outer;
     DevBuf<int> active, active_outer, bad;
-    DevBuf<double> partial, avg_out;
+    DevBuf<double> partial, avg_out, sums;
     std::vector<ColState> h_cols, h_cols_outer;
     std::vector<int> h_active;
     std::vector<int> refine_steps;
@@ -336,12 +336,14 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     part = std::max(part, (size_t)nprob * L.nwg * R * C * 4 + (size_t)nprob * R * C * 4);
     CHOM_HIP(W.partial.ensure(part));
     CHOM_HIP(W.avg_out.ensure((size_t)nprob * R * NC));
+    CHOM_HIP(W.sums.ensure((size_t)nprob * R * (2 + C * 4)));
     W.h_cols.resize((size_t)R * nprob);
     W.h_cols_outer.resize((size_t)R * nprob);
     W.h_active.resize(nprob);
     W.refine_steps.assign(nprob, 0);
     L.geos = B->geos.p;
     L.probs = W.probs.p;
+    L.sums = W.sums.p;
     const void *after[4] = {W.xd.p, W.xf.p, W.partial.p, W.probs.p};
     if (std::memcmp(before, after, sizeof(before)) != 0 || old.nprob != L.nprob || old.nwg != L.nwg ||
         old.max_tiles != L.max_tiles || old.nr != L.nr || old.rg != L.rg)

@@ -14,9 +14,11 @@
 // forces do not accumulate in r and r.z stays accurate.  r.z, its pieces and
 // p.Kp are accumulated in FP64 whatever the vector precision.
 //
+// Vectors are load-case major: [problem][load case][point][component].
 // Vector kernels: a workgroup is R waves; wave w handles load case w of 64
-// consecutive lattice points at a time (grid-stride over the problem's point
-// blocks) and reduces its own column, so partial sums need no block barrier.
+// consecutive lattice points at a time (contiguous accesses; grid-stride over
+// the problem's point blocks) and reduces its own column, so partial sums
+// need no block barrier.
 // Partial layout (k-major): partial[((prob * R + w) * REC + k) * nwg + block],
 // REC = 2 + C * NR with NR the largest row count of the launch; record
 // [r.z0, r.r, C z0 (C x NR, entry c * NR + a)].
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const 
         for (int k = 0; k < MS; ++k) Mi[k] = Mp[pt * MS + k];
         double row[4];
         load_rows<NR>(G, pt, row);
-        const long long o = P.voff + (pt * R + w) * C;
+        const long long o = P.voff + (w * G.npts + pt) * C;
         T rv[C], zv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) rv[c] = b[o + c];
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
     for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const long long pt = blk * 64 + lane;
         if (pt >= G.npts) continue;
-        const long long o = P.voff + (pt * R + w) * C;
+        const long long o = P.voff + (w * G.npts + pt) * C;
         T zv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) zv[c] = z[o + c];
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
         for (int k = 0; k < MS; ++k) Mi[k] = Mp[pt * MS + k];
         double row[4];
         load_rows<NR>(G, pt, row);
-        const long long o = P.voff + (pt * R + w) * C;
+        const long long o = P.voff + (w * G.npts + pt) * C;
         T rv[C], zv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(64 * R) void proj_resid_kernel(const Geo *geos, con
         for (int k = 0; k < MS; ++k) Mi[k] = Mp[pt * MS + k];
         double row[4];
         load_rows<NR>(G, pt, row);
-        const long long o = P.voff + (pt * R + w) * C;
+        const long long o = P.voff + (w * G.npts + pt) * C;
         double rv[C], zv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -296,16 +298,30 @@ __device__ inline void reduce_kmajor(const double *part, int K, int nparts, doub
     }
 }
 
-// alpha = r.z / p.Kp per column (partials from the operator: [prob][R][tiles]).
+// Wide reduction: one 64-lane workgroup per (entry k, problem) sums
+// part[prob][k][0..nparts) into sums[prob][k]; all loads of a lane are
+// independent, so the reduction costs a few memory latencies whatever K is.
+__global__ void reduce_parts_kernel(const double *part, int K, int nparts, double *sums) {
+    const int k = blockIdx.x, prob = blockIdx.y, lane = threadIdx.x;
+    const double *src = part + ((long long)prob * K + k) * nparts;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = lane;
+    for (; i + 7 * 64 < nparts; i += 8 * 64) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += src[i + u * 64];
+    }
+    for (; i < nparts; i += 64) s[0] += src[i];
+    const double t = wave_sum(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
+    if (lane == 0) sums[(long long)prob * K + k] = t;
+}
+
+// alpha = r.z / p.Kp per column (sums: [prob][R] reduced from the operator's partials).
 template <int R>
-__global__ void finish_alpha_kernel(const double *partial_pq, int nparts, ColState *cols) {
+__global__ void finish_alpha_kernel(const double *pq_sums, ColState *cols) {
     const int prob = blockIdx.x;
-    __shared__ double pq[R];
-    reduce_kmajor(partial_pq + (long long)prob * R * nparts, R, nparts, pq);
-    __syncthreads();
     if (threadIdx.x < R) {
         ColState &cs = cols[prob * R + threadIdx.x];
-        const double v = pq[threadIdx.x];
+        const double v = pq_sums[(long long)prob * R + threadIdx.x];
         cs.pq = v;
         if (cs.done) {
             cs.alpha = 0.0;
@@ -318,9 +334,10 @@ __global__ void finish_alpha_kernel(const double *partial_pq, int nparts, ColSta
     }
 }
 
-// rz = r.z0 - c^T (C M^-1 C^T)^-1 c, projection coefficients y, beta, convergence.
+// rz = r.z0 - c^T (C M^-1 C^T)^-1 c, projection coefficients y, beta, convergence
+// (sums: [prob][R][REC] from reduce_parts_kernel).
 template <int C, int R>
-__global__ void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, const double *partial, int nparts,
+__global__ void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, const double *sums_all,
                                    const double *ginv, double *ycoef, ColState *cols, int *prob_active,
                                    int first, double rtol2, int use_init, const ColState *mask) {
     constexpr int SMAX = C * 4;
@@ -328,10 +345,11 @@ __global__ void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, c
     const int nrow = geos[probs[prob].geo].nrow;
     const int REC = 2 + C * NR;
     const int S = C * nrow;
-    __shared__ double sums[R * (2 + SMAX)];
-    reduce_kmajor(partial + (long long)prob * R * REC * nparts, R * REC, nparts, sums);
-    __syncthreads();
+    const double *sums = sums_all + (long long)prob * R * REC;
     const int lane = threadIdx.x;
+    __shared__ double sG[SMAX * SMAX];
+    for (int k = lane; k < S * S; k += blockDim.x) sG[k] = ginv[(long long)prob * SMAX * SMAX + k];
+    __syncthreads();
     if (lane < R) {
         ColState &cs = cols[prob * R + lane];
         const double *rec = &sums[lane * REC];
@@ -340,7 +358,7 @@ __global__ void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, c
             double c[SMAX];
             for (int i = 0; i < C; ++i)
                 for (int a = 0; a < nrow; ++a) c[i * nrow + a] = rec[2 + i * NR + a];
-            const double *Gi = ginv + (long long)prob * SMAX * SMAX;
+            const double *Gi = sG;
             double *yv = ycoef + ((long long)prob * R + lane) * C * NR;
             for (int k = 0; k < C * NR; ++k) yv[k] = 0.0;
             double cy = 0.0;
@@ -425,7 +443,8 @@ hipError_t launch_proj_resid(const Launch &L, double *r64, float *r32, const dou
 
 template <int C, int R>
 hipError_t launch_finish_alpha(const Launch &L, const double *partial_pq, ColState *cols, hipStream_t s) {
-    finish_alpha_kernel<R><<<L.nprob, 256, 0, s>>>(partial_pq, L.max_tiles, cols);
+    reduce_parts_kernel<<<dim3(R, L.nprob), 64, 0, s>>>(partial_pq, R, L.max_tiles, L.sums);
+    finish_alpha_kernel<R><<<L.nprob, 64, 0, s>>>(L.sums, cols);
     return hipGetLastError();
 }
 
@@ -433,8 +452,11 @@ template <int C, int R>
 hipError_t launch_finish_beta(const Launch &L, const double *partial, const double *ginv, double *ycoef,
                               ColState *cols, int *prob_active, int first, double rtol2, int use_init,
                               const ColState *mask, hipStream_t s) {
-    finish_beta_kernel<C, R><<<L.nprob, 256, 0, s>>>(L.geos, L.probs, L.nr, partial, L.nwg, ginv, ycoef, cols,
-                                                     prob_active, first, rtol2, use_init, mask);
+    const int REC = 2 + C * L.nr;
+    double *sums = L.sums;
+    reduce_parts_kernel<<<dim3(R * REC, L.nprob), 64, 0, s>>>(partial, R * REC, L.nwg, sums);
+    finish_beta_kernel<C, R><<<L.nprob, 64, 0, s>>>(L.geos, L.probs, L.nr, sums, ginv, ycoef, cols, prob_active,
+                                                    first, rtol2, use_init, mask);
     return hipGetLastError();
 }
 
@@ -455,11 +477,11 @@ __global__ void residual64_kernel(const Geo *geos, const Prob *probs, int rg, co
         for (int v = 0; v < RC; ++v) qv[v] = 0.0;
         if (qt != nullptr && !dirichlet_boundary(G, X, Y, Z))
             for (int w = 0; w < R; ++w) gather_tiles_col<double, C, R>(G, qt, rg, X, Y, Z, w, qv + w * C);
-        const long long o = P.voff + pt * RC;
         for (int v = 0; v < RC; ++v) {
-            const double val = b[o + v] - qv[v];
-            r64[o + v] = val;
-            if (r32) r32[o + v] = (float)val;
+            const long long o = P.voff + ((v / C) * G.npts + pt) * C + v % C;
+            const double val = b[o] - qv[v];
+            r64[o] = val;
+            if (r32) r32[o] = (float)val;
         }
     }
 }
@@ -501,7 +523,7 @@ __global__ void cx_partial_kernel(const Geo *geos, const Prob *probs, const doub
     for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const long long pt = blk * 64 + lane;
         if (pt >= G.npts) continue;
-        const long long o = P.voff + (pt * R + w) * C;
+        const long long o = P.voff + (w * G.npts + pt) * C;
         for (int a = 0; a < nr; ++a) {
             const double rw = G.rows[4 * pt + rf + a];
             for (int c = 0; c < C; ++c) acc[c * 4 + a] += rw * x[o + c];
@@ -557,7 +579,7 @@ __global__ void cx_correct_kernel(const Geo *geos, const Prob *probs, double *x,
             for (int a = 0; a < nr; ++a) ct[c] += G.rows[4 * pt + rf + a] * yv[c * 4 + a];
         }
         minv_apply<double, C>(Mi, ct, corr);
-        const long long o = P.voff + (pt * R + w) * C;
+        const long long o = P.voff + (w * G.npts + pt) * C;
         for (int c = 0; c < C; ++c) x[o + c] -= corr[c];
     }
 }

@@ -47,7 +47,7 @@ __global__ void average_kernel(const Geo *geos, const Prob *probs, const double 
             double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // int grad(u~) dV
             for (int k = 0; k < 10; ++k)
                 for (int c = 0; c < C; ++c) {
-                    const double u = xp[(idx[k] * R + r) * C + c];
+                    const double u = xp[(r * G.npts + idx[k]) * C + c];
                     for (int d = 0; d < 3; ++d) H[c][d] += u * w[k][d];
                 }
             if constexpr (C == 3) {

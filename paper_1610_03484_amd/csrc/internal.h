@@ -32,6 +32,7 @@ struct Launch {
     int nr;               // largest constraint row count among the problems (0, 1, 4)
     int rg;               // load cases per operator workgroup
     long long max_tets;   // largest tet count among the problems
+    double *sums;         // reduced partial sums, [nprob][R * (2 + C * 4)]
 };
 
 // ------------------------------------------------------------------ launchers

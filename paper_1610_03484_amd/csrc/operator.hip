@@ -30,7 +30,6 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
                                                           const T *__restrict__ x, T *__restrict__ y,
                                                           double *partial_pq, const int *prob_active) {
     constexpr int NG = R / RG;
-    constexpr int RC = R * C;
     constexpr int RCg = RG * C;
     constexpr int PS = RCg + 1;
     constexpr int NBOX = BOXPTS * RCg;
@@ -56,7 +55,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     const int cx0 = tx * TX, cy0 = ty * TY, cz0 = tz * TZ;
     const int X0 = 2 * cx0, Y0 = 2 * cy0, Z0 = 2 * cz0;
     const int hx = min(X0 + 2 * TX, m2), hy = min(Y0 + 2 * TY, m2), hz = min(Z0 + 2 * TZ, m2);
-    const T *xp = x + P.voff + grp * RCg;
+    const T *xp = x + P.voff;   // vectors are [load case][point][component]
 
     // ---- stage the DOF box (this group's values), element data, geometry
     T tmp[NST];
@@ -64,11 +63,13 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     for (int k = 0; k < NST; ++k) {
         const int i = tt + TILE_TETS * k;
         T val = T(0);
-        if (i < NBOX) {
-            const int pt = i / RCg, v = i - pt * RCg;
+        if (i < NBOX) {   // i = (rr * BOXPTS + pt) * C + c: consecutive lanes read contiguous memory
+            const int rr = i / (BOXPTS * C), rem = i - rr * (BOXPTS * C);
+            const int pt = rem / C, c = rem - (rem / C) * C;
             const int bx = pt % BX, by = (pt / BX) % BY, bz = pt / (BX * BY);
             const int X = X0 + bx, Y = Y0 + by, Z = Z0 + bz;
-            if (X <= hx && Y <= hy && Z <= hz) val = xp[lat_index(G, X, Y, Z) * RC + v];
+            if (X <= hx && Y <= hy && Z <= hz)
+                val = xp[((long long)(grp * RG + rr) * G.npts + lat_index(G, X, Y, Z)) * C + c];
         }
         tmp[k] = val;
     }
@@ -85,8 +86,9 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     for (int k = 0; k < NST; ++k) {
         const int i = tt + TILE_TETS * k;
         if (i < NBOX) {
-            const int pt = i / RCg, v = i - pt * RCg;
-            xs[pt * PS + v] = tmp[k];
+            const int rr = i / (BOXPTS * C), rem = i - rr * (BOXPTS * C);
+            const int pt = rem / C, c = rem - (rem / C) * C;
+            xs[pt * PS + rr * C + c] = tmp[k];
         }
     }
     for (int i = tt; i < BOXPTS * PS; i += TILE_TETS) ys[i] = 0.0;

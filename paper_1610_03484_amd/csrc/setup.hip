@@ -464,7 +464,7 @@ __global__ void rhs_kernel(const Geo *geos, const Prob *probs, double *b, ColSta
                 const long long idx = lat_index(G, Pt[kk][0], Pt[kk][1], Pt[kk][2]);
                 for (int c = 0; c < C; ++c) {
                     const double v = -(sig[c][0] * w[0] + sig[c][1] * w[1] + sig[c][2] * w[2]);
-                    atomicAdd(&bp[(idx * R + k) * C + c], v);
+                    atomicAdd(&bp[(k * G.npts + idx) * C + c], v);
                 }
             }
         }
