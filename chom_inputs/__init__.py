@@ -15,4 +15,5 @@ from .params import (  # noqa: F401
     draw_params,
     draw_factors_only,
     batch_sizes_c2,
+    uniform_block,
 )

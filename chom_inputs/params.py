@@ -96,3 +96,14 @@ def batch_sizes_c2(seed: int, n_rves: int, choices=(8, 12, 16, 20, 24)) -> np.nd
     u = uniform01(seed, np.arange(n_rves, dtype=np.uint64), np.uint64(63))
     idx = np.minimum((u * len(choices)).astype(np.int64), len(choices) - 1)
     return np.asarray(choices, dtype=np.int64)[idx]
+
+
+def uniform_block(seed: int, stream: int, count: int) -> np.ndarray:
+    """count doubles in [0, 1) of one stream: element e uses counter (seed, item=e, slot=stream).
+
+    stream must be below 64 so that streams never share a counter.  Used for
+    synthetic network weights and synthetic training rows in tests.
+    """
+    if not 0 <= stream < 64:
+        raise ValueError("stream must be in [0, 64)")
+    return uniform01(seed, np.arange(count, dtype=np.uint64), stream)

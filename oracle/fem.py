@@ -298,6 +298,103 @@ def solve_rve(disc: Discretisation, physics_tensor, bc, ncomp, lo=(0, 0, 0), hi=
     return dict(hom=hom, hom_vol=hom_vol, hom_energy=hom_energy, u=u, lam=lam, K=K, C=C, D=D)
 
 
+def nested_dissection(xyz, adj, leaf=48):
+    """Fill-reducing elimination order (a permutation of the nodes) by geometric
+    nested dissection: split at the median of the widest coordinate, take the
+    left nodes coupled to the right half as the separator, recurse, order the
+    separator last.  Wrap-around couplings of a periodic cell land in the
+    separator too.  Only the factorisation cost depends on it, not the result.
+    """
+    parts = []
+
+    def split(S):
+        if S.size <= leaf:
+            parts.append(S)
+            return
+        ax = int(np.argmax(xyz[S].max(axis=0) - xyz[S].min(axis=0)))
+        med = np.median(xyz[S, ax])
+        L, R = S[xyz[S, ax] < med], S[xyz[S, ax] >= med]
+        if L.size == 0 or R.size == 0:
+            parts.append(S)
+            return
+        on_sep = np.diff(adj[L][:, R].indptr) > 0
+        split(L[~on_sep])
+        split(R)
+        parts.append(L[on_sep])
+
+    split(np.arange(xyz.shape[0]))
+    return np.concatenate(parts)
+
+
+def solve_rve_substituted(disc: Discretisation, physics_tensor, bc, ncomp, lo=(0, 0, 0), hi=(1, 1, 1)):
+    """Same discrete problem as solve_rve for the Dirichlet and periodic conditions,
+    with the constraints eliminated by substitution instead of multipliers.
+
+    Sec. 2 states that condensing the constrained DOFs and adding multipliers are two
+    routes to one constrained system.  Here u = P w + g per load case: Dirichlet
+    nodes take u = X(y) eps_bar; a periodic slave takes its master's value plus
+    (X(y_s) - X(y_m)) eps_bar, and the lower corner's class is fixed to the linear
+    field.  The reduced matrix P^T K P is SPD and factorised once; the homogenised
+    matrix is the volume average of the fluxes (equal to the multiplier route,
+    which this form has no multipliers for).
+    """
+    if bc not in (BC_DIRICHLET, BC_PERIODIC):
+        raise ValueError("substitution is only written for the Dirichlet and periodic conditions")
+    Xf = X_mech if ncomp == 3 else X_scalar
+    K = disc.stiffness_mech(physics_tensor) if ncomp == 3 else disc.stiffness_scalar(physics_tensor)
+    N = disc.n_nodes
+    ncase = 6 if ncomp == 3 else 3
+    rep = np.arange(N)                        # node whose unknowns a node copies
+    fixed = np.zeros(N, dtype=bool)           # nodes whose value is prescribed outright
+    g = np.zeros((N, ncomp, ncase))           # prescribed part of u per node
+    if bc == BC_DIRICHLET:
+        b = disc.boundary_nodes
+        fixed[b] = True
+        g[b] = Xf(disc.nodes[b])
+    else:
+        pairs, corner = disc.periodic_classes(lo, hi)
+        for s, m in pairs:
+            rep[s] = m
+            g[s] = Xf(disc.nodes[s]) - Xf(disc.nodes[m])
+        fixed[corner] = True
+        g[corner] = Xf(disc.nodes[corner])
+        for s, m in pairs:                    # slaves of the corner: linear field outright
+            if m == corner:
+                fixed[s] = True
+                g[s] = Xf(disc.nodes[s])
+    free_nodes = np.nonzero((rep == np.arange(N)) & ~fixed)[0]
+    col_of = -np.ones(N, dtype=np.int64)
+    col_of[free_nodes] = np.arange(free_nodes.size)
+    node_col = np.where(fixed, -1, col_of[rep])
+    rows = (ncomp * np.arange(N)[:, None] + np.arange(ncomp)[None, :])[node_col >= 0].ravel()
+    cols = (ncomp * node_col[:, None] + np.arange(ncomp)[None, :])[node_col >= 0].ravel()
+    P = sp.csr_matrix((np.ones(rows.size), (rows, cols)), shape=(ncomp * N, ncomp * free_nodes.size))
+    G = g.reshape(ncomp * N, ncase)
+    Kr = (P.T @ K @ P).tocsr()
+    # fill-reducing order: nested dissection of the free nodes' coupling graph
+    sel = np.nonzero(node_col >= 0)[0]
+    Pn = sp.csr_matrix((np.ones(sel.size), (sel, node_col[sel])), shape=(N, free_nodes.size))
+    T, nn = disc.e2n.shape
+    E2 = sp.csr_matrix((np.ones(T * nn), (np.repeat(np.arange(T), nn), disc.e2n.ravel())), shape=(T, N))
+    adj = (Pn.T @ (E2.T @ E2) @ Pn).tocsr()
+    order = nested_dissection(disc.nodes[free_nodes], adj)
+    perm = (ncomp * order[:, None] + np.arange(ncomp)[None, :]).ravel()
+    lu = spla.splu(Kr[perm][:, perm].tocsc(), permc_spec="NATURAL", diag_pivot_thresh=0.0,
+                   options=dict(SymmetricMode=True))
+    rhs = -(P.T @ (K @ G))
+    w = np.empty_like(rhs)
+    w[perm] = lu.solve(rhs[perm])
+    u = P @ w + G
+    V = disc.V
+    gint = disc.grad_integrals(u, ncomp)
+    if ncomp == 3:
+        hom_vol = np.einsum("eij,ejq->iq", physics_tensor, _voigt_strain(gint)) / V
+    else:
+        hom_vol = np.einsum("eij,ejq->iq", physics_tensor, gint[:, 0]) / V
+    hom_energy = (u.T @ (K @ u)) / V
+    return dict(hom=hom_vol, hom_vol=hom_vol, hom_energy=hom_energy, u=u, K=K)
+
+
 def voigt_reuss(disc: Discretisation, tensors):
     w = disc.vol / disc.V
     upper = np.einsum("e,eij->ij", w, tensors)
@@ -306,16 +403,22 @@ def voigt_reuss(disc: Discretisation, tensors):
 
 
 def homogenise(coords, tets, phase, axis, p, bc, base, params=None, c_sat=1.5,
-               degrade_yarn=False, lo=(0, 0, 0), hi=(1, 1, 1), disc=None, physics=("mech", "thermal", "moisture")):
-    """C_bar (6x6), K_bar (3x3), D_bar (3x3) of one RVE and one parameter record."""
+               degrade_yarn=False, lo=(0, 0, 0), hi=(1, 1, 1), disc=None, physics=("mech", "thermal", "moisture"),
+               method="multipliers"):
+    """C_bar (6x6), K_bar (3x3), D_bar (3x3) of one RVE and one parameter record.
+
+    method: "multipliers" (the bordered system, every BC) or "substitution"
+    (Dirichlet and periodic only; the same discrete solution, cheaper to factorise).
+    """
+    solve = solve_rve if method == "multipliers" else solve_rve_substituted
     disc = disc or Discretisation(coords, tets, p)
     m, y, keep = mats.phase_materials(base, params, c_sat, degrade_yarn)
     Ce, Ke, De = mats.element_tensors(phase, axis, m, y)
     out = {"omega_keep": keep}
     if "mech" in physics:
-        out["C"] = solve_rve(disc, Ce, bc, 3, lo, hi)["hom"]
+        out["C"] = solve(disc, Ce, bc, 3, lo, hi)["hom"]
     if "thermal" in physics:
-        out["K"] = solve_rve(disc, Ke, bc, 1, lo, hi)["hom"]
+        out["K"] = solve(disc, Ke, bc, 1, lo, hi)["hom"]
     if "moisture" in physics:
-        out["D"] = solve_rve(disc, De, bc, 1, lo, hi)["hom"]
+        out["D"] = solve(disc, De, bc, 1, lo, hi)["hom"]
     return out

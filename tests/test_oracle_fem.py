@@ -239,3 +239,26 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(M, "voigt_to_tensor", bad_tensor)
     assert _rel(solve(), C) > 1e-3
     monkeypatch.setattr(M, "voigt_to_tensor", orig_vt)
+
+
+@pytest.mark.parametrize("n,p", [(3, 2), (2, 3), (3, 1)])
+def test_substitution_equals_multipliers(n, p):
+    """Condensing the Dirichlet / periodic constraints gives the bordered system's answer (Sec. 2)."""
+    c, t, ph, ax = mesh.plain_weave(n)
+    prm = ci.draw_params(5, 1)[0]
+    disc = fem.Discretisation(c, t, p)
+    for bc in (fem.BC_DIRICHLET, fem.BC_PERIODIC):
+        a = fem.homogenise(c, t, ph, ax, p, bc, ci.BASE_MATERIALS, prm, disc=disc)
+        b = fem.homogenise(c, t, ph, ax, p, bc, ci.BASE_MATERIALS, prm, disc=disc, method="substitution")
+        for k in "CKD":
+            assert _rel(b[k], a[k]) < 1e-12, (bc, k)
+
+
+def test_nested_dissection_is_a_permutation():
+    c, t, ph, ax = mesh.plain_weave(3)
+    disc = fem.Discretisation(c, t, 2)
+    N = disc.n_nodes
+    T, nn = disc.e2n.shape
+    E2 = sp.csr_matrix((np.ones(T * nn), (np.repeat(np.arange(T), nn), disc.e2n.ravel())), shape=(T, N))
+    order = fem.nested_dissection(disc.nodes, (E2.T @ E2).tocsr(), leaf=8)
+    np.testing.assert_array_equal(np.sort(order), np.arange(N))
