@@ -217,6 +217,114 @@ int chom_batch_time_operator(chom_batch *batch, int32_t physics, int32_t reps, d
 /* Release a batch (NULL is ignored). */
 void chom_batch_destroy(chom_batch *batch);
 
+/* ---------------------------------------------------------------- learned surrogate
+ * An ensemble of small networks that maps a parameter record (temperature,
+ * moisture, exposure time, eight property factors) to the homogenised
+ * C_bar, K_bar, D_bar of one RVE, trained on that RVE's own solves, with the RVE
+ * solve as fallback where the ensemble disagrees.  The surrogate is not part of
+ * the paper; it reads the record through the paper's degradation law (Sec. 4,
+ * Eq. Eq_Model_final1): its ten features are log(1 - omega), (1 - omega) and
+ * the eight factors.
+ *
+ * Network of each member: 10 -> 256 -> 256 -> 256 -> 33, GELU (z Phi(z)) on the
+ * hidden layers.  Outputs: the 21 + 6 + 6 entries of chom_homogenise.  Features
+ * and outputs are standardised with per-column mean and population deviation
+ * of the training set.  Weights and activations enter the products as
+ * bfloat16 (round to nearest even) with FP32 accumulation; biases, the loss,
+ * gradients and Adam moments are FP32; standardisation is FP64.
+ *
+ * Flat parameter layout of one member (FP32, row-major [out][in]):
+ *   W1 [256][10], b1 [256], W2 [256][256], b2 [256], W3 [256][256], b3 [256],
+ *   W4 [33][256], b4 [33]                       (142,881 numbers)
+ * Standardisation record (FP64, 86 numbers): feature means [10], feature
+ * deviations [10], output means [33], output deviations [33].
+ *
+ * Disagreement of a point: the largest over the C, K, D blocks of
+ * ||s||_F / ||m||_F, with m the member mean and s the sample standard deviation
+ * over members, both in physical units, and ||.||_F the Frobenius norm of the
+ * full symmetric matrix (off-diagonal entries counted twice).
+ *
+ * Pointer convention: params [n] (chom_params), C [n][21], K [n][6], D [n][6],
+ * disagreement [n] and used_fallback [n] are device pointers when
+ * chom_mlp_options.device_ptrs is set, else host pointers.  Weight and
+ * standardisation arrays are always host pointers. */
+typedef struct chom_mlp chom_mlp;
+
+typedef struct {
+    int32_t members;        /* ensemble size, 1..8 (default 5)                           */
+    int32_t device_ptrs;    /* 1: bulk arrays are device pointers                         */
+    uint64_t seed;          /* initial weights (U(-a, a), a = sqrt(3 / fan_in), zero biases) and shuffles */
+    double c_sat;           /* moisture of full saturation in the degradation law (wt%), default 1.5 */
+    void *hip_stream;       /* hipStream_t or NULL (the library's own stream)           */
+} chom_mlp_options;
+
+typedef struct {
+    int32_t epochs;         /* passes over the training set (default 300)                 */
+    int32_t batch;          /* minibatch rows, 1..256 (default 256)                       */
+    float lr, lr_final;     /* Adam step size, cosine-decayed from lr to lr_final over the call (2e-3, 2e-5) */
+    float beta1, beta2, eps;/* Adam constants (0.9, 0.999, 1e-8)                          */
+    int32_t refit_normalisation; /* 1: standardise with this training set's statistics (default 1) */
+} chom_mlp_train_options;
+
+int chom_mlp_default_options(chom_mlp_options *opt);
+int chom_mlp_default_train_options(chom_mlp_train_options *opt);
+
+/* Create an ensemble with seeded initial weights.  opt may be NULL (defaults).
+ * Errors: CHOM_EINVAL, CHOM_EDEVICE, CHOM_ENOMEM. */
+int chom_mlp_create(const chom_mlp_options *opt, chom_mlp **out);
+
+/* Parameters per member (142,881) and members.  Errors: CHOM_EINVAL. */
+int chom_mlp_sizes(const chom_mlp *mlp, int64_t *params_per_member, int32_t *members);
+
+/* Replace (set) or read (get) one member's FP32 master weights, flat layout
+ * above, host memory.  Setting also clears that member's Adam moments and, for
+ * every member, the Adam step count.  Errors: CHOM_EINVAL, CHOM_EDEVICE. */
+int chom_mlp_set_weights(chom_mlp *mlp, int32_t member, const float *flat);
+int chom_mlp_get_weights(const chom_mlp *mlp, int32_t member, float *flat);
+
+/* Replace or read the standardisation record (86 doubles, host).  Deviations
+ * must be positive.  Errors: CHOM_EINVAL (and for get: no record yet). */
+int chom_mlp_set_normalisation(chom_mlp *mlp, const double *record);
+int chom_mlp_get_normalisation(const chom_mlp *mlp, double *record);
+
+/* Train every member on n (record, result) pairs: minibatch Adam on the mean
+ * squared error of the standardised outputs, one launch for the whole call
+ * (each member shuffles the set independently every epoch).  loss_history
+ * [members][epochs] (host, nullable) receives each epoch's mean loss.  Calls
+ * may be repeated (training continues).  1 <= n < 2^31.
+ * Errors: CHOM_EINVAL (records outside the degradation law's domain, sizes),
+ * CHOM_EDEVICE, CHOM_ENOMEM. */
+int chom_mlp_train(chom_mlp *mlp, const chom_params *params, const double *C, const double *K, const double *D,
+                   int64_t n, const chom_mlp_train_options *opt, float *loss_history);
+
+/* Loss of one member on n pairs and its gradient with respect to the flat
+ * parameters (grad [142,881], host), without updating anything; the forward
+ * and backward kernels of chom_mlp_train, for checking.  Needs a
+ * standardisation record.  Errors: CHOM_EINVAL, CHOM_EDEVICE, CHOM_ENOMEM. */
+int chom_mlp_loss_grad(chom_mlp *mlp, int32_t member, const chom_params *params, const double *C,
+                       const double *K, const double *D, int64_t n, double *loss, float *grad);
+
+/* Ensemble prediction for n records: member mean in physical units (C, K, D)
+ * and the disagreement (nullable).  Needs a standardisation record.
+ * Errors: CHOM_EINVAL (records outside the law's domain), CHOM_EDEVICE. */
+int chom_mlp_predict(chom_mlp *mlp, const chom_params *params, int64_t n, double *C, double *K, double *D,
+                     double *disagreement);
+
+/* Surrogate with fallback: predict all n records, then re-solve with the RVE
+ * (chom_homogenise on `fallback`, in chunks of at most `chunk` records; 0 means
+ * 256) every record whose disagreement exceeds thresh, overwriting its
+ * prediction.  used_fallback [n] (uint8, nullable) flags the re-solved records;
+ * *n_fallback (nullable, host) receives their count.  The RVE must use the same
+ * c_sat as the ensemble.  Needs members >= 2.
+ * Errors: those of chom_mlp_predict and chom_homogenise (CHOM_ENOCONV: results
+ * written, some fallback solve did not converge). */
+int chom_homogenise_surrogate(chom_mlp *mlp, chom_rve *fallback, const chom_params *params, int64_t n,
+                              double thresh, int32_t chunk, double *C, double *K, double *D,
+                              double *disagreement, uint8_t *used_fallback, int64_t *n_fallback);
+
+/* Release an ensemble (NULL is ignored). */
+void chom_mlp_destroy(chom_mlp *mlp);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *chom_last_error(void);
 

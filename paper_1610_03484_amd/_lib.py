@@ -46,6 +46,17 @@ class ChomReport(ct.Structure):
                 ("resid", ct.c_double * 12), ("asym", ct.c_double), ("omega_keep", ct.c_double)]
 
 
+class ChomMlpOptions(ct.Structure):
+    _fields_ = [("members", ct.c_int32), ("device_ptrs", ct.c_int32), ("seed", ct.c_uint64),
+                ("c_sat", ct.c_double), ("hip_stream", ct.c_void_p)]
+
+
+class ChomMlpTrainOptions(ct.Structure):
+    _fields_ = [("epochs", ct.c_int32), ("batch", ct.c_int32), ("lr", ct.c_float), ("lr_final", ct.c_float),
+                ("beta1", ct.c_float), ("beta2", ct.c_float), ("eps", ct.c_float),
+                ("refit_normalisation", ct.c_int32)]
+
+
 # every exported symbol of include/chom.h with its ctypes signature
 SIGNATURES = {
     "chom_default_options": (ct.c_int, [ct.POINTER(ChomOptions)]),
@@ -75,6 +86,24 @@ SIGNATURES = {
                                       ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)]),
     "chom_element_apply_host": (ct.c_int, [ct.c_int32, ct.c_void_p, ct.c_double, ct.c_void_p, ct.c_void_p,
                                            ct.c_void_p, ct.c_void_p]),
+    "chom_mlp_default_options": (ct.c_int, [ct.POINTER(ChomMlpOptions)]),
+    "chom_mlp_default_train_options": (ct.c_int, [ct.POINTER(ChomMlpTrainOptions)]),
+    "chom_mlp_create": (ct.c_int, [ct.POINTER(ChomMlpOptions), ct.POINTER(ct.c_void_p)]),
+    "chom_mlp_sizes": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32)]),
+    "chom_mlp_set_weights": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_void_p]),
+    "chom_mlp_get_weights": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_void_p]),
+    "chom_mlp_set_normalisation": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "chom_mlp_get_normalisation": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "chom_mlp_train": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64,
+                                  ct.POINTER(ChomMlpTrainOptions), ct.c_void_p]),
+    "chom_mlp_loss_grad": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                      ct.c_void_p, ct.c_int64, ct.POINTER(ct.c_double), ct.c_void_p]),
+    "chom_mlp_predict": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                    ct.c_void_p]),
+    "chom_homogenise_surrogate": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_double,
+                                             ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                             ct.c_void_p, ct.POINTER(ct.c_int64)]),
+    "chom_mlp_destroy": (None, [ct.c_void_p]),
 }
 
 _lib = None

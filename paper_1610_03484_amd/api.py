@@ -223,3 +223,142 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def mlp_default_options(**kw) -> L.ChomMlpOptions:
+    o = L.ChomMlpOptions()
+    L.check(L.lib().chom_mlp_default_options(ct.byref(o)), "chom_mlp_default_options")
+    for k, v in kw.items():
+        setattr(o, k, ct.c_void_p(v) if k == "hip_stream" else v)
+    return o
+
+
+def mlp_train_options(**kw) -> L.ChomMlpTrainOptions:
+    o = L.ChomMlpTrainOptions()
+    L.check(L.lib().chom_mlp_default_train_options(ct.byref(o)), "chom_mlp_default_train_options")
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(x):
+    """Data pointer of a torch tensor (device convention) or a C-contiguous numpy array (host)."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor arguments must be contiguous")
+        return ct.c_void_p(x.data_ptr())
+    if not x.flags["C_CONTIGUOUS"]:
+        raise ValueError("array arguments must be C-contiguous")
+    return ct.c_void_p(x.ctypes.data)
+
+
+class Surrogate:
+    """Handle of chom_mlp_create: an ensemble of networks mapping parameter records to
+    C_hom, K_hom, D_hom (see include/chom.h).  With device=True the bulk arrays are
+    torch device tensors (float64, contiguous); otherwise numpy arrays."""
+
+    def __init__(self, members=5, seed=0, c_sat=1.5, device=False, hip_stream=None):
+        self.device = bool(device)
+        opt = mlp_default_options(members=members, seed=seed, c_sat=c_sat, device_ptrs=int(self.device))
+        if hip_stream is not None:
+            opt.hip_stream = ct.c_void_p(hip_stream)
+        self._h = ct.c_void_p()
+        L.check(L.lib().chom_mlp_create(ct.byref(opt), ct.byref(self._h)), "chom_mlp_create")
+        self.members = members
+
+    def sizes(self):
+        p, m = ct.c_int64(), ct.c_int32()
+        L.check(L.lib().chom_mlp_sizes(self._h, ct.byref(p), ct.byref(m)), "chom_mlp_sizes")
+        return p.value, m.value
+
+    def set_weights(self, member, flat):
+        w = np.ascontiguousarray(np.asarray(flat, dtype=np.float32))
+        if w.size != self.sizes()[0]:
+            raise ValueError("wrong number of weights")
+        L.check(L.lib().chom_mlp_set_weights(self._h, member, _ptr(w)), "chom_mlp_set_weights")
+
+    def get_weights(self, member):
+        w = np.zeros(self.sizes()[0], dtype=np.float32)
+        L.check(L.lib().chom_mlp_get_weights(self._h, member, _ptr(w)), "chom_mlp_get_weights")
+        return w
+
+    def set_normalisation(self, rec):
+        r = np.ascontiguousarray(np.asarray(rec, dtype=np.float64))
+        if r.size != 86:
+            raise ValueError("the standardisation record has 86 numbers")
+        L.check(L.lib().chom_mlp_set_normalisation(self._h, _ptr(r)), "chom_mlp_set_normalisation")
+
+    def get_normalisation(self):
+        r = np.zeros(86)
+        L.check(L.lib().chom_mlp_get_normalisation(self._h, _ptr(r)), "chom_mlp_get_normalisation")
+        return r
+
+    def _bulk(self, p, C=None, K=None, D=None):
+        if self.device:
+            return p, C, K, D
+        cv = lambda a, w: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1, w))
+        return cv(p, 11), cv(C, 21), cv(K, 6), cv(D, 6)
+
+    def train(self, params, C, K, D, **train_opts):
+        """Train every member; returns the loss history [members, epochs]."""
+        p, C, K, D = self._bulk(params, C, K, D)
+        n = len(p)
+        o = mlp_train_options(**train_opts)
+        hist = np.zeros((self.members, o.epochs), dtype=np.float32)
+        L.check(L.lib().chom_mlp_train(self._h, _ptr(p), _ptr(C), _ptr(K), _ptr(D), n, ct.byref(o), _ptr(hist)),
+                "chom_mlp_train")
+        return hist
+
+    def loss_grad(self, member, params, C, K, D):
+        p, C, K, D = self._bulk(params, C, K, D)
+        loss = ct.c_double()
+        g = np.zeros(self.sizes()[0], dtype=np.float32)
+        L.check(L.lib().chom_mlp_loss_grad(self._h, member, _ptr(p), _ptr(C), _ptr(K), _ptr(D), len(p),
+                                           ct.byref(loss), _ptr(g)), "chom_mlp_loss_grad")
+        return loss.value, g
+
+    def _outputs(self, n):
+        if self.device:
+            import torch
+            mk = lambda *s: torch.empty(s, dtype=torch.float64, device="cuda")
+            return mk(n, 21), mk(n, 6), mk(n, 6), mk(n)
+        return np.zeros((n, 21)), np.zeros((n, 6)), np.zeros((n, 6)), np.zeros(n)
+
+    def predict(self, params):
+        """(C21, K6, D6, disagreement) of the ensemble mean."""
+        p = self._bulk(params)[0]
+        n = len(p)
+        C, K, D, dis = self._outputs(n)
+        L.check(L.lib().chom_mlp_predict(self._h, _ptr(p), n, _ptr(C), _ptr(K), _ptr(D), _ptr(dis)),
+                "chom_mlp_predict")
+        return C, K, D, dis
+
+    def homogenise(self, rve, params, thresh=1e-2, chunk=0, allow_noconv=False):
+        """Surrogate with RVE fallback: (C21, K6, D6, disagreement, used_fallback, n_fallback)."""
+        p = self._bulk(params)[0]
+        n = len(p)
+        C, K, D, dis = self._outputs(n)
+        if self.device:
+            import torch
+            used = torch.empty(n, dtype=torch.uint8, device="cuda")
+        else:
+            used = np.zeros(n, dtype=np.uint8)
+        nfb = ct.c_int64()
+        st = L.lib().chom_homogenise_surrogate(self._h, rve._h, _ptr(p), n, thresh, chunk, _ptr(C), _ptr(K),
+                                               _ptr(D), _ptr(dis), _ptr(used), ct.byref(nfb))
+        if not (st == L.CHOM_OK or (allow_noconv and st == L.CHOM_ENOCONV)):
+            L.check(st, "chom_homogenise_surrogate")
+        return C, K, D, dis, used, nfb.value
+
+    def close(self):
+        if self._h:
+            L.lib().chom_mlp_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

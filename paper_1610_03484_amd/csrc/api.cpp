@@ -21,44 +21,6 @@ namespace chom {
 static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
-#define CHOM_HIP(...)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (__VA_ARGS__);                                                         \
-        if (e_ != hipSuccess) {                                                                \
-            set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #__VA_ARGS__); \
-            return e_ == hipErrorOutOfMemory ? CHOM_ENOMEM : CHOM_EDEVICE;                     \
-        }                                                                                      \
-    } while (0)
-
-#define CHOM_TRY(...)                    \
-    do {                                 \
-        int st_ = (__VA_ARGS__);         \
-        if (st_ != CHOM_OK) return st_;  \
-    } while (0)
-
-// Device buffer owned by a handle.
-template <typename T> struct DevBuf {
-    T *p = nullptr;
-    size_t n = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf &) = delete;
-    DevBuf &operator=(const DevBuf &) = delete;
-    ~DevBuf() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-    }
-    hipError_t ensure(size_t count) {
-        if (count <= n && p) return hipSuccess;
-        release();
-        if (count == 0) count = 1;
-        hipError_t e = hipMalloc((void **)&p, sizeof(T) * count);
-        if (e == hipSuccess) n = count;
-        return e;
-    }
-};
-
 // ------------------------------------------------------------------ materials
 static const double kBeta = -0.001682;     // per day (Sec. 4, Eq. Eq_alphaT_LSF)
 static const double kTgC = 126.0;          // glass transition (Sec. 4)
@@ -646,11 +608,11 @@ static int batch_init(chom_batch *B, chom_rve *const *rves, int n, const chom_op
 }
 
 static int batch_homogenise(chom_batch *B, const chom_params *params, double *C_hom, double *K_hom, double *D_hom,
-                            chom_report *rep) {
+                            chom_report *rep, bool dev) {
     const int batch = (int)B->entries.size();
     hipStream_t s = B->stream;
     std::vector<chom_params> hp(batch);
-    if (B->opt.device_ptrs)
+    if (dev)
         CHOM_HIP(hipMemcpy(hp.data(), params, sizeof(chom_params) * batch, hipMemcpyDeviceToHost));
     else
         std::memcpy(hp.data(), params, sizeof(chom_params) * batch);
@@ -742,7 +704,7 @@ static int batch_homogenise(chom_batch *B, const chom_params *params, double *C_
         if (Rp.status != CHOM_OK) overall = CHOM_ENOCONV;
         if (rep) rep[i] = Rp;
     }
-    if (B->opt.device_ptrs) {
+    if (dev) {
         CHOM_HIP(hipMemcpyAsync(C_hom, oc.data(), sizeof(double) * oc.size(), hipMemcpyHostToDevice, s));
         CHOM_HIP(hipMemcpyAsync(K_hom, ok.data(), sizeof(double) * ok.size(), hipMemcpyHostToDevice, s));
         CHOM_HIP(hipMemcpyAsync(D_hom, od.data(), sizeof(double) * od.size(), hipMemcpyHostToDevice, s));
@@ -802,6 +764,28 @@ static int batch_time_operator(chom_batch *B, int32_t physics, int32_t reps, dou
 }  // namespace chom
 
 // ====================================================================== C ABI
+namespace chom {
+
+int rve_homogenise_host(chom_rve *rve, const chom_params *params, int batch, double *C, double *K, double *D,
+                        chom_report *rep) {
+    if (!rve->self || rve->self_size != batch) {
+        rve->self.reset();
+        std::unique_ptr<chom_batch> B(new chom_batch());
+        std::vector<chom_rve *> ents(batch, rve);
+        CHOM_TRY(batch_init(B.get(), ents.data(), batch, &rve->opt));
+        rve->self = std::move(B);
+        rve->self_size = batch;
+    }
+    return batch_homogenise(rve->self.get(), params, C, K, D, rep, false);
+}
+
+void rve_settings(const chom_rve *rve, double *c_sat, int *degrade_yarn) {
+    *c_sat = rve->opt.c_sat;
+    *degrade_yarn = rve->opt.degrade_yarn;
+}
+
+}  // namespace chom
+
 extern "C" {
 
 const char *chom_last_error(void) { return chom::g_last_error.c_str(); }
@@ -1083,7 +1067,7 @@ int chom_homogenise(chom_rve *rve, const chom_params *params, int32_t batch, dou
         rve->self = std::move(B);
         rve->self_size = batch;
     }
-    const int st = batch_homogenise(rve->self.get(), params, C_hom, K_hom, D_hom, rep);
+    const int st = batch_homogenise(rve->self.get(), params, C_hom, K_hom, D_hom, rep, rve->opt.device_ptrs != 0);
     if (st != CHOM_OK) set_error("chom_homogenise: " + g_last_error);
     return st;
 }
@@ -1123,7 +1107,7 @@ int chom_batch_homogenise(chom_batch *batch, const chom_params *params, double *
         set_error("chom_batch_homogenise: null argument");
         return CHOM_EINVAL;
     }
-    const int st = batch_homogenise(batch, params, C_hom, K_hom, D_hom, rep);
+    const int st = batch_homogenise(batch, params, C_hom, K_hom, D_hom, rep, batch->opt.device_ptrs != 0);
     if (st != CHOM_OK) set_error("chom_batch_homogenise: " + g_last_error);
     return st;
 }

@@ -90,4 +90,49 @@ hipError_t launch_average(const Launch &L, const double *x64, double *partial, i
 
 void set_error(const std::string &msg);
 
+// Homogenises `batch` records given in host memory with the RVE's own batch
+// workspace, whatever the RVE's pointer convention (outputs in host memory too).
+int rve_homogenise_host(chom_rve *rve, const chom_params *params, int batch, double *C, double *K, double *D,
+                        chom_report *rep);
+void rve_settings(const chom_rve *rve, double *c_sat, int *degrade_yarn);
+
+#define CHOM_HIP(...)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (__VA_ARGS__);                                                         \
+        if (e_ != hipSuccess) {                                                                \
+            set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #__VA_ARGS__); \
+            return e_ == hipErrorOutOfMemory ? CHOM_ENOMEM : CHOM_EDEVICE;                     \
+        }                                                                                      \
+    } while (0)
+
+#define CHOM_TRY(...)                    \
+    do {                                 \
+        int st_ = (__VA_ARGS__);         \
+        if (st_ != CHOM_OK) return st_;  \
+    } while (0)
+
+// Device buffer owned by a handle.
+template <typename T> struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t ensure(size_t count) {
+        if (count <= n && p) return hipSuccess;
+        release();
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc((void **)&p, sizeof(T) * count);
+        if (e == hipSuccess) n = count;
+        return e;
+    }
+};
+
+
 }  // namespace chom

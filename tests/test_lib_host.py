@@ -35,7 +35,8 @@ def test_library_exports_every_header_symbol(L):
 def test_struct_layouts_match_c_compiler(L, tmp_path):
     """ctypes structs of the binding have the layout gcc gives the header's structs."""
     structs = {"chom_mesh": L.ChomMesh, "chom_materials": L.ChomMaterials, "chom_params": L.ChomParams,
-               "chom_options": L.ChomOptions, "chom_report": L.ChomReport}
+               "chom_options": L.ChomOptions, "chom_report": L.ChomReport,
+               "chom_mlp_options": L.ChomMlpOptions, "chom_mlp_train_options": L.ChomMlpTrainOptions}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "chom.h"', 'int main(void){']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -211,3 +212,28 @@ def test_mesh_sizes(L):
     assert mesh_sizes(24) == (25 ** 3, 6 * 24 ** 3)
     with pytest.raises(L.ChomError):
         mesh_sizes(0)
+
+
+def test_surrogate_defaults_and_argument_errors(L):
+    from paper_1610_03484_amd import mlp_default_options, mlp_train_options
+    o = mlp_default_options()
+    assert (o.members, o.device_ptrs, o.seed, o.c_sat) == (5, 0, 0, 1.5)
+    t = mlp_train_options()
+    assert (t.epochs, t.batch, t.refit_normalisation) == (300, 256, 1)
+    assert abs(t.lr - 2e-3) < 1e-9 and abs(t.beta2 - 0.999) < 1e-7
+    h = ct.c_void_p()
+    bad = mlp_default_options(members=9)
+    assert L.lib().chom_mlp_create(ct.byref(bad), ct.byref(h)) == L.CHOM_EINVAL
+    assert L.lib().chom_mlp_create(None, None) == L.CHOM_EINVAL
+    assert L.lib().chom_mlp_train(None, None, None, None, None, 0, None, None) == L.CHOM_EINVAL
+    assert L.lib().chom_mlp_predict(None, None, 0, None, None, None, None) == L.CHOM_EINVAL
+
+
+def test_surrogate_needs_a_device(L):
+    """No GPU here: creating an ensemble fails loudly instead of falling back to the CPU."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ct.c_void_p()
+    assert L.lib().chom_mlp_create(None, ct.byref(h)) == L.CHOM_EDEVICE
+    assert not h.value

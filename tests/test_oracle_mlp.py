@@ -6,26 +6,10 @@ import pytest
 import torch
 
 import chom_inputs as ci
+from mlp_util import rows as _rows
+from mlp_util import weights as _weights
 from oracle import materials as mats
 from oracle import mlp
-
-
-def _weights(seed, member=0, scale=1.0):
-    """Synthetic member weights: U(-a, a) with a = sqrt(3 / fan_in) (unit-variance fan-in)."""
-    u = ci.uniform_block(seed, member, mlp.n_params())
-    out, k = [], 0
-    for i, o in mlp.LAYERS:
-        a = scale * math.sqrt(3.0 / i)
-        W = (2.0 * u[k:k + o * i] - 1.0) * a
-        k += o * i
-        b = (2.0 * u[k:k + o] - 1.0) * 0.1
-        k += o
-        out.append(np.concatenate([W, b]))
-    return np.concatenate(out)
-
-
-def _rows(seed, n, width, stream=0):
-    return (2.0 * ci.uniform_block(seed, stream, n * width) - 1.0).reshape(n, width)
 
 
 def test_param_count_and_layout():
