@@ -226,18 +226,21 @@ void chom_batch_destroy(chom_batch *batch);
  * Eq. Eq_Model_final1): its ten features are log(1 - omega), (1 - omega) and
  * the eight factors.
  *
- * Network of each member: 10 -> 256 -> 256 -> 256 -> 33, GELU (z Phi(z)) on the
- * hidden layers.  Outputs: the 21 + 6 + 6 entries of chom_homogenise.  Features
- * and outputs are standardised with per-column mean and population deviation
- * of the training set.  Weights and activations enter the products as
+ * Network of each member: 10 -> 256 -> 256 -> 256 -> 36, GELU (z Phi(z)) on the
+ * hidden layers.  The 36 outputs encode the 21 + 6 + 6 entries of
+ * chom_homogenise per block (C, K, D) as the log of the block's Frobenius norm
+ * followed by the block divided by that norm; decoding rescales the predicted
+ * direction to unit norm, so the error of a block is relative to its size.
+ * Features and encoded outputs are standardised with per-column mean and
+ * population deviation of the training set.  Weights and activations enter the products as
  * bfloat16 (round to nearest even) with FP32 accumulation; biases, the loss,
  * gradients and Adam moments are FP32; standardisation is FP64.
  *
  * Flat parameter layout of one member (FP32, row-major [out][in]):
  *   W1 [256][10], b1 [256], W2 [256][256], b2 [256], W3 [256][256], b3 [256],
- *   W4 [33][256], b4 [33]                       (142,881 numbers)
- * Standardisation record (FP64, 86 numbers): feature means [10], feature
- * deviations [10], output means [33], output deviations [33].
+ *   W4 [36][256], b4 [36]                       (143,652 numbers)
+ * Standardisation record (FP64, 92 numbers): feature means [10], feature
+ * deviations [10], encoded-output means [36], encoded-output deviations [36].
  *
  * Disagreement of a point: the largest over the C, K, D blocks of
  * ||s||_F / ||m||_F, with m the member mean and s the sample standard deviation
@@ -273,7 +276,7 @@ int chom_mlp_default_train_options(chom_mlp_train_options *opt);
  * Errors: CHOM_EINVAL, CHOM_EDEVICE, CHOM_ENOMEM. */
 int chom_mlp_create(const chom_mlp_options *opt, chom_mlp **out);
 
-/* Parameters per member (142,881) and members.  Errors: CHOM_EINVAL. */
+/* Parameters per member (143,652) and members.  Errors: CHOM_EINVAL. */
 int chom_mlp_sizes(const chom_mlp *mlp, int64_t *params_per_member, int32_t *members);
 
 /* Replace (set) or read (get) one member's FP32 master weights, flat layout
@@ -282,7 +285,7 @@ int chom_mlp_sizes(const chom_mlp *mlp, int64_t *params_per_member, int32_t *mem
 int chom_mlp_set_weights(chom_mlp *mlp, int32_t member, const float *flat);
 int chom_mlp_get_weights(const chom_mlp *mlp, int32_t member, float *flat);
 
-/* Replace or read the standardisation record (86 doubles, host).  Deviations
+/* Replace or read the standardisation record (92 doubles, host).  Deviations
  * must be positive.  Errors: CHOM_EINVAL (and for get: no record yet). */
 int chom_mlp_set_normalisation(chom_mlp *mlp, const double *record);
 int chom_mlp_get_normalisation(const chom_mlp *mlp, double *record);
@@ -298,7 +301,7 @@ int chom_mlp_train(chom_mlp *mlp, const chom_params *params, const double *C, co
                    int64_t n, const chom_mlp_train_options *opt, float *loss_history);
 
 /* Loss of one member on n pairs and its gradient with respect to the flat
- * parameters (grad [142,881], host), without updating anything; the forward
+ * parameters (grad [143,652], host), without updating anything; the forward
  * and backward kernels of chom_mlp_train, for checking.  Needs a
  * standardisation record.  Errors: CHOM_EINVAL, CHOM_EDEVICE, CHOM_ENOMEM. */
 int chom_mlp_loss_grad(chom_mlp *mlp, int32_t member, const chom_params *params, const double *C,

@@ -8,16 +8,21 @@ factor (1 - omega) = exp(-gamma(c) alpha(T) t) of Sec. 4 (Eq. Eq_Model_final1),
 so the network sees the record through that law: its ten features are
 log(1 - omega), (1 - omega) and the eight factors.
 
-Network (one ensemble member): features -> 256 -> 256 -> 256 -> 33, GELU on the
+Network (one ensemble member): features -> 256 -> 256 -> 256 -> 36, GELU on the
 hidden layers (exact form z * Phi(z), Phi the standard normal CDF), identity
-output.  Outputs are the 21 upper-triangle entries of C_bar (row-major, Voigt
-order 11, 22, 33, 12, 23, 31), then K_bar and D_bar as (xx, yy, zz, xy, yz, zx).
-Features and outputs are standardised (per column mean and population standard
-deviation of the training set).
+output.  The physical outputs are the 21 upper-triangle entries of C_bar
+(row-major, Voigt order 11, 22, 33, 12, 23, 31), then K_bar and D_bar as
+(xx, yy, zz, xy, yz, zx).  The network predicts them in a per-block encoding:
+for each block (C, K, D) the log of its Frobenius norm and the block divided by
+that norm (21 + 1, 6 + 1, 6 + 1 = 36 numbers); decoding rescales the predicted
+direction to unit norm.  Relative errors of a block then do not grow where the
+block is small (heavily degraded matrix).  Features and encoded outputs are
+standardised (per column mean and population standard deviation of the training
+set).
 
 Flat parameter layout of one member (row-major [out][in] matrices):
     W1 [256][10], b1 [256], W2 [256][256], b2 [256], W3 [256][256], b3 [256],
-    W4 [33][256], b4 [33]                             (142,881 numbers)
+    W4 [36][256], b4 [36]                             (143,652 numbers)
 
 Arithmetic is FP64 here.  With quant=True the values the GPU kernels round to
 bfloat16 are rounded at the same points (round to nearest even from the FP32
@@ -27,8 +32,8 @@ pass treats each rounding as the identity (straight-through), which is what the
 kernels compute.  With quant=False it is the plain network, whose gradient the
 tests check by finite differences.
 
-Training: mean squared error on standardised outputs over the rows and the 33
-outputs; Adam (Kingma and Ba, ICLR 2015) with bias correction.
+Training: mean squared error on the standardised encoded outputs over the rows
+and the 36 columns; Adam (Kingma and Ba, ICLR 2015) with bias correction.
 
 Ensemble: the prediction is the member mean in physical units; the
 disagreement of a point is the largest over the C, K, D blocks of
@@ -46,7 +51,8 @@ from . import materials as mats
 
 N_FEAT = 10
 HIDDEN = 256
-N_OUT = 33
+N_OUT = 36          # encoded outputs of the network
+N_PHYS = 33         # physical outputs
 LAYERS = ((N_FEAT, HIDDEN), (HIDDEN, HIDDEN), (HIDDEN, HIDDEN), (HIDDEN, N_OUT))
 # Frobenius weights of the output blocks (full symmetric matrix from the stored entries)
 _CW = np.array([1.0 if a == b else 2.0 for a in range(6) for b in range(a, 6)])
@@ -122,7 +128,31 @@ def column_stats(A):
 
 
 def targets(C, K, D):
+    """Physical outputs [n, 33]."""
     return np.concatenate([np.asarray(C, float), np.asarray(K, float), np.asarray(D, float)], axis=1)
+
+
+def encode(Y):
+    """[n, 33] physical -> [n, 36]: per block log ||y||_F, then y / ||y||_F."""
+    Y = np.atleast_2d(np.asarray(Y, dtype=np.float64))
+    out = []
+    for blk in BLOCKS:
+        nrm = np.sqrt((OUT_WEIGHTS[blk] * Y[:, blk] ** 2).sum(axis=1))
+        out += [np.log(nrm)[:, None], Y[:, blk] / nrm[:, None]]
+    return np.concatenate(out, axis=1)
+
+
+def decode(T):
+    """[n, 36] encoded -> [n, 33] physical: exp(log norm) times the direction rescaled to unit norm."""
+    T = np.atleast_2d(np.asarray(T, dtype=np.float64))
+    out, k = [], 0
+    for blk in BLOCKS:
+        w = blk.stop - blk.start
+        d = T[:, k + 1:k + 1 + w]
+        dn = np.sqrt((OUT_WEIGHTS[blk] * d ** 2).sum(axis=1))
+        out.append(np.exp(T[:, k])[:, None] * d / dn[:, None])
+        k += 1 + w
+    return np.concatenate(out, axis=1)
 
 
 def standardise(A, mu, sd, quant):
@@ -133,7 +163,7 @@ def standardise(A, mu, sd, quant):
 
 # ------------------------------------------------------------------ network
 def forward(flat, xhat, quant=True):
-    """Standardised output [n, 33] and the cache the backward pass needs."""
+    """Standardised encoded output [n, 36] and the cache the backward pass needs."""
     Wb = unpack(flat)
     a = np.asarray(xhat, dtype=np.float64)
     cache = []
@@ -175,12 +205,14 @@ def adam_step(w, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def predict(members, x_mu, x_sd, y_mu, y_sd, params, c_sat=1.5, quant=True):
-    """Ensemble mean in physical units [n, 33] and the disagreement [n]."""
+    """Ensemble mean in physical units [n, 33] and the disagreement [n].
+
+    y_mu, y_sd standardise the encoded outputs (36 columns)."""
     xhat = standardise(features(params, c_sat), x_mu, x_sd, quant)
     outs = []
     for flat in members:
         y, _ = forward(flat, xhat, quant)
-        outs.append(y_mu + y_sd * y)
+        outs.append(decode(y_mu + y_sd * y))
     Y = np.stack(outs)                                   # [M, n, 33]
     mean = Y.mean(axis=0)
     if len(members) > 1:

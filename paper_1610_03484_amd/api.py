@@ -286,12 +286,12 @@ class Surrogate:
 
     def set_normalisation(self, rec):
         r = np.ascontiguousarray(np.asarray(rec, dtype=np.float64))
-        if r.size != 86:
-            raise ValueError("the standardisation record has 86 numbers")
+        if r.size != 92:
+            raise ValueError("the standardisation record has 92 numbers")
         L.check(L.lib().chom_mlp_set_normalisation(self._h, _ptr(r)), "chom_mlp_set_normalisation")
 
     def get_normalisation(self):
-        r = np.zeros(86)
+        r = np.zeros(92)
         L.check(L.lib().chom_mlp_get_normalisation(self._h, _ptr(r)), "chom_mlp_get_normalisation")
         return r
 

@@ -10,7 +10,8 @@ namespace mlp {
 constexpr int NF = 10;            // features: log(1 - omega), (1 - omega), 8 factors
 constexpr int FP = 32;            // features padded to one MFMA contraction step
 constexpr int H = 256;            // hidden width
-constexpr int NO = 33;            // outputs: C upper 21, K 6, D 6
+constexpr int NO = 36;            // network outputs: per block (C 21, K 6, D 6) log-norm + direction
+constexpr int NPHYS = 33;         // physical outputs: C upper 21, K 6, D 6
 constexpr int OP = 64;            // outputs padded (contraction of the first backward product)
 constexpr int NB = 256;           // largest minibatch
 constexpr int TRAIN_THREADS = 512;
@@ -24,9 +25,9 @@ constexpr int OFF_W3 = OFF_B2 + H;
 constexpr int OFF_B3 = OFF_W3 + H * H;
 constexpr int OFF_W4 = OFF_B3 + H;
 constexpr int OFF_B4 = OFF_W4 + NO * H;
-constexpr int NPARAM = OFF_B4 + NO;   // 142,881
+constexpr int NPARAM = OFF_B4 + NO;   // 143,652
 
-// Standardisation record (FP64): feature means, feature deviations, output means, output deviations.
+// Standardisation record (FP64): feature means, feature deviations, encoded-output means and deviations.
 constexpr int NORM_XMU = 0;
 constexpr int NORM_XSD = NF;
 constexpr int NORM_YMU = 2 * NF;

@@ -1,5 +1,6 @@
 // Learned surrogate of the homogenisation map: an ensemble of small MLPs
-// (10 features -> 256 -> 256 -> 256 -> 33, GELU hidden layers), trained and
+// (10 features -> 256 -> 256 -> 256 -> 36, GELU hidden layers; the 36 outputs
+// encode C_bar, K_bar, D_bar per block as log-norm and direction), trained and
 // evaluated by the kernels in this file.
 //
 // Features of a record (T, c, t, 8 factors): log(1 - omega), (1 - omega) and the
@@ -60,6 +61,38 @@ __device__ __forceinline__ bool record_features(const double *rec, double c_sat,
         if (!(rec[3 + k] > 0.0)) return false;
     }
     return true;
+}
+
+// Output encoding.  Network column k: 0 log||C||, 1..21 C / ||C||, 22 log||K||,
+// 23..28 K / ||K||, 29 log||D||, 30..35 D / ||D||; ||.|| is the Frobenius norm of
+// the full symmetric matrix (off-diagonal entries of the upper triangle count twice).
+__host__ __device__ constexpr int col_block(int col) { return col < 22 ? 0 : (col < 29 ? 1 : 2); }
+__host__ __device__ constexpr bool col_is_log(int col) { return col == 0 || col == 22 || col == 29; }
+__host__ __device__ constexpr int col_phys(int col) { return col - 1 - col_block(col); }
+__host__ __device__ inline float phys_weight(int p) {
+    if (p < 21) {   // upper triangle row-major: diagonal entries at 0, 6, 11, 15, 18, 20
+        return (p == 0 || p == 6 || p == 11 || p == 15 || p == 18 || p == 20) ? 1.0f : 2.0f;
+    }
+    const int k = p < 27 ? p - 21 : p - 27;
+    return k < 3 ? 1.0f : 2.0f;
+}
+
+// Physical output p (0..32) of record i.
+__device__ __forceinline__ double phys_value(const double *C, const double *K, const double *D, long long i, int p) {
+    return p < 21 ? C[i * 21 + p] : (p < 27 ? K[i * 6 + p - 21] : D[i * 6 + p - 27]);
+}
+
+// Encoded column col of record i (FP64).
+__device__ double encoded_value(const double *C, const double *K, const double *D, long long i, int col) {
+    const int b = col_block(col);
+    const int p0 = b == 0 ? 0 : (b == 1 ? 21 : 27), p1 = b == 0 ? 21 : (b == 1 ? 27 : 33);
+    double s = 0.0;
+    for (int p = p0; p < p1; ++p) {
+        const double v = phys_value(C, K, D, i, p);
+        s += (double)phys_weight(p) * v * v;
+    }
+    const double nrm = sqrt(s);
+    return col_is_log(col) ? log(nrm) : phys_value(C, K, D, i, col_phys(col)) / nrm;
 }
 
 // The phases of a training step are separate (non-inlined) functions: inlined
@@ -189,8 +222,8 @@ __global__ void sync_bf16_kernel(Weights W, int members) {
 }
 
 // ------------------------------------------------------------------ standardisation statistics
-// One workgroup per column: columns 0..NF-1 are features, NF..NF+NO-1 targets
-// (C upper 21, K 6, D 6).  Mean and population deviation in FP64 (1 when zero).
+// One workgroup per column: columns 0..NF-1 are features, NF..NF+NO-1 the
+// encoded outputs.  Mean and population deviation in FP64 (1 when zero).
 __global__ __launch_bounds__(256) void stats_kernel(const double *params, const double *C, const double *K,
                                                    const double *D, long long n, double c_sat, double *norm,
                                                    int *bad) {
@@ -204,10 +237,7 @@ __global__ __launch_bounds__(256) void stats_kernel(const double *params, const 
             ok = record_features(params + i * 11, c_sat, f);
             return f[col];
         }
-        const int o = col - NF;
-        if (o < 21) return C[i * 21 + o];
-        if (o < 27) return K[i * 6 + (o - 21)];
-        return D[i * 6 + (o - 27)];
+        return encoded_value(C, K, D, i, col - NF);
     };
     double s = 0.0;
     for (long long i = threadIdx.x; i < n; i += 256) {
@@ -248,7 +278,8 @@ __global__ __launch_bounds__(256) void stats_kernel(const double *params, const 
     }
 }
 
-// Standardised training rows: xn [n][FP] bfloat16 (zero padded), tn [n][NO] FP32.
+// Standardised training rows: xn [n][FP] bfloat16 (zero padded), tn [n][NO] FP32
+// (encoded outputs).
 __global__ void prepare_kernel(const double *params, const double *C, const double *K, const double *D, long long n,
                                double c_sat, const double *norm, uint16_t *xn, float *tn, int *bad) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -261,7 +292,8 @@ __global__ void prepare_kernel(const double *params, const double *C, const doub
             xn[i * FP + k] = v;
         }
         for (int o = 0; o < NO; ++o) {
-            const double y = o < 21 ? C[i * 21 + o] : (o < 27 ? K[i * 6 + o - 21] : D[i * 6 + o - 27]);
+            const double y = encoded_value(C, K, D, i, o);
+            if (!isfinite(y)) atomicOr(bad, 1);
             tn[i * NO + o] = (float)((y - norm[NORM_YMU + o]) / norm[NORM_YSD + o]);
         }
     }
@@ -496,19 +528,21 @@ __device__ __noinline__ void train_step(const TrainArgs &A, const MemberW &M, un
     const int nb = A.nb;
     const long long i0 = st * nb;
     const int nbe = (int)min((long long)nb, n - i0);
-    // ---- gather the minibatch (rows past nbe are zero)
+    // ---- gather the minibatch (rows past nbe are zero): one shuffled row index per thread
+    __shared__ int s_src[NB];
+    if (tid < NB) s_src[tid] = tid < nbe ? (int)perm_index(i0 + tid, n, pa, pb) : -1;
+    __syncthreads();
     for (int e = tid; e < NB * FP; e += TRAIN_THREADS) {
         const int r = e / FP, k = e - (e / FP) * FP;
-        uint16_t v = 0;
-        if (r < nbe) v = A.xn[perm_index(i0 + r, n, pa, pb) * FP + k];
+        const int src = s_src[r];
+        const uint16_t v = src >= 0 ? A.xn[(long long)src * FP + k] : (uint16_t)0;
         S_XB[r * FP + k] = v;
         S_XBT[k * NB + r] = v;
     }
     for (int e = tid; e < NB * NO; e += TRAIN_THREADS) {
         const int r = e / NO, o = e - (e / NO) * NO;
-        float v = 0.f;
-        if (r < nbe) v = A.tn[perm_index(i0 + r, n, pa, pb) * NO + o];
-        S_TB[e] = v;
+        const int src = s_src[r];
+        S_TB[e] = src >= 0 ? A.tn[(long long)src * NO + o] : 0.f;
     }
     __syncthreads();
     // ---- forward
@@ -652,8 +686,13 @@ __device__ __forceinline__ void infer_hidden(const uint16_t *A, int lda, const u
 __global__ __launch_bounds__(256) void predict_kernel(PredictArgs P) {
     __shared__ __attribute__((aligned(16))) uint16_t xs[PT * XS];
     __shared__ __attribute__((aligned(16))) uint16_t hb[2 * PT * HS];
+    __shared__ float s_ymu[NO], s_ysd[NO];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long p0 = (long long)blockIdx.x * PT;
+    if (tid < NO) {
+        s_ymu[tid] = (float)P.norm[NORM_YMU + tid];
+        s_ysd[tid] = (float)P.norm[NORM_YSD + tid];
+    }
     if (tid < PT) {
         const long long p = p0 + tid;
         double f[NF];
@@ -669,9 +708,9 @@ __global__ __launch_bounds__(256) void predict_kernel(PredictArgs P) {
         }
     }
     __syncthreads();
-    float mean[4][4], m2[4][4];
+    float mean[3][4], m2[3][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) mean[j][q] = m2[j][q] = 0.f;
     uint16_t *h0 = hb, *h1 = hb + PT * HS;
@@ -689,13 +728,33 @@ __global__ __launch_bounds__(256) void predict_kernel(PredictArgs P) {
             zero_acc(acc);
             wave_mma<1, 4, H>(h0 + 16 * wave * HS, HS, M.w4b, H, acc);
             const float cnt = (float)(mem + 1);
+            const int c16 = lane & 15, base = lane & ~15;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int col = 16 * j + (lane & 15);
-                const float b = col < NO ? M.w[OFF_B4 + col] : 0.f;
+            for (int q = 0; q < 4; ++q) {
+                // decode this row: de-standardise, block norms of the directions
+                // (sums over the 16 lanes holding the row), scale by exp(log-norm)
+                float v[3], s[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {   // Welford update over members
-                    const float y = acc[0][j][q] + b;
+                for (int j = 0; j < 3; ++j) {
+                    const int col = 16 * j + c16;
+                    v[j] = 0.f;
+                    if (col < NO) {
+                        v[j] = s_ymu[col] + s_ysd[col] * (acc[0][j][q] + M.w[OFF_B4 + col]);
+                        if (!col_is_log(col)) s[col_block(col)] += phys_weight(col_phys(col)) * v[j] * v[j];
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int off = 8; off > 0; off >>= 1) s[b] += __shfl_xor(s[b], off);
+                const float lnC = __shfl(v[0], base + 0);
+                const float lnK = __shfl(v[1], base + 6);
+                const float lnD = __shfl(v[1], base + 13);
+                const float sc[3] = {expf(lnC) / sqrtf(s[0]), expf(lnK) / sqrtf(s[1]), expf(lnD) / sqrtf(s[2])};
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {   // Welford update over members, physical units
+                    const int col = 16 * j + c16;
+                    const float y = (col < NO && !col_is_log(col)) ? v[j] * sc[col_block(col)] : 0.f;
                     const float dlt = y - mean[j][q];
                     mean[j][q] += dlt / cnt;
                     m2[j][q] += dlt * (y - mean[j][q]);
@@ -708,7 +767,7 @@ __global__ __launch_bounds__(256) void predict_kernel(PredictArgs P) {
     float *smean = reinterpret_cast<float *>(hb);
     float *svar = smean + PT * NO;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 3; ++j) {
         const int col = 16 * j + (lane & 15);
         if (col >= NO) continue;
 #pragma unroll
@@ -722,25 +781,14 @@ __global__ __launch_bounds__(256) void predict_kernel(PredictArgs P) {
     if (tid < PT) {
         const long long p = p0 + tid;
         if (p < P.n) {
-            double y[NO], num[3] = {0, 0, 0}, den[3] = {0, 0, 0};
-            for (int o = 0; o < NO; ++o) {
-                const double sd = P.norm[NORM_YSD + o];
-                y[o] = P.norm[NORM_YMU + o] + sd * (double)smean[tid * NO + o];
-                const double s2 = sd * sd * (double)svar[tid * NO + o];
-                const int blk = o < 21 ? 0 : (o < 27 ? 1 : 2);
-                double w;
-                if (blk == 0) {
-                    int a = 0, k = o;           // o -> (a, b) of the 6x6 upper triangle
-                    while (k >= 6 - a) {
-                        k -= 6 - a;
-                        ++a;
-                    }
-                    w = (k == 0) ? 1.0 : 2.0;
-                } else {
-                    w = ((o - (blk == 1 ? 21 : 27)) < 3) ? 1.0 : 2.0;
-                }
-                num[blk] += w * s2;
-                den[blk] += w * y[o] * y[o];
+            double y[NPHYS], num[3] = {0, 0, 0}, den[3] = {0, 0, 0};
+            for (int col = 0; col < NO; ++col) {
+                if (col_is_log(col)) continue;
+                const int ph = col_phys(col), blk = col_block(col);
+                y[ph] = (double)smean[tid * NO + col];
+                const double w = (double)phys_weight(ph);
+                num[blk] += w * (double)svar[tid * NO + col];
+                den[blk] += w * y[ph] * y[ph];
             }
             double dis = 0.0;
             for (int b = 0; b < 3; ++b) dis = fmax(dis, sqrt(num[b]) / sqrt(den[b]));
@@ -780,8 +828,8 @@ __global__ void gather_kernel(const double *params, const int *idx, int m, doubl
 // Writes compact results back to rows idx[0..m) of C, K, D.
 __global__ void scatter_kernel(const double *c, const double *k, const double *d, const int *idx, int m, double *C,
                                double *K, double *D) {
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m * NO; e += gridDim.x * blockDim.x) {
-        const int j = e / NO, o = e % NO;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m * NPHYS; e += gridDim.x * blockDim.x) {
+        const int j = e / NPHYS, o = e % NPHYS;
         const long long p = idx[j];
         if (o < 21) C[p * 21 + o] = c[(long long)j * 21 + o];
         else if (o < 27) K[p * 6 + o - 21] = k[(long long)j * 6 + o - 21];
@@ -844,7 +892,7 @@ hipError_t launch_gather(const double *params, const int *idx, int m, double *ou
 
 hipError_t launch_scatter(const double *c, const double *k, const double *d, const int *idx, int m, double *C,
                           double *K, double *D, hipStream_t s) {
-    scatter_kernel<<<grid_of((long long)m * NO, 256), 256, 0, s>>>(c, k, d, idx, m, C, K, D);
+    scatter_kernel<<<grid_of((long long)m * NPHYS, 256), 256, 0, s>>>(c, k, d, idx, m, C, K, D);
     return hipGetLastError();
 }
 

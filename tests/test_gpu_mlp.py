@@ -3,9 +3,9 @@
 Tolerances: the kernels and the reference round the same values to bfloat16;
 they differ by FP32 vs FP64 accumulation, which now and then moves a value
 across a bfloat16 rounding boundary (one bfloat16 step, 2^-8 relative, in one
-activation or gradient entry).  Outputs are compared in standardised units
-(one unit = one training-set deviation) with a bound of a few such steps, and
-the mean error with a bound far below one step.
+activation or gradient entry).  Predictions are compared by the relative
+Frobenius error of each block (C, K, D) with a bound of a few such steps times
+the output scales, and the median with a bound far below one step.
 """
 import os
 import time
@@ -37,8 +37,12 @@ def _synthetic_targets(n, seed):
 
 def _norm_from(params, C, K, D):
     x_mu, x_sd = ref.column_stats(ref.features(params))
-    y_mu, y_sd = ref.column_stats(ref.targets(C, K, D))
+    y_mu, y_sd = ref.column_stats(ref.encode(ref.targets(C, K, D)))
     return x_mu, x_sd, y_mu, y_sd
+
+
+def _encoded_targets(C, K, D, y_mu, y_sd):
+    return ref.standardise(ref.encode(ref.targets(C, K, D)), y_mu, y_sd, quant=False)
 
 
 @pytest.mark.parametrize("members", [1, 3])
@@ -58,10 +62,11 @@ def test_prediction_matches_reference(members):
     flats32 = [f.astype(np.float32).astype(np.float64) for f in flats]     # what the library holds
     mean, dis_ref = ref.predict(flats32, x_mu, x_sd, y_mu, y_sd, params, quant=True)
     got = np.concatenate([Cg, Kg, Dg], axis=1)
-    err = np.abs(got - mean) / y_sd
-    print(f"[mlp] predict members={members}: max {err.max():.2e}, mean {err.mean():.2e} (standardised units)")
-    assert err.max() <= 5e-3
-    assert err.mean() <= 2e-4
+    err = ref.block_errors(got, mean)
+    print(f"[mlp] predict members={members}: relative block error max {err.max():.2e}, "
+          f"median {np.median(err):.2e}")
+    assert err.max() <= 2e-3
+    assert np.median(err) <= 1e-4
     if members > 1:
         np.testing.assert_allclose(dis, dis_ref, rtol=2e-2)
         assert dis.min() > 0.0
@@ -84,7 +89,7 @@ def test_gradient_matches_reference():
     loss, g = s.loss_grad(1, params, C, K, D)
     f32 = flat.astype(np.float32).astype(np.float64)
     xhat = ref.standardise(ref.features(params), x_mu, x_sd, quant=True)
-    that = ref.standardise(ref.targets(C, K, D), y_mu, y_sd, quant=False)
+    that = _encoded_targets(C, K, D, y_mu, y_sd)
     loss_ref, g_ref = ref.loss_grad(f32, xhat, that, quant=True)
     assert abs(loss - loss_ref) <= 1e-4 * loss_ref
     starts = np.cumsum([0] + [o * i + o for i, o in ref.LAYERS])
@@ -94,7 +99,7 @@ def test_gradient_matches_reference():
         for part, size in (("W", o * i), ("b", o)):
             a, b = g[k:k + size], g_ref[k:k + size]
             e = np.linalg.norm(a - b) / np.linalg.norm(b)
-            print(f"[mlp] grad {names[len([0]) * 0 + 2 * li + (part == 'b')]}: rel {e:.2e}")
+            print(f"[mlp] grad {names[2 * li + (part == 'b')]}: rel {e:.2e}")
             assert e <= 1e-2, (li, part, e)
             k += size
     assert k == starts[-1]
@@ -118,7 +123,7 @@ def test_adam_step_matches_reference():
     w1 = s.get_weights(0).astype(np.float64)
     f32 = flat.astype(np.float32).astype(np.float64)
     xhat = ref.standardise(ref.features(params), x_mu, x_sd, quant=True)
-    that = ref.standardise(ref.targets(C, K, D), y_mu, y_sd, quant=False)
+    that = _encoded_targets(C, K, D, y_mu, y_sd)
     _, g = ref.loss_grad(f32, xhat, that, quant=True)
     w_ref, _, _ = ref.adam_step(f32, 0 * f32, 0 * f32, g, 1, lr)
     dw, dw_ref = w1 - f32, w_ref - f32
@@ -174,7 +179,7 @@ def trained():
     banner("surrogate: training set of 12^3 periodic RVE solves")
     mesh = generate_plain_weave(12, device="cuda:0")
     rve = RVE(*mesh, ci.BASE_MATERIALS, bc="periodic", precision="fp32_refined", rtol=1e-10, max_iter=50000)
-    ntrain = 1024
+    ntrain = 4096
     params = ci.draw_params(0, ntrain)
     t0 = time.perf_counter()
     C, K, D = [], [], []
@@ -188,7 +193,7 @@ def trained():
     t_solve = (time.perf_counter() - t0) / ntrain
     s = _surrogate(5, seed=11)
     t0 = time.perf_counter()
-    hist = s.train(params, C, K, D, epochs=400, batch=128)
+    hist = s.train(params, C, K, D, epochs=200, batch=128)
     t_train = time.perf_counter() - t0
     print(f"[mlp] {t_solve * 1e3:.1f} ms per training solve; training {t_train:.2f} s; "
           f"loss {hist[:, -1]}")

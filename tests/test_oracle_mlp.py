@@ -13,11 +13,11 @@ from oracle import mlp
 
 
 def test_param_count_and_layout():
-    assert mlp.n_params() == 10 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 33 + 33 == 142881
+    assert mlp.n_params() == 10 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 36 + 36 == 143652
     flat = np.arange(mlp.n_params(), dtype=float)
     Wb = mlp.unpack(flat)
     assert Wb[0][0].shape == (256, 10) and Wb[0][0][0, 1] == 1.0 and Wb[0][1][0] == 2560.0
-    assert Wb[3][0].shape == (33, 256) and Wb[3][1][-1] == mlp.n_params() - 1
+    assert Wb[3][0].shape == (36, 256) and Wb[3][1][-1] == mlp.n_params() - 1
     np.testing.assert_array_equal(mlp.pack(Wb), flat)
 
 
@@ -123,25 +123,55 @@ def test_adam_closed_form_first_steps():
     np.testing.assert_allclose(w2, w1 - lr * mh / (np.sqrt(vh) + 1e-8), rtol=1e-13)
 
 
+def test_encoding_round_trip_and_scale_invariance():
+    rng = np.random.default_rng(4)
+    Y = rng.standard_normal((9, 33)) + 3.0
+    T = mlp.encode(Y)
+    assert T.shape == (9, 36)
+    np.testing.assert_allclose(mlp.decode(T), Y, rtol=1e-14)
+    # scaling a block moves only its log-norm column
+    Y2 = Y.copy()
+    Y2[:, :21] *= 7.0
+    T2 = mlp.encode(Y2)
+    np.testing.assert_allclose(T2[:, 0], T[:, 0] + np.log(7.0), rtol=1e-14)
+    np.testing.assert_allclose(T2[:, 1:], T[:, 1:], rtol=1e-13)
+    # decoding renormalises the direction: scaling it changes nothing
+    T3 = T.copy()
+    T3[:, 1:22] *= 1.3
+    np.testing.assert_allclose(mlp.decode(T3), Y, rtol=1e-14)
+    # unit C block: ||C||_F = sqrt(6) for the identity
+    eye = np.zeros((1, 33))
+    eye[0, [0, 6, 11, 15, 18, 20]] = 1.0
+    eye[0, 21:24] = 1.0
+    eye[0, 27:30] = 1.0
+    assert abs(mlp.encode(eye)[0, 0] - 0.5 * math.log(6.0)) < 1e-15
+
+
 def test_ensemble_mean_and_disagreement():
     p = ci.draw_params(12, 7)
     zeros = np.zeros(mlp.n_params())
-    b_a, b_b = zeros.copy(), zeros.copy()
-    b_a[-33:] = 1.0
-    b_b[-33:] = -1.0
     mu = np.zeros(10)
     sd = np.ones(10)
-    ymu = np.linspace(1.0, 3.0, 33)
-    ysd = np.full(33, 0.01)
+    phys = np.linspace(1.0, 3.0, 33)
+    enc = mlp.encode(phys[None, :])[0]
     # zero weights: the output is the last bias, whatever the input
-    mean, dis = mlp.predict([b_a, b_b], mu, sd, ymu, ysd, p)
-    np.testing.assert_allclose(mean, np.tile(ymu, (7, 1)), rtol=1e-15)
-    # two members at ymu +- 0.01: sample std sqrt(2) * 0.01 in every entry
-    w = mlp.OUT_WEIGHTS
-    expect = max(np.sqrt((w[b] * 2e-4).sum()) / np.sqrt((w[b] * ymu[b] ** 2).sum()) for b in mlp.BLOCKS)
-    np.testing.assert_allclose(dis, expect, rtol=1e-12)
-    same, dis0 = mlp.predict([b_a, b_a], mu, sd, ymu, ysd, p)
-    assert np.all(dis0 == 0.0)
+    b_a = zeros.copy()
+    b_a[-36:] = 0.0
+    y_sd = np.full(36, 0.01)
+    mean, dis = mlp.predict([b_a, b_a], mu, sd, enc, y_sd, p)
+    np.testing.assert_allclose(mean, np.tile(phys, (7, 1)), rtol=1e-13)
+    assert np.all(dis == 0.0)
+    # two members whose log-norm outputs differ by +-h: the blocks scale by exp(+-h*0.01)
+    h = 1.0
+    b_p, b_m = zeros.copy(), zeros.copy()
+    for k in (0, 22, 29):
+        b_p[-36 + k] = h
+        b_m[-36 + k] = -h
+    mean, dis = mlp.predict([b_p, b_m], mu, sd, enc, y_sd, p)
+    s = 0.01 * h
+    np.testing.assert_allclose(mean, np.tile(phys * math.cosh(s), (7, 1)), rtol=1e-13)
+    # sample std of {e^s, e^-s} x is sqrt(2)|sinh(s)| x; relative to the mean cosh(s) x
+    np.testing.assert_allclose(dis, math.sqrt(2.0) * math.sinh(s) / math.cosh(s), rtol=1e-10)
 
 
 def test_block_errors_closed_form():
