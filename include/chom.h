@@ -357,6 +357,24 @@ int chom_material_constants(const chom_materials *mat, const chom_params *params
 int chom_element_apply_host(int32_t ncomp, const double *grad_lam, double vol, const double *axis,
                             const double *inv5, const double *u, double *y);
 
+/* Tables of the order-p hierarchic basis (p = 3 or 4) that the order-p kernels
+ * use, for inspection: *n_e local functions (20 or 35) and *m = dim P_{p-1};
+ * S [9][n_e][n_e] = (1/|e|) int d_k phi_i d_l phi_j (k, l over the reference
+ * coordinates xi_1..3 = lam_1..3, entry (k*3 + l)), as the kernels form it from
+ * their derivative tables; W [n_e] = (1/|e|) int phi_i; Wd [3][n_e] =
+ * (1/|e|) int d phi_i / d xi_k; offsets [6][n_e][3] = lattice point of each local
+ * DOF per Kuhn tet type, in units of 1/p cell from the cell origin.  Local order:
+ * vertices, edges (01, 02, 03, 12, 13, 23; p-1 each), faces (omitting vertex
+ * 0, 1, 2, 3; (p-1)(p-2)/2 each), interior.  Functions: see hp_tables.cpp of the
+ * library sources (paper Sec. 1, Sec. 7 name only the hierarchic family).  Any
+ * output pointer may be NULL.  Errors: CHOM_EINVAL (order). */
+int chom_basis_tables_host(int32_t order, int32_t *n_e, int32_t *m, double *S, double *W, double *Wd,
+                           int32_t *offsets);
+
+/* Values of the order-p basis functions (p = 3, 4) at barycentric point lam [4]
+ * (out [n_e]).  Errors: CHOM_EINVAL. */
+int chom_basis_eval_host(int32_t order, const double *lam, double *out);
+
 /* Library version string. */
 const char *chom_version(void);
 

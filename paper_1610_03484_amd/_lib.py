@@ -104,6 +104,9 @@ SIGNATURES = {
                                              ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                              ct.c_void_p, ct.POINTER(ct.c_int64)]),
     "chom_mlp_destroy": (None, [ct.c_void_p]),
+    "chom_basis_tables_host": (ct.c_int, [ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.c_void_p,
+                                          ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "chom_basis_eval_host": (ct.c_int, [ct.c_int32, ct.c_void_p, ct.c_void_p]),
 }
 
 _lib = None

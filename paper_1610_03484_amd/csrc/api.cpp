@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "hp.h"
 #include "internal.h"
 
 namespace chom {
@@ -1154,6 +1155,30 @@ int chom_element_apply_host(int32_t ncomp, const double *grad_lam, double vol, c
         for (int k = 0; k < 10; ++k) uu[k][0] = u[k];
         p2_apply<double, 1>(g, vol, a, m, uu, yy);
         for (int k = 0; k < 10; ++k) y[k] = yy[k][0];
+    }
+    return CHOM_OK;
+}
+
+int chom_basis_tables_host(int32_t order, int32_t *n_e, int32_t *m, double *S, double *W, double *Wd,
+                           int32_t *offsets) {
+    chom::hp::HostTables t;
+    if (!chom::hp::build_tables(order, t)) {
+        set_error("chom_basis_tables_host: order must be 3 or 4");
+        return CHOM_EINVAL;
+    }
+    if (n_e) *n_e = t.ne;
+    if (m) *m = t.m;
+    if (S) std::copy(t.S.begin(), t.S.end(), S);
+    if (W) std::copy(t.W.begin(), t.W.end(), W);
+    if (Wd) std::copy(t.Wd.begin(), t.Wd.end(), Wd);
+    if (offsets) std::copy(t.off.begin(), t.off.end(), offsets);
+    return CHOM_OK;
+}
+
+int chom_basis_eval_host(int32_t order, const double *lam, double *out) {
+    if (!lam || !out || !chom::hp::eval_basis(order, lam, out)) {
+        set_error("chom_basis_eval_host: order must be 3 or 4 and pointers non-null");
+        return CHOM_EINVAL;
     }
     return CHOM_OK;
 }

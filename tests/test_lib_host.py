@@ -237,3 +237,69 @@ def test_surrogate_needs_a_device(L):
     h = ct.c_void_p()
     assert L.lib().chom_mlp_create(None, ct.byref(h)) == L.CHOM_EDEVICE
     assert not h.value
+
+
+def _hp_tables(L, p):
+    ne, m = ct.c_int32(), ct.c_int32()
+    assert L.lib().chom_basis_tables_host(p, ct.byref(ne), ct.byref(m), None, None, None, None) == 0
+    ne, m = ne.value, m.value
+    S = np.zeros((9, ne, ne))
+    W = np.zeros(ne)
+    Wd = np.zeros((3, ne))
+    off = np.zeros((6, ne, 3), dtype=np.int32)
+    assert L.lib().chom_basis_tables_host(p, None, None, S.ctypes.data, W.ctypes.data, Wd.ctypes.data,
+                                          off.ctypes.data) == 0
+    return ne, m, S, W, Wd, off
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_order_p_tables_match_oracle_lagrange(L, p):
+    """The library's order-p hierarchic tables equal the oracle's Lagrange tables under the
+    change of basis phi_hier = T phi_lagrange, T[i, m] = phi_hier_i(node_m) (same P_p space)."""
+    from oracle import lagrange
+    ne, m, S, W, Wd, _ = _hp_tables(L, p)
+    assert ne == (p + 1) * (p + 2) * (p + 3) // 6 and m == p * (p + 1) * (p + 2) // 6
+    ref = lagrange.reference_tables(p)
+    nodes = ref["nodes"] / p                                  # barycentric coordinates of the nodes
+    T = np.zeros((ne, len(nodes)))
+    for k, lam in enumerate(nodes):
+        v = np.zeros(ne)
+        assert L.lib().chom_basis_eval_host(p, np.ascontiguousarray(lam).ctypes.data, v.ctypes.data) == 0
+        T[:, k] = v
+    assert np.linalg.matrix_rank(T) == ne                      # a basis of P_p
+    cxi = np.zeros((3, 4))
+    for k in range(3):
+        cxi[k, k + 1], cxi[k, 0] = 1.0, -1.0                   # d/dxi_k = d/dlam_k - d/dlam_0
+    for k in range(3):
+        for l in range(3):
+            Sl = np.einsum("a,b,abij->ij", cxi[k], cxi[l], ref["S"])
+            np.testing.assert_allclose(S[3 * k + l], T @ Sl @ T.T, rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(Wd[k], T @ (cxi[k] @ ref["Wd"]), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(W, T @ ref["W"], rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_order_p_lattice_points_number_the_dofs(L, p):
+    """Local DOFs mapped to the (p n + 1)^3 lattice: vertices at p x grid points, every
+    point reached (the lattice index is a DOF numbering), edge/face/interior points
+    inside their entity."""
+    ne, _, _, _, _, off = _hp_tables(L, p)
+    n = 2
+    pts = set()
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                for t in range(6):
+                    for q in range(ne):
+                        pts.add(tuple(p * np.array([i, j, k]) + off[t, q]))
+    assert len(pts) == (p * n + 1) ** 3
+    perm = [(0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1)]
+    for t, (a, b) in enumerate(perm):
+        v = np.zeros((4, 3), int)
+        v[1, a] = v[2, a] = v[2, b] = p
+        v[3] = p
+        np.testing.assert_array_equal(off[t, :4], v)
+        edges = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+        for e, (x, y) in enumerate(edges):
+            for s in range(p - 1):
+                np.testing.assert_array_equal(off[t, 4 + e * (p - 1) + s], v[x] + (s + 1) * (v[y] - v[x]) // p)
