@@ -161,6 +161,9 @@ struct chom_rve {
     DevBuf<double> geo64;
     DevBuf<float> geo32;
     DevBuf<double> rows;
+    DevBuf<int> hoff;                                    // orders 3, 4: basis tables
+    DevBuf<double> hW, hWd, hSd, hDA64, hDB64;
+    DevBuf<float> hDA32, hDB32;
     std::unique_ptr<chom_batch> self;   // batch of this RVE alone (chom_homogenise)
     int self_size = 0;
     ~chom_rve();
@@ -236,7 +239,7 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
         P.qoff = qoff;
         voff += G.npts * R * C;
         doff += G.npts;
-        qoff += (long long)G.ntiles * BOXPTS * R * C;
+        qoff += G.p == 2 ? (long long)G.ntiles * BOXPTS * R * C : G.npts * R * C;
         max_pts = std::max(max_pts, G.npts);
         max_tets = std::max(max_tets, 6LL * G.n * G.n * G.n);
         max_tiles = std::max(max_tiles, G.ntiles);
@@ -254,6 +257,8 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     L.nr = nr == 0 ? 0 : (nr == 1 ? 1 : 4);
     L.rg = rg;
     L.max_tets = max_tets;
+    L.order = B->distinct[hp[0].geo]->geo.p;
+    L.total_q = qoff;
     W.nwg_gram = (int)std::min<long long>(std::max<long long>((max_pts + 4095) / 4096, 1), 256);
     W.nwg_avg = (int)std::min<long long>(std::max<long long>((max_tets + 1023) / 1024, 1), 256);
     const bool fp32 = B->opt.precision == CHOM_FP32_REFINED;
@@ -321,7 +326,7 @@ static hipError_t cg_iteration(ClassWS<C, R> &W, T *x, T *r, T *z, T *p, T *q, c
     const Launch &L = W.L;
     hipError_t e;
     if ((e = launch_cg_dir<T, C, R>(L, r, z, p, minv, W.ycoef.p, W.cols.p, W.active.p, s)) != hipSuccess) return e;
-    if ((e = launch_operator<T, C, R>(L.geos, L.probs, L.nprob, L.max_tiles, L.rg, p, q, W.partial.p, W.active.p, s)) != hipSuccess) return e;
+    if ((e = launch_operator<T, C, R>(L, L.nprob, L.rg, p, q, W.partial.p, W.active.p, s)) != hipSuccess) return e;
     if ((e = launch_finish_alpha<C, R>(L, W.partial.p, W.cols.p, s)) != hipSuccess) return e;
     if ((e = launch_cg_update<T, C, R>(L, x, r, z, p, q, minv, W.cols.p, W.partial.p, W.active.p, s)) != hipSuccess) return e;
     return launch_finish_beta<C, R>(L, W.partial.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 0, rtol2, use_init, nullptr, s);
@@ -420,7 +425,7 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
             CHOM_TRY((pcg<float, C, R>(B, W, W.graph32, W.r32.p, W.xf.p, W.rf.p, W.zf.p, W.pf.p, W.qf.p, W.minv32.p,
                                        W.ginv32.p, irtol2, 1, W.cols_outer.p)));
             CHOM_HIP(launch_axpy_x64(W.total_vals, W.x64.p, W.xf.p, s));
-            CHOM_HIP((launch_operator<double, C, R>(L.geos, L.probs, nprob, L.max_tiles, L.rg, W.x64.p, W.q64.p,
+            CHOM_HIP((launch_operator<double, C, R>(L, nprob, L.rg, W.x64.p, W.q64.p,
                                                     W.partial.p, nullptr, s)));
             CHOM_HIP((launch_residual64<C, R>(L, W.b.p, W.q64.p, W.r64.p, W.r32.p, s)));
         }
@@ -450,10 +455,10 @@ static int time_op(chom_batch *B, ClassWS<C, R> &W, const T *x, T *y, int rg, in
     hipEvent_t e0, e1;
     CHOM_HIP(hipEventCreate(&e0));
     CHOM_HIP(hipEventCreate(&e1));
-    CHOM_HIP((launch_operator<T, C, R>(L.geos, L.probs, L.nprob, L.max_tiles, rg, x, y, W.partial.p, nullptr, s)));
+    CHOM_HIP((launch_operator<T, C, R>(L, L.nprob, rg, x, y, W.partial.p, nullptr, s)));
     CHOM_HIP(hipEventRecord(e0, s));
     for (int i = 0; i < reps; ++i)
-        CHOM_HIP((launch_operator<T, C, R>(L.geos, L.probs, L.nprob, L.max_tiles, rg, x, y, W.partial.p, nullptr, s)));
+        CHOM_HIP((launch_operator<T, C, R>(L, L.nprob, rg, x, y, W.partial.p, nullptr, s)));
     CHOM_HIP(hipEventRecord(e1, s));
     CHOM_HIP(hipEventSynchronize(e1));
     float t = 0.f;
@@ -593,6 +598,11 @@ static int batch_init(chom_batch *B, chom_rve *const *rves, int n, const chom_op
             B->geo_of.push_back(it->second);
         }
     }
+    for (auto *r : B->distinct)
+        if (r->order != B->distinct[0]->order) {
+            set_error("chom_batch_create: all RVEs of a batch must have the same order");
+            return CHOM_EINVAL;
+        }
     B->opt = *opt;
     if (B->opt.hip_stream) {
         B->stream = (hipStream_t)B->opt.hip_stream;
@@ -854,8 +864,8 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
         set_error("chom_rve_create: bc_type must be 0 (Dirichlet), 1 (periodic) or 2 (Neumann)");
         return CHOM_EINVAL;
     }
-    if (order != 2) {
-        set_error("chom_rve_create: only order 2 is supported by this build");
+    if (order < 2 || order > 4) {
+        set_error("chom_rve_create: order must be 2, 3 or 4");
         return CHOM_EINVAL;
     }
     chom_options o;
@@ -982,7 +992,9 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
     G.n = n;
     G.bc = bc;
     G.uniform = uniform ? 1 : 0;
-    G.Lw = (bc == CHOM_BC_PERIODIC) ? 2 * n : 2 * n + 1;
+    G.p = order;
+    G.L = order * n;
+    G.Lw = (bc == CHOM_BC_PERIODIC) ? G.L : G.L + 1;
     G.npts = (long long)G.Lw * G.Lw * G.Lw;
     G.volume = (mesh->hi[0] - mesh->lo[0]) * (mesh->hi[1] - mesh->lo[1]) * (mesh->hi[2] - mesh->lo[2]);
     G.nrow = (bc == CHOM_BC_DIRICHLET) ? 0 : (bc == CHOM_BC_PERIODIC ? 1 : 4);
@@ -990,6 +1002,10 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
     G.tiles_y = (n + TY - 1) / TY;
     G.tiles_z = (n + TZ - 1) / TZ;
     G.ntiles = G.tiles_x * G.tiles_y * G.tiles_z;
+    if (order != 2) {   // element batches of the order-3/4 operator
+        G.tiles_x = G.tiles_y = G.tiles_z = 0;
+        G.ntiles = (int)((nt + hp::OP_TETS - 1) / hp::OP_TETS);
+    }
     for (int t = 0; t < 6; ++t) {
         int p0, p1;
         kuhn_perm(t, p0, p1);
@@ -1037,6 +1053,51 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
     G.geo64 = uniform ? nullptr : R->geo64.p;
     G.geo32 = uniform ? nullptr : R->geo32.p;
     G.rows = R->rows.p;
+    if (order != 2) {
+        hp::HostTables tb;
+        if (!hp::build_tables(order, tb)) {
+            set_error("chom_rve_create: order-" + std::to_string(order) + " tables failed");
+            return CHOM_EINVAL;
+        }
+        const int ne = tb.ne, m3 = 3 * tb.m;
+        int MA, KA, MB, KB;
+        if (order == 3) {
+            MA = hp::Shape<3>::MA; KA = hp::Shape<3>::KA; MB = hp::Shape<3>::MB; KB = hp::Shape<3>::KB;
+        } else {
+            MA = hp::Shape<4>::MA; KA = hp::Shape<4>::KA; MB = hp::Shape<4>::MB; KB = hp::Shape<4>::KB;
+        }
+        std::vector<double> DA((size_t)MA * KA, 0.0), DB((size_t)MB * KB, 0.0);
+        for (int r = 0; r < m3; ++r)
+            for (int j = 0; j < ne; ++j) {
+                DA[(size_t)r * KA + j] = tb.D[(size_t)r * ne + j];
+                DB[(size_t)j * KB + r] = tb.D[(size_t)r * ne + j];
+            }
+        std::vector<float> DA32(DA.begin(), DA.end()), DB32(DB.begin(), DB.end());
+        CHOM_HIP(R->hoff.ensure(tb.off.size()));
+        CHOM_HIP(R->hW.ensure(tb.W.size()));
+        CHOM_HIP(R->hWd.ensure(tb.Wd.size()));
+        CHOM_HIP(R->hSd.ensure(tb.Sd.size()));
+        CHOM_HIP(R->hDA64.ensure(DA.size()));
+        CHOM_HIP(R->hDB64.ensure(DB.size()));
+        CHOM_HIP(R->hDA32.ensure(DA.size()));
+        CHOM_HIP(R->hDB32.ensure(DB.size()));
+        CHOM_HIP(hipMemcpy(R->hoff.p, tb.off.data(), sizeof(int) * tb.off.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(R->hW.p, tb.W.data(), sizeof(double) * tb.W.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(R->hWd.p, tb.Wd.data(), sizeof(double) * tb.Wd.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(R->hSd.p, tb.Sd.data(), sizeof(double) * tb.Sd.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(R->hDA64.p, DA.data(), sizeof(double) * DA.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(R->hDB64.p, DB.data(), sizeof(double) * DB.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(R->hDA32.p, DA32.data(), sizeof(float) * DA32.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(R->hDB32.p, DB32.data(), sizeof(float) * DB32.size(), hipMemcpyHostToDevice));
+        G.hoff = R->hoff.p;
+        G.hW = R->hW.p;
+        G.hWd = R->hWd.p;
+        G.hSd = R->hSd.p;
+        G.hDA64 = R->hDA64.p;
+        G.hDB64 = R->hDB64.p;
+        G.hDA32 = R->hDA32.p;
+        G.hDB32 = R->hDB32.p;
+    }
     CHOM_HIP(launch_element_setup(G, dc.p, nullptr, dph.p, dax.p, R->elem64.p, R->elem32.p, G.geo64 ? R->geo64.p : nullptr,
                                   G.geo32 ? R->geo32.p : nullptr, dbad.p, s));
     CHOM_HIP(launch_rows(G, R->rows.p, s));

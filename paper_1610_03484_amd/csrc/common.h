@@ -41,8 +41,14 @@ struct Geo {
     const double *rows;     // per lattice point: int grad(phi) (3) and int phi (1)
     int nrow;               // projection rows per component: 0 (D), 1 (P), 4 (N)
     int tiles_x, tiles_y, tiles_z;
-    int ntiles;
-    int pad_;
+    int ntiles;       // order 2: operator tiles; orders 3, 4: operator element batches
+    int p;            // polynomial order
+    int L;            // lattice points per side minus one: p n
+    // orders 3, 4: basis tables (see hp_tables.cpp)
+    const int *hoff;                 // [6][ne][3] lattice offset of each local DOF per tet type
+    const double *hW, *hWd, *hSd;    // [ne], [3][ne], [9][ne]
+    const double *hDA64, *hDB64;     // padded [D_1; D_2; D_3] and its transpose
+    const float *hDA32, *hDB32;
 };
 
 // Per-problem descriptor (one parameter record x one physics of one RVE).
@@ -279,10 +285,10 @@ template <typename T> __device__ inline const T *prob_mat(const Prob &P, int pha
 template <> __device__ inline const double *prob_mat<double>(const Prob &P, int phase) { return P.mat64[phase ? 1 : 0]; }
 template <> __device__ inline const float *prob_mat<float>(const Prob &P, int phase) { return P.mat32[phase ? 1 : 0]; }
 
-// Lattice index of DOF point (X, Y, Z) in [0, 2n]^3 for the stored layout.
+// Lattice index of DOF point (X, Y, Z) in [0, p n]^3 for the stored layout.
 __device__ inline long long lat_index(const Geo &G, int X, int Y, int Z) {
     if (G.bc == 1) {
-        const int m = 2 * G.n;
+        const int m = G.L;
         if (X == m) X = 0;
         if (Y == m) Y = 0;
         if (Z == m) Z = 0;
@@ -291,7 +297,7 @@ __device__ inline long long lat_index(const Geo &G, int X, int Y, int Z) {
 }
 
 __device__ inline bool dirichlet_boundary(const Geo &G, int X, int Y, int Z) {
-    const int m = 2 * G.n;
+    const int m = G.L;
     return G.bc == 0 && (X == 0 || Y == 0 || Z == 0 || X == m || Y == m || Z == m);
 }
 
@@ -323,6 +329,12 @@ __device__ inline int tile_cands(int X, int T2, int ntiles, int m2, bool per, in
 // group, R / rg groups.
 template <typename T, int C, int R>
 __device__ inline void gather_tiles_col(const Geo &G, const T *qt, int rg, int X, int Y, int Z, int w, double out[C]) {
+    if (G.p != 2) {   // orders 3, 4: the operator output is a plain vector [load case][point][C]
+        const long long off = ((long long)w * G.npts + lat_index(G, X, Y, Z)) * C;
+#pragma unroll
+        for (int v = 0; v < C; ++v) out[v] = (double)qt[off + v];
+        return;
+    }
     const int ng = R / rg, rcg = rg * C;
     const int grp = w / rg, rr = w - grp * rg;
     const bool per = (G.bc == 1);

@@ -101,7 +101,12 @@ __global__ void average_finish_kernel(const Geo *geos, const Prob *probs, int nw
 template <int C, int R>
 hipError_t launch_average(const Launch &L, const double *x64, double *partial, int nwg, double *out, hipStream_t s) {
     dim3 grid(nwg, L.nprob);
-    average_kernel<C, R><<<grid, 256, 0, s>>>(L.geos, L.probs, x64, partial);
+    if (L.order != 2) {
+        const hipError_t e = launch_average_partial_hp<C, R>(L, x64, partial, nwg, s);
+        if (e != hipSuccess) return e;
+    } else {
+        average_kernel<C, R><<<grid, 256, 0, s>>>(L.geos, L.probs, x64, partial);
+    }
     average_finish_kernel<C, R><<<L.nprob, FIN_BS, 0, s>>>(L.geos, L.probs, nwg, partial, out);
     return hipGetLastError();
 }

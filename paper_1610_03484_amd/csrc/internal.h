@@ -33,6 +33,8 @@ struct Launch {
     int rg;               // load cases per operator workgroup
     long long max_tets;   // largest tet count among the problems
     double *sums;         // reduced partial sums, [nprob][R * (2 + C * 4)]
+    int order;            // polynomial order of every problem of the class
+    long long total_q;    // values of the operator output of the class
 };
 
 // ------------------------------------------------------------------ launchers
@@ -56,7 +58,7 @@ template <int C, int R>
 hipError_t launch_rhs(const Launch &L, long long total_vals, double *b, ColState *cols, hipStream_t s);
 
 template <typename T, int C, int R>
-hipError_t launch_operator(const Geo *geos, const Prob *probs, int nprob, int max_tiles, int rg, const T *x, T *y,
+hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y,
                            double *partial_pq, const int *prob_active, hipStream_t s);
 
 template <typename T, int C, int R>
@@ -89,6 +91,16 @@ hipError_t launch_average(const Launch &L, const double *x64, double *partial, i
                           hipStream_t s);
 
 void set_error(const std::string &msg);
+
+// orders 3, 4 (hp.hip)
+hipError_t launch_rows_hp(const Geo &G, double *rows, hipStream_t s);
+template <int C> hipError_t launch_diag_hp(const Launch &L, double *diag, hipStream_t s);
+template <int C, int R> hipError_t launch_rhs_hp(const Launch &L, double *b, ColState *cols, hipStream_t s);
+template <int C, int R>
+hipError_t launch_average_partial_hp(const Launch &L, const double *x64, double *partial, int nwg, hipStream_t s);
+template <typename T, int C, int R>
+hipError_t launch_operator_hp(const Launch &L, int nprob, int rg, const T *x, T *y, double *partial_pq,
+                              const int *prob_active, hipStream_t s);
 
 // Homogenises `batch` records given in host memory with the RVE's own batch
 // workspace, whatever the RVE's pointer convention (outputs in host memory too).

@@ -179,8 +179,12 @@ static hipError_t launch_rg(const Geo *geos, const Prob *probs, int nprob, int m
 }
 
 template <typename T, int C, int R>
-hipError_t launch_operator(const Geo *geos, const Prob *probs, int nprob, int max_tiles, int rg, const T *x, T *y,
-                           double *partial_pq, const int *prob_active, hipStream_t s) {
+hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y, double *partial_pq,
+                           const int *prob_active, hipStream_t s) {
+    if (L.order != 2) return launch_operator_hp<T, C, R>(L, nprob, rg, x, y, partial_pq, prob_active, s);
+    const Geo *geos = L.geos;
+    const Prob *probs = L.probs;
+    const int max_tiles = L.max_tiles;
     if constexpr (C == 3) {
         switch (rg) {
             case 1: return launch_rg<T, C, R, 1>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
@@ -195,9 +199,9 @@ hipError_t launch_operator(const Geo *geos, const Prob *probs, int nprob, int ma
     }
 }
 
-template hipError_t launch_operator<double, 3, 6>(const Geo *, const Prob *, int, int, int, const double *, double *, double *, const int *, hipStream_t);
-template hipError_t launch_operator<float, 3, 6>(const Geo *, const Prob *, int, int, int, const float *, float *, double *, const int *, hipStream_t);
-template hipError_t launch_operator<double, 1, 3>(const Geo *, const Prob *, int, int, int, const double *, double *, double *, const int *, hipStream_t);
-template hipError_t launch_operator<float, 1, 3>(const Geo *, const Prob *, int, int, int, const float *, float *, double *, const int *, hipStream_t);
+template hipError_t launch_operator<double, 3, 6>(const Launch &, int, int, const double *, double *, double *, const int *, hipStream_t);
+template hipError_t launch_operator<float, 3, 6>(const Launch &, int, int, const float *, float *, double *, const int *, hipStream_t);
+template hipError_t launch_operator<double, 1, 3>(const Launch &, int, int, const double *, double *, double *, const int *, hipStream_t);
+template hipError_t launch_operator<float, 1, 3>(const Launch &, int, int, const float *, float *, double *, const int *, hipStream_t);
 
 }  // namespace chom

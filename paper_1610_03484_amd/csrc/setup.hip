@@ -131,6 +131,7 @@ __global__ void rows_kernel(Geo G, double *rows) {
 hipError_t launch_rows(const Geo &G, double *rows, hipStream_t s) {
     hipError_t err = hipMemsetAsync(rows, 0, sizeof(double) * 4 * G.npts, s);
     if (err != hipSuccess) return err;
+    if (G.p != 2) return launch_rows_hp(G, rows, s);
     const long long nt = 6LL * G.n * G.n * G.n;
     rows_kernel<<<grid_for(nt, 256), 256, 0, s>>>(G, rows);
     return hipGetLastError();
@@ -259,7 +260,12 @@ hipError_t launch_precond(const Launch &L, long long total_pts, double *diag, do
     hipError_t err = hipMemsetAsync(diag, 0, sizeof(double) * MS * total_pts, s);
     if (err != hipSuccess) return err;
     dim3 grid(grid_for(L.max_tets, 256, 2048), L.nprob);
-    diag_kernel<C><<<grid, 256, 0, s>>>(L.geos, L.probs, diag);
+    if (L.order != 2) {
+        err = launch_diag_hp<C>(L, diag, s);
+        if (err != hipSuccess) return err;
+    } else {
+        diag_kernel<C><<<grid, 256, 0, s>>>(L.geos, L.probs, diag);
+    }
     invert_diag_kernel<C><<<grid_for(total_pts, 256), 256, 0, s>>>(total_pts, diag, minv64, minv32);
     return hipGetLastError();
 }
@@ -488,6 +494,7 @@ template <int C, int R>
 hipError_t launch_rhs(const Launch &L, long long total_vals, double *b, ColState *cols, hipStream_t s) {
     hipError_t err = hipMemsetAsync(b, 0, sizeof(double) * total_vals, s);
     if (err != hipSuccess) return err;
+    if (L.order != 2) return launch_rhs_hp<C, R>(L, b, cols, s);
     dim3 grid(grid_for(L.max_tets, 256, 2048), L.nprob);
     rhs_kernel<C, R><<<grid, 256, 0, s>>>(L.geos, L.probs, b, cols);
     return hipGetLastError();

@@ -1,0 +1,90 @@
+"""GPU parity at orders 3 and 4 (hierarchic tables, matrix-core element operator)
+against the CPU FP64 oracle (Lagrange P3/P4, exact integration).
+
+Sizes: n = 2 and 3 cells per side (up to 13^3 lattice points at p = 4); the
+operator works on batches of 16 tets, so both sizes end in a ragged batch
+(6 n^3 = 48 and 162 tets).  Tolerances as at order 2: FP64 path 1e-9, FP32
+operator with FP64 refinement 1e-6 (relative Frobenius error of each block).
+"""
+import numpy as np
+import pytest
+
+import chom_inputs as ci
+from oracle import fem as ofem, mesh as omesh
+
+from gpu_util import banner, rel, require_gpu, upper21, upper6
+
+pytestmark = pytest.mark.gpu
+
+BC_ID = {"dirichlet": ofem.BC_DIRICHLET, "periodic": ofem.BC_PERIODIC, "neumann": ofem.BC_NEUMANN}
+_CACHE = {}
+
+
+def oracle_result(n, p, bc, params, key):
+    k = (n, p, bc, key)
+    if k not in _CACHE:
+        c, t, ph, ax = omesh.plain_weave(n)
+        _CACHE[k] = ofem.homogenise(c, t, ph, ax, p, BC_ID[bc], ci.BASE_MATERIALS, params)
+    return _CACHE[k]
+
+
+def gpu_rve(n, bc, p, **opts):
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    coords, tets, phase, axis = generate_plain_weave(n, device="cuda")
+    return RVE(coords, tets, phase, axis, ci.BASE_MATERIALS, bc=bc, order=p, **opts)
+
+
+def errors(C, K, D, ref):
+    return (rel(C, upper21(ref["C"])), rel(K, upper6(ref["K"])), rel(D, upper6(ref["D"])))
+
+
+@pytest.mark.parametrize("p", [3, 4])
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic", "neumann"])
+@pytest.mark.parametrize("n", [2, 3])
+def test_order_p_fp64_matches_oracle(p, bc, n):
+    require_gpu()
+    params = ci.draw_params(13, 1)[0]
+    banner(f"order {p} fp64 n={n} bc={bc}")
+    rve = gpu_rve(n, bc, p, precision="fp64", rtol=1e-13, max_iter=20000)
+    C, K, D, rep = rve.homogenise(params[None])
+    ref = oracle_result(n, p, bc, params, "deg13")
+    eC, eK, eD = errors(C[0], K[0], D[0], ref)
+    banner(f"  errors C={eC:.2e} K={eK:.2e} D={eD:.2e} iters={rep[0]['iters']}")
+    assert rep[0]["status"] == 0
+    assert max(eC, eK, eD) < 1e-9
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_order_p_fp32_refined_matches_oracle(p):
+    require_gpu()
+    params = ci.draw_params(14, 1)[0]
+    banner(f"order {p} fp32 refined n=3 periodic")
+    rve = gpu_rve(3, "periodic", p, precision="fp32_refined", rtol=1e-10, max_iter=20000)
+    C, K, D, rep = rve.homogenise(params[None])
+    ref = oracle_result(3, p, "periodic", params, "deg14")
+    eC, eK, eD = errors(C[0], K[0], D[0], ref)
+    banner(f"  errors C={eC:.2e} K={eK:.2e} D={eD:.2e} refine={rep[0]['refine_steps']}")
+    assert rep[0]["status"] == 0
+    assert max(eC, eK, eD) < 1e-6
+
+
+def test_order_p_batch_of_mixed_sizes_equals_single_solves():
+    require_gpu()
+    from paper_1610_03484_amd import Batch
+    banner("order 3 batch: n = 2, 3 mixed, periodic and Dirichlet")
+    rves = [gpu_rve(2, "periodic", 3, precision="fp64", rtol=1e-13),
+            gpu_rve(3, "dirichlet", 3, precision="fp64", rtol=1e-13),
+            gpu_rve(3, "periodic", 3, precision="fp64", rtol=1e-13)]
+    params = ci.draw_params(15, 3)
+    C, K, D, rep = Batch(rves).homogenise(params)
+    for i, r in enumerate(rves):
+        c1, k1, d1, _ = r.homogenise(params[i:i + 1])
+        assert rel(C[i], c1[0]) < 1e-11 and rel(K[i], k1[0]) < 1e-11 and rel(D[i], d1[0]) < 1e-11
+
+
+def test_batch_rejects_mixed_orders():
+    require_gpu()
+    from paper_1610_03484_amd import Batch
+    from paper_1610_03484_amd import _lib as L
+    with pytest.raises(L.ChomError):
+        Batch([gpu_rve(2, "periodic", 3), gpu_rve(2, "periodic", 2)])

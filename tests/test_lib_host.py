@@ -200,7 +200,7 @@ def test_rve_create_rejects_bad_arguments(L):
     assert e.value.status == L.CHOM_EINVAL
     from paper_1610_03484_amd import RVE
     with pytest.raises(L.ChomError) as e:
-        RVE(coords, tets, phase, axis, ci.BASE_MATERIALS, order=3)
+        RVE(coords, tets, phase, axis, ci.BASE_MATERIALS, order=5)
     assert e.value.status == L.CHOM_EINVAL
     with pytest.raises(L.ChomError) as e:
         RVE(coords, tets, phase, axis, ci.BASE_MATERIALS, rtol=-1.0)
