@@ -140,6 +140,8 @@ template <int C, int R> struct ClassWS {
     DevBuf<ColState> cols, cols_outer;
     DevBuf<int> active, active_outer, bad;
     DevBuf<double> partial, avg_out, sums;
+    DevBuf<double> ef64;                 // orders 3, 4: element factors
+    DevBuf<float> ef32;
     std::vector<ColState> h_cols, h_cols_outer;
     std::vector<int> h_active;
     std::vector<int> refine_steps;
@@ -230,13 +232,16 @@ template <int C, int R>
 static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, int rg, int nwg_override) {
     constexpr int MS = ClassWS<C, R>::MS;
     const int nprob = (int)hp.size();
-    long long voff = 0, doff = 0, qoff = 0, max_pts = 0, max_tets = 0;
+    long long voff = 0, doff = 0, qoff = 0, eoff = 0, max_pts = 0, max_tets = 0;
+    constexpr int NQ = (3 * C) * (3 * C + 1) / 2;
     int max_tiles = 0, nr = 0;
     for (auto &P : hp) {
         const Geo &G = B->distinct[P.geo]->geo;
         P.voff = voff;
         P.doff = doff;
         P.qoff = qoff;
+        P.eoff = eoff;
+        if (G.p != 2) eoff += 6LL * G.n * G.n * G.n * NQ;
         voff += G.npts * R * C;
         doff += G.npts;
         qoff += G.p == 2 ? (long long)G.ntiles * BOXPTS * R * C : G.npts * R * C;
@@ -265,6 +270,12 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     const size_t nv = (size_t)voff, nq = (size_t)qoff;
     void *before[4] = {W.xd.p, W.xf.p, W.partial.p, W.probs.p};
     CHOM_HIP(W.probs.ensure(nprob));
+    if (eoff > 0) {
+        CHOM_HIP(W.ef64.ensure((size_t)eoff));
+        CHOM_HIP(W.ef32.ensure((size_t)eoff));
+    }
+    L.ef64 = eoff > 0 ? W.ef64.p : nullptr;
+    L.ef32 = eoff > 0 ? W.ef32.p : nullptr;
     CHOM_HIP(W.b.ensure(nv));
     CHOM_HIP(W.q64.ensure(nq));
     if (fp32) {
@@ -390,6 +401,7 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
     CHOM_HIP(hipMemcpyAsync(W.probs.p, hprobs.data(), sizeof(Prob) * nprob, hipMemcpyHostToDevice, s));
     CHOM_HIP(hipMemsetAsync(W.cols.p, 0, sizeof(ColState) * R * nprob, s));
     CHOM_HIP(hipMemsetAsync(W.bad.p, 0, sizeof(int), s));
+    if (L.order != 2) CHOM_HIP((launch_factors_hp<C>(L, W.ef64.p, W.ef32.p, s)));
     CHOM_HIP((launch_precond<C>(L, W.total_pts, W.diag.p, W.minv64.p, W.minv32.p, s)));
     CHOM_HIP((launch_gram<C>(L, W.minv64.p, W.minv32.p, W.partial.p, W.nwg_gram, W.ginv64.p, W.ginv32.p, W.bad.p, s)));
     CHOM_HIP((launch_rhs<C, R>(L, W.total_vals, W.b.p, W.cols.p, s)));

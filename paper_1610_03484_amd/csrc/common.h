@@ -58,6 +58,7 @@ struct Prob {
     long long voff;       // offset of this problem's vector segment (values)
     long long doff;       // offset of its per-point preconditioner data (points)
     long long qoff;       // offset of its operator tile boxes (values)
+    long long eoff;       // orders 3, 4: offset of its element factors (values)
     int geo;              // index of its RVE geometry
     int pad_;
 };

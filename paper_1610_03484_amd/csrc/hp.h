@@ -9,7 +9,7 @@
 namespace chom {
 namespace hp {
 
-constexpr int OP_TETS = 16;   // tets per operator workgroup
+constexpr int OP_TETS = 8;    // tets per operator workgroup
 
 // Compile-time shape of order P: element DOFs NE, dimension M of P_{P-1},
 // padded operand shapes of the two element products (16-row tiles, 4-deep steps):

@@ -5,7 +5,8 @@
 //   y_e = sum_k D_k^T [ sum_l Q_e^{kl} (D_l x_e) ],
 //   Q_e^{kl}_{cd} = |e| sum_mn (grad lam_k)_m C_{cmdn} (grad lam_l)_n   (k, l = 1..3),
 // where D_k are the order's derivative tables in a mass-orthonormal basis of
-// P_{p-1} (shared by every tet).  A workgroup takes 16 tets and a group of load
+// P_{p-1} (shared by every tet).  Q_e is precomputed per problem and tet (the
+// element factors, 45 or 6 numbers).  A workgroup takes 8 tets and all load
 // cases: it gathers their coefficients into LDS (columns = tet x load case x
 // component), forms G = [D_1; D_2; D_3] X on the matrix cores (16x16x4 MFMA,
 // FP32 or FP64), mixes the 9 derivative pairs with each tet's Q in place, forms
@@ -16,11 +17,13 @@
 #include "hp.h"
 #include "internal.h"
 
+#include <type_traits>
+
 namespace chom {
 
 using hp::Shape;
 
-constexpr int HP_EB = hp::OP_TETS;
+constexpr int HP_EB = hp::OP_TETS;   // tets per operator workgroup (all load cases)
 constexpr int HP_THREADS = 256;
 
 static inline int hp_grid(long long work, int bs, int cap = 16384) {
@@ -337,152 +340,221 @@ template <> struct Mfma<double> {
     __device__ static inline const double *DB(const Geo &G) { return G.hDB64; }
 };
 
-template <typename T, int P, int C, int R, int RG>
+// ------------------------------------------------------------------ element factors
+// Q_e of every tet of every problem, packed: upper triangle (row-major) of the
+// symmetric (3C) x (3C) matrix with index (k, c) = k C + c (the survey's 45 / 6
+// numbers per element), FP64 master and FP32 copy.
+template <int C>
+__global__ void hp_factor_kernel(const Geo *geos, const Prob *probs, double *ef64, float *ef32) {
+    constexpr int NQ = (3 * C) * (3 * C + 1) / 2;
+    const Prob &Pb = probs[blockIdx.y];
+    const Geo &G = geos[Pb.geo];
+    const long long nt = 6LL * G.n * G.n * G.n;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int t = (int)(e % 6);
+        double g[4][3], vol, a[3];
+        int ph;
+        GeoSel<double>::get(G, e, t, g, vol);
+        GeoSel<double>::elem(G, e, a, ph);
+        double Q[9][C][C];
+        elem_Q<C>(g, vol, a, Pb.mat64[ph ? 1 : 0], Q);
+        double *o64 = ef64 + Pb.eoff + e * NQ;
+        float *o32 = ef32 + Pb.eoff + e * NQ;
+        int u = 0;
+        for (int I = 0; I < 3 * C; ++I)
+            for (int J = I; J < 3 * C; ++J) {
+                const int k = I / C, c = I % C, l = J / C, d = J % C;
+                const double v = Q[k * 3 + l][c][d];
+                o64[u] = v;
+                o32[u] = (float)v;
+                ++u;
+            }
+    }
+}
+
+template <int C>
+hipError_t launch_factors_hp(const Launch &L, double *ef64, float *ef32, hipStream_t s) {
+    dim3 grid(hp_grid(L.max_tets, 256, 4096), L.nprob);
+    hp_factor_kernel<C><<<grid, 256, 0, s>>>(L.geos, L.probs, ef64, ef32);
+    return hipGetLastError();
+}
+template hipError_t launch_factors_hp<3>(const Launch &, double *, float *, hipStream_t);
+template hipError_t launch_factors_hp<1>(const Launch &, double *, float *, hipStream_t);
+
+// ------------------------------------------------------------------ operator
+// One workgroup: EB tets, all R load cases.
+template <typename T, int P, int C, int R, int EB>
 __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, const Prob *probs, int max_batches,
                                                           const T *__restrict__ x, T *__restrict__ y,
-                                                          double *partial_pq, const int *prob_active) {
+                                                          const T *__restrict__ ef, double *partial_pq,
+                                                          const int *prob_active) {
     using Sh = Shape<P>;
     constexpr int NE = Sh::NE, M = Sh::M, MA = Sh::MA, KA = Sh::KA, MB = Sh::MB, KB = Sh::KB;
-    constexpr int NG = R / RG;
-    constexpr int NC = HP_EB * RG * C;       // columns: tet x load case x component
+    constexpr int NQ = (3 * C) * (3 * C + 1) / 2;
+    constexpr int NC = EB * R * C;           // columns: tet x load case x component
     constexpr int NT = (NC + 15) / 16;
     constexpr int NCP = NT * 16;
     constexpr int NW = HP_THREADS / 64;
     using V4 = typename Mfma<T>::v4;
     __shared__ T xs[KA][NCP];
     __shared__ T gs[MA][NCP];
-    __shared__ T qs[HP_EB][9][C][C];
-    __shared__ long long pidx[HP_EB][NE];
-    __shared__ double red[RG][NW];
+    __shared__ T qs[EB][3 * C][3 * C];
+    __shared__ long long pidx[EB][NE];
+    __shared__ double red[R][NW];
     const int prob = blockIdx.y;
-    const int batch = blockIdx.x / NG, grp = blockIdx.x - (blockIdx.x / NG) * NG;
+    const int batch = blockIdx.x;
     const Prob &Pb = probs[prob];
     const Geo &G = geos[Pb.geo];
     const long long nt = 6LL * G.n * G.n * G.n;
-    const long long e0 = (long long)batch * HP_EB;
+    const long long e0 = (long long)batch * EB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (e0 >= nt || (prob_active != nullptr && prob_active[prob] == 0)) {
-        if (tid < RG) partial_pq[((long long)prob * R + grp * RG + tid) * max_batches + batch] = 0.0;
+        if (tid < R) partial_pq[((long long)prob * R + tid) * max_batches + batch] = 0.0;
         return;
     }
-    // ---- per-tet data: Q and the lattice index of every local DOF
-    if (tid < HP_EB) {
-        const long long e = e0 + tid;
-        if (e < nt) {
-            const int t = (int)(e % 6);
-            double g[4][3], vol, a[3];
-            int ph;
-            GeoSel<double>::get(G, e, t, g, vol);
-            GeoSel<double>::elem(G, e, a, ph);
-            double Q[9][C][C];
-            elem_Q<C>(g, vol, a, Pb.mat64[ph ? 1 : 0], Q);
-            for (int kl = 0; kl < 9; ++kl)
-                for (int c = 0; c < C; ++c)
-                    for (int d = 0; d < C; ++d) qs[tid][kl][c][d] = (T)Q[kl][c][d];
-            for (int q = 0; q < NE; ++q) {
-                int X, Y, Z;
-                hp_point<P>(G, e, q, X, Y, Z);
-                pidx[tid][q] = lat_index(G, X, Y, Z);
-            }
-        } else {
-            for (int kl = 0; kl < 9; ++kl)
-                for (int c = 0; c < C; ++c)
-                    for (int d = 0; d < C; ++d) qs[tid][kl][c][d] = T(0);
-            for (int q = 0; q < NE; ++q) pidx[tid][q] = -1;
+    // ---- element factors (unpacked to the full symmetric matrix) and DOF lattice indices
+    for (int i = tid; i < EB * NQ; i += HP_THREADS) {
+        const int e = i / NQ, u = i - (i / NQ) * NQ;
+        int I = 0, rem = u;
+        while (rem >= 3 * C - I) {
+            rem -= 3 * C - I;
+            ++I;
         }
+        const int J = I + rem;
+        const T v = (e0 + e < nt) ? ef[Pb.eoff + (e0 + e) * NQ + u] : T(0);
+        qs[e][I][J] = v;
+        qs[e][J][I] = v;
+    }
+    for (int i = tid; i < EB * NE; i += HP_THREADS) {
+        const int e = i / NE, q = i - (i / NE) * NE;
+        long long v = -1;
+        if (e0 + e < nt) {
+            int X, Y, Z;
+            hp_point<P>(G, e0 + e, q, X, Y, Z);
+            v = lat_index(G, X, Y, Z);
+        }
+        pidx[e][q] = v;
     }
     __syncthreads();
-    // ---- gather X [KA][NCP]: column (tet * RG + load case) * C + component
+    // ---- gather X [KA][NCP]: column (tet * R + load case) * C + component
     const T *xp = x + Pb.voff;
     for (int i = tid; i < KA * NCP; i += HP_THREADS) {
         const int j = i / NCP, col = i - (i / NCP) * NCP;
         T v = T(0);
         if (j < NE && col < NC) {
-            const int e = col / (RG * C), rem = col - (col / (RG * C)) * (RG * C);
+            const int e = col / (R * C), rem = col - (col / (R * C)) * (R * C);
             const int r = rem / C, d = rem - (rem / C) * C;
             const long long pt = pidx[e][j];
-            if (pt >= 0) v = xp[((long long)(grp * RG + r) * G.npts + pt) * C + d];
+            if (pt >= 0) v = xp[((long long)r * G.npts + pt) * C + d];
         }
         xs[j][col] = v;
     }
     __syncthreads();
-    // ---- G = DA X on the matrix cores
+    // ---- G = DA X on the matrix cores: each wave keeps all of DA's fragments in
+    // registers and sweeps its column tiles, reusing each X fragment for all row tiles
     const T *DA = Mfma<T>::DA(G);
     const T *DB = Mfma<T>::DB(G);
     const int lr = lane & 15, lk = lane >> 4;
-    for (int tile = wave; tile < (MA / 16) * NT; tile += NW) {
-        const int mt = tile / NT, ct = tile - (tile / NT) * NT;
-        V4 acc = {T(0), T(0), T(0), T(0)};
+    {
+        constexpr int MT = MA / 16, KS = KA / 4;
+        T af[MT][KS];
 #pragma unroll
-        for (int k0 = 0; k0 < KA; k0 += 4)
-            acc = Mfma<T>::op(DA[(mt * 16 + lr) * KA + k0 + lk], xs[k0 + lk][ct * 16 + lr], acc);
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) gs[mt * 16 + Mfma<T>::row(lk, q)][ct * 16 + lr] = acc[q];
+            for (int ks = 0; ks < KS; ++ks) af[mt][ks] = DA[(mt * 16 + lr) * KA + ks * 4 + lk];
+        for (int ct = wave; ct < NT; ct += NW) {
+            V4 acc[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = V4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const T b = xs[ks * 4 + lk][ct * 16 + lr];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = Mfma<T>::op(af[mt][ks], b, acc[mt]);
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gs[mt * 16 + Mfma<T>::row(lk, q)][ct * 16 + lr] = acc[mt][q];
+        }
     }
     __syncthreads();
     // ---- H = sum_l Q^{kl} G_l, in place (rows k*M + a)
-    for (int i = tid; i < M * HP_EB * RG; i += HP_THREADS) {
+    for (int i = tid; i < M * EB * R; i += HP_THREADS) {
         const int a = i % M, er = i / M;
-        const int e = er / RG, r = er - (er / RG) * RG;
-        const int col0 = (e * RG + r) * C;
-        T gv[3][C];
+        const int e = er / R;
+        const int col0 = er * C;
+        T gv[3 * C];
 #pragma unroll
         for (int l = 0; l < 3; ++l)
 #pragma unroll
-            for (int d = 0; d < C; ++d) gv[l][d] = gs[l * M + a][col0 + d];
+            for (int d = 0; d < C; ++d) gv[l * C + d] = gs[l * M + a][col0 + d];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 T h = T(0);
 #pragma unroll
-                for (int l = 0; l < 3; ++l)
-#pragma unroll
-                    for (int d = 0; d < C; ++d) h += qs[e][k * 3 + l][c][d] * gv[l][d];
+                for (int J = 0; J < 3 * C; ++J) h += qs[e][k * C + c][J] * gv[J];
                 gs[k * M + a][col0 + c] = h;
             }
     }
     __syncthreads();
     // ---- Y = DB H on the matrix cores; add into y, element energies
     T *yp = y + Pb.qoff;
-    double pq[RG];
+    double pq[R];
 #pragma unroll
-    for (int r = 0; r < RG; ++r) pq[r] = 0.0;
-    for (int tile = wave; tile < (MB / 16) * NT; tile += NW) {
-        const int mt = tile / NT, ct = tile - (tile / NT) * NT;
-        V4 acc = {T(0), T(0), T(0), T(0)};
+    for (int r = 0; r < R; ++r) pq[r] = 0.0;
+    {
+        constexpr int MT = MB / 16, KS = KB / 4;
+        T bf[MT][KS];
 #pragma unroll
-        for (int k0 = 0; k0 < KB; k0 += 4)
-            acc = Mfma<T>::op(DB[(mt * 16 + lr) * KB + k0 + lk], gs[k0 + lk][ct * 16 + lr], acc);
-        const int col = ct * 16 + lr;
-        if (col < NC) {
-            const int e = col / (RG * C), rem = col - (col / (RG * C)) * (RG * C);
-            const int r = rem / C, d = rem - (rem / C) * C;
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = mt * 16 + Mfma<T>::row(lk, q);
-                if (i >= NE) continue;
-                const long long pt = pidx[e][i];
-                if (pt < 0) continue;
-                atomicAdd(&yp[((long long)(grp * RG + r) * G.npts + pt) * C + d], acc[q]);
-                const double en = (double)xs[i][col] * (double)acc[q];
+            for (int ks = 0; ks < KS; ++ks) bf[mt][ks] = DB[(mt * 16 + lr) * KB + ks * 4 + lk];
+        for (int ct = wave; ct < NT; ct += NW) {
+            V4 acc[MT];
 #pragma unroll
-                for (int rr = 0; rr < RG; ++rr)
-                    if (rr == r) pq[rr] += en;
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = V4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const T b = gs[ks * 4 + lk][ct * 16 + lr];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = Mfma<T>::op(bf[mt][ks], b, acc[mt]);
             }
+            const int col = ct * 16 + lr;
+            if (col >= NC) continue;
+            const int e = col / (R * C), rem = col - (col / (R * C)) * (R * C);
+            const int r = rem / C, d = rem - (rem / C) * C;
+            double en = 0.0;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = mt * 16 + Mfma<T>::row(lk, q);
+                    if (i >= NE) continue;
+                    const long long pt = pidx[e][i];
+                    if (pt < 0) continue;
+                    atomicAdd(&yp[((long long)r * G.npts + pt) * C + d], acc[mt][q]);
+                    en += (double)xs[i][col] * (double)acc[mt][q];
+                }
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+                if (rr == r) pq[rr] += en;
         }
     }
 #pragma unroll
-    for (int r = 0; r < RG; ++r) {
-        const double s = wave_sum(pq[r]);
-        if (lane == 0) red[r][wave] = s;
+    for (int r = 0; r < R; ++r) {
+        const double sm = wave_sum(pq[r]);
+        if (lane == 0) red[r][wave] = sm;
     }
     __syncthreads();
-    if (tid < RG) {
-        double s = 0.0;
+    if (tid < R) {
+        double sm = 0.0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) s += red[tid][w];
-        partial_pq[((long long)prob * R + grp * RG + tid) * max_batches + batch] = s;
+        for (int w = 0; w < NW; ++w) sm += red[tid][w];
+        partial_pq[((long long)prob * R + tid) * max_batches + batch] = sm;
     }
 }
 
@@ -492,32 +564,24 @@ __global__ void hp_clear_kernel(T *y, long long n) {
         y[i] = T(0);
 }
 
-template <typename T, int P, int C, int R, int RG>
-static hipError_t launch_hp_rg(const Launch &L, int nprob, const T *x, T *y, double *partial_pq,
-                               const int *prob_active, hipStream_t s) {
-    dim3 grid(L.max_tiles * (R / RG), nprob);
-    hp_op_kernel<T, P, C, R, RG><<<grid, HP_THREADS, 0, s>>>(L.geos, L.probs, L.max_tiles, x, y, partial_pq,
-                                                              prob_active);
+template <typename T, int P, int C, int R>
+static hipError_t launch_hp(const Launch &L, int nprob, const T *x, T *y, double *partial_pq, const int *prob_active,
+                            hipStream_t s) {
+    dim3 grid(L.max_tiles, nprob);
+    const T *ef = std::is_same<T, double>::value ? (const T *)L.ef64 : (const T *)L.ef32;
+    hp_op_kernel<T, P, C, R, HP_EB><<<grid, HP_THREADS, 0, s>>>(L.geos, L.probs, L.max_tiles, x, y, ef, partial_pq,
+                                                                prob_active);
     return hipGetLastError();
 }
 
 template <typename T, int C, int R>
-hipError_t launch_operator_hp(const Launch &L, int nprob, int rg, const T *x, T *y, double *partial_pq,
+hipError_t launch_operator_hp(const Launch &L, int nprob, int /*rg*/, const T *x, T *y, double *partial_pq,
                               const int *prob_active, hipStream_t s) {
     hp_clear_kernel<T><<<hp_grid(L.total_q, 256), 256, 0, s>>>(y, L.total_q);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if constexpr (C == 3) {
-        if (rg == 1) {
-            if (L.order == 3) return launch_hp_rg<T, 3, C, R, 1>(L, nprob, x, y, partial_pq, prob_active, s);
-            return launch_hp_rg<T, 4, C, R, 1>(L, nprob, x, y, partial_pq, prob_active, s);
-        }
-        if (L.order == 3) return launch_hp_rg<T, 3, C, R, 2>(L, nprob, x, y, partial_pq, prob_active, s);
-        return launch_hp_rg<T, 4, C, R, 2>(L, nprob, x, y, partial_pq, prob_active, s);
-    } else {
-        if (L.order == 3) return launch_hp_rg<T, 3, C, R, 3>(L, nprob, x, y, partial_pq, prob_active, s);
-        return launch_hp_rg<T, 4, C, R, 3>(L, nprob, x, y, partial_pq, prob_active, s);
-    }
+    if (L.order == 3) return launch_hp<T, 3, C, R>(L, nprob, x, y, partial_pq, prob_active, s);
+    return launch_hp<T, 4, C, R>(L, nprob, x, y, partial_pq, prob_active, s);
 }
 
 template hipError_t launch_operator_hp<double, 3, 6>(const Launch &, int, int, const double *, double *, double *, const int *, hipStream_t);

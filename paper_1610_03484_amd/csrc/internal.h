@@ -35,6 +35,8 @@ struct Launch {
     double *sums;         // reduced partial sums, [nprob][R * (2 + C * 4)]
     int order;            // polynomial order of every problem of the class
     long long total_q;    // values of the operator output of the class
+    const double *ef64;   // orders 3, 4: element factors Q_e (packed symmetric 3C x 3C), per problem at Prob.eoff
+    const float *ef32;
 };
 
 // ------------------------------------------------------------------ launchers
@@ -98,6 +100,7 @@ template <int C> hipError_t launch_diag_hp(const Launch &L, double *diag, hipStr
 template <int C, int R> hipError_t launch_rhs_hp(const Launch &L, double *b, ColState *cols, hipStream_t s);
 template <int C, int R>
 hipError_t launch_average_partial_hp(const Launch &L, const double *x64, double *partial, int nwg, hipStream_t s);
+template <int C> hipError_t launch_factors_hp(const Launch &L, double *ef64, float *ef32, hipStream_t s);
 template <typename T, int C, int R>
 hipError_t launch_operator_hp(const Launch &L, int nprob, int rg, const T *x, T *y, double *partial_pq,
                               const int *prob_active, hipStream_t s);
