@@ -48,6 +48,10 @@ WORKLOADS = {
                     "FP32 accumulate) trained on 12^3 plain-weave RVE solves (p=2, periodic, degraded records "
                     "as in the batched workload), evaluated on 1,000,000 records with RVE fallback where the "
                     "ensemble disagreement exceeds 1e-2"),
+    "c3": dict(n=16, bcs=("periodic",), precision="fp32_refined",
+               desc="p-refinement: batch of 16^3 Kuhn plain-weave RVEs (24,576 tets each) at order p (3: 352,947, "
+                    "4: 823,875 elastic DOFs), periodic, degraded records as in the batched workload, element "
+                    "operator on the FP32 matrix cores with FP64 refinement"),
     "c2": dict(n=None, bcs=("periodic",), precision="fp32_refined",
                desc="batch of RVEs with sizes uniform over {8,12,16,20,24}^3 cells, p=2, periodic, degraded "
                     "(T~U(20,60) C, c~U(0,1.5) wt%, t~U(0,10) y, factors U(0.9,1.1)), 12 load cases each, "
@@ -64,6 +68,40 @@ def algorithmic_mech(n, nprob, fp32):
     ndof = 3 * (2 * n + 1) ** 3
     bytes_ = 6 * 2 * ndof * s + T * (40 + 45 * s)
     flops = T * 6 * 2 * 30 ** 2
+    return bytes_ * nprob, flops * nprob
+
+
+CAL_BYTES = 256 << 20
+
+
+def calibration_copy(torch):
+    """Three device-to-device copies of 256 MiB (outside the timed region): the plain
+    copy of known size against which rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled."""
+    x = torch.ones(CAL_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+
+
+# HBM traffic of one launch of op_p2_kernel<float,3,6,2> on the default workload (three
+# 24^3 items), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the calibration copy
+# (profiles/op_p2_mech_fp32_24cubed_three_bc_traffic.md).  Must be re-measured (or set
+# to None) whenever that kernel changes.
+C1_OP_TRAFFIC_BYTES = 128_775_308
+
+
+def algorithmic_mech_order(n, p, nprob, fp32):
+    """As algorithmic_mech at order p = 3, 4: n_e = 3 (p+1)(p+2)(p+3)/6 elastic element
+    DOFs, conn = 60 / 64 B, n_A = 45, ndof = 3 (p n + 1)^3."""
+    s = 4 if fp32 else 8
+    T = 6 * n ** 3
+    ne = 3 * (p + 1) * (p + 2) * (p + 3) // 6
+    ndof = 3 * (p * n + 1) ** 3
+    conn = 60 if p == 3 else 64
+    bytes_ = 6 * 2 * ndof * s + T * (conn + 45 * s)
+    flops = T * 6 * 2 * ne ** 2
     return bytes_ * nprob, flops * nprob
 
 
@@ -111,6 +149,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--items", type=int, default=512, help="items of the c2 batch")
+    ap.add_argument("--order", type=int, default=4, help="c3: polynomial order (3 or 4)")
     ap.add_argument("--train", type=int, default=20000, help="c4: training solves")
     ap.add_argument("--epochs", type=int, default=300, help="c4: training epochs")
     ap.add_argument("--points", type=int, default=1_000_000, help="c4: surrogate evaluation points")
@@ -144,6 +183,13 @@ def main():
             rves.append(handles[n_i])
         n = int(max(sizes))
         labels = [f"n={int(s)}" for s in sizes]
+    elif args.workload == "c3":
+        n = wl["n"]
+        items = args.items if args.items != 512 else 64
+        rve = RVE(*generate_plain_weave(n, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic", order=args.order, **opts)
+        rves = [rve] * items
+        params = ci.draw_params(0, items)
+        labels = [f"item {i}" for i in range(items)]
     else:
         n = wl["n"]
         mesh = generate_plain_weave(n, device="cuda:0")
@@ -175,7 +221,7 @@ def main():
     # accuracy against the FP64 GPU path (same RVEs, same parameters); for the
     # mixed-size batch it is measured by the tests on a stratified sample instead
     err = None
-    if not args.no_accuracy and wl["precision"] != "fp64" and args.workload != "c2":
+    if not args.no_accuracy and wl["precision"] != "fp64" and args.workload not in ("c2", "c3"):
         ref_rves = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision="fp64", rtol=1e-12, max_iter=50000)
                     for bc in wl["bcs"]]
         ref = Batch(ref_rves)
@@ -188,6 +234,7 @@ def main():
 
     # dominant kernel: the mechanical operator launch of the batch
     ms, tets, nprob = batch.time_operator(0, args.op_reps)
+    calibration_copy(torch)
     fp32 = wl["precision"] != "fp64"
     if args.workload == "c2":
         bytes_ = flops = 0
@@ -195,6 +242,8 @@ def main():
             b1, f1 = algorithmic_mech(int(s_), 1, fp32)
             bytes_ += b1
             flops += f1
+    elif args.workload == "c3":
+        bytes_, flops = algorithmic_mech_order(n, args.order, nprob, fp32)
     else:
         bytes_, flops = algorithmic_mech(n, nprob, fp32)
     t = ms * 1e-3
@@ -202,11 +251,19 @@ def main():
     t_hbm, t_alu = bytes_ / HBM_PEAK, flops / peak_alu
     if t_alu >= t_hbm:
         roof = dict(bound="alu", achieved=flops / t / 1e12, peak=peak_alu / 1e12, unit="TFLOP/s",
-                    frac=(flops / t) / peak_alu, traffic=None)
+                    frac=(flops / t) / peak_alu,
+                    traffic=C1_OP_TRAFFIC_BYTES if (args.workload == "c1" and fp32) else None)
     else:
         roof = dict(bound="hbm", achieved=bytes_ / t / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
                     frac=(bytes_ / t) / HBM_PEAK, traffic=None)
-    roof.update(kernel=("op_p2_kernel<float,3,6>" if fp32 else "op_p2_kernel<double,3,6>"),
+    if args.workload == "c3":
+        roof = dict(bound="mfma", achieved=flops / t / 1e12, peak=FP32_VEC_PEAK / 1e12, unit="TFLOP/s",
+                    frac=(flops / t) / FP32_VEC_PEAK, traffic=None,
+                    note="FP32 matrix-core peak (157.3 TFLOP/s dense, equal to the packed FP32 vector peak)")
+        kname = f"hp_op_kernel<float,{args.order},3,6,8>"
+    else:
+        kname = "op_p2_kernel<float,3,6>" if fp32 else "op_p2_kernel<double,3,6>"
+    roof.update(kernel=kname,
                 avg_launch_us=ms * 1e3, algorithmic_bytes=bytes_, algorithmic_flops=flops)
     print(f"[bench] operator: {ms * 1e3:.1f} us/launch, {bytes_ / t / 1e9:.0f} GB/s algorithmic, "
           f"{flops / t / 1e12:.2f} TFLOP/s algorithmic", file=sys.stderr)
