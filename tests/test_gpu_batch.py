@@ -84,7 +84,9 @@ def test_batch_matches_single_rve_calls(params_and_oracle):
     C, K, D, _ = batch.homogenise(params)
     for i, key in enumerate(_items()):
         Ci, Ki, Di, _ = handles[key].homogenise(params[i:i + 1])
-        assert rel(C[i], Ci[0]) < 1e-11 and rel(K[i], Ki[0]) < 1e-11 and rel(D[i], Di[0]) < 1e-11
+        # two independent CG solves stopped at rtol = 1e-12: each is within ~2 n rtol
+        # (energy norm) of the discrete solution, so they agree to a few 1e-11
+        assert rel(C[i], Ci[0]) < 1e-10 and rel(K[i], Ki[0]) < 1e-10 and rel(D[i], Di[0]) < 1e-10
 
 
 def test_autotuned_batch_gives_same_results(params_and_oracle):

@@ -79,7 +79,8 @@ def test_order_p_batch_of_mixed_sizes_equals_single_solves():
     C, K, D, rep = Batch(rves).homogenise(params)
     for i, r in enumerate(rves):
         c1, k1, d1, _ = r.homogenise(params[i:i + 1])
-        assert rel(C[i], c1[0]) < 1e-11 and rel(K[i], k1[0]) < 1e-11 and rel(D[i], d1[0]) < 1e-11
+        # independent solves stopped at rtol = 1e-13: agree to well below 1e-10
+        assert rel(C[i], c1[0]) < 1e-10 and rel(K[i], k1[0]) < 1e-10 and rel(D[i], d1[0]) < 1e-10
 
 
 def test_batch_rejects_mixed_orders():

@@ -105,4 +105,6 @@ def test_batch_equals_single_calls():
     Cb, Kb, Db, _ = rve.homogenise(params)
     for i in range(3):
         C, K, D, _ = rve.homogenise(params[i:i + 1])
-        assert rel(Cb[i], C[0]) < 1e-12 and rel(Kb[i], K[0]) < 1e-12 and rel(Db[i], D[0]) < 1e-12
+        # independent CG solves stopped at rtol = 1e-12 (FP64 atomic sums vary in order
+        # between runs): each within ~2 n rtol of the discrete solution
+        assert rel(Cb[i], C[0]) < 1e-10 and rel(Kb[i], K[0]) < 1e-10 and rel(Db[i], D[0]) < 1e-10
