@@ -244,7 +244,7 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
         if (G.p != 2) eoff += 6LL * G.n * G.n * G.n * NQ;
         voff += G.npts * R * C;
         doff += G.npts;
-        qoff += G.p == 2 ? (long long)G.ntiles * BOXPTS * R * C : G.npts * R * C;
+        qoff += (long long)G.ntiles * G.boxpts * R * C;
         max_pts = std::max(max_pts, G.npts);
         max_tets = std::max(max_tets, 6LL * G.n * G.n * G.n);
         max_tiles = std::max(max_tiles, G.ntiles);
@@ -260,9 +260,9 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
                               : (int)std::min<long long>(std::max<long long>((max_pts + 127) / 128, 1), 1024);
     L.max_tiles = max_tiles;
     L.nr = nr == 0 ? 0 : (nr == 1 ? 1 : 4);
-    L.rg = rg;
-    L.max_tets = max_tets;
     L.order = B->distinct[hp[0].geo]->geo.p;
+    L.rg = L.order == 2 ? rg : R;   // orders 3, 4: all load cases in one workgroup
+    L.max_tets = max_tets;
     L.total_q = qoff;
     W.nwg_gram = (int)std::min<long long>(std::max<long long>((max_pts + 4095) / 4096, 1), 256);
     W.nwg_avg = (int)std::min<long long>(std::max<long long>((max_tets + 1023) / 1024, 1), 256);
@@ -559,7 +559,7 @@ static int autotune_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp
             best_rg = rgs[i];
         }
     }
-    W.L.rg = best_rg;
+    W.L.rg = W.L.order == 2 ? best_rg : R;   // orders 3, 4 always take all load cases
     const int nwgs[4] = {128, 256, 512, 1024};
     best = 1e30;
     int best_nwg = W.L.nwg;
@@ -1014,10 +1014,18 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
     G.tiles_y = (n + TY - 1) / TY;
     G.tiles_z = (n + TZ - 1) / TZ;
     G.ntiles = G.tiles_x * G.tiles_y * G.tiles_z;
-    if (order != 2) {   // element batches of the order-3/4 operator
-        G.tiles_x = G.tiles_y = G.tiles_z = 0;
-        G.ntiles = (int)((nt + hp::OP_TETS - 1) / hp::OP_TETS);
+    G.tcx = TX;
+    G.tcy = TY;
+    G.tcz = TZ;
+    if (order != 2) {   // orders 3, 4: one cell per operator tile
+        G.tiles_x = G.tiles_y = G.tiles_z = n;
+        G.ntiles = n * n * n;
+        G.tcx = G.tcy = G.tcz = 1;
     }
+    G.bx = order * G.tcx + 1;
+    G.by = order * G.tcy + 1;
+    G.bz = order * G.tcz + 1;
+    G.boxpts = G.bx * G.by * G.bz;
     for (int t = 0; t < 6; ++t) {
         int p0, p1;
         kuhn_perm(t, p0, p1);

@@ -41,7 +41,9 @@ struct Geo {
     const double *rows;     // per lattice point: int grad(phi) (3) and int phi (1)
     int nrow;               // projection rows per component: 0 (D), 1 (P), 4 (N)
     int tiles_x, tiles_y, tiles_z;
-    int ntiles;       // order 2: operator tiles; orders 3, 4: operator element batches
+    int ntiles;       // operator tiles (order 2: TX x TY x TZ cells; orders 3, 4: one cell)
+    int tcx, tcy, tcz;        // cells per operator tile along each axis
+    int bx, by, bz, boxpts;   // DOF box of a tile: p tc + 1 points per axis
     int p;            // polynomial order
     int L;            // lattice points per side minus one: p n
     // orders 3, 4: basis tables (see hp_tables.cpp)
@@ -302,7 +304,7 @@ __device__ inline bool dirichlet_boundary(const Geo &G, int X, int Y, int Z) {
     return G.bc == 0 && (X == 0 || Y == 0 || Z == 0 || X == m || Y == m || Z == m);
 }
 
-// Operator output layout: one (2T+1)^3 box of values per tile ("tile boxes"),
+// Operator output layout: one (p T + 1)^3 box of values per tile ("tile boxes"),
 // tile-major, the RC values of a box point contiguous.  A lattice point on a
 // tile face lies in up to two tiles per axis; its value is the sum of its copies.
 // Candidate (tile, local) pairs of coordinate X along one axis.
@@ -330,27 +332,21 @@ __device__ inline int tile_cands(int X, int T2, int ntiles, int m2, bool per, in
 // group, R / rg groups.
 template <typename T, int C, int R>
 __device__ inline void gather_tiles_col(const Geo &G, const T *qt, int rg, int X, int Y, int Z, int w, double out[C]) {
-    if (G.p != 2) {   // orders 3, 4: the operator output is a plain vector [load case][point][C]
-        const long long off = ((long long)w * G.npts + lat_index(G, X, Y, Z)) * C;
-#pragma unroll
-        for (int v = 0; v < C; ++v) out[v] = (double)qt[off + v];
-        return;
-    }
     const int ng = R / rg, rcg = rg * C;
     const int grp = w / rg, rr = w - grp * rg;
     const bool per = (G.bc == 1);
-    const int m2 = 2 * G.n;
+    const int m2 = G.L;
     int tx[2], ty[2], tz[2], lx[2], ly[2], lz[2];
-    const int nx = tile_cands(X, 2 * TX, G.tiles_x, m2, per, tx, lx);
-    const int ny = tile_cands(Y, 2 * TY, G.tiles_y, m2, per, ty, ly);
-    const int nz = tile_cands(Z, 2 * TZ, G.tiles_z, m2, per, tz, lz);
+    const int nx = tile_cands(X, G.p * G.tcx, G.tiles_x, m2, per, tx, lx);
+    const int ny = tile_cands(Y, G.p * G.tcy, G.tiles_y, m2, per, ty, ly);
+    const int nz = tile_cands(Z, G.p * G.tcz, G.tiles_z, m2, per, tz, lz);
 #pragma unroll
     for (int v = 0; v < C; ++v) out[v] = 0.0;
     for (int a = 0; a < nx; ++a)
         for (int b = 0; b < ny; ++b)
             for (int c = 0; c < nz; ++c) {
                 const long long tile = tx[a] + (long long)G.tiles_x * (ty[b] + (long long)G.tiles_y * tz[c]);
-                const long long off = ((tile * ng + grp) * BOXPTS + lx[a] + BX * (ly[b] + BY * lz[c])) * rcg + rr * C;
+                const long long off = ((tile * ng + grp) * G.boxpts + lx[a] + G.bx * (ly[b] + G.by * lz[c])) * rcg + rr * C;
 #pragma unroll
                 for (int v = 0; v < C; ++v) out[v] += (double)qt[off + v];
             }

@@ -9,8 +9,6 @@
 namespace chom {
 namespace hp {
 
-constexpr int OP_TETS = 8;    // tets per operator workgroup
-
 // Compile-time shape of order P: element DOFs NE, dimension M of P_{P-1},
 // padded operand shapes of the two element products (16-row tiles, 4-deep steps):
 //   G = DA X with DA [MA][KA] = [D_1; D_2; D_3] (3M x NE, padded),

@@ -6,12 +6,13 @@
 //   Q_e^{kl}_{cd} = |e| sum_mn (grad lam_k)_m C_{cmdn} (grad lam_l)_n   (k, l = 1..3),
 // where D_k are the order's derivative tables in a mass-orthonormal basis of
 // P_{p-1} (shared by every tet).  Q_e is precomputed per problem and tet (the
-// element factors, 45 or 6 numbers).  A workgroup takes 8 tets and all load
-// cases: it gathers their coefficients into LDS (columns = tet x load case x
-// component), forms G = [D_1; D_2; D_3] X on the matrix cores (16x16x4 MFMA,
-// FP32 or FP64), mixes the 9 derivative pairs with each tet's Q in place, forms
-// Y = [D_1; D_2; D_3]^T H on the matrix cores, and adds Y into the output vector
-// with global atomics (the output is cleared first).  The element energies
+// element factors, 45 or 6 numbers).  A workgroup takes one cell (6 tets) and
+// all load cases: it stages the cell's DOF box into LDS, lays the tets'
+// coefficients out as columns (tet x load case x component), forms
+// G = [D_1; D_2; D_3] X on the matrix cores (16x16x4 MFMA, FP32 or FP64), mixes
+// the 9 derivative pairs with each tet's Q in place, forms Y = [D_1; D_2; D_3]^T H
+// on the matrix cores, accumulates Y in an FP64 LDS box and writes the box to the
+// cell's slot of the tile-box output (no global atomics).  The element energies
 // x_e . y_e are summed on the way (p.Kp of the CG step).
 #include "common.h"
 #include "hp.h"
@@ -23,7 +24,6 @@ namespace chom {
 
 using hp::Shape;
 
-constexpr int HP_EB = hp::OP_TETS;   // tets per operator workgroup (all load cases)
 constexpr int HP_THREADS = 256;
 
 static inline int hp_grid(long long work, int bs, int cap = 16384) {
@@ -383,37 +383,59 @@ template hipError_t launch_factors_hp<3>(const Launch &, double *, float *, hipS
 template hipError_t launch_factors_hp<1>(const Launch &, double *, float *, hipStream_t);
 
 // ------------------------------------------------------------------ operator
-// One workgroup: EB tets, all R load cases.
-template <typename T, int P, int C, int R, int EB>
-__global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, const Prob *probs, int max_batches,
+// One workgroup: one cell (its 6 tets), all R load cases.  The cell's (p+1)^3 DOF
+// box is staged from HBM once; the element results accumulate in an FP64 LDS box
+// that is written, contiguous, to the cell's slot of the tile-box output
+// (consumers sum the copies of points shared by neighbouring cells).
+template <typename T, int P, int C, int R>
+__global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, const Prob *probs, int max_tiles,
                                                           const T *__restrict__ x, T *__restrict__ y,
                                                           const T *__restrict__ ef, double *partial_pq,
                                                           const int *prob_active) {
     using Sh = Shape<P>;
     constexpr int NE = Sh::NE, M = Sh::M, MA = Sh::MA, KA = Sh::KA, MB = Sh::MB, KB = Sh::KB;
     constexpr int NQ = (3 * C) * (3 * C + 1) / 2;
-    constexpr int NC = EB * R * C;           // columns: tet x load case x component
+    constexpr int EB = 6;
+    constexpr int RC = R * C;
+    constexpr int B1 = P + 1, BP = B1 * B1 * B1;
+    constexpr int NC = EB * RC;              // columns: tet x load case x component
     constexpr int NT = (NC + 15) / 16;
     constexpr int NCP = NT * 16;
     constexpr int NW = HP_THREADS / 64;
     using V4 = typename Mfma<T>::v4;
+    __shared__ T xb[BP * RC];
+    __shared__ double yb[BP * RC];
     __shared__ T xs[KA][NCP];
     __shared__ T gs[MA][NCP];
     __shared__ T qs[EB][3 * C][3 * C];
-    __shared__ long long pidx[EB][NE];
+    __shared__ int bidx[EB][NE];
     __shared__ double red[R][NW];
     const int prob = blockIdx.y;
-    const int batch = blockIdx.x;
+    const int cell = blockIdx.x;
     const Prob &Pb = probs[prob];
     const Geo &G = geos[Pb.geo];
-    const long long nt = 6LL * G.n * G.n * G.n;
-    const long long e0 = (long long)batch * EB;
+    const int n = G.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (e0 >= nt || (prob_active != nullptr && prob_active[prob] == 0)) {
-        if (tid < R) partial_pq[((long long)prob * R + tid) * max_batches + batch] = 0.0;
+    if (cell >= n * n * n || (prob_active != nullptr && prob_active[prob] == 0)) {
+        if (tid < R) partial_pq[((long long)prob * R + tid) * max_tiles + cell] = 0.0;
         return;
     }
-    // ---- element factors (unpacked to the full symmetric matrix) and DOF lattice indices
+    const int ci = cell % n, cj = (cell / n) % n, ck = cell / (n * n);
+    // ---- stage the DOF box, clear the output box, box index of every local DOF, factors
+    const T *xp = x + Pb.voff;
+    for (int i = tid; i < BP * RC; i += HP_THREADS) {
+        const int pt = i / RC, v = i - (i / RC) * RC;
+        const int r = v / C, c = v - (v / C) * C;
+        const int bx = pt % B1, by = (pt / B1) % B1, bz = pt / (B1 * B1);
+        const long long idx = lat_index(G, P * ci + bx, P * cj + by, P * ck + bz);
+        xb[i] = xp[((long long)r * G.npts + idx) * C + c];
+        yb[i] = 0.0;
+    }
+    for (int i = tid; i < EB * NE; i += HP_THREADS) {
+        const int e = i / NE, q = i - (i / NE) * NE;
+        const int *o = G.hoff + (e * NE + q) * 3;
+        bidx[e][q] = o[0] + B1 * (o[1] + B1 * o[2]);
+    }
     for (int i = tid; i < EB * NQ; i += HP_THREADS) {
         const int e = i / NQ, u = i - (i / NQ) * NQ;
         int I = 0, rem = u;
@@ -422,31 +444,18 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
             ++I;
         }
         const int J = I + rem;
-        const T v = (e0 + e < nt) ? ef[Pb.eoff + (e0 + e) * NQ + u] : T(0);
+        const T v = ef[Pb.eoff + ((long long)cell * 6 + e) * NQ + u];
         qs[e][I][J] = v;
         qs[e][J][I] = v;
     }
-    for (int i = tid; i < EB * NE; i += HP_THREADS) {
-        const int e = i / NE, q = i - (i / NE) * NE;
-        long long v = -1;
-        if (e0 + e < nt) {
-            int X, Y, Z;
-            hp_point<P>(G, e0 + e, q, X, Y, Z);
-            v = lat_index(G, X, Y, Z);
-        }
-        pidx[e][q] = v;
-    }
     __syncthreads();
-    // ---- gather X [KA][NCP]: column (tet * R + load case) * C + component
-    const T *xp = x + Pb.voff;
+    // ---- X [KA][NCP]: column (tet * R + load case) * C + component
     for (int i = tid; i < KA * NCP; i += HP_THREADS) {
         const int j = i / NCP, col = i - (i / NCP) * NCP;
         T v = T(0);
         if (j < NE && col < NC) {
-            const int e = col / (R * C), rem = col - (col / (R * C)) * (R * C);
-            const int r = rem / C, d = rem - (rem / C) * C;
-            const long long pt = pidx[e][j];
-            if (pt >= 0) v = xp[((long long)r * G.npts + pt) * C + d];
+            const int e = col / RC, rem = col - (col / RC) * RC;
+            v = xb[bidx[e][j] * RC + rem];
         }
         xs[j][col] = v;
     }
@@ -501,8 +510,7 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
             }
     }
     __syncthreads();
-    // ---- Y = DB H on the matrix cores; add into y, element energies
-    T *yp = y + Pb.qoff;
+    // ---- Y = DB H on the matrix cores; accumulate into the LDS box, element energies
     double pq[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) pq[r] = 0.0;
@@ -525,8 +533,8 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
             }
             const int col = ct * 16 + lr;
             if (col >= NC) continue;
-            const int e = col / (R * C), rem = col - (col / (R * C)) * (R * C);
-            const int r = rem / C, d = rem - (rem / C) * C;
+            const int e = col / RC, rem = col - (col / RC) * RC;
+            const int r = rem / C;
             double en = 0.0;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -534,9 +542,7 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
                 for (int q = 0; q < 4; ++q) {
                     const int i = mt * 16 + Mfma<T>::row(lk, q);
                     if (i >= NE) continue;
-                    const long long pt = pidx[e][i];
-                    if (pt < 0) continue;
-                    atomicAdd(&yp[((long long)r * G.npts + pt) * C + d], acc[mt][q]);
+                    atomicAdd(&yb[bidx[e][i] * RC + rem], (double)acc[mt][q]);
                     en += (double)xs[i][col] * (double)acc[mt][q];
                 }
 #pragma unroll
@@ -544,6 +550,10 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
                 if (rr == r) pq[rr] += en;
         }
     }
+    __syncthreads();
+    // ---- write the cell's box (contiguous)
+    T *yt = y + Pb.qoff + (long long)cell * BP * RC;
+    for (int i = tid; i < BP * RC; i += HP_THREADS) yt[i] = (T)yb[i];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const double sm = wave_sum(pq[r]);
@@ -554,14 +564,8 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
         double sm = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) sm += red[tid][w];
-        partial_pq[((long long)prob * R + tid) * max_batches + batch] = sm;
+        partial_pq[((long long)prob * R + tid) * max_tiles + cell] = sm;
     }
-}
-
-template <typename T>
-__global__ void hp_clear_kernel(T *y, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        y[i] = T(0);
 }
 
 template <typename T, int P, int C, int R>
@@ -569,17 +573,14 @@ static hipError_t launch_hp(const Launch &L, int nprob, const T *x, T *y, double
                             hipStream_t s) {
     dim3 grid(L.max_tiles, nprob);
     const T *ef = std::is_same<T, double>::value ? (const T *)L.ef64 : (const T *)L.ef32;
-    hp_op_kernel<T, P, C, R, HP_EB><<<grid, HP_THREADS, 0, s>>>(L.geos, L.probs, L.max_tiles, x, y, ef, partial_pq,
-                                                                prob_active);
+    hp_op_kernel<T, P, C, R><<<grid, HP_THREADS, 0, s>>>(L.geos, L.probs, L.max_tiles, x, y, ef, partial_pq,
+                                                         prob_active);
     return hipGetLastError();
 }
 
 template <typename T, int C, int R>
 hipError_t launch_operator_hp(const Launch &L, int nprob, int /*rg*/, const T *x, T *y, double *partial_pq,
                               const int *prob_active, hipStream_t s) {
-    hp_clear_kernel<T><<<hp_grid(L.total_q, 256), 256, 0, s>>>(y, L.total_q);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     if (L.order == 3) return launch_hp<T, 3, C, R>(L, nprob, x, y, partial_pq, prob_active, s);
     return launch_hp<T, 4, C, R>(L, nprob, x, y, partial_pq, prob_active, s);
 }
