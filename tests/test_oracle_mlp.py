@@ -182,3 +182,19 @@ def test_block_errors_closed_form():
     pred = ref.copy()
     pred[0, 21 + 3] += 0.3                 # K_xy: counted twice
     assert abs(mlp.block_errors(pred, ref)[0] - math.sqrt(2 * 0.09) / 3.0) < 1e-15
+
+
+def test_heldout_file_matches_its_seeded_records():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "surrogate_heldout_n12_periodic.txt")
+    a = np.loadtxt(path)
+    assert a.shape == (256, 45)
+    np.testing.assert_array_equal(a[:, 0], np.arange(256))
+    np.testing.assert_array_equal(a[:, 1:12], ci.draw_params(1_000_000, 256))
+    # C_bar symmetric positive definite, K_bar and D_bar positive diagonals
+    iu = np.triu_indices(6)
+    Cm = np.zeros((256, 6, 6))
+    Cm[:, iu[0], iu[1]] = a[:, 12:33]
+    Cm[:, iu[1], iu[0]] = a[:, 12:33]
+    assert np.all(np.linalg.eigvalsh(Cm) > 0)
+    assert np.all(a[:, 33:36] > 0) and np.all(a[:, 39:42] > 0)
