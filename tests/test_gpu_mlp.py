@@ -179,7 +179,7 @@ def trained():
     banner("surrogate: training set of 12^3 periodic RVE solves")
     mesh = generate_plain_weave(12, device="cuda:0")
     rve = RVE(*mesh, ci.BASE_MATERIALS, bc="periodic", precision="fp32_refined", rtol=1e-10, max_iter=50000)
-    ntrain = 4096
+    ntrain = 8192
     params = ci.draw_params(0, ntrain)
     t0 = time.perf_counter()
     C, K, D = [], [], []
