@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--items", type=int, default=512, help="items of the c2 batch")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="fixed launch shape instead of the library's autotuner (which runs in the warm-up)")
     ap.add_argument("--order", type=int, default=4, help="c3: polynomial order (3 or 4)")
     ap.add_argument("--rtol", type=float, default=1e-8,
                     help="stopping tolerance of the FP64 residual (relative to the linear-field energy); "
@@ -159,10 +161,12 @@ def main():
     ap.add_argument("--points", type=int, default=1_000_000, help="c4: surrogate evaluation points")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (the RVE batches shard across GPUs without "
+        print(f"bench.py measures one GPU only (the RVE batches would shard across GPUs without "
               f"communication, but no multi-GPU path is built); got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
 
+    if not args.no_autotune:
+        os.environ.setdefault("CHOM_AUTOTUNE", "1")
     import torch
     import chom_inputs as ci
     from paper_1610_03484_amd import RVE, generate_plain_weave
@@ -288,6 +292,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "path": "batched", "rves_per_step": len(rves),
                    "rtol": args.rtol, "inner_rtol": args.inner_rtol,
+                   "autotuned": os.environ.get("CHOM_AUTOTUNE") is not None,
                    "c_hom_rel_err_vs_fp64_gpu": err, "launch": batch.launch_config(),
                    "converged": int(sum(r["status"] == 0 for r in rep))},
         "roofline": roof,
@@ -321,7 +326,7 @@ def run_surrogate(args, wl):
 
     n = wl["n"]
     rve = RVE(*generate_plain_weave(n, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic",
-              precision="fp32_refined", rtol=1e-10, max_iter=50000)
+              precision="fp32_refined", rtol=args.rtol, inner_rtol=args.inner_rtol, max_iter=50000)
     # ---- training set: RVE solves of seeded degraded records
     params = ci.draw_params(0, args.train)
     chunk = 512

@@ -547,9 +547,9 @@ static int autotune_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp
     CHOM_HIP(hipMemsetAsync(W.ycoef.p, 0, sizeof(double) * W.ycoef.n, s));
     const int rgs_mech[3] = {1, 2, 3}, rgs_scal[2] = {1, 3};
     const int *rgs = (C == 3) ? rgs_mech : rgs_scal;
-    const int nrg = (C == 3) ? 3 : 2;
+    const int nrg = W.L.order != 2 ? 0 : (C == 3) ? 3 : 2;   // orders 3, 4 always take all load cases
     double best = 1e30;
-    int best_rg = *rg_out;
+    int best_rg = W.L.order == 2 ? *rg_out : R;
     for (int i = 0; i < nrg; ++i) {
         double ms;
         if (f32) CHOM_TRY((time_op<float, C, R>(B, W, W.pf.p, W.qf.p, rgs[i], 5, &ms)));
@@ -559,7 +559,7 @@ static int autotune_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp
             best_rg = rgs[i];
         }
     }
-    W.L.rg = W.L.order == 2 ? best_rg : R;   // orders 3, 4 always take all load cases
+    W.L.rg = best_rg;
     const int nwgs[4] = {128, 256, 512, 1024};
     best = 1e30;
     int best_nwg = W.L.nwg;
@@ -587,7 +587,8 @@ static std::string tune_key(chom_batch *B, int physics) {
     for (auto &ch : name)
         if (ch == ' ' || ch == ':') ch = '_';
     std::string key = name + "/" + (physics == 0 ? "mech" : "scal") + "/" +
-                      (B->opt.precision == CHOM_FP32_REFINED ? "f32" : "f64") + "/";
+                      (B->opt.precision == CHOM_FP32_REFINED ? "f32" : "f64") + "/p" +
+                      std::to_string(B->distinct.empty() ? 2 : B->distinct[0]->order) + "/";
     std::map<std::pair<int, int>, int> sizes;
     for (auto *r : B->entries) sizes[{r->n, r->bc}] += 1;
     for (auto &kv : sizes)
