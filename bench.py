@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--items", type=int, default=512, help="items of the c2 batch")
+    ap.add_argument("--precond", default="two_level", choices=["block_jacobi", "two_level"],
+                    help="CG preconditioner (two_level: block Jacobi plus a P1 multigrid coarse correction)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed launch shape instead of the library's autotuner (which runs in the warm-up)")
     ap.add_argument("--order", type=int, default=4, help="c3: polynomial order (3 or 4)")
@@ -178,7 +180,8 @@ def main():
     if args.workload == "c4":
         return run_surrogate(args, wl)
     from paper_1610_03484_amd import Batch
-    opts = dict(precision=wl["precision"], rtol=args.rtol, inner_rtol=args.inner_rtol, max_iter=50000)
+    opts = dict(precision=wl["precision"], rtol=args.rtol, inner_rtol=args.inner_rtol, max_iter=50000,
+                precond=args.precond)
     if args.workload == "c2":
         sizes = ci.batch_sizes_c2(0, args.items)
         params = ci.draw_params(0, args.items)
@@ -292,7 +295,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "path": "batched", "rves_per_step": len(rves),
                    "rtol": args.rtol, "inner_rtol": args.inner_rtol,
-                   "autotuned": os.environ.get("CHOM_AUTOTUNE") is not None,
+                   "autotuned": os.environ.get("CHOM_AUTOTUNE") is not None, "precond": args.precond,
                    "c_hom_rel_err_vs_fp64_gpu": err, "launch": batch.launch_config(),
                    "converged": int(sum(r["status"] == 0 for r in rep))},
         "roofline": roof,

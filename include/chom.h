@@ -55,7 +55,15 @@ enum {
 
 enum { CHOM_BC_DIRICHLET = 0, CHOM_BC_PERIODIC = 1, CHOM_BC_NEUMANN = 2 };
 enum { CHOM_FP64 = 0, CHOM_FP32_REFINED = 1 };
-enum { CHOM_PRECOND_BLOCK_JACOBI = 0 };
+/* Preconditioners of the CG solves (the paper factorises directly, Sec. 2):
+ * CHOM_PRECOND_BLOCK_JACOBI: the inverse point blocks M^-1 of K.
+ * CHOM_PRECOND_TWO_LEVEL: M^-1 + P V P^T, with P the injection of the vertex
+ *   (P1) values -- the vertex functions of the hierarchic basis are the P1 hats,
+ *   so P^T K P is the P1 stiffness -- and V one symmetric V-cycle on the P1
+ *   spaces of the Kuhn grids with n, n/2, ... cells (Galerkin coarse matrices,
+ *   l1 block-Jacobi smoothing).  RVEs with odd n or n < 6 have no coarse grid
+ *   and take block Jacobi alone. */
+enum { CHOM_PRECOND_BLOCK_JACOBI = 0, CHOM_PRECOND_TWO_LEVEL = 1 };
 
 typedef struct chom_rve chom_rve;
 typedef struct chom_batch chom_batch;
@@ -106,11 +114,14 @@ typedef struct {
 
 typedef struct {
     int32_t precision;     /* CHOM_FP64 or CHOM_FP32_REFINED                           */
-    int32_t precond;       /* CHOM_PRECOND_BLOCK_JACOBI                                */
+    int32_t precond;       /* CHOM_PRECOND_BLOCK_JACOBI or CHOM_PRECOND_TWO_LEVEL      */
     int32_t max_iter;      /* CG iteration cap per solve (per inner solve when refined) */
     int32_t max_refine;    /* refinement steps cap (CHOM_FP32_REFINED)                 */
-    double rtol;           /* stop when r.M^-1 r <= rtol^2 * (linear-field energy)    */
-    double inner_rtol;     /* FP32 inner solves: reduce r.M^-1 r by inner_rtol^2       */
+    double rtol;           /* stop when r.M^-1 r <= rtol^2 * (linear-field energy)
+                              (FP64 solves with the two-level preconditioner test
+                              r.B r >= r.M^-1 r, which is stricter)                   */
+    double inner_rtol;     /* FP32 inner solves: reduce r.B r by inner_rtol^2, B the
+                              preconditioner                                           */
     double c_sat;          /* moisture content (wt%) with gamma = 1                    */
     int32_t degrade_yarn;  /* 1: the damage factor also scales the yarn moduli         */
     int32_t device_ptrs;   /* 1: params and outputs of chom_homogenise are on device  */

@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "CHOM_OK", -1: "CHOM_EINVAL", -2: "CHOM_EMESH", -3: "CHOM_EMA
                 -4: "CHOM_ENOCONV", -5: "CHOM_EDEVICE", -6: "CHOM_ENOMEM"}
 BC = {"dirichlet": 0, "periodic": 1, "neumann": 2}
 PRECISION = {"fp64": 0, "fp32_refined": 1}
+PRECOND = {"block_jacobi": 0, "two_level": 1}
 
 
 class ChomMesh(ct.Structure):

@@ -17,6 +17,8 @@ def default_options(**kw) -> L.ChomOptions:
     L.check(L.lib().chom_default_options(ct.byref(o)), "chom_default_options")
     if "precision" in kw and isinstance(kw["precision"], str):
         kw["precision"] = L.PRECISION[kw["precision"]]
+    if "precond" in kw and isinstance(kw["precond"], str):
+        kw["precond"] = L.PRECOND[kw["precond"]]
     for k, v in kw.items():
         if k == "hip_stream":
             v = ct.c_void_p(v)

@@ -142,6 +142,11 @@ template <int C, int R> struct ClassWS {
     DevBuf<double> partial, avg_out, sums;
     DevBuf<double> ef64;                 // orders 3, 4: element factors
     DevBuf<float> ef32;
+    // two-level preconditioner: FP64 setup arrays, the solve-precision copies,
+    // level vectors, W = V P^T C^T, Gram matrices (non-inverted) and C B C^T inverse
+    DevBuf<double> mgA64, mgD64, mgrows1, gmat, ginv_mg;
+    DevBuf<float> mgA32, mgD32, mgr32, mgxp32, mgres32, mgx32, mgW32;
+    DevBuf<double> mgr64, mgxp64, mgres64, mgx64, mgW64;
     std::vector<ColState> h_cols, h_cols_outer;
     std::vector<int> h_active;
     std::vector<int> refine_steps;
@@ -232,15 +237,31 @@ template <int C, int R>
 static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, int rg, int nwg_override) {
     constexpr int MS = ClassWS<C, R>::MS;
     const int nprob = (int)hp.size();
-    long long voff = 0, doff = 0, qoff = 0, eoff = 0, max_pts = 0, max_tets = 0;
+    long long voff = 0, doff = 0, qoff = 0, eoff = 0, moff = 0, max_pts = 0, max_tets = 0;
     constexpr int NQ = (3 * C) * (3 * C + 1) / 2;
-    int max_tiles = 0, nr = 0;
+    int max_tiles = 0, nr = 0, mg_nlev = 0;
+    long long mg_max_pts[MG_MAXLEV] = {}, mg_coarse_pts = 0, mg_deep_pts = 0;
+    const bool want_mg = B->opt.precond == CHOM_PRECOND_TWO_LEVEL;
     for (auto &P : hp) {
         const Geo &G = B->distinct[P.geo]->geo;
         P.voff = voff;
         P.doff = doff;
         P.qoff = qoff;
         P.eoff = eoff;
+        P.moff = moff;
+        if (want_mg && G.mg_nlev >= 3) {
+            moff += G.mg_pts;
+            mg_nlev = std::max(mg_nlev, G.mg_nlev);
+            long long deep = 0;
+            for (int l = 0; l < G.mg_nlev; ++l) {
+                const long long np = (long long)G.mg_lw[l] * G.mg_lw[l] * G.mg_lw[l];
+                mg_max_pts[l] = std::max(mg_max_pts[l], np);
+                if (l >= 2) deep += np;
+            }
+            const int lc = G.mg_nlev - 1;
+            mg_deep_pts = std::max(mg_deep_pts, deep);
+            mg_coarse_pts = std::max(mg_coarse_pts, (long long)G.mg_lw[lc] * G.mg_lw[lc] * G.mg_lw[lc]);
+        }
         if (G.p != 2) eoff += 6LL * G.n * G.n * G.n * NQ;
         voff += G.npts * R * C;
         doff += G.npts;
@@ -313,6 +334,70 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     part = std::max(part, (size_t)nprob * W.nwg_gram * 2 * 60);
     part = std::max(part, (size_t)nprob * W.nwg_avg * R * NC);
     part = std::max(part, (size_t)nprob * L.nwg * R * C * 4 + (size_t)nprob * R * C * 4);
+    // two-level preconditioner
+    Launch::Mg &M = L.mg;
+    std::memset(&M, 0, sizeof(M));
+    M.on = mg_nlev >= 3 ? 1 : 0;
+    if (M.on) {
+        constexpr int CC = C * C;
+        M.nlev = mg_nlev;
+        for (int l = 0; l < mg_nlev; ++l) {
+            M.max_pts[l] = mg_max_pts[l];
+            M.nwg[l] = (int)std::min<long long>(std::max<long long>((mg_max_pts[l] + 63) / 64, 1), 1024);
+        }
+        const char *sw = std::getenv("CHOM_MG_SWEEPS");
+        M.sweeps = sw ? std::max(1, std::atoi(sw)) : 20;
+        M.pbase = L.nwg;
+        M.pstride = L.nwg + M.nwg[1];
+        M.total_pts = moff;
+        // LDS of the fused kernel: the four vectors of levels >= 2, then the coarsest stencils
+        const long long tsz = fp32 ? (long long)sizeof(float) : (long long)sizeof(double);
+        const long long vec_el = 4 * mg_deep_pts * C, sten_el = mg_coarse_pts * MG_SLOTS * CC;
+        const long long budget = 60 * 1024;
+        M.lds_vec = vec_el * tsz <= budget ? 1 : 0;
+        M.lds_sten = (M.lds_vec && (vec_el + sten_el) * tsz <= budget) ? 1 : 0;
+        M.lds_elems = (M.lds_vec ? vec_el : 0) + (M.lds_sten ? sten_el : 0);
+        const size_t np = (size_t)moff;
+        CHOM_HIP(W.mgA64.ensure(np * MG_SLOTS * CC));
+        CHOM_HIP(W.mgD64.ensure(np * MS));
+        CHOM_HIP(W.mgrows1.ensure(np * 4));
+        M.rows1 = W.mgrows1.p;
+        CHOM_HIP(W.gmat.ensure((size_t)2 * nprob * (C * 4) * (C * 4)));
+        CHOM_HIP(W.ginv_mg.ensure((size_t)nprob * (C * 4) * (C * 4)));
+        M.A64 = W.mgA64.p;
+        M.D64 = W.mgD64.p;
+        if (fp32) {
+            CHOM_HIP(W.mgA32.ensure(np * MG_SLOTS * CC));
+            CHOM_HIP(W.mgD32.ensure(np * MS));
+            CHOM_HIP(W.mgr32.ensure(np * R * C));
+            CHOM_HIP(W.mgxp32.ensure(np * R * C));
+            CHOM_HIP(W.mgres32.ensure(np * R * C));
+            CHOM_HIP(W.mgx32.ensure(np * R * C));
+            CHOM_HIP(W.mgW32.ensure(np * 4 * C * C));
+            M.A = W.mgA32.p;
+            M.Dinv = W.mgD32.p;
+            M.r = W.mgr32.p;
+            M.xp = W.mgxp32.p;
+            M.res = W.mgres32.p;
+            M.x = W.mgx32.p;
+            M.W = W.mgW32.p;
+        } else {
+            CHOM_HIP(W.mgr64.ensure(np * R * C));
+            CHOM_HIP(W.mgxp64.ensure(np * R * C));
+            CHOM_HIP(W.mgres64.ensure(np * R * C));
+            CHOM_HIP(W.mgx64.ensure(np * R * C));
+            CHOM_HIP(W.mgW64.ensure(np * 4 * C * C));
+            M.A = W.mgA64.p;
+            M.Dinv = W.mgD64.p;
+            M.r = W.mgr64.p;
+            M.xp = W.mgxp64.p;
+            M.res = W.mgres64.p;
+            M.x = W.mgx64.p;
+            M.W = W.mgW64.p;
+        }
+        part = std::max(part, (size_t)nprob * M.pstride * R * (2 + C * 4));
+        part = std::max(part, (size_t)nprob * W.nwg_gram * 144);
+    }
     CHOM_HIP(W.partial.ensure(part));
     CHOM_HIP(W.avg_out.ensure((size_t)nprob * R * NC));
     CHOM_HIP(W.sums.ensure((size_t)nprob * R * (2 + C * 4)));
@@ -325,22 +410,29 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     L.sums = W.sums.p;
     const void *after[4] = {W.xd.p, W.xf.p, W.partial.p, W.probs.p};
     if (std::memcmp(before, after, sizeof(before)) != 0 || old.nprob != L.nprob || old.nwg != L.nwg ||
-        old.max_tiles != L.max_tiles || old.nr != L.nr || old.rg != L.rg)
+        old.max_tiles != L.max_tiles || old.nr != L.nr || old.rg != L.rg ||
+        std::memcmp(&old.mg, &L.mg, sizeof(L.mg)) != 0)
         ++W.gen;
     return CHOM_OK;
 }
 
-// One CG iteration (5 kernels).
+// One CG iteration (5 kernels, plus the V-cycle with the two-level preconditioner).
 template <typename T, int C, int R>
 static hipError_t cg_iteration(ClassWS<C, R> &W, T *x, T *r, T *z, T *p, T *q, const void *minv,
                                const double *ginv, double rtol2, int use_init, hipStream_t s) {
     const Launch &L = W.L;
+    const bool mg = L.mg.on != 0;
+    const int ps = mg ? L.mg.pstride : L.nwg;
     hipError_t e;
-    if ((e = launch_cg_dir<T, C, R>(L, r, z, p, minv, W.ycoef.p, W.cols.p, W.active.p, s)) != hipSuccess) return e;
+    if ((e = launch_cg_dir<T, C, R>(L, r, z, p, minv, W.ycoef.p, W.cols.p, W.active.p, s, mg ? L.mg.x : nullptr,
+                                    mg ? L.mg.W : nullptr)) != hipSuccess)
+        return e;
     if ((e = launch_operator<T, C, R>(L, L.nprob, L.rg, p, q, W.partial.p, W.active.p, s)) != hipSuccess) return e;
     if ((e = launch_finish_alpha<C, R>(L, W.partial.p, W.cols.p, s)) != hipSuccess) return e;
-    if ((e = launch_cg_update<T, C, R>(L, x, r, z, p, q, minv, W.cols.p, W.partial.p, W.active.p, s)) != hipSuccess) return e;
-    return launch_finish_beta<C, R>(L, W.partial.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 0, rtol2, use_init, nullptr, s);
+    if ((e = launch_cg_update<T, C, R>(L, x, r, z, p, q, minv, W.cols.p, W.partial.p, W.active.p, s, ps)) != hipSuccess) return e;
+    if (mg && (e = launch_mg_vcycle<T, C, R>(L, r, W.partial.p, W.active.p, s)) != hipSuccess) return e;
+    return launch_finish_beta<C, R>(L, W.partial.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 0, rtol2, use_init, nullptr,
+                                    s, ps);
 }
 
 // PCG on one class of problems: b -> x (vectors of precision T).  Iterations
@@ -352,9 +444,12 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x
                const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask) {
     hipStream_t s = B->stream;
     const Launch &L = W.L;
-    CHOM_HIP((launch_cg_init<T, C, R>(L, b, x, r, z, minv, W.partial.p, s)));
+    const bool mg = L.mg.on != 0;
+    const int ps = mg ? L.mg.pstride : L.nwg;
+    CHOM_HIP((launch_cg_init<T, C, R>(L, b, x, r, z, minv, W.partial.p, s, ps)));
+    if (mg) CHOM_HIP((launch_mg_vcycle<T, C, R>(L, r, W.partial.p, nullptr, s)));
     CHOM_HIP((launch_finish_beta<C, R>(L, W.partial.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 1, rtol2,
-                                       mask ? 1 : use_init, mask, s)));
+                                       mask ? 1 : use_init, mask, s, ps)));
     const int max_iter = B->opt.max_iter;
     const int chunk = 8;
     const bool use_graph = std::getenv("CHOM_NO_GRAPH") == nullptr;
@@ -403,13 +498,30 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
     CHOM_HIP(hipMemsetAsync(W.bad.p, 0, sizeof(int), s));
     if (L.order != 2) CHOM_HIP((launch_factors_hp<C>(L, W.ef64.p, W.ef32.p, s)));
     CHOM_HIP((launch_precond<C>(L, W.total_pts, W.diag.p, W.minv64.p, W.minv32.p, s)));
-    CHOM_HIP((launch_gram<C>(L, W.minv64.p, W.minv32.p, W.partial.p, W.nwg_gram, W.ginv64.p, W.ginv32.p, W.bad.p, s)));
+    const bool mg = L.mg.on != 0;
+    CHOM_HIP((launch_gram<C>(L, W.minv64.p, W.minv32.p, W.partial.p, W.nwg_gram, W.ginv64.p, W.ginv32.p, W.bad.p, s,
+                             mg ? W.gmat.p : nullptr)));
+    const double *ginv_inner64 = W.ginv64.p, *ginv_inner32 = W.ginv32.p;
+    if (mg) {
+        const size_t SS = (size_t)(C * 4) * (C * 4);
+        if (B->opt.precision == CHOM_FP64) {
+            CHOM_HIP((launch_mg_stencils<double, C>(L, (double *)nullptr, (double *)nullptr, s)));
+            CHOM_HIP((launch_mg_gram<double, C, R>(L, W.pd.p, W.gmat.p, W.partial.p, W.nwg_gram, W.ginv_mg.p,
+                                                   W.bad.p, s)));
+            ginv_inner64 = W.ginv_mg.p;
+        } else {
+            CHOM_HIP((launch_mg_stencils<float, C>(L, W.mgA32.p, W.mgD32.p, s)));
+            CHOM_HIP((launch_mg_gram<float, C, R>(L, W.pf.p, W.gmat.p + SS * nprob, W.partial.p, W.nwg_gram,
+                                                  W.ginv_mg.p, W.bad.p, s)));
+            ginv_inner32 = W.ginv_mg.p;
+        }
+    }
     CHOM_HIP((launch_rhs<C, R>(L, W.total_vals, W.b.p, W.cols.p, s)));
     const double rtol2 = B->opt.rtol * B->opt.rtol;
     double *x64 = nullptr;
     if (B->opt.precision == CHOM_FP64) {
         CHOM_TRY((pcg<double, C, R>(B, W, W.graph64, W.b.p, W.xd.p, W.rd.p, W.zd.p, W.pd.p, W.qd.p, W.minv64.p,
-                                    W.ginv64.p, rtol2, 0, nullptr)));
+                                    ginv_inner64, rtol2, 0, nullptr)));
         x64 = W.xd.p;
     } else {
         const double irtol2 = B->opt.inner_rtol * B->opt.inner_rtol;
@@ -435,7 +547,7 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
             }
             if (act == 0 || step == B->opt.max_refine) break;
             CHOM_TRY((pcg<float, C, R>(B, W, W.graph32, W.r32.p, W.xf.p, W.rf.p, W.zf.p, W.pf.p, W.qf.p, W.minv32.p,
-                                       W.ginv32.p, irtol2, 1, W.cols_outer.p)));
+                                       ginv_inner32, irtol2, 1, W.cols_outer.p)));
             CHOM_HIP(launch_axpy_x64(W.total_vals, W.x64.p, W.xf.p, s));
             CHOM_HIP((launch_operator<double, C, R>(L, nprob, L.rg, W.x64.p, W.q64.p,
                                                     W.partial.p, nullptr, s)));
@@ -747,7 +859,7 @@ static int check_options(const chom_options &o) {
         set_error("unknown precision");
         return CHOM_EINVAL;
     }
-    if (o.precond != CHOM_PRECOND_BLOCK_JACOBI) {
+    if (o.precond != CHOM_PRECOND_BLOCK_JACOBI && o.precond != CHOM_PRECOND_TWO_LEVEL) {
         set_error("unknown preconditioner");
         return CHOM_EINVAL;
     }
@@ -1027,6 +1139,7 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
     G.by = order * G.tcy + 1;
     G.bz = order * G.tcz + 1;
     G.boxpts = G.bx * G.by * G.bz;
+    mg_levels(G);
     for (int t = 0; t < 6; ++t) {
         int p0, p1;
         kuhn_perm(t, p0, p1);

@@ -27,39 +27,23 @@
 
 namespace chom {
 
-template <typename T, int C>
-__device__ inline void minv_apply(const T *Mi, const T v[C], T out[C]) {
-    if constexpr (C == 3) {
-        out[0] = Mi[0] * v[0] + Mi[3] * v[1] + Mi[5] * v[2];
-        out[1] = Mi[3] * v[0] + Mi[1] * v[1] + Mi[4] * v[2];
-        out[2] = Mi[5] * v[0] + Mi[4] * v[1] + Mi[2] * v[2];
-    } else {
-        out[0] = Mi[0] * v[0];
-    }
-}
-
-__device__ inline void wave_partials(const double *acc, int REC, double *partial, int prob, int R, int w) {
+// Partial record of this wave: slot `slot` of `stride` slots per entry.
+__device__ inline void wave_partials(const double *acc, int REC, double *partial, int prob, int R, int w,
+                                     int stride, int slot) {
     const int lane = threadIdx.x & 63;
     for (int k = 0; k < REC; ++k) {
         const double s = wave_sum(acc[k]);
-        if (lane == 0) partial[(((long long)prob * R + w) * REC + k) * gridDim.x + blockIdx.x] = s;
+        if (lane == 0) partial[(((long long)prob * R + w) * REC + k) * stride + slot] = s;
     }
 }
-
-template <int NR>
-__device__ inline void load_rows(const Geo &G, long long pt, double row[4]) {
-    row[0] = row[1] = row[2] = row[3] = 0.0;
-    if constexpr (NR > 0) {
-        const int nr = G.nrow < NR ? G.nrow : NR;
-        const int rf = row_first(G.nrow);
-        for (int a = 0; a < nr; ++a) row[a] = G.rows[4 * pt + rf + a];
-    }
+__device__ inline void wave_partials(const double *acc, int REC, double *partial, int prob, int R, int w) {
+    wave_partials(acc, REC, partial, prob, R, w, gridDim.x, blockIdx.x);
 }
 
 // r = b, x = 0, z0 = M^-1 r; partial sums.  WRITE = false: only the sums.
 template <typename T, int C, int R, int NR, bool WRITE>
 __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const Prob *probs, const T *b, T *x,
-                                                         T *r, T *z, const T *minv, double *partial) {
+                                                         T *r, T *z, const T *minv, double *partial, int pstride) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int REC = 2 + C * NR;
     const int prob = blockIdx.y;
@@ -100,14 +84,18 @@ __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const 
             for (int a = 0; a < NR; ++a) acc[2 + c * NR + a] += row[a] * (double)zv[c];
         }
     }
-    wave_partials(acc, REC, partial, prob, R, w);
+    wave_partials(acc, REC, partial, prob, R, w, pstride, blockIdx.x);
 }
 
-// z = z0 - M^-1 C^T y ; r = r - C^T y ; p = z + beta p.
+// z = z0 - M^-1 C^T y ; r = r - C^T y ; p = z + beta p.  With the two-level
+// preconditioner (mg.on) the vertex points also take the coarse correction
+// z += Q (e1 - W y), e1 = V Q^T r, W = V Q^T C^T, Q = P_0 P_1 (P_0 injects vertex
+// values, P_1 interpolates from the n/2 grid).
 template <typename T, int C, int R, int NR>
 __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const Prob *probs, T *r, const T *z,
                                                         T *p, const T *minv, const double *ycoef,
-                                                        const ColState *cols, const int *prob_active) {
+                                                        const ColState *cols, const int *prob_active,
+                                                        MgDir<T> mg) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int S = C * NR;
     const int prob = blockIdx.y;
@@ -150,6 +138,53 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
                 }
             }
         }
+        if (mg.on && G.mg_nlev > 0) {
+            int X, Y, Z;
+            lattice_xyz(G, pt, X, Y, Z);
+            const int pp = G.p;
+            if (X % pp == 0 && Y % pp == 0 && Z % pp == 0) {
+                // vertex (i, j, k); its level-1 parents: itself halved, or the two ends of
+                // the level-1 Kuhn edge whose midpoint it is
+                const int i = X / pp, j = Y / pp, k = Z / pp;
+                const int px = i & 1, py = j & 1, pz = k & 1;
+                const int n1 = G.mg_n[1], lw1 = G.mg_lw[1];
+                const bool per1 = G.bc == 1;
+                double add[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) add[c] = 0.0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int sg = h == 0 ? -1 : 1;
+                    int a1 = (i + sg * px) >> 1, b1 = (j + sg * py) >> 1, c1 = (k + sg * pz) >> 1;
+                    if (per1) {
+                        if (a1 == n1) a1 = 0;
+                        if (b1 == n1) b1 = 0;
+                        if (c1 == n1) c1 = 0;
+                    }
+                    const long long J = G.mg_off[1] + a1 + (long long)lw1 * (b1 + (long long)lw1 * c1);
+                    const T *e = mg.x0 + (P.moff * R + (long long)w * G.mg_pts + J) * C;
+                    double f[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) f[c] = (double)e[c];
+                    if constexpr (NR > 0) {
+                        if (proj) {
+                            const int nr = G.nrow;
+                            for (int ci = 0; ci < C; ++ci)
+                                for (int a = 0; a < nr; ++a) {
+                                    const double yy = yv[ci * NR + a];
+                                    const T *Wv = mg.W + ((P.moff + J) * (4 * C) + ci * 4 + a) * C;
+#pragma unroll
+                                    for (int c = 0; c < C; ++c) f[c] -= yy * (double)Wv[c];
+                                }
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < C; ++c) add[c] += 0.5 * f[c];
+                }
+#pragma unroll
+                for (int c = 0; c < C; ++c) zv[c] = (T)((double)zv[c] + add[c]);
+            }
+        }
         if (beta == 0.0) {   // first step (p not yet defined) or finished column
 #pragma unroll
             for (int c = 0; c < C; ++c) p[o + c] = zv[c];
@@ -167,7 +202,7 @@ template <typename T, int C, int R, int NR>
 __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, const Prob *probs, int rg, T *x, T *r,
                                                            T *z, const T *p, const T *q, const T *minv,
                                                            const ColState *cols, double *partial,
-                                                           const int *prob_active) {
+                                                           const int *prob_active, int pstride) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int REC = 2 + C * NR;
     const int prob = blockIdx.y;
@@ -176,7 +211,7 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
 #pragma unroll
     for (int k = 0; k < REC; ++k) acc[k] = 0.0;
     if (prob_active[prob] == 0) {
-        wave_partials(acc, REC, partial, prob, R, w);
+        wave_partials(acc, REC, partial, prob, R, w, pstride, blockIdx.x);
         return;
     }
     const Prob &P = probs[prob];
@@ -220,7 +255,7 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
             for (int a = 0; a < NR; ++a) acc[2 + c * NR + a] += row[a] * (double)zv[c];
         }
     }
-    wave_partials(acc, REC, partial, prob, R, w);
+    wave_partials(acc, REC, partial, prob, R, w, pstride, blockIdx.x);
 }
 
 // Outer (refinement) residual projected as a vector: r64 <- r64 - C^T y with
@@ -404,32 +439,37 @@ __global__ void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, c
 
 template <typename T, int C, int R>
 hipError_t launch_cg_init(const Launch &L, const T *b, T *x, T *r, T *z, const void *minv, double *partial,
-                          hipStream_t s) {
+                          hipStream_t s, int pstride) {
     dim3 grid(L.nwg, L.nprob);
     const T *M = (const T *)minv;
+    const int ps = pstride > 0 ? pstride : L.nwg;
     if (x == nullptr) {
-        CHOM_NR_DISPATCH(L.nr, (cg_init_kernel<T, C, R, NR, false><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, b, x, r, z, M, partial)));
+        CHOM_NR_DISPATCH(L.nr, (cg_init_kernel<T, C, R, NR, false><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, b, x, r, z, M, partial, ps)));
     } else {
-        CHOM_NR_DISPATCH(L.nr, (cg_init_kernel<T, C, R, NR, true><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, b, x, r, z, M, partial)));
+        CHOM_NR_DISPATCH(L.nr, (cg_init_kernel<T, C, R, NR, true><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, b, x, r, z, M, partial, ps)));
     }
     return hipGetLastError();
 }
 
 template <typename T, int C, int R>
 hipError_t launch_cg_dir(const Launch &L, T *r, const T *z, T *p, const void *minv, const double *ycoef,
-                         const ColState *cols, const int *prob_active, hipStream_t s) {
+                         const ColState *cols, const int *prob_active, hipStream_t s, const void *mg_x0,
+                         const void *mg_W) {
     dim3 grid(L.nwg, L.nprob);
     const T *M = (const T *)minv;
-    CHOM_NR_DISPATCH(L.nr, (cg_dir_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, r, z, p, M, ycoef, cols, prob_active)));
+    MgDir<T> mg{(const T *)mg_x0, (const T *)mg_W, mg_x0 != nullptr ? 1 : 0};
+    CHOM_NR_DISPATCH(L.nr, (cg_dir_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, r, z, p, M, ycoef, cols, prob_active, mg)));
     return hipGetLastError();
 }
 
 template <typename T, int C, int R>
 hipError_t launch_cg_update(const Launch &L, T *x, T *r, T *z, const T *p, const T *q, const void *minv,
-                            const ColState *cols, double *partial, const int *prob_active, hipStream_t s) {
+                            const ColState *cols, double *partial, const int *prob_active, hipStream_t s,
+                            int pstride) {
     dim3 grid(L.nwg, L.nprob);
     const T *M = (const T *)minv;
-    CHOM_NR_DISPATCH(L.nr, (cg_update_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, L.rg, x, r, z, p, q, M, cols, partial, prob_active)));
+    const int ps = pstride > 0 ? pstride : L.nwg;
+    CHOM_NR_DISPATCH(L.nr, (cg_update_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, L.rg, x, r, z, p, q, M, cols, partial, prob_active, ps)));
     return hipGetLastError();
 }
 
@@ -451,10 +491,10 @@ hipError_t launch_finish_alpha(const Launch &L, const double *partial_pq, ColSta
 template <int C, int R>
 hipError_t launch_finish_beta(const Launch &L, const double *partial, const double *ginv, double *ycoef,
                               ColState *cols, int *prob_active, int first, double rtol2, int use_init,
-                              const ColState *mask, hipStream_t s) {
+                              const ColState *mask, hipStream_t s, int nparts) {
     const int REC = 2 + C * L.nr;
     double *sums = L.sums;
-    reduce_parts_kernel<<<dim3(R * REC, L.nprob), 64, 0, s>>>(partial, R * REC, L.nwg, sums);
+    reduce_parts_kernel<<<dim3(R * REC, L.nprob), 64, 0, s>>>(partial, R * REC, nparts > 0 ? nparts : L.nwg, sums);
     finish_beta_kernel<C, R><<<L.nprob, 64, 0, s>>>(L.geos, L.probs, L.nr, sums, ginv, ycoef, cols, prob_active,
                                                     first, rtol2, use_init, mask);
     return hipGetLastError();
@@ -599,12 +639,13 @@ hipError_t launch_project(const Launch &L, double *x64, const double *minv64, co
 // ------------------------------------------------------------------ instantiations
 #define CHOM_INST(T, C, R)                                                                                        \
     template hipError_t launch_cg_init<T, C, R>(const Launch &, const T *, T *, T *, T *, const void *, double *, \
-                                                hipStream_t);                                                    \
+                                                hipStream_t, int);                                               \
     template hipError_t launch_cg_dir<T, C, R>(const Launch &, T *, const T *, T *, const void *, const double *, \
-                                               const ColState *, const int *, hipStream_t);                      \
+                                               const ColState *, const int *, hipStream_t, const void *,         \
+                                               const void *);                                                    \
     template hipError_t launch_cg_update<T, C, R>(const Launch &, T *, T *, T *, const T *, const T *,           \
                                                   const void *, const ColState *, double *, const int *,         \
-                                                  hipStream_t);
+                                                  hipStream_t, int);
 CHOM_INST(double, 3, 6)
 CHOM_INST(float, 3, 6)
 CHOM_INST(double, 1, 3)
@@ -614,7 +655,7 @@ CHOM_INST(float, 1, 3)
     template hipError_t launch_finish_alpha<C, R>(const Launch &, const double *, ColState *, hipStream_t);      \
     template hipError_t launch_finish_beta<C, R>(const Launch &, const double *, const double *, double *,       \
                                                  ColState *, int *, int, double, int, const ColState *,          \
-                                                 hipStream_t);                                                   \
+                                                 hipStream_t, int);                                              \
     template hipError_t launch_proj_resid<C, R>(const Launch &, double *, float *, const double *,               \
                                                 const double *, double *, hipStream_t);                          \
     template hipError_t launch_residual64<C, R>(const Launch &, const double *, const double *, double *, float *, \

@@ -51,6 +51,36 @@ struct Geo {
     const double *hW, *hWd, *hSd;    // [ne], [3][ne], [9][ne]
     const double *hDA64, *hDB64;     // padded [D_1; D_2; D_3] and its transpose
     const float *hDA32, *hDB32;
+    // P1 coarse hierarchy of the two-level preconditioner (see mg.hip): level 0
+    // is the vertex lattice (the vertex functions of the hierarchic basis are the
+    // P1 hats), level l + 1 halves the cells of level l.  mg_nlev = 0: none.
+    int mg_nlev;
+    int mg_n[8];              // cells per side of level l
+    int mg_lw[8];             // stored points per side: n_l (periodic) or n_l + 1
+    long long mg_off[8];      // first point of level l within the RVE's coarse points
+    long long mg_pts;         // coarse points over all levels
+};
+
+// Kuhn neighbours of a lattice point (the P1 stencil): itself, the seven edge
+// directions of the Kuhn split, and their opposites (slot k + 7 = -slot k).
+__host__ __device__ inline void kuhn_offset(int k, int &dx, int &dy, int &dz) {
+    const int ox[8] = {0, 1, 0, 0, 1, 1, 0, 1};
+    const int oy[8] = {0, 0, 1, 0, 1, 0, 1, 1};
+    const int oz[8] = {0, 0, 0, 1, 0, 1, 1, 1};
+    const int b = k < 8 ? k : k - 7;
+    const int sg = k < 8 ? 1 : -1;
+    dx = sg * ox[b];
+    dy = sg * oy[b];
+    dz = sg * oz[b];
+}
+constexpr int MG_SLOTS = 15;
+constexpr int MG_MAXLEV = 8;
+
+// Coarse-correction operands of the CG direction kernel (two-level preconditioner).
+template <typename T> struct MgDir {
+    const T *x0;   // V-cycle output vectors, [prob: moff * R * C][R][mg_pts][C] (level 1 used)
+    const T *W;    // coarse part of B C^T: [moff + level-1 point][4 C (constraint i * 4 + a)][C]
+    int on;
 };
 
 // Per-problem descriptor (one parameter record x one physics of one RVE).
@@ -61,6 +91,7 @@ struct Prob {
     long long doff;       // offset of its per-point preconditioner data (points)
     long long qoff;       // offset of its operator tile boxes (values)
     long long eoff;       // orders 3, 4: offset of its element factors (values)
+    long long moff;       // offset of its coarse-hierarchy points (two-level preconditioner)
     int geo;              // index of its RVE geometry
     int pad_;
 };
@@ -356,6 +387,55 @@ __device__ inline void lattice_xyz(const Geo &G, long long pt, int &X, int &Y, i
     X = (int)(pt % G.Lw);
     Y = (int)((pt / G.Lw) % G.Lw);
     Z = (int)(pt / ((long long)G.Lw * G.Lw));
+}
+
+// Symmetric point block (packed xx, yy, zz, xy, yz, xz; one entry for C = 1) times v.
+template <typename T, int C>
+__device__ inline void minv_apply(const T *Mi, const T v[C], T out[C]) {
+    if constexpr (C == 3) {
+        out[0] = Mi[0] * v[0] + Mi[3] * v[1] + Mi[5] * v[2];
+        out[1] = Mi[3] * v[0] + Mi[1] * v[1] + Mi[4] * v[2];
+        out[2] = Mi[5] * v[0] + Mi[4] * v[1] + Mi[2] * v[2];
+    } else {
+        out[0] = Mi[0] * v[0];
+    }
+}
+
+// Constraint row functions of lattice point pt (the BC's rows, see Geo.rows).
+template <int NR>
+__device__ inline void load_rows(const Geo &G, long long pt, double row[4]) {
+    row[0] = row[1] = row[2] = row[3] = 0.0;
+    if constexpr (NR > 0) {
+        const int nr = G.nrow < NR ? G.nrow : NR;
+        const int rf = row_first(G.nrow);
+        for (int a = 0; a < nr; ++a) row[a] = G.rows[4 * pt + rf + a];
+    }
+}
+
+// In-place Gauss-Jordan with partial pivoting on the augmented S x 2S system
+// [A | I] (S <= 12): on success the right half holds A^-1.  Returns 0 if singular.
+__device__ inline int gauss_jordan(double A[12][24], int S) {
+    for (int c = 0; c < S; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < S; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (!(fabs(A[piv][c]) > 0.0)) return 0;
+        if (piv != c)
+            for (int k = 0; k < 2 * S; ++k) {
+                const double t = A[c][k];
+                A[c][k] = A[piv][k];
+                A[piv][k] = t;
+            }
+        const double ip = 1.0 / A[c][c];
+        for (int k = 0; k < 2 * S; ++k) A[c][k] *= ip;
+        for (int r = 0; r < S; ++r) {
+            if (r == c) continue;
+            const double f = A[r][c];
+            if (f != 0.0)
+                for (int k = 0; k < 2 * S; ++k) A[r][k] -= f * A[c][k];
+        }
+    }
+    return 1;
 }
 
 // Wavefront sum of a double (64 lanes).

@@ -37,6 +37,23 @@ struct Launch {
     long long total_q;    // values of the operator output of the class
     const double *ef64;   // orders 3, 4: element factors Q_e (packed symmetric 3C x 3C), per problem at Prob.eoff
     const float *ef32;
+    // two-level preconditioner (mg.hip); on = 0: block Jacobi alone
+    struct Mg {
+        int on;
+        int nlev;                  // largest level count among the problems
+        int nwg[MG_MAXLEV];        // workgroups per problem of the level-l kernels
+        int sweeps;                // l1 block-Jacobi sweeps on the coarsest level
+        int pbase, pstride;        // partial slots: level-0 kernel writes [pbase, pstride)
+        long long total_pts;       // coarse points of the class
+        double *A64, *D64;         // FP64 stencils and l1 inverses (setup)
+        const void *A, *Dinv;      // the same in the precision of the solve
+        void *r, *xp, *res, *x;    // level vectors [moff * R * C][R][mg_pts][C]
+        double *rows1;             // level-1 restricted constraint rows [points][4]
+        long long max_pts[MG_MAXLEV];  // largest level-l point count of the class
+        long long lds_elems;       // LDS of the fused kernel (elements of the solve precision)
+        int lds_vec, lds_sten;     // levels >= 2 vectors / coarsest stencils in LDS
+        void *W;                   // coarse part of B C^T [moff + vertex][4C][C]
+    } mg;
 };
 
 // ------------------------------------------------------------------ launchers
@@ -55,7 +72,7 @@ hipError_t launch_precond(const Launch &L, long long total_pts, double *diag, do
                           hipStream_t s);
 template <int C>
 hipError_t launch_gram(const Launch &L, const double *minv64, const float *minv32, double *gram_partial, int nwg,
-                       double *ginv64, double *ginv32, int *bad, hipStream_t s);
+                       double *ginv64, double *ginv32, int *bad, hipStream_t s, double *gmat = nullptr);
 template <int C, int R>
 hipError_t launch_rhs(const Launch &L, long long total_vals, double *b, ColState *cols, hipStream_t s);
 
@@ -65,19 +82,21 @@ hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y,
 
 template <typename T, int C, int R>
 hipError_t launch_cg_init(const Launch &L, const T *b, T *x, T *r, T *z, const void *minv, double *partial,
-                          hipStream_t s);
+                          hipStream_t s, int pstride = 0);
 template <typename T, int C, int R>
 hipError_t launch_cg_dir(const Launch &L, T *r, const T *z, T *p, const void *minv, const double *ycoef,
-                         const ColState *cols, const int *prob_active, hipStream_t s);
+                         const ColState *cols, const int *prob_active, hipStream_t s,
+                         const void *mg_x0 = nullptr, const void *mg_W = nullptr);
 template <typename T, int C, int R>
 hipError_t launch_cg_update(const Launch &L, T *x, T *r, T *z, const T *p, const T *q, const void *minv,
-                            const ColState *cols, double *partial, const int *prob_active, hipStream_t s);
+                            const ColState *cols, double *partial, const int *prob_active, hipStream_t s,
+                            int pstride = 0);
 template <int C, int R>
 hipError_t launch_finish_alpha(const Launch &L, const double *partial_pq, ColState *cols, hipStream_t s);
 template <int C, int R>
 hipError_t launch_finish_beta(const Launch &L, const double *partial, const double *ginv, double *ycoef,
                               ColState *cols, int *prob_active, int first, double rtol2, int use_init,
-                              const ColState *mask, hipStream_t s);
+                              const ColState *mask, hipStream_t s, int nparts = 0);
 template <int C, int R>
 hipError_t launch_proj_resid(const Launch &L, double *r64, float *r32, const double *minv64,
                              const double *ycoef, double *partial, hipStream_t s);
@@ -93,6 +112,25 @@ hipError_t launch_average(const Launch &L, const double *x64, double *partial, i
                           hipStream_t s);
 
 void set_error(const std::string &msg);
+
+// ------------------------------------------------------------------ two-level preconditioner (mg.hip)
+// Fills G.mg_*: level 0 is the vertex lattice of the n^3 grid; a level is
+// halved while its cell count is even and the half is at least 3 (so periodic
+// neighbours never alias).  No hierarchy (mg_nlev = 0) unless there are at least
+// three levels (n divisible by 4, n >= 12).
+void mg_levels(Geo &G);
+// Stencils of every level (FP64), their l1 inverses, and the copies in T.
+template <typename T, int C> hipError_t launch_mg_stencils(const Launch &L, T *A, T *Dinv, hipStream_t s);
+// One V-cycle on the vertex values of the fine vectors r (all load cases):
+// output in L.mg.x (level 0 block); with `partial`, the level-0 kernel also
+// writes r.e0 and C P e0 into partial slots [pbase, pbase + nwg[0]).
+template <typename T, int C, int R>
+hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *partial, const int *prob_active, hipStream_t s);
+// W = V P^T C^T (constraint columns, in batches of R) using `tmp` (a fine
+// vector), then the Gram matrix C B C^T = gmat + C P W and its inverse.
+template <typename T, int C, int R>
+hipError_t launch_mg_gram(const Launch &L, T *tmp, const double *gmat, double *partial, int nwg, double *ginv,
+                          int *bad, hipStream_t s);
 
 // orders 3, 4 (hp.hip)
 hipError_t launch_rows_hp(const Geo &G, double *rows, hipStream_t s);

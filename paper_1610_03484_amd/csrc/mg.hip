@@ -1,0 +1,976 @@
+// Two-level preconditioner for CG on the order-p hierarchic systems.
+//
+// The paper factorises the RVE system directly (Sec. 2); for CG this library
+// adds a coarse space to the point-block Jacobi matrix M:
+//
+//   B = M^-1 + Q V Q^T,   Q = P_0 P_1.
+//
+// P_0 injects vertex values: the vertex functions of the hierarchic basis are
+// the P1 hats, so P_0^T K P_0 is the P1 stiffness matrix A_0 of the same tets
+// (no triple product).  The P1 spaces of the Kuhn grids with n, n/2, n/4, ...
+// cells nest -- the Kuhn split of a grid is refined by the Kuhn split of the grid
+// with half the spacing, every fine vertex being a coarse vertex or the midpoint
+// of a coarse Kuhn edge -- so P_l is linear interpolation and the coarse matrices
+// are the Galerkin products A_{l+1} = P_l^T A_l P_l, each a 15-point stencil of
+// C x C blocks.  V is one symmetric V(1,1) cycle from level 1 (the n/2 grid)
+// down: smoothing on the vertex grid itself adds nothing to what M already does
+// there (measured: the same CG iteration counts) and is skipped.  Smoother: l1
+// block Jacobi (the diagonal block plus the absolute off-block row sums on its
+// diagonal), convergent with no damping parameter; the coarsest level takes a
+// fixed number of such sweeps.  V is therefore a fixed symmetric positive
+// definite operator and the iteration stays preconditioned CG.
+//
+// Layouts, per problem from Prob.moff (points): stencils [pt][15][C*C] (slot order
+// of kuhn_offset, block row-major: row = test component), l1 inverses [pt][MS]
+// (packed as the point-block Jacobi inverse), vectors [R][mg_pts][C], restricted
+// constraint rows of level 1 [pt][4] (FP64).  Dirichlet problems keep their
+// boundary points with zero rows and inverses, so every vector is zero there.
+#include <algorithm>
+#include <type_traits>
+
+#include "common.h"
+#include "internal.h"
+
+namespace chom {
+
+void mg_levels(Geo &G) {
+    G.mg_nlev = 0;
+    G.mg_pts = 0;
+    if (G.n % 2 != 0 || G.n < 6) return;
+    int nl = G.n, cnt = 0;
+    long long off = 0;
+    while (cnt < MG_MAXLEV) {
+        G.mg_n[cnt] = nl;
+        G.mg_lw[cnt] = (G.bc == 1) ? nl : nl + 1;
+        G.mg_off[cnt] = off;
+        off += (long long)G.mg_lw[cnt] * G.mg_lw[cnt] * G.mg_lw[cnt];
+        ++cnt;
+        if (nl % 2 != 0 || nl / 2 < 3) break;
+        nl /= 2;
+    }
+    if (cnt < 3) return;   // the coarse space starts on level 1 and needs a level below it
+    G.mg_nlev = cnt;
+    G.mg_pts = off;
+}
+
+namespace {
+
+constexpr int MG_BS = 256;
+
+inline int grid_cap(long long work, int bs, int cap) {
+    long long g = (work + bs - 1) / bs;
+    if (g < 1) g = 1;
+    return (int)(g < cap ? g : cap);
+}
+
+struct Lev {
+    int n, lw, per, dir;
+    long long off;
+};
+
+__device__ inline Lev level_of(const Geo &G, int l) {
+    Lev V;
+    V.n = G.mg_n[l];
+    V.lw = G.mg_lw[l];
+    V.off = G.mg_off[l];
+    V.per = G.bc == 1;
+    V.dir = G.bc == 0;
+    return V;
+}
+
+__device__ inline int wrap(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Index of level point (i, j, k) (any integers for periodic levels), or -1 outside.
+__device__ inline long long lev_index(const Lev &V, int i, int j, int k) {
+    if (V.per) {
+        i = wrap(i, V.n);
+        j = wrap(j, V.n);
+        k = wrap(k, V.n);
+    } else if (i < 0 || j < 0 || k < 0 || i > V.n || j > V.n || k > V.n) {
+        return -1;
+    }
+    return (long long)i + (long long)V.lw * ((long long)j + (long long)V.lw * k);
+}
+
+__device__ inline bool lev_boundary(const Lev &V, int i, int j, int k) {
+    return V.dir && (i == 0 || j == 0 || k == 0 || i == V.n || j == V.n || k == V.n);
+}
+
+// Coordinates of level point pt (levels hold far fewer than 2^31 points).
+__device__ inline void lev_xyz(const Lev &V, long long pt, int &i, int &j, int &k) {
+    const int q = (int)pt, lw = V.lw;
+    const int t = q / lw;
+    i = q - t * lw;
+    k = t / lw;
+    j = t - k * lw;
+}
+
+// ------------------------------------------------------------------ setup (FP64)
+// Level 0: A_0[I][s] = sum over tets holding I and J = I + offset(s) of
+// |e| (grad lam_J . C . grad lam_I) (mechanics: the C x C block with
+// entry [c][d] = |e| sum_j sigma(sym(e_d x g_J))[c][j] g_I[j]).
+template <int C>
+__global__ void mg_assemble0_kernel(const Geo *geos, const Prob *probs, double *A64) {
+    constexpr int CC = C * C;
+    const Prob &P = probs[blockIdx.y];
+    const Geo &G = geos[P.geo];
+    if (G.mg_nlev == 0) return;
+    const Lev V = level_of(G, 0);
+    const int n = G.n;
+    const long long np = (long long)V.lw * V.lw * V.lw;
+    double *Ap = A64 + (P.moff + V.off) * MG_SLOTS * CC;
+    for (long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x; u < np * MG_SLOTS;
+         u += (long long)gridDim.x * blockDim.x) {
+        const long long pt = u / MG_SLOTS;
+        const int s = (int)(u - pt * MG_SLOTS);
+        int i, j, k, dx, dy, dz;
+        lev_xyz(V, pt, i, j, k);
+        kuhn_offset(s, dx, dy, dz);
+        double acc[CC];
+#pragma unroll
+        for (int q = 0; q < CC; ++q) acc[q] = 0.0;
+        const bool inside = V.per || (i + dx >= 0 && j + dy >= 0 && k + dz >= 0 && i + dx <= n && j + dy <= n && k + dz <= n);
+        if (inside && !lev_boundary(V, i, j, k) && !lev_boundary(V, i + dx, j + dy, k + dz)) {
+            for (int d = 0; d < 8; ++d) {
+                const int ax = d & 1, ay = (d >> 1) & 1, az = (d >> 2) & 1;   // I's corner in the cell
+                const int bx = ax + dx, by = ay + dy, bz = az + dz;            // J's corner
+                if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+                int cx = i - ax, cy = j - ay, cz = k - az;
+                if (V.per) {
+                    cx = wrap(cx, n);
+                    cy = wrap(cy, n);
+                    cz = wrap(cz, n);
+                } else if (cx < 0 || cy < 0 || cz < 0 || cx >= n || cy >= n || cz >= n) {
+                    continue;
+                }
+                for (int t = 0; t < 6; ++t) {
+                    int p0, p1;
+                    kuhn_perm(t, p0, p1);
+                    // chain of the tet: 000, e_p0, e_p0 + e_p1, 111
+                    int va = -1, vb = -1;
+                    for (int q = 0; q < 4; ++q) {
+                        int c3[3] = {0, 0, 0};
+                        if (q >= 1) c3[p0] = 1;
+                        if (q >= 2) c3[p1] = 1;
+                        if (q == 3) c3[0] = c3[1] = c3[2] = 1;
+                        if (c3[0] == ax && c3[1] == ay && c3[2] == az) va = q;
+                        if (c3[0] == bx && c3[1] == by && c3[2] == bz) vb = q;
+                    }
+                    if (va < 0 || vb < 0) continue;
+                    const long long tet = ((long long)cx + (long long)n * ((long long)cy + (long long)n * cz)) * 6 + t;
+                    double g[4][3], vol, a[3];
+                    int ph;
+                    GeoSel<double>::get(G, tet, t, g, vol);
+                    GeoSel<double>::elem(G, tet, a, ph);
+                    const double *m = P.mat64[ph ? 1 : 0];
+                    if constexpr (C == 3) {
+                        for (int dd = 0; dd < 3; ++dd) {
+                            double Gm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+                            for (int l2 = 0; l2 < 3; ++l2) Gm[dd][l2] = g[vb][l2];
+                            const double e[6] = {Gm[0][0], Gm[1][1], Gm[2][2], 0.5 * (Gm[0][1] + Gm[1][0]),
+                                                 0.5 * (Gm[1][2] + Gm[2][1]), 0.5 * (Gm[2][0] + Gm[0][2])};
+                            double sg[6];
+                            stress_ti<double>(e, a, m, sg);
+                            const double *ga = g[va];
+                            acc[0 * 3 + dd] += vol * (sg[0] * ga[0] + sg[3] * ga[1] + sg[5] * ga[2]);
+                            acc[1 * 3 + dd] += vol * (sg[3] * ga[0] + sg[1] * ga[1] + sg[4] * ga[2]);
+                            acc[2 * 3 + dd] += vol * (sg[5] * ga[0] + sg[4] * ga[1] + sg[2] * ga[2]);
+                        }
+                    } else {
+                        double fl[3];
+                        flux_ti<double>(g[vb], a, m, fl);
+                        acc[0] += vol * (fl[0] * g[va][0] + fl[1] * g[va][1] + fl[2] * g[va][2]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CC; ++q) Ap[(pt * MG_SLOTS + s) * CC + q] = acc[q];
+    }
+}
+
+// Level l + 1 from level l: A_c[I][s] = sum_{i child of I} sum_{j fine neighbour of i,
+// J parent of j, J = I + offset(s)} w_iI A_f[i][j] w_jJ.  Coordinates stay unwrapped
+// (geometric) until a level array is indexed, so a coupling is credited to the slot
+// of its geometric offset.
+template <int C>
+__global__ void mg_rap_kernel(const Geo *geos, const Prob *probs, int l, double *A64) {
+    constexpr int CC = C * C;
+    const Prob &P = probs[blockIdx.y];
+    const Geo &G = geos[P.geo];
+    if (G.mg_nlev <= l + 1) return;
+    const Lev F = level_of(G, l), Cv = level_of(G, l + 1);
+    const long long npc = (long long)Cv.lw * Cv.lw * Cv.lw;
+    const double *Af = A64 + (P.moff + F.off) * MG_SLOTS * CC;
+    double *Ac = A64 + (P.moff + Cv.off) * MG_SLOTS * CC;
+    for (long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x; u < npc * MG_SLOTS;
+         u += (long long)gridDim.x * blockDim.x) {
+        const long long pt = u / MG_SLOTS;
+        const int s = (int)(u - pt * MG_SLOTS);
+        int I, Jy, K, dx, dy, dz;
+        lev_xyz(Cv, pt, I, Jy, K);
+        kuhn_offset(s, dx, dy, dz);
+        const int TX = I + dx, TY = Jy + dy, TZ = K + dz;   // target coarse point (unwrapped)
+        double acc[CC];
+#pragma unroll
+        for (int q = 0; q < CC; ++q) acc[q] = 0.0;
+        const bool ok = lev_index(Cv, TX, TY, TZ) >= 0 && !lev_boundary(Cv, I, Jy, K) &&
+                        !lev_boundary(Cv, TX, TY, TZ);
+        if (ok) {
+            for (int m = 0; m < MG_SLOTS; ++m) {
+                int ox, oy, oz;
+                kuhn_offset(m, ox, oy, oz);
+                const int fi = 2 * I + ox, fj = 2 * Jy + oy, fk = 2 * K + oz;   // child (unwrapped)
+                const long long fidx = lev_index(F, fi, fj, fk);
+                if (fidx < 0 || lev_boundary(F, fi, fj, fk)) continue;
+                const double wi = (m == 0) ? 1.0 : 0.5;
+                for (int q = 0; q < MG_SLOTS; ++q) {
+                    int qx, qy, qz;
+                    kuhn_offset(q, qx, qy, qz);
+                    const int gx = fi + qx, gy = fj + qy, gz = fk + qz;   // fine neighbour (unwrapped)
+                    const int px = gx & 1, py = gy & 1, pz = gz & 1;
+                    double wj = 0.0;
+                    if (px == 0 && py == 0 && pz == 0) {
+                        if ((gx >> 1) == TX && (gy >> 1) == TY && (gz >> 1) == TZ) wj = 1.0;
+                    } else {
+                        if (((gx - px) >> 1) == TX && ((gy - py) >> 1) == TY && ((gz - pz) >> 1) == TZ) wj += 0.5;
+                        if (((gx + px) >> 1) == TX && ((gy + py) >> 1) == TY && ((gz + pz) >> 1) == TZ) wj += 0.5;
+                    }
+                    if (wj == 0.0) continue;
+                    const double *blk = Af + (fidx * MG_SLOTS + q) * CC;
+                    const double w = wi * wj;
+#pragma unroll
+                    for (int e = 0; e < CC; ++e) acc[e] += w * blk[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < CC; ++e) Ac[(pt * MG_SLOTS + s) * CC + e] = acc[e];
+    }
+}
+
+// l1 block-Jacobi inverse of every coarse point of the class, and the T copies.
+template <int C>
+__global__ void mg_dinv_kernel(long long total, const double *A64, double *D64) {
+    constexpr int CC = C * C;
+    constexpr int MS = (C == 3) ? 6 : 1;
+    for (long long pt = blockIdx.x * (long long)blockDim.x + threadIdx.x; pt < total;
+         pt += (long long)gridDim.x * blockDim.x) {
+        const double *row = A64 + pt * MG_SLOTS * CC;
+        double D[CC];
+#pragma unroll
+        for (int e = 0; e < CC; ++e) D[e] = row[e];
+        for (int s = 1; s < MG_SLOTS; ++s)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                double a = 0.0;
+#pragma unroll
+                for (int d = 0; d < C; ++d) a += fabs(row[s * CC + c * C + d]);
+                D[c * C + c] += a;
+            }
+        double out[MS];
+        if constexpr (C == 3) {
+            const double a = D[0], b = D[4], c = D[8];
+            const double xy = 0.5 * (D[1] + D[3]), yz = 0.5 * (D[5] + D[7]), xz = 0.5 * (D[2] + D[6]);
+            const double c00 = b * c - yz * yz, c11 = a * c - xz * xz, c22 = a * b - xy * xy;
+            const double c01 = xz * yz - xy * c, c12 = xy * xz - a * yz, c02 = xy * yz - b * xz;
+            const double det = a * c00 + xy * c01 + xz * c02;
+            const double id = det > 0.0 ? 1.0 / det : 0.0;
+            out[0] = c00 * id;
+            out[1] = c11 * id;
+            out[2] = c22 * id;
+            out[3] = c01 * id;
+            out[4] = c12 * id;
+            out[5] = c02 * id;
+        } else {
+            out[0] = D[0] > 0.0 ? 1.0 / D[0] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < MS; ++e) D64[pt * MS + e] = out[e];
+    }
+}
+
+__global__ void mg_to_float_kernel(long long n, const double *src, float *dst) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+// Level-1 restricted constraint rows: rows1[I][k] = sum over the level-0 children
+// v of I (weights 1 and 1/2) of the fine row k at vertex v (FP64, all 4 rows).
+__global__ void mg_rows1_kernel(const Geo *geos, const Prob *probs, double *rows1) {
+    const Prob &P = probs[blockIdx.y];
+    const Geo &G = geos[P.geo];
+    if (G.mg_nlev == 0) return;
+    const Lev F = level_of(G, 0), Cv = level_of(G, 1);
+    const long long np = (long long)Cv.lw * Cv.lw * Cv.lw;
+    const int p = G.p;
+    for (long long pt = blockIdx.x * (long long)blockDim.x + threadIdx.x; pt < np; pt += (long long)gridDim.x * blockDim.x) {
+        int I, J, K;
+        lev_xyz(Cv, pt, I, J, K);
+        double acc[4] = {0, 0, 0, 0};
+        for (int m = 0; m < MG_SLOTS; ++m) {
+            int ox, oy, oz;
+            kuhn_offset(m, ox, oy, oz);
+            int fi = 2 * I + ox, fj = 2 * J + oy, fk = 2 * K + oz;
+            if (lev_index(F, fi, fj, fk) < 0) continue;
+            if (F.per) {
+                fi = wrap(fi, F.n);
+                fj = wrap(fj, F.n);
+                fk = wrap(fk, F.n);
+            }
+            const long long lat = (long long)(p * fi) + (long long)G.Lw * ((long long)(p * fj) + (long long)G.Lw * (p * fk));
+            const double wgt = (m == 0) ? 1.0 : 0.5;
+            for (int k = 0; k < 4; ++k) acc[k] += wgt * G.rows[4 * lat + k];
+        }
+        for (int k = 0; k < 4; ++k) rows1[(P.moff + Cv.off + pt) * 4 + k] = acc[k];
+    }
+}
+
+// ------------------------------------------------------------------ V-cycle
+// The coarse correction starts on level 1 (the n/2 grid): its right side is
+// r_1 = P_1^T P^T r, gathered from the fine vector at the vertex lattice points.
+// Per (problem, load case) and level l the vectors are r (restricted right
+// side), xp = D^-1 r (the pre-smoothed iterate from zero), res (r - A xp; later
+// the corrected iterate xc = xp + P e_{l+1}) and x (the level's output e_l).
+// Level 1 runs over the whole grid; levels 2 .. coarsest of one (problem, load
+// case) run in one workgroup (mg_fused_kernel), in LDS when they fit.
+
+template <typename T>
+struct LV {   // vectors of one level for one (problem, load case), each [points][C]
+    T *r, *xp, *res, *x;
+};
+
+template <typename T, int C, int R>
+__device__ inline LV<T> level_vecs(const Geo &G, const Prob &P, int w, const Lev &V, T *r, T *xp, T *res, T *x) {
+    const long long o = (P.moff * R + (long long)w * G.mg_pts + V.off) * C;
+    return LV<T>{r + o, xp + o, res + o, x + o};
+}
+
+template <typename T, int C>
+__device__ inline void load_c(const T *p, T v[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = p[c];
+}
+
+template <typename T, int C>
+__device__ inline void store_c(T *p, const T v[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) p[c] = v[c];
+}
+
+// Stencil neighbour s of (i, j, k): index, or the point itself with valid = false
+// outside a non-periodic lattice.
+__device__ inline bool nbr(const Lev &V, int i, int j, int k, int s, long long self, long long &q) {
+    int dx, dy, dz;
+    kuhn_offset(s, dx, dy, dz);
+    int qi = i + dx, qj = j + dy, qk = k + dz;
+    if (V.per) {
+        qi = qi < 0 ? qi + V.n : (qi >= V.n ? qi - V.n : qi);
+        qj = qj < 0 ? qj + V.n : (qj >= V.n ? qj - V.n : qj);
+        qk = qk < 0 ? qk + V.n : (qk >= V.n ? qk - V.n : qk);
+    } else if (qi < 0 || qj < 0 || qk < 0 || qi > V.n || qj > V.n || qk > V.n) {
+        q = self;
+        return false;
+    }
+    q = (long long)qi + (long long)V.lw * ((long long)qj + (long long)V.lw * qk);
+    return true;
+}
+
+// acc -= sum_s A[s] v[q_s] (A: the point's 15 blocks; v: level vector).
+template <typename T, int C>
+__device__ inline void apply_stencil(const Lev &V, const T *Arow, const T *v, int i, int j, int k, long long pt,
+                                     T acc[C]) {
+    constexpr int CC = C * C;
+#pragma unroll
+    for (int s = 0; s < MG_SLOTS; ++s) {
+        long long q;
+        const bool ok = nbr(V, i, j, k, s, pt, q);
+        T vq[C];
+        load_c<T, C>(v + q * C, vq);
+        const T m = ok ? T(1) : T(0);
+        const T *blk = Arow + s * CC;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T t = T(0);
+#pragma unroll
+            for (int d = 0; d < C; ++d) t += blk[c * C + d] * vq[d];
+            acc[c] -= m * t;
+        }
+    }
+}
+
+// Prolongation of the level-(l+1) vector e to level-l point (i, j, k) (wrapped):
+// e at the point if all coordinates are even, else the mean of the two ends of
+// the coarse Kuhn edge whose midpoint it is.
+template <typename T, int C>
+__device__ inline void prolong(const Lev &Cv, const T *e, int i, int j, int k, T out[C]) {
+    const int px = i & 1, py = j & 1, pz = k & 1;
+    const long long a = lev_index(Cv, (i - px) >> 1, (j - py) >> 1, (k - pz) >> 1);
+    const long long b = lev_index(Cv, (i + px) >> 1, (j + py) >> 1, (k + pz) >> 1);
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = T(0.5) * (e[a * C + c] + e[b * C + c]);
+}
+
+// r_1[I] = sum over the level-0 children v of I of the fine right side at v
+// (zero on a Dirichlet boundary); xp_1 = D^-1 r_1.
+template <typename T, int C>
+__device__ inline void restrict01_pt(const Geo &G, const Prob &P, const Lev &F, const Lev &Cv, int w,
+                                     const T *fine_r, const T *Dinv1, LV<T> v1, long long pt) {
+    constexpr int MS = (C == 3) ? 6 : 1;
+    int I, J, K;
+    lev_xyz(Cv, pt, I, J, K);
+    T acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = T(0);
+    if (!lev_boundary(Cv, I, J, K)) {
+        const int p = G.p;
+        const T *fr = fine_r + P.voff + (long long)w * G.npts * C;
+#pragma unroll
+        for (int m = 0; m < MG_SLOTS; ++m) {
+            int ox, oy, oz;
+            kuhn_offset(m, ox, oy, oz);
+            int fi = 2 * I + ox, fj = 2 * J + oy, fk = 2 * K + oz;
+            bool ok = true;
+            if (F.per) {
+                fi = fi < 0 ? fi + F.n : (fi >= F.n ? fi - F.n : fi);
+                fj = fj < 0 ? fj + F.n : (fj >= F.n ? fj - F.n : fj);
+                fk = fk < 0 ? fk + F.n : (fk >= F.n ? fk - F.n : fk);
+            } else {
+                ok = fi >= 0 && fj >= 0 && fk >= 0 && fi <= F.n && fj <= F.n && fk <= F.n && !lev_boundary(F, fi, fj, fk);
+                if (!ok) fi = fj = fk = 0;
+            }
+            const long long lat = (long long)(p * fi) + (long long)G.Lw * ((long long)(p * fj) + (long long)G.Lw * (p * fk));
+            T v[C];
+            load_c<T, C>(fr + lat * C, v);
+            const T wgt = ok ? (m == 0 ? T(1) : T(0.5)) : T(0);
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += wgt * v[c];
+        }
+    }
+    store_c<T, C>(v1.r + pt * C, acc);
+    T xv[C];
+    minv_apply<T, C>(Dinv1 + pt * MS, acc, xv);
+    store_c<T, C>(v1.xp + pt * C, xv);
+}
+
+// res = r - A xp.
+template <typename T, int C>
+__device__ inline void resid_pt(const Lev &V, const T *A, LV<T> v, long long pt) {
+    constexpr int CC = C * C;
+    int i, j, k;
+    lev_xyz(V, pt, i, j, k);
+    T acc[C];
+    load_c<T, C>(v.r + pt * C, acc);
+    apply_stencil<T, C>(V, A + pt * MG_SLOTS * CC, v.xp, i, j, k, pt, acc);
+    store_c<T, C>(v.res + pt * C, acc);
+}
+
+// r_{l+1}[I] = sum of the children of I (I with weight 1, the midpoints of its
+// 14 Kuhn edges with weight 1/2) of res_l; xp_{l+1} = D^-1 r_{l+1}.
+template <typename T, int C>
+__device__ inline void restrict_pt(const Lev &F, const Lev &Cv, const T *Dinv, LV<T> vf, LV<T> vc, long long pt) {
+    constexpr int MS = (C == 3) ? 6 : 1;
+    int I, J, K;
+    lev_xyz(Cv, pt, I, J, K);
+    T acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = T(0);
+    if (!lev_boundary(Cv, I, J, K)) {
+#pragma unroll
+        for (int m = 0; m < MG_SLOTS; ++m) {
+            int ox, oy, oz;
+            kuhn_offset(m, ox, oy, oz);
+            const long long f = lev_index(F, 2 * I + ox, 2 * J + oy, 2 * K + oz);
+            const long long fs = f < 0 ? 0 : f;
+            const T wgt = f < 0 ? T(0) : (m == 0 ? T(1) : T(0.5));
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += wgt * vf.res[fs * C + c];
+        }
+    }
+    store_c<T, C>(vc.r + pt * C, acc);
+    T xv[C];
+    minv_apply<T, C>(Dinv + pt * MS, acc, xv);
+    store_c<T, C>(vc.xp + pt * C, xv);
+}
+
+// xc = xp + P e_{l+1}, stored in res.
+template <typename T, int C>
+__device__ inline void correct_pt(const Lev &V, const Lev &Cv, LV<T> v, const T *e, long long pt) {
+    int i, j, k;
+    lev_xyz(V, pt, i, j, k);
+    T xv[C];
+    load_c<T, C>(v.xp + pt * C, xv);
+    if (!lev_boundary(V, i, j, k)) {
+        T pe[C];
+        prolong<T, C>(Cv, e, i, j, k, pe);
+#pragma unroll
+        for (int c = 0; c < C; ++c) xv[c] += pe[c];
+    }
+    store_c<T, C>(v.res + pt * C, xv);
+}
+
+// x = xc + D^-1 (r - A xc).
+template <typename T, int C>
+__device__ inline void post_pt(const Lev &V, const T *A, const T *Dinv, LV<T> v, long long pt) {
+    constexpr int CC = C * C;
+    constexpr int MS = (C == 3) ? 6 : 1;
+    int i, j, k;
+    lev_xyz(V, pt, i, j, k);
+    T acc[C];
+    load_c<T, C>(v.r + pt * C, acc);
+    apply_stencil<T, C>(V, A + pt * MG_SLOTS * CC, v.res, i, j, k, pt, acc);
+    T d[C], xi[C];
+    minv_apply<T, C>(Dinv + pt * MS, acc, d);
+    load_c<T, C>(v.res + pt * C, xi);
+#pragma unroll
+    for (int c = 0; c < C; ++c) xi[c] += d[c];
+    store_c<T, C>(v.x + pt * C, xi);
+}
+
+template <typename T, int C, int R>
+struct VPtr {
+    const T *fine_r;
+    const T *A, *Dinv;
+    T *r, *xp, *res, *x;
+    const double *rows1;
+};
+
+#define MG_LEVEL_KERNEL_HEAD(LEVEL_OK)                                            \
+    const int prob = blockIdx.y;                                                  \
+    if (prob_active != nullptr && prob_active[prob] == 0) return;                 \
+    const Prob &P = probs[prob];                                                  \
+    const Geo &G = geos[P.geo];                                                   \
+    if (!(LEVEL_OK)) return;                                                      \
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+
+template <typename T, int C, int R>
+__global__ __launch_bounds__(64 * R) void mg_restrict01_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
+                                                               const int *prob_active) {
+    constexpr int MS = (C == 3) ? 6 : 1;
+    MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 3)
+    const Lev F = level_of(G, 0), V = level_of(G, 1);
+    const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
+    const T *D = Q.Dinv + (P.moff + V.off) * MS;
+    const long long np = (long long)V.lw * V.lw * V.lw;
+    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL)
+        restrict01_pt<T, C>(G, P, F, V, w, Q.fine_r, D, v, pt);
+}
+
+template <typename T, int C, int R>
+__global__ __launch_bounds__(64 * R) void mg_resid1_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
+                                                           const int *prob_active) {
+    constexpr int CC = C * C;
+    MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 3)
+    const Lev V = level_of(G, 1);
+    const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
+    const T *A = Q.A + (P.moff + V.off) * MG_SLOTS * CC;
+    const long long np = (long long)V.lw * V.lw * V.lw;
+    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) resid_pt<T, C>(V, A, v, pt);
+}
+
+template <typename T, int C, int R>
+__global__ __launch_bounds__(64 * R) void mg_correct1_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
+                                                             const int *prob_active) {
+    MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 3)
+    const Lev V = level_of(G, 1), Cv = level_of(G, 2);
+    const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
+    const LV<T> vc = level_vecs<T, C, R>(G, P, w, Cv, Q.r, Q.xp, Q.res, Q.x);
+    const long long np = (long long)V.lw * V.lw * V.lw;
+    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) correct_pt<T, C>(V, Cv, v, vc.x, pt);
+}
+
+// Level-1 post-smoothing; with `partial`, the partial sums r_1 . e_1 (= r . Q e_1)
+// and rows1 . e_1 (= C Q e_1) into slots [pbase, pbase + gridDim.x).
+template <typename T, int C, int R, int NR>
+__global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
+                                                          double *partial, int pstride, int pbase,
+                                                          const int *prob_active) {
+    constexpr int CC = C * C;
+    constexpr int MS = (C == 3) ? 6 : 1;
+    constexpr int REC = 2 + C * NR;
+    const int prob = blockIdx.y;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double pacc[REC];
+#pragma unroll
+    for (int k = 0; k < REC; ++k) pacc[k] = 0.0;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    if ((prob_active == nullptr || prob_active[prob] != 0) && G.mg_nlev >= 3) {
+        const Lev V = level_of(G, 1);
+        const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
+        const T *A = Q.A + (P.moff + V.off) * MG_SLOTS * CC;
+        const T *D = Q.Dinv + (P.moff + V.off) * MS;
+        const double *r1 = Q.rows1 + (P.moff + V.off) * 4;
+        const int rf = row_first(G.nrow);
+        const int nr = G.nrow < NR ? G.nrow : NR;
+        const long long np = (long long)V.lw * V.lw * V.lw;
+        for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) {
+            post_pt<T, C>(V, A, D, v, pt);
+            if (partial != nullptr) {
+                T rv[C], ov[C];
+                load_c<T, C>(v.r + pt * C, rv);
+                load_c<T, C>(v.x + pt * C, ov);
+                double row[4] = {0, 0, 0, 0};
+                for (int a = 0; a < nr; ++a) row[a] = r1[pt * 4 + rf + a];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    pacc[0] += (double)rv[c] * (double)ov[c];
+#pragma unroll
+                    for (int a = 0; a < NR; ++a) pacc[2 + c * NR + a] += row[a] * (double)ov[c];
+                }
+            }
+        }
+    }
+    if (partial != nullptr) {
+        for (int k = 0; k < REC; ++k) {
+            const double sum = wave_sum(pacc[k]);
+            if (lane == 0) partial[(((long long)prob * R + w) * REC + k) * pstride + pbase + blockIdx.x] = sum;
+        }
+    }
+}
+
+constexpr int MG_FUSED_BS = 512;
+
+// Levels 2 .. coarsest of one (load case, problem): restrict from level 1, the
+// residuals, `sweeps` l1 block-Jacobi sweeps on the coarsest level, correct and
+// post-smooth back up to level 2, whose output goes to global memory for level 1.
+// With `lds` the vectors of levels >= 2 live in LDS (layout [level][r|xp|res|x]
+// [points][C]); with `lds_sten` the coarsest stencils too.  Stages are separated
+// by workgroup barriers.
+template <typename T, int C, int R>
+__global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
+                                                               int sweeps, int lds, int lds_sten,
+                                                               const int *prob_active) {
+    constexpr int CC = C * C;
+    constexpr int MS = (C == 3) ? 6 : 1;
+    extern __shared__ unsigned char mg_smem[];
+    const int prob = blockIdx.y, w = blockIdx.x;
+    if (prob_active != nullptr && prob_active[prob] == 0) return;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    if (G.mg_nlev < 3) return;
+    const int lc = G.mg_nlev - 1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    T *smem = (T *)mg_smem;
+    // vectors of level l: levels >= 2 in LDS (when `lds`), packed in level order
+    auto lvec = [&](int l) -> LV<T> {
+        const Lev V = level_of(G, l);
+        if (l >= 2 && lds) {
+            const long long np = (long long)V.lw * V.lw * V.lw * C;
+            T *b = smem + 4LL * C * (V.off - G.mg_off[2]);
+            return LV<T>{b, b + np, b + 2 * np, b + 3 * np};
+        }
+        return level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
+    };
+    const long long used = lds ? 4LL * C * (G.mg_pts - G.mg_off[2]) : 0;
+    // down
+    for (int l = 1; l < lc; ++l) {
+        const Lev F = level_of(G, l), Cv = level_of(G, l + 1);
+        const long long npc = (long long)Cv.lw * Cv.lw * Cv.lw;
+        const T *D = Q.Dinv + (P.moff + Cv.off) * MS;
+        const LV<T> vf = lvec(l), vc = lvec(l + 1);
+        for (long long pt = tid; pt < npc; pt += nt) restrict_pt<T, C>(F, Cv, D, vf, vc, pt);
+        __syncthreads();
+        if (l + 1 < lc) {
+            const T *A = Q.A + (P.moff + Cv.off) * MG_SLOTS * CC;
+            for (long long pt = tid; pt < npc; pt += nt) resid_pt<T, C>(Cv, A, vc, pt);
+            __syncthreads();
+        }
+    }
+    // coarsest: x <- x + D^-1 (r - A x) from x = xp, iterates alternating between x and res
+    {
+        const Lev V = level_of(G, lc);
+        const long long np = (long long)V.lw * V.lw * V.lw;
+        const T *A = Q.A + (P.moff + V.off) * MG_SLOTS * CC;
+        const T *D = Q.Dinv + (P.moff + V.off) * MS;
+        if (lds_sten) {
+            T *sA = smem + used;
+            for (long long e = tid; e < np * MG_SLOTS * CC; e += nt) sA[e] = A[e];
+            A = sA;
+        }
+        const LV<T> v = lvec(lc);
+        for (long long pt = tid; pt < np; pt += nt)
+#pragma unroll
+            for (int c = 0; c < C; ++c) v.x[pt * C + c] = v.xp[pt * C + c];
+        __syncthreads();
+        T *bufs[2] = {v.x, v.res};
+        int cur = 0;
+        if (np <= nt) {
+            // one point per thread: neighbour indices, right side and inverse held in registers
+            const bool have = tid < np;
+            const long long pt = have ? tid : 0;
+            int i, j, k;
+            lev_xyz(V, pt, i, j, k);
+            int qi[MG_SLOTS];
+            T qm[MG_SLOTS];
+#pragma unroll
+            for (int s2 = 0; s2 < MG_SLOTS; ++s2) {
+                long long q;
+                qm[s2] = nbr(V, i, j, k, s2, pt, q) ? T(1) : T(0);
+                qi[s2] = (int)q;
+            }
+            T rv[C], Dv[MS];
+            load_c<T, C>(v.r + pt * C, rv);
+#pragma unroll
+            for (int e = 0; e < MS; ++e) Dv[e] = D[pt * MS + e];
+            const T *Ap = A + pt * MG_SLOTS * CC;
+            for (int it = 1; it < sweeps; ++it) {
+                const T *xs = bufs[cur];
+                T *xd = bufs[cur ^ 1];
+                if (have) {
+                    T acc[C];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[c] = rv[c];
+#pragma unroll
+                    for (int s2 = 0; s2 < MG_SLOTS; ++s2) {
+                        T vq[C];
+                        load_c<T, C>(xs + (long long)qi[s2] * C, vq);
+                        const T *blk = Ap + s2 * CC;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            T t = T(0);
+#pragma unroll
+                            for (int d = 0; d < C; ++d) t += blk[c * C + d] * vq[d];
+                            acc[c] -= qm[s2] * t;
+                        }
+                    }
+                    T d[C];
+                    minv_apply<T, C>(Dv, acc, d);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) xd[pt * C + c] = xs[pt * C + c] + d[c];
+                }
+                __syncthreads();
+                cur ^= 1;
+            }
+        } else {
+            for (int it = 1; it < sweeps; ++it) {
+                const T *xs = bufs[cur];
+                T *xd = bufs[cur ^ 1];
+                for (long long pt = tid; pt < np; pt += nt) {
+                    int i, j, k;
+                    lev_xyz(V, pt, i, j, k);
+                    T acc[C];
+                    load_c<T, C>(v.r + pt * C, acc);
+                    apply_stencil<T, C>(V, A + pt * MG_SLOTS * CC, xs, i, j, k, pt, acc);
+                    T d[C];
+                    minv_apply<T, C>(D + pt * MS, acc, d);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) xd[pt * C + c] = xs[pt * C + c] + d[c];
+                }
+                __syncthreads();
+                cur ^= 1;
+            }
+        }
+        if (cur == 1) {
+            for (long long e = tid; e < np * C; e += nt) v.x[e] = v.res[e];
+            __syncthreads();
+        }
+    }
+    // up: levels lc - 1 .. 2
+    for (int l = lc - 1; l >= 2; --l) {
+        const Lev V = level_of(G, l), Cv = level_of(G, l + 1);
+        const long long np = (long long)V.lw * V.lw * V.lw;
+        const LV<T> v = lvec(l), vc = lvec(l + 1);
+        for (long long pt = tid; pt < np; pt += nt) correct_pt<T, C>(V, Cv, v, vc.x, pt);
+        __syncthreads();
+        const T *A = Q.A + (P.moff + V.off) * MG_SLOTS * CC;
+        const T *D = Q.Dinv + (P.moff + V.off) * MS;
+        for (long long pt = tid; pt < np; pt += nt) post_pt<T, C>(V, A, D, v, pt);
+        __syncthreads();
+    }
+    // level-2 output to global memory for the level-1 correction
+    if (lds) {
+        const Lev V2 = level_of(G, 2);
+        const LV<T> g2 = level_vecs<T, C, R>(G, P, w, V2, Q.r, Q.xp, Q.res, Q.x);
+        const long long n2 = (long long)V2.lw * V2.lw * V2.lw * C;
+        const T *x2 = lvec(2).x;
+        for (long long e = tid; e < n2; e += nt) g2.x[e] = x2[e];
+    }
+}
+
+// Fine vector of constraint columns for the Gram setup: load case w carries the
+// column (i, a) = (s / nrow, s % nrow), s = first + w: component i equals row a.
+template <typename T, int C, int R>
+__global__ __launch_bounds__(64 * R) void mg_cols_kernel(const Geo *geos, const Prob *probs, int first, T *v) {
+    const int prob = blockIdx.y;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nr = G.nrow, rf = row_first(G.nrow);
+    const int s = first + w;
+    const int ci = nr > 0 ? s / nr : C, a = nr > 0 ? s % nr : 0;
+    const long long nblk = (G.npts + 63) / 64;
+    for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const long long pt = blk * 64 + lane;
+        if (pt >= G.npts) continue;
+        T *dst = v + P.voff + ((long long)w * G.npts + pt) * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) dst[c] = (c == ci) ? (T)G.rows[4 * pt + rf + a] : T(0);
+    }
+}
+
+// W[level-1 point][i * 4 + a] = level-1 output of the column batch.
+template <typename T, int C, int R>
+__global__ void mg_store_w_kernel(const Geo *geos, const Prob *probs, int first, const T *lx, T *W) {
+    const int prob = blockIdx.y;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    if (G.mg_nlev < 3 || G.nrow == 0) return;
+    const int nr = G.nrow;
+    const Lev V = level_of(G, 1);
+    const long long np1 = (long long)V.lw * V.lw * V.lw;
+    for (long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x; u < np1 * R;
+         u += (long long)gridDim.x * blockDim.x) {
+        const int w = (int)(u / np1);
+        const long long v = u - (long long)w * np1;
+        const int s = first + w;
+        if (s >= C * nr) continue;
+        const int i = s / nr, a = s % nr;
+        const T *src = lx + (P.moff * R + (long long)w * G.mg_pts + V.off + v) * C;
+        T *dst = W + ((P.moff + V.off + v) * (4 * C) + i * 4 + a) * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) dst[c] = src[c];
+    }
+}
+
+// E[(i,a),(j,b)] = sum over level-1 points of rows1_a W[.][j*4+b][i]; partials per workgroup.
+template <int C, typename T>
+__global__ void mg_gram_partial_kernel(const Geo *geos, const Prob *probs, const T *W, const double *rows1,
+                                       double *partial) {
+    const int prob = blockIdx.y;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    double *out = partial + ((long long)prob * gridDim.x + blockIdx.x) * 144;
+    const int nr = G.nrow, S = C * nr, rf = row_first(G.nrow);
+    const int u = threadIdx.x;
+    if (G.mg_nlev < 3 || nr == 0) {
+        if (u < 144) out[u] = 0.0;
+        return;
+    }
+    double acc = 0.0;
+    if (u < S * S) {
+        const int I = u / S, J = u % S;
+        const int i = I / nr, a = I % nr, j = J / nr, b = J % nr;
+        const Lev V = level_of(G, 1);
+        const long long np1 = (long long)V.lw * V.lw * V.lw;
+        for (long long v = blockIdx.x; v < np1; v += gridDim.x)
+            acc += rows1[(P.moff + V.off + v) * 4 + rf + a] *
+                   (double)W[((P.moff + V.off + v) * (4 * C) + j * 4 + b) * C + i];
+    }
+    if (u < 144) out[u] = acc;
+}
+
+// G_B = G_M + E, inverted (one thread per problem).
+template <int C>
+__global__ void mg_gram_finish_kernel(const Geo *geos, const Prob *probs, int nprob, int nwg, const double *partial,
+                                      const double *gmat, double *ginv, int *bad) {
+    constexpr int SMAX = C * 4;
+    const int prob = blockIdx.x * blockDim.x + threadIdx.x;
+    if (prob >= nprob) return;
+    const Geo &G = geos[probs[prob].geo];
+    const int nr = G.nrow, S = C * nr;
+    if (nr == 0) return;
+    double A[12][24];
+    for (int I = 0; I < S; ++I)
+        for (int J = 0; J < S; ++J) {
+            double e = 0.0;
+            if (G.mg_nlev >= 3)
+                for (int b = 0; b < nwg; ++b) e += partial[((long long)prob * nwg + b) * 144 + I * S + J];
+            A[I][J] = gmat[(long long)prob * SMAX * SMAX + I * S + J] + e;
+            A[I][S + J] = (I == J) ? 1.0 : 0.0;
+        }
+    const int ok = gauss_jordan(A, S);
+    if (!ok) atomicAdd(bad, 1);
+    for (int I = 0; I < S; ++I)
+        for (int J = 0; J < S; ++J) ginv[(long long)prob * SMAX * SMAX + I * S + J] = ok ? A[I][S + J] : 0.0;
+}
+
+#define CHOM_MG_NR_DISPATCH(NRV, CALL)                 \
+    switch (NRV) {                                     \
+        case 0: { constexpr int NR = 0; CALL; } break; \
+        case 1: { constexpr int NR = 1; CALL; } break; \
+        default: { constexpr int NR = 4; CALL; } break; \
+    }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+template <typename T, int C>
+hipError_t launch_mg_stencils(const Launch &L, T *A, T *Dinv, hipStream_t s) {
+    constexpr int CC = C * C;
+    constexpr int MS = (C == 3) ? 6 : 1;
+    const auto &M = L.mg;
+    mg_assemble0_kernel<C><<<dim3(grid_cap(M.max_pts[0] * MG_SLOTS, MG_BS, 4096), L.nprob), MG_BS, 0, s>>>(
+        L.geos, L.probs, M.A64);
+    for (int l = 0; l + 1 < M.nlev; ++l)
+        mg_rap_kernel<C><<<dim3(grid_cap(M.max_pts[l + 1] * MG_SLOTS, MG_BS, 4096), L.nprob), MG_BS, 0, s>>>(
+            L.geos, L.probs, l, M.A64);
+    mg_dinv_kernel<C><<<grid_cap(M.total_pts, MG_BS, 8192), MG_BS, 0, s>>>(M.total_pts, M.A64, M.D64);
+    mg_rows1_kernel<<<dim3(grid_cap(M.max_pts[1], MG_BS, 1024), L.nprob), MG_BS, 0, s>>>(L.geos, L.probs, M.rows1);
+    if constexpr (std::is_same<T, float>::value) {
+        mg_to_float_kernel<<<grid_cap(M.total_pts * MG_SLOTS * CC, MG_BS, 8192), MG_BS, 0, s>>>(
+            M.total_pts * MG_SLOTS * CC, M.A64, A);
+        mg_to_float_kernel<<<grid_cap(M.total_pts * MS, MG_BS, 8192), MG_BS, 0, s>>>(M.total_pts * MS, M.D64, Dinv);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int C, int R>
+hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *partial, const int *prob_active, hipStream_t s) {
+    const auto &M = L.mg;
+    VPtr<T, C, R> Q;
+    Q.fine_r = r;
+    Q.A = (const T *)M.A;
+    Q.Dinv = (const T *)M.Dinv;
+    Q.r = (T *)M.r;
+    Q.xp = (T *)M.xp;
+    Q.res = (T *)M.res;
+    Q.x = (T *)M.x;
+    Q.rows1 = M.rows1;
+    const dim3 g1(M.nwg[1], L.nprob);
+    mg_restrict01_kernel<T, C, R><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, prob_active);
+    mg_resid1_kernel<T, C, R><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, prob_active);
+    const size_t shm = (size_t)M.lds_elems * sizeof(T);
+    mg_fused_kernel<T, C, R><<<dim3(R, L.nprob), MG_FUSED_BS, shm, s>>>(L.geos, L.probs, Q, M.sweeps, M.lds_vec,
+                                                                       M.lds_sten, prob_active);
+    mg_correct1_kernel<T, C, R><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, prob_active);
+    CHOM_MG_NR_DISPATCH(L.nr, (mg_post1_kernel<T, C, R, NR><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, partial,
+                                                                                  M.pstride, M.pbase, prob_active)));
+    return hipGetLastError();
+}
+
+template <typename T, int C, int R>
+hipError_t launch_mg_gram(const Launch &L, T *tmp, const double *gmat, double *partial, int nwg, double *ginv,
+                          int *bad, hipStream_t s) {
+    if (L.nr == 0) return hipSuccess;
+    const auto &M = L.mg;
+    const int S = C * 4;
+    for (int first = 0; first < S; first += R) {
+        mg_cols_kernel<T, C, R><<<dim3(L.nwg, L.nprob), 64 * R, 0, s>>>(L.geos, L.probs, first, tmp);
+        hipError_t e = launch_mg_vcycle<T, C, R>(L, tmp, nullptr, nullptr, s);
+        if (e != hipSuccess) return e;
+        mg_store_w_kernel<T, C, R><<<dim3(grid_cap(M.max_pts[1] * R, MG_BS, 1024), L.nprob), MG_BS, 0, s>>>(
+            L.geos, L.probs, first, (const T *)M.x, (T *)M.W);
+    }
+    mg_gram_partial_kernel<C, T><<<dim3(nwg, L.nprob), 192, 0, s>>>(L.geos, L.probs, (const T *)M.W, M.rows1, partial);
+    mg_gram_finish_kernel<C><<<(L.nprob + 63) / 64, 64, 0, s>>>(L.geos, L.probs, L.nprob, nwg, partial, gmat, ginv, bad);
+    return hipGetLastError();
+}
+
+#define CHOM_MG_INST(T, C, R)                                                                                    \
+    template hipError_t launch_mg_vcycle<T, C, R>(const Launch &, const T *, double *, const int *, hipStream_t); \
+    template hipError_t launch_mg_gram<T, C, R>(const Launch &, T *, const double *, double *, int, double *,    \
+                                                int *, hipStream_t);
+CHOM_MG_INST(float, 3, 6)
+CHOM_MG_INST(float, 1, 3)
+CHOM_MG_INST(double, 3, 6)
+CHOM_MG_INST(double, 1, 3)
+template hipError_t launch_mg_stencils<float, 3>(const Launch &, float *, float *, hipStream_t);
+template hipError_t launch_mg_stencils<float, 1>(const Launch &, float *, float *, hipStream_t);
+template hipError_t launch_mg_stencils<double, 3>(const Launch &, double *, double *, hipStream_t);
+template hipError_t launch_mg_stencils<double, 1>(const Launch &, double *, double *, hipStream_t);
+
+}  // namespace chom

@@ -344,7 +344,7 @@ __global__ void gram_partial_kernel(const Geo *geos, const Prob *probs, const do
 // Expand the unique sums of one problem, invert (Gauss-Jordan, pivoted), store.
 template <int C>
 __global__ void gram_finish_kernel(const Geo *geos, const Prob *probs, int nprob, int nwg, const double *partial,
-                                   double *ginv64, double *ginv32, int *bad) {
+                                   double *ginv64, double *ginv32, int *bad, double *gmat) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int NUMAX = 60;
     constexpr int SMAX = C * 4;
@@ -377,23 +377,10 @@ __global__ void gram_finish_kernel(const Geo *geos, const Prob *probs, int nprob
                 A[I][J] = s;
                 A[I][S + J] = (I == J) ? 1.0 : 0.0;
             }
-        int ok = 1;
-        for (int c = 0; c < S; ++c) {
-            int piv = c;
-            for (int r = c + 1; r < S; ++r)
-                if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
-            if (!(fabs(A[piv][c]) > 0.0)) { ok = 0; break; }
-            if (piv != c)
-                for (int k = 0; k < 2 * S; ++k) { double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
-            const double ip = 1.0 / A[c][c];
-            for (int k = 0; k < 2 * S; ++k) A[c][k] *= ip;
-            for (int r = 0; r < S; ++r) {
-                if (r == c) continue;
-                const double f = A[r][c];
-                if (f != 0.0)
-                    for (int k = 0; k < 2 * S; ++k) A[r][k] -= f * A[c][k];
-            }
-        }
+        if (gmat != nullptr)
+            for (int I = 0; I < S; ++I)
+                for (int J = 0; J < S; ++J) gmat[((long long)which * nprob + prob) * SMAX * SMAX + I * S + J] = A[I][J];
+        const int ok = gauss_jordan(A, S);
         if (!ok) atomicAdd(bad, 1);
         double *out = (which == 0 ? ginv64 : ginv32) + (long long)prob * SMAX * SMAX;
         for (int I = 0; I < S; ++I)
@@ -403,16 +390,16 @@ __global__ void gram_finish_kernel(const Geo *geos, const Prob *probs, int nprob
 
 template <int C>
 hipError_t launch_gram(const Launch &L, const double *minv64, const float *minv32, double *gram_partial, int nwg,
-                       double *ginv64, double *ginv32, int *bad, hipStream_t s) {
+                       double *ginv64, double *ginv32, int *bad, hipStream_t s, double *gmat) {
     if (L.nr == 0) return hipSuccess;
     dim3 grid(nwg, L.nprob);
     gram_partial_kernel<C><<<grid, GRAM_CHUNK, 0, s>>>(L.geos, L.probs, minv64, minv32, gram_partial);
     gram_finish_kernel<C><<<(L.nprob + 63) / 64, 64, 0, s>>>(L.geos, L.probs, L.nprob, nwg, gram_partial, ginv64,
-                                                             ginv32, bad);
+                                                             ginv32, bad, gmat);
     return hipGetLastError();
 }
-template hipError_t launch_gram<3>(const Launch &, const double *, const float *, double *, int, double *, double *, int *, hipStream_t);
-template hipError_t launch_gram<1>(const Launch &, const double *, const float *, double *, int, double *, double *, int *, hipStream_t);
+template hipError_t launch_gram<3>(const Launch &, const double *, const float *, double *, int, double *, double *, int *, hipStream_t, double *);
+template hipError_t launch_gram<1>(const Launch &, const double *, const float *, double *, int, double *, double *, int *, hipStream_t, double *);
 
 // ------------------------------------------------------------------ load vectors
 // b_i = - int grad(phi_i) : C eps_k dV for the unit strains (or - int grad(phi_i) . k e_k
