@@ -931,7 +931,7 @@ int chom_default_options(chom_options *opt) {
     if (!opt) return CHOM_EINVAL;
     std::memset(opt, 0, sizeof(*opt));
     opt->precision = CHOM_FP64;
-    opt->precond = CHOM_PRECOND_BLOCK_JACOBI;
+    opt->precond = CHOM_PRECOND_TWO_LEVEL;
     opt->max_iter = 20000;
     opt->max_refine = 30;
     opt->rtol = 1e-12;
