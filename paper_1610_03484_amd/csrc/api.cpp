@@ -346,7 +346,7 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
             M.nwg[l] = (int)std::min<long long>(std::max<long long>((mg_max_pts[l] + 63) / 64, 1), 1024);
         }
         const char *sw = std::getenv("CHOM_MG_SWEEPS");
-        M.sweeps = sw ? std::max(1, std::atoi(sw)) : 20;
+        M.sweeps = sw ? std::max(1, std::atoi(sw)) : 10;
         M.pbase = L.nwg;
         M.pstride = L.nwg + M.nwg[1];
         M.total_pts = moff;
@@ -424,8 +424,9 @@ static hipError_t cg_iteration(ClassWS<C, R> &W, T *x, T *r, T *z, T *p, T *q, c
     const bool mg = L.mg.on != 0;
     const int ps = mg ? L.mg.pstride : L.nwg;
     hipError_t e;
-    if ((e = launch_cg_dir<T, C, R>(L, r, z, p, minv, W.ycoef.p, W.cols.p, W.active.p, s, mg ? L.mg.x : nullptr,
-                                    mg ? L.mg.W : nullptr)) != hipSuccess)
+    if (mg && (e = launch_mg_fcorr<T, C, R>(L, W.ycoef.p, W.active.p, s)) != hipSuccess) return e;
+    if ((e = launch_cg_dir<T, C, R>(L, r, z, p, minv, W.ycoef.p, W.cols.p, W.active.p, s, mg ? L.mg.res : nullptr,
+                                    nullptr)) != hipSuccess)
         return e;
     if ((e = launch_operator<T, C, R>(L, L.nprob, L.rg, p, q, W.partial.p, W.active.p, s)) != hipSuccess) return e;
     if ((e = launch_finish_alpha<C, R>(L, W.partial.p, W.cols.p, s)) != hipSuccess) return e;

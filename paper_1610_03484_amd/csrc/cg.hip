@@ -89,8 +89,9 @@ __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const 
 
 // z = z0 - M^-1 C^T y ; r = r - C^T y ; p = z + beta p.  With the two-level
 // preconditioner (mg.on) the vertex points also take the coarse correction
-// z += Q (e1 - W y), e1 = V Q^T r, W = V Q^T C^T, Q = P_0 P_1 (P_0 injects vertex
-// values, P_1 interpolates from the n/2 grid).
+// z += Q f, f = e1 - W y on the n/2 grid (e1 = V Q^T r, W = V Q^T C^T, formed by
+// mg_fcorr_kernel), Q = P_0 P_1 (P_0 injects vertex values, P_1 interpolates
+// from the n/2 grid).
 template <typename T, int C, int R, int NR>
 __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const Prob *probs, T *r, const T *z,
                                                         T *p, const T *minv, const double *ycoef,
@@ -143,46 +144,24 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
             lattice_xyz(G, pt, X, Y, Z);
             const int pp = G.p;
             if (X % pp == 0 && Y % pp == 0 && Z % pp == 0) {
-                // vertex (i, j, k); its level-1 parents: itself halved, or the two ends of
-                // the level-1 Kuhn edge whose midpoint it is
+                // vertex (i, j, k): f at its level-1 parents (itself halved, or the two
+                // ends of the level-1 Kuhn edge whose midpoint it is), averaged
                 const int i = X / pp, j = Y / pp, k = Z / pp;
                 const int px = i & 1, py = j & 1, pz = k & 1;
                 const int n1 = G.mg_n[1], lw1 = G.mg_lw[1];
                 const bool per1 = G.bc == 1;
-                double add[C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) add[c] = 0.0;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int sg = h == 0 ? -1 : 1;
-                    int a1 = (i + sg * px) >> 1, b1 = (j + sg * py) >> 1, c1 = (k + sg * pz) >> 1;
-                    if (per1) {
-                        if (a1 == n1) a1 = 0;
-                        if (b1 == n1) b1 = 0;
-                        if (c1 == n1) c1 = 0;
-                    }
-                    const long long J = G.mg_off[1] + a1 + (long long)lw1 * (b1 + (long long)lw1 * c1);
-                    const T *e = mg.x0 + (P.moff * R + (long long)w * G.mg_pts + J) * C;
-                    double f[C];
-#pragma unroll
-                    for (int c = 0; c < C; ++c) f[c] = (double)e[c];
-                    if constexpr (NR > 0) {
-                        if (proj) {
-                            const int nr = G.nrow;
-                            for (int ci = 0; ci < C; ++ci)
-                                for (int a = 0; a < nr; ++a) {
-                                    const double yy = yv[ci * NR + a];
-                                    const T *Wv = mg.W + ((P.moff + J) * (4 * C) + ci * 4 + a) * C;
-#pragma unroll
-                                    for (int c = 0; c < C; ++c) f[c] -= yy * (double)Wv[c];
-                                }
-                        }
-                    }
-#pragma unroll
-                    for (int c = 0; c < C; ++c) add[c] += 0.5 * f[c];
+                const T *f = mg.x0 + (P.moff * R + (long long)w * G.mg_pts + G.mg_off[1]) * C;
+                int a0 = (i - px) >> 1, b0 = (j - py) >> 1, c0 = (k - pz) >> 1;
+                int a1 = (i + px) >> 1, b1 = (j + py) >> 1, c1 = (k + pz) >> 1;
+                if (per1) {
+                    if (a1 == n1) a1 = 0;
+                    if (b1 == n1) b1 = 0;
+                    if (c1 == n1) c1 = 0;
                 }
+                const long long J0 = a0 + (long long)lw1 * (b0 + (long long)lw1 * c0);
+                const long long J1 = a1 + (long long)lw1 * (b1 + (long long)lw1 * c1);
 #pragma unroll
-                for (int c = 0; c < C; ++c) zv[c] = (T)((double)zv[c] + add[c]);
+                for (int c = 0; c < C; ++c) zv[c] += T(0.5) * (f[J0 * C + c] + f[J1 * C + c]);
             }
         }
         if (beta == 0.0) {   // first step (p not yet defined) or finished column

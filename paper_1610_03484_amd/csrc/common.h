@@ -78,8 +78,8 @@ constexpr int MG_MAXLEV = 8;
 
 // Coarse-correction operands of the CG direction kernel (two-level preconditioner).
 template <typename T> struct MgDir {
-    const T *x0;   // V-cycle output vectors, [prob: moff * R * C][R][mg_pts][C] (level 1 used)
-    const T *W;    // coarse part of B C^T: [moff + level-1 point][4 C (constraint i * 4 + a)][C]
+    const T *x0;   // coarse correction f on the n/2 grid, inside vectors [moff * R * C][R][mg_pts][C]
+    const T *W;    // unused by the direction kernel
     int on;
 };
 

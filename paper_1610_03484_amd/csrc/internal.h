@@ -126,6 +126,9 @@ template <typename T, int C> hipError_t launch_mg_stencils(const Launch &L, T *A
 // writes r.e0 and C P e0 into partial slots [pbase, pbase + nwg[0]).
 template <typename T, int C, int R>
 hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *partial, const int *prob_active, hipStream_t s);
+// Coarse correction f = e_1 - W y of the current CG step (into the level-1 res block).
+template <typename T, int C, int R>
+hipError_t launch_mg_fcorr(const Launch &L, const double *ycoef, const int *prob_active, hipStream_t s);
 // W = V P^T C^T (constraint columns, in batches of R) using `tmp` (a fine
 // vector), then the Gram matrix C B C^T = gmat + C P W and its inverse.
 template <typename T, int C, int R>

@@ -632,6 +632,37 @@ __global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const
     }
 }
 
+// f = e_1 - W y per (problem, load case) on the n/2 grid (y: projection
+// coefficients of the current CG step), into the level-1 res block.
+template <typename T, int C, int R, int NR>
+__global__ __launch_bounds__(64 * R) void mg_fcorr_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
+                                                          const T *W, const double *ycoef, const int *prob_active) {
+    MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 3)
+    const Lev V = level_of(G, 1);
+    const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
+    const int nr = G.nrow < NR ? G.nrow : NR;
+    double yv[C * NR > 0 ? C * NR : 1];
+#pragma unroll
+    for (int k = 0; k < C * NR; ++k) yv[k] = ycoef[((long long)prob * R + w) * C * NR + k];
+    const long long np = (long long)V.lw * V.lw * V.lw;
+    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) {
+        double f[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) f[c] = (double)v.x[pt * C + c];
+        if constexpr (NR > 0) {
+            const T *Wp = W + (P.moff + V.off + pt) * (4 * C) * C;
+            for (int i = 0; i < C; ++i)
+                for (int a = 0; a < nr; ++a) {
+                    const double yy = yv[i * NR + a];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) f[c] -= yy * (double)Wp[(i * 4 + a) * C + c];
+                }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) v.res[pt * C + c] = (T)f[c];
+    }
+}
+
 constexpr int MG_FUSED_BS = 512;
 
 // Levels 2 .. coarsest of one (load case, problem): restrict from level 1, the
@@ -863,29 +894,34 @@ __global__ void mg_gram_partial_kernel(const Geo *geos, const Prob *probs, const
     if (u < 144) out[u] = acc;
 }
 
-// G_B = G_M + E, inverted (one thread per problem).
+// G_B = G_M + E, inverted (one workgroup per problem).
 template <int C>
-__global__ void mg_gram_finish_kernel(const Geo *geos, const Prob *probs, int nprob, int nwg, const double *partial,
-                                      const double *gmat, double *ginv, int *bad) {
+__global__ __launch_bounds__(256) void mg_gram_finish_kernel(const Geo *geos, const Prob *probs, int nwg,
+                                                             const double *partial, const double *gmat,
+                                                             double *ginv, int *bad) {
     constexpr int SMAX = C * 4;
-    const int prob = blockIdx.x * blockDim.x + threadIdx.x;
-    if (prob >= nprob) return;
+    __shared__ double A[12][24];
+    __shared__ int ok_s;
+    const int prob = blockIdx.x;
     const Geo &G = geos[probs[prob].geo];
     const int nr = G.nrow, S = C * nr;
     if (nr == 0) return;
-    double A[12][24];
-    for (int I = 0; I < S; ++I)
-        for (int J = 0; J < S; ++J) {
-            double e = 0.0;
-            if (G.mg_nlev >= 3)
-                for (int b = 0; b < nwg; ++b) e += partial[((long long)prob * nwg + b) * 144 + I * S + J];
-            A[I][J] = gmat[(long long)prob * SMAX * SMAX + I * S + J] + e;
-            A[I][S + J] = (I == J) ? 1.0 : 0.0;
-        }
-    const int ok = gauss_jordan(A, S);
-    if (!ok) atomicAdd(bad, 1);
-    for (int I = 0; I < S; ++I)
-        for (int J = 0; J < S; ++J) ginv[(long long)prob * SMAX * SMAX + I * S + J] = ok ? A[I][S + J] : 0.0;
+    for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
+        const int I = t / S, J = t % S;
+        double e = 0.0;
+        if (G.mg_nlev >= 3)
+            for (int b = 0; b < nwg; ++b) e += partial[((long long)prob * nwg + b) * 144 + t];
+        A[I][J] = gmat[(long long)prob * SMAX * SMAX + t] + e;
+        A[I][S + J] = (I == J) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok_s = gauss_jordan(A, S);
+        if (!ok_s) atomicAdd(bad, 1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < S * S; t += blockDim.x)
+        ginv[(long long)prob * SMAX * SMAX + t] = ok_s ? A[t / S][S + t % S] : 0.0;
 }
 
 #define CHOM_MG_NR_DISPATCH(NRV, CALL)                 \
@@ -943,6 +979,23 @@ hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *partial, const 
 }
 
 template <typename T, int C, int R>
+hipError_t launch_mg_fcorr(const Launch &L, const double *ycoef, const int *prob_active, hipStream_t s) {
+    const auto &M = L.mg;
+    VPtr<T, C, R> Q;
+    Q.fine_r = nullptr;
+    Q.A = (const T *)M.A;
+    Q.Dinv = (const T *)M.Dinv;
+    Q.r = (T *)M.r;
+    Q.xp = (T *)M.xp;
+    Q.res = (T *)M.res;
+    Q.x = (T *)M.x;
+    Q.rows1 = M.rows1;
+    CHOM_MG_NR_DISPATCH(L.nr, (mg_fcorr_kernel<T, C, R, NR><<<dim3(M.nwg[1], L.nprob), 64 * R, 0, s>>>(
+                                  L.geos, L.probs, Q, (const T *)M.W, ycoef, prob_active)));
+    return hipGetLastError();
+}
+
+template <typename T, int C, int R>
 hipError_t launch_mg_gram(const Launch &L, T *tmp, const double *gmat, double *partial, int nwg, double *ginv,
                           int *bad, hipStream_t s) {
     if (L.nr == 0) return hipSuccess;
@@ -956,12 +1009,13 @@ hipError_t launch_mg_gram(const Launch &L, T *tmp, const double *gmat, double *p
             L.geos, L.probs, first, (const T *)M.x, (T *)M.W);
     }
     mg_gram_partial_kernel<C, T><<<dim3(nwg, L.nprob), 192, 0, s>>>(L.geos, L.probs, (const T *)M.W, M.rows1, partial);
-    mg_gram_finish_kernel<C><<<(L.nprob + 63) / 64, 64, 0, s>>>(L.geos, L.probs, L.nprob, nwg, partial, gmat, ginv, bad);
+    mg_gram_finish_kernel<C><<<L.nprob, 256, 0, s>>>(L.geos, L.probs, nwg, partial, gmat, ginv, bad);
     return hipGetLastError();
 }
 
 #define CHOM_MG_INST(T, C, R)                                                                                    \
     template hipError_t launch_mg_vcycle<T, C, R>(const Launch &, const T *, double *, const int *, hipStream_t); \
+    template hipError_t launch_mg_fcorr<T, C, R>(const Launch &, const double *, const int *, hipStream_t);      \
     template hipError_t launch_mg_gram<T, C, R>(const Launch &, T *, const double *, double *, int, double *,    \
                                                 int *, hipStream_t);
 CHOM_MG_INST(float, 3, 6)

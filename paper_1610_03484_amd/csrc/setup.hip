@@ -342,50 +342,55 @@ __global__ void gram_partial_kernel(const Geo *geos, const Prob *probs, const do
 }
 
 // Expand the unique sums of one problem, invert (Gauss-Jordan, pivoted), store.
+// One workgroup per problem: the threads sum the partials of the S x S entries
+// into LDS, one thread inverts.
 template <int C>
-__global__ void gram_finish_kernel(const Geo *geos, const Prob *probs, int nprob, int nwg, const double *partial,
-                                   double *ginv64, double *ginv32, int *bad, double *gmat) {
+__global__ __launch_bounds__(256) void gram_finish_kernel(const Geo *geos, const Prob *probs, int nprob, int nwg,
+                                                          const double *partial, double *ginv64, double *ginv32,
+                                                          int *bad, double *gmat) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int NUMAX = 60;
     constexpr int SMAX = C * 4;
-    const int prob = blockIdx.x * blockDim.x + threadIdx.x;
-    if (prob >= nprob) return;
+    __shared__ double A[12][24];
+    __shared__ int ok_s;
+    const int prob = blockIdx.x;
     const int nrow = geos[probs[prob].geo].nrow;
     if (nrow == 0) return;
     const int nRs = nrow * (nrow + 1) / 2;
-    const int nU = MS * nRs;
     const int S = C * nrow;
     for (int which = 0; which < 2; ++which) {
-        double A[12][24];
-        for (int I = 0; I < S; ++I)
-            for (int J = 0; J < S; ++J) {
-                const int i = I / nrow, a = I % nrow, j = J / nrow, b = J % nrow;
-                int mi;
-                if (C == 3) {
-                    const int lo = i < j ? i : j, hi = i < j ? j : i;
-                    mi = (lo == hi) ? lo : (lo == 0 && hi == 1 ? 3 : (lo == 1 && hi == 2 ? 4 : 5));
-                } else {
-                    mi = 0;
-                }
-                const int ra = a < b ? a : b, rb = a < b ? b : a;
-                int ri = 0;
-                for (int q = 0; q < ra; ++q) ri += nrow - q;
-                ri += rb - ra;
-                const int u = mi * nRs + ri;
-                double s = 0.0;
-                for (int w = 0; w < nwg; ++w) s += partial[((long long)prob * nwg + w) * 2 * NUMAX + which * NUMAX + u];
-                A[I][J] = s;
-                A[I][S + J] = (I == J) ? 1.0 : 0.0;
+        for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
+            const int I = t / S, J = t % S;
+            const int i = I / nrow, a = I % nrow, j = J / nrow, b = J % nrow;
+            int mi;
+            if (C == 3) {
+                const int lo = i < j ? i : j, hi = i < j ? j : i;
+                mi = (lo == hi) ? lo : (lo == 0 && hi == 1 ? 3 : (lo == 1 && hi == 2 ? 4 : 5));
+            } else {
+                mi = 0;
             }
-        if (gmat != nullptr)
-            for (int I = 0; I < S; ++I)
-                for (int J = 0; J < S; ++J) gmat[((long long)which * nprob + prob) * SMAX * SMAX + I * S + J] = A[I][J];
-        const int ok = gauss_jordan(A, S);
-        if (!ok) atomicAdd(bad, 1);
+            const int ra = a < b ? a : b, rb = a < b ? b : a;
+            int ri = 0;
+            for (int q = 0; q < ra; ++q) ri += nrow - q;
+            ri += rb - ra;
+            const int u = mi * nRs + ri;
+            double sum = 0.0;
+            for (int w = 0; w < nwg; ++w) sum += partial[((long long)prob * nwg + w) * 2 * NUMAX + which * NUMAX + u];
+            A[I][J] = sum;
+            A[I][S + J] = (I == J) ? 1.0 : 0.0;
+            if (gmat != nullptr) gmat[((long long)which * nprob + prob) * SMAX * SMAX + I * S + J] = sum;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ok_s = gauss_jordan(A, S);
+            if (!ok_s) atomicAdd(bad, 1);
+        }
+        __syncthreads();
         double *out = (which == 0 ? ginv64 : ginv32) + (long long)prob * SMAX * SMAX;
-        for (int I = 0; I < S; ++I)
-            for (int J = 0; J < S; ++J) out[I * S + J] = ok ? A[I][S + J] : 0.0;
+        for (int t = threadIdx.x; t < S * S; t += blockDim.x) out[t] = ok_s ? A[t / S][S + t % S] : 0.0;
+        __syncthreads();
     }
+    (void)MS;
 }
 
 template <int C>
@@ -394,8 +399,8 @@ hipError_t launch_gram(const Launch &L, const double *minv64, const float *minv3
     if (L.nr == 0) return hipSuccess;
     dim3 grid(nwg, L.nprob);
     gram_partial_kernel<C><<<grid, GRAM_CHUNK, 0, s>>>(L.geos, L.probs, minv64, minv32, gram_partial);
-    gram_finish_kernel<C><<<(L.nprob + 63) / 64, 64, 0, s>>>(L.geos, L.probs, L.nprob, nwg, gram_partial, ginv64,
-                                                             ginv32, bad, gmat);
+    gram_finish_kernel<C><<<L.nprob, 256, 0, s>>>(L.geos, L.probs, L.nprob, nwg, gram_partial, ginv64, ginv32, bad,
+                                                  gmat);
     return hipGetLastError();
 }
 template hipError_t launch_gram<3>(const Launch &, const double *, const float *, double *, int, double *, double *, int *, hipStream_t, double *);
