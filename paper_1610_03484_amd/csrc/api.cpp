@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -128,6 +129,7 @@ struct GraphCache {
 template <int C, int R> struct ClassWS {
     static constexpr int MS = (C == 3) ? 6 : 1;
     Launch L{};
+    hipStream_t stream = nullptr;        // the class's stream (mechanics: the batch stream)
     long long total_vals = 0, total_pts = 0, total_q = 0;
     int nwg_gram = 0, nwg_avg = 0;
     unsigned long long gen = 0;          // bumped whenever the launch shape may change
@@ -182,6 +184,7 @@ struct chom_batch {
     std::vector<int> geo_of;            // entry -> index in distinct
     chom_options opt;
     hipStream_t stream = nullptr;
+    hipStream_t stream2 = nullptr;      // scalar class, run concurrently with the mechanical one
     bool own_stream = false;
     DevBuf<Geo> geos;
     ClassWS<3, 6> mech;
@@ -195,6 +198,7 @@ struct chom_batch {
         scal.graph64.reset();
         scal.graph32.reset();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
+        if (stream2) (void)hipStreamDestroy(stream2);
     }
 };
 
@@ -443,7 +447,7 @@ static hipError_t cg_iteration(ClassWS<C, R> &W, T *x, T *r, T *z, T *p, T *q, c
 template <typename T, int C, int R>
 static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x, T *r, T *z, T *p, T *q,
                const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask) {
-    hipStream_t s = B->stream;
+    hipStream_t s = W.stream;
     const Launch &L = W.L;
     const bool mg = L.mg.on != 0;
     const int ps = mg ? L.mg.pstride : L.nwg;
@@ -490,7 +494,7 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x
 // Solve one class (mechanical or scalar) for all its problems.  Result: W.avg_out.
 template <int C, int R>
 static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs, int rg, int nwg) {
-    hipStream_t s = B->stream;
+    hipStream_t s = W.stream;
     CHOM_TRY((setup_class<C, R>(B, W, hprobs, rg, nwg)));
     const Launch &L = W.L;
     const int nprob = L.nprob;
@@ -576,7 +580,7 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
 template <typename T, int C, int R>
 static int time_op(chom_batch *B, ClassWS<C, R> &W, const T *x, T *y, int rg, int reps, double *ms) {
     const Launch &L = W.L;
-    hipStream_t s = B->stream;
+    hipStream_t s = W.stream;
     hipEvent_t e0, e1;
     CHOM_HIP(hipEventCreate(&e0));
     CHOM_HIP(hipEventCreate(&e1));
@@ -600,7 +604,7 @@ static int time_vec(chom_batch *B, ClassWS<C, R> &W, T *x, T *r, T *z, T *p, con
                     int reps, double *ms) {
     Launch L = W.L;
     L.nwg = nwg;
-    hipStream_t s = B->stream;
+    hipStream_t s = W.stream;
     std::vector<int> ones(L.nprob, 1);
     CHOM_HIP(hipMemcpyAsync(W.active.p, ones.data(), sizeof(int) * L.nprob, hipMemcpyHostToDevice, s));
     CHOM_HIP(hipMemsetAsync(W.cols.p, 0, sizeof(ColState) * R * L.nprob, s));
@@ -638,7 +642,7 @@ static int autotune_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp
         return CHOM_OK;
     }
     CHOM_TRY((setup_class<C, R>(B, W, hp, *rg_out, 1024)));   // partials sized for the largest candidate
-    hipStream_t s = B->stream;
+    hipStream_t s = W.stream;
     CHOM_HIP(hipMemcpyAsync(W.probs.p, hp.data(), sizeof(Prob) * hp.size(), hipMemcpyHostToDevice, s));
     const bool f32 = B->opt.precision == CHOM_FP32_REFINED;
     const size_t nv = W.total_vals, nq = W.total_q;
@@ -736,6 +740,9 @@ static int batch_init(chom_batch *B, chom_rve *const *rves, int n, const chom_op
         CHOM_HIP(hipStreamCreate(&B->stream));   // default priority
         B->own_stream = true;
     }
+    CHOM_HIP(hipStreamCreate(&B->stream2));      // default priority
+    B->mech.stream = B->stream;
+    B->scal.stream = B->stream2;
     std::vector<Geo> hg;
     for (auto *r : B->distinct) hg.push_back(r->geo);
     CHOM_HIP(B->geos.ensure(hg.size()));
@@ -785,11 +792,48 @@ static int batch_homogenise(chom_batch *B, const chom_params *params, double *C_
         CHOM_TRY((autotune_class<1, 3>(B, B->scal, ps, tune_key(B, 1), &B->rg_scal, &B->nwg_scal)));
         B->tuned = true;
     }
-    CHOM_TRY((run_class<3, 6>(B, B->mech, pm, B->rg_mech, B->nwg_mech)));
-    CHOM_TRY((run_class<1, 3>(B, B->scal, ps, B->rg_scal, B->nwg_scal)));
+    // the two classes are independent: the scalar one runs on its own stream from
+    // a second host thread (its host loops then overlap the mechanical ones)
+    {
+        hipEvent_t ev;
+        CHOM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        CHOM_HIP(hipEventRecord(ev, s));
+        CHOM_HIP(hipStreamWaitEvent(B->stream2, ev, 0));
+        (void)hipEventDestroy(ev);
+    }
+    int device = 0;
+    CHOM_HIP(hipGetDevice(&device));
+    int st_scal = CHOM_OK;
+    std::string err_scal;
+    const bool serial = std::getenv("CHOM_SERIAL_CLASSES") != nullptr;
+    auto scal_job = [&]() {
+        if (hipSetDevice(device) != hipSuccess) {
+            st_scal = CHOM_EDEVICE;
+            err_scal = "hipSetDevice failed in the scalar-class thread";
+            return;
+        }
+        st_scal = run_class<1, 3>(B, B->scal, ps, B->rg_scal, B->nwg_scal);
+        if (st_scal != CHOM_OK) err_scal = g_last_error;
+    };
+    int st_mech = CHOM_OK;
+    if (serial) {
+        st_mech = run_class<3, 6>(B, B->mech, pm, B->rg_mech, B->nwg_mech);
+        if (st_mech == CHOM_OK) scal_job();
+    } else {
+        std::thread th(scal_job);
+        st_mech = run_class<3, 6>(B, B->mech, pm, B->rg_mech, B->nwg_mech);
+        th.join();
+    }
+    if (st_mech != CHOM_OK) return st_mech;
+    if (st_scal != CHOM_OK) {
+        set_error(err_scal);
+        return st_scal;
+    }
     std::vector<double> cm((size_t)batch * 36), cs((size_t)2 * batch * 9);
     CHOM_HIP(hipMemcpyAsync(cm.data(), B->mech.avg_out.p, sizeof(double) * cm.size(), hipMemcpyDeviceToHost, s));
-    CHOM_HIP(hipMemcpyAsync(cs.data(), B->scal.avg_out.p, sizeof(double) * cs.size(), hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipMemcpyAsync(cs.data(), B->scal.avg_out.p, sizeof(double) * cs.size(), hipMemcpyDeviceToHost,
+                            B->stream2));
+    CHOM_HIP(hipStreamSynchronize(B->stream2));
     CHOM_HIP(hipStreamSynchronize(s));
     std::vector<double> oc((size_t)batch * 21), ok((size_t)batch * 6), od((size_t)batch * 6);
     int overall = CHOM_OK;
