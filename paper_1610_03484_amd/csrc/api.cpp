@@ -135,13 +135,14 @@ template <int C, int R> struct ClassWS {
     unsigned long long gen = 0;          // bumped whenever the launch shape may change
     DevBuf<Prob> probs;
     DevBuf<double> b, x64, r64, q64;
-    DevBuf<double> xd, rd, zd, pd, qd;
-    DevBuf<float> xf, rf, zf, pf, qf, r32;
+    DevBuf<double> xd, rd, pd, qd;
+    DevBuf<float> xf, rf, pf, qf, r32;
     DevBuf<double> diag, minv64, ginv64, ginv32, ycoef;
     DevBuf<float> minv32;
     DevBuf<ColState> cols, cols_outer;
     DevBuf<int> active, active_outer, bad;
-    DevBuf<double> partial, avg_out, sums;
+    DevBuf<double> partial, avg_out;
+    DevBuf<double> acc, accpq;           // striped CG accumulators (see ACC_STRIPES)
     DevBuf<double> ef64;                 // orders 3, 4: element factors
     DevBuf<float> ef32;
     // two-level preconditioner: FP64 setup arrays, the solve-precision copies,
@@ -293,7 +294,7 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     W.nwg_avg = (int)std::min<long long>(std::max<long long>((max_tets + 1023) / 1024, 1), 256);
     const bool fp32 = B->opt.precision == CHOM_FP32_REFINED;
     const size_t nv = (size_t)voff, nq = (size_t)qoff;
-    void *before[4] = {W.xd.p, W.xf.p, W.partial.p, W.probs.p};
+    void *before[6] = {W.xd.p, W.xf.p, W.partial.p, W.probs.p, W.acc.p, W.accpq.p};
     CHOM_HIP(W.probs.ensure(nprob));
     if (eoff > 0) {
         CHOM_HIP(W.ef64.ensure((size_t)eoff));
@@ -308,14 +309,12 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
         CHOM_HIP(W.r64.ensure(nv));
         CHOM_HIP(W.xf.ensure(nv));
         CHOM_HIP(W.rf.ensure(nv));
-        CHOM_HIP(W.zf.ensure(nv));
         CHOM_HIP(W.pf.ensure(nv));
         CHOM_HIP(W.qf.ensure(nq));
         CHOM_HIP(W.r32.ensure(nv));
     } else {
         CHOM_HIP(W.xd.ensure(nv));
         CHOM_HIP(W.rd.ensure(nv));
-        CHOM_HIP(W.zd.ensure(nv));
         CHOM_HIP(W.pd.ensure(nv));
         CHOM_HIP(W.qd.ensure(nq));
     }
@@ -351,8 +350,6 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
         }
         const char *sw = std::getenv("CHOM_MG_SWEEPS");
         M.sweeps = sw ? std::max(1, std::atoi(sw)) : 10;
-        M.pbase = L.nwg;
-        M.pstride = L.nwg + M.nwg[1];
         M.total_pts = moff;
         // LDS of the fused kernel: the four vectors of levels >= 2, then the coarsest stencils
         const long long tsz = fp32 ? (long long)sizeof(float) : (long long)sizeof(double);
@@ -399,20 +396,26 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
             M.x = W.mgx64.p;
             M.W = W.mgW64.p;
         }
-        part = std::max(part, (size_t)nprob * M.pstride * R * (2 + C * 4));
         part = std::max(part, (size_t)nprob * W.nwg_gram * 144);
     }
     CHOM_HIP(W.partial.ensure(part));
+    {
+        const size_t nacc = (size_t)nprob * R * ACC_RECMAX<C> * ACC_STRIPES, npq = (size_t)nprob * R * ACC_STRIPES;
+        if (W.acc.n < nacc || W.accpq.n < npq) {
+            CHOM_HIP(W.acc.ensure(nacc));
+            CHOM_HIP(W.accpq.ensure(npq));
+            CHOM_HIP(hipMemsetAsync(W.acc.p, 0, sizeof(double) * W.acc.n, W.stream));
+            CHOM_HIP(hipMemsetAsync(W.accpq.p, 0, sizeof(double) * W.accpq.n, W.stream));
+        }
+    }
     CHOM_HIP(W.avg_out.ensure((size_t)nprob * R * NC));
-    CHOM_HIP(W.sums.ensure((size_t)nprob * R * (2 + C * 4)));
     W.h_cols.resize((size_t)R * nprob);
     W.h_cols_outer.resize((size_t)R * nprob);
     W.h_active.resize(nprob);
     W.refine_steps.assign(nprob, 0);
     L.geos = B->geos.p;
     L.probs = W.probs.p;
-    L.sums = W.sums.p;
-    const void *after[4] = {W.xd.p, W.xf.p, W.partial.p, W.probs.p};
+    const void *after[6] = {W.xd.p, W.xf.p, W.partial.p, W.probs.p, W.acc.p, W.accpq.p};
     if (std::memcmp(before, after, sizeof(before)) != 0 || old.nprob != L.nprob || old.nwg != L.nwg ||
         old.max_tiles != L.max_tiles || old.nr != L.nr || old.rg != L.rg ||
         std::memcmp(&old.mg, &L.mg, sizeof(L.mg)) != 0)
@@ -422,22 +425,20 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
 
 // One CG iteration (5 kernels, plus the V-cycle with the two-level preconditioner).
 template <typename T, int C, int R>
-static hipError_t cg_iteration(ClassWS<C, R> &W, T *x, T *r, T *z, T *p, T *q, const void *minv,
+static hipError_t cg_iteration(ClassWS<C, R> &W, T *x, T *r, T *p, T *q, const void *minv,
                                const double *ginv, double rtol2, int use_init, hipStream_t s) {
     const Launch &L = W.L;
     const bool mg = L.mg.on != 0;
-    const int ps = mg ? L.mg.pstride : L.nwg;
     hipError_t e;
     if (mg && (e = launch_mg_fcorr<T, C, R>(L, W.ycoef.p, W.active.p, s)) != hipSuccess) return e;
-    if ((e = launch_cg_dir<T, C, R>(L, r, z, p, minv, W.ycoef.p, W.cols.p, W.active.p, s, mg ? L.mg.res : nullptr,
+    if ((e = launch_cg_dir<T, C, R>(L, r, p, minv, W.ycoef.p, W.cols.p, W.active.p, s, mg ? L.mg.res : nullptr,
                                     nullptr)) != hipSuccess)
         return e;
-    if ((e = launch_operator<T, C, R>(L, L.nprob, L.rg, p, q, W.partial.p, W.active.p, s)) != hipSuccess) return e;
-    if ((e = launch_finish_alpha<C, R>(L, W.partial.p, W.cols.p, s)) != hipSuccess) return e;
-    if ((e = launch_cg_update<T, C, R>(L, x, r, z, p, q, minv, W.cols.p, W.partial.p, W.active.p, s, ps)) != hipSuccess) return e;
-    if (mg && (e = launch_mg_vcycle<T, C, R>(L, r, W.partial.p, W.active.p, s)) != hipSuccess) return e;
-    return launch_finish_beta<C, R>(L, W.partial.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 0, rtol2, use_init, nullptr,
-                                    s, ps);
+    if ((e = launch_operator<T, C, R>(L, L.nprob, L.rg, p, q, W.accpq.p, W.active.p, s)) != hipSuccess) return e;
+    if ((e = launch_finish_alpha<C, R>(L, W.accpq.p, W.cols.p, s)) != hipSuccess) return e;
+    if ((e = launch_cg_update<T, C, R>(L, x, r, p, q, minv, W.cols.p, W.acc.p, W.active.p, s)) != hipSuccess) return e;
+    if (mg && (e = launch_mg_vcycle<T, C, R>(L, r, W.acc.p, W.active.p, s)) != hipSuccess) return e;
+    return launch_finish_beta<C, R>(L, W.acc.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 0, rtol2, use_init, nullptr, s);
 }
 
 // PCG on one class of problems: b -> x (vectors of precision T).  Iterations
@@ -445,16 +446,18 @@ static hipError_t cg_iteration(ClassWS<C, R> &W, T *x, T *r, T *z, T *p, T *q, c
 // host reads the per-problem active counts (finished problems cost only an
 // early exit in every kernel).
 template <typename T, int C, int R>
-static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x, T *r, T *z, T *p, T *q,
+static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x, T *r, T *p, T *q,
                const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask) {
     hipStream_t s = W.stream;
     const Launch &L = W.L;
     const bool mg = L.mg.on != 0;
-    const int ps = mg ? L.mg.pstride : L.nwg;
-    CHOM_HIP((launch_cg_init<T, C, R>(L, b, x, r, z, minv, W.partial.p, s, ps)));
-    if (mg) CHOM_HIP((launch_mg_vcycle<T, C, R>(L, r, W.partial.p, nullptr, s)));
-    CHOM_HIP((launch_finish_beta<C, R>(L, W.partial.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 1, rtol2,
-                                       mask ? 1 : use_init, mask, s, ps)));
+    // the accumulators may hold sums of kernels run outside a CG step (timing, residuals)
+    CHOM_HIP(launch_zero(W.acc.p, (long long)W.acc.n, s));
+    CHOM_HIP(launch_zero(W.accpq.p, (long long)W.accpq.n, s));
+    CHOM_HIP((launch_cg_init<T, C, R>(L, b, x, r, minv, W.acc.p, s)));
+    if (mg) CHOM_HIP((launch_mg_vcycle<T, C, R>(L, r, W.acc.p, nullptr, s)));
+    CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 1, rtol2,
+                                       mask ? 1 : use_init, mask, s)));
     const int max_iter = B->opt.max_iter;
     const int chunk = 8;
     const bool use_graph = std::getenv("CHOM_NO_GRAPH") == nullptr;
@@ -464,7 +467,7 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x
         CHOM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipSuccess;
         for (int k = 0; k < chunk && ce == hipSuccess; ++k)
-            ce = cg_iteration<T, C, R>(W, x, r, z, p, q, minv, ginv, rtol2, use_init, s);
+            ce = cg_iteration<T, C, R>(W, x, r, p, q, minv, ginv, rtol2, use_init, s);
         hipError_t ee = hipStreamEndCapture(s, &g);
         CHOM_HIP(ce);
         CHOM_HIP(ee);
@@ -485,7 +488,7 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x
             CHOM_HIP(hipGraphLaunch(GC.exec, s));
         } else {
             for (int k = 0; k < chunk; ++k)
-                CHOM_HIP((cg_iteration<T, C, R>(W, x, r, z, p, q, minv, ginv, rtol2, use_init, s)));
+                CHOM_HIP((cg_iteration<T, C, R>(W, x, r, p, q, minv, ginv, rtol2, use_init, s)));
         }
     }
     return CHOM_OK;
@@ -525,7 +528,7 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
     const double rtol2 = B->opt.rtol * B->opt.rtol;
     double *x64 = nullptr;
     if (B->opt.precision == CHOM_FP64) {
-        CHOM_TRY((pcg<double, C, R>(B, W, W.graph64, W.b.p, W.xd.p, W.rd.p, W.zd.p, W.pd.p, W.qd.p, W.minv64.p,
+        CHOM_TRY((pcg<double, C, R>(B, W, W.graph64, W.b.p, W.xd.p, W.rd.p, W.pd.p, W.qd.p, W.minv64.p,
                                     ginv_inner64, rtol2, 0, nullptr)));
         x64 = W.xd.p;
     } else {
@@ -535,12 +538,13 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
         CHOM_HIP(hipMemcpyAsync(W.cols_outer.p, W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToDevice, s));
         for (int step = 0; step <= B->opt.max_refine; ++step) {
             // outer residual norm in FP64: project r64, then r64 . M^-1 r64 against the linear-field energy
-            CHOM_HIP((launch_cg_init<double, C, R>(L, W.r64.p, nullptr, nullptr, nullptr, W.minv64.p, W.partial.p, s)));
-            CHOM_HIP((launch_finish_beta<C, R>(L, W.partial.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p, W.active_outer.p,
+            CHOM_HIP(launch_zero(W.acc.p, (long long)W.acc.n, s));
+            CHOM_HIP((launch_cg_init<double, C, R>(L, W.r64.p, nullptr, nullptr, W.minv64.p, W.acc.p, s)));
+            CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p, W.active_outer.p,
                                                1, rtol2, 0, nullptr, s)));
             if (L.nr > 0) {
-                CHOM_HIP((launch_proj_resid<C, R>(L, W.r64.p, W.r32.p, W.minv64.p, W.ycoef.p, W.partial.p, s)));
-                CHOM_HIP((launch_finish_beta<C, R>(L, W.partial.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p,
+                CHOM_HIP((launch_proj_resid<C, R>(L, W.r64.p, W.r32.p, W.minv64.p, W.ycoef.p, W.acc.p, s)));
+                CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p,
                                                    W.active_outer.p, 1, rtol2, 0, nullptr, s)));
             }
             CHOM_HIP(hipMemcpyAsync(W.h_active.data(), W.active_outer.p, sizeof(int) * nprob, hipMemcpyDeviceToHost, s));
@@ -551,11 +555,11 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
                 if (W.h_active[i]) W.refine_steps[i] = step;
             }
             if (act == 0 || step == B->opt.max_refine) break;
-            CHOM_TRY((pcg<float, C, R>(B, W, W.graph32, W.r32.p, W.xf.p, W.rf.p, W.zf.p, W.pf.p, W.qf.p, W.minv32.p,
+            CHOM_TRY((pcg<float, C, R>(B, W, W.graph32, W.r32.p, W.xf.p, W.rf.p, W.pf.p, W.qf.p, W.minv32.p,
                                        ginv_inner32, irtol2, 1, W.cols_outer.p)));
             CHOM_HIP(launch_axpy_x64(W.total_vals, W.x64.p, W.xf.p, s));
             CHOM_HIP((launch_operator<double, C, R>(L, nprob, L.rg, W.x64.p, W.q64.p,
-                                                    W.partial.p, nullptr, s)));
+                                                    W.accpq.p, nullptr, s)));
             CHOM_HIP((launch_residual64<C, R>(L, W.b.p, W.q64.p, W.r64.p, W.r32.p, s)));
         }
         x64 = W.x64.p;
@@ -584,10 +588,10 @@ static int time_op(chom_batch *B, ClassWS<C, R> &W, const T *x, T *y, int rg, in
     hipEvent_t e0, e1;
     CHOM_HIP(hipEventCreate(&e0));
     CHOM_HIP(hipEventCreate(&e1));
-    CHOM_HIP((launch_operator<T, C, R>(L, L.nprob, rg, x, y, W.partial.p, nullptr, s)));
+    CHOM_HIP((launch_operator<T, C, R>(L, L.nprob, rg, x, y, W.accpq.p, nullptr, s)));
     CHOM_HIP(hipEventRecord(e0, s));
     for (int i = 0; i < reps; ++i)
-        CHOM_HIP((launch_operator<T, C, R>(L, L.nprob, rg, x, y, W.partial.p, nullptr, s)));
+        CHOM_HIP((launch_operator<T, C, R>(L, L.nprob, rg, x, y, W.accpq.p, nullptr, s)));
     CHOM_HIP(hipEventRecord(e1, s));
     CHOM_HIP(hipEventSynchronize(e1));
     float t = 0.f;
@@ -600,7 +604,7 @@ static int time_op(chom_batch *B, ClassWS<C, R> &W, const T *x, T *y, int rg, in
 
 // Time `reps` CG vector sweeps (dir + update) with nwg workgroups per problem.
 template <typename T, int C, int R>
-static int time_vec(chom_batch *B, ClassWS<C, R> &W, T *x, T *r, T *z, T *p, const T *q, const void *minv, int nwg,
+static int time_vec(chom_batch *B, ClassWS<C, R> &W, T *x, T *r, T *p, const T *q, const void *minv, int nwg,
                     int reps, double *ms) {
     Launch L = W.L;
     L.nwg = nwg;
@@ -613,8 +617,8 @@ static int time_vec(chom_batch *B, ClassWS<C, R> &W, T *x, T *r, T *z, T *p, con
     CHOM_HIP(hipEventCreate(&e1));
     CHOM_HIP(hipEventRecord(e0, s));
     for (int i = 0; i < reps; ++i) {
-        CHOM_HIP((launch_cg_dir<T, C, R>(L, r, z, p, minv, W.ycoef.p, W.cols.p, W.active.p, s)));
-        CHOM_HIP((launch_cg_update<T, C, R>(L, x, r, z, p, q, minv, W.cols.p, W.partial.p, W.active.p, s)));
+        CHOM_HIP((launch_cg_dir<T, C, R>(L, r, p, minv, W.ycoef.p, W.cols.p, W.active.p, s)));
+        CHOM_HIP((launch_cg_update<T, C, R>(L, x, r, p, q, minv, W.cols.p, W.acc.p, W.active.p, s)));
     }
     CHOM_HIP(hipEventRecord(e1, s));
     CHOM_HIP(hipEventSynchronize(e1));
@@ -648,14 +652,12 @@ static int autotune_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp
     const size_t nv = W.total_vals, nq = W.total_q;
     if (f32) {
         CHOM_HIP(hipMemsetAsync(W.pf.p, 0, sizeof(float) * nv, s));
-        CHOM_HIP(hipMemsetAsync(W.zf.p, 0, sizeof(float) * nv, s));
         CHOM_HIP(hipMemsetAsync(W.rf.p, 0, sizeof(float) * nv, s));
         CHOM_HIP(hipMemsetAsync(W.xf.p, 0, sizeof(float) * nv, s));
         CHOM_HIP(hipMemsetAsync(W.qf.p, 0, sizeof(float) * nq, s));
         CHOM_HIP(hipMemsetAsync(W.minv32.p, 0, sizeof(float) * W.total_pts * ClassWS<C, R>::MS, s));
     } else {
         CHOM_HIP(hipMemsetAsync(W.pd.p, 0, sizeof(double) * nv, s));
-        CHOM_HIP(hipMemsetAsync(W.zd.p, 0, sizeof(double) * nv, s));
         CHOM_HIP(hipMemsetAsync(W.rd.p, 0, sizeof(double) * nv, s));
         CHOM_HIP(hipMemsetAsync(W.xd.p, 0, sizeof(double) * nv, s));
         CHOM_HIP(hipMemsetAsync(W.qd.p, 0, sizeof(double) * nq, s));
@@ -682,8 +684,8 @@ static int autotune_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp
     int best_nwg = W.L.nwg;
     for (int i = 0; i < 4; ++i) {
         double ms;
-        if (f32) CHOM_TRY((time_vec<float, C, R>(B, W, W.xf.p, W.rf.p, W.zf.p, W.pf.p, W.qf.p, W.minv32.p, nwgs[i], 5, &ms)));
-        else CHOM_TRY((time_vec<double, C, R>(B, W, W.xd.p, W.rd.p, W.zd.p, W.pd.p, W.qd.p, W.minv64.p, nwgs[i], 5, &ms)));
+        if (f32) CHOM_TRY((time_vec<float, C, R>(B, W, W.xf.p, W.rf.p, W.pf.p, W.qf.p, W.minv32.p, nwgs[i], 5, &ms)));
+        else CHOM_TRY((time_vec<double, C, R>(B, W, W.xd.p, W.rd.p, W.pd.p, W.qd.p, W.minv64.p, nwgs[i], 5, &ms)));
         if (ms < best) {
             best = ms;
             best_nwg = nwgs[i];

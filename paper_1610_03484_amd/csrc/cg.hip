@@ -40,10 +40,21 @@ __device__ inline void wave_partials(const double *acc, int REC, double *partial
     wave_partials(acc, REC, partial, prob, R, w, gridDim.x, blockIdx.x);
 }
 
-// r = b, x = 0, z0 = M^-1 r; partial sums.  WRITE = false: only the sums.
+// Adds this wave's record to the striped accumulators of its column (see ACC_STRIPES).
+template <int C>
+__device__ inline void wave_accum(const double *acc, int REC, double *accbuf, int prob, int R, int w) {
+    const int lane = threadIdx.x & 63;
+    const int stripe = blockIdx.x & (ACC_STRIPES - 1);
+    for (int k = 0; k < REC; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) unsafeAtomicAdd(&accbuf[acc_index<C>(prob, R, w, k, stripe)], s);
+    }
+}
+
+// r = b, x = 0; partial sums of r, z0 = M^-1 r.  WRITE = false: only the sums.
 template <typename T, int C, int R, int NR, bool WRITE>
 __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const Prob *probs, const T *b, T *x,
-                                                         T *r, T *z, const T *minv, double *partial, int pstride) {
+                                                         T *r, const T *minv, double *accbuf) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int REC = 2 + C * NR;
     const int prob = blockIdx.y;
@@ -73,7 +84,6 @@ __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const 
             for (int c = 0; c < C; ++c) {
                 r[o + c] = rv[c];
                 x[o + c] = T(0);
-                z[o + c] = zv[c];
             }
         }
 #pragma unroll
@@ -84,7 +94,7 @@ __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const 
             for (int a = 0; a < NR; ++a) acc[2 + c * NR + a] += row[a] * (double)zv[c];
         }
     }
-    wave_partials(acc, REC, partial, prob, R, w, pstride, blockIdx.x);
+    wave_accum<C>(acc, REC, accbuf, prob, R, w);
 }
 
 // z = z0 - M^-1 C^T y ; r = r - C^T y ; p = z + beta p.  With the two-level
@@ -93,8 +103,8 @@ __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const 
 // mg_fcorr_kernel), Q = P_0 P_1 (P_0 injects vertex values, P_1 interpolates
 // from the n/2 grid).
 template <typename T, int C, int R, int NR>
-__global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const Prob *probs, T *r, const T *z,
-                                                        T *p, const T *minv, const double *ycoef,
+__global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const Prob *probs, T *r, T *p,
+                                                        const T *minv, const double *ycoef,
                                                         const ColState *cols, const int *prob_active,
                                                         MgDir<T> mg) {
     constexpr int MS = (C == 3) ? 6 : 1;
@@ -115,9 +125,10 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
         const long long pt = blk * 64 + lane;
         if (pt >= G.npts) continue;
         const long long o = P.voff + (w * G.npts + pt) * C;
-        T zv[C];
+        T rv[C], zv[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) zv[c] = z[o + c];
+        for (int c = 0; c < C; ++c) rv[c] = r[o + c];
+        minv_apply<T, C>(Mp + pt * MS, rv, zv);   // z0 = M^-1 r, as in the update kernel's sums
         if constexpr (NR > 0) {
             if (proj) {
                 // projection correction M^-1 C^T y evaluated in FP64
@@ -135,7 +146,7 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     zv[c] = (T)((double)zv[c] - corr[c]);
-                    r[o + c] = (T)((double)r[o + c] - ct[c]);
+                    r[o + c] = (T)((double)rv[c] - ct[c]);
                 }
             }
         }
@@ -176,12 +187,13 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
 }
 
 // x += alpha p ; r -= alpha q (q gathered from the operator's tile boxes) ;
-// z0 = M^-1 r ; partial sums.
+// partial sums of r and z0 = M^-1 r (z0 itself is formed again by the
+// direction kernel, which reads r anyway).
 template <typename T, int C, int R, int NR>
 __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, const Prob *probs, int rg, T *x, T *r,
-                                                           T *z, const T *p, const T *q, const T *minv,
-                                                           const ColState *cols, double *partial,
-                                                           const int *prob_active, int pstride) {
+                                                           const T *p, const T *q, const T *minv,
+                                                           const ColState *cols, double *accbuf,
+                                                           const int *prob_active) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int REC = 2 + C * NR;
     const int prob = blockIdx.y;
@@ -189,10 +201,7 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
     double acc[REC];
 #pragma unroll
     for (int k = 0; k < REC; ++k) acc[k] = 0.0;
-    if (prob_active[prob] == 0) {
-        wave_partials(acc, REC, partial, prob, R, w, pstride, blockIdx.x);
-        return;
-    }
+    if (prob_active[prob] == 0) return;
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
     const T al = (T)cols[prob * R + w].alpha;
@@ -227,14 +236,13 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
         minv_apply<T, C>(Mi, rv, zv);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            z[o + c] = zv[c];
             acc[0] += (double)rv[c] * (double)zv[c];
             acc[1] += (double)rv[c] * (double)rv[c];
 #pragma unroll
             for (int a = 0; a < NR; ++a) acc[2 + c * NR + a] += row[a] * (double)zv[c];
         }
     }
-    wave_partials(acc, REC, partial, prob, R, w, pstride, blockIdx.x);
+    wave_accum<C>(acc, REC, accbuf, prob, R, w);
 }
 
 // Outer (refinement) residual projected as a vector: r64 <- r64 - C^T y with
@@ -245,7 +253,7 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
 template <int C, int R, int NR>
 __global__ __launch_bounds__(64 * R) void proj_resid_kernel(const Geo *geos, const Prob *probs, double *r64,
                                                             float *r32, const double *minv64,
-                                                            const double *ycoef, double *partial) {
+                                                            const double *ycoef, double *accbuf) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int REC = 2 + C * NR;
     constexpr int S = C * NR;
@@ -289,7 +297,7 @@ __global__ __launch_bounds__(64 * R) void proj_resid_kernel(const Geo *geos, con
             for (int a = 0; a < NR; ++a) acc[2 + c * NR + a] += row[a] * zv[c];
         }
     }
-    wave_partials(acc, REC, partial, prob, R, w);
+    wave_accum<C>(acc, REC, accbuf, prob, R, w);
 }
 
 // Sum of part[k][0..nparts) for k in [0, K) into sums[k]; wave q takes
@@ -312,30 +320,23 @@ __device__ inline void reduce_kmajor(const double *part, int K, int nparts, doub
     }
 }
 
-// Wide reduction: one 64-lane workgroup per (entry k, problem) sums
-// part[prob][k][0..nparts) into sums[prob][k]; all loads of a lane are
-// independent, so the reduction costs a few memory latencies whatever K is.
-__global__ void reduce_parts_kernel(const double *part, int K, int nparts, double *sums) {
-    const int k = blockIdx.x, prob = blockIdx.y, lane = threadIdx.x;
-    const double *src = part + ((long long)prob * K + k) * nparts;
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int i = lane;
-    for (; i + 7 * 64 < nparts; i += 8 * 64) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) s[u] += src[i + u * 64];
-    }
-    for (; i < nparts; i += 64) s[0] += src[i];
-    const double t = wave_sum(((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])));
-    if (lane == 0) sums[(long long)prob * K + k] = t;
-}
-
-// alpha = r.z / p.Kp per column (sums: [prob][R] reduced from the operator's partials).
+// alpha = r.z / p.Kp per column; p.Kp is read from the operator's striped
+// accumulators ([prob][R][ACC_STRIPES]), which are cleared for the next step.
+// One workgroup per problem.
 template <int R>
-__global__ void finish_alpha_kernel(const double *pq_sums, ColState *cols) {
+__global__ __launch_bounds__(256) void finish_alpha_kernel(double *acc_pq, ColState *cols) {
+    __shared__ double vals[R * ACC_STRIPES];
     const int prob = blockIdx.x;
+    for (int t = threadIdx.x; t < R * ACC_STRIPES; t += blockDim.x) {
+        double *a = acc_pq + (long long)prob * R * ACC_STRIPES + t;
+        vals[t] = *a;
+        *a = 0.0;
+    }
+    __syncthreads();
     if (threadIdx.x < R) {
+        double v = 0.0;
+        for (int st = 0; st < ACC_STRIPES; ++st) v += vals[threadIdx.x * ACC_STRIPES + st];
         ColState &cs = cols[prob * R + threadIdx.x];
-        const double v = pq_sums[(long long)prob * R + threadIdx.x];
         cs.pq = v;
         if (cs.done) {
             cs.alpha = 0.0;
@@ -348,25 +349,41 @@ __global__ void finish_alpha_kernel(const double *pq_sums, ColState *cols) {
     }
 }
 
-// rz = r.z0 - c^T (C M^-1 C^T)^-1 c, projection coefficients y, beta, convergence
-// (sums: [prob][R][REC] from reduce_parts_kernel).
+// rz = r.z0 - c^T (C M^-1 C^T)^-1 c, projection coefficients y, beta, convergence;
+// the records [R][REC] are read from the vector kernels' striped accumulators,
+// which are cleared for the next step.  One workgroup per problem.
 template <int C, int R>
-__global__ void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, const double *sums_all,
-                                   const double *ginv, double *ycoef, ColState *cols, int *prob_active,
-                                   int first, double rtol2, int use_init, const ColState *mask) {
+__global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, double *accbuf,
+                                                         const double *ginv, double *ycoef, ColState *cols,
+                                                         int *prob_active, int first, double rtol2, int use_init,
+                                                         const ColState *mask) {
     constexpr int SMAX = C * 4;
+    constexpr int RECMAX = ACC_RECMAX<C>;
     const int prob = blockIdx.x;
     const int nrow = geos[probs[prob].geo].nrow;
     const int REC = 2 + C * NR;
     const int S = C * nrow;
-    const double *sums = sums_all + (long long)prob * R * REC;
     const int lane = threadIdx.x;
+    __shared__ double vals[R * RECMAX * ACC_STRIPES];
+    __shared__ double sums[R * RECMAX];
     __shared__ double sG[SMAX * SMAX];
+    __shared__ int sdone[R];
+    double *base = accbuf + (long long)prob * R * RECMAX * ACC_STRIPES;
+    for (int t = lane; t < R * RECMAX * ACC_STRIPES; t += blockDim.x) {
+        vals[t] = base[t];
+        base[t] = 0.0;
+    }
     for (int k = lane; k < S * S; k += blockDim.x) sG[k] = ginv[(long long)prob * SMAX * SMAX + k];
+    __syncthreads();
+    for (int e = lane; e < R * RECMAX; e += blockDim.x) {
+        double v = 0.0;
+        for (int st = 0; st < ACC_STRIPES; ++st) v += vals[e * ACC_STRIPES + st];
+        sums[e] = v;
+    }
     __syncthreads();
     if (lane < R) {
         ColState &cs = cols[prob * R + lane];
-        const double *rec = &sums[lane * REC];
+        const double *rec = &sums[lane * RECMAX];
         double rz = rec[0];
         if (S > 0) {
             double c[SMAX];
@@ -399,11 +416,12 @@ __global__ void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, c
         const double ref = use_init ? cs.rz_init : cs.eref;
         if (!cs.done && rz <= rtol2 * ref) cs.done = 1;
         if (cs.done) cs.beta = 0.0;
+        sdone[lane] = cs.done;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int act = 0;
-        for (int rr = 0; rr < R; ++rr) act += cols[prob * R + rr].done ? 0 : 1;
+        for (int rr = 0; rr < R; ++rr) act += sdone[rr] ? 0 : 1;
         prob_active[prob] = act;
     }
 }
@@ -417,38 +435,34 @@ __global__ void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, c
     }
 
 template <typename T, int C, int R>
-hipError_t launch_cg_init(const Launch &L, const T *b, T *x, T *r, T *z, const void *minv, double *partial,
-                          hipStream_t s, int pstride) {
+hipError_t launch_cg_init(const Launch &L, const T *b, T *x, T *r, const void *minv, double *accbuf, hipStream_t s) {
     dim3 grid(L.nwg, L.nprob);
     const T *M = (const T *)minv;
-    const int ps = pstride > 0 ? pstride : L.nwg;
     if (x == nullptr) {
-        CHOM_NR_DISPATCH(L.nr, (cg_init_kernel<T, C, R, NR, false><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, b, x, r, z, M, partial, ps)));
+        CHOM_NR_DISPATCH(L.nr, (cg_init_kernel<T, C, R, NR, false><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, b, x, r, M, accbuf)));
     } else {
-        CHOM_NR_DISPATCH(L.nr, (cg_init_kernel<T, C, R, NR, true><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, b, x, r, z, M, partial, ps)));
+        CHOM_NR_DISPATCH(L.nr, (cg_init_kernel<T, C, R, NR, true><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, b, x, r, M, accbuf)));
     }
     return hipGetLastError();
 }
 
 template <typename T, int C, int R>
-hipError_t launch_cg_dir(const Launch &L, T *r, const T *z, T *p, const void *minv, const double *ycoef,
+hipError_t launch_cg_dir(const Launch &L, T *r, T *p, const void *minv, const double *ycoef,
                          const ColState *cols, const int *prob_active, hipStream_t s, const void *mg_x0,
                          const void *mg_W) {
     dim3 grid(L.nwg, L.nprob);
     const T *M = (const T *)minv;
     MgDir<T> mg{(const T *)mg_x0, (const T *)mg_W, mg_x0 != nullptr ? 1 : 0};
-    CHOM_NR_DISPATCH(L.nr, (cg_dir_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, r, z, p, M, ycoef, cols, prob_active, mg)));
+    CHOM_NR_DISPATCH(L.nr, (cg_dir_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, r, p, M, ycoef, cols, prob_active, mg)));
     return hipGetLastError();
 }
 
 template <typename T, int C, int R>
-hipError_t launch_cg_update(const Launch &L, T *x, T *r, T *z, const T *p, const T *q, const void *minv,
-                            const ColState *cols, double *partial, const int *prob_active, hipStream_t s,
-                            int pstride) {
+hipError_t launch_cg_update(const Launch &L, T *x, T *r, const T *p, const T *q, const void *minv,
+                            const ColState *cols, double *accbuf, const int *prob_active, hipStream_t s) {
     dim3 grid(L.nwg, L.nprob);
     const T *M = (const T *)minv;
-    const int ps = pstride > 0 ? pstride : L.nwg;
-    CHOM_NR_DISPATCH(L.nr, (cg_update_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, L.rg, x, r, z, p, q, M, cols, partial, prob_active, ps)));
+    CHOM_NR_DISPATCH(L.nr, (cg_update_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, L.rg, x, r, p, q, M, cols, accbuf, prob_active)));
     return hipGetLastError();
 }
 
@@ -461,21 +475,28 @@ hipError_t launch_proj_resid(const Launch &L, double *r64, float *r32, const dou
 }
 
 template <int C, int R>
-hipError_t launch_finish_alpha(const Launch &L, const double *partial_pq, ColState *cols, hipStream_t s) {
-    reduce_parts_kernel<<<dim3(R, L.nprob), 64, 0, s>>>(partial_pq, R, L.max_tiles, L.sums);
-    finish_alpha_kernel<R><<<L.nprob, 64, 0, s>>>(L.sums, cols);
+hipError_t launch_finish_alpha(const Launch &L, double *acc_pq, ColState *cols, hipStream_t s) {
+    finish_alpha_kernel<R><<<L.nprob, 256, 0, s>>>(acc_pq, cols);
     return hipGetLastError();
 }
 
 template <int C, int R>
-hipError_t launch_finish_beta(const Launch &L, const double *partial, const double *ginv, double *ycoef,
-                              ColState *cols, int *prob_active, int first, double rtol2, int use_init,
-                              const ColState *mask, hipStream_t s, int nparts) {
-    const int REC = 2 + C * L.nr;
-    double *sums = L.sums;
-    reduce_parts_kernel<<<dim3(R * REC, L.nprob), 64, 0, s>>>(partial, R * REC, nparts > 0 ? nparts : L.nwg, sums);
-    finish_beta_kernel<C, R><<<L.nprob, 64, 0, s>>>(L.geos, L.probs, L.nr, sums, ginv, ycoef, cols, prob_active,
+hipError_t launch_finish_beta(const Launch &L, double *accbuf, const double *ginv, double *ycoef, ColState *cols,
+                              int *prob_active, int first, double rtol2, int use_init, const ColState *mask,
+                              hipStream_t s) {
+    finish_beta_kernel<C, R><<<L.nprob, 512, 0, s>>>(L.geos, L.probs, L.nr, accbuf, ginv, ycoef, cols, prob_active,
                                                     first, rtol2, use_init, mask);
+    return hipGetLastError();
+}
+
+__global__ void zero_kernel(long long n, double *p) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+hipError_t launch_zero(double *p, long long n, hipStream_t s) {
+    long long g = (n + 255) / 256;
+    zero_kernel<<<(int)(g < 1024 ? (g < 1 ? 1 : g) : 1024), 256, 0, s>>>(n, p);
     return hipGetLastError();
 }
 
@@ -617,24 +638,23 @@ hipError_t launch_project(const Launch &L, double *x64, const double *minv64, co
 
 // ------------------------------------------------------------------ instantiations
 #define CHOM_INST(T, C, R)                                                                                        \
-    template hipError_t launch_cg_init<T, C, R>(const Launch &, const T *, T *, T *, T *, const void *, double *, \
-                                                hipStream_t, int);                                               \
-    template hipError_t launch_cg_dir<T, C, R>(const Launch &, T *, const T *, T *, const void *, const double *, \
+    template hipError_t launch_cg_init<T, C, R>(const Launch &, const T *, T *, T *, const void *, double *,      \
+                                                hipStream_t);                                                    \
+    template hipError_t launch_cg_dir<T, C, R>(const Launch &, T *, T *, const void *, const double *,           \
                                                const ColState *, const int *, hipStream_t, const void *,         \
                                                const void *);                                                    \
-    template hipError_t launch_cg_update<T, C, R>(const Launch &, T *, T *, T *, const T *, const T *,           \
+    template hipError_t launch_cg_update<T, C, R>(const Launch &, T *, T *, const T *, const T *,                \
                                                   const void *, const ColState *, double *, const int *,         \
-                                                  hipStream_t, int);
+                                                  hipStream_t);
 CHOM_INST(double, 3, 6)
 CHOM_INST(float, 3, 6)
 CHOM_INST(double, 1, 3)
 CHOM_INST(float, 1, 3)
 
 #define CHOM_INST2(C, R)                                                                                         \
-    template hipError_t launch_finish_alpha<C, R>(const Launch &, const double *, ColState *, hipStream_t);      \
-    template hipError_t launch_finish_beta<C, R>(const Launch &, const double *, const double *, double *,       \
-                                                 ColState *, int *, int, double, int, const ColState *,          \
-                                                 hipStream_t, int);                                              \
+    template hipError_t launch_finish_alpha<C, R>(const Launch &, double *, ColState *, hipStream_t);            \
+    template hipError_t launch_finish_beta<C, R>(const Launch &, double *, const double *, double *, ColState *, \
+                                                 int *, int, double, int, const ColState *, hipStream_t);        \
     template hipError_t launch_proj_resid<C, R>(const Launch &, double *, float *, const double *,               \
                                                 const double *, double *, hipStream_t);                          \
     template hipError_t launch_residual64<C, R>(const Launch &, const double *, const double *, double *, float *, \

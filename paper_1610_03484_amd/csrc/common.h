@@ -438,6 +438,18 @@ __device__ inline int gauss_jordan(double A[12][24], int S) {
     return 1;
 }
 
+// Reductions of the CG steps (p.Kp, r.z0, r.r, C z0) go to striped FP64
+// accumulators: a workgroup adds its wave sums to stripe (block index mod
+// ACC_STRIPES) with hardware atomics, so no address sees more than a few dozen
+// adds; the finishing kernel sums the stripes and clears them.  Record k of load
+// case w of problem prob: acc_index<C>(prob, R, w, k, stripe).
+constexpr int ACC_STRIPES = 32;
+template <int C> constexpr int ACC_RECMAX = 2 + C * 4;
+template <int C>
+__host__ __device__ inline long long acc_index(int prob, int R, int w, int k, int stripe) {
+    return (((long long)prob * R + w) * ACC_RECMAX<C> + k) * ACC_STRIPES + stripe;
+}
+
 // Wavefront sum of a double (64 lanes).
 __device__ inline double wave_sum(double v) {
 #pragma unroll

@@ -390,7 +390,7 @@ template hipError_t launch_factors_hp<1>(const Launch &, double *, float *, hipS
 template <typename T, int P, int C, int R>
 __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, const Prob *probs, int max_tiles,
                                                           const T *__restrict__ x, T *__restrict__ y,
-                                                          const T *__restrict__ ef, double *partial_pq,
+                                                          const T *__restrict__ ef, double *acc_pq,
                                                           const int *prob_active) {
     using Sh = Shape<P>;
     constexpr int NE = Sh::NE, M = Sh::M, MA = Sh::MA, KA = Sh::KA, MB = Sh::MB, KB = Sh::KB;
@@ -416,10 +416,7 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
     const Geo &G = geos[Pb.geo];
     const int n = G.n;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (cell >= n * n * n || (prob_active != nullptr && prob_active[prob] == 0)) {
-        if (tid < R) partial_pq[((long long)prob * R + tid) * max_tiles + cell] = 0.0;
-        return;
-    }
+    if (cell >= n * n * n || (prob_active != nullptr && prob_active[prob] == 0)) return;
     const int ci = cell % n, cj = (cell / n) % n, ck = cell / (n * n);
     // ---- stage the DOF box, clear the output box, box index of every local DOF, factors
     const T *xp = x + Pb.voff;
@@ -564,25 +561,25 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
         double sm = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) sm += red[tid][w];
-        partial_pq[((long long)prob * R + tid) * max_tiles + cell] = sm;
+        unsafeAtomicAdd(&acc_pq[((long long)prob * R + tid) * ACC_STRIPES + (cell & (ACC_STRIPES - 1))], sm);
     }
 }
 
 template <typename T, int P, int C, int R>
-static hipError_t launch_hp(const Launch &L, int nprob, const T *x, T *y, double *partial_pq, const int *prob_active,
+static hipError_t launch_hp(const Launch &L, int nprob, const T *x, T *y, double *acc_pq, const int *prob_active,
                             hipStream_t s) {
     dim3 grid(L.max_tiles, nprob);
     const T *ef = std::is_same<T, double>::value ? (const T *)L.ef64 : (const T *)L.ef32;
-    hp_op_kernel<T, P, C, R><<<grid, HP_THREADS, 0, s>>>(L.geos, L.probs, L.max_tiles, x, y, ef, partial_pq,
+    hp_op_kernel<T, P, C, R><<<grid, HP_THREADS, 0, s>>>(L.geos, L.probs, L.max_tiles, x, y, ef, acc_pq,
                                                          prob_active);
     return hipGetLastError();
 }
 
 template <typename T, int C, int R>
-hipError_t launch_operator_hp(const Launch &L, int nprob, int /*rg*/, const T *x, T *y, double *partial_pq,
+hipError_t launch_operator_hp(const Launch &L, int nprob, int /*rg*/, const T *x, T *y, double *acc_pq,
                               const int *prob_active, hipStream_t s) {
-    if (L.order == 3) return launch_hp<T, 3, C, R>(L, nprob, x, y, partial_pq, prob_active, s);
-    return launch_hp<T, 4, C, R>(L, nprob, x, y, partial_pq, prob_active, s);
+    if (L.order == 3) return launch_hp<T, 3, C, R>(L, nprob, x, y, acc_pq, prob_active, s);
+    return launch_hp<T, 4, C, R>(L, nprob, x, y, acc_pq, prob_active, s);
 }
 
 template hipError_t launch_operator_hp<double, 3, 6>(const Launch &, int, int, const double *, double *, double *, const int *, hipStream_t);

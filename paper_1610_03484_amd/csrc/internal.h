@@ -32,7 +32,6 @@ struct Launch {
     int nr;               // largest constraint row count among the problems (0, 1, 4)
     int rg;               // load cases per operator workgroup
     long long max_tets;   // largest tet count among the problems
-    double *sums;         // reduced partial sums, [nprob][R * (2 + C * 4)]
     int order;            // polynomial order of every problem of the class
     long long total_q;    // values of the operator output of the class
     const double *ef64;   // orders 3, 4: element factors Q_e (packed symmetric 3C x 3C), per problem at Prob.eoff
@@ -43,7 +42,6 @@ struct Launch {
         int nlev;                  // largest level count among the problems
         int nwg[MG_MAXLEV];        // workgroups per problem of the level-l kernels
         int sweeps;                // l1 block-Jacobi sweeps on the coarsest level
-        int pbase, pstride;        // partial slots: level-0 kernel writes [pbase, pstride)
         long long total_pts;       // coarse points of the class
         double *A64, *D64;         // FP64 stencils and l1 inverses (setup)
         const void *A, *Dinv;      // the same in the precision of the solve
@@ -81,22 +79,20 @@ hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y,
                            double *partial_pq, const int *prob_active, hipStream_t s);
 
 template <typename T, int C, int R>
-hipError_t launch_cg_init(const Launch &L, const T *b, T *x, T *r, T *z, const void *minv, double *partial,
-                          hipStream_t s, int pstride = 0);
+hipError_t launch_cg_init(const Launch &L, const T *b, T *x, T *r, const void *minv, double *accbuf, hipStream_t s);
 template <typename T, int C, int R>
-hipError_t launch_cg_dir(const Launch &L, T *r, const T *z, T *p, const void *minv, const double *ycoef,
+hipError_t launch_cg_dir(const Launch &L, T *r, T *p, const void *minv, const double *ycoef,
                          const ColState *cols, const int *prob_active, hipStream_t s,
                          const void *mg_x0 = nullptr, const void *mg_W = nullptr);
 template <typename T, int C, int R>
-hipError_t launch_cg_update(const Launch &L, T *x, T *r, T *z, const T *p, const T *q, const void *minv,
-                            const ColState *cols, double *partial, const int *prob_active, hipStream_t s,
-                            int pstride = 0);
+hipError_t launch_cg_update(const Launch &L, T *x, T *r, const T *p, const T *q, const void *minv,
+                            const ColState *cols, double *accbuf, const int *prob_active, hipStream_t s);
 template <int C, int R>
-hipError_t launch_finish_alpha(const Launch &L, const double *partial_pq, ColState *cols, hipStream_t s);
+hipError_t launch_finish_alpha(const Launch &L, double *acc_pq, ColState *cols, hipStream_t s);
 template <int C, int R>
-hipError_t launch_finish_beta(const Launch &L, const double *partial, const double *ginv, double *ycoef,
-                              ColState *cols, int *prob_active, int first, double rtol2, int use_init,
-                              const ColState *mask, hipStream_t s, int nparts = 0);
+hipError_t launch_finish_beta(const Launch &L, double *accbuf, const double *ginv, double *ycoef, ColState *cols,
+                              int *prob_active, int first, double rtol2, int use_init, const ColState *mask,
+                              hipStream_t s);
 template <int C, int R>
 hipError_t launch_proj_resid(const Launch &L, double *r64, float *r32, const double *minv64,
                              const double *ycoef, double *partial, hipStream_t s);
@@ -104,6 +100,8 @@ template <int C, int R>
 hipError_t launch_residual64(const Launch &L, const double *b, const double *q64t, double *r64, float *r32,
                              hipStream_t s);
 hipError_t launch_axpy_x64(long long total, double *x64, const float *d32, hipStream_t s);
+// Clears n doubles with a kernel (safe inside captured graphs).
+hipError_t launch_zero(double *p, long long n, hipStream_t s);
 template <int C, int R>
 hipError_t launch_project(const Launch &L, double *x64, const double *minv64, const double *ginv64,
                           double *partial, hipStream_t s);
@@ -121,11 +119,11 @@ void set_error(const std::string &msg);
 void mg_levels(Geo &G);
 // Stencils of every level (FP64), their l1 inverses, and the copies in T.
 template <typename T, int C> hipError_t launch_mg_stencils(const Launch &L, T *A, T *Dinv, hipStream_t s);
-// One V-cycle on the vertex values of the fine vectors r (all load cases):
-// output in L.mg.x (level 0 block); with `partial`, the level-0 kernel also
-// writes r.e0 and C P e0 into partial slots [pbase, pbase + nwg[0]).
+// One V-cycle on the fine vectors r (all load cases), from the n/2 grid: output
+// e_1 in the level-1 block of L.mg.x; with `accbuf`, r . Q e_1 and C Q e_1 are
+// added to the CG step's accumulators.
 template <typename T, int C, int R>
-hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *partial, const int *prob_active, hipStream_t s);
+hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *accbuf, const int *prob_active, hipStream_t s);
 // Coarse correction f = e_1 - W y of the current CG step (into the level-1 res block).
 template <typename T, int C, int R>
 hipError_t launch_mg_fcorr(const Launch &L, const double *ycoef, const int *prob_active, hipStream_t s);

@@ -582,12 +582,11 @@ __global__ __launch_bounds__(64 * R) void mg_correct1_kernel(const Geo *geos, co
     for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) correct_pt<T, C>(V, Cv, v, vc.x, pt);
 }
 
-// Level-1 post-smoothing; with `partial`, the partial sums r_1 . e_1 (= r . Q e_1)
-// and rows1 . e_1 (= C Q e_1) into slots [pbase, pbase + gridDim.x).
+// Level-1 post-smoothing; with `accbuf`, the sums r_1 . e_1 (= r . Q e_1) and
+// rows1 . e_1 (= C Q e_1) are added to the CG step's striped accumulators.
 template <typename T, int C, int R, int NR>
 __global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
-                                                          double *partial, int pstride, int pbase,
-                                                          const int *prob_active) {
+                                                          double *accbuf, const int *prob_active) {
     constexpr int CC = C * C;
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int REC = 2 + C * NR;
@@ -609,7 +608,7 @@ __global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const
         const long long np = (long long)V.lw * V.lw * V.lw;
         for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) {
             post_pt<T, C>(V, A, D, v, pt);
-            if (partial != nullptr) {
+            if (accbuf != nullptr) {
                 T rv[C], ov[C];
                 load_c<T, C>(v.r + pt * C, rv);
                 load_c<T, C>(v.x + pt * C, ov);
@@ -624,10 +623,11 @@ __global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const
             }
         }
     }
-    if (partial != nullptr) {
+    if (accbuf != nullptr) {
+        const int stripe = blockIdx.x & (ACC_STRIPES - 1);
         for (int k = 0; k < REC; ++k) {
             const double sum = wave_sum(pacc[k]);
-            if (lane == 0) partial[(((long long)prob * R + w) * REC + k) * pstride + pbase + blockIdx.x] = sum;
+            if (lane == 0 && k != 1) unsafeAtomicAdd(&accbuf[acc_index<C>(prob, R, w, k, stripe)], sum);
         }
     }
 }
@@ -955,7 +955,7 @@ hipError_t launch_mg_stencils(const Launch &L, T *A, T *Dinv, hipStream_t s) {
 }
 
 template <typename T, int C, int R>
-hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *partial, const int *prob_active, hipStream_t s) {
+hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *accbuf, const int *prob_active, hipStream_t s) {
     const auto &M = L.mg;
     VPtr<T, C, R> Q;
     Q.fine_r = r;
@@ -973,8 +973,8 @@ hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *partial, const 
     mg_fused_kernel<T, C, R><<<dim3(R, L.nprob), MG_FUSED_BS, shm, s>>>(L.geos, L.probs, Q, M.sweeps, M.lds_vec,
                                                                        M.lds_sten, prob_active);
     mg_correct1_kernel<T, C, R><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, prob_active);
-    CHOM_MG_NR_DISPATCH(L.nr, (mg_post1_kernel<T, C, R, NR><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, partial,
-                                                                                  M.pstride, M.pbase, prob_active)));
+    CHOM_MG_NR_DISPATCH(L.nr, (mg_post1_kernel<T, C, R, NR><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, accbuf,
+                                                                                  prob_active)));
     return hipGetLastError();
 }
 

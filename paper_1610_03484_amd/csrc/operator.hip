@@ -28,7 +28,7 @@ int operator_tiles(const Geo &G) { return G.tiles_x * G.tiles_y * G.tiles_z; }
 template <typename T, int C, int R, int RG>
 __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const Prob *probs, int max_tiles,
                                                           const T *__restrict__ x, T *__restrict__ y,
-                                                          double *partial_pq, const int *prob_active) {
+                                                          double *acc_pq, const int *prob_active) {
     constexpr int NG = R / RG;
     constexpr int RCg = RG * C;
     constexpr int PS = RCg + 1;
@@ -46,10 +46,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     const int tt = threadIdx.x;
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
-    if (tile >= G.ntiles || (prob_active != nullptr && prob_active[prob] == 0)) {
-        if (tt < RG) partial_pq[((long long)prob * R + grp * RG + tt) * max_tiles + tile] = 0.0;
-        return;
-    }
+    if (tile >= G.ntiles || (prob_active != nullptr && prob_active[prob] == 0)) return;
     const int n = G.n, m2 = 2 * n;
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, tz = tile / (G.tiles_x * G.tiles_y);
     const int cx0 = tx * TX, cy0 = ty * TY, cz0 = tz * TZ;
@@ -154,7 +151,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
         qt[i] = (T)ys[pt * PS + v];
     }
 
-    // ---- element-energy partial sums (layout [prob][load case][max_tiles])
+    // ---- element energies p.Kp into the striped accumulators [prob][load case][ACC_STRIPES]
     const int lane = tt & 63, wv = tt >> 6;
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
@@ -166,35 +163,35 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) s += red[tt][w];
-        partial_pq[((long long)prob * R + grp * RG + tt) * max_tiles + tile] = s;
+        unsafeAtomicAdd(&acc_pq[((long long)prob * R + grp * RG + tt) * ACC_STRIPES + (tile & (ACC_STRIPES - 1))], s);
     }
 }
 
 template <typename T, int C, int R, int RG>
 static hipError_t launch_rg(const Geo *geos, const Prob *probs, int nprob, int max_tiles, const T *x, T *y,
-                            double *partial_pq, const int *prob_active, hipStream_t s) {
+                            double *acc_pq, const int *prob_active, hipStream_t s) {
     dim3 grid(max_tiles * (R / RG), nprob);
-    op_p2_kernel<T, C, R, RG><<<grid, TILE_TETS, 0, s>>>(geos, probs, max_tiles, x, y, partial_pq, prob_active);
+    op_p2_kernel<T, C, R, RG><<<grid, TILE_TETS, 0, s>>>(geos, probs, max_tiles, x, y, acc_pq, prob_active);
     return hipGetLastError();
 }
 
 template <typename T, int C, int R>
-hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y, double *partial_pq,
+hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y, double *acc_pq,
                            const int *prob_active, hipStream_t s) {
-    if (L.order != 2) return launch_operator_hp<T, C, R>(L, nprob, rg, x, y, partial_pq, prob_active, s);
+    if (L.order != 2) return launch_operator_hp<T, C, R>(L, nprob, rg, x, y, acc_pq, prob_active, s);
     const Geo *geos = L.geos;
     const Prob *probs = L.probs;
     const int max_tiles = L.max_tiles;
     if constexpr (C == 3) {
         switch (rg) {
-            case 1: return launch_rg<T, C, R, 1>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
-            case 3: return launch_rg<T, C, R, 3>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
-            default: return launch_rg<T, C, R, 2>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
+            case 1: return launch_rg<T, C, R, 1>(geos, probs, nprob, max_tiles, x, y, acc_pq, prob_active, s);
+            case 3: return launch_rg<T, C, R, 3>(geos, probs, nprob, max_tiles, x, y, acc_pq, prob_active, s);
+            default: return launch_rg<T, C, R, 2>(geos, probs, nprob, max_tiles, x, y, acc_pq, prob_active, s);
         }
     } else {
         switch (rg) {
-            case 1: return launch_rg<T, C, R, 1>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
-            default: return launch_rg<T, C, R, 3>(geos, probs, nprob, max_tiles, x, y, partial_pq, prob_active, s);
+            case 1: return launch_rg<T, C, R, 1>(geos, probs, nprob, max_tiles, x, y, acc_pq, prob_active, s);
+            default: return launch_rg<T, C, R, 3>(geos, probs, nprob, max_tiles, x, y, acc_pq, prob_active, s);
         }
     }
 }
