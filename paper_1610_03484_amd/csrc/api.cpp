@@ -524,7 +524,7 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
             ginv_inner32 = W.ginv_mg.p;
         }
     }
-    CHOM_HIP((launch_rhs<C, R>(L, W.total_vals, W.b.p, W.cols.p, s)));
+    CHOM_HIP((launch_rhs<C, R>(L, W.total_vals, W.b.p, W.cols.p, W.q64.p, W.accpq.p, s)));
     const double rtol2 = B->opt.rtol * B->opt.rtol;
     double *x64 = nullptr;
     if (B->opt.precision == CHOM_FP64) {

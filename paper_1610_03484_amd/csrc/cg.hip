@@ -519,7 +519,7 @@ __global__ void residual64_kernel(const Geo *geos, const Prob *probs, int rg, co
             for (int w = 0; w < R; ++w) gather_tiles_col<double, C, R>(G, qt, rg, X, Y, Z, w, qv + w * C);
         for (int v = 0; v < RC; ++v) {
             const long long o = P.voff + ((v / C) * G.npts + pt) * C + v % C;
-            const double val = b[o] - qv[v];
+            const double val = (b ? b[o] : 0.0) - qv[v];
             r64[o] = val;
             if (r32) r32[o] = (float)val;
         }

@@ -71,8 +71,13 @@ hipError_t launch_precond(const Launch &L, long long total_pts, double *diag, do
 template <int C>
 hipError_t launch_gram(const Launch &L, const double *minv64, const float *minv32, double *gram_partial, int nwg,
                        double *ginv64, double *ginv32, int *bad, hipStream_t s, double *gmat = nullptr);
+// Load vectors b and linear-field energies (cols[].eref); q64t: FP64 tile-box
+// scratch, acc_pq: accumulator scratch (both overwritten).
 template <int C, int R>
-hipError_t launch_rhs(const Launch &L, long long total_vals, double *b, ColState *cols, hipStream_t s);
+hipError_t launch_rhs(const Launch &L, long long total_vals, double *b, ColState *cols, double *q64t,
+                      double *acc_pq, hipStream_t s);
+template <int C, int R>
+hipError_t launch_rhs_operator(const Launch &L, int rg, double *y, double *acc_pq, hipStream_t s);
 
 template <typename T, int C, int R>
 hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y,

@@ -25,7 +25,11 @@ namespace chom {
 
 int operator_tiles(const Geo &G) { return G.tiles_x * G.tiles_y * G.tiles_z; }
 
-template <typename T, int C, int R, int RG>
+// RHS = true: no input vector; every tet applies its constant stress (flux) of
+// the unit macro strain (gradient) of the load case, y = int grad(phi) . C eps_k,
+// and its energy |e| eps_k . C eps_k goes to the accumulators (load vectors of
+// the fluctuation problems, Sec. 2, Eqs. Eq_C_stress and eq_homo_flux).
+template <typename T, int C, int R, int RG, bool RHS = false>
 __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const Prob *probs, int max_tiles,
                                                           const T *__restrict__ x, T *__restrict__ y,
                                                           double *acc_pq, const int *prob_active) {
@@ -52,7 +56,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     const int cx0 = tx * TX, cy0 = ty * TY, cz0 = tz * TZ;
     const int X0 = 2 * cx0, Y0 = 2 * cy0, Z0 = 2 * cz0;
     const int hx = min(X0 + 2 * TX, m2), hy = min(Y0 + 2 * TY, m2), hz = min(Z0 + 2 * TZ, m2);
-    const T *xp = x + P.voff;   // vectors are [load case][point][component]
+    const T *xp = RHS ? nullptr : x + P.voff;   // vectors are [load case][point][component]
 
     // ---- stage the DOF box (this group's values), element data, geometry
     T tmp[NST];
@@ -60,7 +64,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     for (int k = 0; k < NST; ++k) {
         const int i = tt + TILE_TETS * k;
         T val = T(0);
-        if (i < NBOX) {   // i = (rr * BOXPTS + pt) * C + c: consecutive lanes read contiguous memory
+        if (!RHS && i < NBOX) {   // i = (rr * BOXPTS + pt) * C + c: consecutive lanes read contiguous memory
             const int rr = i / (BOXPTS * C), rem = i - rr * (BOXPTS * C);
             const int pt = rem / C, c = rem - (rem / C) * C;
             const int bx = pt % BX, by = (pt / BX) % BY, bz = pt / (BX * BY);
@@ -125,20 +129,60 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
             lp[k] = ((2 * lcx + off[k][0]) + BX * ((2 * lcy + off[k][1]) + BY * (2 * lcz + off[k][2]))) * PS;
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
-            T u[10][C], yv[10][C];
-#pragma unroll
-            for (int k = 0; k < 10; ++k)
-#pragma unroll
-                for (int c = 0; c < C; ++c) u[k][c] = xs[lp[k] + r * C + c];
-            p2_apply<T, C>(g, vol, a, mloc, u, yv);
+            T yv[10][C];
             double en = 0.0;
+            if constexpr (RHS) {
+                // constant stress of the unit load case: y_a = |e| sigma g_a, y_ab = |e| sigma (g_a + g_b)
+                const int kc = grp * RG + r;
+                T sv[3][3];
+                if constexpr (C == 3) {
+                    T eps[6] = {0, 0, 0, 0, 0, 0};
+                    eps[kc] = kc < 3 ? T(1) : T(0.5);   // engineering shear 1
+                    T sgm[6];
+                    stress_ti<T>(eps, a, mloc, sgm);
+                    sv[0][0] = sgm[0]; sv[0][1] = sgm[3]; sv[0][2] = sgm[5];
+                    sv[1][0] = sgm[3]; sv[1][1] = sgm[1]; sv[1][2] = sgm[4];
+                    sv[2][0] = sgm[5]; sv[2][1] = sgm[4]; sv[2][2] = sgm[2];
+                    en = (double)vol * (double)sgm[kc];
+                } else {
+                    T gk[3] = {0, 0, 0};
+                    gk[kc] = T(1);
+                    T fl[3];
+                    flux_ti<T>(gk, a, mloc, fl);
+                    sv[0][0] = fl[0]; sv[0][1] = fl[1]; sv[0][2] = fl[2];
+                    en = (double)vol * (double)fl[kc];
+                }
+#pragma unroll
+                for (int k = 0; k < 10; ++k) {
+                    T w3[3];
+                    if (k < 4) {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) w3[d] = vol * g[k][d];
+                    } else {
+                        int ea, eb;
+                        edge_verts(k - 4, ea, eb);
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) w3[d] = vol * (g[ea][d] + g[eb][d]);
+                    }
+#pragma unroll
+                    for (int c = 0; c < C; ++c) yv[k][c] = sv[c][0] * w3[0] + sv[c][1] * w3[1] + sv[c][2] * w3[2];
+                }
+            } else {
+                T u[10][C];
+#pragma unroll
+                for (int k = 0; k < 10; ++k)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) u[k][c] = xs[lp[k] + r * C + c];
+                p2_apply<T, C>(g, vol, a, mloc, u, yv);
+#pragma unroll
+                for (int k = 0; k < 10; ++k)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) en += (double)u[k][c] * (double)yv[k][c];
+            }
 #pragma unroll
             for (int k = 0; k < 10; ++k)
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    en += (double)u[k][c] * (double)yv[k][c];
-                    atomicAdd(&ys[lp[k] + r * C + c], (double)yv[k][c]);
-                }
+                for (int c = 0; c < C; ++c) atomicAdd(&ys[lp[k] + r * C + c], (double)yv[k][c]);
             pq[r] = en;
         }
     }
@@ -174,6 +218,28 @@ static hipError_t launch_rg(const Geo *geos, const Prob *probs, int nprob, int m
     op_p2_kernel<T, C, R, RG><<<grid, TILE_TETS, 0, s>>>(geos, probs, max_tiles, x, y, acc_pq, prob_active);
     return hipGetLastError();
 }
+
+// Tile boxes of K x_lin for the unit load cases (FP64, grouping rg) and the
+// linear-field energies in acc_pq.
+template <int C, int R>
+hipError_t launch_rhs_operator(const Launch &L, int rg, double *y, double *acc_pq, hipStream_t s) {
+    const int G = L.max_tiles;
+    if constexpr (C == 3) {
+        switch (rg) {
+            case 1: op_p2_kernel<double, C, R, 1, true><<<dim3(G * R, L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
+            case 3: op_p2_kernel<double, C, R, 3, true><<<dim3(G * (R / 3), L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
+            default: op_p2_kernel<double, C, R, 2, true><<<dim3(G * (R / 2), L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
+        }
+    } else {
+        switch (rg) {
+            case 1: op_p2_kernel<double, C, R, 1, true><<<dim3(G * R, L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
+            default: op_p2_kernel<double, C, R, 3, true><<<dim3(G * (R / 3), L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
+        }
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_rhs_operator<3, 6>(const Launch &, int, double *, double *, hipStream_t);
+template hipError_t launch_rhs_operator<1, 3>(const Launch &, int, double *, double *, hipStream_t);
 
 template <typename T, int C, int R>
 hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y, double *acc_pq,

@@ -83,6 +83,14 @@ hipError_t launch_element_setup(const Geo &G, const double *coords, const int32_
     return hipGetLastError();
 }
 
+// Tet handled by thread index u of a scatter kernel: threads run type-major
+// (u = t * cells + cell), so the 64 tets of a wave are of one type in 64
+// neighbouring cells and their atomic adds mostly hit different points.
+__device__ inline long long scatter_tet(long long u, long long ncells) {
+    const long long t = u / ncells;
+    return (u - t * ncells) * 6 + t;
+}
+
 // Decode tet id -> (cell coords, type) and the 10 DOF lattice points.
 __device__ inline void tet_points(const Geo &G, long long e, int &t, int P[10][3]) {
     const int n = G.n;
@@ -166,8 +174,9 @@ __global__ void diag_kernel(const Geo *geos, const Prob *probs, double *diag) {
     const Geo &G = geos[P.geo];
     double *D = diag + P.doff * MS;
     const long long nt = 6LL * G.n * G.n * G.n;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
-         e += (long long)gridDim.x * blockDim.x) {
+    for (long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x; u < nt;
+         u += (long long)gridDim.x * blockDim.x) {
+        const long long e = scatter_tet(u, nt / 6);
         int t, Pt[10][3];
         tet_points(G, e, t, Pt);
         double g[4][3], vol, a[3];
@@ -411,87 +420,41 @@ template hipError_t launch_gram<1>(const Launch &, const double *, const float *
 // for unit gradients), i.e. minus the stiffness times the interpolated linear
 // field; also the energy of the linear field eps_k : C_e eps_k |e| (reference
 // scale of the stopping test).
-template <int C, int R>
-__global__ void rhs_kernel(const Geo *geos, const Prob *probs, double *b, ColState *cols) {
-    const int prob = blockIdx.y;
-    const Prob &P = probs[prob];
-    const Geo &G = geos[P.geo];
-    double *bp = b + P.voff;
-    const long long nt = 6LL * G.n * G.n * G.n;
-    double eref[R];
-    for (int k = 0; k < R; ++k) eref[k] = 0.0;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
-         e += (long long)gridDim.x * blockDim.x) {
-        int t, Pt[10][3];
-        tet_points(G, e, t, Pt);
-        double g[4][3], vol, a[3];
-        int ph;
-        GeoSel<double>::get(G, e, t, g, vol);
-        GeoSel<double>::elem(G, e, a, ph);
-        const double *m = P.mat64[ph ? 1 : 0];
-        for (int k = 0; k < R; ++k) {
-            double sig[3][3];
-            if constexpr (C == 3) {
-                double eps[6] = {0, 0, 0, 0, 0, 0};
-                if (k < 3) eps[k] = 1.0; else eps[k] = 0.5;  // engineering shear 1
-                double s[6];
-                stress_ti<double>(eps, a, m, s);
-                sig[0][0] = s[0]; sig[1][1] = s[1]; sig[2][2] = s[2];
-                sig[0][1] = sig[1][0] = s[3];
-                sig[1][2] = sig[2][1] = s[4];
-                sig[2][0] = sig[0][2] = s[5];
-                eref[k] += vol * s[k];
-            } else {
-                double gk[3] = {0, 0, 0};
-                gk[k] = 1.0;
-                double q[3];
-                flux_ti<double>(gk, a, m, q);
-                sig[0][0] = q[0]; sig[0][1] = q[1]; sig[0][2] = q[2];
-                eref[k] += vol * q[k];
-            }
-            for (int kk = 0; kk < 10; ++kk) {
-                if (dirichlet_boundary(G, Pt[kk][0], Pt[kk][1], Pt[kk][2])) continue;
-                double w[3];
-                if (kk < 4) {
-                    for (int d = 0; d < 3; ++d) w[d] = vol * g[kk][d];
-                } else {
-                    int a2, b2;
-                    edge_verts(kk - 4, a2, b2);
-                    for (int d = 0; d < 3; ++d) w[d] = vol * (g[a2][d] + g[b2][d]);
-                }
-                const long long idx = lat_index(G, Pt[kk][0], Pt[kk][1], Pt[kk][2]);
-                for (int c = 0; c < C; ++c) {
-                    const double v = -(sig[c][0] * w[0] + sig[c][1] * w[1] + sig[c][2] * w[2]);
-                    atomicAdd(&bp[(k * G.npts + idx) * C + c], v);
-                }
-            }
-        }
-    }
-    // block reduction of eref, one atomic per block and load case
-    __shared__ double red[R][4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int k = 0; k < R; ++k) {
-        const double v = wave_sum(eref[k]);
-        if (lane == 0) red[k][wv] = v;
-    }
-    __syncthreads();
+// Linear-field energies of the unit load cases from the striped accumulators
+// (cleared afterwards).
+template <int R>
+__global__ void eref_kernel(double *acc_pq, ColState *cols) {
+    const int prob = blockIdx.x;
     if (threadIdx.x < R) {
-        double s = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[threadIdx.x][w];
-        atomicAdd(&cols[prob * R + threadIdx.x].eref, s);
+        double *a = acc_pq + ((long long)prob * R + threadIdx.x) * ACC_STRIPES;
+        double v = 0.0;
+        for (int st = 0; st < ACC_STRIPES; ++st) {
+            v += a[st];
+            a[st] = 0.0;
+        }
+        cols[prob * R + threadIdx.x].eref = v;
     }
 }
 
+// Order 2: the operator kernel in its load-vector mode writes the tile boxes of
+// K x_lin (no global atomics) and b = -K x_lin is gathered from them; orders 3,
+// 4 scatter per tet.
 template <int C, int R>
-hipError_t launch_rhs(const Launch &L, long long total_vals, double *b, ColState *cols, hipStream_t s) {
-    hipError_t err = hipMemsetAsync(b, 0, sizeof(double) * total_vals, s);
+hipError_t launch_rhs(const Launch &L, long long total_vals, double *b, ColState *cols, double *q64t,
+                      double *acc_pq, hipStream_t s) {
+    if (L.order != 2) {
+        hipError_t err = hipMemsetAsync(b, 0, sizeof(double) * total_vals, s);
+        if (err != hipSuccess) return err;
+        return launch_rhs_hp<C, R>(L, b, cols, s);
+    }
+    hipError_t err = launch_zero(acc_pq, (long long)L.nprob * R * ACC_STRIPES, s);
     if (err != hipSuccess) return err;
-    if (L.order != 2) return launch_rhs_hp<C, R>(L, b, cols, s);
-    dim3 grid(grid_for(L.max_tets, 256, 2048), L.nprob);
-    rhs_kernel<C, R><<<grid, 256, 0, s>>>(L.geos, L.probs, b, cols);
+    if ((err = launch_rhs_operator<C, R>(L, L.rg, q64t, acc_pq, s)) != hipSuccess) return err;
+    if ((err = launch_residual64<C, R>(L, nullptr, q64t, b, nullptr, s)) != hipSuccess) return err;
+    eref_kernel<R><<<L.nprob, 64, 0, s>>>(acc_pq, cols);
     return hipGetLastError();
 }
-template hipError_t launch_rhs<3, 6>(const Launch &, long long, double *, ColState *, hipStream_t);
-template hipError_t launch_rhs<1, 3>(const Launch &, long long, double *, ColState *, hipStream_t);
+template hipError_t launch_rhs<3, 6>(const Launch &, long long, double *, ColState *, double *, double *, hipStream_t);
+template hipError_t launch_rhs<1, 3>(const Launch &, long long, double *, ColState *, double *, double *, hipStream_t);
 
 }  // namespace chom
