@@ -89,7 +89,7 @@ def calibration_copy(torch):
 # 24^3 items), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the calibration copy
 # (profiles/op_p2_mech_fp32_24cubed_three_bc_traffic.md).  Must be re-measured (or set
 # to None) whenever that kernel changes.
-C1_OP_TRAFFIC_BYTES = 128_775_308
+C1_OP_TRAFFIC_BYTES = 128_768_158
 
 
 def algorithmic_mech_order(n, p, nprob, fp32):
