@@ -193,7 +193,7 @@ def main():
                                    bc="periodic", **opts)
             rves.append(handles[n_i])
         n = int(max(sizes))
-        labels = [f"n={int(s)}" for s in sizes]
+        labels = [f"item {i} (n={int(s)})" for i, s in enumerate(sizes)]
     elif args.workload == "c3":
         n = wl["n"]
         items = args.items if args.items != 512 else 64
@@ -226,8 +226,10 @@ def main():
     for i, lab in enumerate(labels[:6]):
         print(f"[bench] {lab}: iters={rep[i]['iters']} refine={rep[i]['refine_steps']} "
               f"resid_max={max(rep[i]['resid']):.1e} asym={rep[i]['asym']:.1e}", file=sys.stderr)
+    worst = max(range(len(rep)), key=lambda i: max(rep[i]["iters"]))
     print(f"[bench] status: {sum(r['status'] == 0 for r in rep)}/{len(rep)} converged; "
-          f"max iters {max(max(r['iters']) for r in rep)}", file=sys.stderr)
+          f"max iters {max(rep[worst]['iters'])} ({labels[worst]}: iters={rep[worst]['iters']} "
+          f"refine={rep[worst]['refine_steps']})", file=sys.stderr)
 
     # accuracy against the FP64 GPU path (same RVEs, same parameters); for the
     # mixed-size batch it is measured by the tests on a stratified sample instead

@@ -173,6 +173,7 @@ struct chom_rve {
     DevBuf<double> rows;
     DevBuf<int> hoff;                                    // orders 3, 4: basis tables
     DevBuf<double> hW, hWd, hSd, hDA64, hDB64;
+    DevBuf<int> mg_nbr, mg_child, mg_par;               // coarse-level index tables
     DevBuf<float> hDA32, hDB32;
     std::unique_ptr<chom_batch> self;   // batch of this RVE alone (chom_homogenise)
     int self_size = 0;
@@ -254,7 +255,7 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
         P.qoff = qoff;
         P.eoff = eoff;
         P.moff = moff;
-        if (want_mg && G.mg_nlev >= 3) {
+        if (want_mg && G.mg_nlev >= 2) {
             moff += G.mg_pts;
             mg_nlev = std::max(mg_nlev, G.mg_nlev);
             long long deep = 0;
@@ -340,7 +341,7 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     // two-level preconditioner
     Launch::Mg &M = L.mg;
     std::memset(&M, 0, sizeof(M));
-    M.on = mg_nlev >= 3 ? 1 : 0;
+    M.on = mg_nlev >= 2 ? 1 : 0;
     if (M.on) {
         constexpr int CC = C * C;
         M.nlev = mg_nlev;
@@ -358,6 +359,30 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
         M.lds_vec = vec_el * tsz <= budget ? 1 : 0;
         M.lds_sten = (M.lds_vec && (vec_el + sten_el) * tsz <= budget) ? 1 : 0;
         M.lds_elems = (M.lds_vec ? vec_el : 0) + (M.lds_sten ? sten_el : 0);
+        // FP32 and every coarsest level at depth 1, 2 or 3 with at most 512 points per level:
+        // the up-front-load kernel (LDS: 3 level-2 vectors, 2 level-3 vectors, level-3 stencils and
+        // inverses; on a level-1 coarsest the two iterates)
+        M.small_elems = 0;
+        if (fp32 && !std::getenv("CHOM_MG_GENERIC")) {
+            long long need = 0;
+            bool ok = true;
+            for (auto &P : hp) {
+                const Geo &G = B->distinct[P.geo]->geo;
+                if (G.mg_nlev < 2) continue;
+                const int lc = G.mg_nlev - 1;
+                if (lc == 1) {
+                    const long long n1 = (long long)G.mg_lw[1] * G.mg_lw[1] * G.mg_lw[1];
+                    if (n1 > 512) ok = false;
+                    need = std::max(need, 2 * n1 * C);
+                    continue;
+                }
+                const long long n2 = (long long)G.mg_lw[2] * G.mg_lw[2] * G.mg_lw[2];
+                const long long n3 = lc == 3 ? (long long)G.mg_lw[3] * G.mg_lw[3] * G.mg_lw[3] : 0;
+                if (lc > 3 || n2 > 512 || n3 > 512) ok = false;
+                need = std::max(need, 3 * (n2 + 1) * C + 2 * (n3 + 1) * C + n3 * MG_SLOTS * CC + n3 * MS);
+            }
+            if (ok && need * (long long)sizeof(float) <= 64 * 1024) M.small_elems = need;
+        }
         const size_t np = (size_t)moff;
         CHOM_HIP(W.mgA64.ensure(np * MG_SLOTS * CC));
         CHOM_HIP(W.mgD64.ensure(np * MS));
@@ -1055,6 +1080,13 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
         set_error("chom_rve_create: mesh is not a Kuhn lattice (need (n+1)^3 vertices and 6 n^3 tets)");
         return CHOM_EMESH;
     }
+    {
+        const long long side = (long long)order * n + 1;   // lattice points are indexed in 32 bits
+        if (side * side * side >= (1LL << 31)) {
+            set_error("chom_rve_create: lattice of (order n + 1)^3 points too large (limit 2^31)");
+            return CHOM_EINVAL;
+        }
+    }
     if (!mesh->coords || !mesh->tets || !mesh->phase || !mesh->fibre_axis) {
         set_error("chom_rve_create: null mesh array");
         return CHOM_EINVAL;
@@ -1234,6 +1266,19 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
     G.geo64 = uniform ? nullptr : R->geo64.p;
     G.geo32 = uniform ? nullptr : R->geo32.p;
     G.rows = R->rows.p;
+    if (G.mg_nlev > 0) {
+        std::vector<int> nb, ch, pa;
+        mg_tables(G, nb, ch, pa);
+        CHOM_HIP(R->mg_nbr.ensure(nb.size()));
+        CHOM_HIP(R->mg_child.ensure(ch.size()));
+        CHOM_HIP(R->mg_par.ensure(pa.size()));
+        CHOM_HIP(hipMemcpy(R->mg_nbr.p, nb.data(), sizeof(int) * nb.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(R->mg_child.p, ch.data(), sizeof(int) * ch.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(R->mg_par.p, pa.data(), sizeof(int) * pa.size(), hipMemcpyHostToDevice));
+        G.mg_nbr = R->mg_nbr.p;
+        G.mg_child = R->mg_child.p;
+        G.mg_par = R->mg_par.p;
+    }
     if (order != 2) {
         hp::HostTables tb;
         if (!hp::build_tables(order, tb)) {

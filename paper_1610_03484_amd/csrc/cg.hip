@@ -157,20 +157,11 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
             if (X % pp == 0 && Y % pp == 0 && Z % pp == 0) {
                 // vertex (i, j, k): f at its level-1 parents (itself halved, or the two
                 // ends of the level-1 Kuhn edge whose midpoint it is), averaged
-                const int i = X / pp, j = Y / pp, k = Z / pp;
-                const int px = i & 1, py = j & 1, pz = k & 1;
-                const int n1 = G.mg_n[1], lw1 = G.mg_lw[1];
-                const bool per1 = G.bc == 1;
+                const int lw0 = G.mg_lw[0];
+                const long long v = X / pp + (long long)lw0 * (Y / pp + (long long)lw0 * (Z / pp));
+                const int *pa = G.mg_par + (G.mg_off[0] + v) * 16;
+                const long long J0 = pa[0], J1 = pa[1];
                 const T *f = mg.x0 + (P.moff * R + (long long)w * G.mg_pts + G.mg_off[1]) * C;
-                int a0 = (i - px) >> 1, b0 = (j - py) >> 1, c0 = (k - pz) >> 1;
-                int a1 = (i + px) >> 1, b1 = (j + py) >> 1, c1 = (k + pz) >> 1;
-                if (per1) {
-                    if (a1 == n1) a1 = 0;
-                    if (b1 == n1) b1 = 0;
-                    if (c1 == n1) c1 = 0;
-                }
-                const long long J0 = a0 + (long long)lw1 * (b0 + (long long)lw1 * c0);
-                const long long J1 = a1 + (long long)lw1 * (b1 + (long long)lw1 * c1);
 #pragma unroll
                 for (int c = 0; c < C; ++c) zv[c] += T(0.5) * (f[J0 * C + c] + f[J1 * C + c]);
             }

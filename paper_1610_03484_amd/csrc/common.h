@@ -59,6 +59,12 @@ struct Geo {
     int mg_lw[8];             // stored points per side: n_l (periodic) or n_l + 1
     long long mg_off[8];      // first point of level l within the RVE's coarse points
     long long mg_pts;         // coarse points over all levels
+    // index tables of the coarse levels, [mg_off[l] + point][16] (built on the host):
+    const int *mg_nbr;        // the 15 stencil neighbours (the point itself outside the lattice,
+                              // where the stencil block is zero)
+    const int *mg_child;      // l >= 1: the 15 children on level l - 1 (-1: none); level 1:
+                              // fine lattice indices of the children (-1: none or Dirichlet)
+    const int *mg_par;        // l < nlev - 1: the two parents on level l + 1 (equal for an even point)
 };
 
 // Kuhn neighbours of a lattice point (the P1 stencil): itself, the seven edge
@@ -383,10 +389,13 @@ __device__ inline void gather_tiles_col(const Geo &G, const T *qt, int rg, int X
             }
 }
 
+// Lattice coordinates of point pt (32-bit arithmetic: a lattice holds fewer than 2^31 points).
 __device__ inline void lattice_xyz(const Geo &G, long long pt, int &X, int &Y, int &Z) {
-    X = (int)(pt % G.Lw);
-    Y = (int)((pt / G.Lw) % G.Lw);
-    Z = (int)(pt / ((long long)G.Lw * G.Lw));
+    const int q = (int)pt, lw = G.Lw;
+    const int t = q / lw;
+    X = q - t * lw;
+    Z = t / lw;
+    Y = t - Z * lw;
 }
 
 // Symmetric point block (packed xx, yy, zz, xy, yz, xz; one entry for C = 1) times v.

@@ -50,6 +50,7 @@ struct Launch {
         long long max_pts[MG_MAXLEV];  // largest level-l point count of the class
         long long lds_elems;       // LDS of the fused kernel (elements of the solve precision)
         int lds_vec, lds_sten;     // levels >= 2 vectors / coarsest stencils in LDS
+        long long small_elems;     // > 0: FP32 levels >= 2 small enough for mg_fused_small_kernel (its LDS, floats)
         void *W;                   // coarse part of B C^T [moff + vertex][4C][C]
     } mg;
 };
@@ -120,8 +121,11 @@ void set_error(const std::string &msg);
 // Fills G.mg_*: level 0 is the vertex lattice of the n^3 grid; a level is
 // halved while its cell count is even and the half is at least 3 (so periodic
 // neighbours never alias).  No hierarchy (mg_nlev = 0) unless there are at least
-// three levels (n divisible by 4, n >= 12).
+// two levels (n even, n >= 6).
 void mg_levels(Geo &G);
+// Host index tables of the coarse levels (see Geo.mg_nbr / mg_child / mg_par),
+// [mg_pts][16] ints each.
+void mg_tables(const Geo &G, std::vector<int> &nbr, std::vector<int> &child, std::vector<int> &par);
 // Stencils of every level (FP64), their l1 inverses, and the copies in T.
 template <typename T, int C> hipError_t launch_mg_stencils(const Launch &L, T *A, T *Dinv, hipStream_t s);
 // One V-cycle on the fine vectors r (all load cases), from the n/2 grid: output

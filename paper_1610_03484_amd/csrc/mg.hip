@@ -48,9 +48,69 @@ void mg_levels(Geo &G) {
         if (nl % 2 != 0 || nl / 2 < 3) break;
         nl /= 2;
     }
-    if (cnt < 3) return;   // the coarse space starts on level 1 and needs a level below it
+    if (cnt < 2) return;   // the coarse space starts on level 1
     G.mg_nlev = cnt;
     G.mg_pts = off;
+}
+
+void mg_tables(const Geo &G, std::vector<int> &nbr, std::vector<int> &child, std::vector<int> &par) {
+    const long long tot = G.mg_pts;
+    nbr.assign((size_t)tot * 16, 0);
+    child.assign((size_t)tot * 16, -1);
+    par.assign((size_t)tot * 16, 0);
+    const bool per = G.bc == 1, dir = G.bc == 0;
+    auto wrapi = [](int i, int n) { i %= n; return i < 0 ? i + n : i; };
+    auto index = [&](int l, int i, int j, int k) -> long long {   // -1 outside
+        const int n = G.mg_n[l], lw = G.mg_lw[l];
+        if (per) {
+            i = wrapi(i, n); j = wrapi(j, n); k = wrapi(k, n);
+        } else if (i < 0 || j < 0 || k < 0 || i > n || j > n || k > n) {
+            return -1;
+        }
+        return (long long)i + (long long)lw * ((long long)j + (long long)lw * k);
+    };
+    auto boundary = [&](int l, int i, int j, int k) {
+        const int n = G.mg_n[l];
+        return dir && (i == 0 || j == 0 || k == 0 || i == n || j == n || k == n);
+    };
+    for (int l = 0; l < G.mg_nlev; ++l) {
+        const int lw = G.mg_lw[l];
+        const long long np = (long long)lw * lw * lw;
+        for (long long pt = 0; pt < np; ++pt) {
+            const int i = (int)(pt % lw), j = (int)((pt / lw) % lw), k = (int)(pt / ((long long)lw * lw));
+            const size_t row = (size_t)(G.mg_off[l] + pt) * 16;
+            for (int s = 0; s < MG_SLOTS; ++s) {
+                int dx, dy, dz;
+                kuhn_offset(s, dx, dy, dz);
+                const long long q = index(l, i + dx, j + dy, k + dz);
+                nbr[row + s] = (int)(q < 0 ? pt : q);
+            }
+            if (l >= 1) {
+                for (int m = 0; m < MG_SLOTS; ++m) {
+                    int ox, oy, oz;
+                    kuhn_offset(m, ox, oy, oz);
+                    int fi = 2 * i + ox, fj = 2 * j + oy, fk = 2 * k + oz;
+                    const long long f = index(l - 1, fi, fj, fk);
+                    if (f < 0 || boundary(l, i, j, k)) continue;
+                    if (l == 1) {
+                        if (boundary(0, fi, fj, fk)) continue;
+                        if (per) {
+                            fi = wrapi(fi, G.mg_n[0]); fj = wrapi(fj, G.mg_n[0]); fk = wrapi(fk, G.mg_n[0]);
+                        }
+                        const int p = G.p;
+                        child[row + m] = (int)((long long)(p * fi) + (long long)G.Lw * ((long long)(p * fj) + (long long)G.Lw * (p * fk)));
+                    } else {
+                        child[row + m] = (int)f;
+                    }
+                }
+            }
+            if (l + 1 < G.mg_nlev) {
+                const int px = i & 1, py = j & 1, pz = k & 1;
+                par[row + 0] = (int)index(l + 1, (i - px) >> 1, (j - py) >> 1, (k - pz) >> 1);
+                par[row + 1] = (int)index(l + 1, (i + px) >> 1, (j + py) >> 1, (k + pz) >> 1);
+            }
+        }
+    }
 }
 
 namespace {
@@ -361,94 +421,47 @@ __device__ inline void store_c(T *p, const T v[C]) {
     for (int c = 0; c < C; ++c) p[c] = v[c];
 }
 
-// Stencil neighbour s of (i, j, k): index, or the point itself with valid = false
-// outside a non-periodic lattice.
-__device__ inline bool nbr(const Lev &V, int i, int j, int k, int s, long long self, long long &q) {
-    int dx, dy, dz;
-    kuhn_offset(s, dx, dy, dz);
-    int qi = i + dx, qj = j + dy, qk = k + dz;
-    if (V.per) {
-        qi = qi < 0 ? qi + V.n : (qi >= V.n ? qi - V.n : qi);
-        qj = qj < 0 ? qj + V.n : (qj >= V.n ? qj - V.n : qj);
-        qk = qk < 0 ? qk + V.n : (qk >= V.n ? qk - V.n : qk);
-    } else if (qi < 0 || qj < 0 || qk < 0 || qi > V.n || qj > V.n || qk > V.n) {
-        q = self;
-        return false;
-    }
-    q = (long long)qi + (long long)V.lw * ((long long)qj + (long long)V.lw * qk);
-    return true;
-}
-
-// acc -= sum_s A[s] v[q_s] (A: the point's 15 blocks; v: level vector).
+// acc -= sum_s A[s] v[nb[s]] (A: the point's 15 blocks; nb: its row of the
+// neighbour table -- outside the lattice the point itself, whose block is zero).
 template <typename T, int C>
-__device__ inline void apply_stencil(const Lev &V, const T *Arow, const T *v, int i, int j, int k, long long pt,
-                                     T acc[C]) {
+__device__ inline void apply_stencil(const int *nb, const T *Arow, const T *v, T acc[C]) {
     constexpr int CC = C * C;
 #pragma unroll
     for (int s = 0; s < MG_SLOTS; ++s) {
-        long long q;
-        const bool ok = nbr(V, i, j, k, s, pt, q);
         T vq[C];
-        load_c<T, C>(v + q * C, vq);
-        const T m = ok ? T(1) : T(0);
+        load_c<T, C>(v + (long long)nb[s] * C, vq);
         const T *blk = Arow + s * CC;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            T t = T(0);
+        for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int d = 0; d < C; ++d) t += blk[c * C + d] * vq[d];
-            acc[c] -= m * t;
-        }
+            for (int d = 0; d < C; ++d) acc[c] -= blk[c * C + d] * vq[d];
     }
 }
 
-// Prolongation of the level-(l+1) vector e to level-l point (i, j, k) (wrapped):
-// e at the point if all coordinates are even, else the mean of the two ends of
-// the coarse Kuhn edge whose midpoint it is.
-template <typename T, int C>
-__device__ inline void prolong(const Lev &Cv, const T *e, int i, int j, int k, T out[C]) {
-    const int px = i & 1, py = j & 1, pz = k & 1;
-    const long long a = lev_index(Cv, (i - px) >> 1, (j - py) >> 1, (k - pz) >> 1);
-    const long long b = lev_index(Cv, (i + px) >> 1, (j + py) >> 1, (k + pz) >> 1);
-#pragma unroll
-    for (int c = 0; c < C; ++c) out[c] = T(0.5) * (e[a * C + c] + e[b * C + c]);
+__device__ inline const int *row16(const int *table, const Lev &V, long long pt) {
+    return table + (V.off + pt) * 16;
 }
 
 // r_1[I] = sum over the level-0 children v of I of the fine right side at v
-// (zero on a Dirichlet boundary); xp_1 = D^-1 r_1.
+// (children on a Dirichlet boundary and outside the lattice are absent from the
+// table); xp_1 = D^-1 r_1.
 template <typename T, int C>
-__device__ inline void restrict01_pt(const Geo &G, const Prob &P, const Lev &F, const Lev &Cv, int w,
-                                     const T *fine_r, const T *Dinv1, LV<T> v1, long long pt) {
+__device__ inline void restrict01_pt(const Geo &G, const Prob &P, const Lev &Cv, int w, const T *fine_r,
+                                     const T *Dinv1, LV<T> v1, long long pt) {
     constexpr int MS = (C == 3) ? 6 : 1;
-    int I, J, K;
-    lev_xyz(Cv, pt, I, J, K);
+    const int *ch = row16(G.mg_child, Cv, pt);
+    const T *fr = fine_r + P.voff + (long long)w * G.npts * C;
     T acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = T(0);
-    if (!lev_boundary(Cv, I, J, K)) {
-        const int p = G.p;
-        const T *fr = fine_r + P.voff + (long long)w * G.npts * C;
 #pragma unroll
-        for (int m = 0; m < MG_SLOTS; ++m) {
-            int ox, oy, oz;
-            kuhn_offset(m, ox, oy, oz);
-            int fi = 2 * I + ox, fj = 2 * J + oy, fk = 2 * K + oz;
-            bool ok = true;
-            if (F.per) {
-                fi = fi < 0 ? fi + F.n : (fi >= F.n ? fi - F.n : fi);
-                fj = fj < 0 ? fj + F.n : (fj >= F.n ? fj - F.n : fj);
-                fk = fk < 0 ? fk + F.n : (fk >= F.n ? fk - F.n : fk);
-            } else {
-                ok = fi >= 0 && fj >= 0 && fk >= 0 && fi <= F.n && fj <= F.n && fk <= F.n && !lev_boundary(F, fi, fj, fk);
-                if (!ok) fi = fj = fk = 0;
-            }
-            const long long lat = (long long)(p * fi) + (long long)G.Lw * ((long long)(p * fj) + (long long)G.Lw * (p * fk));
-            T v[C];
-            load_c<T, C>(fr + lat * C, v);
-            const T wgt = ok ? (m == 0 ? T(1) : T(0.5)) : T(0);
+    for (int m = 0; m < MG_SLOTS; ++m) {
+        const int f = ch[m];
+        T v[C];
+        load_c<T, C>(fr + (long long)(f < 0 ? 0 : f) * C, v);
+        const T wgt = f < 0 ? T(0) : (m == 0 ? T(1) : T(0.5));
 #pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] += wgt * v[c];
-        }
+        for (int c = 0; c < C; ++c) acc[c] += wgt * v[c];
     }
     store_c<T, C>(v1.r + pt * C, acc);
     T xv[C];
@@ -458,37 +471,30 @@ __device__ inline void restrict01_pt(const Geo &G, const Prob &P, const Lev &F, 
 
 // res = r - A xp.
 template <typename T, int C>
-__device__ inline void resid_pt(const Lev &V, const T *A, LV<T> v, long long pt) {
+__device__ inline void resid_pt(const Geo &G, const Lev &V, const T *A, LV<T> v, long long pt) {
     constexpr int CC = C * C;
-    int i, j, k;
-    lev_xyz(V, pt, i, j, k);
     T acc[C];
     load_c<T, C>(v.r + pt * C, acc);
-    apply_stencil<T, C>(V, A + pt * MG_SLOTS * CC, v.xp, i, j, k, pt, acc);
+    apply_stencil<T, C>(row16(G.mg_nbr, V, pt), A + pt * MG_SLOTS * CC, v.xp, acc);
     store_c<T, C>(v.res + pt * C, acc);
 }
 
 // r_{l+1}[I] = sum of the children of I (I with weight 1, the midpoints of its
 // 14 Kuhn edges with weight 1/2) of res_l; xp_{l+1} = D^-1 r_{l+1}.
 template <typename T, int C>
-__device__ inline void restrict_pt(const Lev &F, const Lev &Cv, const T *Dinv, LV<T> vf, LV<T> vc, long long pt) {
+__device__ inline void restrict_pt(const Geo &G, const Lev &Cv, const T *Dinv, LV<T> vf, LV<T> vc, long long pt) {
     constexpr int MS = (C == 3) ? 6 : 1;
-    int I, J, K;
-    lev_xyz(Cv, pt, I, J, K);
+    const int *ch = row16(G.mg_child, Cv, pt);
     T acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = T(0);
-    if (!lev_boundary(Cv, I, J, K)) {
 #pragma unroll
-        for (int m = 0; m < MG_SLOTS; ++m) {
-            int ox, oy, oz;
-            kuhn_offset(m, ox, oy, oz);
-            const long long f = lev_index(F, 2 * I + ox, 2 * J + oy, 2 * K + oz);
-            const long long fs = f < 0 ? 0 : f;
-            const T wgt = f < 0 ? T(0) : (m == 0 ? T(1) : T(0.5));
+    for (int m = 0; m < MG_SLOTS; ++m) {
+        const int f = ch[m];
+        const T wgt = f < 0 ? T(0) : (m == 0 ? T(1) : T(0.5));
+        const long long fs = f < 0 ? 0 : f;
 #pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] += wgt * vf.res[fs * C + c];
-        }
+        for (int c = 0; c < C; ++c) acc[c] += wgt * vf.res[fs * C + c];
     }
     store_c<T, C>(vc.r + pt * C, acc);
     T xv[C];
@@ -496,32 +502,35 @@ __device__ inline void restrict_pt(const Lev &F, const Lev &Cv, const T *Dinv, L
     store_c<T, C>(vc.xp + pt * C, xv);
 }
 
-// xc = xp + P e_{l+1}, stored in res.
+// Prolongation of the level-(l+1) vector e to level-l point pt: the mean of e at
+// its two parents (equal for a point with even coordinates).
 template <typename T, int C>
-__device__ inline void correct_pt(const Lev &V, const Lev &Cv, LV<T> v, const T *e, long long pt) {
-    int i, j, k;
-    lev_xyz(V, pt, i, j, k);
-    T xv[C];
-    load_c<T, C>(v.xp + pt * C, xv);
-    if (!lev_boundary(V, i, j, k)) {
-        T pe[C];
-        prolong<T, C>(Cv, e, i, j, k, pe);
+__device__ inline void prolong(const Geo &G, const Lev &V, const T *e, long long pt, T out[C]) {
+    const int *pa = row16(G.mg_par, V, pt);
+    const long long a = pa[0], b = pa[1];
 #pragma unroll
-        for (int c = 0; c < C; ++c) xv[c] += pe[c];
-    }
+    for (int c = 0; c < C; ++c) out[c] = T(0.5) * (e[a * C + c] + e[b * C + c]);
+}
+
+// xc = xp + P e_{l+1}, stored in res (e vanishes at Dirichlet boundary points).
+template <typename T, int C>
+__device__ inline void correct_pt(const Geo &G, const Lev &V, LV<T> v, const T *e, long long pt) {
+    T xv[C], pe[C];
+    load_c<T, C>(v.xp + pt * C, xv);
+    prolong<T, C>(G, V, e, pt, pe);
+#pragma unroll
+    for (int c = 0; c < C; ++c) xv[c] += pe[c];
     store_c<T, C>(v.res + pt * C, xv);
 }
 
 // x = xc + D^-1 (r - A xc).
 template <typename T, int C>
-__device__ inline void post_pt(const Lev &V, const T *A, const T *Dinv, LV<T> v, long long pt) {
+__device__ inline void post_pt(const Geo &G, const Lev &V, const T *A, const T *Dinv, LV<T> v, long long pt) {
     constexpr int CC = C * C;
     constexpr int MS = (C == 3) ? 6 : 1;
-    int i, j, k;
-    lev_xyz(V, pt, i, j, k);
     T acc[C];
     load_c<T, C>(v.r + pt * C, acc);
-    apply_stencil<T, C>(V, A + pt * MG_SLOTS * CC, v.res, i, j, k, pt, acc);
+    apply_stencil<T, C>(row16(G.mg_nbr, V, pt), A + pt * MG_SLOTS * CC, v.res, acc);
     T d[C], xi[C];
     minv_apply<T, C>(Dinv + pt * MS, acc, d);
     load_c<T, C>(v.res + pt * C, xi);
@@ -550,13 +559,13 @@ template <typename T, int C, int R>
 __global__ __launch_bounds__(64 * R) void mg_restrict01_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
                                                                const int *prob_active) {
     constexpr int MS = (C == 3) ? 6 : 1;
-    MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 3)
+    MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 2)
     const Lev F = level_of(G, 0), V = level_of(G, 1);
     const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
     const T *D = Q.Dinv + (P.moff + V.off) * MS;
     const long long np = (long long)V.lw * V.lw * V.lw;
     for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL)
-        restrict01_pt<T, C>(G, P, F, V, w, Q.fine_r, D, v, pt);
+        restrict01_pt<T, C>(G, P, V, w, Q.fine_r, D, v, pt);
 }
 
 template <typename T, int C, int R>
@@ -568,7 +577,7 @@ __global__ __launch_bounds__(64 * R) void mg_resid1_kernel(const Geo *geos, cons
     const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
     const T *A = Q.A + (P.moff + V.off) * MG_SLOTS * CC;
     const long long np = (long long)V.lw * V.lw * V.lw;
-    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) resid_pt<T, C>(V, A, v, pt);
+    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) resid_pt<T, C>(G, V, A, v, pt);
 }
 
 template <typename T, int C, int R>
@@ -579,7 +588,7 @@ __global__ __launch_bounds__(64 * R) void mg_correct1_kernel(const Geo *geos, co
     const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
     const LV<T> vc = level_vecs<T, C, R>(G, P, w, Cv, Q.r, Q.xp, Q.res, Q.x);
     const long long np = (long long)V.lw * V.lw * V.lw;
-    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) correct_pt<T, C>(V, Cv, v, vc.x, pt);
+    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) correct_pt<T, C>(G, V, v, vc.x, pt);
 }
 
 // Level-1 post-smoothing; with `accbuf`, the sums r_1 . e_1 (= r . Q e_1) and
@@ -597,7 +606,8 @@ __global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const
     for (int k = 0; k < REC; ++k) pacc[k] = 0.0;
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
-    if ((prob_active == nullptr || prob_active[prob] != 0) && G.mg_nlev >= 3) {
+    if ((prob_active == nullptr || prob_active[prob] != 0) && G.mg_nlev >= 2) {
+        const bool smooth = G.mg_nlev >= 3;   // level 1 coarsest: its output is final
         const Lev V = level_of(G, 1);
         const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
         const T *A = Q.A + (P.moff + V.off) * MG_SLOTS * CC;
@@ -607,7 +617,7 @@ __global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const
         const int nr = G.nrow < NR ? G.nrow : NR;
         const long long np = (long long)V.lw * V.lw * V.lw;
         for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) {
-            post_pt<T, C>(V, A, D, v, pt);
+            if (smooth) post_pt<T, C>(G, V, A, D, v, pt);
             if (accbuf != nullptr) {
                 T rv[C], ov[C];
                 load_c<T, C>(v.r + pt * C, rv);
@@ -637,7 +647,7 @@ __global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const
 template <typename T, int C, int R, int NR>
 __global__ __launch_bounds__(64 * R) void mg_fcorr_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
                                                           const T *W, const double *ycoef, const int *prob_active) {
-    MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 3)
+    MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 2)
     const Lev V = level_of(G, 1);
     const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
     const int nr = G.nrow < NR ? G.nrow : NR;
@@ -682,32 +692,32 @@ __global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_kernel(const Geo *geos, 
     if (prob_active != nullptr && prob_active[prob] == 0) return;
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
-    if (G.mg_nlev < 3) return;
-    const int lc = G.mg_nlev - 1;
+    if (G.mg_nlev < 2) return;
+    const int lc = G.mg_nlev - 1;   // 1: the n/2 grid itself is the coarsest
     const int tid = threadIdx.x, nt = blockDim.x;
     T *smem = (T *)mg_smem;
     // vectors of level l: levels >= 2 in LDS (when `lds`), packed in level order
     auto lvec = [&](int l) -> LV<T> {
         const Lev V = level_of(G, l);
-        if (l >= 2 && lds) {
+        if (l >= 2 && lds && lc >= 2) {
             const long long np = (long long)V.lw * V.lw * V.lw * C;
             T *b = smem + 4LL * C * (V.off - G.mg_off[2]);
             return LV<T>{b, b + np, b + 2 * np, b + 3 * np};
         }
         return level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
     };
-    const long long used = lds ? 4LL * C * (G.mg_pts - G.mg_off[2]) : 0;
+    const long long used = (lds && lc >= 2) ? 4LL * C * (G.mg_pts - G.mg_off[2]) : 0;
     // down
     for (int l = 1; l < lc; ++l) {
         const Lev F = level_of(G, l), Cv = level_of(G, l + 1);
         const long long npc = (long long)Cv.lw * Cv.lw * Cv.lw;
         const T *D = Q.Dinv + (P.moff + Cv.off) * MS;
         const LV<T> vf = lvec(l), vc = lvec(l + 1);
-        for (long long pt = tid; pt < npc; pt += nt) restrict_pt<T, C>(F, Cv, D, vf, vc, pt);
+        for (long long pt = tid; pt < npc; pt += nt) restrict_pt<T, C>(G, Cv, D, vf, vc, pt);
         __syncthreads();
         if (l + 1 < lc) {
             const T *A = Q.A + (P.moff + Cv.off) * MG_SLOTS * CC;
-            for (long long pt = tid; pt < npc; pt += nt) resid_pt<T, C>(Cv, A, vc, pt);
+            for (long long pt = tid; pt < npc; pt += nt) resid_pt<T, C>(G, Cv, A, vc, pt);
             __syncthreads();
         }
     }
@@ -727,30 +737,24 @@ __global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_kernel(const Geo *geos, 
 #pragma unroll
             for (int c = 0; c < C; ++c) v.x[pt * C + c] = v.xp[pt * C + c];
         __syncthreads();
-        T *bufs[2] = {v.x, v.res};
+        T *const b0 = v.x, *const b1 = v.res;   // iterates alternate (selected, not indexed)
         int cur = 0;
         if (np <= nt) {
             // one point per thread: neighbour indices, right side and inverse held in registers
             const bool have = tid < np;
             const long long pt = have ? tid : 0;
-            int i, j, k;
-            lev_xyz(V, pt, i, j, k);
             int qi[MG_SLOTS];
-            T qm[MG_SLOTS];
+            const int *nb = row16(G.mg_nbr, V, pt);
 #pragma unroll
-            for (int s2 = 0; s2 < MG_SLOTS; ++s2) {
-                long long q;
-                qm[s2] = nbr(V, i, j, k, s2, pt, q) ? T(1) : T(0);
-                qi[s2] = (int)q;
-            }
+            for (int s2 = 0; s2 < MG_SLOTS; ++s2) qi[s2] = nb[s2];
             T rv[C], Dv[MS];
             load_c<T, C>(v.r + pt * C, rv);
 #pragma unroll
             for (int e = 0; e < MS; ++e) Dv[e] = D[pt * MS + e];
             const T *Ap = A + pt * MG_SLOTS * CC;
             for (int it = 1; it < sweeps; ++it) {
-                const T *xs = bufs[cur];
-                T *xd = bufs[cur ^ 1];
+                const T *xs = cur ? b1 : b0;
+                T *xd = cur ? b0 : b1;
                 if (have) {
                     T acc[C];
 #pragma unroll
@@ -761,12 +765,9 @@ __global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_kernel(const Geo *geos, 
                         load_c<T, C>(xs + (long long)qi[s2] * C, vq);
                         const T *blk = Ap + s2 * CC;
 #pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            T t = T(0);
+                        for (int c = 0; c < C; ++c)
 #pragma unroll
-                            for (int d = 0; d < C; ++d) t += blk[c * C + d] * vq[d];
-                            acc[c] -= qm[s2] * t;
-                        }
+                            for (int d = 0; d < C; ++d) acc[c] -= blk[c * C + d] * vq[d];
                     }
                     T d[C];
                     minv_apply<T, C>(Dv, acc, d);
@@ -778,14 +779,12 @@ __global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_kernel(const Geo *geos, 
             }
         } else {
             for (int it = 1; it < sweeps; ++it) {
-                const T *xs = bufs[cur];
-                T *xd = bufs[cur ^ 1];
+                const T *xs = cur ? b1 : b0;
+                T *xd = cur ? b0 : b1;
                 for (long long pt = tid; pt < np; pt += nt) {
-                    int i, j, k;
-                    lev_xyz(V, pt, i, j, k);
                     T acc[C];
                     load_c<T, C>(v.r + pt * C, acc);
-                    apply_stencil<T, C>(V, A + pt * MG_SLOTS * CC, xs, i, j, k, pt, acc);
+                    apply_stencil<T, C>(row16(G.mg_nbr, V, pt), A + pt * MG_SLOTS * CC, xs, acc);
                     T d[C];
                     minv_apply<T, C>(D + pt * MS, acc, d);
 #pragma unroll
@@ -805,21 +804,280 @@ __global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_kernel(const Geo *geos, 
         const Lev V = level_of(G, l), Cv = level_of(G, l + 1);
         const long long np = (long long)V.lw * V.lw * V.lw;
         const LV<T> v = lvec(l), vc = lvec(l + 1);
-        for (long long pt = tid; pt < np; pt += nt) correct_pt<T, C>(V, Cv, v, vc.x, pt);
+        for (long long pt = tid; pt < np; pt += nt) correct_pt<T, C>(G, V, v, vc.x, pt);
         __syncthreads();
         const T *A = Q.A + (P.moff + V.off) * MG_SLOTS * CC;
         const T *D = Q.Dinv + (P.moff + V.off) * MS;
-        for (long long pt = tid; pt < np; pt += nt) post_pt<T, C>(V, A, D, v, pt);
+        for (long long pt = tid; pt < np; pt += nt) post_pt<T, C>(G, V, A, D, v, pt);
         __syncthreads();
     }
     // level-2 output to global memory for the level-1 correction
-    if (lds) {
+    if (lds && lc >= 2) {
         const Lev V2 = level_of(G, 2);
         const LV<T> g2 = level_vecs<T, C, R>(G, P, w, V2, Q.r, Q.xp, Q.res, Q.x);
         const long long n2 = (long long)V2.lw * V2.lw * V2.lw * C;
         const T *x2 = lvec(2).x;
         for (long long e = tid; e < n2; e += nt) g2.x[e] = x2[e];
     }
+}
+
+// Levels 2 .. coarsest when they are small (coarsest level 1, 2 or 3, at most
+// MG_FUSED_BS points each; a level-1 coarsest gets only its sweeps): the same
+// arithmetic as mg_fused_kernel with the global loads issued up front -- thread t owns level-2 point t and keeps its
+// stencil row, l1 inverse and neighbour indices in registers; level-3 stencils,
+// inverses and all level >= 2 vectors sit in LDS -- so the kernel waits on
+// memory about once instead of once per stage.
+template <int C, int R>
+__global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_small_kernel(const Geo *geos, const Prob *probs,
+                                                                     VPtr<float, C, R> Q, int sweeps,
+                                                                     const int *prob_active) {
+    using T = float;
+    constexpr int CC = C * C;
+    constexpr int MS = (C == 3) ? 6 : 1;
+    extern __shared__ unsigned char mg_smem[];
+    const int prob = blockIdx.y, w = blockIdx.x;
+    if (prob_active != nullptr && prob_active[prob] == 0) return;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    if (G.mg_nlev < 2) return;
+    const int lc = G.mg_nlev - 1;   // 1, 2 or 3 (checked on the host)
+    const int tid = threadIdx.x;
+    const Lev V1 = level_of(G, 1);
+    const LV<T> g1 = level_vecs<T, C, R>(G, P, w, V1, Q.r, Q.xp, Q.res, Q.x);
+    if (lc == 1) {
+        // the n/2 grid is the coarsest: sweeps from xp1 with thread t owning point t,
+        // its stencil row and inverse in registers, the iterates ping-ponging in LDS
+        const int np1 = V1.lw * V1.lw * V1.lw;
+        const bool own = tid < np1;
+        const int p1 = own ? tid : 0;
+        T *const b0 = (T *)mg_smem, *const b1 = b0 + np1 * C;
+        T A1[MG_SLOTS * CC], D1[MS], r1[C], x1[C];
+        const T *A1g = Q.A + (P.moff + V1.off + p1) * MG_SLOTS * CC;
+#pragma unroll
+        for (int e = 0; e < MG_SLOTS * CC; ++e) A1[e] = A1g[e];
+#pragma unroll
+        for (int e = 0; e < MS; ++e) D1[e] = Q.Dinv[(P.moff + V1.off + p1) * MS + e];
+        int q1[MG_SLOTS];
+        const int *nb1 = row16(G.mg_nbr, V1, p1);
+#pragma unroll
+        for (int s = 0; s < MG_SLOTS; ++s) q1[s] = nb1[s];
+        load_c<T, C>(g1.r + p1 * C, r1);
+        load_c<T, C>(g1.xp + p1 * C, x1);
+        if (own) store_c<T, C>(b0 + p1 * C, x1);
+        __syncthreads();
+        int cur = 0;
+#pragma unroll 1
+        for (int it = 1; it < sweeps; ++it) {
+            if (own) {
+                const T *xs = cur ? b1 : b0;
+                T acc[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] = r1[c];
+#pragma unroll
+                for (int s = 0; s < MG_SLOTS; ++s) {
+                    T v[C];
+                    load_c<T, C>(xs + q1[s] * C, v);
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+#pragma unroll
+                        for (int d = 0; d < C; ++d) acc[c] -= A1[s * CC + c * C + d] * v[d];
+                }
+                T d[C];
+                minv_apply<T, C>(D1, acc, d);
+#pragma unroll
+                for (int c = 0; c < C; ++c) x1[c] += d[c];
+                store_c<T, C>((cur ? b0 : b1) + p1 * C, x1);
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        if (own) store_c<T, C>(g1.x + p1 * C, x1);
+        return;
+    }
+    const Lev V2 = level_of(G, 2);
+    const int np2 = V2.lw * V2.lw * V2.lw;
+    const LV<T> g2 = level_vecs<T, C, R>(G, P, w, V2, Q.r, Q.xp, Q.res, Q.x);
+    // LDS: level 2 xp, res|xc, x (x also the ping-pong partner on a level-2 coarsest);
+    // level 3 x, tmp, stencils, inverses (one spare point per vector, kept at zero).
+    Lev V3 = V2;
+    int np3 = 0;
+    if (lc == 3) {
+        V3 = level_of(G, 3);
+        np3 = V3.lw * V3.lw * V3.lw;
+    }
+    const int v2 = (np2 + 1) * C, v3 = (np3 + 1) * C;
+    T *s2xp = (T *)mg_smem, *s2res = s2xp + v2, *s2x = s2res + v2;
+    T *s3x = s2x + v2, *s3t = s3x + v3;
+    T *s3A = s3t + v3, *s3D = s3A + np3 * MG_SLOTS * CC;
+    if (tid < C) {
+        s2xp[np2 * C + tid] = T(0);
+        s2res[np2 * C + tid] = T(0);
+        s2x[np2 * C + tid] = T(0);
+        s3x[np3 * C + tid] = T(0);
+        s3t[np3 * C + tid] = T(0);
+    }
+
+    // ---- all global loads of the kernel
+    const bool own2 = tid < np2;
+    const int p2 = own2 ? tid : 0;
+    T A2[MG_SLOTS * CC], D2[MS];
+    const T *A2g = Q.A + (P.moff + V2.off + p2) * MG_SLOTS * CC;
+#pragma unroll
+    for (int e = 0; e < MG_SLOTS * CC; ++e) A2[e] = A2g[e];
+#pragma unroll
+    for (int e = 0; e < MS; ++e) D2[e] = Q.Dinv[(P.moff + V2.off + p2) * MS + e];
+    T ch[MG_SLOTS][C];   // level-1 residuals at the children of the owned level-2 point
+    T wch[MG_SLOTS];
+    const int *chrow = row16(G.mg_child, V2, p2);
+#pragma unroll
+    for (int m = 0; m < MG_SLOTS; ++m) {
+        const int f = chrow[m];
+        wch[m] = f < 0 ? T(0) : (m == 0 ? T(1) : T(0.5));
+        load_c<T, C>(g1.res + (long long)(f < 0 ? 0 : f) * C, ch[m]);
+    }
+    if (lc == 3) {
+        const T *A3g = Q.A + (P.moff + V3.off) * MG_SLOTS * CC;
+        for (int e = tid; e < np3 * MG_SLOTS * CC; e += blockDim.x) s3A[e] = A3g[e];
+        const T *D3g = Q.Dinv + (P.moff + V3.off) * MS;
+        for (int e = tid; e < np3 * MS; e += blockDim.x) s3D[e] = D3g[e];
+    }
+    int q2[MG_SLOTS];
+    const int *nb2 = row16(G.mg_nbr, V2, p2);
+#pragma unroll
+    for (int s = 0; s < MG_SLOTS; ++s) q2[s] = nb2[s];
+
+    // ---- restrict 1 -> 2, xp2 = D2^-1 r2
+    T r2[C], xp2[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T a = T(0);
+#pragma unroll
+        for (int m = 0; m < MG_SLOTS; ++m) a += wch[m] * ch[m][c];
+        r2[c] = a;
+    }
+    minv_apply<T, C>(D2, r2, xp2);
+    if (own2) store_c<T, C>(s2xp + p2 * C, xp2);
+    __syncthreads();
+    // l1 block-Jacobi step on level 2 with the stencil row in registers:
+    // out = x_self + D2^-1 (rhs - A2 x)
+    auto level2_step = [&](const T *xs, const T rhs[C], const T xself[C], T out[C]) {
+        T acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = rhs[c];
+#pragma unroll
+        for (int s = 0; s < MG_SLOTS; ++s) {
+            T v[C];
+            load_c<T, C>(xs + q2[s] * C, v);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int d = 0; d < C; ++d) acc[c] -= A2[s * CC + c * C + d] * v[d];
+        }
+        T d[C];
+        minv_apply<T, C>(D2, acc, d);
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[c] = xself[c] + d[c];
+    };
+    T x2[C];
+    if (lc == 2) {
+        // coarsest is level 2: sweeps from xp2, ping-pong between s2x and s2res
+        T *const b0 = s2x, *const b1 = s2res;
+        if (own2) store_c<T, C>(s2x + p2 * C, xp2);
+        __syncthreads();
+        int cur = 0;
+#pragma unroll 1
+        for (int it = 1; it < sweeps; ++it) {
+            if (own2) {
+                T xs_self[C], o[C];
+                const T *xs = cur ? b1 : b0;
+                load_c<T, C>(xs + p2 * C, xs_self);
+                level2_step(xs, r2, xs_self, o);
+                store_c<T, C>((cur ? b0 : b1) + p2 * C, o);
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        load_c<T, C>((cur ? b1 : b0) + p2 * C, x2);
+    } else {
+        // residual on level 2: res2 = r2 - A2 xp2
+        T res2[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) res2[c] = r2[c];
+#pragma unroll
+        for (int s = 0; s < MG_SLOTS; ++s) {
+            T v[C];
+            load_c<T, C>(s2xp + q2[s] * C, v);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int d = 0; d < C; ++d) res2[c] -= A2[s * CC + c * C + d] * v[d];
+        }
+        if (own2) store_c<T, C>(s2res + p2 * C, res2);
+        __syncthreads();
+        // restrict 2 -> 3 and the coarsest sweeps (threads < np3)
+        const bool own3 = tid < np3;
+        const int p3 = own3 ? tid : 0;
+        int q3[MG_SLOTS];
+        const int *nb3 = row16(G.mg_nbr, V3, p3);
+#pragma unroll
+        for (int s = 0; s < MG_SLOTS; ++s) q3[s] = nb3[s];
+        T r3[C], D3[MS];
+#pragma unroll
+        for (int c = 0; c < C; ++c) r3[c] = T(0);
+        const int *ch3 = row16(G.mg_child, V3, p3);
+#pragma unroll
+        for (int m = 0; m < MG_SLOTS; ++m) {
+            const int f = ch3[m];
+            const T wgt = f < 0 ? T(0) : (m == 0 ? T(1) : T(0.5));
+            const int fs = f < 0 ? 0 : f;
+#pragma unroll
+            for (int c = 0; c < C; ++c) r3[c] += wgt * s2res[fs * C + c];
+        }
+#pragma unroll
+        for (int e = 0; e < MS; ++e) D3[e] = s3D[p3 * MS + e];
+        T xp3[C];
+        minv_apply<T, C>(D3, r3, xp3);
+        if (own3) store_c<T, C>(s3x + p3 * C, xp3);
+        __syncthreads();
+        T *const b0 = s3x, *const b1 = s3t;
+        int cur = 0;
+        const T *A3 = s3A + p3 * MG_SLOTS * CC;
+#pragma unroll 1
+        for (int it = 1; it < sweeps; ++it) {
+            if (own3) {
+                const T *xs = cur ? b1 : b0;
+                T acc[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[c] = r3[c];
+#pragma unroll
+                for (int s = 0; s < MG_SLOTS; ++s) {
+                    T v[C];
+                    load_c<T, C>(xs + q3[s] * C, v);
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+#pragma unroll
+                        for (int d = 0; d < C; ++d) acc[c] -= A3[s * CC + c * C + d] * v[d];
+                }
+                T d[C], xo[C];
+                minv_apply<T, C>(D3, acc, d);
+                load_c<T, C>(xs + p3 * C, xo);
+#pragma unroll
+                for (int c = 0; c < C; ++c) (cur ? b0 : b1)[p3 * C + c] = xo[c] + d[c];
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        const T *e3 = cur ? b1 : b0;
+        // correct and post-smooth level 2
+        T xc2[C], pe[C];
+        prolong<T, C>(G, V2, e3, p2, pe);
+#pragma unroll
+        for (int c = 0; c < C; ++c) xc2[c] = xp2[c] + pe[c];
+        if (own2) store_c<T, C>(s2res + p2 * C, xc2);
+        __syncthreads();
+        level2_step(s2res, r2, xc2, x2);
+    }
+    if (own2) store_c<T, C>(g2.x + p2 * C, x2);
 }
 
 // Fine vector of constraint columns for the Gram setup: load case w carries the
@@ -849,7 +1107,7 @@ __global__ void mg_store_w_kernel(const Geo *geos, const Prob *probs, int first,
     const int prob = blockIdx.y;
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
-    if (G.mg_nlev < 3 || G.nrow == 0) return;
+    if (G.mg_nlev < 2 || G.nrow == 0) return;
     const int nr = G.nrow;
     const Lev V = level_of(G, 1);
     const long long np1 = (long long)V.lw * V.lw * V.lw;
@@ -877,7 +1135,7 @@ __global__ void mg_gram_partial_kernel(const Geo *geos, const Prob *probs, const
     double *out = partial + ((long long)prob * gridDim.x + blockIdx.x) * 144;
     const int nr = G.nrow, S = C * nr, rf = row_first(G.nrow);
     const int u = threadIdx.x;
-    if (G.mg_nlev < 3 || nr == 0) {
+    if (G.mg_nlev < 2 || nr == 0) {
         if (u < 144) out[u] = 0.0;
         return;
     }
@@ -909,7 +1167,7 @@ __global__ __launch_bounds__(256) void mg_gram_finish_kernel(const Geo *geos, co
     for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
         const int I = t / S, J = t % S;
         double e = 0.0;
-        if (G.mg_nlev >= 3)
+        if (G.mg_nlev >= 2)
             for (int b = 0; b < nwg; ++b) e += partial[((long long)prob * nwg + b) * 144 + t];
         A[I][J] = gmat[(long long)prob * SMAX * SMAX + t] + e;
         A[I][S + J] = (I == J) ? 1.0 : 0.0;
@@ -969,9 +1227,18 @@ hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *accbuf, const i
     const dim3 g1(M.nwg[1], L.nprob);
     mg_restrict01_kernel<T, C, R><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, prob_active);
     mg_resid1_kernel<T, C, R><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, prob_active);
-    const size_t shm = (size_t)M.lds_elems * sizeof(T);
-    mg_fused_kernel<T, C, R><<<dim3(R, L.nprob), MG_FUSED_BS, shm, s>>>(L.geos, L.probs, Q, M.sweeps, M.lds_vec,
-                                                                       M.lds_sten, prob_active);
+    if constexpr (std::is_same<T, float>::value) {
+        if (M.small_elems > 0) {
+            mg_fused_small_kernel<C, R><<<dim3(R, L.nprob), MG_FUSED_BS, (size_t)M.small_elems * sizeof(float), s>>>(
+                L.geos, L.probs, Q, M.sweeps, prob_active);
+        } else {
+            mg_fused_kernel<T, C, R><<<dim3(R, L.nprob), MG_FUSED_BS, (size_t)M.lds_elems * sizeof(T), s>>>(
+                L.geos, L.probs, Q, M.sweeps, M.lds_vec, M.lds_sten, prob_active);
+        }
+    } else {
+        mg_fused_kernel<T, C, R><<<dim3(R, L.nprob), MG_FUSED_BS, (size_t)M.lds_elems * sizeof(T), s>>>(
+            L.geos, L.probs, Q, M.sweeps, M.lds_vec, M.lds_sten, prob_active);
+    }
     mg_correct1_kernel<T, C, R><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, prob_active);
     CHOM_MG_NR_DISPATCH(L.nr, (mg_post1_kernel<T, C, R, NR><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, accbuf,
                                                                                   prob_active)));

@@ -3,9 +3,10 @@
 The preconditioner changes the CG iteration, not the discrete solution: with
 both preconditioners driven to rtol = 1e-12 (energy-norm error of the
 fluctuation <~ 2 n rtol, see the parity tests) the homogenised matrices agree
-to ~1e-10; the bound used is 1e-9.  The coarse grid exists for n divisible by 4
-and n >= 12; n = 8 and n = 10 exercise the block-Jacobi-only path inside a
-two-level launch.
+to ~1e-10; the bound used is 1e-9.  The coarse grid exists for even n >= 6
+(n = 6, 8, 10: the n/2 grid is the coarsest level; n divisible by 4 and
+n >= 12: deeper hierarchies); odd n (9) exercises the block-Jacobi-only path
+inside a two-level launch.
 """
 import numpy as np
 import pytest
@@ -33,7 +34,7 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("bc", ["dirichlet", "periodic", "neumann"])
-@pytest.mark.parametrize("n", [8, 12])
+@pytest.mark.parametrize("n", [8, 9, 12])
 def test_two_level_matches_block_jacobi(n, bc):
     require_gpu()
     banner(f"two-level vs block Jacobi, n={n} {bc}, FP64")
@@ -43,7 +44,7 @@ def test_two_level_matches_block_jacobi(n, bc):
     print(f"[mg] n={n} {bc}: max rel diff {e:.2e}; iters jacobi {max(ra[0]['iters'])} two-level {max(rb[0]['iters'])}")
     assert all(r["status"] == 0 for r in ra + rb)
     assert e <= AGREE
-    if n == 8:   # no coarse grid: the same iteration (up to the operator's summation order)
+    if n == 9:   # no coarse grid: the same iteration (up to the operator's summation order)
         assert max(abs(x - y) for x, y in zip(ra[0]["iters"], rb[0]["iters"])) <= 2
 
 
@@ -72,11 +73,12 @@ def test_two_level_higher_order(order):
 
 
 def test_two_level_mixed_batch_fp32_refined():
-    """Sizes with and without a coarse grid and all BCs in one launch."""
+    """Sizes with no coarse grid, a level-1 coarsest and deeper hierarchies, all BCs, in one launch."""
     require_gpu()
     from paper_1610_03484_amd import RVE, Batch, generate_plain_weave
-    banner("two-level mixed batch (n = 8, 10, 12, 16; D/P/N), FP32 refined vs FP64 block Jacobi")
-    items = [(8, "periodic"), (12, "neumann"), (16, "dirichlet"), (10, "neumann"), (12, "periodic"), (16, "periodic")]
+    banner("two-level mixed batch (n = 6, 8, 9, 10, 12, 16; D/P/N), FP32 refined vs FP64 block Jacobi")
+    items = [(8, "periodic"), (12, "neumann"), (16, "dirichlet"), (10, "neumann"), (12, "periodic"), (16, "periodic"),
+             (9, "dirichlet"), (6, "periodic")]
     params = ci.draw_params(7, len(items))
     meshes = {n: generate_plain_weave(n) for n in {n for n, _ in items}}
     rves = [RVE(*meshes[n], ci.BASE_MATERIALS, bc=bc, precision="fp32_refined", precond="two_level", rtol=1e-10,
