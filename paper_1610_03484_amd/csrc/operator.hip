@@ -11,7 +11,8 @@
 // markedly faster than FP32 ones on gfx950), and stores the whole box,
 // contiguous, to its slot of the tile-box output: no global atomics, no zeroing
 // pass; consumers sum the copies of points on shared tile faces.  The element
-// energies x_e . K_e x_e are summed on the fly in FP64 (p.Kp for CG).
+// energies x_e . K_e x_e (p.Kp for CG) are formed per tet in the vector
+// precision and summed in FP64.
 //
 // Problems of different RVEs (sizes, BCs) share a launch: grid.x covers the
 // largest problem's tiles x groups; workgroups past a problem's tiles only
@@ -35,14 +36,21 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
                                                           double *acc_pq, const int *prob_active) {
     constexpr int NG = R / RG;
     constexpr int RCg = RG * C;
-    constexpr int PS = RCg + 1;
+    // LDS layout of the box: point (bx, by, bz) at bx + BXP (by + BY bz), PS
+    // values per point.  Neighbouring tets of a wave sit two lattice points apart,
+    // so an even point stride maps them onto few banks; an odd PS and a row pitch
+    // of 10 (12 for narrow FP32 boxes) keep the per-node LDS reads and FP64
+    // atomics of a wave at about two passes per 32 lanes.
+    constexpr int PS = RCg | 1;
+    constexpr int BXP = (sizeof(T) == 4 && RCg <= 3) ? 12 : 10;
+    constexpr int LPTS = BXP * BY * BZ;
     constexpr int NBOX = BOXPTS * RCg;
     constexpr int NST = (NBOX + TILE_TETS - 1) / TILE_TETS;
     constexpr int NCELL = TX * TY * TZ;
     constexpr int NW = TILE_TETS / 64;
     using V4 = typename std::conditional<std::is_same<T, double>::value, double4, float4>::type;
-    __shared__ T xs[BOXPTS * PS];
-    __shared__ double ys[BOXPTS * PS];
+    __shared__ T xs[LPTS * PS];
+    __shared__ double ys[LPTS * PS];
     __shared__ T sg[6][10];
     __shared__ double red[RG][NW];
     const int prob = blockIdx.y;
@@ -58,21 +66,31 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     const int hx = min(X0 + 2 * TX, m2), hy = min(Y0 + 2 * TY, m2), hz = min(Z0 + 2 * TZ, m2);
     const T *xp = RHS ? nullptr : x + P.voff;   // vectors are [load case][point][component]
 
-    // ---- stage the DOF box (this group's values), element data, geometry
+    // ---- stage the DOF box (this group's values), element data, geometry.
+    // Every load is issued unconditionally (out-of-box elements read element 0
+    // and are replaced by zero) with the lattice fields held in registers, so
+    // all NST loads are in flight together with no branch between them.
     T tmp[NST];
+    if constexpr (!RHS) {
+        const int Lw = G.Lw, Lm = (G.bc == 1) ? G.L : -1;   // periodic: index L wraps to 0
+        const long long col0 = (long long)grp * RG * G.npts;
+        const long long np = G.npts;
 #pragma unroll
-    for (int k = 0; k < NST; ++k) {
-        const int i = tt + TILE_TETS * k;
-        T val = T(0);
-        if (!RHS && i < NBOX) {   // i = (rr * BOXPTS + pt) * C + c: consecutive lanes read contiguous memory
+        for (int k = 0; k < NST; ++k) {
+            const int i = tt + TILE_TETS * k;   // i = (rr * BOXPTS + pt) * C + c: lanes read contiguous memory
             const int rr = i / (BOXPTS * C), rem = i - rr * (BOXPTS * C);
             const int pt = rem / C, c = rem - (rem / C) * C;
             const int bx = pt % BX, by = (pt / BX) % BY, bz = pt / (BX * BY);
-            const int X = X0 + bx, Y = Y0 + by, Z = Z0 + bz;
-            if (X <= hx && Y <= hy && Z <= hz)
-                val = xp[((long long)(grp * RG + rr) * G.npts + lat_index(G, X, Y, Z)) * C + c];
+            int X = X0 + bx, Y = Y0 + by, Z = Z0 + bz;
+            const bool in = i < NBOX && X <= hx && Y <= hy && Z <= hz;
+            X = X == Lm ? 0 : X;
+            Y = Y == Lm ? 0 : Y;
+            Z = Z == Lm ? 0 : Z;
+            const int lin = X + Lw * (Y + Lw * Z);
+            const long long idx = in ? (col0 + rr * np + lin) * C + c : 0;
+            const T v = xp[idx];
+            tmp[k] = in ? v : T(0);
         }
-        tmp[k] = val;
     }
     const int type = tt / NCELL, lc = tt - (tt / NCELL) * NCELL;
     const int lcx = lc % TX, lcy = (lc / TX) % TY, lcz = lc / (TX * TY);
@@ -83,16 +101,18 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     if (live) {
         if constexpr (std::is_same<T, double>::value) ev = G.elem64[tet]; else ev = G.elem32[tet];
     }
+    if constexpr (!RHS) {
 #pragma unroll
-    for (int k = 0; k < NST; ++k) {
-        const int i = tt + TILE_TETS * k;
-        if (i < NBOX) {
-            const int rr = i / (BOXPTS * C), rem = i - rr * (BOXPTS * C);
-            const int pt = rem / C, c = rem - (rem / C) * C;
-            xs[pt * PS + rr * C + c] = tmp[k];
+        for (int k = 0; k < NST; ++k) {
+            const int i = tt + TILE_TETS * k;
+            if (i < NBOX) {
+                const int rr = i / (BOXPTS * C), rem = i - rr * (BOXPTS * C);
+                const int pt = rem / C, c = rem - (rem / C) * C;
+                xs[(pt % BX + BXP * (pt / BX)) * PS + rr * C + c] = tmp[k];
+            }
         }
     }
-    for (int i = tt; i < BOXPTS * PS; i += TILE_TETS) ys[i] = 0.0;
+    for (int i = tt; i < LPTS * PS; i += TILE_TETS) ys[i] = 0.0;
     if (tt < 60 && G.uniform) {
         if constexpr (std::is_same<T, double>::value) sg[tt / 10][tt % 10] = G.tg64[tt / 10][tt % 10];
         else sg[tt / 10][tt % 10] = G.tg32[tt / 10][tt % 10];
@@ -126,7 +146,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
         int lp[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k)
-            lp[k] = ((2 * lcx + off[k][0]) + BX * ((2 * lcy + off[k][1]) + BY * (2 * lcz + off[k][2]))) * PS;
+            lp[k] = ((2 * lcx + off[k][0]) + BXP * ((2 * lcy + off[k][1]) + BY * (2 * lcz + off[k][2]))) * PS;
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
             T yv[10][C];
@@ -174,10 +194,13 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
 #pragma unroll
                     for (int c = 0; c < C; ++c) u[k][c] = xs[lp[k] + r * C + c];
                 p2_apply<T, C>(g, vol, a, mloc, u, yv);
+                // element energy in the vector precision (one FP64 conversion per tet)
+                T et = T(0);
 #pragma unroll
                 for (int k = 0; k < 10; ++k)
 #pragma unroll
-                    for (int c = 0; c < C; ++c) en += (double)u[k][c] * (double)yv[k][c];
+                    for (int c = 0; c < C; ++c) et += u[k][c] * yv[k][c];
+                en = (double)et;
             }
 #pragma unroll
             for (int k = 0; k < 10; ++k)
@@ -192,7 +215,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     T *qt = y + P.qoff + ((long long)tile * NG + grp) * NBOX;
     for (int i = tt; i < NBOX; i += TILE_TETS) {
         const int pt = i / RCg, v = i - pt * RCg;
-        qt[i] = (T)ys[pt * PS + v];
+        qt[i] = (T)ys[(pt % BX + BXP * (pt / BX)) * PS + v];
     }
 
     // ---- element energies p.Kp into the striped accumulators [prob][load case][ACC_STRIPES]
