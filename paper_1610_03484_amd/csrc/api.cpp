@@ -456,12 +456,12 @@ static hipError_t cg_iteration(ClassWS<C, R> &W, T *x, T *r, T *p, T *q, const v
     const bool mg = L.mg.on != 0;
     hipError_t e;
     if (mg && (e = launch_mg_fcorr<T, C, R>(L, W.ycoef.p, W.active.p, s)) != hipSuccess) return e;
-    if ((e = launch_cg_dir<T, C, R>(L, r, p, minv, W.ycoef.p, W.cols.p, W.active.p, s, mg ? L.mg.res : nullptr,
+    if ((e = launch_cg_dir<T, C, R>(L, x, r, p, minv, W.ycoef.p, W.cols.p, W.active.p, s, mg ? L.mg.res : nullptr,
                                     nullptr)) != hipSuccess)
         return e;
     if ((e = launch_operator<T, C, R>(L, L.nprob, L.rg, p, q, W.accpq.p, W.active.p, s)) != hipSuccess) return e;
     if ((e = launch_finish_alpha<C, R>(L, W.accpq.p, W.cols.p, s)) != hipSuccess) return e;
-    if ((e = launch_cg_update<T, C, R>(L, x, r, p, q, minv, W.cols.p, W.acc.p, W.active.p, s)) != hipSuccess) return e;
+    if ((e = launch_cg_update<T, C, R>(L, r, q, minv, W.cols.p, W.acc.p, W.active.p, s)) != hipSuccess) return e;
     if (mg && (e = launch_mg_vcycle<T, C, R>(L, r, W.acc.p, W.active.p, s)) != hipSuccess) return e;
     return launch_finish_beta<C, R>(L, W.acc.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 0, rtol2, use_init, nullptr, s);
 }
@@ -516,6 +516,8 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x
                 CHOM_HIP((cg_iteration<T, C, R>(W, x, r, p, q, minv, ginv, rtol2, use_init, s)));
         }
     }
+    // the last step's x += alpha p (every earlier one was applied by a direction kernel)
+    CHOM_HIP((launch_cg_flush_x<T, C, R>(L, x, p, W.cols.p, s)));
     return CHOM_OK;
 }
 
@@ -642,8 +644,8 @@ static int time_vec(chom_batch *B, ClassWS<C, R> &W, T *x, T *r, T *p, const T *
     CHOM_HIP(hipEventCreate(&e1));
     CHOM_HIP(hipEventRecord(e0, s));
     for (int i = 0; i < reps; ++i) {
-        CHOM_HIP((launch_cg_dir<T, C, R>(L, r, p, minv, W.ycoef.p, W.cols.p, W.active.p, s)));
-        CHOM_HIP((launch_cg_update<T, C, R>(L, x, r, p, q, minv, W.cols.p, W.acc.p, W.active.p, s)));
+        CHOM_HIP((launch_cg_dir<T, C, R>(L, x, r, p, minv, W.ycoef.p, W.cols.p, W.active.p, s)));
+        CHOM_HIP((launch_cg_update<T, C, R>(L, r, q, minv, W.cols.p, W.acc.p, W.active.p, s)));
     }
     CHOM_HIP(hipEventRecord(e1, s));
     CHOM_HIP(hipEventSynchronize(e1));

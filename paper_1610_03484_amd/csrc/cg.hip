@@ -97,23 +97,29 @@ __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const 
     wave_accum<C>(acc, REC, accbuf, prob, R, w);
 }
 
-// z = z0 - M^-1 C^T y ; r = r - C^T y ; p = z + beta p.  With the two-level
+// x += alpha p (the step length of the previous iteration, applied here while
+// p is read anyway; cg_flush_x_kernel applies the last one) ; z = z0 - M^-1 C^T y ;
+// r = r - C^T y ; p = z + beta p.  With the two-level
 // preconditioner (mg.on) the vertex points also take the coarse correction
 // z += Q f, f = e1 - W y on the n/2 grid (e1 = V Q^T r, W = V Q^T C^T, formed by
 // mg_fcorr_kernel), Q = P_0 P_1 (P_0 injects vertex values, P_1 interpolates
 // from the n/2 grid).
 template <typename T, int C, int R, int NR>
-__global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const Prob *probs, T *r, T *p,
+__global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const Prob *probs, T *x, T *r, T *p,
                                                         const T *minv, const double *ycoef,
                                                         const ColState *cols, const int *prob_active,
                                                         MgDir<T> mg) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int S = C * NR;
     const int prob = blockIdx.y;
-    if (prob_active[prob] == 0) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // a finished problem still takes the pending x update of its last step
+    // (the finishing kernel zeroes alpha of finished columns afterwards)
+    const bool active = prob_active[prob] != 0;
+    const double alpha = cols[prob * R + w].alpha;
+    if (!active && alpha == 0.0) return;   // per wave: the kernel has no block barrier
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double beta = cols[prob * R + w].beta;
     double yv[S > 0 ? S : 1];
 #pragma unroll
@@ -125,6 +131,17 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
         const long long pt = blk * 64 + lane;
         if (pt >= G.npts) continue;
         const long long o = P.voff + (w * G.npts + pt) * C;
+        T pv[C];
+        if (alpha != 0.0 || beta != 0.0) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) pv[c] = p[o + c];
+        }
+        if (alpha != 0.0) {
+            const T al = (T)alpha;
+#pragma unroll
+            for (int c = 0; c < C; ++c) x[o + c] += al * pv[c];
+        }
+        if (!active) continue;
         T rv[C], zv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) rv[c] = r[o + c];
@@ -172,17 +189,17 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
         } else {
             const T bt = (T)beta;
 #pragma unroll
-            for (int c = 0; c < C; ++c) p[o + c] = zv[c] + bt * p[o + c];
+            for (int c = 0; c < C; ++c) p[o + c] = zv[c] + bt * pv[c];
         }
     }
 }
 
-// x += alpha p ; r -= alpha q (q gathered from the operator's tile boxes) ;
-// partial sums of r and z0 = M^-1 r (z0 itself is formed again by the
-// direction kernel, which reads r anyway).
+// r -= alpha q (q gathered from the operator's tile boxes) ; partial sums of r
+// and z0 = M^-1 r (z0 itself is formed again by the direction kernel, which
+// reads r anyway; x += alpha p is deferred to the next direction kernel).
 template <typename T, int C, int R, int NR>
-__global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, const Prob *probs, int rg, T *x, T *r,
-                                                           const T *p, const T *q, const T *minv,
+__global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, const Prob *probs, int rg, T *r,
+                                                           const T *q, const T *minv,
                                                            const ColState *cols, double *accbuf,
                                                            const int *prob_active) {
     constexpr int MS = (C == 3) ? 6 : 1;
@@ -220,7 +237,6 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
         T rv[C], zv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            x[o + c] += al * p[o + c];
             rv[c] = r[o + c] - al * (T)qv[c];
             r[o + c] = rv[c];
         }
@@ -234,6 +250,28 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
         }
     }
     wave_accum<C>(acc, REC, accbuf, prob, R, w);
+}
+
+// x += alpha p with the pending step length of each column (after the last CG
+// step of a solve).
+template <typename T, int C, int R>
+__global__ __launch_bounds__(64 * R) void cg_flush_x_kernel(const Geo *geos, const Prob *probs, T *x, const T *p,
+                                                            const ColState *cols) {
+    const int prob = blockIdx.y;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double alpha = cols[prob * R + w].alpha;
+    if (alpha == 0.0) return;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    const T al = (T)alpha;
+    const long long nblk = (G.npts + 63) / 64;
+    for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const long long pt = blk * 64 + lane;
+        if (pt >= G.npts) continue;
+        const long long o = P.voff + (w * G.npts + pt) * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[o + c] += al * p[o + c];
+    }
 }
 
 // Outer (refinement) residual projected as a vector: r64 <- r64 - C^T y with
@@ -397,6 +435,7 @@ __global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const
         if (first) {
             cs.rz_init = rz;
             cs.beta = 0.0;
+            cs.alpha = 0.0;   // no pending x update (see cg_dir_kernel)
             cs.done = (mask != nullptr && mask[prob * R + lane].done) ? 1 : 0;
         } else {
             cs.beta = (cs.done || cs.rz == 0.0) ? 0.0 : rz / cs.rz;
@@ -438,22 +477,28 @@ hipError_t launch_cg_init(const Launch &L, const T *b, T *x, T *r, const void *m
 }
 
 template <typename T, int C, int R>
-hipError_t launch_cg_dir(const Launch &L, T *r, T *p, const void *minv, const double *ycoef,
+hipError_t launch_cg_dir(const Launch &L, T *x, T *r, T *p, const void *minv, const double *ycoef,
                          const ColState *cols, const int *prob_active, hipStream_t s, const void *mg_x0,
                          const void *mg_W) {
     dim3 grid(L.nwg, L.nprob);
     const T *M = (const T *)minv;
     MgDir<T> mg{(const T *)mg_x0, (const T *)mg_W, mg_x0 != nullptr ? 1 : 0};
-    CHOM_NR_DISPATCH(L.nr, (cg_dir_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, r, p, M, ycoef, cols, prob_active, mg)));
+    CHOM_NR_DISPATCH(L.nr, (cg_dir_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, x, r, p, M, ycoef, cols, prob_active, mg)));
     return hipGetLastError();
 }
 
 template <typename T, int C, int R>
-hipError_t launch_cg_update(const Launch &L, T *x, T *r, const T *p, const T *q, const void *minv,
-                            const ColState *cols, double *accbuf, const int *prob_active, hipStream_t s) {
+hipError_t launch_cg_update(const Launch &L, T *r, const T *q, const void *minv, const ColState *cols,
+                            double *accbuf, const int *prob_active, hipStream_t s) {
     dim3 grid(L.nwg, L.nprob);
     const T *M = (const T *)minv;
-    CHOM_NR_DISPATCH(L.nr, (cg_update_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, L.rg, x, r, p, q, M, cols, accbuf, prob_active)));
+    CHOM_NR_DISPATCH(L.nr, (cg_update_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, L.rg, r, q, M, cols, accbuf, prob_active)));
+    return hipGetLastError();
+}
+
+template <typename T, int C, int R>
+hipError_t launch_cg_flush_x(const Launch &L, T *x, const T *p, const ColState *cols, hipStream_t s) {
+    cg_flush_x_kernel<T, C, R><<<dim3(L.nwg, L.nprob), 64 * R, 0, s>>>(L.geos, L.probs, x, p, cols);
     return hipGetLastError();
 }
 
@@ -631,12 +676,12 @@ hipError_t launch_project(const Launch &L, double *x64, const double *minv64, co
 #define CHOM_INST(T, C, R)                                                                                        \
     template hipError_t launch_cg_init<T, C, R>(const Launch &, const T *, T *, T *, const void *, double *,      \
                                                 hipStream_t);                                                    \
-    template hipError_t launch_cg_dir<T, C, R>(const Launch &, T *, T *, const void *, const double *,           \
+    template hipError_t launch_cg_dir<T, C, R>(const Launch &, T *, T *, T *, const void *, const double *,      \
                                                const ColState *, const int *, hipStream_t, const void *,         \
                                                const void *);                                                    \
-    template hipError_t launch_cg_update<T, C, R>(const Launch &, T *, T *, const T *, const T *,                \
-                                                  const void *, const ColState *, double *, const int *,         \
-                                                  hipStream_t);
+    template hipError_t launch_cg_update<T, C, R>(const Launch &, T *, const T *, const void *, const ColState *, \
+                                                  double *, const int *, hipStream_t);                           \
+    template hipError_t launch_cg_flush_x<T, C, R>(const Launch &, T *, const T *, const ColState *, hipStream_t);
 CHOM_INST(double, 3, 6)
 CHOM_INST(float, 3, 6)
 CHOM_INST(double, 1, 3)

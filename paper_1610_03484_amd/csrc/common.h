@@ -341,9 +341,10 @@ __device__ inline bool dirichlet_boundary(const Geo &G, int X, int Y, int Z) {
     return G.bc == 0 && (X == 0 || Y == 0 || Z == 0 || X == m || Y == m || Z == m);
 }
 
-// Operator output layout: one (p T + 1)^3 box of values per tile ("tile boxes"),
-// tile-major, the RC values of a box point contiguous.  A lattice point on a
-// tile face lies in up to two tiles per axis; its value is the sum of its copies.
+// Operator output layout: one (p T + 1)^3 box of values per tile and load case
+// ("tile boxes"): [tile][load-case group][load case of the group][box point][C],
+// so a wave gathering one load case reads contiguous values.  A lattice point on
+// a tile face lies in up to two tiles per axis; its value is the sum of its copies.
 // Candidate (tile, local) pairs of coordinate X along one axis.
 __device__ inline int tile_cands(int X, int T2, int ntiles, int m2, bool per, int tl[2], int lc[2]) {
     int t = X / T2;
@@ -369,7 +370,7 @@ __device__ inline int tile_cands(int X, int T2, int ntiles, int m2, bool per, in
 // group, R / rg groups.
 template <typename T, int C, int R>
 __device__ inline void gather_tiles_col(const Geo &G, const T *qt, int rg, int X, int Y, int Z, int w, double out[C]) {
-    const int ng = R / rg, rcg = rg * C;
+    const int ng = R / rg;
     const int grp = w / rg, rr = w - grp * rg;
     const bool per = (G.bc == 1);
     const int m2 = G.L;
@@ -383,7 +384,8 @@ __device__ inline void gather_tiles_col(const Geo &G, const T *qt, int rg, int X
         for (int b = 0; b < ny; ++b)
             for (int c = 0; c < nz; ++c) {
                 const long long tile = tx[a] + (long long)G.tiles_x * (ty[b] + (long long)G.tiles_y * tz[c]);
-                const long long off = ((tile * ng + grp) * G.boxpts + lx[a] + G.bx * (ly[b] + G.by * lz[c])) * rcg + rr * C;
+                const long long off =
+                    (((tile * ng + grp) * rg + rr) * G.boxpts + lx[a] + G.bx * (ly[b] + G.by * lz[c])) * C;
 #pragma unroll
                 for (int v = 0; v < C; ++v) out[v] += (double)qt[off + v];
             }

@@ -550,7 +550,11 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
     __syncthreads();
     // ---- write the cell's box (contiguous)
     T *yt = y + Pb.qoff + (long long)cell * BP * RC;
-    for (int i = tid; i < BP * RC; i += HP_THREADS) yt[i] = (T)yb[i];
+    for (int i = tid; i < BP * RC; i += HP_THREADS) {   // load-case major: i = (r * BP + pt) * C + c
+        const int r = i / (BP * C), rem = i - r * (BP * C);
+        const int pt = rem / C, c = rem - (rem / C) * C;
+        yt[i] = (T)yb[pt * RC + r * C + c];
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const double sm = wave_sum(pq[r]);

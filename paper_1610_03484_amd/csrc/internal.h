@@ -86,13 +86,17 @@ hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y,
 
 template <typename T, int C, int R>
 hipError_t launch_cg_init(const Launch &L, const T *b, T *x, T *r, const void *minv, double *accbuf, hipStream_t s);
+// Direction step; also applies the previous step's x += alpha p (deferred from
+// the update kernel); launch_cg_flush_x applies the last one after a solve.
 template <typename T, int C, int R>
-hipError_t launch_cg_dir(const Launch &L, T *r, T *p, const void *minv, const double *ycoef,
+hipError_t launch_cg_dir(const Launch &L, T *x, T *r, T *p, const void *minv, const double *ycoef,
                          const ColState *cols, const int *prob_active, hipStream_t s,
                          const void *mg_x0 = nullptr, const void *mg_W = nullptr);
 template <typename T, int C, int R>
-hipError_t launch_cg_update(const Launch &L, T *x, T *r, const T *p, const T *q, const void *minv,
-                            const ColState *cols, double *accbuf, const int *prob_active, hipStream_t s);
+hipError_t launch_cg_update(const Launch &L, T *r, const T *q, const void *minv, const ColState *cols,
+                            double *accbuf, const int *prob_active, hipStream_t s);
+template <typename T, int C, int R>
+hipError_t launch_cg_flush_x(const Launch &L, T *x, const T *p, const ColState *cols, hipStream_t s);
 template <int C, int R>
 hipError_t launch_finish_alpha(const Launch &L, double *acc_pq, ColState *cols, hipStream_t s);
 template <int C, int R>

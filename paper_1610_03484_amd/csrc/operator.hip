@@ -9,8 +9,9 @@
 // the stiffness is evaluated on the fly from five invariants), accumulates the
 // element results in an FP64 LDS box with LDS atomics (FP64 LDS atomic adds are
 // markedly faster than FP32 ones on gfx950), and stores the whole box,
-// contiguous, to its slot of the tile-box output: no global atomics, no zeroing
-// pass; consumers sum the copies of points on shared tile faces.  The element
+// contiguous and load-case major, to its slot of the tile-box output: no
+// global atomics, no zeroing pass; consumers sum the copies of points on shared
+// tile faces.  The element
 // energies x_e . K_e x_e (p.Kp for CG) are formed per tet in the vector
 // precision and summed in FP64.
 //
@@ -213,9 +214,10 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
 
     // ---- write this group's tile box (contiguous, coalesced)
     T *qt = y + P.qoff + ((long long)tile * NG + grp) * NBOX;
-    for (int i = tt; i < NBOX; i += TILE_TETS) {
-        const int pt = i / RCg, v = i - pt * RCg;
-        qt[i] = (T)ys[(pt % BX + BXP * (pt / BX)) * PS + v];
+    for (int i = tt; i < NBOX; i += TILE_TETS) {   // i = (rr * BOXPTS + pt) * C + c
+        const int rr = i / (BOXPTS * C), rem = i - rr * (BOXPTS * C);
+        const int pt = rem / C, c = rem - (rem / C) * C;
+        qt[i] = (T)ys[(pt % BX + BXP * (pt / BX)) * PS + rr * C + c];
     }
 
     // ---- element energies p.Kp into the striped accumulators [prob][load case][ACC_STRIPES]
