@@ -532,7 +532,7 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
     CHOM_HIP(hipMemsetAsync(W.cols.p, 0, sizeof(ColState) * R * nprob, s));
     CHOM_HIP(hipMemsetAsync(W.bad.p, 0, sizeof(int), s));
     if (L.order != 2) CHOM_HIP((launch_factors_hp<C>(L, W.ef64.p, W.ef32.p, s)));
-    CHOM_HIP((launch_precond<C>(L, W.total_pts, W.diag.p, W.minv64.p, W.minv32.p, s)));
+    CHOM_HIP((launch_precond<C>(L, W.total_pts, W.diag.p, W.minv64.p, W.minv32.p, W.q64.p, s)));
     const bool mg = L.mg.on != 0;
     CHOM_HIP((launch_gram<C>(L, W.minv64.p, W.minv32.p, W.partial.p, W.nwg_gram, W.ginv64.p, W.ginv32.p, W.bad.p, s,
                              mg ? W.gmat.p : nullptr)));

@@ -341,6 +341,27 @@ __device__ inline bool dirichlet_boundary(const Geo &G, int X, int Y, int Z) {
     return G.bc == 0 && (X == 0 || Y == 0 || Z == 0 || X == m || Y == m || Z == m);
 }
 
+// Acoustic tensor Q(w)_cd = sum_kl C_ckdl w_k w_l from the stress law.
+__device__ inline void acoustic(const double w[3], const double a[3], const double *m, double Q[3][3]) {
+    for (int d = 0; d < 3; ++d) {
+        double e[6] = {0, 0, 0, 0, 0, 0};
+        // sym(e_d (x) w)
+        double G3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int l = 0; l < 3; ++l) G3[d][l] = w[l];
+        e[0] = G3[0][0];
+        e[1] = G3[1][1];
+        e[2] = G3[2][2];
+        e[3] = 0.5 * (G3[0][1] + G3[1][0]);
+        e[4] = 0.5 * (G3[1][2] + G3[2][1]);
+        e[5] = 0.5 * (G3[2][0] + G3[0][2]);
+        double s[6];
+        stress_ti<double>(e, a, m, s);
+        Q[0][d] = s[0] * w[0] + s[3] * w[1] + s[5] * w[2];
+        Q[1][d] = s[3] * w[0] + s[1] * w[1] + s[4] * w[2];
+        Q[2][d] = s[5] * w[0] + s[4] * w[1] + s[2] * w[2];
+    }
+}
+
 // Operator output layout: one (p T + 1)^3 box of values per tile and load case
 // ("tile boxes"): [tile][load-case group][load case of the group][box point][C],
 // so a wave gathering one load case reads contiguous values.  A lattice point on
@@ -424,27 +445,54 @@ __device__ inline void load_rows(const Geo &G, long long pt, double row[4]) {
 }
 
 // In-place Gauss-Jordan with partial pivoting on the augmented S x 2S system
-// [A | I] (S <= 12): on success the right half holds A^-1.  Returns 0 if singular.
-__device__ inline int gauss_jordan(double A[12][24], int S) {
+// [A | I] (S <= 12) by a whole workgroup (blockDim.x >= 144; every thread
+// calls it; `sh` is two ints of LDS): on success the right half holds A^-1;
+// returns 0 if singular.  Per pivot one thread picks the row, then the threads
+// update one or two entries each between barriers.
+__device__ inline int gauss_jordan_wg(double A[12][24], int S, int *sh) {
+    const int tid = threadIdx.x, nt = blockDim.x, W = 2 * S;
     for (int c = 0; c < S; ++c) {
-        int piv = c;
-        for (int r = c + 1; r < S; ++r)
-            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
-        if (!(fabs(A[piv][c]) > 0.0)) return 0;
-        if (piv != c)
-            for (int k = 0; k < 2 * S; ++k) {
+        if (tid == 0) {
+            int piv = c;
+            for (int r = c + 1; r < S; ++r)
+                if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+            sh[0] = piv;
+            sh[1] = fabs(A[piv][c]) > 0.0 ? 1 : 0;
+        }
+        __syncthreads();
+        if (!sh[1]) return 0;
+        const int piv = sh[0];
+        if (piv != c) {
+            for (int k = tid; k < W; k += nt) {
                 const double t = A[c][k];
                 A[c][k] = A[piv][k];
                 A[piv][k] = t;
             }
-        const double ip = 1.0 / A[c][c];
-        for (int k = 0; k < 2 * S; ++k) A[c][k] *= ip;
-        for (int r = 0; r < S; ++r) {
-            if (r == c) continue;
-            const double f = A[r][c];
-            if (f != 0.0)
-                for (int k = 0; k < 2 * S; ++k) A[r][k] -= f * A[c][k];
+            __syncthreads();
         }
+        const double ip = 1.0 / A[c][c];
+        double nv[2], fv[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int e = tid + m * nt;
+            nv[m] = fv[m] = 0.0;
+            if (e < S * W) {
+                const int r = e / W, k = e - (e / W) * W;
+                nv[m] = A[c][k] * ip;
+                fv[m] = (r == c) ? 0.0 : A[r][c];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int e = tid + m * nt;
+            if (e < S * W) {
+                const int r = e / W, k = e - (e / W) * W;
+                if (r == c) A[c][k] = nv[m];
+                else if (fv[m] != 0.0) A[r][k] -= fv[m] * nv[m];
+            }
+        }
+        __syncthreads();
     }
     return 1;
 }

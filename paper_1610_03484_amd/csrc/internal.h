@@ -68,7 +68,7 @@ int operator_tiles(const Geo &G);
 // Per class of problems.
 template <int C>
 hipError_t launch_precond(const Launch &L, long long total_pts, double *diag, double *minv64, float *minv32,
-                          hipStream_t s);
+                          double *qscratch, hipStream_t s);
 template <int C>
 hipError_t launch_gram(const Launch &L, const double *minv64, const float *minv32, double *gram_partial, int nwg,
                        double *ginv64, double *ginv32, int *bad, hipStream_t s, double *gmat = nullptr);
@@ -79,6 +79,9 @@ hipError_t launch_rhs(const Launch &L, long long total_vals, double *b, ColState
                       double *acc_pq, hipStream_t s);
 template <int C, int R>
 hipError_t launch_rhs_operator(const Launch &L, int rg, double *y, double *acc_pq, hipStream_t s);
+// Tile boxes of the order-2 diagonal point blocks (group 0 of the FP64 boxes;
+// packed xx yy zz xy yz xz for elasticity); summed per point by launch_precond.
+template <int C, int R> hipError_t launch_diag_operator(const Launch &L, double *y, hipStream_t s);
 
 template <typename T, int C, int R>
 hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y,

@@ -1159,7 +1159,7 @@ __global__ __launch_bounds__(256) void mg_gram_finish_kernel(const Geo *geos, co
                                                              double *ginv, int *bad) {
     constexpr int SMAX = C * 4;
     __shared__ double A[12][24];
-    __shared__ int ok_s;
+    __shared__ int ok_s, piv_s[2];
     const int prob = blockIdx.x;
     const Geo &G = geos[probs[prob].geo];
     const int nr = G.nrow, S = C * nr;
@@ -1173,9 +1173,10 @@ __global__ __launch_bounds__(256) void mg_gram_finish_kernel(const Geo *geos, co
         A[I][S + J] = (I == J) ? 1.0 : 0.0;
     }
     __syncthreads();
+    const int ok = gauss_jordan_wg(A, S, piv_s);
     if (threadIdx.x == 0) {
-        ok_s = gauss_jordan(A, S);
-        if (!ok_s) atomicAdd(bad, 1);
+        ok_s = ok;
+        if (!ok) atomicAdd(bad, 1);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < S * S; t += blockDim.x)

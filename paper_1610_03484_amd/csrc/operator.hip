@@ -27,14 +27,23 @@ namespace chom {
 
 int operator_tiles(const Geo &G) { return G.tiles_x * G.tiles_y * G.tiles_z; }
 
-// RHS = true: no input vector; every tet applies its constant stress (flux) of
-// the unit macro strain (gradient) of the load case, y = int grad(phi) . C eps_k,
-// and its energy |e| eps_k . C eps_k goes to the accumulators (load vectors of
-// the fluctuation problems, Sec. 2, Eqs. Eq_C_stress and eq_homo_flux).
-template <typename T, int C, int R, int RG, bool RHS = false>
+// MODE: OP_APPLY  y = K x (and the element energies x.Kx);
+//       OP_RHS    no input vector; every tet applies its constant stress (flux)
+//                 of the unit macro strain (gradient) of the load case,
+//                 y = int grad(phi) . C eps_k, and its energy |e| eps_k . C eps_k
+//                 goes to the accumulators (load vectors of the fluctuation
+//                 problems, Sec. 2, Eqs. Eq_C_stress and eq_homo_flux);
+//       OP_DIAG   (FP64, group 0 only; RG C = 6 for elasticity, 1 for the scalar
+//                 fields) the point blocks of diag(K): per node the element's
+//                 block int grad(phi) C grad(phi), packed xx yy zz | xy yz xz in
+//                 the group's RG C slots.
+enum { OP_APPLY = 0, OP_RHS = 1, OP_DIAG = 2 };
+template <typename T, int C, int R, int RG, int MODE = OP_APPLY>
 __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const Prob *probs, int max_tiles,
                                                           const T *__restrict__ x, T *__restrict__ y,
                                                           double *acc_pq, const int *prob_active) {
+    constexpr bool RHS = MODE == OP_RHS, DIAG = MODE == OP_DIAG, STAGE = MODE == OP_APPLY;
+    static_assert(!DIAG || (std::is_same<T, double>::value && RG * C == (C == 3 ? 6 : 1)), "diag mode layout");
     constexpr int NG = R / RG;
     constexpr int RCg = RG * C;
     // LDS layout of the box: point (bx, by, bz) at bx + BXP (by + BY bz), PS
@@ -55,7 +64,8 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     __shared__ T sg[6][10];
     __shared__ double red[RG][NW];
     const int prob = blockIdx.y;
-    const int tile = blockIdx.x / NG, grp = blockIdx.x - (blockIdx.x / NG) * NG;
+    const int tile = DIAG ? (int)blockIdx.x : (int)blockIdx.x / NG;
+    const int grp = DIAG ? 0 : (int)blockIdx.x - ((int)blockIdx.x / NG) * NG;
     const int tt = threadIdx.x;
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
@@ -65,14 +75,14 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     const int cx0 = tx * TX, cy0 = ty * TY, cz0 = tz * TZ;
     const int X0 = 2 * cx0, Y0 = 2 * cy0, Z0 = 2 * cz0;
     const int hx = min(X0 + 2 * TX, m2), hy = min(Y0 + 2 * TY, m2), hz = min(Z0 + 2 * TZ, m2);
-    const T *xp = RHS ? nullptr : x + P.voff;   // vectors are [load case][point][component]
+    const T *xp = STAGE ? x + P.voff : nullptr;   // vectors are [load case][point][component]
 
     // ---- stage the DOF box (this group's values), element data, geometry.
     // Every load is issued unconditionally (out-of-box elements read element 0
     // and are replaced by zero) with the lattice fields held in registers, so
     // all NST loads are in flight together with no branch between them.
     T tmp[NST];
-    if constexpr (!RHS) {
+    if constexpr (STAGE) {
         const int Lw = G.Lw, Lm = (G.bc == 1) ? G.L : -1;   // periodic: index L wraps to 0
         const long long col0 = (long long)grp * RG * G.npts;
         const long long np = G.npts;
@@ -102,7 +112,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     if (live) {
         if constexpr (std::is_same<T, double>::value) ev = G.elem64[tet]; else ev = G.elem32[tet];
     }
-    if constexpr (!RHS) {
+    if constexpr (STAGE) {
 #pragma unroll
         for (int k = 0; k < NST; ++k) {
             const int i = tt + TILE_TETS * k;
@@ -148,6 +158,53 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
 #pragma unroll
         for (int k = 0; k < 10; ++k)
             lp[k] = ((2 * lcx + off[k][0]) + BXP * ((2 * lcy + off[k][1]) + BY * (2 * lcz + off[k][2]))) * PS;
+        if constexpr (DIAG) {
+            // vertex a: |e| Q(g_a); edge (a, b): (4/5)|e| [Q(g_a + g_b) + Q(g_a) + Q(g_b)],
+            // Q(w) = sum_kl C_.k.l w_k w_l (the integrals of the hierarchic basis products)
+#pragma unroll 1
+            for (int k = 0; k < 10; ++k) {
+                double ws[3][3], cs;
+                int nw;
+                if (k < 4) {
+                    nw = 1;
+                    for (int d = 0; d < 3; ++d) ws[0][d] = g[k][d];
+                    cs = vol;
+                } else {
+                    int a2, b2;
+                    edge_verts(k - 4, a2, b2);
+                    nw = 3;
+                    for (int d = 0; d < 3; ++d) {
+                        ws[0][d] = g[a2][d] + g[b2][d];
+                        ws[1][d] = g[a2][d];
+                        ws[2][d] = g[b2][d];
+                    }
+                    cs = 0.8 * vol;
+                }
+                if constexpr (C == 3) {
+                    double acc[6] = {0, 0, 0, 0, 0, 0};
+                    for (int q = 0; q < nw; ++q) {
+                        double Q[3][3];
+                        acoustic(ws[q], a, mloc, Q);
+                        acc[0] += cs * Q[0][0];
+                        acc[1] += cs * Q[1][1];
+                        acc[2] += cs * Q[2][2];
+                        acc[3] += cs * Q[0][1];
+                        acc[4] += cs * Q[1][2];
+                        acc[5] += cs * Q[0][2];
+                    }
+#pragma unroll
+                    for (int v = 0; v < 6; ++v) atomicAdd(&ys[lp[k] + v], acc[v]);
+                } else {
+                    double acc = 0.0;
+                    for (int q = 0; q < nw; ++q) {
+                        double fl[3];
+                        flux_ti<double>(ws[q], a, mloc, fl);
+                        acc += cs * (fl[0] * ws[q][0] + fl[1] * ws[q][1] + fl[2] * ws[q][2]);
+                    }
+                    atomicAdd(&ys[lp[k]], acc);
+                }
+            }
+        } else {
 #pragma unroll
         for (int r = 0; r < RG; ++r) {
             T yv[10][C];
@@ -209,6 +266,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
                 for (int c = 0; c < C; ++c) atomicAdd(&ys[lp[k] + r * C + c], (double)yv[k][c]);
             pq[r] = en;
         }
+        }
     }
     __syncthreads();
 
@@ -221,6 +279,7 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     }
 
     // ---- element energies p.Kp into the striped accumulators [prob][load case][ACC_STRIPES]
+    if constexpr (DIAG) return;
     const int lane = tt & 63, wv = tt >> 6;
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
@@ -251,20 +310,31 @@ hipError_t launch_rhs_operator(const Launch &L, int rg, double *y, double *acc_p
     const int G = L.max_tiles;
     if constexpr (C == 3) {
         switch (rg) {
-            case 1: op_p2_kernel<double, C, R, 1, true><<<dim3(G * R, L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
-            case 3: op_p2_kernel<double, C, R, 3, true><<<dim3(G * (R / 3), L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
-            default: op_p2_kernel<double, C, R, 2, true><<<dim3(G * (R / 2), L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
+            case 1: op_p2_kernel<double, C, R, 1, OP_RHS><<<dim3(G * R, L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
+            case 3: op_p2_kernel<double, C, R, 3, OP_RHS><<<dim3(G * (R / 3), L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
+            default: op_p2_kernel<double, C, R, 2, OP_RHS><<<dim3(G * (R / 2), L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
         }
     } else {
         switch (rg) {
-            case 1: op_p2_kernel<double, C, R, 1, true><<<dim3(G * R, L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
-            default: op_p2_kernel<double, C, R, 3, true><<<dim3(G * (R / 3), L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
+            case 1: op_p2_kernel<double, C, R, 1, OP_RHS><<<dim3(G * R, L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
+            default: op_p2_kernel<double, C, R, 3, OP_RHS><<<dim3(G * (R / 3), L.nprob), TILE_TETS, 0, s>>>(L.geos, L.probs, G, nullptr, y, acc_pq, nullptr); break;
         }
     }
     return hipGetLastError();
 }
 template hipError_t launch_rhs_operator<3, 6>(const Launch &, int, double *, double *, hipStream_t);
 template hipError_t launch_rhs_operator<1, 3>(const Launch &, int, double *, double *, hipStream_t);
+
+// Tile boxes (group 0, FP64) of the point blocks of diag(K), order 2.
+template <int C, int R>
+hipError_t launch_diag_operator(const Launch &L, double *y, hipStream_t s) {
+    constexpr int RG = (C == 3) ? 2 : 1;
+    op_p2_kernel<double, C, R, RG, OP_DIAG><<<dim3(L.max_tiles, L.nprob), TILE_TETS, 0, s>>>(
+        L.geos, L.probs, L.max_tiles, nullptr, y, nullptr, nullptr);
+    return hipGetLastError();
+}
+template hipError_t launch_diag_operator<3, 6>(const Launch &, double *, hipStream_t);
+template hipError_t launch_diag_operator<1, 3>(const Launch &, double *, hipStream_t);
 
 template <typename T, int C, int R>
 hipError_t launch_operator(const Launch &L, int nprob, int rg, const T *x, T *y, double *acc_pq,

@@ -146,88 +146,35 @@ hipError_t launch_rows(const Geo &G, double *rows, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ preconditioner
-// Acoustic tensor Q(w)_cd = sum_kl C_ckdl w_k w_l from the stress law.
-__device__ inline void acoustic(const double w[3], const double a[3], const double *m, double Q[3][3]) {
-    for (int d = 0; d < 3; ++d) {
-        double e[6] = {0, 0, 0, 0, 0, 0};
-        // sym(e_d (x) w)
-        double G3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        for (int l = 0; l < 3; ++l) G3[d][l] = w[l];
-        e[0] = G3[0][0];
-        e[1] = G3[1][1];
-        e[2] = G3[2][2];
-        e[3] = 0.5 * (G3[0][1] + G3[1][0]);
-        e[4] = 0.5 * (G3[1][2] + G3[2][1]);
-        e[5] = 0.5 * (G3[2][0] + G3[0][2]);
-        double s[6];
-        stress_ti<double>(e, a, m, s);
-        Q[0][d] = s[0] * w[0] + s[3] * w[1] + s[5] * w[2];
-        Q[1][d] = s[3] * w[0] + s[1] * w[1] + s[4] * w[2];
-        Q[2][d] = s[5] * w[0] + s[4] * w[1] + s[2] * w[2];
-    }
-}
-
+// Point-block Jacobi: the blocks of diag(K) come, for order 2, from the
+// operator kernel's diagonal mode (tile boxes, LDS accumulation) summed per
+// point here; Dirichlet points get a zero block (and a zero inverse).
 template <int C>
-__global__ void diag_kernel(const Geo *geos, const Prob *probs, double *diag) {
+__global__ void diag_gather_kernel(const Geo *geos, const Prob *probs, const double *q, double *diag) {
     constexpr int MS = (C == 3) ? 6 : 1;
+    constexpr int R = (C == 3) ? 6 : 3;
+    constexpr int RG = (C == 3) ? 2 : 1;
     const Prob &P = probs[blockIdx.y];
     const Geo &G = geos[P.geo];
     double *D = diag + P.doff * MS;
-    const long long nt = 6LL * G.n * G.n * G.n;
-    for (long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x; u < nt;
-         u += (long long)gridDim.x * blockDim.x) {
-        const long long e = scatter_tet(u, nt / 6);
-        int t, Pt[10][3];
-        tet_points(G, e, t, Pt);
-        double g[4][3], vol, a[3];
-        int ph;
-        GeoSel<double>::get(G, e, t, g, vol);
-        GeoSel<double>::elem(G, e, a, ph);
-        const double *m = P.mat64[ph ? 1 : 0];
-        for (int k = 0; k < 10; ++k) {
-            if (dirichlet_boundary(G, Pt[k][0], Pt[k][1], Pt[k][2])) continue;
-            const long long idx = lat_index(G, Pt[k][0], Pt[k][1], Pt[k][2]);
-            // decomposition sum_m c_m w_m w_m^T of int grad(phi) grad(phi)^T
-            double ws[3][3], cs[3];
-            int nw;
-            if (k < 4) {
-                nw = 1;
-                for (int d = 0; d < 3; ++d) ws[0][d] = g[k][d];
-                cs[0] = vol;
-            } else {
-                int a2, b2;
-                edge_verts(k - 4, a2, b2);
-                nw = 3;
-                for (int d = 0; d < 3; ++d) {
-                    ws[0][d] = g[a2][d] + g[b2][d];
-                    ws[1][d] = g[a2][d];
-                    ws[2][d] = g[b2][d];
-                }
-                cs[0] = cs[1] = cs[2] = 0.8 * vol;
-            }
+    const double *qt = q + P.qoff;
+    for (long long pt = blockIdx.x * (long long)blockDim.x + threadIdx.x; pt < G.npts;
+         pt += (long long)gridDim.x * blockDim.x) {
+        int X, Y, Z;
+        lattice_xyz(G, pt, X, Y, Z);
+        double out[MS];
+#pragma unroll
+        for (int v = 0; v < MS; ++v) out[v] = 0.0;
+        if (!dirichlet_boundary(G, X, Y, Z)) {
             if constexpr (C == 3) {
-                double acc[6] = {0, 0, 0, 0, 0, 0};
-                for (int q = 0; q < nw; ++q) {
-                    double Q[3][3];
-                    acoustic(ws[q], a, m, Q);
-                    acc[0] += cs[q] * Q[0][0];
-                    acc[1] += cs[q] * Q[1][1];
-                    acc[2] += cs[q] * Q[2][2];
-                    acc[3] += cs[q] * Q[0][1];
-                    acc[4] += cs[q] * Q[1][2];
-                    acc[5] += cs[q] * Q[0][2];
-                }
-                for (int c = 0; c < 6; ++c) atomicAdd(&D[6 * idx + c], acc[c]);
+                gather_tiles_col<double, 3, R>(G, qt, RG, X, Y, Z, 0, out);
+                gather_tiles_col<double, 3, R>(G, qt, RG, X, Y, Z, 1, out + 3);
             } else {
-                double acc = 0.0;
-                for (int q = 0; q < nw; ++q) {
-                    double fl[3];
-                    flux_ti<double>(ws[q], a, m, fl);
-                    acc += cs[q] * (fl[0] * ws[q][0] + fl[1] * ws[q][1] + fl[2] * ws[q][2]);
-                }
-                atomicAdd(&D[idx], acc);
+                gather_tiles_col<double, 1, R>(G, qt, RG, X, Y, Z, 0, out);
             }
         }
+#pragma unroll
+        for (int v = 0; v < MS; ++v) D[pt * MS + v] = out[v];
     }
 }
 
@@ -264,22 +211,26 @@ __global__ void invert_diag_kernel(long long total, const double *diag, double *
 
 template <int C>
 hipError_t launch_precond(const Launch &L, long long total_pts, double *diag, double *minv64, float *minv32,
-                          hipStream_t s) {
+                          double *qscratch, hipStream_t s) {
     constexpr int MS = (C == 3) ? 6 : 1;
-    hipError_t err = hipMemsetAsync(diag, 0, sizeof(double) * MS * total_pts, s);
-    if (err != hipSuccess) return err;
-    dim3 grid(grid_for(L.max_tets, 256, 2048), L.nprob);
+    constexpr int R = (C == 3) ? 6 : 3;
+    hipError_t err;
     if (L.order != 2) {
+        err = hipMemsetAsync(diag, 0, sizeof(double) * MS * total_pts, s);
+        if (err != hipSuccess) return err;
         err = launch_diag_hp<C>(L, diag, s);
         if (err != hipSuccess) return err;
     } else {
-        diag_kernel<C><<<grid, 256, 0, s>>>(L.geos, L.probs, diag);
+        err = launch_diag_operator<C, R>(L, qscratch, s);
+        if (err != hipSuccess) return err;
+        diag_gather_kernel<C><<<dim3(grid_for(L.max_tets / 6 + 1, 256, 1024), L.nprob), 256, 0, s>>>(L.geos, L.probs,
+                                                                                                    qscratch, diag);
     }
     invert_diag_kernel<C><<<grid_for(total_pts, 256), 256, 0, s>>>(total_pts, diag, minv64, minv32);
     return hipGetLastError();
 }
-template hipError_t launch_precond<3>(const Launch &, long long, double *, double *, float *, hipStream_t);
-template hipError_t launch_precond<1>(const Launch &, long long, double *, double *, float *, hipStream_t);
+template hipError_t launch_precond<3>(const Launch &, long long, double *, double *, float *, double *, hipStream_t);
+template hipError_t launch_precond<1>(const Launch &, long long, double *, double *, float *, double *, hipStream_t);
 
 // ------------------------------------------------------------------ Gram matrices
 // G[(i,a),(j,b)] = sum_pt row_a(pt) row_b(pt) Minv_pt[i][j] for the rows of the
@@ -361,7 +312,7 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const Geo *geos, const
     constexpr int NUMAX = 60;
     constexpr int SMAX = C * 4;
     __shared__ double A[12][24];
-    __shared__ int ok_s;
+    __shared__ int ok_s, piv_s[2];
     const int prob = blockIdx.x;
     const int nrow = geos[probs[prob].geo].nrow;
     if (nrow == 0) return;
@@ -390,9 +341,10 @@ __global__ __launch_bounds__(256) void gram_finish_kernel(const Geo *geos, const
             if (gmat != nullptr) gmat[((long long)which * nprob + prob) * SMAX * SMAX + I * S + J] = sum;
         }
         __syncthreads();
+        const int ok = gauss_jordan_wg(A, S, piv_s);
         if (threadIdx.x == 0) {
-            ok_s = gauss_jordan(A, S);
-            if (!ok_s) atomicAdd(bad, 1);
+            ok_s = ok;
+            if (!ok) atomicAdd(bad, 1);
         }
         __syncthreads();
         double *out = (which == 0 ? ginv64 : ginv32) + (long long)prob * SMAX * SMAX;
