@@ -85,11 +85,12 @@ def calibration_copy(torch):
     del x, y
 
 
-# HBM traffic of one launch of op_p2_kernel<float,3,6,2> on the default workload (three
-# 24^3 items), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the calibration copy
+# HBM traffic of one launch of op_p2_kernel<float,3,6,RG> on the default workload (three
+# 24^3 items, all active) per load-case grouping RG, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE scaled by the calibration copy
 # (profiles/op_p2_mech_fp32_24cubed_three_bc_traffic.md).  Must be re-measured (or set
 # to None) whenever that kernel changes.
-C1_OP_TRAFFIC_BYTES = 128_768_158
+C1_OP_TRAFFIC_BYTES = {1: 124_281_609, 2: 128_774_867, 3: 108_237_127}
 
 
 def algorithmic_mech_order(n, p, nprob, fp32):
@@ -247,6 +248,7 @@ def main():
 
     # dominant kernel: the mechanical operator launch of the batch
     ms, tets, nprob = batch.time_operator(0, args.op_reps)
+    rg_mech = batch.launch_config()["rg_mech"]
     calibration_copy(torch)
     fp32 = wl["precision"] != "fp64"
     if args.workload == "c2":
@@ -265,7 +267,7 @@ def main():
     if t_alu >= t_hbm:
         roof = dict(bound="alu", achieved=flops / t / 1e12, peak=peak_alu / 1e12, unit="TFLOP/s",
                     frac=(flops / t) / peak_alu,
-                    traffic=C1_OP_TRAFFIC_BYTES if (args.workload == "c1" and fp32) else None)
+                    traffic=C1_OP_TRAFFIC_BYTES.get(rg_mech) if (args.workload == "c1" and fp32) else None)
     else:
         roof = dict(bound="hbm", achieved=bytes_ / t / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
                     frac=(bytes_ / t) / HBM_PEAK, traffic=None)
@@ -275,7 +277,7 @@ def main():
                     note="FP32 matrix-core peak (157.3 TFLOP/s dense, equal to the packed FP32 vector peak)")
         kname = f"hp_op_kernel<float,{args.order},3,6,8>"
     else:
-        kname = "op_p2_kernel<float,3,6>" if fp32 else "op_p2_kernel<double,3,6>"
+        kname = f"op_p2_kernel<float,3,6,{rg_mech}>" if fp32 else f"op_p2_kernel<double,3,6,{rg_mech}>"
     roof.update(kernel=kname,
                 avg_launch_us=ms * 1e3, algorithmic_bytes=bytes_, algorithmic_flops=flops)
     print(f"[bench] operator: {ms * 1e3:.1f} us/launch, {bytes_ / t / 1e9:.0f} GB/s algorithmic, "
