@@ -155,10 +155,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed launch shape instead of the library's autotuner (which runs in the warm-up)")
     ap.add_argument("--order", type=int, default=4, help="c3: polynomial order (3 or 4)")
-    ap.add_argument("--rtol", type=float, default=1e-8,
-                    help="stopping tolerance of the FP64 residual (relative to the linear-field energy); "
-                         "1e-8 gives C_hom within ~1e-9 of the FP64 path (measured and reported each run)")
-    ap.add_argument("--inner-rtol", type=float, default=1e-4, help="FP32 inner solve tolerance per refinement pass")
+    ap.add_argument("--rtol", type=float, default=3e-5,
+                    help="stopping tolerance of the FP64 residual (relative to the linear-field energy); with "
+                         "the library's energy-form averages the default keeps C_hom >= 10x inside the 1e-6 "
+                         "target of the FP32-refined form (the error against the FP64 path is measured and "
+                         "reported each run)")
+    ap.add_argument("--inner-rtol", type=float, default=3e-5, help="FP32 inner solve tolerance per refinement pass")
     ap.add_argument("--train", type=int, default=20000, help="c4: training solves")
     ap.add_argument("--epochs", type=int, default=300, help="c4: training epochs")
     ap.add_argument("--points", type=int, default=1_000_000, help="c4: surrogate evaluation points")
@@ -232,17 +234,33 @@ def main():
           f"max iters {max(rep[worst]['iters'])} ({labels[worst]}: iters={rep[worst]['iters']} "
           f"refine={rep[worst]['refine_steps']})", file=sys.stderr)
 
-    # accuracy against the FP64 GPU path (same RVEs, same parameters); for the
-    # mixed-size batch it is measured by the tests on a stratified sample instead
+    # accuracy against the FP64 GPU path solved to rtol 1e-12 (same RVEs, same
+    # parameters): every item of the three-BC batch; for the mixed-size batch the
+    # first item of each size; for the order-3/4 batch the first two items
     err = None
-    if not args.no_accuracy and wl["precision"] != "fp64" and args.workload not in ("c2", "c3"):
-        ref_rves = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision="fp64", rtol=1e-12, max_iter=50000)
-                    for bc in wl["bcs"]]
+    acc_items = []
+    if not args.no_accuracy and wl["precision"] != "fp64":
+        if args.workload == "c2":
+            first = {}
+            for i, s_ in enumerate(sizes):
+                first.setdefault(int(s_), i)
+            acc_items = sorted(first.values())
+            ref_rves = [RVE(*generate_plain_weave(int(sizes[i]), device="cuda:0"), ci.BASE_MATERIALS, bc="periodic",
+                            precision="fp64", rtol=1e-12, max_iter=50000) for i in acc_items]
+        elif args.workload == "c3":
+            acc_items = [0, 1]
+            r64 = RVE(*generate_plain_weave(n, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic", order=args.order,
+                      precision="fp64", rtol=1e-12, max_iter=50000)
+            ref_rves = [r64] * len(acc_items)
+        else:
+            acc_items = list(range(len(rves)))
+            ref_rves = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision="fp64", rtol=1e-12, max_iter=50000)
+                        for bc in wl["bcs"]]
         ref = Batch(ref_rves)
-        Cr, Kr, Dr, _ = ref.homogenise(params)
-        errs = [max(np.linalg.norm(C[i] - Cr[i]) / np.linalg.norm(Cr[i]),
-                    np.linalg.norm(K[i] - Kr[i]) / np.linalg.norm(Kr[i]),
-                    np.linalg.norm(D[i] - Dr[i]) / np.linalg.norm(Dr[i])) for i in range(len(rves))]
+        Cr, Kr, Dr, _ = ref.homogenise(np.ascontiguousarray(params[acc_items]))
+        errs = [max(np.linalg.norm(C[i] - Cr[j]) / np.linalg.norm(Cr[j]),
+                    np.linalg.norm(K[i] - Kr[j]) / np.linalg.norm(Kr[j]),
+                    np.linalg.norm(D[i] - Dr[j]) / np.linalg.norm(Dr[j])) for j, i in enumerate(acc_items)]
         err = float(max(errs))
         ref.close()
 
@@ -300,7 +318,8 @@ def main():
         "config": {"workload": wl["desc"], "path": "batched", "rves_per_step": len(rves),
                    "rtol": args.rtol, "inner_rtol": args.inner_rtol,
                    "autotuned": os.environ.get("CHOM_AUTOTUNE") is not None, "precond": args.precond,
-                   "c_hom_rel_err_vs_fp64_gpu": err, "launch": batch.launch_config(),
+                   "c_hom_rel_err_vs_fp64_gpu": err, "accuracy_items": acc_items,
+                   "launch": batch.launch_config(),
                    "converged": int(sum(r["status"] == 0 for r in rep))},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -336,7 +336,7 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     part = std::max(part, (size_t)nprob * L.nwg * R * (2 + C * 4));
     part = std::max(part, (size_t)nprob * L.max_tiles * R);
     part = std::max(part, (size_t)nprob * W.nwg_gram * 2 * 60);
-    part = std::max(part, (size_t)nprob * W.nwg_avg * R * NC);
+    part = std::max(part, (size_t)nprob * W.nwg_avg * R * NC + (size_t)nprob * W.nwg_avg * R * R);
     part = std::max(part, (size_t)nprob * L.nwg * R * C * 4 + (size_t)nprob * R * C * 4);
     // two-level preconditioner
     Launch::Mg &M = L.mg;
@@ -592,7 +592,10 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
         x64 = W.x64.p;
     }
     CHOM_HIP((launch_project<C, R>(L, x64, W.minv64.p, W.ginv64.p, W.partial.p, s)));
-    CHOM_HIP((launch_average<C, R>(L, x64, W.partial.p, W.nwg_avg, W.avg_out.p, s)));
+    // energy form of the averages: the final projected residual (FP64 CG residual,
+    // or the FP64 refinement residual of the refined path) corrects them
+    const double *r_final = B->opt.precision == CHOM_FP64 ? W.rd.p : W.r64.p;
+    CHOM_HIP((launch_average<C, R>(L, x64, r_final, W.partial.p, W.nwg_avg, W.avg_out.p, s)));
     CHOM_HIP(hipMemcpyAsync(W.h_cols.data(), W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToHost, s));
     if (B->opt.precision == CHOM_FP32_REFINED)
         CHOM_HIP(hipMemcpyAsync(W.h_cols_outer.data(), W.cols_outer.p, sizeof(ColState) * R * nprob,

@@ -3,6 +3,11 @@
 //   sigma_bar_k = (1/V) sum_e C_e (eps_k |e| + int_e sym grad(u~_k) dV),
 // accumulated in FP64 from the FP64 fluctuation.  Column k of C_bar is
 // sigma_bar_k; K_bar and D_bar likewise with fluxes k_e (e_k |e| + int grad psi~).
+// For the exact discrete fluctuation this equals the energy form
+// (1/V) (x_i + u_i)^T K (x_k + u_k) (the residual of load case k vanishes on
+// admissible u_i); for an iterate u = u* + e the plain average is off by a term
+// linear in e, the energy form only by e_i^T K e_k.  The library therefore
+// subtracts (1/V) u_i . r_k, r_k = b_k - K u_k the final projected residual.
 #include "common.h"
 #include "internal.h"
 
@@ -80,26 +85,62 @@ __global__ void average_kernel(const Geo *geos, const Prob *probs, const double 
     }
 }
 
-// out[prob][i][j] = (1/V) sum of partials: row i = stress/flux component, column j = load case.
+// Residual correction of the average: u_l . r_k summed over the lattice for every
+// pair of load cases (l, k), u the fluctuation and r = b - K u its projected
+// residual.  Wave w takes u_w; partial[((prob * nwg + block) * R + l) * R + k].
 template <int C, int R>
-__global__ void average_finish_kernel(const Geo *geos, const Prob *probs, int nwg, const double *partial, double *out) {
+__global__ __launch_bounds__(64 * R) void residual_pair_kernel(const Geo *geos, const Prob *probs, const double *x,
+                                                               const double *r, double *partial) {
+    const int prob = blockIdx.y;
+    const Prob &P = probs[prob];
+    const Geo &G = geos[P.geo];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.0;
+    const double *xp = x + P.voff, *rp = r + P.voff;
+    for (long long pt = blockIdx.x * 64LL + lane; pt < G.npts; pt += gridDim.x * 64LL) {
+        double u[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) u[c] = xp[(w * G.npts + pt) * C + c];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[k] += u[c] * rp[(k * G.npts + pt) * C + c];
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) partial[(((long long)prob * gridDim.x + blockIdx.x) * R + w) * R + k] = v;
+    }
+}
+
+// out[prob][i][j] = (1/V) sum of partials: row i = stress/flux component, column j = load case.
+// With `rpart` (residual_pair_kernel sums, nwg2 blocks) the entry becomes the
+// energy form (1/V) (x_i + u_i)^T K (x_j + u_j) = sigma_bar_j[i] - (1/V) u_i . r_j
+// (unit load cases in the stress/flux component order, so NC = R).
+template <int C, int R>
+__global__ void average_finish_kernel(const Geo *geos, const Prob *probs, int nwg, const double *partial, int nwg2,
+                                      const double *rpart, double *out) {
     constexpr int NC = (C == 3) ? 6 : 3;
+    static_assert(NC == R, "load cases are the unit strains / gradients");
     const int prob = blockIdx.x;
     const double volume = geos[probs[prob].geo].volume;
     const int lane = threadIdx.x;
     for (int k = 0; k < R * NC; ++k) {
+        const int r = k / NC, i = k % NC;   // load case r, component i
         double s = 0.0;
         for (int w = lane; w < nwg; w += 64) s += partial[((long long)prob * nwg + w) * R * NC + k];
+        if (rpart != nullptr)
+            for (int w = lane; w < nwg2; w += 64) s -= rpart[(((long long)prob * nwg2 + w) * R + i) * R + r];
         s = wave_sum(s);
-        if (lane == 0) {
-            const int r = k / NC, i = k % NC;   // load case r, component i
-            out[(long long)prob * NC * R + i * R + r] = s / volume;
-        }
+        if (lane == 0) out[(long long)prob * NC * R + i * R + r] = s / volume;
     }
 }
 
 template <int C, int R>
-hipError_t launch_average(const Launch &L, const double *x64, double *partial, int nwg, double *out, hipStream_t s) {
+hipError_t launch_average(const Launch &L, const double *x64, const double *r64, double *partial, int nwg,
+                          double *out, hipStream_t s) {
     dim3 grid(nwg, L.nprob);
     if (L.order != 2) {
         const hipError_t e = launch_average_partial_hp<C, R>(L, x64, partial, nwg, s);
@@ -107,10 +148,15 @@ hipError_t launch_average(const Launch &L, const double *x64, double *partial, i
     } else {
         average_kernel<C, R><<<grid, 256, 0, s>>>(L.geos, L.probs, x64, partial);
     }
-    average_finish_kernel<C, R><<<L.nprob, FIN_BS, 0, s>>>(L.geos, L.probs, nwg, partial, out);
+    constexpr int NC = (C == 3) ? 6 : 3;
+    double *rpart = r64 ? partial + (size_t)L.nprob * nwg * R * NC : nullptr;
+    if (r64) residual_pair_kernel<C, R><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, x64, r64, rpart);
+    average_finish_kernel<C, R><<<L.nprob, FIN_BS, 0, s>>>(L.geos, L.probs, nwg, partial, nwg, rpart, out);
     return hipGetLastError();
 }
-template hipError_t launch_average<3, 6>(const Launch &, const double *, double *, int, double *, hipStream_t);
-template hipError_t launch_average<1, 3>(const Launch &, const double *, double *, int, double *, hipStream_t);
+template hipError_t launch_average<3, 6>(const Launch &, const double *, const double *, double *, int, double *,
+                                        hipStream_t);
+template hipError_t launch_average<1, 3>(const Launch &, const double *, const double *, double *, int, double *,
+                                        hipStream_t);
 
 }  // namespace chom

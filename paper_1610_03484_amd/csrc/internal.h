@@ -119,8 +119,8 @@ template <int C, int R>
 hipError_t launch_project(const Launch &L, double *x64, const double *minv64, const double *ginv64,
                           double *partial, hipStream_t s);
 template <int C, int R>
-hipError_t launch_average(const Launch &L, const double *x64, double *partial, int nwg, double *out,
-                          hipStream_t s);
+hipError_t launch_average(const Launch &L, const double *x64, const double *r64, double *partial, int nwg,
+                          double *out, hipStream_t s);
 
 void set_error(const std::string &msg);
 
