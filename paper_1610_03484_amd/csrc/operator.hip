@@ -55,7 +55,6 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     constexpr int BXP = (sizeof(T) == 4 && RCg <= 3) ? 12 : 10;
     constexpr int LPTS = BXP * BY * BZ;
     constexpr int NBOX = BOXPTS * RCg;
-    constexpr int NST = (NBOX + TILE_TETS - 1) / TILE_TETS;
     constexpr int NCELL = TX * TY * TZ;
     constexpr int NW = TILE_TETS / 64;
     using V4 = typename std::conditional<std::is_same<T, double>::value, double4, float4>::type;
@@ -78,28 +77,39 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     const T *xp = STAGE ? x + P.voff : nullptr;   // vectors are [load case][point][component]
 
     // ---- stage the DOF box (this group's values), element data, geometry.
-    // Every load is issued unconditionally (out-of-box elements read element 0
-    // and are replaced by zero) with the lattice fields held in registers, so
-    // all NST loads are in flight together with no branch between them.
-    T tmp[NST];
+    // The box is RG x BY x BZ rows of BX points x C values, each row contiguous
+    // in the lattice: thread tt takes column tt % ROWLEN of rows tt / ROWLEN +
+    // RPP k, so its x coordinate, periodic wrap and LDS column are fixed and only
+    // a row offset changes per pass.  Every load is issued unconditionally
+    // (out-of-box elements read element 0 and are replaced by zero), all NPASS
+    // loads in flight together.
+    constexpr int ROWLEN = BX * C;
+    constexpr int NROW = RG * BY * BZ;
+    constexpr int RPP = TILE_TETS / ROWLEN;   // rows per pass
+    constexpr int NPASS = (NROW + RPP - 1) / RPP;
+    const int col = tt % ROWLEN, r0 = tt / ROWLEN;
+    const bool colok = r0 < RPP;
+    const int bxc = col / C, cc = col - (col / C) * C;
+    const int colL = bxc * PS + cc;   // LDS offset of the column within a box row
+    T tmp[NPASS];
     if constexpr (STAGE) {
         const int Lw = G.Lw, Lm = (G.bc == 1) ? G.L : -1;   // periodic: index L wraps to 0
-        const long long col0 = (long long)grp * RG * G.npts;
         const long long np = G.npts;
+        const T *xg = xp + (long long)grp * RG * np * C;
+        const int Xc = X0 + bxc;
+        const bool inx = colok && Xc <= hx;
+        const int Xw = Xc == Lm ? 0 : Xc;
 #pragma unroll
-        for (int k = 0; k < NST; ++k) {
-            const int i = tt + TILE_TETS * k;   // i = (rr * BOXPTS + pt) * C + c: lanes read contiguous memory
-            const int rr = i / (BOXPTS * C), rem = i - rr * (BOXPTS * C);
-            const int pt = rem / C, c = rem - (rem / C) * C;
-            const int bx = pt % BX, by = (pt / BX) % BY, bz = pt / (BX * BY);
-            int X = X0 + bx, Y = Y0 + by, Z = Z0 + bz;
-            const bool in = i < NBOX && X <= hx && Y <= hy && Z <= hz;
-            X = X == Lm ? 0 : X;
+        for (int k = 0; k < NPASS; ++k) {
+            const int row = r0 + RPP * k;
+            const int rr = row / (BY * BZ), rem = row - rr * (BY * BZ);
+            const int bz = rem / BY, by = rem - (rem / BY) * BY;
+            int Y = Y0 + by, Z = Z0 + bz;
+            const bool in = inx && row < NROW && Y <= hy && Z <= hz;
             Y = Y == Lm ? 0 : Y;
             Z = Z == Lm ? 0 : Z;
-            const int lin = X + Lw * (Y + Lw * Z);
-            const long long idx = in ? (col0 + rr * np + lin) * C + c : 0;
-            const T v = xp[idx];
+            const long long idx = in ? ((long long)rr * np + Xw + (long long)Lw * (Y + Lw * Z)) * C + cc : 0;
+            const T v = xg[idx];
             tmp[k] = in ? v : T(0);
         }
     }
@@ -114,12 +124,11 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     }
     if constexpr (STAGE) {
 #pragma unroll
-        for (int k = 0; k < NST; ++k) {
-            const int i = tt + TILE_TETS * k;
-            if (i < NBOX) {
-                const int rr = i / (BOXPTS * C), rem = i - rr * (BOXPTS * C);
-                const int pt = rem / C, c = rem - (rem / C) * C;
-                xs[(pt % BX + BXP * (pt / BX)) * PS + rr * C + c] = tmp[k];
+        for (int k = 0; k < NPASS; ++k) {
+            const int row = r0 + RPP * k;
+            if (colok && row < NROW) {
+                const int rr = row / (BY * BZ), rem = row - rr * (BY * BZ);
+                xs[BXP * rem * PS + rr * C + colL] = tmp[k];   // rem = by + BY bz
             }
         }
     }
@@ -270,12 +279,15 @@ __global__ __launch_bounds__(TILE_TETS) void op_p2_kernel(const Geo *geos, const
     }
     __syncthreads();
 
-    // ---- write this group's tile box (contiguous, coalesced)
+    // ---- write this group's tile box (load-case major, rows contiguous)
     T *qt = y + P.qoff + ((long long)tile * NG + grp) * NBOX;
-    for (int i = tt; i < NBOX; i += TILE_TETS) {   // i = (rr * BOXPTS + pt) * C + c
-        const int rr = i / (BOXPTS * C), rem = i - rr * (BOXPTS * C);
-        const int pt = rem / C, c = rem - (rem / C) * C;
-        qt[i] = (T)ys[(pt % BX + BXP * (pt / BX)) * PS + rr * C + c];
+#pragma unroll
+    for (int k = 0; k < NPASS; ++k) {
+        const int row = r0 + RPP * k;
+        if (colok && row < NROW) {
+            const int rr = row / (BY * BZ), rem = row - rr * (BY * BZ);   // rem = by + BY bz
+            qt[(rr * BOXPTS + BX * rem) * C + col] = (T)ys[BXP * rem * PS + rr * C + colL];
+        }
     }
 
     // ---- element energies p.Kp into the striped accumulators [prob][load case][ACC_STRIPES]
