@@ -116,6 +116,8 @@ struct GraphCache {
     const void *key = nullptr;   // buffer identity the graph was captured for
     int iters = 0;
     unsigned long long gen = 0;  // workspace generation it was captured for
+    const void *probs = nullptr; // problem range it was captured for
+    int nprob = 0;
     ~GraphCache() { reset(); }
     void reset() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -123,6 +125,8 @@ struct GraphCache {
         key = nullptr;
         iters = 0;
         gen = 0;
+        probs = nullptr;
+        nprob = 0;
     }
 };
 
@@ -130,6 +134,7 @@ template <int C, int R> struct ClassWS {
     static constexpr int MS = (C == 3) ? 6 : 1;
     Launch L{};
     hipStream_t stream = nullptr;        // the class's stream (mechanics: the batch stream)
+    hipStream_t stream_b = nullptr;      // the second CG chain's stream
     long long total_vals = 0, total_pts = 0, total_q = 0;
     int nwg_gram = 0, nwg_avg = 0;
     unsigned long long gen = 0;          // bumped whenever the launch shape may change
@@ -153,7 +158,7 @@ template <int C, int R> struct ClassWS {
     std::vector<ColState> h_cols, h_cols_outer;
     std::vector<int> h_active;
     std::vector<int> refine_steps;
-    GraphCache graph64, graph32;
+    GraphCache graph64, graph32, graph64b, graph32b;   // per precision and CG chain
 };
 
 }  // namespace chom
@@ -195,12 +200,13 @@ struct chom_batch {
     int nwg_mech = 0, nwg_scal = 0;     // vector workgroups per problem (0: default)
     bool tuned = false;
     ~chom_batch() {
-        mech.graph64.reset();
-        mech.graph32.reset();
-        scal.graph64.reset();
-        scal.graph32.reset();
+        for (GraphCache *g : {&mech.graph64, &mech.graph32, &mech.graph64b, &mech.graph32b, &scal.graph64,
+                              &scal.graph32, &scal.graph64b, &scal.graph32b})
+            g->reset();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         if (stream2) (void)hipStreamDestroy(stream2);
+        if (mech.stream_b) (void)hipStreamDestroy(mech.stream_b);
+        if (scal.stream_b) (void)hipStreamDestroy(scal.stream_b);
     }
 };
 
@@ -448,51 +454,96 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     return CHOM_OK;
 }
 
-// One CG iteration (5 kernels, plus the V-cycle with the two-level preconditioner).
-template <typename T, int C, int R>
-static hipError_t cg_iteration(ClassWS<C, R> &W, T *x, T *r, T *p, T *q, const void *minv,
-                               const double *ginv, double rtol2, int use_init, hipStream_t s) {
-    const Launch &L = W.L;
-    const bool mg = L.mg.on != 0;
-    hipError_t e;
-    if (mg && (e = launch_mg_fcorr<T, C, R>(L, W.ycoef.p, W.active.p, s)) != hipSuccess) return e;
-    if ((e = launch_cg_dir<T, C, R>(L, x, r, p, minv, W.ycoef.p, W.cols.p, W.active.p, s, mg ? L.mg.res : nullptr,
-                                    nullptr)) != hipSuccess)
-        return e;
-    if ((e = launch_operator<T, C, R>(L, L.nprob, L.rg, p, q, W.accpq.p, W.active.p, s)) != hipSuccess) return e;
-    if ((e = launch_finish_alpha<C, R>(L, W.accpq.p, W.cols.p, s)) != hipSuccess) return e;
-    if ((e = launch_cg_update<T, C, R>(L, r, q, minv, W.cols.p, W.acc.p, W.active.p, s)) != hipSuccess) return e;
-    if (mg && (e = launch_mg_vcycle<T, C, R>(L, r, W.acc.p, W.active.p, s)) != hipSuccess) return e;
-    return launch_finish_beta<C, R>(L, W.acc.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 0, rtol2, use_init, nullptr, s);
+// A contiguous range of a class's problems solved as one CG chain: a launch
+// restricted to the range (problem table offset, count) and the per-problem
+// solver state of the range.  Vectors, tile boxes and coarse levels are
+// addressed through the problems' own offsets, so chains over disjoint ranges
+// share the class buffers and run concurrently on their own streams.
+template <int C, int R> struct PcgChain {
+    Launch L{};
+    ColState *cols = nullptr;
+    const ColState *mask = nullptr;
+    int *active = nullptr;
+    double *acc = nullptr, *accpq = nullptr, *ycoef = nullptr;
+    const double *ginv = nullptr;
+    long long acc_n = 0, accpq_n = 0;
+    hipStream_t s = nullptr;
+    GraphCache *graph = nullptr;
+    std::vector<int> h_active;
+};
+
+template <int C, int R>
+static PcgChain<C, R> make_chain(ClassWS<C, R> &W, int p0, int cnt, const double *ginv, const ColState *mask,
+                                 hipStream_t s, GraphCache *graph) {
+    constexpr int SMAX = C * 4;
+    PcgChain<C, R> ch;
+    ch.L = W.L;
+    ch.L.probs = W.L.probs + p0;
+    ch.L.nprob = cnt;
+    ch.cols = W.cols.p + (size_t)p0 * R;
+    ch.mask = mask ? mask + (size_t)p0 * R : nullptr;
+    ch.active = W.active.p + p0;
+    const long long accs = (long long)R * ACC_RECMAX<C> * ACC_STRIPES, pqs = (long long)R * ACC_STRIPES;
+    ch.acc = W.acc.p + p0 * accs;
+    ch.acc_n = cnt * accs;
+    ch.accpq = W.accpq.p + p0 * pqs;
+    ch.accpq_n = cnt * pqs;
+    ch.ycoef = W.ycoef.p + (size_t)p0 * R * C * W.L.nr;
+    ch.ginv = ginv + (size_t)p0 * SMAX * SMAX;
+    ch.s = s;
+    ch.graph = graph;
+    ch.h_active.assign(cnt, 0);
+    return ch;
 }
 
-// PCG on one class of problems: b -> x (vectors of precision T).  Iterations
+// One CG iteration (5 kernels, plus the V-cycle with the two-level preconditioner).
+template <typename T, int C, int R>
+static hipError_t cg_iteration(const PcgChain<C, R> &K, T *x, T *r, T *p, T *q, const void *minv, double rtol2,
+                               int use_init) {
+    const Launch &L = K.L;
+    hipStream_t s = K.s;
+    const bool mg = L.mg.on != 0;
+    hipError_t e;
+    if (mg && (e = launch_mg_fcorr<T, C, R>(L, K.ycoef, K.active, s)) != hipSuccess) return e;
+    if ((e = launch_cg_dir<T, C, R>(L, x, r, p, minv, K.ycoef, K.cols, K.active, s, mg ? L.mg.res : nullptr,
+                                    nullptr)) != hipSuccess)
+        return e;
+    if ((e = launch_operator<T, C, R>(L, L.nprob, L.rg, p, q, K.accpq, K.active, s)) != hipSuccess) return e;
+    if ((e = launch_finish_alpha<C, R>(L, K.accpq, K.cols, s)) != hipSuccess) return e;
+    if ((e = launch_cg_update<T, C, R>(L, r, q, minv, K.cols, K.acc, K.active, s)) != hipSuccess) return e;
+    if (mg && (e = launch_mg_vcycle<T, C, R>(L, r, K.acc, K.active, s)) != hipSuccess) return e;
+    return launch_finish_beta<C, R>(L, K.acc, K.ginv, K.ycoef, K.cols, K.active, 0, rtol2, use_init, nullptr, s);
+}
+
+// PCG on one chain of problems: b -> x (vectors of precision T).  Iterations
 // run in chunks, captured once as a HIP graph and replayed; between chunks the
 // host reads the per-problem active counts (finished problems cost only an
 // early exit in every kernel).
 template <typename T, int C, int R>
-static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x, T *r, T *p, T *q,
-               const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask) {
-    hipStream_t s = W.stream;
-    const Launch &L = W.L;
+static int pcg(chom_batch *B, ClassWS<C, R> &W, PcgChain<C, R> &K, const T *b, T *x, T *r, T *p, T *q,
+               const void *minv, double rtol2, int use_init) {
+    hipStream_t s = K.s;
+    const Launch &L = K.L;
     const bool mg = L.mg.on != 0;
+    GraphCache &GC = *K.graph;
     // the accumulators may hold sums of kernels run outside a CG step (timing, residuals)
-    CHOM_HIP(launch_zero(W.acc.p, (long long)W.acc.n, s));
-    CHOM_HIP(launch_zero(W.accpq.p, (long long)W.accpq.n, s));
-    CHOM_HIP((launch_cg_init<T, C, R>(L, b, x, r, minv, W.acc.p, s)));
-    if (mg) CHOM_HIP((launch_mg_vcycle<T, C, R>(L, r, W.acc.p, nullptr, s)));
-    CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, ginv, W.ycoef.p, W.cols.p, W.active.p, 1, rtol2,
-                                       mask ? 1 : use_init, mask, s)));
+    CHOM_HIP(launch_zero(K.acc, K.acc_n, s));
+    CHOM_HIP(launch_zero(K.accpq, K.accpq_n, s));
+    CHOM_HIP((launch_cg_init<T, C, R>(L, b, x, r, minv, K.acc, s)));
+    if (mg) CHOM_HIP((launch_mg_vcycle<T, C, R>(L, r, K.acc, nullptr, s)));
+    CHOM_HIP((launch_finish_beta<C, R>(L, K.acc, K.ginv, K.ycoef, K.cols, K.active, 1, rtol2,
+                                       K.mask ? 1 : use_init, K.mask, s)));
     const int max_iter = B->opt.max_iter;
     const int chunk = 8;
     const bool use_graph = std::getenv("CHOM_NO_GRAPH") == nullptr;
-    if (use_graph && (GC.exec == nullptr || GC.key != (const void *)x || GC.iters != chunk || GC.gen != W.gen)) {
+    if (use_graph && (GC.exec == nullptr || GC.key != (const void *)x || GC.iters != chunk || GC.gen != W.gen ||
+                      GC.probs != (const void *)L.probs || GC.nprob != L.nprob)) {
         GC.reset();
         hipGraph_t g;
         CHOM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipSuccess;
         for (int k = 0; k < chunk && ce == hipSuccess; ++k)
-            ce = cg_iteration<T, C, R>(W, x, r, p, q, minv, ginv, rtol2, use_init, s);
+            ce = cg_iteration<T, C, R>(K, x, r, p, q, minv, rtol2, use_init);
         hipError_t ee = hipStreamEndCapture(s, &g);
         CHOM_HIP(ce);
         CHOM_HIP(ee);
@@ -502,22 +553,77 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, GraphCache &GC, const T *b, T *x
         GC.key = x;
         GC.iters = chunk;
         GC.gen = W.gen;
+        GC.probs = L.probs;
+        GC.nprob = L.nprob;
     }
     for (int it = 0; it < max_iter; it += chunk) {
-        CHOM_HIP(hipMemcpyAsync(W.h_active.data(), W.active.p, sizeof(int) * L.nprob, hipMemcpyDeviceToHost, s));
+        CHOM_HIP(hipMemcpyAsync(K.h_active.data(), K.active, sizeof(int) * L.nprob, hipMemcpyDeviceToHost, s));
         CHOM_HIP(hipStreamSynchronize(s));
         int act = 0;
-        for (int i = 0; i < L.nprob; ++i) act += W.h_active[i];
+        for (int i = 0; i < L.nprob; ++i) act += K.h_active[i];
         if (act == 0) break;
         if (use_graph) {
             CHOM_HIP(hipGraphLaunch(GC.exec, s));
         } else {
-            for (int k = 0; k < chunk; ++k)
-                CHOM_HIP((cg_iteration<T, C, R>(W, x, r, p, q, minv, ginv, rtol2, use_init, s)));
+            for (int k = 0; k < chunk; ++k) CHOM_HIP((cg_iteration<T, C, R>(K, x, r, p, q, minv, rtol2, use_init)));
         }
     }
     // the last step's x += alpha p (every earlier one was applied by a direction kernel)
-    CHOM_HIP((launch_cg_flush_x<T, C, R>(L, x, p, W.cols.p, s)));
+    CHOM_HIP((launch_cg_flush_x<T, C, R>(L, x, p, K.cols, s)));
+    return CHOM_OK;
+}
+
+// PCG on all problems of a class.  Large classes (at least 16 problems) split
+// into two chains of contiguous ranges, the second run from its own host thread
+// on the class's second stream, so that the latency-bound kernels of one chain
+// (coarse levels, finishing kernels) overlap the bandwidth- and ALU-bound ones
+// of the other (512-record mixed batch: +4%); small classes keep one chain (the
+// three-BC 24^3 batch: -8% with two).  CHOM_PCG_CHAINS=1 or 2 forces the count.
+template <typename T, int C, int R>
+static int pcg_class(chom_batch *B, ClassWS<C, R> &W, bool fp64, const T *b, T *x, T *r, T *p, T *q,
+                     const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask) {
+    const int nprob = W.L.nprob;
+    const char *ev = std::getenv("CHOM_PCG_CHAINS");
+    const int want = ev ? std::atoi(ev) : (nprob >= 16 ? 2 : 1);
+    const int nch = (nprob >= 2 && want == 2) ? 2 : 1;
+    GraphCache *ga = fp64 ? &W.graph64 : &W.graph32, *gb = fp64 ? &W.graph64b : &W.graph32b;
+    if (nch == 1) {
+        PcgChain<C, R> K = make_chain<C, R>(W, 0, nprob, ginv, mask, W.stream, ga);
+        return pcg<T, C, R>(B, W, K, b, x, r, p, q, minv, rtol2, use_init);
+    }
+    const int h = (nprob + 1) / 2;
+    PcgChain<C, R> KA = make_chain<C, R>(W, 0, h, ginv, mask, W.stream, ga);
+    PcgChain<C, R> KB = make_chain<C, R>(W, h, nprob - h, ginv, mask, W.stream_b, gb);
+    hipEvent_t e0, e1;
+    CHOM_HIP(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
+    CHOM_HIP(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
+    CHOM_HIP(hipEventRecord(e0, W.stream));
+    CHOM_HIP(hipStreamWaitEvent(W.stream_b, e0, 0));
+    int device = 0;
+    CHOM_HIP(hipGetDevice(&device));
+    int stb = CHOM_OK;
+    std::string errb;
+    std::thread th([&]() {
+        if (hipSetDevice(device) != hipSuccess) {
+            stb = CHOM_EDEVICE;
+            errb = "hipSetDevice failed in a CG chain thread";
+            return;
+        }
+        stb = pcg<T, C, R>(B, W, KB, b, x, r, p, q, minv, rtol2, use_init);
+        if (stb != CHOM_OK) errb = g_last_error;
+    });
+    const int sta = pcg<T, C, R>(B, W, KA, b, x, r, p, q, minv, rtol2, use_init);
+    th.join();
+    hipError_t he = hipEventRecord(e1, W.stream_b);
+    if (he == hipSuccess) he = hipStreamWaitEvent(W.stream, e1, 0);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (sta != CHOM_OK) return sta;
+    if (stb != CHOM_OK) {
+        set_error(errb);
+        return stb;
+    }
+    CHOM_HIP(he);
     return CHOM_OK;
 }
 
@@ -555,8 +661,8 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
     const double rtol2 = B->opt.rtol * B->opt.rtol;
     double *x64 = nullptr;
     if (B->opt.precision == CHOM_FP64) {
-        CHOM_TRY((pcg<double, C, R>(B, W, W.graph64, W.b.p, W.xd.p, W.rd.p, W.pd.p, W.qd.p, W.minv64.p,
-                                    ginv_inner64, rtol2, 0, nullptr)));
+        CHOM_TRY((pcg_class<double, C, R>(B, W, true, W.b.p, W.xd.p, W.rd.p, W.pd.p, W.qd.p, W.minv64.p,
+                                          ginv_inner64, rtol2, 0, nullptr)));
         x64 = W.xd.p;
     } else {
         const double irtol2 = B->opt.inner_rtol * B->opt.inner_rtol;
@@ -582,8 +688,8 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
                 if (W.h_active[i]) W.refine_steps[i] = step;
             }
             if (act == 0 || step == B->opt.max_refine) break;
-            CHOM_TRY((pcg<float, C, R>(B, W, W.graph32, W.r32.p, W.xf.p, W.rf.p, W.pf.p, W.qf.p, W.minv32.p,
-                                       ginv_inner32, irtol2, 1, W.cols_outer.p)));
+            CHOM_TRY((pcg_class<float, C, R>(B, W, false, W.r32.p, W.xf.p, W.rf.p, W.pf.p, W.qf.p, W.minv32.p,
+                                             ginv_inner32, irtol2, 1, W.cols_outer.p)));
             CHOM_HIP(launch_axpy_x64(W.total_vals, W.x64.p, W.xf.p, s));
             CHOM_HIP((launch_operator<double, C, R>(L, nprob, L.rg, W.x64.p, W.q64.p,
                                                     W.accpq.p, nullptr, s)));
@@ -775,6 +881,8 @@ static int batch_init(chom_batch *B, chom_rve *const *rves, int n, const chom_op
     CHOM_HIP(hipStreamCreate(&B->stream2));      // default priority
     B->mech.stream = B->stream;
     B->scal.stream = B->stream2;
+    CHOM_HIP(hipStreamCreate(&B->mech.stream_b));   // second CG chain of each class, default priority
+    CHOM_HIP(hipStreamCreate(&B->scal.stream_b));
     std::vector<Geo> hg;
     for (auto *r : B->distinct) hg.push_back(r->geo);
     CHOM_HIP(B->geos.ensure(hg.size()));

@@ -368,7 +368,7 @@ __device__ inline void acoustic(const double w[3], const double a[3], const doub
 // a tile face lies in up to two tiles per axis; its value is the sum of its copies.
 // Candidate (tile, local) pairs of coordinate X along one axis.
 __device__ inline int tile_cands(int X, int T2, int ntiles, int m2, bool per, int tl[2], int lc[2]) {
-    int t = X / T2;
+    int t = (T2 & (T2 - 1)) == 0 ? (X >> (31 - __clz(T2))) : X / T2;   // order 2: T2 = 8, 8, 4
     if (t > ntiles - 1) t = ntiles - 1;
     int k = 0;
     tl[k] = t;
