@@ -252,10 +252,70 @@ __global__ void mg_assemble0_kernel(const Geo *geos, const Prob *probs, double *
     }
 }
 
-// Level l + 1 from level l: A_c[I][s] = sum_{i child of I} sum_{j fine neighbour of i,
-// J parent of j, J = I + offset(s)} w_iI A_f[i][j] w_jJ.  Coordinates stay unwrapped
-// (geometric) until a level array is indexed, so a coupling is credited to the slot
-// of its geometric offset.
+// Galerkin product on nested Kuhn grids in relative form: the fine children of
+// a coarse point sit at 2 I + o_m (the 15 stencil offsets o_m, weight 1 for the
+// point itself, 1/2 for an edge midpoint) and a fine neighbour 2 I + o_m + o_q
+// prolongs from its even parent(s); which (m, q) pairs reach coarse slot s, and
+// with which weight, does not depend on I.  The pairs (421 over the 15 slots)
+// are tabulated at compile time.
+struct RapTable {
+    int start[MG_SLOTS + 1];
+    int code[448];   // m | q << 4 | wcode << 8 (weight 1, 1/2, 1/4 for wcode 0, 1, 2)
+};
+constexpr int rap_off(int k, int d) {
+    constexpr int ox[8] = {0, 1, 0, 0, 1, 1, 0, 1}, oy[8] = {0, 0, 1, 0, 1, 0, 1, 1}, oz[8] = {0, 0, 0, 1, 0, 1, 1, 1};
+    const int b = k < 8 ? k : k - 7, sg = k < 8 ? 1 : -1;
+    return sg * (d == 0 ? ox[b] : d == 1 ? oy[b] : oz[b]);
+}
+constexpr int rap_half(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }   // floor(v / 2)
+constexpr RapTable make_rap_table() {
+    RapTable t{};
+    int n = 0;
+    for (int s = 0; s < MG_SLOTS; ++s) {
+        t.start[s] = n;
+        for (int m = 0; m < MG_SLOTS; ++m)
+            for (int q = 0; q < MG_SLOTS; ++q) {
+                int g[3] = {0, 0, 0}, par[3] = {0, 0, 0}, d[3] = {0, 0, 0};
+                bool even = true;
+                for (int a = 0; a < 3; ++a) {
+                    g[a] = rap_off(m, a) + rap_off(q, a);
+                    par[a] = g[a] & 1;
+                    d[a] = rap_off(s, a);
+                    if (par[a]) even = false;
+                }
+                int w2 = 0;   // wj in halves
+                if (even) {
+                    bool hit = true;
+                    for (int a = 0; a < 3; ++a) hit = hit && rap_half(g[a]) == d[a];
+                    if (hit) w2 = 2;
+                } else {
+                    bool lo = true, hi = true;
+                    for (int a = 0; a < 3; ++a) {
+                        lo = lo && rap_half(g[a] - par[a]) == d[a];
+                        hi = hi && rap_half(g[a] + par[a]) == d[a];
+                    }
+                    w2 = (lo ? 1 : 0) + (hi ? 1 : 0);
+                }
+                if (w2 == 0) continue;
+                // w = wi * wj, wi = 1 (m = 0) or 1/2; wj = w2 / 2
+                const int wcode = (m == 0 ? 0 : 1) + (w2 == 2 ? 0 : 1);
+                t.code[n++] = m | (q << 4) | (wcode << 8);
+            }
+    }
+    t.start[MG_SLOTS] = n;
+    return t;
+}
+__constant__ RapTable c_rap = make_rap_table();
+static_assert(make_rap_table().start[MG_SLOTS] == 421, "Galerkin pair count of the 15-point Kuhn stencil");
+
+// Level l + 1 from level l: A_c[I][s] = sum_{i child of I} sum_{j fine neighbour
+// of i, J parent of j, J = I + offset(s)} w_iI A_f[i][j] w_jJ.  Coordinates stay
+// unwrapped (geometric) until a level array is indexed, so a coupling is credited
+// to the slot of its geometric offset.
+// Work item (slot, coarse point), slot-major so a wave walks one slot's pairs;
+// every pair's block is loaded unconditionally (an absent or boundary child
+// weighs 0 and reads the point's own block), so the loads of consecutive pairs
+// are in flight together.
 template <int C>
 __global__ void mg_rap_kernel(const Geo *geos, const Prob *probs, int l, double *A64) {
     constexpr int CC = C * C;
@@ -268,8 +328,8 @@ __global__ void mg_rap_kernel(const Geo *geos, const Prob *probs, int l, double 
     double *Ac = A64 + (P.moff + Cv.off) * MG_SLOTS * CC;
     for (long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x; u < npc * MG_SLOTS;
          u += (long long)gridDim.x * blockDim.x) {
-        const long long pt = u / MG_SLOTS;
-        const int s = (int)(u - pt * MG_SLOTS);
+        const int s = (int)(u / npc);
+        const long long pt = u - s * npc;
         int I, Jy, K, dx, dy, dz;
         lev_xyz(Cv, pt, I, Jy, K);
         kuhn_offset(s, dx, dy, dz);
@@ -280,35 +340,24 @@ __global__ void mg_rap_kernel(const Geo *geos, const Prob *probs, int l, double 
         const bool ok = lev_index(Cv, TX, TY, TZ) >= 0 && !lev_boundary(Cv, I, Jy, K) &&
                         !lev_boundary(Cv, TX, TY, TZ);
         if (ok) {
-            for (int m = 0; m < MG_SLOTS; ++m) {
+            const int e1 = c_rap.start[s + 1];
+#pragma unroll 4
+            for (int e = c_rap.start[s]; e < e1; ++e) {
+                const int code = c_rap.code[e];
+                const int m = code & 15, q = (code >> 4) & 15, wc = code >> 8;
                 int ox, oy, oz;
                 kuhn_offset(m, ox, oy, oz);
                 const int fi = 2 * I + ox, fj = 2 * Jy + oy, fk = 2 * K + oz;   // child (unwrapped)
-                const long long fidx = lev_index(F, fi, fj, fk);
-                if (fidx < 0 || lev_boundary(F, fi, fj, fk)) continue;
-                const double wi = (m == 0) ? 1.0 : 0.5;
-                for (int q = 0; q < MG_SLOTS; ++q) {
-                    int qx, qy, qz;
-                    kuhn_offset(q, qx, qy, qz);
-                    const int gx = fi + qx, gy = fj + qy, gz = fk + qz;   // fine neighbour (unwrapped)
-                    const int px = gx & 1, py = gy & 1, pz = gz & 1;
-                    double wj = 0.0;
-                    if (px == 0 && py == 0 && pz == 0) {
-                        if ((gx >> 1) == TX && (gy >> 1) == TY && (gz >> 1) == TZ) wj = 1.0;
-                    } else {
-                        if (((gx - px) >> 1) == TX && ((gy - py) >> 1) == TY && ((gz - pz) >> 1) == TZ) wj += 0.5;
-                        if (((gx + px) >> 1) == TX && ((gy + py) >> 1) == TY && ((gz + pz) >> 1) == TZ) wj += 0.5;
-                    }
-                    if (wj == 0.0) continue;
-                    const double *blk = Af + (fidx * MG_SLOTS + q) * CC;
-                    const double w = wi * wj;
+                const long long f0 = lev_index(F, fi, fj, fk);
+                const bool live = f0 >= 0 && !lev_boundary(F, fi, fj, fk);
+                const double w = live ? (wc == 0 ? 1.0 : wc == 1 ? 0.5 : 0.25) : 0.0;
+                const double *blk = Af + ((live ? f0 : 0) * MG_SLOTS + q) * CC;
 #pragma unroll
-                    for (int e = 0; e < CC; ++e) acc[e] += w * blk[e];
-                }
+                for (int c = 0; c < CC; ++c) acc[c] += w * blk[c];
             }
         }
 #pragma unroll
-        for (int e = 0; e < CC; ++e) Ac[(pt * MG_SLOTS + s) * CC + e] = acc[e];
+        for (int c = 0; c < CC; ++c) Ac[(pt * MG_SLOTS + s) * CC + c] = acc[c];
     }
 }
 
