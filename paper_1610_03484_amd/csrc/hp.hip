@@ -403,10 +403,23 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
     constexpr int NCP = NT * 16;
     constexpr int NW = HP_THREADS / 64;
     using V4 = typename Mfma<T>::v4;
-    __shared__ T xb[BP * RC];
-    __shared__ double yb[BP * RC];
-    __shared__ T xs[KA][NCP];
-    __shared__ T gs[MA][NCP];
+    // LDS shared by phases: X (xs) is dead once G is formed, so the output box
+    // yb takes its place (cleared after the G product; the element energies are
+    // formed from the box at write-back).  At order 4 the staged box xb is also
+    // dead once X is built and G/H (gs) take its place (x for the energies is
+    // then read again from memory): 50 instead of 75 KB, three workgroups per CU.
+    constexpr bool XB_IN_GS = P >= 4;
+    constexpr int GSB = (int)(MA * NCP * sizeof(T)), XBB = (int)(BP * RC * sizeof(T));
+    constexpr int U1 = XB_IN_GS ? (XBB > GSB ? XBB : GSB) : GSB;
+    constexpr int U2 = (int)(KA * NCP * sizeof(T) > BP * RC * sizeof(double) ? KA * NCP * sizeof(T)
+                                                                           : BP * RC * sizeof(double));
+    __shared__ __align__(16) unsigned char u1[U1];
+    __shared__ __align__(16) unsigned char u2[U2];
+    __shared__ __align__(16) unsigned char u0[XB_IN_GS ? 16 : XBB];
+    T *const xb = XB_IN_GS ? (T *)u1 : (T *)u0;
+    T(*const gs)[NCP] = (T(*)[NCP])u1;
+    T(*const xs)[NCP] = (T(*)[NCP])u2;
+    double *const yb = (double *)u2;
     __shared__ T qs[EB][3 * C][3 * C];
     __shared__ int bidx[EB][NE];
     __shared__ double red[R][NW];
@@ -426,7 +439,6 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
         const int bx = pt % B1, by = (pt / B1) % B1, bz = pt / (B1 * B1);
         const long long idx = lat_index(G, P * ci + bx, P * cj + by, P * ck + bz);
         xb[i] = xp[((long long)r * G.npts + idx) * C + c];
-        yb[i] = 0.0;
     }
     for (int i = tid; i < EB * NE; i += HP_THREADS) {
         const int e = i / NE, q = i - (i / NE) * NE;
@@ -486,6 +498,7 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
         }
     }
     __syncthreads();
+    for (int i = tid; i < BP * RC; i += HP_THREADS) yb[i] = 0.0;   // X is dead: its space holds the output box
     // ---- H = sum_l Q^{kl} G_l, in place (rows k*M + a)
     for (int i = tid; i < M * EB * R; i += HP_THREADS) {
         const int a = i % M, er = i / M;
@@ -531,8 +544,6 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
             const int col = ct * 16 + lr;
             if (col >= NC) continue;
             const int e = col / RC, rem = col - (col / RC) * RC;
-            const int r = rem / C;
-            double en = 0.0;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -540,20 +551,30 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
                     const int i = mt * 16 + Mfma<T>::row(lk, q);
                     if (i >= NE) continue;
                     atomicAdd(&yb[bidx[e][i] * RC + rem], (double)acc[mt][q]);
-                    en += (double)xs[i][col] * (double)acc[mt][q];
                 }
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr)
-                if (rr == r) pq[rr] += en;
         }
     }
     __syncthreads();
-    // ---- write the cell's box (contiguous)
+    // ---- write the cell's box (contiguous); the cell's energies x_e . K_e x_e
+    // summed over its tets are x . y over its box (x read again, cached)
     T *yt = y + Pb.qoff + (long long)cell * BP * RC;
     for (int i = tid; i < BP * RC; i += HP_THREADS) {   // load-case major: i = (r * BP + pt) * C + c
         const int r = i / (BP * C), rem = i - r * (BP * C);
         const int pt = rem / C, c = rem - (rem / C) * C;
-        yt[i] = (T)yb[pt * RC + r * C + c];
+        const double v = yb[pt * RC + r * C + c];
+        yt[i] = (T)v;
+        double xv;
+        if constexpr (XB_IN_GS) {
+            const int bx = pt % B1, by = (pt / B1) % B1, bz = pt / (B1 * B1);
+            const long long idx = lat_index(G, P * ci + bx, P * cj + by, P * ck + bz);
+            xv = (double)xp[((long long)r * G.npts + idx) * C + c];
+        } else {
+            xv = (double)xb[pt * RC + r * C + c];
+        }
+        const double en = xv * v;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+            if (rr == r) pq[rr] += en;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
