@@ -28,32 +28,35 @@
 namespace chom {
 
 // Partial record of this wave: slot `slot` of `stride` slots per entry.
-__device__ inline void wave_partials(const double *acc, int REC, double *partial, int prob, int R, int w,
-                                     int stride, int slot) {
+template <int REC>
+__device__ inline void wave_partials(double *acc, double *partial, int prob, int R, int w, int stride, int slot) {
     const int lane = threadIdx.x & 63;
-    for (int k = 0; k < REC; ++k) {
-        const double s = wave_sum(acc[k]);
-        if (lane == 0) partial[(((long long)prob * R + w) * REC + k) * stride + slot] = s;
+    wave_sums<REC>(acc);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < REC; ++k) partial[(((long long)prob * R + w) * REC + k) * stride + slot] = acc[k];
     }
 }
-__device__ inline void wave_partials(const double *acc, int REC, double *partial, int prob, int R, int w) {
-    wave_partials(acc, REC, partial, prob, R, w, gridDim.x, blockIdx.x);
+template <int REC>
+__device__ inline void wave_partials(double *acc, double *partial, int prob, int R, int w) {
+    wave_partials<REC>(acc, partial, prob, R, w, gridDim.x, blockIdx.x);
 }
 
 // Adds this wave's record to the striped accumulators of its column (see ACC_STRIPES).
-template <int C>
-__device__ inline void wave_accum(const double *acc, int REC, double *accbuf, int prob, int R, int w) {
+template <int C, int REC>
+__device__ inline void wave_accum(double *acc, double *accbuf, int prob, int R, int w) {
     const int lane = threadIdx.x & 63;
     const int stripe = blockIdx.x & (ACC_STRIPES - 1);
-    for (int k = 0; k < REC; ++k) {
-        const double s = wave_sum(acc[k]);
-        if (lane == 0) unsafeAtomicAdd(&accbuf[acc_index<C>(prob, R, w, k, stripe)], s);
+    wave_sums<REC>(acc);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < REC; ++k) unsafeAtomicAdd(&accbuf[acc_index<C>(prob, R, w, k, stripe)], acc[k]);
     }
 }
 
 // r = b, x = 0; partial sums of r, z0 = M^-1 r.  WRITE = false: only the sums.
 template <typename T, int C, int R, int NR, bool WRITE>
-__global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const Prob *probs, const T *b, T *x,
+__global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *__restrict__ geos, const Prob *__restrict__ probs, const T *b, T *x,
                                                          T *r, const T *minv, double *accbuf) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int REC = 2 + C * NR;
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const 
             for (int a = 0; a < NR; ++a) acc[2 + c * NR + a] += row[a] * (double)zv[c];
         }
     }
-    wave_accum<C>(acc, REC, accbuf, prob, R, w);
+    wave_accum<C, REC>(acc, accbuf, prob, R, w);
 }
 
 // x += alpha p (the step length of the previous iteration, applied here while
@@ -105,7 +108,7 @@ __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *geos, const 
 // mg_fcorr_kernel), Q = P_0 P_1 (P_0 injects vertex values, P_1 interpolates
 // from the n/2 grid).
 template <typename T, int C, int R, int NR>
-__global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const Prob *probs, T *x, T *r, T *p,
+__global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *__restrict__ geos, const Prob *__restrict__ probs, T *x, T *r, T *p,
                                                         const T *minv, const double *ycoef,
                                                         const ColState *cols, const int *prob_active,
                                                         MgDir<T> mg) {
@@ -131,28 +134,54 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
         const long long pt = blk * 64 + lane;
         if (pt >= G.npts) continue;
         const long long o = P.voff + (w * G.npts + pt) * C;
-        T pv[C];
+        // every load that does not depend on another is issued before any use
+        // (alpha, beta and active are uniform over the wave)
+        T pv[C], xv[C], rv[C], Mi[MS];
+        double row[4] = {0.0, 0.0, 0.0, 0.0};
         if (alpha != 0.0 || beta != 0.0) {
 #pragma unroll
             for (int c = 0; c < C; ++c) pv[c] = p[o + c];
         }
         if (alpha != 0.0) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) xv[c] = x[o + c];
+        }
+        long long J0 = -1, J1 = -1;
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) rv[c] = r[o + c];
+#pragma unroll
+            for (int k = 0; k < MS; ++k) Mi[k] = Mp[pt * MS + k];
+            if (proj) load_rows<NR>(G, pt, row);
+            if (mg.on && G.mg_nlev > 0) {
+                int X, Y, Z;
+                lattice_xyz(G, pt, X, Y, Z);
+                const int pp = G.p;
+                if (X % pp == 0 && Y % pp == 0 && Z % pp == 0) {
+                    // vertex (i, j, k): f at its level-1 parents (itself halved, or the two
+                    // ends of the level-1 Kuhn edge whose midpoint it is), averaged
+                    const int lw0 = G.mg_lw[0];
+                    const long long v = X / pp + (long long)lw0 * (Y / pp + (long long)lw0 * (Z / pp));
+                    const int *pa = G.mg_par + (G.mg_off[0] + v) * 16;
+                    J0 = pa[0];
+                    J1 = pa[1];
+                }
+            }
+        }
+        if (alpha != 0.0) {
             const T al = (T)alpha;
 #pragma unroll
-            for (int c = 0; c < C; ++c) x[o + c] += al * pv[c];
+            for (int c = 0; c < C; ++c) x[o + c] = xv[c] + al * pv[c];
         }
         if (!active) continue;
-        T rv[C], zv[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) rv[c] = r[o + c];
-        minv_apply<T, C>(Mp + pt * MS, rv, zv);   // z0 = M^-1 r, as in the update kernel's sums
+        T zv[C];
+        minv_apply<T, C>(Mi, rv, zv);   // z0 = M^-1 r, as in the update kernel's sums
         if constexpr (NR > 0) {
             if (proj) {
                 // projection correction M^-1 C^T y evaluated in FP64
-                double Md[MS], ct[C], corr[C], row[4];
+                double Md[MS], ct[C], corr[C];
 #pragma unroll
-                for (int k = 0; k < MS; ++k) Md[k] = (double)Mp[pt * MS + k];
-                load_rows<NR>(G, pt, row);
+                for (int k = 0; k < MS; ++k) Md[k] = (double)Mi[k];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     ct[c] = 0.0;
@@ -167,21 +196,10 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
                 }
             }
         }
-        if (mg.on && G.mg_nlev > 0) {
-            int X, Y, Z;
-            lattice_xyz(G, pt, X, Y, Z);
-            const int pp = G.p;
-            if (X % pp == 0 && Y % pp == 0 && Z % pp == 0) {
-                // vertex (i, j, k): f at its level-1 parents (itself halved, or the two
-                // ends of the level-1 Kuhn edge whose midpoint it is), averaged
-                const int lw0 = G.mg_lw[0];
-                const long long v = X / pp + (long long)lw0 * (Y / pp + (long long)lw0 * (Z / pp));
-                const int *pa = G.mg_par + (G.mg_off[0] + v) * 16;
-                const long long J0 = pa[0], J1 = pa[1];
-                const T *f = mg.x0 + (P.moff * R + (long long)w * G.mg_pts + G.mg_off[1]) * C;
+        if (J0 >= 0) {
+            const T *f = mg.x0 + (P.moff * R + (long long)w * G.mg_pts + G.mg_off[1]) * C;
 #pragma unroll
-                for (int c = 0; c < C; ++c) zv[c] += T(0.5) * (f[J0 * C + c] + f[J1 * C + c]);
-            }
+            for (int c = 0; c < C; ++c) zv[c] += T(0.5) * (f[J0 * C + c] + f[J1 * C + c]);
         }
         if (beta == 0.0) {   // first step (p not yet defined) or finished column
 #pragma unroll
@@ -198,7 +216,7 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *geos, const P
 // and z0 = M^-1 r (z0 itself is formed again by the direction kernel, which
 // reads r anyway; x += alpha p is deferred to the next direction kernel).
 template <typename T, int C, int R, int NR>
-__global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, const Prob *probs, int rg, T *r,
+__global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *__restrict__ geos, const Prob *__restrict__ probs, int rg, T *r,
                                                            const T *q, const T *minv,
                                                            const ColState *cols, double *accbuf,
                                                            const int *prob_active) {
@@ -219,6 +237,15 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
     for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const long long pt = blk * 64 + lane;
         if (pt >= G.npts) continue;
+        // the point's own loads first, then the gather: all in flight together
+        const long long o = P.voff + (w * G.npts + pt) * C;
+        T Mi[MS], rv[C], zv[C];
+#pragma unroll
+        for (int k = 0; k < MS; ++k) Mi[k] = Mp[pt * MS + k];
+#pragma unroll
+        for (int c = 0; c < C; ++c) rv[c] = r[o + c];
+        double row[4];
+        load_rows<NR>(G, pt, row);
         int X, Y, Z;
         lattice_xyz(G, pt, X, Y, Z);
         double qv[C];
@@ -228,16 +255,9 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
         } else {
             gather_tiles_col<T, C, R>(G, qt, rg, X, Y, Z, w, qv);
         }
-        T Mi[MS];
-#pragma unroll
-        for (int k = 0; k < MS; ++k) Mi[k] = Mp[pt * MS + k];
-        double row[4];
-        load_rows<NR>(G, pt, row);
-        const long long o = P.voff + (w * G.npts + pt) * C;
-        T rv[C], zv[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            rv[c] = r[o + c] - al * (T)qv[c];
+            rv[c] = rv[c] - al * (T)qv[c];
             r[o + c] = rv[c];
         }
         minv_apply<T, C>(Mi, rv, zv);
@@ -249,7 +269,7 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *geos, cons
             for (int a = 0; a < NR; ++a) acc[2 + c * NR + a] += row[a] * (double)zv[c];
         }
     }
-    wave_accum<C>(acc, REC, accbuf, prob, R, w);
+    wave_accum<C, REC>(acc, accbuf, prob, R, w);
 }
 
 // x += alpha p with the pending step length of each column (after the last CG
@@ -280,7 +300,7 @@ __global__ __launch_bounds__(64 * R) void cg_flush_x_kernel(const Geo *geos, con
 // projected vector keeps the multiplier forces of the exact solution out of
 // the FP64 stopping test.
 template <int C, int R, int NR>
-__global__ __launch_bounds__(64 * R) void proj_resid_kernel(const Geo *geos, const Prob *probs, double *r64,
+__global__ __launch_bounds__(64 * R) void proj_resid_kernel(const Geo *__restrict__ geos, const Prob *__restrict__ probs, double *r64,
                                                             float *r32, const double *minv64,
                                                             const double *ycoef, double *accbuf) {
     constexpr int MS = (C == 3) ? 6 : 1;
@@ -326,7 +346,7 @@ __global__ __launch_bounds__(64 * R) void proj_resid_kernel(const Geo *geos, con
             for (int a = 0; a < NR; ++a) acc[2 + c * NR + a] += row[a] * zv[c];
         }
     }
-    wave_accum<C>(acc, REC, accbuf, prob, R, w);
+    wave_accum<C, REC>(acc, accbuf, prob, R, w);
 }
 
 // Sum of part[k][0..nparts) for k in [0, K) into sums[k]; wave q takes
@@ -605,7 +625,7 @@ __global__ void cx_partial_kernel(const Geo *geos, const Prob *probs, const doub
             for (int c = 0; c < C; ++c) acc[c * 4 + a] += rw * x[o + c];
         }
     }
-    wave_partials(acc, S4, partial, prob, R, w);
+    wave_partials<S4>(acc, partial, prob, R, w);
 }
 
 template <int C, int R>

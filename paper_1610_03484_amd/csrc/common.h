@@ -399,17 +399,34 @@ __device__ inline void gather_tiles_col(const Geo &G, const T *qt, int rg, int X
     const int nx = tile_cands(X, G.p * G.tcx, G.tiles_x, m2, per, tx, lx);
     const int ny = tile_cands(Y, G.p * G.tcy, G.tiles_y, m2, per, ty, ly);
     const int nz = tile_cands(Z, G.p * G.tcz, G.tiles_z, m2, per, tz, lz);
+    // all (up to eight) copies are loaded before any is summed, so their
+    // latencies overlap (zeroed first: no register write waits on a load)
+    T cp[8][C];
 #pragma unroll
-    for (int v = 0; v < C; ++v) out[v] = 0.0;
-    for (int a = 0; a < nx; ++a)
-        for (int b = 0; b < ny; ++b)
-            for (int c = 0; c < nz; ++c) {
-                const long long tile = tx[a] + (long long)G.tiles_x * (ty[b] + (long long)G.tiles_y * tz[c]);
-                const long long off =
-                    (((tile * ng + grp) * rg + rr) * G.boxpts + lx[a] + G.bx * (ly[b] + G.by * lz[c])) * C;
+    for (int k = 0; k < 8; ++k)
 #pragma unroll
-                for (int v = 0; v < C; ++v) out[v] += (double)qt[off + v];
+        for (int v = 0; v < C; ++v) cp[k][v] = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (a < nx && b < ny && c < nz) {
+                    const long long tile = tx[a] + (long long)G.tiles_x * (ty[b] + (long long)G.tiles_y * tz[c]);
+                    const long long off =
+                        (((tile * ng + grp) * rg + rr) * G.boxpts + lx[a] + G.bx * (ly[b] + G.by * lz[c])) * C;
+#pragma unroll
+                    for (int v = 0; v < C; ++v) cp[4 * a + 2 * b + c][v] = qt[off + v];
+                }
             }
+#pragma unroll
+    for (int v = 0; v < C; ++v) {
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += (double)cp[k][v];
+        out[v] = sum;
+    }
 }
 
 // Lattice coordinates of point pt (32-bit arithmetic: a lattice holds fewer than 2^31 points).
@@ -438,9 +455,20 @@ template <int NR>
 __device__ inline void load_rows(const Geo &G, long long pt, double row[4]) {
     row[0] = row[1] = row[2] = row[3] = 0.0;
     if constexpr (NR > 0) {
-        const int nr = G.nrow < NR ? G.nrow : NR;
-        const int rf = row_first(G.nrow);
-        for (int a = 0; a < nr; ++a) row[a] = G.rows[4 * pt + rf + a];
+        if (G.nrow > 0) {
+            // the point's four row values in one 32-byte access (rows is 256-byte aligned)
+            const double4 v = reinterpret_cast<const double4 *>(G.rows)[pt];
+            if (G.nrow == 1) {   // periodic: int(phi) only (row_first)
+                row[0] = v.w;
+            } else {
+                row[0] = v.x;
+                if constexpr (NR >= 4) {
+                    row[1] = v.y;
+                    row[2] = v.z;
+                    row[3] = v.w;
+                }
+            }
+        }
     }
 }
 
@@ -514,6 +542,20 @@ __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Wavefront sums of N doubles at once (every lane ends with the totals): the N
+// butterflies advance in step, so each exchange round waits once for all N.
+template <int N>
+__device__ inline void wave_sums(double v[N]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double t[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) t[k] = __shfl_xor(v[k], off, 64);
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += t[k];
+    }
 }
 
 }  // namespace chom
