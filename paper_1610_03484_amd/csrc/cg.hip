@@ -416,6 +416,7 @@ __global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const
     __shared__ double vals[R * RECMAX * ACC_STRIPES];
     __shared__ double sums[R * RECMAX];
     __shared__ double sG[SMAX * SMAX];
+    __shared__ double sy[R * SMAX];
     __shared__ int sdone[R];
     double *base = accbuf + (long long)prob * R * RECMAX * ACC_STRIPES;
     for (int t = lane; t < R * RECMAX * ACC_STRIPES; t += blockDim.x) {
@@ -423,6 +424,8 @@ __global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const
         base[t] = 0.0;
     }
     for (int k = lane; k < S * S; k += blockDim.x) sG[k] = ginv[(long long)prob * SMAX * SMAX + k];
+    // coefficients of rows the problem does not have stay zero
+    for (int k = lane; k < R * C * NR; k += blockDim.x) ycoef[(long long)prob * R * C * NR + k] = 0.0;
     __syncthreads();
     for (int e = lane; e < R * RECMAX; e += blockDim.x) {
         double v = 0.0;
@@ -430,24 +433,23 @@ __global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const
         sums[e] = v;
     }
     __syncthreads();
+    // y = (C M^-1 C^T)^-1 c: one thread per (load case, row) entry
+    if (lane < R * S) {
+        const int w = lane / S, I = lane - (lane / S) * S;
+        const double *rec = &sums[w * RECMAX];
+        double t = 0.0;
+        for (int J = 0; J < S; ++J) t += sG[I * S + J] * rec[2 + (J / nrow) * NR + (J % nrow)];
+        sy[w * SMAX + I] = t;
+        ycoef[((long long)prob * R + w) * C * NR + (I / nrow) * NR + (I % nrow)] = t;
+    }
+    __syncthreads();
     if (lane < R) {
         ColState &cs = cols[prob * R + lane];
         const double *rec = &sums[lane * RECMAX];
         double rz = rec[0];
         if (S > 0) {
-            double c[SMAX];
-            for (int i = 0; i < C; ++i)
-                for (int a = 0; a < nrow; ++a) c[i * nrow + a] = rec[2 + i * NR + a];
-            const double *Gi = sG;
-            double *yv = ycoef + ((long long)prob * R + lane) * C * NR;
-            for (int k = 0; k < C * NR; ++k) yv[k] = 0.0;
             double cy = 0.0;
-            for (int I = 0; I < S; ++I) {
-                double t = 0.0;
-                for (int J = 0; J < S; ++J) t += Gi[I * S + J] * c[J];
-                yv[(I / nrow) * NR + (I % nrow)] = t;
-                cy += c[I] * t;
-            }
+            for (int I = 0; I < S; ++I) cy += rec[2 + (I / nrow) * NR + (I % nrow)] * sy[lane * SMAX + I];
             rz -= cy;
         }
         if (rz < 0.0) rz = 0.0;
