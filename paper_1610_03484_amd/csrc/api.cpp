@@ -256,6 +256,8 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     const bool want_mg = B->opt.precond == CHOM_PRECOND_TWO_LEVEL;
     for (auto &P : hp) {
         const Geo &G = B->distinct[P.geo]->geo;
+        // the vector kernels index one problem's tile boxes with 32-bit offsets
+        if ((long long)G.ntiles * G.boxpts * R * C > 0x7fffffffLL) return CHOM_EINVAL;
         P.voff = voff;
         P.doff = doff;
         P.qoff = qoff;

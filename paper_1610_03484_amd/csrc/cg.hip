@@ -31,11 +31,9 @@ namespace chom {
 template <int REC>
 __device__ inline void wave_partials(double *acc, double *partial, int prob, int R, int w, int stride, int slot) {
     const int lane = threadIdx.x & 63;
-    wave_sums<REC>(acc);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < REC; ++k) partial[(((long long)prob * R + w) * REC + k) * stride + slot] = acc[k];
-    }
+    int k;
+    const double s = wave_sums_spread<REC>(acc, k);
+    if (wave_spread_writer<REC>(lane) && k < REC) partial[(((long long)prob * R + w) * REC + k) * stride + slot] = s;
 }
 template <int REC>
 __device__ inline void wave_partials(double *acc, double *partial, int prob, int R, int w) {
@@ -47,11 +45,9 @@ template <int C, int REC>
 __device__ inline void wave_accum(double *acc, double *accbuf, int prob, int R, int w) {
     const int lane = threadIdx.x & 63;
     const int stripe = blockIdx.x & (ACC_STRIPES - 1);
-    wave_sums<REC>(acc);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < REC; ++k) unsafeAtomicAdd(&accbuf[acc_index<C>(prob, R, w, k, stripe)], acc[k]);
-    }
+    int k;
+    const double s = wave_sums_spread<REC>(acc, k);
+    if (wave_spread_writer<REC>(lane) && k < REC) unsafeAtomicAdd(&accbuf[acc_index<C>(prob, R, w, k, stripe)], s);
 }
 
 // r = b, x = 0; partial sums of r, z0 = M^-1 r.  WRITE = false: only the sums.

@@ -413,9 +413,9 @@ __device__ inline void gather_tiles_col(const Geo &G, const T *qt, int rg, int X
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 if (a < nx && b < ny && c < nz) {
-                    const long long tile = tx[a] + (long long)G.tiles_x * (ty[b] + (long long)G.tiles_y * tz[c]);
-                    const long long off =
-                        (((tile * ng + grp) * rg + rr) * G.boxpts + lx[a] + G.bx * (ly[b] + G.by * lz[c])) * C;
+                    // 32-bit: one problem's tile boxes hold fewer than 2^31 values (checked at setup)
+                    const int tile = tx[a] + G.tiles_x * (ty[b] + G.tiles_y * tz[c]);
+                    const int off = (((tile * ng + grp) * rg + rr) * G.boxpts + lx[a] + G.bx * (ly[b] + G.by * lz[c])) * C;
 #pragma unroll
                     for (int v = 0; v < C; ++v) cp[4 * a + 2 * b + c][v] = qt[off + v];
                 }
@@ -544,18 +544,47 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Wavefront sums of N doubles at once (every lane ends with the totals): the N
-// butterflies advance in step, so each exchange round waits once for all N.
+// Wavefront sums of N <= 16 doubles with the values spread over the lanes:
+// with M = N rounded up to a power of two, each of the first log2(M) exchange
+// rounds halves the values a lane carries (it keeps one half of them and
+// sends the other half to its partner), and the remaining rounds finish the
+// single value left.  Every entry is summed over the same pairing tree, in the
+// same operand order, as the plain butterfly, so the totals are those of
+// wave_sum bit for bit, with M - 1 + (6 - log2 M) exchanges instead of 6 N.
+// Returns this lane's total; k receives its entry, which the lanes with
+// (lane & (64 / M - 1)) == 0 hold once each (entries k >= N are padding).
 template <int N>
-__device__ inline void wave_sums(double v[N]) {
+__device__ inline double wave_sums_spread(const double *v, int &k) {
+    static_assert(N >= 1 && N <= 16, "at most 16 values");
+    constexpr int M = N <= 1 ? 1 : N <= 2 ? 2 : N <= 4 ? 4 : N <= 8 ? 8 : 16;
+    const int lane = threadIdx.x & 63;
+    double a[M];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        double t[N];
+    for (int j = 0; j < M; ++j) a[j] = j < N ? v[j] : 0.0;
+    int idx = 0, off = 32;
 #pragma unroll
-        for (int k = 0; k < N; ++k) t[k] = __shfl_xor(v[k], off, 64);
+    for (int m = M; m > 1; m >>= 1, off >>= 1) {
+        const bool hi = (lane & off) != 0;
+        const int half = m >> 1;
 #pragma unroll
-        for (int k = 0; k < N; ++k) v[k] += t[k];
+        for (int j = 0; j < half; ++j) {
+            const double send = hi ? a[j] : a[j + half];
+            const double keep = hi ? a[j + half] : a[j];
+            a[j] = keep + __shfl_xor(send, off, 64);
+        }
+        idx += hi ? half : 0;
     }
+    double s = a[0];
+#pragma unroll
+    for (; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    k = idx;
+    return s;
+}
+// Lanes that write the totals of wave_sums_spread<N>.
+template <int N>
+__device__ inline bool wave_spread_writer(int lane) {
+    constexpr int M = N <= 1 ? 1 : N <= 2 ? 2 : N <= 4 ? 4 : N <= 8 ? 8 : 16;
+    return (lane & (64 / M - 1)) == 0;
 }
 
 }  // namespace chom

@@ -684,10 +684,10 @@ __global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const
     }
     if (accbuf != nullptr) {
         const int stripe = blockIdx.x & (ACC_STRIPES - 1);
-        for (int k = 0; k < REC; ++k) {
-            const double sum = wave_sum(pacc[k]);
-            if (lane == 0 && k != 1) unsafeAtomicAdd(&accbuf[acc_index<C>(prob, R, w, k, stripe)], sum);
-        }
+        int k;
+        const double sum = wave_sums_spread<REC>(pacc, k);
+        if (wave_spread_writer<REC>(lane) && k < REC && k != 1)
+            unsafeAtomicAdd(&accbuf[acc_index<C>(prob, R, w, k, stripe)], sum);
     }
 }
 
