@@ -558,7 +558,6 @@ hipError_t launch_zero(double *p, long long n, hipStream_t s) {
 template <int C, int R>
 __global__ void residual64_kernel(const Geo *geos, const Prob *probs, int rg, const double *b, const double *q64t,
                                   double *r64, float *r32) {
-    constexpr int RC = R * C;
     const int prob = blockIdx.y;
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
@@ -567,15 +566,19 @@ __global__ void residual64_kernel(const Geo *geos, const Prob *probs, int rg, co
          pt += (long long)gridDim.x * blockDim.x) {
         int X, Y, Z;
         lattice_xyz(G, pt, X, Y, Z);
-        double qv[RC];
-        for (int v = 0; v < RC; ++v) qv[v] = 0.0;
-        if (qt != nullptr && !dirichlet_boundary(G, X, Y, Z))
-            for (int w = 0; w < R; ++w) gather_tiles_col<double, C, R>(G, qt, rg, X, Y, Z, w, qv + w * C);
-        for (int v = 0; v < RC; ++v) {
-            const long long o = P.voff + ((v / C) * G.npts + pt) * C + v % C;
-            const double val = (b ? b[o] : 0.0) - qv[v];
-            r64[o] = val;
-            if (r32) r32[o] = (float)val;
+        const bool gather = qt != nullptr && !dirichlet_boundary(G, X, Y, Z);
+        for (int w = 0; w < R; ++w) {   // one load case at a time: few live registers
+            double qv[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) qv[c] = 0.0;
+            if (gather) gather_tiles_col<double, C, R>(G, qt, rg, X, Y, Z, w, qv);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const long long o = P.voff + ((long long)w * G.npts + pt) * C + c;
+                const double val = (b ? b[o] : 0.0) - qv[c];
+                r64[o] = val;
+                if (r32) r32[o] = (float)val;
+            }
         }
     }
 }
