@@ -14,14 +14,15 @@
 namespace chom {
 
 template <int C, int R>
-__global__ void average_kernel(const Geo *geos, const Prob *probs, const double *x, double *partial) {
+__global__ __launch_bounds__(256) void average_kernel(const Geo *geos, const Prob *probs, const double *x, double *partial) {
     constexpr int NC = (C == 3) ? 6 : 3;
     const int prob = blockIdx.y;
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
     const double *xp = x + P.voff;
     const long long nt = 6LL * G.n * G.n * G.n;
-    double acc[R * NC];
+    double acc[R * NC];   // indexed with compile-time indices only (all loops over it unrolled)
+#pragma unroll
     for (int k = 0; k < R * NC; ++k) acc[k] = 0.0;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
          e += (long long)gridDim.x * blockDim.x) {
@@ -38,6 +39,7 @@ __global__ void average_kernel(const Geo *geos, const Prob *probs, const double 
         const double *m = P.mat64[ph ? 1 : 0];
         long long idx[10];
         double w[10][3];
+#pragma unroll
         for (int k = 0; k < 10; ++k) {
             idx[k] = lat_index(G, 2 * ci + off[k][0], 2 * cj + off[k][1], 2 * ck + off[k][2]);
             if (k < 4) {
@@ -48,9 +50,12 @@ __global__ void average_kernel(const Geo *geos, const Prob *probs, const double 
                 for (int d = 0; d < 3; ++d) w[k][d] = vol * (g[a2][d] + g[b2][d]);
             }
         }
+#pragma unroll
         for (int r = 0; r < R; ++r) {
             double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // int grad(u~) dV
+#pragma unroll
             for (int k = 0; k < 10; ++k)
+#pragma unroll
                 for (int c = 0; c < C; ++c) {
                     const double u = xp[(r * G.npts + idx[k]) * C + c];
                     for (int d = 0; d < 3; ++d) H[c][d] += u * w[k][d];
@@ -61,18 +66,21 @@ __global__ void average_kernel(const Geo *geos, const Prob *probs, const double 
                 if (r < 3) eps[r] += vol; else eps[r] += 0.5 * vol;
                 double s[6];
                 stress_ti<double>(eps, a, m, s);
+#pragma unroll
                 for (int k = 0; k < 6; ++k) acc[r * NC + k] += s[k];
             } else {
                 double gr[3] = {H[0][0], H[0][1], H[0][2]};
                 gr[r] += vol;
                 double q[3];
                 flux_ti<double>(gr, a, m, q);
+#pragma unroll
                 for (int k = 0; k < 3; ++k) acc[r * NC + k] += q[k];
             }
         }
     }
     __shared__ double red[R * NC][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
     for (int k = 0; k < R * NC; ++k) {
         const double v = wave_sum(acc[k]);
         if (lane == 0) red[k][wv] = v;

@@ -116,7 +116,7 @@ hipError_t launch_rows_hp(const Geo &G, double *rows, hipStream_t s) {
 
 // ------------------------------------------------------------------ block-Jacobi diagonal
 template <int P, int C>
-__global__ void hp_diag_kernel(const Geo *geos, const Prob *probs, double *diag) {
+__global__ __launch_bounds__(256) void hp_diag_kernel(const Geo *geos, const Prob *probs, double *diag) {
     constexpr int NE = Shape<P>::NE;
     constexpr int MS = (C == 3) ? 6 : 1;
     const Prob &Pb = probs[blockIdx.y];
@@ -249,7 +249,7 @@ template hipError_t launch_rhs_hp<1, 3>(const Launch &, double *, ColState *, hi
 // Partial sums per workgroup of sum_e C_e (eps_k |e| + int sym grad(u~_k)), as the
 // order-2 kernel (Eq. macro_stress, Eq. Eq_C_stress; Eq. eq_homo_flux).
 template <int P, int C, int R>
-__global__ void hp_average_kernel(const Geo *geos, const Prob *probs, const double *x, double *partial) {
+__global__ __launch_bounds__(256) void hp_average_kernel(const Geo *geos, const Prob *probs, const double *x, double *partial) {
     constexpr int NE = Shape<P>::NE;
     constexpr int NC = (C == 3) ? 6 : 3;
     const int prob = blockIdx.y;
@@ -345,7 +345,7 @@ template <> struct Mfma<double> {
 // symmetric (3C) x (3C) matrix with index (k, c) = k C + c (the survey's 45 / 6
 // numbers per element), FP64 master and FP32 copy.
 template <int C>
-__global__ void hp_factor_kernel(const Geo *geos, const Prob *probs, double *ef64, float *ef32) {
+__global__ __launch_bounds__(256) void hp_factor_kernel(const Geo *geos, const Prob *probs, double *ef64, float *ef32) {
     constexpr int NQ = (3 * C) * (3 * C + 1) / 2;
     const Prob &Pb = probs[blockIdx.y];
     const Geo &G = geos[Pb.geo];

@@ -363,7 +363,7 @@ __global__ void mg_rap_kernel(const Geo *geos, const Prob *probs, int l, double 
 
 // l1 block-Jacobi inverse of every coarse point of the class, and the T copies.
 template <int C>
-__global__ void mg_dinv_kernel(long long total, const double *A64, double *D64) {
+__global__ __launch_bounds__(MG_BS) void mg_dinv_kernel(long long total, const double *A64, double *D64) {
     constexpr int CC = C * C;
     constexpr int MS = (C == 3) ? 6 : 1;
     for (long long pt = blockIdx.x * (long long)blockDim.x + threadIdx.x; pt < total;
