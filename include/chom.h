@@ -173,7 +173,9 @@ int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc
  * D_hom [batch][6], rep [batch] (rep may be NULL; rep is always host memory).
  * Returns CHOM_ENOCONV (results written, rep.status set) if a load case hit the
  * iteration cap, CHOM_EMATERIAL if a record gives a non-positive-definite
- * material, CHOM_EINVAL / CHOM_EDEVICE / CHOM_ENOMEM otherwise. */
+ * material, CHOM_EINVAL / CHOM_EDEVICE / CHOM_ENOMEM otherwise (CHOM_EINVAL
+ * also for an RVE whose operator tile boxes exceed 2^31 values for one problem,
+ * far beyond device memory for any supported order). */
 int chom_homogenise(chom_rve *rve, const chom_params *params, int32_t batch,
                     double *C_hom, double *K_hom, double *D_hom, chom_report *rep);
 

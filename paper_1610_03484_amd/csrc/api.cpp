@@ -257,7 +257,10 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     for (auto &P : hp) {
         const Geo &G = B->distinct[P.geo]->geo;
         // the vector kernels index one problem's tile boxes with 32-bit offsets
-        if ((long long)G.ntiles * G.boxpts * R * C > 0x7fffffffLL) return CHOM_EINVAL;
+        if ((long long)G.ntiles * G.boxpts * R * C > 0x7fffffffLL) {
+            set_error("RVE too large: one problem's operator tile boxes exceed 2^31 values");
+            return CHOM_EINVAL;
+        }
         P.voff = voff;
         P.doff = doff;
         P.qoff = qoff;
