@@ -156,7 +156,7 @@ template <int C, int R> struct ClassWS {
     DevBuf<float> mgA32, mgD32, mgr32, mgxp32, mgres32, mgx32, mgW32;
     DevBuf<double> mgr64, mgxp64, mgres64, mgx64, mgW64;
     std::vector<ColState> h_cols, h_cols_outer;
-    std::vector<int> h_active;
+    HostBuf<int> h_poll;               // pinned: per-problem active flags polled between graph chunks
     std::vector<int> refine_steps;
     GraphCache graph64, graph32, graph64b, graph32b;   // per precision and CG chain
 };
@@ -447,7 +447,7 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     CHOM_HIP(W.avg_out.ensure((size_t)nprob * R * NC));
     W.h_cols.resize((size_t)R * nprob);
     W.h_cols_outer.resize((size_t)R * nprob);
-    W.h_active.resize(nprob);
+    CHOM_HIP(W.h_poll.ensure(nprob));
     W.refine_steps.assign(nprob, 0);
     L.geos = B->geos.p;
     L.probs = W.probs.p;
@@ -474,7 +474,7 @@ template <int C, int R> struct PcgChain {
     long long acc_n = 0, accpq_n = 0;
     hipStream_t s = nullptr;
     GraphCache *graph = nullptr;
-    std::vector<int> h_active;
+    int *h_active = nullptr;   // this chain's slice of the class's pinned poll buffer
 };
 
 template <int C, int R>
@@ -497,7 +497,7 @@ static PcgChain<C, R> make_chain(ClassWS<C, R> &W, int p0, int cnt, const double
     ch.ginv = ginv + (size_t)p0 * SMAX * SMAX;
     ch.s = s;
     ch.graph = graph;
-    ch.h_active.assign(cnt, 0);
+    ch.h_active = W.h_poll.p + p0;
     return ch;
 }
 
@@ -562,7 +562,7 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, PcgChain<C, R> &K, const T *b, T
         GC.nprob = L.nprob;
     }
     for (int it = 0; it < max_iter; it += chunk) {
-        CHOM_HIP(hipMemcpyAsync(K.h_active.data(), K.active, sizeof(int) * L.nprob, hipMemcpyDeviceToHost, s));
+        CHOM_HIP(hipMemcpyAsync(K.h_active, K.active, sizeof(int) * L.nprob, hipMemcpyDeviceToHost, s));
         CHOM_HIP(hipStreamSynchronize(s));
         int act = 0;
         for (int i = 0; i < L.nprob; ++i) act += K.h_active[i];
@@ -685,12 +685,12 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
                 CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p,
                                                    W.active_outer.p, 1, rtol2, 0, nullptr, s)));
             }
-            CHOM_HIP(hipMemcpyAsync(W.h_active.data(), W.active_outer.p, sizeof(int) * nprob, hipMemcpyDeviceToHost, s));
+            CHOM_HIP(hipMemcpyAsync(W.h_poll.p, W.active_outer.p, sizeof(int) * nprob, hipMemcpyDeviceToHost, s));
             CHOM_HIP(hipStreamSynchronize(s));
             int act = 0;
             for (int i = 0; i < nprob; ++i) {
-                act += W.h_active[i];
-                if (W.h_active[i]) W.refine_steps[i] = step;
+                act += W.h_poll.p[i];
+                if (W.h_poll.p[i]) W.refine_steps[i] = step;
             }
             if (act == 0 || step == B->opt.max_refine) break;
             CHOM_TRY((pcg_class<float, C, R>(B, W, false, W.r32.p, W.xf.p, W.rf.p, W.pf.p, W.qf.p, W.minv32.p,

@@ -181,6 +181,30 @@ void rve_settings(const chom_rve *rve, double *c_sat, int *degrade_yarn);
         if (st_ != CHOM_OK) return st_;  \
     } while (0)
 
+// Pinned host buffer owned by a handle (device-to-host polls copy into it
+// directly, without a staging copy).
+template <typename T> struct HostBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf() { release(); }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t ensure(size_t count) {
+        if (count <= n && p) return hipSuccess;
+        release();
+        if (count == 0) count = 1;
+        hipError_t e = hipHostMalloc((void **)&p, sizeof(T) * count, hipHostMallocDefault);
+        if (e == hipSuccess) n = count;
+        return e;
+    }
+};
+
 // Device buffer owned by a handle.
 template <typename T> struct DevBuf {
     T *p = nullptr;
