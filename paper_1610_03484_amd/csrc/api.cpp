@@ -361,7 +361,7 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
             M.nwg[l] = (int)std::min<long long>(std::max<long long>((mg_max_pts[l] + 63) / 64, 1), 1024);
         }
         const char *sw = std::getenv("CHOM_MG_SWEEPS");
-        M.sweeps = sw ? std::max(1, std::atoi(sw)) : 10;
+        M.sweeps = sw ? std::max(1, std::atoi(sw)) : 4;
         M.total_pts = moff;
         // LDS of the fused kernel: the four vectors of levels >= 2, then the coarsest stencils
         const long long tsz = fp32 ? (long long)sizeof(float) : (long long)sizeof(double);

@@ -34,7 +34,7 @@ def batch():
         r.close()
 
 
-@pytest.mark.parametrize("switch", [("CHOM_MG_GENERIC", "1"), ("CHOM_MG_SWEEPS", "4"), ("CHOM_MG_SWEEPS", "16"),
+@pytest.mark.parametrize("switch", [("CHOM_MG_GENERIC", "1"), ("CHOM_MG_SWEEPS", "10"), ("CHOM_MG_SWEEPS", "16"),
                                     ("CHOM_SERIAL_CLASSES", "1"), ("CHOM_NO_GRAPH", "1")])
 def test_switch_keeps_the_result(batch, switch):
     b, params, ref = batch
