@@ -117,27 +117,53 @@ typedef struct {
     int32_t precond;       /* CHOM_PRECOND_BLOCK_JACOBI or CHOM_PRECOND_TWO_LEVEL      */
     int32_t max_iter;      /* CG iteration cap per solve (per inner solve when refined) */
     int32_t max_refine;    /* refinement steps cap (CHOM_FP32_REFINED)                 */
-    double rtol;           /* stop when r.M^-1 r <= rtol^2 * (linear-field energy)
-                              (FP64 solves with the two-level preconditioner test
-                              r.B r >= r.M^-1 r, which is stricter)                   */
-    double inner_rtol;     /* FP32 inner solves: reduce r.B r by inner_rtol^2, B the
-                              preconditioner                                           */
+    double rtol;           /* stop a load case when r.P r <= rtol^2 E: P the
+                              preconditioner (M^-1, or the two-level B), r the projected
+                              residual (the FP64 one of the refinement), E the load
+                              case's energy (x_lin + u)^T K (x_lin + u), tracked from the
+                              CG steps and kept within [1e-6, 1] x the linear-field
+                              energy x_lin^T K x_lin.  Relative to E, the energy-form
+                              averages are accurate against the homogenised value itself,
+                              also in the soft directions of a degraded matrix         */
+    double inner_rtol;     /* FP32 inner solves: stop when r.B r falls below
+                              inner_rtol^2 times the smaller of its initial value and E */
     double c_sat;          /* moisture content (wt%) with gamma = 1                    */
     int32_t degrade_yarn;  /* 1: the damage factor also scales the yarn moduli         */
     int32_t device_ptrs;   /* 1: params and outputs of chom_homogenise are on device  */
     void *hip_stream;      /* hipStream_t to queue work on (NULL: null stream)        */
 } chom_options;
 
+/* Why a load case did not converge (chom_report.fail). */
+enum {
+    CHOM_FAIL_NONE = 0,       /* converged                                                   */
+    CHOM_FAIL_CAP = 1,        /* max_iter CG steps (or max_refine refinement steps) reached   */
+    CHOM_FAIL_BREAKDOWN = 2,  /* p.Kp <= 0 (operator not positive definite in that direction) */
+    CHOM_FAIL_NONFINITE = 3   /* a CG scalar became NaN or infinite; the solve stopped there   */
+};
+
 typedef struct {
     int32_t iters[12];        /* CG iterations per load case: 6 mech, 3 thermal, 3 moisture */
     int32_t refine_steps[3];  /* refinement steps (mech, thermal, moisture)                 */
     int32_t status;           /* CHOM_OK or CHOM_ENOCONV                                    */
-    double resid[12];         /* final sqrt(r.M^-1 r / linear-field energy) per load case    */
+    double resid[12];         /* final sqrt(r.P r / linear-field energy) per load case (P as
+                                 for chom_options.rtol)                                      */
     double asym;              /* ||C - C^T||_F / ||C||_F of the unsymmetrised C_bar           */
     double omega_keep;        /* (1 - omega) applied to the matrix modulus                   */
+    int32_t fail[12];         /* CHOM_FAIL_* per load case                                   */
+    int32_t fp64_fallback[3]; /* CHOM_FP32_REFINED: 1 if the FP32 corrections of that physics
+                                 (mech, thermal, moisture) stopped contracting the FP64
+                                 residual (less than a half per step over three steps) and
+                                 an FP64 block-Jacobi correction solve finished it          */
+    int32_t spd;              /* 1: the symmetric parts of C_bar, K_bar, D_bar are positive
+                                 definite (Cholesky test)                                     */
+    double hill_mandel_gap;   /* largest over C, K, D of ||A_avg - A||_F / ||A||_F, A the
+                                 reported (energy-form) matrix and A_avg the plain volume
+                                 average of stress / flux (Sec. 2, Eq. macro_stress): the
+                                 defect of the Hill-Mandel equality (Eq. Hill_prin), zero
+                                 up to rounding for the exact discrete solution           */
 } chom_report;
 
-/* Fill *opt with defaults: FP64, block Jacobi, max_iter 20000, max_refine 30,
+/* Fill *opt with defaults: FP64, two-level preconditioner, max_iter 20000, max_refine 30,
  * rtol 1e-12, inner_rtol 1e-4, c_sat 1.5, no yarn damage, host pointers,
  * null stream.  Always succeeds for non-null opt. */
 int chom_default_options(chom_options *opt);
@@ -161,7 +187,7 @@ int chom_generate_plain_weave(int32_t n, double *coords, int32_t *tets, int8_t *
                               double *fibre_axis, void *hip_stream);
 
 /* Create an RVE handle: copies the mesh to the device, checks it (CHOM_EMESH),
- * tabulates the order-p hierarchic basis (p = 2 supported), precomputes
+ * tabulates the order-p hierarchic basis (order 2, 3 or 4), precomputes
  * element geometry and the constraint rows of bc_type.  opt may be NULL
  * (defaults).  *out receives a caller-owned handle.  Errors: CHOM_EINVAL,
  * CHOM_EMESH, CHOM_EDEVICE, CHOM_ENOMEM. */

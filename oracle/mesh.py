@@ -119,6 +119,37 @@ def yarn_test(cx, cy, cz):
     return phase, axis
 
 
+def yarn_test_values(cx, cy, cz):
+    """Ellipse test value f of every yarn (f <= 1: inside), shape [..., 4] in tagging order."""
+    cx, cy, cz = (np.asarray(a, float) for a in (cx, cy, cz))
+    out = []
+    for kind, off, ph in YARNS:
+        if kind == 0:
+            zc = 0.5 + AMPLITUDE * np.sin(2.0 * np.pi * cx + ph)
+            d_in = (cy - off) / SEMI_IN_PLANE
+        else:
+            zc = 0.5 - AMPLITUDE * np.sin(2.0 * np.pi * cy + ph)
+            d_in = (cx - off) / SEMI_IN_PLANE
+        d_z = (cz - zc) / SEMI_Z
+        out.append(d_in * d_in + d_z * d_z)
+    return np.stack(out, axis=-1)
+
+
+def yarn_tangents(cx, cy, cz):
+    """Unit centreline tangent of every yarn at the centroid's abscissa, shape [..., 4, 3]."""
+    cx, cy, cz = (np.asarray(a, float) for a in (cx, cy, cz))
+    out = []
+    for kind, off, ph in YARNS:
+        if kind == 0:
+            t = np.stack([np.ones_like(cx), np.zeros_like(cx),
+                          AMPLITUDE * 2.0 * np.pi * np.cos(2.0 * np.pi * cx + ph)], axis=-1)
+        else:
+            t = np.stack([np.zeros_like(cx), np.ones_like(cx),
+                          -AMPLITUDE * 2.0 * np.pi * np.cos(2.0 * np.pi * cy + ph)], axis=-1)
+        out.append(t / np.linalg.norm(t, axis=-1, keepdims=True))
+    return np.stack(out, axis=-2)
+
+
 def yarn_margin(cx, cy, cz):
     """min over yarns of |f - 1| (ellipse test value), to spot near-ties."""
     cx, cy, cz = (np.asarray(a, float) for a in (cx, cy, cz))

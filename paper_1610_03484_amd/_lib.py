@@ -14,6 +14,7 @@ CHOM_OK, CHOM_EINVAL, CHOM_EMESH, CHOM_EMATERIAL, CHOM_ENOCONV, CHOM_EDEVICE, CH
 STATUS_NAMES = {0: "CHOM_OK", -1: "CHOM_EINVAL", -2: "CHOM_EMESH", -3: "CHOM_EMATERIAL",
                 -4: "CHOM_ENOCONV", -5: "CHOM_EDEVICE", -6: "CHOM_ENOMEM"}
 BC = {"dirichlet": 0, "periodic": 1, "neumann": 2}
+FAIL_NONE, FAIL_CAP, FAIL_BREAKDOWN, FAIL_NONFINITE = 0, 1, 2, 3
 PRECISION = {"fp64": 0, "fp32_refined": 1}
 PRECOND = {"block_jacobi": 0, "two_level": 1}
 
@@ -44,7 +45,9 @@ class ChomOptions(ct.Structure):
 
 class ChomReport(ct.Structure):
     _fields_ = [("iters", ct.c_int32 * 12), ("refine_steps", ct.c_int32 * 3), ("status", ct.c_int32),
-                ("resid", ct.c_double * 12), ("asym", ct.c_double), ("omega_keep", ct.c_double)]
+                ("resid", ct.c_double * 12), ("asym", ct.c_double), ("omega_keep", ct.c_double),
+                ("fail", ct.c_int32 * 12), ("fp64_fallback", ct.c_int32 * 3), ("spd", ct.c_int32),
+                ("hill_mandel_gap", ct.c_double)]
 
 
 class ChomMlpOptions(ct.Structure):

@@ -148,7 +148,8 @@ class RVE:
 
 def report_dict(r: L.ChomReport) -> dict:
     return dict(iters=list(r.iters), refine_steps=list(r.refine_steps), status=r.status,
-                resid=list(r.resid), asym=r.asym, omega_keep=r.omega_keep)
+                resid=list(r.resid), asym=r.asym, omega_keep=r.omega_keep, fail=list(r.fail),
+                fp64_fallback=list(r.fp64_fallback), spd=r.spd, hill_mandel_gap=r.hill_mandel_gap)
 
 
 def upper21_to_matrix(c21):

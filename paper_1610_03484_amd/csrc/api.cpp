@@ -155,9 +155,13 @@ template <int C, int R> struct ClassWS {
     DevBuf<double> mgA64, mgD64, mgrows1, gmat, ginv_mg;
     DevBuf<float> mgA32, mgD32, mgr32, mgxp32, mgres32, mgx32, mgW32;
     DevBuf<double> mgr64, mgxp64, mgres64, mgx64, mgW64;
-    std::vector<ColState> h_cols, h_cols_outer;
+    DevBuf<double> avg_corr;             // Hill-Mandel gap terms (1/V) u_i . r_j [prob][NC][R]
+    DevBuf<ColState> cols_tmp, cols_fb;  // final-residual projection; mask of the FP64 fallback solve
+    DevBuf<int> active_tmp;
+    std::vector<ColState> h_cols, h_cols_outer, h_cols_tmp;
     HostBuf<int> h_poll;               // pinned: per-problem active flags polled between graph chunks
     std::vector<int> refine_steps;
+    std::vector<int> fallback;         // per problem: an FP64 solve finished a stalled refinement
     GraphCache graph64, graph32, graph64b, graph32b;   // per precision and CG chain
 };
 
@@ -316,9 +320,9 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     L.ef32 = eoff > 0 ? W.ef32.p : nullptr;
     CHOM_HIP(W.b.ensure(nv));
     CHOM_HIP(W.q64.ensure(nq));
+    CHOM_HIP(W.r64.ensure(nv));   // FP64 residual (refinement; final residual of the energy form)
     if (fp32) {
         CHOM_HIP(W.x64.ensure(nv));
-        CHOM_HIP(W.r64.ensure(nv));
         CHOM_HIP(W.xf.ensure(nv));
         CHOM_HIP(W.rf.ensure(nv));
         CHOM_HIP(W.pf.ensure(nv));
@@ -445,8 +449,12 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
         }
     }
     CHOM_HIP(W.avg_out.ensure((size_t)nprob * R * NC));
+    CHOM_HIP(W.avg_corr.ensure((size_t)nprob * R * NC));
+    CHOM_HIP(W.cols_tmp.ensure((size_t)R * nprob));
+    CHOM_HIP(W.active_tmp.ensure(nprob));
     W.h_cols.resize((size_t)R * nprob);
     W.h_cols_outer.resize((size_t)R * nprob);
+    W.h_cols_tmp.resize((size_t)R * nprob);
     CHOM_HIP(W.h_poll.ensure(nprob));
     W.refine_steps.assign(nprob, 0);
     L.geos = B->geos.p;
@@ -475,6 +483,7 @@ template <int C, int R> struct PcgChain {
     hipStream_t s = nullptr;
     GraphCache *graph = nullptr;
     int *h_active = nullptr;   // this chain's slice of the class's pinned poll buffer
+    int max_iter = 0;          // CG steps per solve and column (0: no cap)
 };
 
 template <int C, int R>
@@ -517,7 +526,8 @@ static hipError_t cg_iteration(const PcgChain<C, R> &K, T *x, T *r, T *p, T *q, 
     if ((e = launch_finish_alpha<C, R>(L, K.accpq, K.cols, s)) != hipSuccess) return e;
     if ((e = launch_cg_update<T, C, R>(L, r, q, minv, K.cols, K.acc, K.active, s)) != hipSuccess) return e;
     if (mg && (e = launch_mg_vcycle<T, C, R>(L, r, K.acc, K.active, s)) != hipSuccess) return e;
-    return launch_finish_beta<C, R>(L, K.acc, K.ginv, K.ycoef, K.cols, K.active, 0, rtol2, use_init, nullptr, s);
+    return launch_finish_beta<C, R>(L, K.acc, K.ginv, K.ycoef, K.cols, K.active, 0, rtol2, use_init, nullptr, s,
+                                    K.max_iter);
 }
 
 // PCG on one chain of problems: b -> x (vectors of precision T).  Iterations
@@ -531,6 +541,7 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, PcgChain<C, R> &K, const T *b, T
     const Launch &L = K.L;
     const bool mg = L.mg.on != 0;
     GraphCache &GC = *K.graph;
+    K.max_iter = B->opt.max_iter;
     // the accumulators may hold sums of kernels run outside a CG step (timing, residuals)
     CHOM_HIP(launch_zero(K.acc, K.acc_n, s));
     CHOM_HIP(launch_zero(K.accpq, K.accpq_n, s));
@@ -632,6 +643,149 @@ static int pcg_class(chom_batch *B, ClassWS<C, R> &W, bool fp64, const T *b, T *
     return CHOM_OK;
 }
 
+// FP64 correction solve of the refinement for the problems flagged in `which`
+// (the others are masked out): K d = r64 with the FP64 operator and block-Jacobi
+// preconditioning to a tenth of the outer tolerance, then x64 += d.  Used when
+// the FP32 inner solves stop contracting the FP64 residual.  The FP64 vectors
+// are allocated on first use.
+template <int C, int R>
+static int fp64_correction(chom_batch *B, ClassWS<C, R> &W, const std::vector<int> &which, double rtol2) {
+    const Launch saved = W.L;
+    const int nprob = saved.nprob;
+    hipStream_t s = W.stream;
+    const size_t nv = (size_t)W.total_vals, nq = (size_t)W.total_q;
+    CHOM_HIP(W.xd.ensure(nv));
+    CHOM_HIP(W.rd.ensure(nv));
+    CHOM_HIP(W.pd.ensure(nv));
+    CHOM_HIP(W.qd.ensure(nq));
+    CHOM_HIP(W.cols_fb.ensure((size_t)R * nprob));
+    std::vector<ColState> mask(W.h_cols_outer);
+    for (int i = 0; i < nprob; ++i)
+        if (!which[i])
+            for (int r = 0; r < R; ++r) mask[(size_t)i * R + r].done = COL_CONVERGED;
+    CHOM_HIP(hipMemcpyAsync(W.cols_fb.p, mask.data(), sizeof(ColState) * R * nprob, hipMemcpyHostToDevice, s));
+    W.L.mg.on = 0;   // the coarse levels hold FP32 data in this mode: block Jacobi alone
+    ++W.gen;
+    const int st = pcg_class<double, C, R>(B, W, true, W.r64.p, W.xd.p, W.rd.p, W.pd.p, W.qd.p, W.minv64.p,
+                                           W.ginv64.p, 0.01 * rtol2, 0, W.cols_fb.p);
+    W.L = saved;
+    ++W.gen;
+    CHOM_TRY(st);
+    CHOM_HIP(launch_axpy64(W.total_vals, W.x64.p, W.xd.p, s));
+    return CHOM_OK;
+}
+
+// FP32 operator with FP64 refinement: x64 += PCG_32(r64), r64 = b - K_64 x64,
+// until the projected FP64 residual meets rtol.  A problem whose FP64 residual
+// norm contracts by less than a half per step over three steps is finished by
+// an FP64 correction solve (CHOM_FORCE_FP64_FALLBACK forces that from the second
+// step on, for tests).
+template <int C, int R>
+static int refine_class(chom_batch *B, ClassWS<C, R> &W, const double *ginv_inner32, double rtol2) {
+    const Launch &L = W.L;
+    const int nprob = L.nprob;
+    hipStream_t s = W.stream;
+    const double irtol2 = B->opt.inner_rtol * B->opt.inner_rtol;
+    const bool force_fb = std::getenv("CHOM_FORCE_FP64_FALLBACK") != nullptr;
+    CHOM_HIP(hipMemsetAsync(W.x64.p, 0, sizeof(double) * W.total_vals, s));
+    CHOM_HIP((launch_residual64<C, R>(L, W.b.p, nullptr, W.r64.p, W.r32.p, s)));
+    CHOM_HIP(hipMemcpyAsync(W.cols_outer.p, W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToDevice, s));
+    std::vector<double> prev_rz((size_t)R * nprob, 0.0);
+    std::vector<int> slow((size_t)R * nprob, 0);
+    for (int step = 0; step <= B->opt.max_refine; ++step) {
+        // outer residual: project r64 (FP64), then measure it in the metric of the
+        // solver's preconditioner (r.M^-1 r, or r.B r with the two-level one, from
+        // the FP32 copy with FP64 sums) against the column's energy
+        CHOM_HIP(launch_zero(W.acc.p, (long long)W.acc.n, s));
+        CHOM_HIP((launch_cg_init<double, C, R>(L, W.r64.p, nullptr, nullptr, W.minv64.p, W.acc.p, s)));
+        CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p, W.active_outer.p, 1,
+                                           rtol2, 0, nullptr, s, 0, W.cols.p)));
+        if (L.nr > 0) {
+            CHOM_HIP((launch_proj_resid<C, R>(L, W.r64.p, W.r32.p, W.minv64.p, W.ycoef.p, W.acc.p, s)));
+            CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p, W.active_outer.p,
+                                               1, rtol2, 0, nullptr, s, 0, W.cols.p)));
+        }
+        const bool mg = L.mg.on != 0;
+        if (mg) {   // the two-level metric, into cols_tmp (merged on the host below)
+            CHOM_HIP(hipMemcpyAsync(W.cols_tmp.p, W.cols_outer.p, sizeof(ColState) * R * nprob,
+                                    hipMemcpyDeviceToDevice, s));
+            CHOM_HIP(launch_zero(W.acc.p, (long long)W.acc.n, s));
+            CHOM_HIP((launch_cg_init<float, C, R>(L, W.r32.p, nullptr, nullptr, W.minv32.p, W.acc.p, s)));
+            CHOM_HIP((launch_mg_vcycle<float, C, R>(L, W.r32.p, W.acc.p, nullptr, s)));
+            CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, ginv_inner32, W.ycoef.p, W.cols_tmp.p, W.active_tmp.p,
+                                               1, rtol2, 0, nullptr, s, 0, W.cols.p)));
+            CHOM_HIP(hipMemcpyAsync(W.h_cols_tmp.data(), W.cols_tmp.p, sizeof(ColState) * R * nprob,
+                                    hipMemcpyDeviceToHost, s));
+        }
+        CHOM_HIP(hipMemcpyAsync(W.h_cols_outer.data(), W.cols_outer.p, sizeof(ColState) * R * nprob,
+                                hipMemcpyDeviceToHost, s));
+        CHOM_HIP(hipStreamSynchronize(s));
+        // merge: the two-level measurement where it is finite; where the FP32
+        // coarse levels overflow, the FP64 block-Jacobi one stands and an active
+        // column goes to the FP64 correction solve
+        std::vector<int> fp32_failed(nprob, 0);
+        if (mg) {
+            for (size_t k = 0; k < (size_t)R * nprob; ++k) {
+                ColState &h = W.h_cols_outer[k];
+                const ColState &t = W.h_cols_tmp[k];
+                if (std::isfinite(t.rz)) {
+                    if (h.done != COL_NONFINITE) {
+                        h.rz = t.rz;
+                        h.rz_init = t.rz_init;
+                        h.done = t.done;
+                    }
+                } else if (h.done == COL_ACTIVE) {
+                    fp32_failed[k / R] = 1;
+                }
+            }
+            CHOM_HIP(hipMemcpyAsync(W.cols_outer.p, W.h_cols_outer.data(), sizeof(ColState) * R * nprob,
+                                    hipMemcpyHostToDevice, s));
+        }
+        int act = 0;
+        std::vector<int> stalled(nprob, 0);
+        bool any_stalled = false;
+        for (int i = 0; i < nprob; ++i) {
+            int active = 0;
+            for (int r = 0; r < R; ++r) active += W.h_cols_outer[(size_t)i * R + r].done == COL_ACTIVE;
+            act += active;
+            if (!active) continue;
+            W.refine_steps[i] = step;
+            if (fp32_failed[i]) stalled[i] = 1;
+            for (int r = 0; r < R; ++r) {
+                const size_t k = (size_t)i * R + r;
+                const ColState &cs = W.h_cols_outer[k];
+                if (cs.done) continue;
+                const bool contracted = step > 0 && cs.rz <= 0.25 * prev_rz[k];
+                slow[k] = (step > 0 && !contracted) ? slow[k] + 1 : 0;
+                if (slow[k] >= 3 || (force_fb && step >= 1)) stalled[i] = 1;
+                prev_rz[k] = cs.rz;
+            }
+            if (stalled[i]) {
+                any_stalled = true;
+                W.fallback[i] = 1;
+                for (int r = 0; r < R; ++r) slow[(size_t)i * R + r] = 0;
+            }
+        }
+        if (act == 0 || step == B->opt.max_refine) break;
+        if (any_stalled) {
+            CHOM_TRY((fp64_correction<C, R>(B, W, stalled, rtol2)));
+            // the other active problems still take their FP32 correction this step
+            for (int i = 0; i < nprob; ++i)
+                if (stalled[i])
+                    for (int r = 0; r < R; ++r) W.h_cols_outer[(size_t)i * R + r].done = COL_CONVERGED;
+            CHOM_HIP(hipMemcpyAsync(W.cols_fb.p, W.h_cols_outer.data(), sizeof(ColState) * R * nprob,
+                                    hipMemcpyHostToDevice, s));
+        }
+        const ColState *mask32 = any_stalled ? W.cols_fb.p : W.cols_outer.p;
+        CHOM_TRY((pcg_class<float, C, R>(B, W, false, W.r32.p, W.xf.p, W.rf.p, W.pf.p, W.qf.p, W.minv32.p,
+                                         ginv_inner32, irtol2, 1, mask32)));
+        CHOM_HIP(launch_axpy_x64(W.total_vals, W.x64.p, W.xf.p, s));
+        CHOM_HIP((launch_operator<double, C, R>(L, nprob, L.rg, W.x64.p, W.q64.p, W.accpq.p, nullptr, s)));
+        CHOM_HIP((launch_residual64<C, R>(L, W.b.p, W.q64.p, W.r64.p, W.r32.p, s)));
+    }
+    return CHOM_OK;
+}
+
 // Solve one class (mechanical or scalar) for all its problems.  Result: W.avg_out.
 template <int C, int R>
 static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs, int rg, int nwg) {
@@ -664,49 +818,32 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
     }
     CHOM_HIP((launch_rhs<C, R>(L, W.total_vals, W.b.p, W.cols.p, W.q64.p, W.accpq.p, s)));
     const double rtol2 = B->opt.rtol * B->opt.rtol;
+    W.fallback.assign(nprob, 0);
     double *x64 = nullptr;
     if (B->opt.precision == CHOM_FP64) {
         CHOM_TRY((pcg_class<double, C, R>(B, W, true, W.b.p, W.xd.p, W.rd.p, W.pd.p, W.qd.p, W.minv64.p,
                                           ginv_inner64, rtol2, 0, nullptr)));
         x64 = W.xd.p;
     } else {
-        const double irtol2 = B->opt.inner_rtol * B->opt.inner_rtol;
-        CHOM_HIP(hipMemsetAsync(W.x64.p, 0, sizeof(double) * W.total_vals, s));
-        CHOM_HIP((launch_residual64<C, R>(L, W.b.p, nullptr, W.r64.p, W.r32.p, s)));
-        CHOM_HIP(hipMemcpyAsync(W.cols_outer.p, W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToDevice, s));
-        for (int step = 0; step <= B->opt.max_refine; ++step) {
-            // outer residual norm in FP64: project r64, then r64 . M^-1 r64 against the linear-field energy
-            CHOM_HIP(launch_zero(W.acc.p, (long long)W.acc.n, s));
-            CHOM_HIP((launch_cg_init<double, C, R>(L, W.r64.p, nullptr, nullptr, W.minv64.p, W.acc.p, s)));
-            CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p, W.active_outer.p,
-                                               1, rtol2, 0, nullptr, s)));
-            if (L.nr > 0) {
-                CHOM_HIP((launch_proj_resid<C, R>(L, W.r64.p, W.r32.p, W.minv64.p, W.ycoef.p, W.acc.p, s)));
-                CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p,
-                                                   W.active_outer.p, 1, rtol2, 0, nullptr, s)));
-            }
-            CHOM_HIP(hipMemcpyAsync(W.h_poll.p, W.active_outer.p, sizeof(int) * nprob, hipMemcpyDeviceToHost, s));
-            CHOM_HIP(hipStreamSynchronize(s));
-            int act = 0;
-            for (int i = 0; i < nprob; ++i) {
-                act += W.h_poll.p[i];
-                if (W.h_poll.p[i]) W.refine_steps[i] = step;
-            }
-            if (act == 0 || step == B->opt.max_refine) break;
-            CHOM_TRY((pcg_class<float, C, R>(B, W, false, W.r32.p, W.xf.p, W.rf.p, W.pf.p, W.qf.p, W.minv32.p,
-                                             ginv_inner32, irtol2, 1, W.cols_outer.p)));
-            CHOM_HIP(launch_axpy_x64(W.total_vals, W.x64.p, W.xf.p, s));
-            CHOM_HIP((launch_operator<double, C, R>(L, nprob, L.rg, W.x64.p, W.q64.p,
-                                                    W.accpq.p, nullptr, s)));
-            CHOM_HIP((launch_residual64<C, R>(L, W.b.p, W.q64.p, W.r64.p, W.r32.p, s)));
-        }
+        CHOM_TRY((refine_class<C, R>(B, W, ginv_inner32, rtol2)));
         x64 = W.x64.p;
     }
     CHOM_HIP((launch_project<C, R>(L, x64, W.minv64.p, W.ginv64.p, W.partial.p, s)));
-    // energy form of the averages: the final projected residual (FP64 CG residual,
-    // or the FP64 refinement residual of the refined path) corrects them
-    const double *r_final = B->opt.precision == CHOM_FP64 ? W.rd.p : W.r64.p;
-    CHOM_HIP((launch_average<C, R>(L, x64, r_final, W.partial.p, W.nwg_avg, W.avg_out.p, s)));
+    // residual of the projected solution, r = b - K x (FP64 operator), itself
+    // projected: the energy form of the averages and the Hill-Mandel gap take it
+    CHOM_HIP((launch_operator<double, C, R>(L, nprob, L.rg, x64, W.q64.p, W.accpq.p, nullptr, s)));
+    CHOM_HIP((launch_residual64<C, R>(L, W.b.p, W.q64.p, W.r64.p, nullptr, s)));
+    if (L.nr > 0) {
+        CHOM_HIP(hipMemsetAsync(W.cols_tmp.p, 0, sizeof(ColState) * R * nprob, s));
+        CHOM_HIP(launch_zero(W.acc.p, (long long)W.acc.n, s));
+        CHOM_HIP((launch_cg_init<double, C, R>(L, W.r64.p, nullptr, nullptr, W.minv64.p, W.acc.p, s)));
+        CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, W.ginv64.p, W.ycoef.p, W.cols_tmp.p, W.active_tmp.p, 1, rtol2,
+                                           0, nullptr, s)));
+        CHOM_HIP((launch_proj_resid<C, R>(L, W.r64.p, nullptr, W.minv64.p, W.ycoef.p, W.acc.p, s)));
+        CHOM_HIP(launch_zero(W.acc.p, (long long)W.acc.n, s));
+    }
+    CHOM_HIP(launch_zero(W.accpq.p, (long long)W.accpq.n, s));
+    CHOM_HIP((launch_average<C, R>(L, x64, W.r64.p, W.partial.p, W.nwg_avg, W.avg_out.p, s, W.avg_corr.p)));
     CHOM_HIP(hipMemcpyAsync(W.h_cols.data(), W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToHost, s));
     if (B->opt.precision == CHOM_FP32_REFINED)
         CHOM_HIP(hipMemcpyAsync(W.h_cols_outer.data(), W.cols_outer.p, sizeof(ColState) * R * nprob,
@@ -896,6 +1033,32 @@ static int batch_init(chom_batch *B, chom_rve *const *rves, int n, const chom_op
     return CHOM_OK;
 }
 
+// Cholesky test of a symmetric n x n matrix (row-major): true if positive definite.
+static bool cholesky_ok(const double *A, int n) {
+    double L[36];
+    for (int j = 0; j < n; ++j) {
+        double d = A[j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+        if (!(d > 0.0) || !std::isfinite(d)) return false;
+        L[j * n + j] = std::sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = v / L[j * n + j];
+        }
+    }
+    return true;
+}
+
+static double fro_ratio(const double *num, const double *den, int n) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < n; ++k) {
+        a += num[k] * num[k];
+        b += den[k] * den[k];
+    }
+    return b > 0.0 ? std::sqrt(a / b) : 0.0;
+}
+
 static int batch_homogenise(chom_batch *B, const chom_params *params, double *C_hom, double *K_hom, double *D_hom,
                             chom_report *rep, bool dev) {
     const int batch = (int)B->entries.size();
@@ -975,15 +1138,18 @@ static int batch_homogenise(chom_batch *B, const chom_params *params, double *C_
         return st_scal;
     }
     std::vector<double> cm((size_t)batch * 36), cs((size_t)2 * batch * 9);
+    std::vector<double> gm((size_t)batch * 36), gs((size_t)2 * batch * 9);
     CHOM_HIP(hipMemcpyAsync(cm.data(), B->mech.avg_out.p, sizeof(double) * cm.size(), hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipMemcpyAsync(gm.data(), B->mech.avg_corr.p, sizeof(double) * gm.size(), hipMemcpyDeviceToHost, s));
     CHOM_HIP(hipMemcpyAsync(cs.data(), B->scal.avg_out.p, sizeof(double) * cs.size(), hipMemcpyDeviceToHost,
+                            B->stream2));
+    CHOM_HIP(hipMemcpyAsync(gs.data(), B->scal.avg_corr.p, sizeof(double) * gs.size(), hipMemcpyDeviceToHost,
                             B->stream2));
     CHOM_HIP(hipStreamSynchronize(B->stream2));
     CHOM_HIP(hipStreamSynchronize(s));
     std::vector<double> oc((size_t)batch * 21), ok((size_t)batch * 6), od((size_t)batch * 6);
     int overall = CHOM_OK;
     const bool refined = B->opt.precision == CHOM_FP32_REFINED;
-    const double rtol2 = B->opt.rtol * B->opt.rtol;
     for (int i = 0; i < batch; ++i) {
         const double *Cm = &cm[(size_t)i * 36];
         int q = 0;
@@ -1019,13 +1185,36 @@ static int batch_homogenise(chom_batch *B, const chom_params *params, double *C_
             }
             Rp.iters[c] = cin->iters;
             Rp.resid[c] = cout->eref > 0 ? std::sqrt(cout->rz / cout->eref) : 0.0;
-            const bool conv = (cout->done == 1) || (cout->rz <= rtol2 * cout->eref);
-            if (!conv) Rp.status = CHOM_ENOCONV;
+            const bool finite = std::isfinite(cout->rz) && cout->done != COL_NONFINITE && cin->done != COL_NONFINITE;
+            const bool conv = finite && cout->done == COL_CONVERGED;
+            if (!conv) {
+                Rp.status = CHOM_ENOCONV;
+                Rp.fail[c] = !finite ? CHOM_FAIL_NONFINITE
+                                     : (cout->done == COL_BREAKDOWN || cin->done == COL_BREAKDOWN) ? CHOM_FAIL_BREAKDOWN
+                                                                                                  : CHOM_FAIL_CAP;
+            }
         }
         if (refined) {
             Rp.refine_steps[0] = B->mech.refine_steps[i];
             Rp.refine_steps[1] = B->scal.refine_steps[i];
             Rp.refine_steps[2] = B->scal.refine_steps[batch + i];
+            Rp.fp64_fallback[0] = B->mech.fallback[i];
+            Rp.fp64_fallback[1] = B->scal.fallback[i];
+            Rp.fp64_fallback[2] = B->scal.fallback[batch + i];
+        }
+        // positive definiteness of the symmetric parts, and the Hill-Mandel gap
+        {
+            double S6[36], S3k[9], S3d[9];
+            for (int a = 0; a < 6; ++a)
+                for (int b = 0; b < 6; ++b) S6[a * 6 + b] = 0.5 * (Cm[a * 6 + b] + Cm[b * 6 + a]);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    S3k[a * 3 + b] = 0.5 * (Kt[a * 3 + b] + Kt[b * 3 + a]);
+                    S3d[a * 3 + b] = 0.5 * (Dt[a * 3 + b] + Dt[b * 3 + a]);
+                }
+            Rp.spd = (cholesky_ok(S6, 6) && cholesky_ok(S3k, 3) && cholesky_ok(S3d, 3)) ? 1 : 0;
+            const double *Gm = &gm[(size_t)i * 36], *Gk = &gs[(size_t)i * 9], *Gd = &gs[(size_t)(batch + i) * 9];
+            Rp.hill_mandel_gap = std::max(fro_ratio(Gm, Cm, 36), std::max(fro_ratio(Gk, Kt, 9), fro_ratio(Gd, Dt, 9)));
         }
         if (Rp.status != CHOM_OK) overall = CHOM_ENOCONV;
         if (rep) rep[i] = Rp;

@@ -331,7 +331,7 @@ __global__ __launch_bounds__(64 * R) void proj_resid_kernel(const Geo *__restric
             for (int a = 0; a < NR; ++a) ct += row[a] * yv[c * NR + a];
             rv[c] = r64[o + c] - ct;
             r64[o + c] = rv[c];
-            r32[o + c] = (float)rv[c];
+            if (r32) r32[o + c] = (float)rv[c];
         }
         minv_apply<double, C>(Mi, rv, zv);
 #pragma unroll
@@ -385,23 +385,36 @@ __global__ __launch_bounds__(256) void finish_alpha_kernel(double *acc_pq, ColSt
         cs.pq = v;
         if (cs.done) {
             cs.alpha = 0.0;
+        } else if (!isfinite(v)) {
+            cs.alpha = 0.0;
+            cs.done = COL_NONFINITE;
         } else if (!(v > 0.0)) {
             cs.alpha = 0.0;
-            cs.done = 2;
+            cs.done = COL_BREAKDOWN;
         } else {
             cs.alpha = cs.rz / v;
+            // a CG step lowers the energy functional of the total field by alpha r.z
+            cs.energy -= cs.alpha * cs.rz;
         }
     }
 }
 
 // rz = r.z0 - c^T (C M^-1 C^T)^-1 c, projection coefficients y, beta, convergence;
 // the records [R][REC] are read from the vector kernels' striped accumulators,
-// which are cleared for the next step.  One workgroup per problem.
+// which are cleared for the next step.  One workgroup per problem.  A column
+// stops when it converges, when rz is not finite, or (max_iter > 0) after
+// max_iter steps of the current solve.  Convergence is measured against the
+// column's own energy E = (x_lin + u)^T K (x_lin + u) (its running estimate,
+// from `esrc` when given, else from the column itself; at most the linear-field
+// energy eref, at least 1e-6 eref): rz <= rtol2 E, or with use_init
+// rz <= rtol2 min(rz_init, E).  Relative to E, the error of the energy-form
+// average stays small against the homogenised value itself, also in the soft
+// directions of a degraded matrix, where E is far below eref.
 template <int C, int R>
 __global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, double *accbuf,
                                                          const double *ginv, double *ycoef, ColState *cols,
                                                          int *prob_active, int first, double rtol2, int use_init,
-                                                         const ColState *mask) {
+                                                         const ColState *mask, int max_iter, const ColState *esrc) {
     constexpr int SMAX = C * 4;
     constexpr int RECMAX = ACC_RECMAX<C>;
     const int prob = blockIdx.x;
@@ -454,15 +467,24 @@ __global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const
             cs.rz_init = rz;
             cs.beta = 0.0;
             cs.alpha = 0.0;   // no pending x update (see cg_dir_kernel)
-            cs.done = (mask != nullptr && mask[prob * R + lane].done) ? 1 : 0;
+            cs.done = (mask != nullptr && mask[prob * R + lane].done) ? COL_CONVERGED : COL_ACTIVE;
+            cs.iters0 = cs.iters;
+            if (!(cs.energy > 0.0)) cs.energy = cs.eref;   // start of the call: no CG step taken yet
         } else {
             cs.beta = (cs.done || cs.rz == 0.0) ? 0.0 : rz / cs.rz;
             if (was_active) cs.iters += 1;
         }
-        cs.rz_prev = cs.rz;
-        cs.rz = rz;
-        const double ref = use_init ? cs.rz_init : cs.eref;
-        if (!cs.done && rz <= rtol2 * ref) cs.done = 1;
+        if (first || was_active) {   // a stopped column keeps the residual it stopped with
+            cs.rz_prev = cs.rz;
+            cs.rz = rz;
+        }
+        double en = esrc != nullptr ? esrc[prob * R + lane].energy : cs.energy;
+        if (!(en > 0.0)) en = cs.eref;
+        en = fmin(fmax(en, 1e-6 * cs.eref), cs.eref);
+        const double ref = use_init ? fmin(cs.rz_init, en) : en;
+        if (!cs.done && !isfinite(rz)) cs.done = COL_NONFINITE;
+        if (!cs.done && rz <= rtol2 * ref) cs.done = COL_CONVERGED;
+        if (!cs.done && !first && max_iter > 0 && cs.iters - cs.iters0 >= max_iter) cs.done = COL_CAPPED;
         if (cs.done) cs.beta = 0.0;
         sdone[lane] = cs.done;
     }
@@ -537,9 +559,9 @@ hipError_t launch_finish_alpha(const Launch &L, double *acc_pq, ColState *cols, 
 template <int C, int R>
 hipError_t launch_finish_beta(const Launch &L, double *accbuf, const double *ginv, double *ycoef, ColState *cols,
                               int *prob_active, int first, double rtol2, int use_init, const ColState *mask,
-                              hipStream_t s) {
+                              hipStream_t s, int max_iter, const ColState *esrc) {
     finish_beta_kernel<C, R><<<L.nprob, 512, 0, s>>>(L.geos, L.probs, L.nr, accbuf, ginv, ycoef, cols, prob_active,
-                                                    first, rtol2, use_init, mask);
+                                                    first, rtol2, use_init, mask, max_iter, esrc);
     return hipGetLastError();
 }
 
@@ -601,6 +623,19 @@ hipError_t launch_axpy_x64(long long total, double *x64, const float *d32, hipSt
     long long g = (total + 255) / 256;
     g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
     axpy_x64_kernel<<<(int)g, 256, 0, s>>>(total, x64, d32);
+    return hipGetLastError();
+}
+
+__global__ void axpy64_kernel(long long total, double *x64, const double *d64) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x)
+        x64[i] += d64[i];
+}
+
+hipError_t launch_axpy64(long long total, double *x64, const double *d64, hipStream_t s) {
+    long long g = (total + 255) / 256;
+    g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
+    axpy64_kernel<<<(int)g, 256, 0, s>>>(total, x64, d64);
     return hipGetLastError();
 }
 
@@ -711,7 +746,8 @@ CHOM_INST(float, 1, 3)
 #define CHOM_INST2(C, R)                                                                                         \
     template hipError_t launch_finish_alpha<C, R>(const Launch &, double *, ColState *, hipStream_t);            \
     template hipError_t launch_finish_beta<C, R>(const Launch &, double *, const double *, double *, ColState *, \
-                                                 int *, int, double, int, const ColState *, hipStream_t);        \
+                                                 int *, int, double, int, const ColState *, hipStream_t, int,    \
+                                                 const ColState *);                                              \
     template hipError_t launch_proj_resid<C, R>(const Launch &, double *, float *, const double *,               \
                                                 const double *, double *, hipStream_t);                          \
     template hipError_t launch_residual64<C, R>(const Launch &, const double *, const double *, double *, float *, \

@@ -126,10 +126,13 @@ __global__ __launch_bounds__(64 * R) void residual_pair_kernel(const Geo *geos, 
 // out[prob][i][j] = (1/V) sum of partials: row i = stress/flux component, column j = load case.
 // With `rpart` (residual_pair_kernel sums, nwg2 blocks) the entry becomes the
 // energy form (1/V) (x_i + u_i)^T K (x_j + u_j) = sigma_bar_j[i] - (1/V) u_i . r_j
-// (unit load cases in the stress/flux component order, so NC = R).
+// (unit load cases in the stress/flux component order, so NC = R), and `corr`
+// (nullable) receives (1/V) u_i . r_j: the gap between the plain average and the
+// energy form, i.e. the Hill-Mandel defect of the computed fluctuation (zero for
+// the exact discrete solution, Sec. 2).
 template <int C, int R>
 __global__ void average_finish_kernel(const Geo *geos, const Prob *probs, int nwg, const double *partial, int nwg2,
-                                      const double *rpart, double *out) {
+                                      const double *rpart, double *out, double *corr) {
     constexpr int NC = (C == 3) ? 6 : 3;
     static_assert(NC == R, "load cases are the unit strains / gradients");
     const int prob = blockIdx.x;
@@ -137,18 +140,22 @@ __global__ void average_finish_kernel(const Geo *geos, const Prob *probs, int nw
     const int lane = threadIdx.x;
     for (int k = 0; k < R * NC; ++k) {
         const int r = k / NC, i = k % NC;   // load case r, component i
-        double s = 0.0;
+        double s = 0.0, g = 0.0;
         for (int w = lane; w < nwg; w += 64) s += partial[((long long)prob * nwg + w) * R * NC + k];
         if (rpart != nullptr)
-            for (int w = lane; w < nwg2; w += 64) s -= rpart[(((long long)prob * nwg2 + w) * R + i) * R + r];
+            for (int w = lane; w < nwg2; w += 64) g += rpart[(((long long)prob * nwg2 + w) * R + i) * R + r];
         s = wave_sum(s);
-        if (lane == 0) out[(long long)prob * NC * R + i * R + r] = s / volume;
+        g = wave_sum(g);
+        if (lane == 0) {
+            out[(long long)prob * NC * R + i * R + r] = (s - g) / volume;
+            if (corr != nullptr) corr[(long long)prob * NC * R + i * R + r] = g / volume;
+        }
     }
 }
 
 template <int C, int R>
 hipError_t launch_average(const Launch &L, const double *x64, const double *r64, double *partial, int nwg,
-                          double *out, hipStream_t s) {
+                          double *out, hipStream_t s, double *corr) {
     dim3 grid(nwg, L.nprob);
     if (L.order != 2) {
         const hipError_t e = launch_average_partial_hp<C, R>(L, x64, partial, nwg, s);
@@ -159,12 +166,13 @@ hipError_t launch_average(const Launch &L, const double *x64, const double *r64,
     constexpr int NC = (C == 3) ? 6 : 3;
     double *rpart = r64 ? partial + (size_t)L.nprob * nwg * R * NC : nullptr;
     if (r64) residual_pair_kernel<C, R><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, x64, r64, rpart);
-    average_finish_kernel<C, R><<<L.nprob, FIN_BS, 0, s>>>(L.geos, L.probs, nwg, partial, nwg, rpart, out);
+    average_finish_kernel<C, R><<<L.nprob, FIN_BS, 0, s>>>(L.geos, L.probs, nwg, partial, nwg, rpart, out,
+                                                           rpart ? corr : nullptr);
     return hipGetLastError();
 }
 template hipError_t launch_average<3, 6>(const Launch &, const double *, const double *, double *, int, double *,
-                                        hipStream_t);
+                                        hipStream_t, double *);
 template hipError_t launch_average<1, 3>(const Launch &, const double *, const double *, double *, int, double *,
-                                        hipStream_t);
+                                        hipStream_t, double *);
 
 }  // namespace chom

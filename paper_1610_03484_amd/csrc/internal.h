@@ -13,11 +13,15 @@
 namespace chom {
 
 // Per-column (problem x load case) solver state, device-resident.
+// done: COL_ACTIVE, or why the column stopped (any nonzero value stops it).
+enum { COL_ACTIVE = 0, COL_CONVERGED = 1, COL_BREAKDOWN = 2, COL_NONFINITE = 3, COL_CAPPED = 4 };
 struct ColState {
-    double alpha, beta, rz, rz_init, eref, pq, rz_prev, pad;
-    int done;    // 0 active, 1 converged, 2 breakdown / no progress
-    int iters;
-    int pad2[2];
+    double alpha, beta, rz, rz_init, eref, pq, rz_prev;
+    double energy;   // running estimate of (x_lin + u)^T K (x_lin + u): eref minus alpha r.z of every CG step
+    int done;    // COL_* above
+    int iters;   // CG steps taken by this column (all solves of the call)
+    int iters0;  // iters at the start of the current solve (the cap counts from here)
+    int pad2;
 };
 
 constexpr int FIN_BS = 64;
@@ -105,7 +109,7 @@ hipError_t launch_finish_alpha(const Launch &L, double *acc_pq, ColState *cols, 
 template <int C, int R>
 hipError_t launch_finish_beta(const Launch &L, double *accbuf, const double *ginv, double *ycoef, ColState *cols,
                               int *prob_active, int first, double rtol2, int use_init, const ColState *mask,
-                              hipStream_t s);
+                              hipStream_t s, int max_iter = 0, const ColState *esrc = nullptr);
 template <int C, int R>
 hipError_t launch_proj_resid(const Launch &L, double *r64, float *r32, const double *minv64,
                              const double *ycoef, double *partial, hipStream_t s);
@@ -113,14 +117,17 @@ template <int C, int R>
 hipError_t launch_residual64(const Launch &L, const double *b, const double *q64t, double *r64, float *r32,
                              hipStream_t s);
 hipError_t launch_axpy_x64(long long total, double *x64, const float *d32, hipStream_t s);
+hipError_t launch_axpy64(long long total, double *x64, const double *d64, hipStream_t s);
 // Clears n doubles with a kernel (safe inside captured graphs).
 hipError_t launch_zero(double *p, long long n, hipStream_t s);
 template <int C, int R>
 hipError_t launch_project(const Launch &L, double *x64, const double *minv64, const double *ginv64,
                           double *partial, hipStream_t s);
+// out: energy form of the averages [prob][NC][R]; corr (nullable, with r64):
+// the residual term (1/V) u_i . r_j that separates it from the plain average.
 template <int C, int R>
 hipError_t launch_average(const Launch &L, const double *x64, const double *r64, double *partial, int nwg,
-                          double *out, hipStream_t s);
+                          double *out, hipStream_t s, double *corr = nullptr);
 
 void set_error(const std::string &msg);
 

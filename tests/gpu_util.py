@@ -26,3 +26,41 @@ def upper6(K):
 
 def banner(msg):
     print(f"[gpu-test] {msg}", flush=True)
+
+
+def full6(c21):
+    """Symmetric 6x6 from the 21 upper-triangle entries (row-major)."""
+    M = np.zeros((6, 6))
+    iu = np.triu_indices(6)
+    M[iu] = np.asarray(c21)
+    return M + np.triu(M, 1).T
+
+
+def full3(k6):
+    """Symmetric 3x3 from [xx, yy, zz, xy, yz, xz]."""
+    a = np.asarray(k6)
+    return np.array([[a[0], a[3], a[5]], [a[3], a[1], a[4]], [a[5], a[4], a[2]]])
+
+
+def block_errors(got, ref):
+    """Errors of a symmetric matrix `got` against the symmetric reference `ref`:
+    relative Frobenius norm, largest entry error relative to ||ref||_F, and the
+    energy-weighted error ||ref^-1/2 (got - ref) ref^-1/2||_2 (soft directions of
+    a degraded material count as much as stiff ones)."""
+    got, ref = np.asarray(got, float), np.asarray(ref, float)
+    d = got - ref
+    fro = float(np.linalg.norm(d) / np.linalg.norm(ref))
+    elem = float(np.abs(d).max() / np.linalg.norm(ref))
+    w, V = np.linalg.eigh(0.5 * (ref + ref.T))
+    assert w.min() > 0, "reference not positive definite"
+    h = V @ np.diag(w ** -0.5) @ V.T
+    energy = float(np.abs(np.linalg.eigvalsh(h @ (0.5 * (d + d.T)) @ h)).max())
+    return fro, elem, energy
+
+
+def result_errors(C21, K6, D6, refC21, refK6, refD6):
+    """max over the C, K, D blocks of each measure of block_errors (all three returned)."""
+    out = np.zeros(3)
+    for g, r in ((full6(C21), full6(refC21)), (full3(K6), full3(refK6)), (full3(D6), full3(refD6))):
+        out = np.maximum(out, block_errors(g, r))
+    return tuple(float(v) for v in out)

@@ -1,0 +1,125 @@
+"""GPU parity of the benchmark's own solver configuration against the CPU FP64 oracle.
+
+The benchmark runs the FP32 operator with FP64 refinement, the two-level
+preconditioner (in FP32 the small-grid coarse-level kernel), stopping tolerances
+rtol = inner_rtol = 3e-5 with the energy form of the averages, and launch shapes
+picked by the autotuner.  The same configuration is compared with the oracle:
+
+* n = 8 (hierarchy 8 -> 4, a level-1 coarsest grid), linear Dirichlet, periodic
+  and uniform traction in one batch, on a degraded record, against fresh oracle
+  solves (bordered saddle-point system);
+* n = 12 periodic (hierarchy 12 -> 6 -> 3, a level-2 coarsest grid), the first 16
+  held-out records whose oracle solves are stored in tests/golden, as one batch
+  (16 problems per class: two concurrent CG chains).
+
+Each comparison asserts three measures per block (C, K, D): the relative
+Frobenius error, the largest entry error relative to the block's Frobenius norm,
+and the energy-weighted error ||A_o^-1/2 (A_g - A_o) A_o^-1/2||_2, against the
+targets of the two forms (FP32 operator + FP64 refinement 1e-6; the FP64 path at
+rtol 1e-12, 1e-9).  The reports must show convergence, positive definite
+results and a Hill-Mandel gap within what the stopping tolerance allows.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import chom_inputs as ci
+from oracle import fem as ofem, mesh as omesh
+
+from gpu_util import banner, require_gpu, result_errors
+
+pytestmark = pytest.mark.gpu
+
+BCS = ["dirichlet", "periodic", "neumann"]
+BC_ID = {"dirichlet": ofem.BC_DIRICHLET, "periodic": ofem.BC_PERIODIC, "neumann": ofem.BC_NEUMANN}
+BENCH = dict(precision="fp32_refined", precond="two_level", rtol=3e-5, inner_rtol=3e-5, max_iter=50000)
+FP64 = dict(precision="fp64", precond="two_level", rtol=1e-12, max_iter=50000)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "surrogate_heldout_n12_periodic.txt")
+_CACHE = {}
+
+
+def _autotuned():
+    """Run with the library's autotuner on, as the benchmark does (restored afterwards)."""
+    class _Ctx:
+        def __enter__(self):
+            self.old = os.environ.get("CHOM_AUTOTUNE")
+            os.environ["CHOM_AUTOTUNE"] = "1"
+
+        def __exit__(self, *a):
+            if self.old is None:
+                os.environ.pop("CHOM_AUTOTUNE", None)
+            else:
+                os.environ["CHOM_AUTOTUNE"] = self.old
+    return _Ctx()
+
+
+def _oracle_n8(params):
+    if "n8" not in _CACHE:
+        c, t, ph, ax = omesh.plain_weave(8)
+        iu = np.triu_indices(6)
+        sym3 = [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)]
+        out = []
+        for bc in BCS:
+            r = ofem.homogenise(c, t, ph, ax, 2, BC_ID[bc], ci.BASE_MATERIALS, params)
+            out.append((r["C"][iu], np.array([r["K"][a, b] for a, b in sym3]),
+                        np.array([r["D"][a, b] for a, b in sym3])))
+        _CACHE["n8"] = out
+    return _CACHE["n8"]
+
+
+def _solve(rves_spec, params, opts, tune):
+    from paper_1610_03484_amd import RVE, Batch, generate_plain_weave
+    handles = {}
+    rves = []
+    for n, bc in rves_spec:
+        if (n, bc) not in handles:
+            handles[(n, bc)] = RVE(*generate_plain_weave(n, device="cuda"), ci.BASE_MATERIALS, bc=bc, **opts)
+        rves.append(handles[(n, bc)])
+    batch = Batch(rves)
+    if tune:
+        with _autotuned():
+            res = batch.homogenise(params)
+    else:
+        res = batch.homogenise(params)
+    batch.close()
+    for h in handles.values():
+        h.close()
+    return res
+
+
+def _check(label, res, refs, tol, gap_tol):
+    C, K, D, rep = res
+    worst = np.zeros(3)
+    for i, (rc, rk, rd) in enumerate(refs):
+        e = np.array(result_errors(C[i], K[i], D[i], rc, rk, rd))
+        worst = np.maximum(worst, e)
+        banner(f"  {label} item {i}: fro {e[0]:.2e} elem {e[1]:.2e} energy {e[2]:.2e} "
+               f"iters {max(rep[i]['iters'])} refine {rep[i]['refine_steps']} "
+               f"asym {rep[i]['asym']:.1e} HM gap {rep[i]['hill_mandel_gap']:.1e}")
+        assert rep[i]["status"] == 0 and rep[i]["fail"] == [0] * 12
+        assert rep[i]["spd"] == 1
+        assert rep[i]["hill_mandel_gap"] <= gap_tol
+    assert worst.max() <= tol, (label, worst)
+
+
+def test_bench_configuration_n8_three_bcs():
+    require_gpu()
+    params = ci.draw_params(11, 1)[0]
+    banner(f"bench configuration, 8^3 D/P/N, degraded record {np.round(params[:3], 3)}")
+    refs = _oracle_n8(params)
+    spec = [(8, bc) for bc in BCS]
+    P = np.repeat(params[None], 3, axis=0)
+    _check("fp32-refined", _solve(spec, P, BENCH, True), refs, 1e-6, 1e-3)
+    _check("fp64 two-level", _solve(spec, P, FP64, False), refs, 1e-9, 1e-9)
+
+
+def test_bench_configuration_n12_periodic_golden():
+    require_gpu()
+    a = np.loadtxt(GOLDEN)[:16]
+    params = a[:, 1:12]
+    refs = [(row[12:33], row[33:39], row[39:45]) for row in a]
+    banner("bench configuration, 12^3 periodic, 16 stored oracle records, one batch")
+    spec = [(12, "periodic")] * len(a)
+    _check("fp32-refined", _solve(spec, params, BENCH, True), refs, 1e-6, 1e-3)
+    _check("fp64 two-level", _solve(spec, params, FP64, False), refs, 1e-9, 1e-9)

@@ -1,0 +1,103 @@
+"""Solver failure detection and recovery (GPU, through the C ABI).
+
+Every case here is forced from the host and ends normally on the device:
+
+* iteration cap: max_iter = 1 must stop every load case after one CG step of
+  each solve, still write finite results, and report CHOM_ENOCONV with the cap
+  as the reason (FP64 path, and the refined path with a refinement cap);
+* FP32 range exceeded: every modulus scaled by 1e38 (homogenisation is
+  homogeneous of degree one in the moduli, so C_bar scales by 1e38 exactly)
+  overflows the FP32 operator; the inner solves stop at their first non-finite
+  CG scalar, the refinement stalls, and an FP64 correction solve must finish the
+  mechanical problem: status OK, fp64_fallback set for mechanics only, C_bar =
+  1e38 x the unscaled FP64 result;
+* forced FP64 fallback (CHOM_FORCE_FP64_FALLBACK) on the constrained BCs: the
+  fallback solve (block Jacobi, FP64, masked to the stalled problems) must give
+  the oracle's result.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import chom_inputs as ci
+from oracle import fem as ofem, mesh as omesh
+
+from gpu_util import banner, require_gpu, result_errors
+
+pytestmark = pytest.mark.gpu
+
+BC_ID = {"dirichlet": ofem.BC_DIRICHLET, "periodic": ofem.BC_PERIODIC, "neumann": ofem.BC_NEUMANN}
+
+
+def _rve(n, bc, materials=None, **opts):
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    return RVE(*generate_plain_weave(n, device="cuda"), materials or ci.BASE_MATERIALS, bc=bc, **opts)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_iteration_cap_reports_enoconv(precision):
+    require_gpu()
+    from paper_1610_03484_amd import _lib as L
+    banner(f"iteration cap max_iter=1, {precision}, 5^3 periodic")
+    rve = _rve(5, "periodic", precision=precision, max_iter=1, max_refine=4, rtol=1e-10)
+    C, K, D, rep = rve.homogenise(ci.draw_params(11, 1), allow_noconv=True)
+    rve.close()
+    r = rep[0]
+    banner(f"  status {r['status']} fail {r['fail']} iters {r['iters']} refine {r['refine_steps']}")
+    assert r["status"] == L.CHOM_ENOCONV
+    assert r["fail"] == [L.FAIL_CAP] * 12
+    assert np.all(np.isfinite(C)) and np.all(np.isfinite(K)) and np.all(np.isfinite(D))
+    if precision == "fp64":
+        assert r["iters"] == [1] * 12          # one CG step, not a whole graph chunk of 8
+    else:
+        # one step per inner solve: at most one per refinement pass (FP32 passes and FP64 fallbacks)
+        assert max(r["iters"]) <= 5
+
+
+def test_fp32_overflow_falls_back_to_fp64():
+    require_gpu()
+    s = 1e38
+    mat = dict(ci.BASE_MATERIALS)
+    for k in ("E", "E1", "E2", "G12"):
+        mat[k] = mat[k] * s
+    params = ci.draw_params(11, 1)
+    banner("moduli x 1e38 (beyond FP32), 6^3 Dirichlet, FP32-refined vs the FP64 path at scale 1")
+    rve = _rve(6, "dirichlet", materials=mat, precision="fp32_refined", rtol=1e-10, inner_rtol=1e-4)
+    C, K, D, rep = rve.homogenise(params)
+    rve.close()
+    ref = _rve(6, "dirichlet", precision="fp64", rtol=1e-12)
+    Cr, Kr, Dr, _ = ref.homogenise(params)
+    ref.close()
+    r = rep[0]
+    e = result_errors(C[0] / s, K[0], D[0], Cr[0], Kr[0], Dr[0])
+    banner(f"  status {r['status']} fallback {r['fp64_fallback']} refine {r['refine_steps']} errors {e}")
+    assert r["status"] == 0
+    assert r["fp64_fallback"] == [1, 0, 0]
+    assert max(e) <= 1e-8
+
+
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+def test_forced_fp64_fallback_matches_oracle(bc):
+    require_gpu()
+    n = 5
+    params = ci.draw_params(11, 1)
+    banner(f"forced FP64 fallback, {n}^3 {bc}")
+    os.environ["CHOM_FORCE_FP64_FALLBACK"] = "1"
+    try:
+        rve = _rve(n, bc, precision="fp32_refined", rtol=1e-10, inner_rtol=1e-4)
+        C, K, D, rep = rve.homogenise(params)
+        rve.close()
+    finally:
+        os.environ.pop("CHOM_FORCE_FP64_FALLBACK", None)
+    c, t, ph, ax = omesh.plain_weave(n)
+    o = ofem.homogenise(c, t, ph, ax, 2, BC_ID[bc], ci.BASE_MATERIALS, params[0])
+    iu = np.triu_indices(6)
+    sym3 = [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)]
+    e = result_errors(C[0], K[0], D[0], o["C"][iu], [o["K"][a, b] for a, b in sym3],
+                      [o["D"][a, b] for a, b in sym3])
+    r = rep[0]
+    banner(f"  status {r['status']} fallback {r['fp64_fallback']} refine {r['refine_steps']} errors {e}")
+    assert r["status"] == 0
+    assert r["fp64_fallback"] == [1, 1, 1]
+    assert max(e) <= 1e-9

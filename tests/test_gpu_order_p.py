@@ -2,8 +2,8 @@
 against the CPU FP64 oracle (Lagrange P3/P4, exact integration).
 
 Sizes: n = 2 and 3 cells per side (up to 13^3 lattice points at p = 4); the
-operator works on batches of 16 tets, so both sizes end in a ragged batch
-(6 n^3 = 48 and 162 tets).  Tolerances as at order 2: FP64 path 1e-9, FP32
+operator gives each workgroup one cell (its six tets), so these sizes exercise
+lattice wrap-around and boundary cells on every side.  Tolerances as at order 2: FP64 path 1e-9, FP32
 operator with FP64 refinement 1e-6 (relative Frobenius error of each block).
 """
 import numpy as np

@@ -114,3 +114,19 @@ def test_tagger_axes_and_no_overlap():
             ph, _ = mesh.yarn_test(np.full_like(x, off), x, zc)
             ph2, _ = mesh.yarn_test(np.full_like(x, off), x, zc + 0.07)
         assert np.all(ph > 0) and np.all(ph2 == 0)
+
+
+def test_yarn_test_values_and_tangents_agree_with_the_tagger():
+    """The per-yarn ellipse values and tangents (used to judge exact-tie tags) give
+    the tagger's phase (first yarn with f <= 1) and axis on every tet."""
+    for n in (3, 8):
+        c, t, ph, ax = mesh.plain_weave(n)
+        cen = mesh.centroids(c, t)
+        f = mesh.yarn_test_values(cen[:, 0], cen[:, 1], cen[:, 2])
+        tang = mesh.yarn_tangents(cen[:, 0], cen[:, 1], cen[:, 2])
+        inside = f <= 1.0
+        first = np.where(inside.any(axis=1), inside.argmax(axis=1) + 1, 0)
+        assert np.array_equal(first, ph)
+        yarn = ph > 0
+        assert np.allclose(tang[yarn, ph[yarn] - 1], ax[yarn], rtol=0, atol=1e-15)
+        assert np.allclose(np.linalg.norm(tang, axis=-1), 1.0)
