@@ -346,6 +346,22 @@ int chom_mlp_train(chom_mlp *mlp, const chom_params *params, const double *C, co
 int chom_mlp_loss_grad(chom_mlp *mlp, int32_t member, const chom_params *params, const double *C,
                        const double *K, const double *D, int64_t n, double *loss, float *grad);
 
+/* chom_mlp_loss_grad without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc).  The same kernels and results as
+ * chom_mlp_loss_grad, but every pointer is a device pointer -- params [n]
+ * (chom_params), C [n][21], K [n][6], D [n][6] in, *loss (one double) and grad
+ * [143,652] (FP32) out -- whatever the handle's device_ptrs setting, and the
+ * working memory (standardised rows, flag, training scratch; about 3.4 MB) is a
+ * static array of the library that each device holds until the process ends.
+ * n is limited to 4096 records (CHOM_EINVAL beyond).  Calls that overlap on one
+ * device share that array and race: serialise them.  Work is queued on the
+ * handle's stream; the call returns after the input check has been read back.
+ * Errors: CHOM_EINVAL (argument, n, member, no standardisation record, records
+ * outside the degradation law's domain), CHOM_EDEVICE. */
+int chom_mlp_loss_grad_noalloc(chom_mlp *mlp, int32_t member, const chom_params *params, const double *C,
+                               const double *K, const double *D, int64_t n, double *loss, float *grad);
+
 /* Ensemble prediction for n records: member mean in physical units (C, K, D)
  * and the disagreement (nullable).  Needs a standardisation record.
  * Errors: CHOM_EINVAL (records outside the law's domain), CHOM_EDEVICE. */

@@ -102,6 +102,8 @@ SIGNATURES = {
                                   ct.POINTER(ChomMlpTrainOptions), ct.c_void_p]),
     "chom_mlp_loss_grad": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                       ct.c_void_p, ct.c_int64, ct.POINTER(ct.c_double), ct.c_void_p]),
+    "chom_mlp_loss_grad_noalloc": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                              ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p]),
     "chom_mlp_predict": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                     ct.c_void_p]),
     "chom_homogenise_surrogate": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_double,

@@ -322,6 +322,14 @@ class Surrogate:
                                            ct.byref(loss), _ptr(g)), "chom_mlp_loss_grad")
         return loss.value, g
 
+    def loss_grad_noalloc(self, member, params, C, K, D, loss, grad):
+        """chom_mlp_loss_grad_noalloc: every argument a contiguous torch device tensor
+        (params [n,11], C [n,21], K [n,6], D [n,6] float64; loss [1] float64 and
+        grad [143652] float32 written)."""
+        n = params.shape[0]
+        L.check(L.lib().chom_mlp_loss_grad_noalloc(self._h, member, _ptr(params), _ptr(C), _ptr(K), _ptr(D), n,
+                                                   _ptr(loss), _ptr(grad)), "chom_mlp_loss_grad_noalloc")
+
     def _outputs(self, n):
         if self.device:
             import torch

@@ -21,7 +21,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include")]
-SOURCES = ["mesh.hip", "setup.hip", "operator.hip", "cg.hip", "mg.hip", "hom.hip", "mlp.hip", "api.cpp", "mlp_api.cpp", "hp_tables.cpp", "hp.hip"]
+SOURCES = ["mesh.hip", "setup.hip", "operator.hip", "cg.hip", "mg.hip", "hom.hip", "mlp.hip", "api.cpp", "mlp_api.cpp", "hp_tables.cpp", "hp.hip",
+           "mlp_noalloc.hip"]
 
 
 def _compile(src: str) -> str:

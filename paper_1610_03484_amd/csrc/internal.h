@@ -172,6 +172,10 @@ hipError_t launch_operator_hp(const Launch &L, int nprob, int rg, const T *x, T 
 int rve_homogenise_host(chom_rve *rve, const chom_params *params, int batch, double *C, double *K, double *D,
                         chom_report *rep);
 void rve_settings(const chom_rve *rve, double *c_sat, int *degrade_yarn);
+// Surrogate gradient evaluation in a caller-provided device workspace (mlp_api.cpp).
+int mlp_loss_grad_ws(chom_mlp *m, int member, const double *p, const double *c, const double *k, const double *d,
+                     long long n, double *loss, float *grad, unsigned char *ws, long long max_rows);
+bool mlp_ready(const chom_mlp *m, int member);
 
 #define CHOM_HIP(...)                                                                          \
     do {                                                                                       \

@@ -38,6 +38,17 @@ constexpr int NORM_LEN = 2 * NF + 2 * NO;
 constexpr long long SCRATCH_BYTES = 2LL * NB * FP * 2 + (long long)NB * NO * 4 + 6LL * NB * H * 2 +
                                     3LL * NB * H * 4 + 2LL * NB * OP * 2 + 6LL * NB * H * 2;
 
+// Workspace of a gradient evaluation in caller-provided memory (no allocation):
+// the bad-record flag, the standardised rows of up to `rows` records (bfloat16
+// features, FP32 targets) and one training workgroup's minibatch scratch, each
+// part 256-byte aligned.
+constexpr long long ws_align(long long b) { return (b + 255) / 256 * 256; }
+constexpr long long WS_FLAG = 0;
+constexpr long long WS_XN = 256;
+constexpr long long ws_tn(long long rows) { return WS_XN + ws_align(rows * FP * 2); }
+constexpr long long ws_train(long long rows) { return ws_tn(rows) + ws_align(rows * NO * 4); }
+constexpr long long ws_bytes(long long rows) { return ws_train(rows) + ws_align(SCRATCH_BYTES); }
+
 // Degradation law of Sec. 4 (constant exposure).
 constexpr double BETA = -0.001682;    // per day
 constexpr double TG_CELSIUS = 126.0;

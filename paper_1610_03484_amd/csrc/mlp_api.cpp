@@ -142,6 +142,57 @@ int predict_device(chom_mlp *m, const double *p, long long n, double *C, double 
 
 }  // namespace
 
+namespace chom {
+
+// chom_mlp_loss_grad's evaluation on device inputs and outputs, with the rows,
+// the flag and the training scratch in the caller's workspace `ws` (layout of
+// mlp::ws_bytes(max_rows), 256-byte aligned): no allocation.  All work is queued
+// on the handle's stream; returns after the flag has been read back.
+int mlp_loss_grad_ws(chom_mlp *m, int member, const double *p, const double *c, const double *k, const double *d,
+                     long long n, double *loss, float *grad, unsigned char *ws, long long max_rows) {
+    if (n < 1 || n > max_rows) {
+        set_error("workspace holds at most " + std::to_string(max_rows) + " records");
+        return CHOM_EINVAL;
+    }
+    int *flag = reinterpret_cast<int *>(ws + M_::WS_FLAG);
+    uint16_t *xn = reinterpret_cast<uint16_t *>(ws + M_::WS_XN);
+    float *tn = reinterpret_cast<float *>(ws + M_::ws_tn(max_rows));
+    unsigned char *tr = ws + M_::ws_train(max_rows);
+    // a fill kernel, not a memset, clears the flag (the zero bit pattern)
+    CHOM_HIP(M_::launch_fill(reinterpret_cast<float *>(flag), 1, 0.0f, m->stream));
+    CHOM_HIP(M_::launch_prepare(p, c, k, d, n, m->opt.c_sat, m->norm.p, xn, tn, flag, m->stream));
+    CHOM_HIP(M_::launch_fill(grad, M_::NPARAM, 0.0f, m->stream));
+    M_::TrainArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.xn = xn;
+    a.tn = tn;
+    a.n = n;
+    a.epochs = 1;
+    a.nb = M_::NB;
+    a.lr0 = a.lr1 = 0.0f;
+    a.beta1 = 0.9f;
+    a.beta2 = 0.999f;
+    a.eps = 1e-8f;
+    a.member = member;
+    a.grad = grad;
+    a.loss_out = loss;
+    a.W = m->weights();
+    a.scratch = tr;
+    CHOM_HIP(M_::launch_train(a, 1, m->stream));
+    int bad = 0;
+    CHOM_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, m->stream));
+    CHOM_HIP(hipStreamSynchronize(m->stream));
+    if (bad) {
+        set_error("a record is outside the degradation law's domain or a result is not finite");
+        return CHOM_EINVAL;
+    }
+    return CHOM_OK;
+}
+
+bool mlp_ready(const chom_mlp *m, int member) { return m && m->has_norm && member >= 0 && member < m->members; }
+
+}  // namespace chom
+
 extern "C" {
 
 int chom_mlp_default_options(chom_mlp_options *opt) {
