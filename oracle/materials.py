@@ -14,7 +14,9 @@ vector): [11, 22, 33, 12, 23, 31] with engineering shear strains (2*eps_ij).
   temperatures in kelvin, beta = -0.001682 per day, T_g = 126 C; the moisture
   factor gamma(c) is linear with gamma(0) = 0 and gamma(saturation) = 1 (Eq.
   Eq_Model3); for constant exposure the stiffness factor is
-  (1 - omega) = exp(-gamma(c) alpha(T) t) (Eq. Eq_Model_final1), t in days.
+  (1 - omega) = exp(-gamma(c) alpha(T) t) (Eq. Eq_Model_final1), t in days;
+  for time-varying exposure the rate form (Eq. Eq_Model_RateForm) is stepped
+  with backward Euler, as the paper states.
   Only the matrix is degraded (Sec. 5, end of the FE^2 description).
 """
 from __future__ import annotations
@@ -136,6 +138,35 @@ def stiffness_factor(T_celsius, c, t_years, c_sat=1.5):
     """(1 - omega) = exp(-gamma(c) alpha(T) t) for constant exposure (Eq. Eq_Model_final1)."""
     t_days = np.asarray(t_years, float) * DAYS_PER_YEAR
     return np.exp(-gamma_of_c(c, c_sat) * alpha_of_T(T_celsius) * t_days)
+
+
+def damage_history(T_celsius, c, dt_years, keep0=1.0, c_sat=1.5):
+    """(1 - omega) after every step of a time history (Sec. 4, Eq. Eq_Model_RateForm).
+
+    The rate form d(1 - omega)/dt = -gamma(c) alpha(T) (1 - omega) is discretised
+    with the implicit (backward) Euler method the paper names: over step k, of
+    length dt_k (days) with exposure T_k, c_k,
+        (1 - omega)_k - (1 - omega)_{k-1} = -dt_k gamma(c_k) alpha(T_k) (1 - omega)_k,
+    solved for (1 - omega)_k (the equation is linear in it).
+    T_celsius, c: [m, n] (step k of every point in row k); dt_years: [m];
+    keep0: (1 - omega) before the first step, scalar or [n].  Returns [m, n].
+    """
+    T = np.atleast_2d(np.asarray(T_celsius, float))
+    cc = np.atleast_2d(np.asarray(c, float))
+    dt_days = np.asarray(dt_years, float).reshape(-1) * DAYS_PER_YEAR
+    keep = np.broadcast_to(np.asarray(keep0, float), T.shape[1:]).copy()
+    out = np.empty_like(T)
+    for k in range(T.shape[0]):
+        rate = gamma_of_c(cc[k], c_sat) * alpha_of_T(T[k])      # per day
+        keep = keep / (1.0 + dt_days[k] * rate)
+        out[k] = keep
+    return out
+
+
+def equivalent_exposure_years(keep, T_ref_celsius=60.0):
+    """Time (years) of constant exposure at T_ref and full saturation (gamma = 1)
+    after which Eq. Eq_Model_final1 gives the factor `keep`."""
+    return -np.log(np.asarray(keep, float)) / (alpha_of_T(T_ref_celsius) * DAYS_PER_YEAR)
 
 
 def fit_beta(T_celsius, alphas, Tg_celsius=TG_CELSIUS, kelvin=True):

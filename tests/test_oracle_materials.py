@@ -125,3 +125,64 @@ def test_phase_materials_groups():
     assert np.isclose(m["E"], 3.5 * 1.1 * keep) and np.isclose(m["nu"], 0.35 * 0.9)
     assert np.isclose(y["E1"], 55 * 1.02) and np.isclose(y["G12"], 4.5 * 1.02)
     assert np.isclose(y["nu23"], 0.4 * 0.98) and np.isclose(y["D2"], 0.2 * 0.99)
+
+
+# ---------------------------------------------------------------- time-history degradation
+def test_damage_history_converges_at_first_order_to_the_closed_form():
+    """Constant exposure: backward Euler on the rate form approaches Eq.
+    Eq_Model_final1 from above (implicit Euler over-estimates exp(-x)), with the
+    error halving as the step halves; a forward step or a dropped moisture factor
+    would fail one of these."""
+    T, c, years = 60.0, 1.2, 3.0
+    exact = float(M.stiffness_factor(T, c, years))
+    errs = []
+    for m in (50, 100, 200, 400):
+        h = M.damage_history(np.full((m, 1), T), np.full((m, 1), c), np.full(m, years / m))
+        assert h[-1, 0] > exact
+        errs.append(h[-1, 0] - exact)
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(1.9 < r < 2.1 for r in ratios), ratios
+    assert errs[-1] < 1e-2 * exact    # (lambda t)^2 / (2 m) relative: 0.9% at m = 400
+
+
+def test_damage_history_piecewise_exposure_limit():
+    """Two exposure phases: as the step shrinks the history tends to the exact
+    solution of the rate form with piecewise-constant inputs,
+    exp(-gamma1 alpha1 t1 - gamma2 alpha2 t2), not to a restart of the closed form."""
+    (T1, c1, t1), (T2, c2, t2) = (40.0, 1.5, 2.0), (70.0, 0.5, 1.0)
+    lam1 = M.gamma_of_c(c1) * M.alpha_of_T(T1) * t1 * M.DAYS_PER_YEAR
+    lam2 = M.gamma_of_c(c2) * M.alpha_of_T(T2) * t2 * M.DAYS_PER_YEAR
+    exact = np.exp(-lam1 - lam2)
+    m = 4000
+    T = np.r_[np.full(m, T1), np.full(m, T2)][:, None]
+    c = np.r_[np.full(m, c1), np.full(m, c2)][:, None]
+    dt = np.r_[np.full(m, t1 / m), np.full(m, t2 / m)]
+    h = M.damage_history(T, c, dt)
+    assert abs(h[m - 1, 0] - np.exp(-lam1)) < 1e-3 * np.exp(-lam1)
+    assert abs(h[-1, 0] - exact) < 1e-3 * exact
+
+
+def test_damage_history_invariants():
+    """Dry material and absolute zero do not degrade (Sec. 4: degradation stops
+    at 0 K); the factor never rises; the final value does not depend on the order
+    of the steps (each step multiplies by its own factor); keep0 scales the result."""
+    rng = np.random.default_rng(3)
+    m, n = 30, 5
+    T = rng.uniform(20, 60, (m, n))
+    c = rng.uniform(0, 1.5, (m, n))
+    dt = rng.uniform(0.01, 0.5, m)
+    assert np.all(M.damage_history(T, np.zeros((m, n)), dt) == 1.0)
+    assert np.all(M.damage_history(np.full((m, n), -M.KELVIN), c, dt) == 1.0)
+    h = M.damage_history(T, c, dt)
+    assert np.all(np.diff(np.vstack([np.ones(n), h]), axis=0) <= 0.0) and np.all(h > 0)
+    perm = rng.permutation(m)
+    hp = M.damage_history(T[perm], c[perm], dt[perm])
+    np.testing.assert_allclose(hp[-1], h[-1], rtol=1e-13)
+    keep0 = rng.uniform(0.2, 1.0, n)
+    np.testing.assert_allclose(M.damage_history(T, c, dt, keep0=keep0), h * keep0, rtol=1e-13)
+
+
+def test_equivalent_exposure_reproduces_the_factor():
+    keep = np.array([1.0, 0.9, 0.3, 1e-3])
+    t = M.equivalent_exposure_years(keep)
+    np.testing.assert_allclose(M.stiffness_factor(60.0, 1.5, t, c_sat=1.5), keep, rtol=1e-12)
