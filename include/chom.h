@@ -194,6 +194,29 @@ int chom_generate_plain_weave(int32_t n, double *coords, int32_t *tets, int8_t *
 int chom_rve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc_type,
                     int32_t order, const chom_options *opt, chom_rve **out);
 
+/* Matrix damage under time-varying exposure at n macro Gauss points (Sec. 4,
+ * Eq. Eq_Model_RateForm): d(1 - omega)/dt = -gamma(c) alpha(T) (1 - omega) with
+ * alpha, gamma as in chom_params, stepped with implicit (backward) Euler as the
+ * paper states: over step k, (1 - omega)_k = (1 - omega)_{k-1} /
+ * (1 + gamma(c_k) alpha(T_k) dt_k).  For constant exposure it tends to the
+ * closed form of chom_params (Eq. Eq_Model_final1) at first order in dt.
+ * Inputs: T_celsius [m][n] and c_wt [m][n] (step-major: step k of every point
+ * is row k), dt_years [m], keep0 [n] (nullable: 1, undamaged), factors [n][8]
+ * (nullable: 1; copied into params_out).  Outputs (at least one non-null):
+ * keep [m][n], (1 - omega) after every step; params_out [n], for each point an
+ * equivalent constant-exposure record -- T = 60 C, c = c_sat (gamma = 1) and the
+ * exposure time after which the closed form gives the final (1 - omega) -- that
+ * chom_homogenise, chom_batch_homogenise and the surrogate take as they are
+ * (use the same c_sat there).  device_ptrs: 1 if every array is device memory,
+ * 0 if every array is host memory.  Work is queued on hip_stream (NULL: null
+ * stream); the call returns when the outputs are written.
+ * Errors: CHOM_EINVAL (sizes, null arrays, c_sat <= 0, or an exposure outside the
+ * law's domain: T >= T_g, c < 0, dt < 0, keep0 outside (0, 1]), CHOM_EDEVICE,
+ * CHOM_ENOMEM. */
+int chom_damage_history(int64_t n, int32_t m, const double *T_celsius, const double *c_wt, const double *dt_years,
+                        const double *keep0, const double *factors, double c_sat, int32_t device_ptrs,
+                        void *hip_stream, double *keep, chom_params *params_out);
+
 /* Homogenise the RVE for `batch` parameter records: 6 mechanical + 3 thermal
  * + 3 moisture load cases each.  Outputs: C_hom [batch][21], K_hom [batch][6],
  * D_hom [batch][6], rep [batch] (rep may be NULL; rep is always host memory).

@@ -72,6 +72,9 @@ SIGNATURES = {
     "chom_homogenise": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                    ct.POINTER(ChomReport)]),
     "chom_rve_destroy": (None, [ct.c_void_p]),
+    "chom_damage_history": (ct.c_int, [ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                       ct.c_void_p, ct.c_double, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                       ct.c_void_p]),
     "chom_last_error": (ct.c_char_p, []),
     "chom_material_constants": (ct.c_int, [ct.POINTER(ChomMaterials), ct.POINTER(ChomParams), ct.c_double,
                                            ct.c_int32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),

@@ -76,6 +76,32 @@ def material_constants(materials: dict, params=None, c_sat=1.5, degrade_yarn=0):
     return np.array(mech[:]), np.array(th[:]), np.array(mo[:]), keep.value
 
 
+def damage_history(T_celsius, c_wt, dt_years, keep0=None, factors=None, c_sat=1.5, keep=True, params=True,
+                   hip_stream=None):
+    """chom_damage_history.  T_celsius, c_wt [m, n] (step-major), dt_years [m], keep0 [n],
+    factors [n, 8]: all numpy arrays (host) or all contiguous torch device tensors
+    (float64).  Returns (keep [m, n] or None, params [n, 11] or None) in the same
+    kind of memory."""
+    dev = hasattr(T_celsius, "data_ptr")
+    m, n = T_celsius.shape
+    if dev:
+        import torch
+        mk = lambda *s: torch.empty(s, dtype=torch.float64, device=T_celsius.device)
+        conv = lambda a: a
+        if hip_stream is None:
+            hip_stream = torch.cuda.current_stream(T_celsius.device).cuda_stream
+    else:
+        mk = lambda *s: np.zeros(s)
+        conv = lambda a: None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    T, c, dt, k0, f = (conv(a) for a in (T_celsius, c_wt, dt_years, keep0, factors))
+    out_keep = mk(m, n) if keep else None
+    out_par = mk(n, 11) if params else None
+    L.check(L.lib().chom_damage_history(n, m, _ptr(T), _ptr(c), _ptr(dt), _ptr(k0), _ptr(f), c_sat, int(dev),
+                                        ct.c_void_p(hip_stream) if hip_stream else None, _ptr(out_keep),
+                                        _ptr(out_par)), "chom_damage_history")
+    return out_keep, out_par
+
+
 class RVE:
     """Handle of chom_rve_create; homogenise() wraps chom_homogenise."""
 

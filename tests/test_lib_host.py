@@ -303,3 +303,17 @@ def test_order_p_lattice_points_number_the_dofs(L, p):
         for e, (x, y) in enumerate(edges):
             for s in range(p - 1):
                 np.testing.assert_array_equal(off[t, 4 + e * (p - 1) + s], v[x] + (s + 1) * (v[y] - v[x]) // p)
+
+
+def test_damage_history_argument_errors(L):
+    """Checks that fail before any device work."""
+    lib = L.lib()
+    a = np.ones((2, 3))
+    dt = np.ones(2)
+    out = np.zeros((2, 3))
+    p = lambda x: x.ctypes.data
+    # no output, m < 1, c_sat <= 0
+    assert lib.chom_damage_history(3, 2, p(a), p(a), p(dt), None, None, 1.5, 0, None, None, None) == L.CHOM_EINVAL
+    assert lib.chom_damage_history(3, 0, p(a), p(a), p(dt), None, None, 1.5, 0, None, p(out), None) == L.CHOM_EINVAL
+    assert lib.chom_damage_history(3, 2, p(a), p(a), p(dt), None, None, 0.0, 0, None, p(out), None) == L.CHOM_EINVAL
+    assert lib.chom_damage_history(3, 2, None, p(a), p(dt), None, None, 1.5, 0, None, p(out), None) == L.CHOM_EINVAL
