@@ -1,28 +1,42 @@
 #!/usr/bin/env python
-"""Benchmark: RVE homogenisations per second on one MI355X.
+"""Benchmark: RVE homogenisations per second on one MI355X, plain vs batched vs surrogate.
 
-Workload (default "c1"): the synthetic plain-weave RVE on a 24^3 Kuhn lattice
-(82,944 tets), order-2 hierarchic basis (352,947 elastic DOFs), homogenised
-under each of the three boundary conditions (linear Dirichlet, periodic,
-uniform traction), 6 mechanical + 3 thermal + 3 moisture load cases each,
-FP32 operator with FP64 CG reductions, constraint projection, refinement
-residual and volume average.  One step = the three homogenisations.  The mesh,
-tags and element data are resident on the GPU before timing starts.
+Default workload ("c2"): 512 parameter records, one per macro Gauss point, each
+on a synthetic plain-weave RVE whose size is drawn uniformly from
+{8, 12, 16, 20, 24}^3 cells, order-2 hierarchic basis, periodic conditions,
+degraded by the paper's law at T ~ U(20, 60) C, c ~ U(0, 1.5) wt%,
+t ~ U(0, 10) years with seeded property factors; 6 mechanical + 3 thermal + 3
+moisture load cases each; FP32 operator with FP64 reductions, projection,
+refinement residual and averages.  One step = the whole batch in one
+chom_batch_homogenise call (`value`).  Meshes, tags and element data are
+resident on the GPU before timing starts.
 
-Also reported (outside the timed region):
-  * the error of the timed results against the FP64 GPU path on the same RVE
-    (the FP64 path is checked against the CPU oracle at smaller sizes by tests);
-  * the roofline record of the dominant kernel (the FP32 mechanical operator):
-    HIP-event timing of its launches, algorithmic bytes/flops per launch;
-  * the CPU oracle timed on the host on a bounded sample.
+Also measured, outside the timed region, into `config`:
+  * plain GPU path: the same 512 records, one chom_homogenise call per record
+    (same options), and the batched-over-plain speedup;
+  * C0: the 8^3 linear-Dirichlet FP64 RVE, one call per record, with its error
+    against a fresh oracle solve;
+  * accuracy of the batch: items solved by the CPU oracle in this run (the 8^3
+    items of the cpu_baseline sample), and one item of every size against the
+    FP64 GPU path at rtol 1e-12 (labelled as such); relative Frobenius,
+    largest-entry and energy-weighted errors;
+  * surrogate (unless --no-surrogate): the ensemble trained on 12^3 solves, run
+    on 1,000,000 records with fallback, its held-out error against stored
+    oracle solves and its speedup over the plain and batched paths;
+  * the damage-history kernel (time-varying exposure) on 1,000,000 points x
+    100 steps, against the HBM peak;
+  * roofline of the dominant kernel (the FP32 mechanical operator on the batch),
+    from HIP events on the library's stream.
+`cpu_baseline`: the oracle on host cores, on the 8^3 records of the batch.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c0|c3|c4]
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import subprocess
 import sys
 import time
@@ -36,8 +50,13 @@ if ROOT not in sys.path:
 HBM_PEAK = 8.0e12          # B/s, MI355X HBM3E
 FP32_VEC_PEAK = 157.3e12   # flop/s, MI355X FP32 vector (published)
 FP64_VEC_PEAK = 78.6e12
+METRIC = "RVE homogenisations/s (12 load cases) @ stated C_hom error: plain vs batched vs MLP"
 
 WORKLOADS = {
+    "c2": dict(n=None, bcs=("periodic",), precision="fp32_refined",
+               desc="512 RVEs (one per macro Gauss point) with sizes uniform over {8,12,16,20,24}^3 cells, "
+                    "p=2, periodic, degraded (T~U(20,60) C, c~U(0,1.5) wt%, t~U(0,10) y, factors U(0.9,1.1)), "
+                    "12 load cases each, FP32 operator + FP64 refinement, one batched call"),
     "c1": dict(n=24, bcs=("dirichlet", "periodic", "neumann"), precision="fp32_refined",
                desc="24^3 Kuhn plain-weave RVE (82,944 tets), p=2 (352,947 elastic DOFs), "
                     "Dirichlet+periodic+Neumann in one batch, 6+3+3 load cases each, FP32 operator + FP64 refinement"),
@@ -52,45 +71,20 @@ WORKLOADS = {
                desc="p-refinement: batch of 16^3 Kuhn plain-weave RVEs (24,576 tets each) at order p (3: 352,947, "
                     "4: 823,875 elastic DOFs), periodic, degraded records as in the batched workload, element "
                     "operator on the FP32 matrix cores with FP64 refinement"),
-    "c2": dict(n=None, bcs=("periodic",), precision="fp32_refined",
-               desc="batch of RVEs with sizes uniform over {8,12,16,20,24}^3 cells, p=2, periodic, degraded "
-                    "(T~U(20,60) C, c~U(0,1.5) wt%, t~U(0,10) y, factors U(0.9,1.1)), 12 load cases each, "
-                    "FP32 operator + FP64 refinement, one batch"),
 }
 
 
+# ---------------------------------------------------------------- algorithmic counts
 def algorithmic_mech(n, nprob, fp32):
-    """Bytes and flops of one mechanical operator launch (6 load cases) per the
-    survey's definition: bytes = sum_RHS 2 ndof s + T (conn + n_A s),
-    flops = T n_RHS 2 n_e^2, with conn = 40 B, n_A = 45, n_e = 30 at p = 2."""
+    """Bytes and flops of one mechanical operator launch (6 load cases) per problem:
+    bytes = sum_RHS 2 ndof s + T (conn + n_A s), flops = T n_RHS 2 n_e^2, with
+    conn = 40 B, n_A = 45, n_e = 30 at p = 2 (the dense element-block contraction)."""
     s = 4 if fp32 else 8
     T = 6 * n ** 3
     ndof = 3 * (2 * n + 1) ** 3
     bytes_ = 6 * 2 * ndof * s + T * (40 + 45 * s)
     flops = T * 6 * 2 * 30 ** 2
     return bytes_ * nprob, flops * nprob
-
-
-CAL_BYTES = 256 << 20
-
-
-def calibration_copy(torch):
-    """Three device-to-device copies of 256 MiB (outside the timed region): the plain
-    copy of known size against which rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled."""
-    x = torch.ones(CAL_BYTES // 4, dtype=torch.float32, device="cuda:0")
-    y = torch.empty_like(x)
-    for _ in range(3):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    del x, y
-
-
-# HBM traffic of one launch of op_p2_kernel<float,3,6,RG> on the default workload (three
-# 24^3 items, all active) per load-case grouping RG, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE scaled by the calibration copy
-# (profiles/op_p2_mech_fp32_24cubed_three_bc_traffic.md).  Must be re-measured (or set
-# to None) whenever that kernel changes.
-C1_OP_TRAFFIC_BYTES = {1: 124257650, 2: 128732682, 3: 108221564}
 
 
 def algorithmic_mech_order(n, p, nprob, fp32):
@@ -106,225 +100,53 @@ def algorithmic_mech_order(n, p, nprob, fp32):
     return bytes_ * nprob, flops * nprob
 
 
-CPU_SAMPLE_CODE = r"""
-import sys, time, json
-sys.path.insert(0, {root!r})
-import chom_inputs as ci
-from oracle import fem, mesh
-n = {n}
-params = ci.draw_factors_only(0, 1)[0]
-c, t, ph, ax = mesh.plain_weave(n)
-t0 = time.perf_counter()
-count = 0
-for bc in (fem.BC_DIRICHLET, fem.BC_PERIODIC, fem.BC_NEUMANN):
-    fem.homogenise(c, t, ph, ax, 2, bc, ci.BASE_MATERIALS, params)
-    count += 1
-dt = time.perf_counter() - t0
-print(json.dumps(dict(count=count, seconds=dt)))
-"""
+# HBM traffic of one all-active launch of op_p2_kernel<float,3,6,RG>, rocprofv3
+# FETCH_SIZE + WRITE_SIZE scaled by the calibration copy, per workload and load-case
+# grouping RG (profiles/op_p2_mech_fp32_*_traffic.md).  Must be re-measured (or the
+# entry removed) whenever that kernel changes.
+OP_TRAFFIC_BYTES = {
+    "c1": {1: 124257650, 2: 128732682, 3: 108221564},
+}
+
+CAL_BYTES = 256 << 20
 
 
-def cpu_baseline(n_sample=8):
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
-               CUDA_VISIBLE_DEVICES="", HIP_VISIBLE_DEVICES="")
-    code = CPU_SAMPLE_CODE.format(root=ROOT, n=n_sample)
-    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
-    if res.returncode != 0:
-        return None
-    rec = json.loads(res.stdout.strip().splitlines()[-1])
-    return dict(value=rec["count"] / rec["seconds"], unit="homogenisations/s", cores=1, kind="oracle",
-                sample=(f"CPU FP64 oracle (Lagrange P2, SuperLU saddle point, factorised once per BC and "
-                        f"physics) on the {n_sample}^3 plain-weave RVE, Dirichlet+periodic+Neumann x 12 load "
-                        f"cases = {rec['count']} homogenisations in {rec['seconds']:.1f} s on 1 thread; the "
-                        f"24^3 RVE is not run (about 40 min per mechanical factorisation), so this rate "
-                        f"overstates the oracle's rate on the benchmark RVE"))
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOADS))
-    ap.add_argument("--op-reps", type=int, default=50)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--items", type=int, default=512, help="items of the c2 batch")
-    ap.add_argument("--precond", default="two_level", choices=["block_jacobi", "two_level"],
-                    help="CG preconditioner (two_level: block Jacobi plus a P1 multigrid coarse correction)")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="fixed launch shape instead of the library's autotuner (which runs in the warm-up)")
-    ap.add_argument("--order", type=int, default=4, help="c3: polynomial order (3 or 4)")
-    ap.add_argument("--rtol", type=float, default=3e-5,
-                    help="stopping tolerance of the FP64 residual (relative to the linear-field energy); with "
-                         "the library's energy-form averages the default keeps C_hom >= 10x inside the 1e-6 "
-                         "target of the FP32-refined form (the error against the FP64 path is measured and "
-                         "reported each run)")
-    ap.add_argument("--inner-rtol", type=float, default=3e-5, help="FP32 inner solve tolerance per refinement pass")
-    ap.add_argument("--train", type=int, default=20000, help="c4: training solves")
-    ap.add_argument("--epochs", type=int, default=300, help="c4: training epochs")
-    ap.add_argument("--points", type=int, default=1_000_000, help="c4: surrogate evaluation points")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (the RVE batches would shard across GPUs without "
-              f"communication, but no multi-GPU path is built); got --gpus {args.gpus}", file=sys.stderr)
-        sys.exit(2)
-
-    if not args.no_autotune:
-        os.environ.setdefault("CHOM_AUTOTUNE", "1")
-    import torch
-    import chom_inputs as ci
-    from paper_1610_03484_amd import RVE, generate_plain_weave
-
-    if not torch.cuda.is_available():
-        print("bench.py: needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    wl = WORKLOADS[args.workload]
-    if args.workload == "c4":
-        return run_surrogate(args, wl)
-    from paper_1610_03484_amd import Batch
-    opts = dict(precision=wl["precision"], rtol=args.rtol, inner_rtol=args.inner_rtol, max_iter=50000,
-                precond=args.precond)
-    if args.workload == "c2":
-        sizes = ci.batch_sizes_c2(0, args.items)
-        params = ci.draw_params(0, args.items)
-        handles = {}
-        rves = []
-        for n_i in sizes:
-            if n_i not in handles:
-                handles[n_i] = RVE(*generate_plain_weave(int(n_i), device="cuda:0"), ci.BASE_MATERIALS,
-                                   bc="periodic", **opts)
-            rves.append(handles[n_i])
-        n = int(max(sizes))
-        labels = [f"item {i} (n={int(s)})" for i, s in enumerate(sizes)]
-    elif args.workload == "c3":
-        n = wl["n"]
-        items = args.items if args.items != 512 else 64
-        rve = RVE(*generate_plain_weave(n, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic", order=args.order, **opts)
-        rves = [rve] * items
-        params = ci.draw_params(0, items)
-        labels = [f"item {i}" for i in range(items)]
-    else:
-        n = wl["n"]
-        mesh = generate_plain_weave(n, device="cuda:0")
-        rves = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, **opts) for bc in wl["bcs"]]
-        params = np.repeat(ci.draw_factors_only(0, 1), len(rves), axis=0)
-        labels = list(wl["bcs"])
-    batch = Batch(rves)
-
-    def step():
-        return batch.homogenise(params)
-
-    for _ in range(args.warmup):
-        step()
+def calibration_copy(torch):
+    """Three device-to-device copies of 256 MiB (outside the timed region): the plain
+    copy of known size against which rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled."""
+    x = torch.ones(CAL_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    homs = len(rves) * args.steps
-    value = homs / dt
-    C, K, D, rep = res
-    for i, lab in enumerate(labels[:6]):
-        print(f"[bench] {lab}: iters={rep[i]['iters']} refine={rep[i]['refine_steps']} "
-              f"resid_max={max(rep[i]['resid']):.1e} asym={rep[i]['asym']:.1e}", file=sys.stderr)
-    worst = max(range(len(rep)), key=lambda i: max(rep[i]["iters"]))
-    print(f"[bench] status: {sum(r['status'] == 0 for r in rep)}/{len(rep)} converged; "
-          f"max iters {max(rep[worst]['iters'])} ({labels[worst]}: iters={rep[worst]['iters']} "
-          f"refine={rep[worst]['refine_steps']})", file=sys.stderr)
+    del x, y
 
-    # accuracy against the FP64 GPU path solved to rtol 1e-12 (same RVEs, same
-    # parameters): every item of the three-BC batch; for the mixed-size batch the
-    # first item of each size; for the order-3/4 batch the first two items
-    err = None
-    acc_items = []
-    if not args.no_accuracy and wl["precision"] != "fp64":
-        if args.workload == "c2":
-            first = {}
-            for i, s_ in enumerate(sizes):
-                first.setdefault(int(s_), i)
-            acc_items = sorted(first.values())
-            ref_rves = [RVE(*generate_plain_weave(int(sizes[i]), device="cuda:0"), ci.BASE_MATERIALS, bc="periodic",
-                            precision="fp64", rtol=1e-12, max_iter=50000) for i in acc_items]
-        elif args.workload == "c3":
-            acc_items = [0, 1]
-            r64 = RVE(*generate_plain_weave(n, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic", order=args.order,
-                      precision="fp64", rtol=1e-12, max_iter=50000)
-            ref_rves = [r64] * len(acc_items)
-        else:
-            acc_items = list(range(len(rves)))
-            ref_rves = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision="fp64", rtol=1e-12, max_iter=50000)
-                        for bc in wl["bcs"]]
-        ref = Batch(ref_rves)
-        Cr, Kr, Dr, _ = ref.homogenise(np.ascontiguousarray(params[acc_items]))
-        errs = [max(np.linalg.norm(C[i] - Cr[j]) / np.linalg.norm(Cr[j]),
-                    np.linalg.norm(K[i] - Kr[j]) / np.linalg.norm(Kr[j]),
-                    np.linalg.norm(D[i] - Dr[j]) / np.linalg.norm(Dr[j])) for j, i in enumerate(acc_items)]
-        err = float(max(errs))
-        ref.close()
 
-    # dominant kernel: the mechanical operator launch of the batch
-    ms, tets, nprob = batch.time_operator(0, args.op_reps)
-    rg_mech = batch.launch_config()["rg_mech"]
-    calibration_copy(torch)
-    fp32 = wl["precision"] != "fp64"
-    if args.workload == "c2":
-        bytes_ = flops = 0
-        for s_ in sizes:
-            b1, f1 = algorithmic_mech(int(s_), 1, fp32)
-            bytes_ += b1
-            flops += f1
-    elif args.workload == "c3":
-        bytes_, flops = algorithmic_mech_order(n, args.order, nprob, fp32)
-    else:
-        bytes_, flops = algorithmic_mech(n, nprob, fp32)
-    t = ms * 1e-3
-    peak_alu = FP32_VEC_PEAK if fp32 else FP64_VEC_PEAK
-    t_hbm, t_alu = bytes_ / HBM_PEAK, flops / peak_alu
-    if t_alu >= t_hbm:
-        roof = dict(bound="alu", achieved=flops / t / 1e12, peak=peak_alu / 1e12, unit="TFLOP/s",
-                    frac=(flops / t) / peak_alu,
-                    traffic=C1_OP_TRAFFIC_BYTES.get(rg_mech) if (args.workload == "c1" and fp32) else None)
-    else:
-        roof = dict(bound="hbm", achieved=bytes_ / t / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
-                    frac=(bytes_ / t) / HBM_PEAK, traffic=None)
-    if args.workload == "c3":
-        roof = dict(bound="mfma", achieved=flops / t / 1e12, peak=FP32_VEC_PEAK / 1e12, unit="TFLOP/s",
-                    frac=(flops / t) / FP32_VEC_PEAK, traffic=None,
-                    note="FP32 matrix-core peak (157.3 TFLOP/s dense, equal to the packed FP32 vector peak)")
-        kname = f"hp_op_kernel<float,{args.order},3,6,8>"
-    else:
-        kname = f"op_p2_kernel<float,3,6,{rg_mech}>" if fp32 else f"op_p2_kernel<double,3,6,{rg_mech}>"
-    roof.update(kernel=kname,
-                avg_launch_us=ms * 1e3, algorithmic_bytes=bytes_, algorithmic_flops=flops)
-    print(f"[bench] operator: {ms * 1e3:.1f} us/launch, {bytes_ / t / 1e9:.0f} GB/s algorithmic, "
-          f"{flops / t / 1e12:.2f} TFLOP/s algorithmic", file=sys.stderr)
+# ---------------------------------------------------------------- errors
+def _full6(c21):
+    M = np.zeros((6, 6))
+    M[np.triu_indices(6)] = c21
+    return M + np.triu(M, 1).T
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline()
-    line = {
-        "metric": "RVE homogenisations/s (12 load cases) @ stated C_hom error",
-        "value": value,
-        "unit": "homogenisations/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if fp32 else "f64",
-        "data": "synthetic",
-        "config": {"workload": wl["desc"], "path": "batched", "rves_per_step": len(rves),
-                   "rtol": args.rtol, "inner_rtol": args.inner_rtol,
-                   "autotuned": os.environ.get("CHOM_AUTOTUNE") is not None, "precond": args.precond,
-                   "c_hom_rel_err_vs_fp64_gpu": err, "accuracy_items": acc_items,
-                   "launch": batch.launch_config(),
-                   "converged": int(sum(r["status"] == 0 for r in rep))},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(line))
+
+def _full3(k6):
+    a = np.asarray(k6)
+    return np.array([[a[0], a[3], a[5]], [a[3], a[1], a[4]], [a[5], a[4], a[2]]])
+
+
+def result_errors(got, ref):
+    """(relative Frobenius, largest entry / ||ref||_F, energy-weighted ||ref^-1/2 d ref^-1/2||_2),
+    each the largest over the C, K, D blocks; got, ref: 33-vectors (C upper 21, K 6, D 6)."""
+    out = np.zeros(3)
+    for sl, full in ((slice(0, 21), _full6), (slice(21, 27), _full3), (slice(27, 33), _full3)):
+        g, r = full(got[sl]), full(ref[sl])
+        d = g - r
+        w, V = np.linalg.eigh(r)
+        h = V @ np.diag(w ** -0.5) @ V.T
+        e = [np.linalg.norm(d) / np.linalg.norm(r), np.abs(d).max() / np.linalg.norm(r),
+             np.abs(np.linalg.eigvalsh(h @ d @ h)).max()]
+        out = np.maximum(out, e)
+    return [float(v) for v in out]
 
 
 def block_errors(pred, truth):
@@ -339,111 +161,511 @@ def block_errors(pred, truth):
     return err
 
 
-MLP_FLOPS_PER_POINT = 2 * (10 * 256 + 2 * 256 * 256 + 256 * 36)   # one member, one record
-BF16_PEAK = 2.5e15
+def _stack(C, K, D):
+    return np.concatenate([np.asarray(C), np.asarray(K), np.asarray(D)], axis=1)
 
 
-def run_surrogate(args, wl):
-    """C4: train the ensemble on RVE solves, then time surrogate + fallback on many records."""
-    import torch
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- CPU oracle (host cores)
+ORACLE_WORKER = r"""
+import json, os, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import chom_inputs as ci
+from oracle import fem, mesh
+n, bc, method = {n}, {bc}, {method!r}
+recs = np.array(json.loads(sys.argv[1]))
+c, t, ph, ax = mesh.plain_weave(n)
+disc = fem.Discretisation(c, t, 2)
+iu = np.triu_indices(6)
+sym3 = [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (0, 2)]
+out = []
+for p in recs:
+    t0 = time.perf_counter()
+    r = fem.homogenise(c, t, ph, ax, 2, bc, ci.BASE_MATERIALS, p, disc=disc, method=method)
+    v = list(r["C"][iu]) + [r["K"][a, b] for a, b in sym3] + [r["D"][a, b] for a, b in sym3]
+    out.append(dict(seconds=time.perf_counter() - t0, result=[float(x) for x in v]))
+print(json.dumps(out))
+"""
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_pool(n, bc, method, records, workers, timeout=900):
+    """Solve `records` on the n^3 RVE with the CPU oracle in `workers` processes
+    (one thread each; one record list per process).  Returns (results [k, 33],
+    per-record seconds, wall seconds)."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               CUDA_VISIBLE_DEVICES="", HIP_VISIBLE_DEVICES="")
+    code = ORACLE_WORKER.format(root=ROOT, n=n, bc=bc, method=method)
+    chunks = [records[i::workers] for i in range(workers)]
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen([sys.executable, "-c", code, json.dumps(np.asarray(ch).tolist())],
+                              stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+             for ch in chunks if len(ch)]
+    outs = [p.communicate(timeout=timeout) for p in procs]
+    wall = time.perf_counter() - t0
+    res = [None] * len(records)
+    secs = [None] * len(records)
+    for w, (p, (so, se)) in enumerate(zip(procs, outs)):
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed: {se[-2000:]}")
+        for j, rec in enumerate(json.loads(so.strip().splitlines()[-1])):
+            res[w + j * workers] = rec["result"]
+            secs[w + j * workers] = rec["seconds"]
+    return np.array(res), np.array(secs), wall
+
+
+# ---------------------------------------------------------------- workloads
+def bench_opts(args, precision):
+    return dict(precision=precision, rtol=args.rtol, inner_rtol=args.inner_rtol, max_iter=50000,
+                precond=args.precond)
+
+
+def make_c2(args, torch):
+    import chom_inputs as ci
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    sizes = ci.batch_sizes_c2(0, args.items)
+    params = ci.draw_params(0, args.items)
+    handles = {}
+    for n_i in sorted(set(int(s) for s in sizes)):
+        handles[n_i] = RVE(*generate_plain_weave(n_i, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic",
+                           **bench_opts(args, "fp32_refined"))
+    rves = [handles[int(s)] for s in sizes]
+    return sizes, params, handles, rves
+
+
+def time_batch(batch, params, steps, warmup, torch):
+    for _ in range(warmup):
+        batch.homogenise(params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = batch.homogenise(params)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, res
+
+
+def plain_path(handles, sizes, params, torch):
+    """One chom_homogenise call per record on the record's own RVE handle (a warm-up
+    call per size first): the plain GPU path on the same records."""
+    first = {}
+    for i, s in enumerate(sizes):
+        first.setdefault(int(s), i)
+    for s, i in first.items():
+        handles[s].homogenise(params[i:i + 1])
+    torch.cuda.synchronize()
+    out = np.zeros((len(sizes), 33))
+    t0 = time.perf_counter()
+    for i, s in enumerate(sizes):
+        C, K, D, _ = handles[int(s)].homogenise(params[i:i + 1])
+        out[i] = _stack(C, K, D)[0]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+def roofline_mech(batch, sizes_or_n, nprob_items, fp32, args, workload, order=2):
+    ms, tets, nprob = batch.time_operator(0, args.op_reps)
+    rg = batch.launch_config()["rg_mech"]
+    if order != 2:
+        bytes_, flops = algorithmic_mech_order(sizes_or_n, order, nprob, fp32)
+    elif isinstance(sizes_or_n, (list, tuple, np.ndarray)):
+        bytes_ = flops = 0
+        for s_ in sizes_or_n:
+            b1, f1 = algorithmic_mech(int(s_), 1, fp32)
+            bytes_ += b1
+            flops += f1
+    else:
+        bytes_, flops = algorithmic_mech(sizes_or_n, nprob, fp32)
+    t = ms * 1e-3
+    peak_alu = FP32_VEC_PEAK if fp32 else FP64_VEC_PEAK
+    traffic = OP_TRAFFIC_BYTES.get(workload, {}).get(rg) if (fp32 and order == 2) else None
+    if order != 2:
+        roof = dict(bound="mfma", achieved=flops / t / 1e12, peak=FP32_VEC_PEAK / 1e12, unit="TFLOP/s",
+                    frac=(flops / t) / FP32_VEC_PEAK, traffic=None,
+                    note="FP32 matrix-core peak (157.3 TFLOP/s dense, equal to the packed FP32 vector peak)")
+        kname = f"hp_op_kernel<float,{order},3,6,8>"
+    elif flops / peak_alu >= bytes_ / HBM_PEAK:
+        roof = dict(bound="alu", achieved=flops / t / 1e12, peak=peak_alu / 1e12, unit="TFLOP/s",
+                    frac=(flops / t) / peak_alu, traffic=traffic)
+        kname = f"op_p2_kernel<{'float' if fp32 else 'double'},3,6,{rg}>"
+    else:
+        roof = dict(bound="hbm", achieved=bytes_ / t / 1e9, peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=(bytes_ / t) / HBM_PEAK, traffic=traffic)
+        kname = f"op_p2_kernel<{'float' if fp32 else 'double'},3,6,{rg}>"
+    roof.update(kernel=kname, avg_launch_us=ms * 1e3, algorithmic_bytes=bytes_, algorithmic_flops=flops,
+                hbm_frac=(bytes_ / t) / HBM_PEAK, problems_per_launch=nprob)
+    log(f"operator: {ms * 1e3:.1f} us/launch, {bytes_ / t / 1e9:.0f} GB/s algorithmic, "
+        f"{flops / t / 1e12:.2f} TFLOP/s algorithmic")
+    return roof
+
+
+def damage_history_kernel(torch):
+    """chom_damage_history on 1,000,000 points x 100 steps (device arrays): per launch
+    16 B read (T, c) and 8 B written per point and step."""
+    import chom_inputs as ci
+    from paper_1610_03484_amd import damage_history
+    n, m = 1_000_000, 100
+    u = torch.tensor(ci.uniform_block(71, 0, 2 * 4096), device="cuda:0")
+    T = (20.0 + 40.0 * u[:4096]).repeat(m * n // 4096 + 1)[: m * n].reshape(m, n).contiguous()
+    c = (1.5 * u[4096:]).repeat(m * n // 4096 + 1)[: m * n].reshape(m, n).contiguous()
+    dt = torch.full((m,), 0.1, dtype=torch.float64, device="cuda:0")
+    for _ in range(2):
+        damage_history(T, c, dt, keep=True, params=False)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        damage_history(T, c, dt, keep=True, params=False)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    bytes_ = 24.0 * n * m
+    del T, c
+    return dict(points=n, steps=m, ms_per_call=t * 1e3, achieved_GBps=bytes_ / t / 1e9,
+                hbm_frac=bytes_ / t / HBM_PEAK, bound="hbm",
+                note="host-timed call (one kernel launch plus a 4-byte status read)")
+
+
+def c0_plain(args, torch):
+    """C0: 8^3 linear-Dirichlet FP64, one record per call; error against a fresh oracle solve."""
+    import chom_inputs as ci
+    from oracle import fem
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    params = ci.draw_factors_only(0, 1)
+    rve = RVE(*generate_plain_weave(8, device="cuda:0"), ci.BASE_MATERIALS, bc="dirichlet", precision="fp64",
+              rtol=1e-12, max_iter=50000)
+    rve.homogenise(params)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        C, K, D, _ = rve.homogenise(params)
+    torch.cuda.synchronize()
+    rate = reps / (time.perf_counter() - t0)
+    rve.close()
+    ref, secs, _ = oracle_pool(8, fem.BC_DIRICHLET, "multipliers", params, 1)
+    err = result_errors(_stack(C, K, D)[0], ref[0])
+    return dict(rate=rate, err_vs_oracle=dict(fro=err[0], elem=err[1], energy=err[2]),
+                oracle_seconds=float(secs[0]))
+
+
+def surrogate_leg(args, torch, plain12_rate=None):
+    """C4: train on 12^3 solves (outside timing), then the timed surrogate + fallback."""
     import chom_inputs as ci
     from paper_1610_03484_amd import RVE, Surrogate, generate_plain_weave
-    from paper_1610_03484_amd import _lib as L
-
-    n = wl["n"]
+    n = 12
     rve = RVE(*generate_plain_weave(n, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic",
-              precision="fp32_refined", rtol=args.rtol, inner_rtol=args.inner_rtol, max_iter=50000)
-    # ---- training set: RVE solves of seeded degraded records
+              **bench_opts(args, "fp32_refined"))
     params = ci.draw_params(0, args.train)
     chunk = 512
+    rve.homogenise(params[:chunk])
     t0 = time.perf_counter()
     parts = []
     for s0 in range(0, args.train, chunk):
         parts.append(rve.homogenise(params[s0:s0 + chunk])[:3])
-        print(f"[bench] training solves {min(s0 + chunk, args.train)}/{args.train}", file=sys.stderr, flush=True)
+        if (s0 // chunk) % 8 == 0:
+            log(f"training solves {min(s0 + chunk, args.train)}/{args.train}")
     t_solve = time.perf_counter() - t0
     C = np.concatenate([q[0] for q in parts])
     K = np.concatenate([q[1] for q in parts])
     D = np.concatenate([q[2] for q in parts])
-    batched_rate = args.train / t_solve
+    batched12 = args.train / t_solve
+    if plain12_rate is None:
+        rve.homogenise(params[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(32):
+            rve.homogenise(params[i:i + 1])
+        torch.cuda.synchronize()
+        plain12_rate = 32 / (time.perf_counter() - t0)
     stream = torch.cuda.current_stream().cuda_stream
     sur = Surrogate(members=5, seed=11, device=True, hip_stream=stream)
     dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
     t0 = time.perf_counter()
     hist = sur.train(dev(params), dev(C), dev(K), dev(D), epochs=args.epochs, batch=256)
     t_train = time.perf_counter() - t0
-    print(f"[bench] {args.train} solves in {t_solve:.1f} s ({batched_rate:.0f}/s); training {t_train:.1f} s, "
-          f"final loss {hist[:, -1].mean():.2e}", file=sys.stderr, flush=True)
-
-    # ---- timed: surrogate with fallback on many records (inputs resident in HBM)
+    log(f"{args.train} solves in {t_solve:.1f} s ({batched12:.0f}/s); training {t_train:.1f} s, "
+        f"final loss {hist[:, -1].mean():.2e}")
     pts = dev(ci.draw_params(3_000_000, args.points))
-    sur.homogenise(rve, pts[:4096], thresh=1e-2, chunk=256)      # warm-up (also builds the fallback batch)
+    sur.homogenise(rve, pts[:4096], thresh=1e-2, chunk=256)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    Cs, Ks, Ds, dis, used, nfb = sur.homogenise(rve, pts, thresh=1e-2, chunk=256)
+    _, _, _, _, _, nfb = sur.homogenise(rve, pts, thresh=1e-2, chunk=256)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    value = args.points / dt
-
-    # ---- dominant kernel: the ensemble inference (HIP events on the stream it runs on)
+    rate = args.points / dt
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 5
     ev0.record()
-    for _ in range(reps):
+    for _ in range(5):
         sur.predict(pts)
     ev1.record()
     torch.cuda.synchronize()
-    t_pred = ev0.elapsed_time(ev1) / reps * 1e-3
-    flops = MLP_FLOPS_PER_POINT * 5 * args.points
-    roof = dict(bound="mfma", achieved=flops / t_pred / 1e12, peak=BF16_PEAK / 1e12, unit="TFLOP/s",
-                frac=flops / t_pred / BF16_PEAK, traffic=None, kernel="predict_kernel (bf16 MFMA)",
-                avg_launch_us=t_pred * 1e6, algorithmic_flops=flops,
-                note="per-launch time includes the feature and output passes of the same kernel")
-
-    # ---- accuracy on held-out records against the oracle's stored solves (else the FP64 GPU path)
+    t_pred = ev0.elapsed_time(ev1) / 5 * 1e-3
+    flops = 2 * (10 * 256 + 2 * 256 * 256 + 256 * 36) * 5 * args.points
     golden = os.path.join(ROOT, "tests", "golden", "surrogate_heldout_n12_periodic.txt")
-    if os.path.exists(golden):
-        a = np.loadtxt(golden)
-        hp, truth, judge = a[:, 1:12], a[:, 12:45], "CPU FP64 oracle (stored)"
-    else:
-        hp = ci.draw_params(1_000_000, 256)
-        fp64 = RVE(*generate_plain_weave(n, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic", precision="fp64",
-                   rtol=1e-12, max_iter=50000)
-        c, k, d, _ = fp64.homogenise(hp)
-        truth, judge = np.concatenate([c, k, d], axis=1), "FP64 GPU path"
-        fp64.close()
-    Ch, Kh, Dh, dish, usedh, nfbh = sur.homogenise(rve, dev(hp), thresh=1e-2, chunk=256)
-    got = np.concatenate([Ch.cpu().numpy(), Kh.cpu().numpy(), Dh.cpu().numpy()], axis=1)
-    err = block_errors(got, truth)
+    a = np.loadtxt(golden)
+    hp, truth = a[:, 1:12], a[:, 12:45]
+    Ch, Kh, Dh, _, _, nfbh = sur.homogenise(rve, dev(hp), thresh=1e-2, chunk=256)
+    err = block_errors(_stack(Ch.cpu().numpy(), Kh.cpu().numpy(), Dh.cpu().numpy()), truth)
     Cp, Kp, Dp, _ = sur.predict(dev(hp))
-    raw = block_errors(np.concatenate([Cp.cpu().numpy(), Kp.cpu().numpy(), Dp.cpu().numpy()], axis=1), truth)
-    print(f"[bench] surrogate: {args.points} points in {dt:.2f} s, {nfb} fallbacks; held-out ({judge}) "
-          f"max err {err.max():.2e} (network alone {raw.max():.2e}, median {np.median(raw):.2e})",
-          file=sys.stderr, flush=True)
+    raw = block_errors(_stack(Cp.cpu().numpy(), Kp.cpu().numpy(), Dp.cpu().numpy()), truth)
+    log(f"surrogate: {args.points} points in {dt:.2f} s ({rate:.3g}/s), {nfb} fallbacks; held-out max error "
+        f"{err.max():.2e} (network alone {raw.max():.2e})")
+    out = dict(rate=rate, points=args.points, fallbacks=int(nfb), training_solves=args.train,
+               training_solve_s=t_solve, training_s=t_train, epochs=args.epochs,
+               batched_rate_12cubed=batched12, plain_rate_12cubed=plain12_rate,
+               speedup_vs_plain_12cubed=rate / plain12_rate, speedup_vs_batched_12cubed=rate / batched12,
+               heldout_points=len(hp), heldout_judge="CPU FP64 oracle (stored)",
+               heldout_max_err=float(err.max()), heldout_max_err_network_alone=float(raw.max()),
+               heldout_fallbacks=int(nfbh),
+               predict_kernel=dict(avg_launch_us=t_pred * 1e6, achieved_TFLOPs=flops / t_pred / 1e12,
+                                   frac_bf16_peak=flops / t_pred / 2.5e15))
+    sur.close()
+    rve.close()
+    return out
+
+
+def run_c2(args, torch):
+    import chom_inputs as ci
+    from oracle import fem
+    from paper_1610_03484_amd import RVE, Batch, generate_plain_weave
+    wl = WORKLOADS["c2"]
+    sizes, params, handles, rves = make_c2(args, torch)
+    batch = Batch(rves)
+    log(f"c2: {len(rves)} records, sizes {dict(zip(*np.unique(sizes, return_counts=True)))}")
+    dt, (C, K, D, rep) = time_batch(batch, params, args.steps, args.warmup, torch)
+    value = len(rves) * args.steps / dt
+    launch = batch.launch_config()
+    got = _stack(C, K, D)
+    worst = max(range(len(rep)), key=lambda i: max(rep[i]["iters"]))
+    log(f"batched: {value:.1f}/s; {sum(r['status'] == 0 for r in rep)}/{len(rep)} converged; max iters "
+        f"{max(rep[worst]['iters'])} (item {worst}, n={sizes[worst]})")
+    roof = roofline_mech(batch, list(sizes), len(rves), True, args, "c2")
+
+    # ---- plain GPU path on the same records
+    t_plain, plain = plain_path(handles, sizes, params, torch)
+    plain_rate = len(rves) / t_plain
+    log(f"plain path (one record per call): {plain_rate:.1f}/s; batched/plain {value / plain_rate:.2f}")
+
+    # ---- accuracy: FP64 GPU path (one item per size) and the oracle (8^3 items, with the cpu baseline)
+    acc = {}
+    if not args.no_accuracy:
+        first = {}
+        for i, s_ in enumerate(sizes):
+            first.setdefault(int(s_), i)
+        items = sorted(first.values())
+        refs = [RVE(*generate_plain_weave(int(sizes[i]), device="cuda:0"), ci.BASE_MATERIALS, bc="periodic",
+                    precision="fp64", rtol=1e-12, max_iter=50000) for i in items]
+        rb = Batch(refs)
+        Cr, Kr, Dr, _ = rb.homogenise(np.ascontiguousarray(params[items]))
+        ref64 = _stack(Cr, Kr, Dr)
+        e64 = np.array([result_errors(got[i], ref64[j]) for j, i in enumerate(items)])
+        ep = np.array([result_errors(plain[i], ref64[j]) for j, i in enumerate(items)])
+        acc.update(vs_fp64_gpu=dict(items=items, sizes=[int(sizes[i]) for i in items],
+                                    fro=float(e64[:, 0].max()), elem=float(e64[:, 1].max()),
+                                    energy=float(e64[:, 2].max()), plain_path_fro=float(ep[:, 0].max()),
+                                    plain_path_energy=float(ep[:, 2].max()),
+                                    judge="FP64 GPU path at rtol 1e-12 (oracle-matched at 8^3 and 12^3 by tests)"))
+        rb.close()
+        for r in refs:
+            r.close()
+        log(f"batch vs FP64 GPU path: fro {e64[:, 0].max():.2e} energy {e64[:, 2].max():.2e}")
+
+    # ---- C0 plain FP64
+    c0 = None if args.no_c0 else c0_plain(args, torch)
+    if c0:
+        log(f"c0 plain FP64 8^3 Dirichlet: {c0['rate']:.1f}/s, error vs oracle {c0['err_vs_oracle']}")
+
+    # ---- damage history kernel
+    dmg = damage_history_kernel(torch)
+    log(f"damage history: {dmg['ms_per_call']:.3f} ms per call, {dmg['achieved_GBps']:.0f} GB/s")
+
+    # ---- surrogate
+    sur = None
+    if not args.no_surrogate:
+        sur = surrogate_leg(args, torch)
+
+    calibration_copy(torch)
+    batch.close()
+
+    # ---- cpu baseline: oracle on the 8^3 records of the batch, worker processes on the host cores
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = max(1, min(16, os.cpu_count() or 1))
+        idx8 = [i for i, s_ in enumerate(sizes) if int(s_) == 8][:workers]
+        res, secs, wall = oracle_pool(8, fem.BC_PERIODIC, "substitution", params[idx8], workers)
+        eo = np.array([result_errors(got[i], res[j]) for j, i in enumerate(idx8)])
+        acc["vs_oracle"] = dict(items=idx8, size=8, fro=float(eo[:, 0].max()), elem=float(eo[:, 1].max()),
+                                energy=float(eo[:, 2].max()),
+                                judge="CPU FP64 oracle, solved in this run (substitution route)")
+        log(f"batch vs oracle (8^3 items): fro {eo[:, 0].max():.2e} energy {eo[:, 2].max():.2e}")
+        cpu = dict(value=len(idx8) / wall, unit="homogenisations/s", cores=len(idx8), kind="oracle",
+                   sample=(f"CPU FP64 oracle (Lagrange P2, SuperLU, constraints by substitution) on the "
+                           f"{len(idx8)} first 8^3 records of the batch, one per worker process ({len(idx8)} "
+                           f"processes, one thread each) on {cpu_model()} ({os.cpu_count()} logical CPUs): "
+                           f"{wall:.1f} s wall, {np.mean(secs):.1f} s per record; the larger records of the "
+                           f"batch (12^3 to 24^3) are not run (a 12^3 periodic solve takes about two minutes on "
+                           f"one core, 24^3 about 40 minutes), so this rate overstates the oracle on the mix"),
+                   single_rve_latency_s=float(np.mean(secs)), cpu_model=cpu_model(),
+                   logical_cpus=os.cpu_count())
+
     line = {
-        "metric": "RVE homogenisations/s (12 load cases) @ stated C_hom error",
+        "metric": METRIC,
         "value": value,
         "unit": "homogenisations/s",
         "n_gpus": 1,
-        "steps": 1,
-        "warmup": 1,
-        "ms_per_step": dt * 1e3,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16+f32 (network), f32+f64 (fallback)",
+        "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": wl["desc"], "path": "surrogate+fallback", "points": args.points,
-                   "fallbacks": int(nfb), "training_solves": args.train, "training_solve_s": t_solve,
-                   "training_s": t_train, "epochs": args.epochs, "batched_rate_12cubed": batched_rate,
-                   "speedup_vs_batched": value / batched_rate, "heldout_points": len(hp),
-                   "heldout_judge": judge, "heldout_max_err": float(err.max()),
-                   "heldout_max_err_network_alone": float(raw.max()),
-                   "heldout_fallbacks": int(nfbh)},
+        "config": {"workload": wl["desc"], "path": "batched", "rves_per_step": len(rves),
+                   "sizes": {int(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))},
+                   "rtol": args.rtol, "inner_rtol": args.inner_rtol, "precond": args.precond,
+                   "autotuned": os.environ.get("CHOM_AUTOTUNE") is not None, "launch": launch,
+                   "converged": int(sum(r["status"] == 0 for r in rep)),
+                   "max_cg_iters": int(max(rep[worst]["iters"])),
+                   "plain_rate": plain_rate, "speedup_batched_over_plain": value / plain_rate,
+                   "accuracy": acc, "c0_plain_fp64_8cubed": c0,
+                   "surrogate": sur,
+                   "speedup_surrogate_over_plain": (sur["speedup_vs_plain_12cubed"] if sur else None),
+                   "damage_history_kernel": dmg},
         "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def run_single(args, wl, torch):
+    """c1 / c0 / c3: one batch of a few RVEs of one size (the earlier headline forms)."""
+    import chom_inputs as ci
+    from paper_1610_03484_amd import RVE, Batch, generate_plain_weave
+    opts = bench_opts(args, wl["precision"])
+    if args.workload == "c3":
+        n = wl["n"]
+        items = args.items if args.items != 512 else 64
+        rve = RVE(*generate_plain_weave(n, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic", order=args.order,
+                  **opts)
+        rves = [rve] * items
+        params = ci.draw_params(0, items)
+    else:
+        n = wl["n"]
+        mesh = generate_plain_weave(n, device="cuda:0")
+        rves = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, **opts) for bc in wl["bcs"]]
+        params = np.repeat(ci.draw_factors_only(0, 1), len(rves), axis=0)
+    batch = Batch(rves)
+    dt, (C, K, D, rep) = time_batch(batch, params, args.steps, args.warmup, torch)
+    value = len(rves) * args.steps / dt
+    for i, r in enumerate(rep[:6]):
+        log(f"item {i}: iters={r['iters']} refine={r['refine_steps']} resid_max={max(r['resid']):.1e} "
+            f"asym={r['asym']:.1e} HM gap={r['hill_mandel_gap']:.1e}")
+    err = None
+    if not args.no_accuracy and wl["precision"] != "fp64":
+        acc_items = [0, 1] if args.workload == "c3" else list(range(len(rves)))
+        if args.workload == "c3":
+            r64 = RVE(*generate_plain_weave(n, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic",
+                      order=args.order, precision="fp64", rtol=1e-12, max_iter=50000)
+            refs = [r64] * 2
+        else:
+            refs = [RVE(*mesh, ci.BASE_MATERIALS, bc=bc, precision="fp64", rtol=1e-12, max_iter=50000)
+                    for bc in wl["bcs"]]
+        rb = Batch(refs)
+        Cr, Kr, Dr, _ = rb.homogenise(np.ascontiguousarray(params[acc_items]))
+        got, ref = _stack(C, K, D), _stack(Cr, Kr, Dr)
+        e = np.array([result_errors(got[i], ref[j]) for j, i in enumerate(acc_items)])
+        err = dict(fro=float(e[:, 0].max()), elem=float(e[:, 1].max()), energy=float(e[:, 2].max()),
+                   judge="FP64 GPU path at rtol 1e-12")
+        rb.close()
+    fp32 = wl["precision"] != "fp64"
+    if args.workload == "c3":
+        roof = roofline_mech(batch, n, len(rves), fp32, args, "c3", order=args.order)
+    else:
+        roof = roofline_mech(batch, n, len(rves), fp32, args, args.workload)
+    calibration_copy(torch)
+    line = {
+        "metric": METRIC, "value": value, "unit": "homogenisations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if fp32 else "f64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "path": "batched", "rves_per_step": len(rves), "rtol": args.rtol,
+                   "inner_rtol": args.inner_rtol, "precond": args.precond, "launch": batch.launch_config(),
+                   "accuracy_vs_fp64_gpu": err, "converged": int(sum(r["status"] == 0 for r in rep))},
+        "roofline": roof, "cpu_baseline": None,
+    }
+    print(json.dumps(line))
+
+
+def run_c4(args, torch):
+    sur = surrogate_leg(args, torch)
+    line = {
+        "metric": METRIC, "value": sur["rate"], "unit": "homogenisations/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": args.points / sur["rate"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+f32 (network), f32+f64 (fallback)", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c4"]["desc"], "path": "surrogate+fallback", **sur},
+        "roofline": dict(bound="mfma", achieved=sur["predict_kernel"]["achieved_TFLOPs"], peak=2500.0,
+                         unit="TFLOP/s", frac=sur["predict_kernel"]["frac_bf16_peak"], traffic=None,
+                         kernel="predict_kernel (bf16 MFMA)",
+                         avg_launch_us=sur["predict_kernel"]["avg_launch_us"]),
         "cpu_baseline": None,
     }
     print(json.dumps(line))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--op-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="c2: skip the surrogate leg")
+    ap.add_argument("--no-c0", action="store_true", help="c2: skip the 8^3 FP64 plain (C0) leg")
+    ap.add_argument("--items", type=int, default=512, help="items of the c2 batch (c3: 64 unless set)")
+    ap.add_argument("--precond", default="two_level", choices=["block_jacobi", "two_level"],
+                    help="CG preconditioner (two_level: block Jacobi plus a P1 multigrid coarse correction)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="fixed launch shape instead of the library's autotuner (which runs in the warm-up)")
+    ap.add_argument("--order", type=int, default=4, help="c3: polynomial order (3 or 4)")
+    ap.add_argument("--rtol", type=float, default=3e-5,
+                    help="stopping tolerance of each load case (relative to its own energy, in the metric of "
+                         "the preconditioner); the errors against the FP64 path and the oracle are measured "
+                         "and reported each run")
+    ap.add_argument("--inner-rtol", type=float, default=3e-5, help="FP32 inner solve tolerance per refinement pass")
+    ap.add_argument("--train", type=int, default=20000, help="surrogate: training solves")
+    ap.add_argument("--epochs", type=int, default=300, help="surrogate: training epochs")
+    ap.add_argument("--points", type=int, default=1_000_000, help="surrogate: evaluation points")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the RVE batches would shard across GPUs without "
+              f"communication, but no multi-GPU path is built); got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+    if not args.no_autotune:
+        os.environ.setdefault("CHOM_AUTOTUNE", "1")
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.workload == "c2":
+        run_c2(args, torch)
+    elif args.workload == "c4":
+        run_c4(args, torch)
+    else:
+        run_single(args, WORKLOADS[args.workload], torch)
 
 
 if __name__ == "__main__":
