@@ -454,9 +454,11 @@ def run_c2(args, torch):
     roof = roofline_mech(batch, list(sizes), len(rves), True, args, "c2")
 
     # ---- plain GPU path on the same records
-    t_plain, plain = plain_path(handles, sizes, params, torch)
-    plain_rate = len(rves) / t_plain
-    log(f"plain path (one record per call): {plain_rate:.1f}/s; batched/plain {value / plain_rate:.2f}")
+    plain_rate, plain = None, None
+    if not args.no_plain:
+        t_plain, plain = plain_path(handles, sizes, params, torch)
+        plain_rate = len(rves) / t_plain
+        log(f"plain path (one record per call): {plain_rate:.1f}/s; batched/plain {value / plain_rate:.2f}")
 
     # ---- accuracy: FP64 GPU path (one item per size) and the oracle (8^3 items, with the cpu baseline)
     acc = {}
@@ -471,7 +473,8 @@ def run_c2(args, torch):
         Cr, Kr, Dr, _ = rb.homogenise(np.ascontiguousarray(params[items]))
         ref64 = _stack(Cr, Kr, Dr)
         e64 = np.array([result_errors(got[i], ref64[j]) for j, i in enumerate(items)])
-        ep = np.array([result_errors(plain[i], ref64[j]) for j, i in enumerate(items)])
+        ep = (np.array([result_errors(plain[i], ref64[j]) for j, i in enumerate(items)]) if plain is not None
+              else np.full((1, 3), np.nan))
         acc.update(vs_fp64_gpu=dict(items=items, sizes=[int(sizes[i]) for i in items],
                                     fro=float(e64[:, 0].max()), elem=float(e64[:, 1].max()),
                                     energy=float(e64[:, 2].max()), plain_path_fro=float(ep[:, 0].max()),
@@ -488,8 +491,10 @@ def run_c2(args, torch):
         log(f"c0 plain FP64 8^3 Dirichlet: {c0['rate']:.1f}/s, error vs oracle {c0['err_vs_oracle']}")
 
     # ---- damage history kernel
-    dmg = damage_history_kernel(torch)
-    log(f"damage history: {dmg['ms_per_call']:.3f} ms per call, {dmg['achieved_GBps']:.0f} GB/s")
+    dmg = None
+    if not args.no_damage:
+        dmg = damage_history_kernel(torch)
+        log(f"damage history: {dmg['ms_per_call']:.3f} ms per call, {dmg['achieved_GBps']:.0f} GB/s")
 
     # ---- surrogate
     sur = None
@@ -539,7 +544,7 @@ def run_c2(args, torch):
                    "autotuned": os.environ.get("CHOM_AUTOTUNE") is not None, "launch": launch,
                    "converged": int(sum(r["status"] == 0 for r in rep)),
                    "max_cg_iters": int(max(rep[worst]["iters"])),
-                   "plain_rate": plain_rate, "speedup_batched_over_plain": value / plain_rate,
+                   "plain_rate": plain_rate, "speedup_batched_over_plain": value / plain_rate if plain_rate else None,
                    "accuracy": acc, "c0_plain_fp64_8cubed": c0,
                    "surrogate": sur,
                    "speedup_surrogate_over_plain": (sur["speedup_vs_plain_12cubed"] if sur else None),
@@ -635,6 +640,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="c2: skip the surrogate leg")
     ap.add_argument("--no-c0", action="store_true", help="c2: skip the 8^3 FP64 plain (C0) leg")
+    ap.add_argument("--no-plain", action="store_true", help="c2: skip the one-record-per-call leg")
+    ap.add_argument("--no-damage", action="store_true", help="c2: skip the damage-history kernel leg")
     ap.add_argument("--items", type=int, default=512, help="items of the c2 batch (c3: 64 unless set)")
     ap.add_argument("--precond", default="two_level", choices=["block_jacobi", "two_level"],
                     help="CG preconditioner (two_level: block Jacobi plus a P1 multigrid coarse correction)")

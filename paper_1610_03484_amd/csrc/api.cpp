@@ -157,6 +157,7 @@ template <int C, int R> struct ClassWS {
     DevBuf<double> mgr64, mgxp64, mgres64, mgx64, mgW64;
     DevBuf<double> avg_corr;             // Hill-Mandel gap terms (1/V) u_i . r_j [prob][NC][R]
     DevBuf<ColState> cols_tmp, cols_fb;  // final-residual projection; mask of the FP64 fallback solve
+    DevBuf<ColState> cols_flush;         // CG chain compaction: pending updates of the leaving problems
     DevBuf<int> active_tmp;
     std::vector<ColState> h_cols, h_cols_outer, h_cols_tmp;
     HostBuf<int> h_poll;               // pinned: per-problem active flags polled between graph chunks
@@ -451,6 +452,7 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
     CHOM_HIP(W.avg_out.ensure((size_t)nprob * R * NC));
     CHOM_HIP(W.avg_corr.ensure((size_t)nprob * R * NC));
     CHOM_HIP(W.cols_tmp.ensure((size_t)R * nprob));
+    CHOM_HIP(W.cols_flush.ensure((size_t)R * nprob));
     CHOM_HIP(W.active_tmp.ensure(nprob));
     W.h_cols.resize((size_t)R * nprob);
     W.h_cols_outer.resize((size_t)R * nprob);
@@ -484,6 +486,7 @@ template <int C, int R> struct PcgChain {
     GraphCache *graph = nullptr;
     int *h_active = nullptr;   // this chain's slice of the class's pinned poll buffer
     int max_iter = 0;          // CG steps per solve and column (0: no cap)
+    ColState *cols_scratch = nullptr;   // this chain's slice of a scratch column buffer (compaction)
 };
 
 template <int C, int R>
@@ -507,6 +510,7 @@ static PcgChain<C, R> make_chain(ClassWS<C, R> &W, int p0, int cnt, const double
     ch.s = s;
     ch.graph = graph;
     ch.h_active = W.h_poll.p + p0;
+    ch.cols_scratch = W.cols_flush.p + (size_t)p0 * R;
     return ch;
 }
 
@@ -530,10 +534,115 @@ static hipError_t cg_iteration(const PcgChain<C, R> &K, T *x, T *r, T *p, T *q, 
                                     K.max_iter);
 }
 
+// Slot state of a chain that compaction permutes: problem table, column
+// states, active counts, projection coefficients, Gram inverses (the vectors,
+// tile boxes and coarse levels are addressed through the problem table).
+template <int C, int R> struct ChainSlots {
+    std::vector<Prob> pr;
+    std::vector<ColState> cs;
+    std::vector<int> act;
+    std::vector<double> yc, gi;
+};
+
+template <int C, int R>
+static int chain_download(const PcgChain<C, R> &K, int n, ChainSlots<C, R> &S) {
+    const size_t ysz = (size_t)R * C * K.L.nr, gsz = (size_t)(4 * C) * (4 * C);
+    S.pr.resize(n);
+    S.cs.resize((size_t)n * R);
+    S.act.resize(n);
+    S.yc.resize((size_t)n * ysz);
+    S.gi.resize((size_t)n * gsz);
+    CHOM_HIP(hipMemcpyAsync(S.pr.data(), K.L.probs, sizeof(Prob) * n, hipMemcpyDeviceToHost, K.s));
+    CHOM_HIP(hipMemcpyAsync(S.cs.data(), K.cols, sizeof(ColState) * n * R, hipMemcpyDeviceToHost, K.s));
+    CHOM_HIP(hipMemcpyAsync(S.act.data(), K.active, sizeof(int) * n, hipMemcpyDeviceToHost, K.s));
+    if (ysz) CHOM_HIP(hipMemcpyAsync(S.yc.data(), K.ycoef, sizeof(double) * n * ysz, hipMemcpyDeviceToHost, K.s));
+    CHOM_HIP(hipMemcpyAsync(S.gi.data(), K.ginv, sizeof(double) * n * gsz, hipMemcpyDeviceToHost, K.s));
+    CHOM_HIP(hipStreamSynchronize(K.s));
+    return CHOM_OK;
+}
+
+// Writes the slots back in the order perm: new slot j takes old slot perm[j].
+template <int C, int R>
+static int chain_upload(const PcgChain<C, R> &K, const ChainSlots<C, R> &S, const std::vector<int> &perm) {
+    const int n = (int)perm.size();
+    const size_t ysz = (size_t)R * C * K.L.nr, gsz = (size_t)(4 * C) * (4 * C);
+    ChainSlots<C, R> T;
+    T.pr.resize(n);
+    T.cs.resize((size_t)n * R);
+    T.act.resize(n);
+    T.yc.resize((size_t)n * ysz);
+    T.gi.resize((size_t)n * gsz);
+    for (int j = 0; j < n; ++j) {
+        const int i = perm[j];
+        T.pr[j] = S.pr[i];
+        T.act[j] = S.act[i];
+        for (int r = 0; r < R; ++r) T.cs[(size_t)j * R + r] = S.cs[(size_t)i * R + r];
+        std::copy(S.yc.begin() + i * ysz, S.yc.begin() + (i + 1) * ysz, T.yc.begin() + j * ysz);
+        std::copy(S.gi.begin() + i * gsz, S.gi.begin() + (i + 1) * gsz, T.gi.begin() + j * gsz);
+    }
+    CHOM_HIP(hipMemcpyAsync(const_cast<Prob *>(K.L.probs), T.pr.data(), sizeof(Prob) * n, hipMemcpyHostToDevice, K.s));
+    CHOM_HIP(hipMemcpyAsync(K.cols, T.cs.data(), sizeof(ColState) * n * R, hipMemcpyHostToDevice, K.s));
+    CHOM_HIP(hipMemcpyAsync(K.active, T.act.data(), sizeof(int) * n, hipMemcpyHostToDevice, K.s));
+    if (ysz) CHOM_HIP(hipMemcpyAsync(K.ycoef, T.yc.data(), sizeof(double) * n * ysz, hipMemcpyHostToDevice, K.s));
+    CHOM_HIP(hipMemcpyAsync(const_cast<double *>(K.ginv), T.gi.data(), sizeof(double) * n * gsz,
+                            hipMemcpyHostToDevice, K.s));
+    CHOM_HIP(hipStreamSynchronize(K.s));   // the host vectors die here
+    return CHOM_OK;
+}
+
+// Compaction of a CG chain: when at most half of its problems are still active,
+// the active ones move to the front of the chain's range and the launches shrink
+// to them (problem count, tile count and coarse-level grids of those problems),
+// so finished problems stop costing empty workgroups.  The pending x update of
+// every leaving problem is applied first.  order[j]: original position of slot j.
+template <typename T, int C, int R>
+static int compact_chain(chom_batch *B, PcgChain<C, R> &K, T *x, const T *p, std::vector<int> &order) {
+    const int n = K.L.nprob;
+    ChainSlots<C, R> S;
+    CHOM_TRY(chain_download<C, R>(K, n, S));
+    std::vector<int> perm, leave;
+    for (int i = 0; i < n; ++i) (S.act[i] ? perm : leave).push_back(i);
+    const int nact = (int)perm.size();
+    std::vector<ColState> fl(S.cs);
+    for (int j = 0; j < nact; ++j)
+        for (int r = 0; r < R; ++r) fl[(size_t)perm[j] * R + r].alpha = 0.0;
+    CHOM_HIP(hipMemcpyAsync(K.cols_scratch, fl.data(), sizeof(ColState) * n * R, hipMemcpyHostToDevice, K.s));
+    CHOM_HIP((launch_cg_flush_x<T, C, R>(K.L, x, p, K.cols_scratch, K.s)));
+    for (int i : leave)
+        for (int r = 0; r < R; ++r) S.cs[(size_t)i * R + r].alpha = 0.0;
+    perm.insert(perm.end(), leave.begin(), leave.end());
+    CHOM_TRY((chain_upload<C, R>(K, S, perm)));
+    std::vector<int> o2(order.size());
+    for (int j = 0; j < n; ++j) o2[j] = order[perm[j]];
+    for (size_t j = n; j < order.size(); ++j) o2[j] = order[j];
+    order.swap(o2);
+    // launch shape of the remaining problems
+    Launch &L = K.L;
+    L.nprob = nact;
+    int mt = 1;
+    long long mp[MG_MAXLEV] = {};
+    for (int j = 0; j < nact; ++j) {
+        const Geo &G = B->distinct[S.pr[perm[j]].geo]->geo;
+        mt = std::max(mt, G.ntiles);
+        for (int l = 0; l < G.mg_nlev && l < MG_MAXLEV; ++l)
+            mp[l] = std::max(mp[l], (long long)G.mg_lw[l] * G.mg_lw[l] * G.mg_lw[l]);
+    }
+    L.max_tiles = mt;
+    if (L.mg.on)
+        for (int l = 0; l < L.mg.nlev; ++l) {
+            L.mg.max_pts[l] = mp[l];
+            L.mg.nwg[l] = (int)std::min<long long>(std::max<long long>((mp[l] + 63) / 64, 1), 1024);
+        }
+    K.graph->reset();
+    return CHOM_OK;
+}
+
 // PCG on one chain of problems: b -> x (vectors of precision T).  Iterations
-// run in chunks, captured once as a HIP graph and replayed; between chunks the
-// host reads the per-problem active counts (finished problems cost only an
-// early exit in every kernel).
+// run in chunks, captured as a HIP graph and replayed; between chunks the host
+// reads the per-problem active counts (finished problems cost only an early
+// exit in every kernel) and compacts the chain when at most half of its
+// problems remain (CHOM_NO_COMPACT turns that off); the slot order is restored
+// at the end.
 template <typename T, int C, int R>
 static int pcg(chom_batch *B, ClassWS<C, R> &W, PcgChain<C, R> &K, const T *b, T *x, T *r, T *p, T *q,
                const void *minv, double rtol2, int use_init) {
@@ -552,32 +661,44 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, PcgChain<C, R> &K, const T *b, T
     const int max_iter = B->opt.max_iter;
     const int chunk = 8;
     const bool use_graph = std::getenv("CHOM_NO_GRAPH") == nullptr;
-    if (use_graph && (GC.exec == nullptr || GC.key != (const void *)x || GC.iters != chunk || GC.gen != W.gen ||
-                      GC.probs != (const void *)L.probs || GC.nprob != L.nprob)) {
-        GC.reset();
-        hipGraph_t g;
-        CHOM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t ce = hipSuccess;
-        for (int k = 0; k < chunk && ce == hipSuccess; ++k)
-            ce = cg_iteration<T, C, R>(K, x, r, p, q, minv, rtol2, use_init);
-        hipError_t ee = hipStreamEndCapture(s, &g);
-        CHOM_HIP(ce);
-        CHOM_HIP(ee);
-        hipError_t ie = hipGraphInstantiate(&GC.exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        CHOM_HIP(ie);
-        GC.key = x;
-        GC.iters = chunk;
-        GC.gen = W.gen;
-        GC.probs = L.probs;
-        GC.nprob = L.nprob;
-    }
+    const bool compact = std::getenv("CHOM_NO_COMPACT") == nullptr;
+    const int nfull = L.nprob;
+    std::vector<int> order(nfull);
+    for (int i = 0; i < nfull; ++i) order[i] = i;
+    bool permuted = false;
     for (int it = 0; it < max_iter; it += chunk) {
         CHOM_HIP(hipMemcpyAsync(K.h_active, K.active, sizeof(int) * L.nprob, hipMemcpyDeviceToHost, s));
         CHOM_HIP(hipStreamSynchronize(s));
-        int act = 0;
-        for (int i = 0; i < L.nprob; ++i) act += K.h_active[i];
+        int act = 0, nact = 0;
+        for (int i = 0; i < L.nprob; ++i) {
+            act += K.h_active[i];
+            nact += K.h_active[i] ? 1 : 0;
+        }
         if (act == 0) break;
+        if (compact && L.nprob > 1 && 2 * nact <= L.nprob) {
+            CHOM_TRY((compact_chain<T, C, R>(B, K, x, p, order)));
+            permuted = true;
+        }
+        if (use_graph && (GC.exec == nullptr || GC.key != (const void *)x || GC.iters != chunk || GC.gen != W.gen ||
+                          GC.probs != (const void *)L.probs || GC.nprob != L.nprob)) {
+            GC.reset();
+            hipGraph_t g;
+            CHOM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t ce = hipSuccess;
+            for (int k = 0; k < chunk && ce == hipSuccess; ++k)
+                ce = cg_iteration<T, C, R>(K, x, r, p, q, minv, rtol2, use_init);
+            hipError_t ee = hipStreamEndCapture(s, &g);
+            CHOM_HIP(ce);
+            CHOM_HIP(ee);
+            hipError_t ie = hipGraphInstantiate(&GC.exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            CHOM_HIP(ie);
+            GC.key = x;
+            GC.iters = chunk;
+            GC.gen = W.gen;
+            GC.probs = L.probs;
+            GC.nprob = L.nprob;
+        }
         if (use_graph) {
             CHOM_HIP(hipGraphLaunch(GC.exec, s));
         } else {
@@ -586,6 +707,15 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, PcgChain<C, R> &K, const T *b, T
     }
     // the last step's x += alpha p (every earlier one was applied by a direction kernel)
     CHOM_HIP((launch_cg_flush_x<T, C, R>(L, x, p, K.cols, s)));
+    if (permuted) {   // back to the original slot order
+        ChainSlots<C, R> S;
+        CHOM_TRY((chain_download<C, R>(K, nfull, S)));
+        std::vector<int> inv(nfull);
+        for (int j = 0; j < nfull; ++j) inv[order[j]] = j;
+        CHOM_TRY((chain_upload<C, R>(K, S, inv)));
+        // the graph of the compacted chain no longer matches the problem table
+        GC.reset();
+    }
     return CHOM_OK;
 }
 

@@ -1,0 +1,67 @@
+"""CG chain compaction (GPU, through the C ABI).
+
+When at most half of a chain's problems are still iterating, the library moves
+the active ones to the front of the chain (problem table and per-problem solver
+state permuted, pending updates of the leaving problems applied) and shrinks
+the launches to them; the original order is restored after the solve.  Each
+problem's arithmetic is unchanged, so results must match the uncompacted run
+(CHOM_NO_COMPACT) to the level of the FP64 reductions' summation order, with
+iteration counts within a few steps, for batches whose problems finish at very different
+steps (sizes 3 to 12, all BCs, degraded records), in both precisions and with
+one and two chains.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import chom_inputs as ci
+from gpu_util import banner, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+ITEMS = [(4, "dirichlet"), (12, "periodic"), (3, "neumann"), (8, "periodic"), (6, "dirichlet"), (10, "neumann"),
+         (5, "periodic"), (8, "neumann"), (12, "dirichlet")]
+
+
+def _solve(precision, compact, chains, params):
+    from paper_1610_03484_amd import RVE, Batch, generate_plain_weave
+    env = {"CHOM_PCG_CHAINS": str(chains)}
+    if not compact:
+        env["CHOM_NO_COMPACT"] = "1"
+    os.environ.update(env)
+    try:
+        meshes = {n: generate_plain_weave(n) for n in {n for n, _ in ITEMS}}
+        rves = [RVE(*meshes[n], ci.BASE_MATERIALS, bc=bc, precision=precision, rtol=1e-11, max_iter=50000)
+                for n, bc in ITEMS]
+        b = Batch(rves)
+        C, K, D, rep = b.homogenise(params)
+        b.close()
+        for r in rves:
+            r.close()
+    finally:
+        for k in env:
+            os.environ.pop(k, None)
+    return np.concatenate([C, K, D], axis=1), rep
+
+
+@pytest.mark.parametrize("chains", [1, 2])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_compaction_keeps_results_and_iterations(precision, chains):
+    require_gpu()
+    banner(f"compaction on/off, {len(ITEMS)} items, {precision}, {chains} chain(s)")
+    params = ci.draw_params(19, len(ITEMS))
+    a, ra = _solve(precision, True, chains, params)
+    b, rb = _solve(precision, False, chains, params)
+    e = float(np.abs(a - b).max() / np.abs(b).max())
+    its_a = [r["iters"] for r in ra]
+    its_b = [r["iters"] for r in rb]
+    steps = sorted(max(i) for i in its_b)
+    print(f"[compaction] {precision} chains={chains}: max rel diff {e:.2e}; CG steps per item {steps}")
+    assert all(r["status"] == 0 for r in ra + rb)
+    assert e <= 1e-10
+    # the FP64 sums are atomic, so their order (and a column sitting at the
+    # threshold) can move a stop by a step or two between any two runs; the
+    # refined form adds such moves over its FP32 passes
+    for x, y in zip(its_a, its_b):
+        assert max(abs(u - v) for u, v in zip(x, y)) <= 3 + 0.03 * max(y)

@@ -3,7 +3,8 @@
 Each switch is compared with the default path on one small mixed batch (FP32
 refined, rtol 1e-11): the generic coarse-level kernel instead of the small-grid
 one, other coarsest-level sweep counts, the two classes run one after the
-other, and CG steps launched one by one instead of replayed as graphs.
+other, CG steps launched one by one instead of replayed as graphs, and CG
+chains that keep finished problems in their launches instead of compacting.
 """
 import os
 
@@ -35,7 +36,8 @@ def batch():
 
 
 @pytest.mark.parametrize("switch", [("CHOM_MG_GENERIC", "1"), ("CHOM_MG_SWEEPS", "10"), ("CHOM_MG_SWEEPS", "16"),
-                                    ("CHOM_SERIAL_CLASSES", "1"), ("CHOM_NO_GRAPH", "1")])
+                                    ("CHOM_SERIAL_CLASSES", "1"), ("CHOM_NO_GRAPH", "1"),
+                                    ("CHOM_NO_COMPACT", "1")])
 def test_switch_keeps_the_result(batch, switch):
     b, params, ref = batch
     key, val = switch
