@@ -25,6 +25,8 @@ Also measured, outside the timed region, into `config`:
     oracle solves and its speedup over the plain and batched paths;
   * the damage-history kernel (time-varying exposure) on 1,000,000 points x
     100 steps, against the HBM peak;
+  * the potential-flow yarn directions of the 24^3 RVE: time per call and the
+    change of C_bar against the analytic centreline tangent;
   * roofline of the dominant kernel (the FP32 mechanical operator on the batch),
     from HIP events on the library's stream.
 `cpu_baseline`: the oracle on host cores, on the 8^3 records of the batch.
@@ -337,6 +339,37 @@ def damage_history_kernel(torch):
                 note="host-timed call (one kernel launch plus a 4-byte status read)")
 
 
+def yarn_directions_leg(args, torch):
+    """Potential-flow fibre directions of the 24^3 plain weave (four yarns, P1, FP64 CG):
+    time per call, and the change of C_bar against the analytic centreline tangent."""
+    import chom_inputs as ci
+    from paper_1610_03484_amd import RVE, generate_plain_weave, yarn_directions
+    coords, tets, phase, tangent = generate_plain_weave(24, device="cuda:0")
+    yarn_directions(coords, tets, phase, (0, 0, 1, 1), rtol=1e-10)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        axis = yarn_directions(coords, tets, phase, (0, 0, 1, 1), rtol=1e-10)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    y = phase > 0
+    ang = torch.rad2deg(torch.arccos(torch.clamp((axis[y] * tangent[y]).sum(dim=1).abs(), max=1.0)))
+    params = ci.draw_factors_only(0, 1)
+    out = []
+    for ax in (tangent, axis):
+        rve = RVE(coords, tets, phase, ax, ci.BASE_MATERIALS, bc="periodic", precision="fp64", rtol=1e-12,
+                  max_iter=50000)
+        C, K, D, _ = rve.homogenise(params)
+        rve.close()
+        out.append(_stack(C, K, D)[0])
+    e = result_errors(out[1], out[0])
+    return dict(rve="24^3 plain weave, 4 yarns, 12,624 yarn tets", ms_per_call=ms,
+                mean_angle_to_tangent_deg=float(ang.mean()), max_angle_to_tangent_deg=float(ang.max()),
+                c_hom_change_vs_tangent=dict(fro=e[0], energy=e[2]),
+                note="host-timed call: stencil assembly, one CG workgroup per yarn, per-tet gradients")
+
+
 def c0_plain(args, torch):
     """C0: 8^3 linear-Dirichlet FP64, one record per call; error against a fresh oracle solve."""
     import chom_inputs as ci
@@ -496,6 +529,12 @@ def run_c2(args, torch):
         dmg = damage_history_kernel(torch)
         log(f"damage history: {dmg['ms_per_call']:.3f} ms per call, {dmg['achieved_GBps']:.0f} GB/s")
 
+    # ---- potential-flow yarn directions
+    flow = None if args.no_flow else yarn_directions_leg(args, torch)
+    if flow:
+        log(f"yarn directions 24^3: {flow['ms_per_call']:.2f} ms per call, mean angle to the tangent "
+            f"{flow['mean_angle_to_tangent_deg']:.1f} deg, C_bar change {flow['c_hom_change_vs_tangent']}")
+
     # ---- surrogate
     sur = None
     if not args.no_surrogate:
@@ -548,7 +587,7 @@ def run_c2(args, torch):
                    "accuracy": acc, "c0_plain_fp64_8cubed": c0,
                    "surrogate": sur,
                    "speedup_surrogate_over_plain": (sur["speedup_vs_plain_12cubed"] if sur else None),
-                   "damage_history_kernel": dmg},
+                   "damage_history_kernel": dmg, "yarn_directions_potential_flow": flow},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -642,6 +681,7 @@ def main():
     ap.add_argument("--no-c0", action="store_true", help="c2: skip the 8^3 FP64 plain (C0) leg")
     ap.add_argument("--no-plain", action="store_true", help="c2: skip the one-record-per-call leg")
     ap.add_argument("--no-damage", action="store_true", help="c2: skip the damage-history kernel leg")
+    ap.add_argument("--no-flow", action="store_true", help="c2: skip the potential-flow yarn-direction leg")
     ap.add_argument("--items", type=int, default=512, help="items of the c2 batch (c3: 64 unless set)")
     ap.add_argument("--precond", default="two_level", choices=["block_jacobi", "two_level"],
                     help="CG preconditioner (two_level: block Jacobi plus a P1 multigrid coarse correction)")

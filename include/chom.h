@@ -186,6 +186,26 @@ int chom_mesh_sizes(int32_t n, int32_t *n_vertices, int32_t *n_tets);
 int chom_generate_plain_weave(int32_t n, double *coords, int32_t *tets, int8_t *phase,
                               double *fibre_axis, void *hip_stream);
 
+/* Fibre directions from a potential-flow solve on each yarn (Sec. 6): for yarn
+ * j (tets with phase j + 1) Laplace's equation for a potential phi on that
+ * yarn's tets alone, phi = 0 on the yarn's vertices on the inlet face lo[d] and
+ * phi = 1 on those on the outlet face hi[d] (d = yarn_axis[j], the coordinate
+ * the yarn runs along; the paper states no boundary data, this is the reading),
+ * no flux through the rest of the yarn's surface; linear elements on the Kuhn
+ * lattice (any vertex positions that keep the lattice valid), FP64, Jacobi-
+ * preconditioned CG to r.z <= rtol^2 r0.z0 or max_iter steps.  The fibre axis of
+ * a yarn tet is its normalised gradient of phi (pointing from inlet to outlet);
+ * matrix tets get zero.  The result can be passed as chom_mesh.fibre_axis.
+ * mesh: a Kuhn lattice as for chom_rve_create, phase in 0..n_yarns (fibre_axis
+ * ignored); fibre_axis [n_tets][3] out, device memory if mesh->on_device, else
+ * host.  Work is queued on hip_stream; returns when the output is written.
+ * Errors: CHOM_EINVAL (arguments), CHOM_EMESH (not a Kuhn lattice, phase out of
+ * range, or a yarn tet with no gradient: a yarn part reaching neither end
+ * face), CHOM_ENOCONV (some yarn's solve hit max_iter; directions written),
+ * CHOM_EDEVICE, CHOM_ENOMEM. */
+int chom_yarn_directions(const chom_mesh *mesh, int32_t n_yarns, const int32_t *yarn_axis, double rtol,
+                         int32_t max_iter, double *fibre_axis, void *hip_stream);
+
 /* Create an RVE handle: copies the mesh to the device, checks it (CHOM_EMESH),
  * tabulates the order-p hierarchic basis (order 2, 3 or 4), precomputes
  * element geometry and the constraint rows of bc_type.  opt may be NULL

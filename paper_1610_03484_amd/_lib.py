@@ -72,6 +72,8 @@ SIGNATURES = {
     "chom_homogenise": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                    ct.POINTER(ChomReport)]),
     "chom_rve_destroy": (None, [ct.c_void_p]),
+    "chom_yarn_directions": (ct.c_int, [ct.POINTER(ChomMesh), ct.c_int32, ct.c_void_p, ct.c_double, ct.c_int32,
+                                        ct.c_void_p, ct.c_void_p]),
     "chom_damage_history": (ct.c_int, [ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                        ct.c_void_p, ct.c_double, ct.c_int32, ct.c_void_p, ct.c_void_p,
                                        ct.c_void_p]),

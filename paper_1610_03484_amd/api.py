@@ -76,6 +76,39 @@ def material_constants(materials: dict, params=None, c_sat=1.5, degrade_yarn=0):
     return np.array(mech[:]), np.array(th[:]), np.array(mo[:]), keep.value
 
 
+def yarn_directions(coords, tets, phase, yarn_axis=(0, 0, 1, 1), rtol=1e-12, max_iter=20000,
+                    lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    """chom_yarn_directions: fibre axes [n_tets, 3] from the potential-flow solve of
+    every yarn.  coords/tets/phase: all torch device tensors (result on the device)
+    or all numpy arrays (result in host memory)."""
+    mesh = L.ChomMesh()
+    dev = hasattr(coords, "is_cuda") and coords.is_cuda
+    if dev:
+        import torch
+        arrs = [coords.contiguous(), tets.contiguous(), phase.contiguous()]
+        ptrs = [a.data_ptr() for a in arrs]
+        out = torch.empty((arrs[1].shape[0], 3), dtype=torch.float64, device=coords.device)
+        optr = out.data_ptr()
+        stream = torch.cuda.current_stream(coords.device).cuda_stream
+    else:
+        arrs = [np.ascontiguousarray(coords, np.float64), np.ascontiguousarray(tets, np.int32),
+                np.ascontiguousarray(phase, np.int8)]
+        ptrs = [a.ctypes.data for a in arrs]
+        out = np.zeros((arrs[1].shape[0], 3))
+        optr = out.ctypes.data
+        stream = None
+    mesh.n_vertices, mesh.n_tets = arrs[0].shape[0], arrs[1].shape[0]
+    mesh.coords, mesh.tets, mesh.phase = ptrs
+    mesh.fibre_axis = None
+    mesh.lo[:] = lo
+    mesh.hi[:] = hi
+    mesh.on_device = int(dev)
+    ax = (ct.c_int32 * len(yarn_axis))(*yarn_axis)
+    L.check(L.lib().chom_yarn_directions(ct.byref(mesh), len(yarn_axis), ax, rtol, max_iter, ct.c_void_p(optr),
+                                         ct.c_void_p(stream) if stream else None), "chom_yarn_directions")
+    return out
+
+
 def damage_history(T_celsius, c_wt, dt_years, keep0=None, factors=None, c_sat=1.5, keep=True, params=True,
                    hip_stream=None):
     """chom_damage_history.  T_celsius, c_wt [m, n] (step-major), dt_years [m], keep0 [n],
