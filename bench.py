@@ -108,6 +108,7 @@ def algorithmic_mech_order(n, p, nprob, fp32):
 # entry removed) whenever that kernel changes.
 OP_TRAFFIC_BYTES = {
     "c1": {1: 124257650, 2: 128732682, 3: 108221564},
+    "c2": {1: 7952610802, 2: 8208382168, 3: 7050862621},
 }
 
 CAL_BYTES = 256 << 20

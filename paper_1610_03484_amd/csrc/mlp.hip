@@ -20,7 +20,7 @@
 // the next layer's product and transposed for the weight-gradient product, so
 // that both operands of every product are contiguous along the contraction.
 //
-// Inference: one workgroup per 64 points evaluates every member with the
+// Inference: one workgroup per 128 points evaluates every member with the
 // activations in LDS and keeps the ensemble mean and variance in registers.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -39,10 +39,30 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// The same rounding (to nearest, ties to even) by the hardware conversion; finite values only.
+__device__ __forceinline__ uint16_t to_bf16_hw(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// Standard normal distribution function Phi(z) = erfc(-z / sqrt 2) / 2, with erfc
+// from the Chebyshev fit published in Numerical Recipes (Press, Teukolsky,
+// Vetterling, Flannery; function erfcc: fractional error below 1.2e-7 for every
+// argument), one hardware reciprocal and one hardware exponential: far cheaper on
+// the vector units than a general-purpose erf, and exact to well below the
+// bfloat16 rounding the activations then take.
+__device__ __forceinline__ float norm_cdf(float z) {
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * x);
+    const float q = 1.00002368f +
+                    t * (0.37409196f +
+                         t * (0.09678418f +
+                              t * (-0.18628806f +
+                                   t * (0.27886807f +
+                                        t * (-1.13520398f + t * (1.48851587f + t * (-0.82215223f + t * 0.17087277f)))))));
+    const float ec = t * __expf(-x * x - 1.26551223f + t * q);   // erfc(x)
+    return z >= 0.0f ? 1.0f - 0.5f * ec : 0.5f * ec;
+}
+__device__ __forceinline__ float gelu(float z) { return z * norm_cdf(z); }
 __device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    return norm_cdf(z) + z * __expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
 // Features of one record; false when the record is outside the law's domain.
@@ -657,36 +677,45 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_kernel(TrainArgs A) {
 }
 
 // ------------------------------------------------------------------ inference
+// One workgroup of four waves takes PT points through every member.  A hidden
+// layer's product is split by output columns: wave w forms columns
+// [64 w, 64 w + 64) for all PT rows, so each weight is read once per workgroup
+// (not once per wave) and used for PT rows; the activations stay in one LDS
+// buffer, overwritten in place once every wave has read them.  The output layer
+// (36 columns) is split by rows, so each wave holds whole output rows for the
+// decode (block norms by lane shuffles).
 constexpr int PT = 64;          // points per workgroup
 constexpr int XS = FP + 8;      // LDS row strides (bfloat16 elements), padded against bank conflicts
 constexpr int HS = H + 8;
+constexpr int PTILES = PT / 16;
 
 template <int K>
 __device__ __forceinline__ void infer_hidden(const uint16_t *A, int lda, const uint16_t *Wb, const float *bias,
                                              uint16_t *out) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m0 = 16 * wave;
-#pragma unroll 1
-    for (int ch = 0; ch < 4; ++ch) {
-        const int n0 = 64 * ch;
-        f32x4 acc[1][4];
-        zero_acc(acc);
-        wave_mma<1, 4, K>(A + m0 * lda, lda, Wb + n0 * K, K, acc);
+    const int n0 = 64 * wave;
+    f32x4 acc[PTILES][4];
+    zero_acc(acc);
+    wave_mma<PTILES, 4, K>(A, lda, Wb + n0 * K, K, acc);
+    __syncthreads();   // every wave has read A (out may be A)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = n0 + 16 * j + (lane & 15);
-            const int row0 = m0 + 4 * (lane >> 4);
-            const float b = bias[col];
+    for (int j = 0; j < 4; ++j) {
+        const int col = n0 + 16 * j + (lane & 15);
+        const float b = bias[col];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) out[(row0 + q) * HS + col] = to_bf16(gelu(acc[0][j][q] + b));
+        for (int i = 0; i < PTILES; ++i) {
+            const int row0 = 16 * i + 4 * (lane >> 4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out[(row0 + q) * HS + col] = to_bf16_hw(gelu(acc[i][j][q] + b));
         }
     }
 }
 
 __global__ __launch_bounds__(256) void predict_kernel(PredictArgs P) {
     __shared__ __attribute__((aligned(16))) uint16_t xs[PT * XS];
-    __shared__ __attribute__((aligned(16))) uint16_t hb[2 * PT * HS];
+    __shared__ __attribute__((aligned(16))) uint16_t hb[PT * HS];
     __shared__ float s_ymu[NO], s_ysd[NO];
+    static_assert(2 * PT * NO * sizeof(float) <= PT * HS * sizeof(uint16_t), "statistics reuse the activations");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long p0 = (long long)blockIdx.x * PT;
     if (tid < NO) {
@@ -708,58 +737,63 @@ __global__ __launch_bounds__(256) void predict_kernel(PredictArgs P) {
         }
     }
     __syncthreads();
-    float mean[3][4], m2[3][4];
+    // the output layer's rows of this wave: two row tiles of 16
+    constexpr int OT = PTILES / 4;
+    float mean[OT][3][4], m2[OT][3][4];
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
+    for (int i = 0; i < OT; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) mean[j][q] = m2[j][q] = 0.f;
-    uint16_t *h0 = hb, *h1 = hb + PT * HS;
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) mean[i][j][q] = m2[i][j][q] = 0.f;
 #pragma unroll 1
     for (int mem = 0; mem < P.members; ++mem) {
         const MemberW M = member_weights(P.W, mem);
-        infer_hidden<FP>(xs, XS, M.w1b, M.w + OFF_B1, h0);
+        infer_hidden<FP>(xs, XS, M.w1b, M.w + OFF_B1, hb);
         __syncthreads();
-        infer_hidden<H>(h0, HS, M.w2b, M.w + OFF_B2, h1);
+        infer_hidden<H>(hb, HS, M.w2b, M.w + OFF_B2, hb);
         __syncthreads();
-        infer_hidden<H>(h1, HS, M.w3b, M.w + OFF_B3, h0);
+        infer_hidden<H>(hb, HS, M.w3b, M.w + OFF_B3, hb);
         __syncthreads();
         {
-            f32x4 acc[1][4];
+            f32x4 acc[OT][3];
             zero_acc(acc);
-            wave_mma<1, 4, H>(h0 + 16 * wave * HS, HS, M.w4b, H, acc);
+            wave_mma<OT, 3, H>(hb + 16 * OT * wave * HS, HS, M.w4b, H, acc);
             const float cnt = (float)(mem + 1);
             const int c16 = lane & 15, base = lane & ~15;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                // decode this row: de-standardise, block norms of the directions
-                // (sums over the 16 lanes holding the row), scale by exp(log-norm)
-                float v[3], s[3] = {0.f, 0.f, 0.f};
+            for (int i = 0; i < OT; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const int col = 16 * j + c16;
-                    v[j] = 0.f;
-                    if (col < NO) {
-                        v[j] = s_ymu[col] + s_ysd[col] * (acc[0][j][q] + M.w[OFF_B4 + col]);
-                        if (!col_is_log(col)) s[col_block(col)] += phys_weight(col_phys(col)) * v[j] * v[j];
+                for (int q = 0; q < 4; ++q) {
+                    // decode this row: de-standardise, block norms of the directions
+                    // (sums over the 16 lanes holding the row), scale by exp(log-norm)
+                    float v[3], s[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const int col = 16 * j + c16;
+                        v[j] = 0.f;
+                        if (col < NO) {
+                            v[j] = s_ymu[col] + s_ysd[col] * (acc[i][j][q] + M.w[OFF_B4 + col]);
+                            if (!col_is_log(col)) s[col_block(col)] += phys_weight(col_phys(col)) * v[j] * v[j];
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+#pragma unroll
+                        for (int off = 8; off > 0; off >>= 1) s[b] += __shfl_xor(s[b], off);
+                    const float lnC = __shfl(v[0], base + 0);
+                    const float lnK = __shfl(v[1], base + 6);
+                    const float lnD = __shfl(v[1], base + 13);
+                    const float sc[3] = {expf(lnC) / sqrtf(s[0]), expf(lnK) / sqrtf(s[1]), expf(lnD) / sqrtf(s[2])};
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {   // Welford update over members, physical units
+                        const int col = 16 * j + c16;
+                        const float y = (col < NO && !col_is_log(col)) ? v[j] * sc[col_block(col)] : 0.f;
+                        const float dlt = y - mean[i][j][q];
+                        mean[i][j][q] += dlt / cnt;
+                        m2[i][j][q] += dlt * (y - mean[i][j][q]);
                     }
                 }
-#pragma unroll
-                for (int b = 0; b < 3; ++b)
-#pragma unroll
-                    for (int off = 8; off > 0; off >>= 1) s[b] += __shfl_xor(s[b], off);
-                const float lnC = __shfl(v[0], base + 0);
-                const float lnK = __shfl(v[1], base + 6);
-                const float lnD = __shfl(v[1], base + 13);
-                const float sc[3] = {expf(lnC) / sqrtf(s[0]), expf(lnK) / sqrtf(s[1]), expf(lnD) / sqrtf(s[2])};
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {   // Welford update over members, physical units
-                    const int col = 16 * j + c16;
-                    const float y = (col < NO && !col_is_log(col)) ? v[j] * sc[col_block(col)] : 0.f;
-                    const float dlt = y - mean[j][q];
-                    mean[j][q] += dlt / cnt;
-                    m2[j][q] += dlt * (y - mean[j][q]);
-                }
-            }
         }
         __syncthreads();
     }
@@ -767,16 +801,18 @@ __global__ __launch_bounds__(256) void predict_kernel(PredictArgs P) {
     float *smean = reinterpret_cast<float *>(hb);
     float *svar = smean + PT * NO;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int col = 16 * j + (lane & 15);
-        if (col >= NO) continue;
+    for (int i = 0; i < OT; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int row = 16 * wave + 4 * (lane >> 4) + q;
-            smean[row * NO + col] = mean[j][q];
-            svar[row * NO + col] = P.members > 1 ? m2[j][q] / (float)(P.members - 1) : 0.f;
+        for (int j = 0; j < 3; ++j) {
+            const int col = 16 * j + (lane & 15);
+            if (col >= NO) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * (OT * wave + i) + 4 * (lane >> 4) + q;
+                smean[row * NO + col] = mean[i][j][q];
+                svar[row * NO + col] = P.members > 1 ? m2[i][j][q] / (float)(P.members - 1) : 0.f;
+            }
         }
-    }
     __syncthreads();
     if (tid < PT) {
         const long long p = p0 + tid;
