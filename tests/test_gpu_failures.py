@@ -101,3 +101,39 @@ def test_forced_fp64_fallback_matches_oracle(bc):
     assert r["status"] == 0
     assert r["fp64_fallback"] == [1, 1, 1]
     assert max(e) <= 1e-9
+
+
+@pytest.mark.parametrize("thresh", [0.0, float("inf")])
+def test_surrogate_threshold_limits(thresh):
+    """Threshold 0: every record of a 3-member ensemble (disagreement > 0) goes to
+    the RVE fallback, in chunks, and takes the RVE's own result.  Infinite
+    threshold: none does, and the result is the ensemble mean of predict."""
+    require_gpu()
+    from paper_1610_03484_amd import Surrogate
+    from mlp_util import norm_record, weights
+    from oracle import mlp as ref
+    n = 5
+    params = ci.draw_params(41, n)
+    banner(f"surrogate fallback with threshold {thresh}, {n} records, 4^3 periodic FP64 fallback, chunks of 2")
+    s = Surrogate(members=3, seed=0)
+    for m in range(3):
+        s.set_weights(m, weights(50 + m))
+    x_mu, x_sd = ref.column_stats(ref.features(ci.draw_params(42, 64)))
+    y_mu = np.zeros(36)
+    y_sd = np.ones(36)
+    s.set_normalisation(norm_record(x_mu, x_sd, y_mu, y_sd))
+    rve = _rve(4, "periodic", precision="fp64", rtol=1e-12)
+    C, K, D, dis, used, nfb = s.homogenise(rve, params, thresh=thresh, chunk=2)
+    Cp, Kp, Dp, disp = s.predict(params)
+    assert np.all(dis > 0.0) and np.array_equal(dis, disp)
+    if thresh == 0.0:
+        Cr, Kr, Dr, rep = rve.homogenise(params)
+        assert nfb == n and np.all(used == 1)
+        for i in range(n):
+            e = result_errors(C[i], K[i], D[i], Cr[i], Kr[i], Dr[i])
+            assert max(e) <= 1e-12, (i, e)
+    else:
+        assert nfb == 0 and np.all(used == 0)
+        assert np.array_equal(C, Cp) and np.array_equal(K, Kp) and np.array_equal(D, Dp)
+    rve.close()
+    s.close()
