@@ -373,8 +373,10 @@ int chom_mlp_set_normalisation(chom_mlp *mlp, const double *record);
 int chom_mlp_get_normalisation(const chom_mlp *mlp, double *record);
 
 /* Train every member on n (record, result) pairs: minibatch Adam on the mean
- * squared error of the standardised outputs, one launch for the whole call
- * (each member shuffles the set independently every epoch).  loss_history
+ * squared error of the standardised outputs (each member shuffles the set
+ * independently every epoch; all members advance together, every minibatch
+ * step a fixed sequence of kernels replayed from HIP graphs; the call returns
+ * when training has finished).  loss_history
  * [members][epochs] (host, nullable) receives each epoch's mean loss.  Calls
  * may be repeated (training continues).  1 <= n < 2^31.
  * Errors: CHOM_EINVAL (records outside the degradation law's domain, sizes),
@@ -395,7 +397,7 @@ int chom_mlp_loss_grad(chom_mlp *mlp, int32_t member, const chom_params *params,
  * chom_mlp_loss_grad, but every pointer is a device pointer -- params [n]
  * (chom_params), C [n][21], K [n][6], D [n][6] in, *loss (one double) and grad
  * [143,652] (FP32) out -- whatever the handle's device_ptrs setting, and the
- * working memory (standardised rows, flag, training scratch; about 3.4 MB) is a
+ * working memory (standardised rows, flag, training scratch; about 2.7 MB) is a
  * static array of the library that each device holds until the process ends.
  * n is limited to 4096 records (CHOM_EINVAL beyond).  Calls that overlap on one
  * device share that array and race: serialise them.  Work is queued on the

@@ -14,7 +14,9 @@ constexpr int NO = 36;            // network outputs: per block (C 21, K 6, D 6)
 constexpr int NPHYS = 33;         // physical outputs: C upper 21, K 6, D 6
 constexpr int OP = 64;            // outputs padded (contraction of the first backward product)
 constexpr int NB = 256;           // largest minibatch
-constexpr int TRAIN_THREADS = 512;
+constexpr int TRAIN_THREADS = 512;   // eight waves
+constexpr int SL = 32;            // hidden columns per training workgroup
+constexpr int NSL = H / SL;       // training workgroups per member
 
 // Flat FP32 parameter layout of one member (row-major [out][in] matrices).
 constexpr int OFF_W1 = 0;
@@ -34,20 +36,38 @@ constexpr int NORM_YMU = 2 * NF;
 constexpr int NORM_YSD = 2 * NF + NO;
 constexpr int NORM_LEN = 2 * NF + 2 * NO;
 
-// Minibatch scratch of one training workgroup (bytes).
-constexpr long long SCRATCH_BYTES = 2LL * NB * FP * 2 + (long long)NB * NO * 4 + 6LL * NB * H * 2 +
-                                    3LL * NB * H * 4 + 2LL * NB * OP * 2 + 6LL * NB * H * 2;
+// Training scratch: a control block (the step counters of a launch sequence),
+// then per member the minibatch arrays shared by its workgroups (byte offsets):
+// activations of the three hidden layers row-major and transposed (bfloat16),
+// gelu'(z) (FP32), the hidden gradients of layers 3 and 2 (bfloat16), the
+// output-bias gradient of the step, the minibatch rows, the epoch's shuffle and
+// the loss accumulator.
+constexpr long long TS_CTRL = 256;
+constexpr long long MS_A = 0;
+constexpr long long MS_AT = MS_A + 3LL * NB * H * 2;
+constexpr long long MS_D = MS_AT + 3LL * NB * H * 2;
+constexpr long long MS_G = MS_D + 3LL * NB * H * 4;
+constexpr long long MS_B4G = MS_G + 2LL * NB * H * 2;
+constexpr long long MS_SRC = MS_B4G + 256;          // 2 x [NB] source rows of a step (by step parity)
+constexpr long long MS_PERM = MS_SRC + 2LL * NB * 4;  // the current epoch's shuffle (2 x int64)
+constexpr long long MS_LOSS = MS_PERM + 16;
+constexpr long long MEMBER_SCRATCH = MS_LOSS + 240;
+constexpr long long train_scratch_bytes(int members) { return TS_CTRL + members * MEMBER_SCRATCH; }
+
+// bfloat16 copies of one member's weights (elements): w1b [H][FP], w2b, w3b
+// [H][H], w4b [OP][H], w2t, w3t [H][H], w4t [H][OP].
+constexpr long long BF_PER_MEMBER = (long long)H * FP + 4LL * H * H + 2LL * OP * H;
 
 // Workspace of a gradient evaluation in caller-provided memory (no allocation):
 // the bad-record flag, the standardised rows of up to `rows` records (bfloat16
-// features, FP32 targets) and one training workgroup's minibatch scratch, each
-// part 256-byte aligned.
+// features, FP32 targets) and the training scratch of one member, each part
+// 256-byte aligned.
 constexpr long long ws_align(long long b) { return (b + 255) / 256 * 256; }
 constexpr long long WS_FLAG = 0;
 constexpr long long WS_XN = 256;
 constexpr long long ws_tn(long long rows) { return WS_XN + ws_align(rows * FP * 2); }
 constexpr long long ws_train(long long rows) { return ws_tn(rows) + ws_align(rows * NO * 4); }
-constexpr long long ws_bytes(long long rows) { return ws_train(rows) + ws_align(SCRATCH_BYTES); }
+constexpr long long ws_bytes(long long rows) { return ws_train(rows) + ws_align(train_scratch_bytes(1)); }
 
 // Degradation law of Sec. 4 (constant exposure).
 constexpr double BETA = -0.001682;    // per day
@@ -59,6 +79,7 @@ struct Weights {                 // all members, member-major
     float *master, *adam_m, *adam_v;            // [M][NPARAM]
     uint16_t *w1b, *w2b, *w3b, *w4b;            // bfloat16 copies [M][H][FP], [M][H][H] x2, [M][OP][H]
     uint16_t *w2t, *w3t, *w4t;                  // transposes [M][H][H] x2, [M][H][OP]
+    uint16_t *alt;                              // training: second set of copies, [M][BF_PER_MEMBER]
 };
 
 struct TrainArgs {
@@ -68,13 +89,13 @@ struct TrainArgs {
     int epochs, epoch0, nb;      // epoch0: index of the first epoch (shuffle stream)
     float lr0, lr1, beta1, beta2, eps;
     unsigned long long seed;
-    long long step0;             // Adam steps taken before this launch
+    long long step0;             // Adam steps taken before this launch sequence
     int member;                  // first member (gradient mode: the member)
     float *grad;                 // gradient mode: accumulate dLoss/dparam here (NPARAM), no update
     float *loss_hist;            // [members][epochs] or null
     double *loss_out;            // loss of the last epoch (or of the gradient evaluation)
     Weights W;
-    unsigned char *scratch;      // members x SCRATCH_BYTES
+    unsigned char *scratch;      // train_scratch_bytes(members)
 };
 
 struct PredictArgs {
@@ -93,7 +114,11 @@ hipError_t launch_stats(const double *params, const double *C, const double *K, 
                         double c_sat, double *norm, int *bad, hipStream_t s);
 hipError_t launch_prepare(const double *params, const double *C, const double *K, const double *D, long long n,
                           double c_sat, const double *norm, uint16_t *xn, float *tn, int *bad, hipStream_t s);
-hipError_t launch_train(const TrainArgs &a, int blocks, hipStream_t s);
+// Training (or, with a.grad set, gradient accumulation) over a.epochs epochs of
+// minibatches, `members` members at once.  Every step is five kernels; `cap` is
+// an optional stream on which the library captures a HIP graph of up to 64 steps
+// that it then replays on s (null: the kernels are launched one by one).
+hipError_t launch_train(const TrainArgs &a, int members, hipStream_t s, hipStream_t cap);
 hipError_t launch_predict(const PredictArgs &a, hipStream_t s);
 hipError_t launch_select(const double *dis, long long n, double thresh, int *idx, int *count, unsigned char *flag,
                          hipStream_t s);

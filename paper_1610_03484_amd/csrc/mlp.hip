@@ -13,14 +13,14 @@
 // activations, the loss, gradients and the Adam state are FP32; feature
 // standardisation and the final de-standardisation are FP64.
 //
-// Training: one workgroup per ensemble member runs every epoch and minibatch
-// (forward, backward, Adam) in one launch; members never exchange data, so the
-// launch needs no grid-wide synchronisation.  Activations of the minibatch live
-// in a per-member global scratch (L2 resident); each is stored row-major for
-// the next layer's product and transposed for the weight-gradient product, so
-// that both operands of every product are contiguous along the contraction.
+// Training: each member's minibatch step is spread over eight workgroups that
+// split every hidden layer by columns (details at the training kernels); all
+// members run in the same launches.  Activations of the minibatch live in a
+// per-member global scratch; each is stored row-major for the next layer's
+// product and transposed for the weight-gradient product, so that both operands
+// of every product are contiguous along the contraction.
 //
-// Inference: one workgroup per 128 points evaluates every member with the
+// Inference: one workgroup per 64 points evaluates every member with the
 // activations in LDS and keeps the ensemble mean and variance in registers.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -115,23 +115,23 @@ __device__ double encoded_value(const double *C, const double *K, const double *
     return col_is_log(col) ? log(nrm) : phys_value(C, K, D, i, col_phys(col)) / nrm;
 }
 
-// The phases of a training step are separate (non-inlined) functions: inlined
-// into the step loop, the compiler hoists every phase's loop-invariant address
-// arithmetic out of the loop at once and spills.
-//
 // One wave: acc[i][j] += A[16i.., :K] * B[16j.., :K]^T for 16x16 tiles; A and B are
 // bfloat16, row-major with the contraction index contiguous (row strides lda, ldb).
 // Lane l supplies row (l & 15) and the 8 contraction entries starting at 8 (l >> 4)
 // of each operand tile; the result element (4 (l >> 4) + q, l & 15) of tile (i, j)
 // lands in acc[i][j][q].
-template <int TM, int TN, int K>
+//
+// FULL unrolls the contraction completely, so that every operand load is issued
+// before the first product (for operands that come from memory written by the
+// previous kernel, whose latency would otherwise be paid once per step of 32).
+template <int TM, int TN, int K, bool FULL = false>
 __device__ __forceinline__ void wave_mma(const uint16_t *__restrict__ A, int lda, const uint16_t *__restrict__ B,
                                          int ldb, f32x4 (&acc)[TM][TN]) {
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, kq = (lane >> 4) << 3;
     const uint16_t *Ap = A + r * lda + kq;
     const uint16_t *Bp = B + r * ldb + kq;
-#pragma unroll 2
+#pragma unroll FULL ? K / 32 : 2
     for (int k0 = 0; k0 < K; k0 += 32) {
         bf16x8 a[TM], b[TN];
 #pragma unroll
@@ -176,33 +176,6 @@ __device__ __forceinline__ MemberW member_weights(const Weights &W, int mem) {
     o.w4t = W.w4t + (size_t)mem * H * OP;
     return o;
 }
-
-// Minibatch scratch of one member (SCRATCH_BYTES): byte offsets of each array.
-constexpr long long SO_XB = 0;                                   // [NB][FP] bf16
-constexpr long long SO_XBT = SO_XB + NB * FP * 2;                // [FP][NB] bf16
-constexpr long long SO_TB = SO_XBT + NB * FP * 2;                // [NB][NO] f32
-constexpr long long SO_A = SO_TB + NB * NO * 4;                  // 3 x [NB][H] bf16 (hidden outputs)
-constexpr long long SO_AT = SO_A + 3LL * NB * H * 2;             // 3 x [H][NB] bf16 (transposed)
-constexpr long long SO_D = SO_AT + 3LL * NB * H * 2;             // 3 x [NB][H] f32 (gelu'(z))
-constexpr long long SO_G4 = SO_D + 3LL * NB * H * 4;             // [NB][OP] bf16 (output gradient)
-constexpr long long SO_G4T = SO_G4 + NB * OP * 2;                // [OP][NB] bf16
-constexpr long long SO_G = SO_G4T + NB * OP * 2;                 // 3 x [NB][H] bf16 (hidden gradients)
-constexpr long long SO_GT = SO_G + 3LL * NB * H * 2;             // 3 x [H][NB] bf16
-static_assert(SO_GT + 3LL * NB * H * 2 == SCRATCH_BYTES, "scratch layout");
-
-template <typename T> __device__ __forceinline__ T *sp(unsigned char *base, long long off) {
-    return reinterpret_cast<T *>(base + off);
-}
-#define S_XB sp<uint16_t>(sb, SO_XB)
-#define S_XBT sp<uint16_t>(sb, SO_XBT)
-#define S_TB sp<float>(sb, SO_TB)
-#define S_A(l) sp<uint16_t>(sb, SO_A + (l) * (long long)NB * H * 2)
-#define S_AT(l) sp<uint16_t>(sb, SO_AT + (l) * (long long)NB * H * 2)
-#define S_D(l) sp<float>(sb, SO_D + (l) * (long long)NB * H * 4)
-#define S_G4 sp<uint16_t>(sb, SO_G4)
-#define S_G4T sp<uint16_t>(sb, SO_G4T)
-#define S_G(l) sp<uint16_t>(sb, SO_G + (l) * (long long)NB * H * 2)
-#define S_GT(l) sp<uint16_t>(sb, SO_GT + (l) * (long long)NB * H * 2)
 
 // ------------------------------------------------------------------ bf16 copies of the master weights
 // For every member: w1b [H][FP] (columns >= NF zero), w2b/w3b [H][H], w4b [OP][H]
@@ -320,201 +293,77 @@ __global__ void prepare_kernel(const double *params, const double *C, const doub
 }
 
 // ------------------------------------------------------------------ training
+// A minibatch step of one member is spread over NSL workgroups, workgroup j
+// owning hidden columns [SL j, SL j + SL) of every layer: it forms those columns
+// of the layer's output for all rows, and the weight rows of those outputs are
+// its alone -- their gradient (the product of its own output-gradient columns
+// with the full input activations), their Adam state and their update.  Only
+// whole activations and output gradients cross workgroups, through the
+// member's scratch, so a step is five kernels in order:
+//   F2, F3      hidden layers 2 and 3 (layer 1 runs at the end of the previous step)
+//   B3          output layer and loss (every workgroup, redundantly), output-layer
+//               weight columns, layer-3 gradient columns, layer-3 weight rows
+//   B2          layer-2 gradient columns and weight rows (and the output bias)
+//   B1F1        layer-1 gradient columns and weight rows, then layer 1 of the
+//               next step with the updated rows
+// A step reads the bfloat16 weight copies of set (step & 1) and writes the
+// updated copies into the other set, so no kernel reads a copy that another
+// workgroup of the same step is rewriting.  Each kernel reads its step index
+// from a counter of its own that the previous kernel of the sequence set, so a
+// graph of several steps can be replayed unchanged.
+constexpr int K_F2 = 0, K_F3 = 1, K_B3 = 2, K_B2 = 3, K_B1 = 4;
+static_assert(TRAIN_THREADS % 64 == 0 && TRAIN_THREADS / 64 == 8 && TRAIN_THREADS >= NB, "eight waves; a thread per row");
+// LDS row strides (bfloat16 elements), padded so that the 16 rows an MFMA
+// operand load touches fall on different banks.
+constexpr int GTS = NB + 8;    // transposed gradient tiles [.][NB]
+constexpr int G4S = OP + 8;    // output gradient [NB][OP]
+constexpr int X1S = FP + 8;    // features [NB][FP]
+
+struct BfView {
+    uint16_t *w1b, *w2b, *w3b, *w4b, *w2t, *w3t, *w4t;
+};
+
+__device__ __forceinline__ BfView bf_view(const Weights &W, int mem, int set) {
+    BfView v;
+    if (set == 0) {
+        v.w1b = W.w1b + (size_t)mem * H * FP;
+        v.w2b = W.w2b + (size_t)mem * H * H;
+        v.w3b = W.w3b + (size_t)mem * H * H;
+        v.w4b = W.w4b + (size_t)mem * OP * H;
+        v.w2t = W.w2t + (size_t)mem * H * H;
+        v.w3t = W.w3t + (size_t)mem * H * H;
+        v.w4t = W.w4t + (size_t)mem * H * OP;
+    } else {
+        uint16_t *b = W.alt + (size_t)mem * BF_PER_MEMBER;
+        v.w1b = b;
+        v.w2b = v.w1b + H * FP;
+        v.w3b = v.w2b + H * H;
+        v.w4b = v.w3b + H * H;
+        v.w2t = v.w4b + OP * H;
+        v.w3t = v.w2t + H * H;
+        v.w4t = v.w3t + H * H;
+    }
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ T *sp(unsigned char *base, long long off) {
+    return reinterpret_cast<T *>(base + off);
+}
+#define S_A(l) sp<uint16_t>(sb, MS_A + (l) * (long long)NB * H * 2)
+#define S_AT(l) sp<uint16_t>(sb, MS_AT + (l) * (long long)NB * H * 2)
+#define S_D(l) sp<float>(sb, MS_D + (l) * (long long)NB * H * 4)
+#define S_G(l) sp<uint16_t>(sb, MS_G + (l) * (long long)NB * H * 2)   // l = 0: layer 3, 1: layer 2
+#define S_B4G sp<float>(sb, MS_B4G)
+#define S_LOSS sp<double>(sb, MS_LOSS)
+
 struct AdamC {
     float lr, b1, b2, eps, bc1, bc2;
 };
 
-__device__ __forceinline__ float adam_update(float *w, float *m, float *v, float g, const AdamC &c) {
-    const float mm = c.b1 * *m + (1.0f - c.b1) * g;
-    const float vv = c.b2 * *v + (1.0f - c.b2) * g * g;
-    *m = mm;
-    *v = vv;
-    const float nw = *w - c.lr * (mm / c.bc1) / (sqrtf(vv / c.bc2) + c.eps);
-    *w = nw;
-    return nw;
-}
-
-// Hidden layer forward over the NB minibatch rows: z = A W^T + b, a = gelu(z).
-// Writes a (row-major and transposed, bfloat16) and gelu'(z) (FP32).
-template <int K>
-__device__ __noinline__ void fwd_hidden(const uint16_t *A, const uint16_t *Wb, const float *bias, uint16_t *aout,
-                                           uint16_t *atout, float *dout) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m0 = 32 * wave;
-#pragma unroll 1
-    for (int ch = 0; ch < 4; ++ch) {
-        const int n0 = 64 * ch;
-        f32x4 acc[2][4];
-        zero_acc(acc);
-        wave_mma<2, 4, K>(A + m0 * K, K, Wb + n0 * K, K, acc);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int col = n0 + 16 * j + (lane & 15);
-                const int row0 = m0 + 16 * i + 4 * (lane >> 4);
-                const float b = bias[col];
-                uint16_t h[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float z = acc[i][j][q] + b;
-                    h[q] = to_bf16(gelu(z));
-                    aout[(row0 + q) * H + col] = h[q];
-                    dout[(row0 + q) * H + col] = gelu_grad(z);
-                }
-                uint2 pk;
-                pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-                pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-                *reinterpret_cast<uint2 *>(atout + col * NB + row0) = pk;
-            }
-    }
-}
-
-// Backward through a hidden layer's input: g = bf16((G Wt^T) * gelu'(z)), with G
-// [NB][K] and Wt [H][K] (the transpose of the layer's weights).  Writes g
-// row-major (when grow) and transposed.
-template <int K>
-__device__ __noinline__ void bwd_data(const uint16_t *G, const uint16_t *Wt, const float *dprev, uint16_t *grow,
-                                         uint16_t *gtr) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m0 = 32 * wave;
-#pragma unroll 1
-    for (int ch = 0; ch < 4; ++ch) {
-        const int n0 = 64 * ch;
-        f32x4 acc[2][4];
-        zero_acc(acc);
-        wave_mma<2, 4, K>(G + m0 * K, K, Wt + n0 * K, K, acc);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int col = n0 + 16 * j + (lane & 15);
-                const int row0 = m0 + 16 * i + 4 * (lane >> 4);
-                uint16_t h[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    h[q] = to_bf16(acc[i][j][q] * dprev[(row0 + q) * H + col]);
-                    if (grow) grow[(row0 + q) * H + col] = h[q];
-                }
-                uint2 pk;
-                pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-                pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-                *reinterpret_cast<uint2 *>(gtr + col * NB + row0) = pk;
-            }
-    }
-}
-
-// Sum over the NB rows of a transposed gradient row (bias gradient).
-__device__ __forceinline__ float row_sum(const uint16_t *gt_row) {
-    float s = 0.f;
-#pragma unroll 4
-    for (int r = 0; r < NB; r += 8) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(gt_row + r);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s += from_bf16((uint16_t)(w[k] & 0xFFFF)) + from_bf16((uint16_t)(w[k] >> 16));
-    }
-    return s;
-}
-
-// Gradient of one weight entry: accumulate (gradient mode) or Adam-update the master
-// and return the new value through *nw.
-__device__ __forceinline__ bool apply_grad(const MemberW &M, float *grad, int off, float g, const AdamC &c,
-                                           float *nw) {
-    if (grad) {
-        grad[off] += g;
-        return false;
-    }
-    *nw = adam_update(M.w + off, M.m + off, M.v + off, g, c);
-    return true;
-}
-
-// Weight gradient of a 256 x 256 layer (l = 2 or 3): dW[o][i] = sum_r Gt[o][r] At[i][r].
-__device__ __noinline__ void wgrad_hidden(const MemberW &M, float *grad, const uint16_t *Gt, const uint16_t *At,
-                                             int off_w, uint16_t *wb, uint16_t *wt, const AdamC &c) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m0 = 32 * wave;
-#pragma unroll 1
-    for (int ch = 0; ch < 4; ++ch) {
-        const int n0 = 64 * ch;
-        f32x4 acc[2][4];
-        zero_acc(acc);
-        wave_mma<2, 4, NB>(Gt + m0 * NB, NB, At + n0 * NB, NB, acc);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int in = n0 + 16 * j + (lane & 15);
-                const int o0 = m0 + 16 * i + 4 * (lane >> 4);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    float nw;
-                    if (apply_grad(M, grad, off_w + (o0 + q) * H + in, acc[i][j][q], c, &nw)) {
-                        const uint16_t h = to_bf16(nw);
-                        wb[(o0 + q) * H + in] = h;
-                        wt[in * H + o0 + q] = h;
-                    }
-                }
-            }
-    }
-}
-
-// Weight gradient of the output layer: dW4[o][i] = sum_r G4t[o][r] A3t[i][r], o < NO.
-__device__ __noinline__ void wgrad_out(const MemberW &M, float *grad, const uint16_t *G4t, const uint16_t *A3t,
-                                          const AdamC &c) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // 3 row tiles (rows 48..63 are padding) x 4 column quarters = 12 jobs over 8 waves
-#pragma unroll 1
-    for (int job = wave; job < 12; job += TRAIN_THREADS / 64) {
-        const int o_tile = job % 3, quarter = job / 3;
-        f32x4 acc[1][4];
-        zero_acc(acc);
-        wave_mma<1, 4, NB>(G4t + 16 * o_tile * NB, NB, A3t + 64 * quarter * NB, NB, acc);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int in = 64 * quarter + 16 * j + (lane & 15);
-            const int o0 = 16 * o_tile + 4 * (lane >> 4);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int o = o0 + q;
-                if (o >= NO) continue;
-                float nw;
-                if (apply_grad(M, grad, OFF_W4 + o * H + in, acc[0][j][q], c, &nw)) {
-                    const uint16_t h = to_bf16(nw);
-                    M.w4b[o * H + in] = h;
-                    M.w4t[in * OP + o] = h;
-                }
-            }
-        }
-    }
-}
-
-// Weight gradient of the first layer: dW1[o][k] = sum_r G1t[o][r] Xt[k][r], k < NF.
-__device__ __noinline__ void wgrad_first(const MemberW &M, float *grad, const uint16_t *G1t, const uint16_t *Xt,
-                                            const AdamC &c) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m0 = 32 * wave;
-    f32x4 acc[2][1];
-    zero_acc(acc);
-    wave_mma<2, 1, NB>(G1t + m0 * NB, NB, Xt, NB, acc);
-    const int k = lane & 15;
-    if (k >= NF) return;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int o0 = m0 + 16 * i + 4 * (lane >> 4);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            float nw;
-            if (apply_grad(M, grad, OFF_W1 + (o0 + q) * NF + k, acc[i][0][q], c, &nw))
-                M.w1b[(o0 + q) * FP + k] = to_bf16(nw);
-        }
-    }
-}
-
-__device__ __noinline__ void bias_grad(const MemberW &M, float *grad, const uint16_t *gt_row, int off, const AdamC &c) {
-    const float g = row_sum(gt_row);
-    float nw;
-    (void)apply_grad(M, grad, off, g, c, &nw);
+__device__ __forceinline__ void adam_update(float &w, float &m, float &v, float g, const AdamC &c) {
+    m = c.b1 * m + (1.0f - c.b1) * g;
+    v = c.b2 * v + (1.0f - c.b2) * g * g;
+    w = w - c.lr * (m / c.bc1) / (sqrtf(v / c.bc2) + c.eps);
 }
 
 __device__ __forceinline__ long long perm_index(long long i, long long n, long long a, long long b) {
@@ -539,141 +388,547 @@ __device__ __forceinline__ long long gcd_ll(long long a, long long b) {
     return a;
 }
 
-// One minibatch step of one member: gather, forward, loss, backward, update.
-__device__ __noinline__ void train_step(const TrainArgs &A, const MemberW &M, unsigned char *sb, long long st,
-                                        long long total, long long gstep, long long pa, long long pb,
-                                        double *s_loss) {
-    const int tid = threadIdx.x, lane = tid & 63;
-    const long long n = A.n;
-    const int nb = A.nb;
-    const long long i0 = st * nb;
-    const int nbe = (int)min((long long)nb, n - i0);
-    // ---- gather the minibatch (rows past nbe are zero): one shuffled row index per thread
-    __shared__ int s_src[NB];
-    if (tid < NB) s_src[tid] = tid < nbe ? (int)perm_index(i0 + tid, n, pa, pb) : -1;
-    __syncthreads();
-    for (int e = tid; e < NB * FP; e += TRAIN_THREADS) {
-        const int r = e / FP, k = e - (e / FP) * FP;
-        const int src = s_src[r];
-        const uint16_t v = src >= 0 ? A.xn[(long long)src * FP + k] : (uint16_t)0;
-        S_XB[r * FP + k] = v;
-        S_XBT[k * NB + r] = v;
+// Where step g of the sequence stands: its epoch, its position in the epoch
+// and its rows.
+struct StepPos {
+    long long g, ep, st, i0, steps, total;
+    int nbe;
+};
+
+__device__ __forceinline__ StepPos step_pos(const TrainArgs &A, long long g) {
+    StepPos c;
+    c.g = g;
+    c.steps = (A.n + A.nb - 1) / A.nb;
+    c.total = c.steps * (long long)A.epochs;
+    c.ep = g / c.steps;
+    c.st = g - c.ep * c.steps;
+    c.i0 = c.st * A.nb;
+    c.nbe = (int)min((long long)A.nb, A.n - c.i0);
+    return c;
+}
+
+// Source rows of step c's minibatch into src[NB] (LDS; -1 past the rows of the
+// step).  The epoch's shuffle is an affine bijection drawn from the member's
+// stream when the epoch starts (and kept in the member's scratch by workgroup 0
+// for the rest of the epoch).  Every thread of the workgroup must call this.
+__device__ void step_rows(const TrainArgs &A, int mem, const StepPos &c, unsigned char *sb, int *src) {
+    __shared__ long long s_pa, s_pb;
+    long long *perm = reinterpret_cast<long long *>(sb + MS_PERM);
+    __syncthreads();   // src and s_pa, s_pb of an earlier call are no longer read
+    if (threadIdx.x == 0) {
+        long long a = 1, b = 0;
+        if (A.grad == nullptr && A.n > 1) {
+            if (c.st == 0) {
+                const uint64_t key = (A.seed << 32) + ((uint64_t)mem << 20) + (uint64_t)(A.epoch0 + c.ep);
+                a = 1 + (long long)(splitmix(key) % (uint64_t)(A.n - 1));
+                while (gcd_ll(a, A.n) != 1) a = a % (A.n - 1) + 1;      // ends: a = 1 is coprime
+                b = (long long)(splitmix(key ^ 0x5DEECE66Dull) % (uint64_t)A.n);
+                if (blockIdx.x == 0) {
+                    perm[0] = a;
+                    perm[1] = b;
+                }
+            } else {
+                a = perm[0];
+                b = perm[1];
+            }
+        }
+        s_pa = a;
+        s_pb = b;
     }
-    for (int e = tid; e < NB * NO; e += TRAIN_THREADS) {
-        const int r = e / NO, o = e - (e / NO) * NO;
-        const int src = s_src[r];
-        S_TB[e] = src >= 0 ? A.tn[(long long)src * NO + o] : 0.f;
+    __syncthreads();
+    for (int r = threadIdx.x; r < NB; r += TRAIN_THREADS)
+        src[r] = r < c.nbe ? (int)perm_index(c.i0 + r, A.n, s_pa, s_pb) : -1;
+    __syncthreads();
+}
+
+__device__ AdamC adam_constants(const TrainArgs &A, const StepPos &c) {
+    AdamC a;
+    const long long t = A.step0 + c.g + 1;
+    const double frac = c.total > 1 ? (double)c.g / (double)(c.total - 1) : 1.0;
+    const double lr = A.lr1 + 0.5 * (A.lr0 - A.lr1) * (1.0 + cos(3.14159265358979323846 * frac));
+    a.lr = (float)lr;
+    a.b1 = A.beta1;
+    a.b2 = A.beta2;
+    a.eps = A.eps;
+    a.bc1 = (float)(1.0 - pow((double)A.beta1, (double)t));
+    a.bc2 = (float)(1.0 - pow((double)A.beta2, (double)t));
+    return a;
+}
+
+// Gradients of N parameters of a lane: accumulate them (gradient mode) or take
+// an Adam step (the new master values are left in w).  Every load is issued
+// before the first store, so the lane waits for memory once, not once per
+// parameter.
+template <int N>
+__device__ __forceinline__ void apply_grads(const TrainArgs &A, const MemberW &M, const int (&off)[N],
+                                            const float (&g)[N], const bool (&on)[N], const AdamC &c,
+                                            float (&w)[N]) {
+    if (A.grad != nullptr) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) w[k] = on[k] ? A.grad[off[k]] : 0.f;
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            if (on[k]) A.grad[off[k]] = w[k] + g[k];
+        return;
     }
-    __syncthreads();
-    // ---- forward
-    fwd_hidden<FP>(S_XB, M.w1b, M.w + OFF_B1, S_A(0), S_AT(0), S_D(0));
-    __syncthreads();
-    fwd_hidden<H>(S_A(0), M.w2b, M.w + OFF_B2, S_A(1), S_AT(1), S_D(1));
-    __syncthreads();
-    fwd_hidden<H>(S_A(1), M.w3b, M.w + OFF_B3, S_A(2), S_AT(2), S_D(2));
-    __syncthreads();
-    // ---- output layer, loss and output gradient
-    {
-        const int wave = tid >> 6;
-        const int m0 = 32 * wave;
-        const float scale = 2.0f / (float)((A.grad != nullptr ? (double)n : (double)nbe) * NO);
-        f32x4 acc[2][4];
-        zero_acc(acc);
-        wave_mma<2, 4, H>(S_A(2) + m0 * H, H, M.w4b, H, acc);
-        double ls = 0.0;
+    float m[N], v[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        w[k] = on[k] ? M.w[off[k]] : 0.f;
+        m[k] = on[k] ? M.m[off[k]] : 0.f;
+        v[k] = on[k] ? M.v[off[k]] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        if (!on[k]) continue;
+        adam_update(w[k], m[k], v[k], g[k], c);
+        M.w[off[k]] = w[k];
+        M.m[off[k]] = m[k];
+        M.v[off[k]] = v[k];
+    }
+}
+
+__device__ __forceinline__ void apply_grad1(const TrainArgs &A, const MemberW &M, int off, float g, const AdamC &c) {
+    const int o[1] = {off};
+    const float gg[1] = {g};
+    const bool on[1] = {true};
+    float w[1];
+    apply_grads<1>(A, M, o, gg, on, c, w);
+}
+
+// Sum over the NB rows of a transposed gradient row (bias gradient).
+__device__ __forceinline__ float row_sum(const uint16_t *gt_row) {
+    float s = 0.f;
+#pragma unroll 4
+    for (int r = 0; r < NB; r += 8) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(gt_row + r);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += from_bf16((uint16_t)(w[k] & 0xFFFF)) + from_bf16((uint16_t)(w[k] >> 16));
+    }
+    return s;
+}
+
+// The step counter of kernel k; the first workgroup hands the step on to the
+// next kernel of the sequence (B1F1 hands on the next step).
+__device__ __forceinline__ long long take_step(const TrainArgs &A, int k) {
+    int *ctr = reinterpret_cast<int *>(A.scratch);
+    const long long g = ctr[k];
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ctr[(k + 1) % 5] = (int)g + (k == K_B1 ? 1 : 0);
+    return g;
+}
+
+__device__ __forceinline__ unsigned char *member_scratch(const TrainArgs &A) {
+    return A.scratch + TS_CTRL + (size_t)blockIdx.y * MEMBER_SCRATCH;
+}
+
+// Columns [SL j, SL j + SL) of a hidden layer for all NB rows: z = A W^T + b,
+// written as a = gelu(z) (bfloat16, row-major and transposed) and gelu'(z).  A is
+// [NB][K] with row stride lda; Wrows points at the first of the layer's weight
+// rows SL j .. SL j + SL - 1 (row stride K).
+template <int K>
+__device__ __forceinline__ void fwd_slice(const uint16_t *A, int lda, const uint16_t *Wrows, const float *bias,
+                                          int j, uint16_t *aout, uint16_t *atout, float *dout) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m0 = 32 * wave;
+    f32x4 acc[2][2];
+    zero_acc(acc);
+    wave_mma<2, 2, K, true>(A + m0 * lda, lda, Wrows, K, acc);
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+        const int col = SL * j + 16 * jj + (lane & 15);
+        const float b = bias[col];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row0 = m0 + 16 * i + 4 * (lane >> 4);
+            uint16_t h[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float z = acc[i][jj][q] + b;
+                h[q] = to_bf16(gelu(z));
+                aout[(row0 + q) * H + col] = h[q];
+                dout[(row0 + q) * H + col] = gelu_grad(z);
+            }
+            uint2 pk;
+            pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+            pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+            *reinterpret_cast<uint2 *>(atout + col * NB + row0) = pk;
+        }
+    }
+}
+
+// Columns [SL j, SL j + SL) of a hidden layer's output gradient: g = bf16((G Wt^T) * gelu'(z)),
+// G [NB][K] (stride ldg), Wt the transposed weights of the layer above (rows = this
+// layer's columns, stride K).  Written transposed into gt [SL][GTS] (LDS) and, when
+// grow is set, row-major into grow [NB][H].  The product is formed first; the
+// barrier before the writes lets gt share memory with an operand.
+template <int K>
+__device__ __forceinline__ void bwd_slice(const uint16_t *G, int ldg, const uint16_t *Wt, const float *dprev, int j,
+                                          uint16_t *grow, uint16_t *gt) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m0 = 32 * wave;
+    float dp[2][2][4];   // gelu'(z) of this lane's outputs, loaded with the operands
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int col = 16 * j + (lane & 15);
-                const int row0 = m0 + 16 * i + 4 * (lane >> 4);
+            for (int q = 0; q < 4; ++q)
+                dp[jj][i][q] = dprev[(m0 + 16 * i + 4 * (lane >> 4) + q) * H + SL * j + 16 * jj + (lane & 15)];
+    f32x4 acc[2][2];
+    zero_acc(acc);
+    wave_mma<2, 2, K, true>(G + m0 * ldg, ldg, Wt + SL * j * K, K, acc);
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+        const int cl = 16 * jj + (lane & 15);
+        const int col = SL * j + cl;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row0 = m0 + 16 * i + 4 * (lane >> 4);
+            uint16_t h[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                h[q] = to_bf16(acc[i][jj][q] * dp[jj][i][q]);
+                if (grow) grow[(row0 + q) * H + col] = h[q];
+            }
+            uint2 pk;
+            pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+            pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+            *reinterpret_cast<uint2 *>(gt + cl * GTS + row0) = pk;
+        }
+    }
+}
+
+// The parameters of a lane in the weight-row update of a 256-wide hidden layer
+// (wgrad_rows): lane l of wave w holds o = SL j + 16 i + 4 (l >> 4) + q,
+// in = 32 w + 16 jj + (l & 15), entry (2 i + jj) 4 + q.  Their master values and
+// Adam moments (or accumulated gradients) are loaded once, at the start of the
+// kernel, so the update does not wait for memory.
+struct RowState {
+    float w[16], m[16], v[16];
+};
+
+__device__ __forceinline__ int row_param(int off_w, int j, int k) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = k >> 3, jj = (k >> 2) & 1, q = k & 3;
+    return off_w + (SL * j + 16 * i + 4 * (lane >> 4) + q) * H + 32 * wave + 16 * jj + (lane & 15);
+}
+
+__device__ __forceinline__ RowState load_row_state(const TrainArgs &A, const MemberW &M, int off_w, int j) {
+    RowState st;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int off = row_param(off_w, j, k);
+        if (A.grad != nullptr) {
+            st.w[k] = A.grad[off];
+            st.m[k] = st.v[k] = 0.f;
+        } else {
+            st.w[k] = M.w[off];
+            st.m[k] = M.m[off];
+            st.v[k] = M.v[off];
+        }
+    }
+    return st;
+}
+
+// Weight rows [SL j, SL j + SL) of a 256-wide hidden layer (offset off_w, bias
+// off_b): dW[o][i] = sum_r gt[o][r] At[i][r] with gt this workgroup's gradient
+// columns (LDS, [SL][GTS]) and At the transposed input activations [H][NB]; then
+// the bias rows.  Adam mode writes the new bfloat16 copies into nb (rows) and nt
+// (transposed).
+__device__ __forceinline__ void wgrad_rows(const TrainArgs &A, const MemberW &M, const AdamC &c, RowState &st,
+                                           const uint16_t *gt, const uint16_t *At, int j, int off_w, int off_b,
+                                           uint16_t *nb, uint16_t *nt) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n0 = 32 * wave;
+    f32x4 acc[2][2];
+    zero_acc(acc);
+    wave_mma<2, 2, NB, true>(gt, GTS, At + n0 * NB, NB, acc);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const int in = n0 + 16 * jj + (lane & 15);
+            const int o0 = SL * j + 16 * i + 4 * (lane >> 4);
+            uint16_t h[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = (2 * i + jj) * 4 + q;
+                const int off = off_w + (o0 + q) * H + in;
+                if (A.grad != nullptr) {
+                    A.grad[off] = st.w[k] + acc[i][jj][q];
+                } else {
+                    adam_update(st.w[k], st.m[k], st.v[k], acc[i][jj][q], c);
+                    M.w[off] = st.w[k];
+                    M.m[off] = st.m[k];
+                    M.v[off] = st.v[k];
+                    h[q] = to_bf16(st.w[k]);
+                    nb[(o0 + q) * H + in] = h[q];
+                }
+            }
+            if (A.grad == nullptr) {
+                uint2 pk;
+                pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+                pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+                *reinterpret_cast<uint2 *>(nt + in * H + o0) = pk;
+            }
+        }
+    if (threadIdx.x < SL) apply_grad1(A, M, off_b + SL * j + threadIdx.x, row_sum(gt + threadIdx.x * GTS), c);
+}
+
+// Layer 1 of a step for columns [SL j, SL j + SL): gathers the step's rows
+// (src, LDS) into LDS (xs [NB][X1S]) and forms a, a^T, gelu'(z) with the weight
+// rows w1rows ([SL][FP], global or LDS).
+__device__ __forceinline__ void forward_first(const TrainArgs &A, const int *src, const uint16_t *w1rows,
+                                              const float *b1, int j, unsigned char *sb, uint16_t *xs) {
+    for (int e = threadIdx.x; e < NB * FP / 8; e += TRAIN_THREADS) {
+        const int r = e / (FP / 8), k8 = (e % (FP / 8)) * 8;
+        const int sr = src[r];
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (sr >= 0) v = *reinterpret_cast<const uint4 *>(A.xn + (long long)sr * FP + k8);
+        *reinterpret_cast<uint4 *>(xs + r * X1S + k8) = v;
+    }
+    __syncthreads();
+    fwd_slice<FP>(xs, X1S, w1rows, b1, j, S_A(0), S_AT(0), S_D(0));
+}
+
+// Step counters and loss accumulators of a launch sequence start at zero (a
+// kernel, not a memset, so the sequence may be captured).
+__global__ __launch_bounds__(256) void train_init_kernel(unsigned char *scratch, int members) {
+    int *ctr = reinterpret_cast<int *>(scratch);
+    if (threadIdx.x < 5) ctr[threadIdx.x] = 0;
+    for (int m = threadIdx.x; m < members; m += blockDim.x)
+        *reinterpret_cast<double *>(scratch + TS_CTRL + (size_t)m * MEMBER_SCRATCH + MS_LOSS) = 0.0;
+}
+
+// Layer 1 of the first step of a sequence (and its rows, for the step's kernels).
+__global__ __launch_bounds__(TRAIN_THREADS) void train_f1_kernel(TrainArgs A) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs[NB * X1S];
+    __shared__ int src[NB];
+    const int j = blockIdx.x, mem = A.member + (int)blockIdx.y;
+    const MemberW M = member_weights(A.W, mem);
+    unsigned char *sb = member_scratch(A);
+    const StepPos c = step_pos(A, 0);
+    step_rows(A, mem, c, sb, src);
+    if (j == 0 && threadIdx.x < NB) reinterpret_cast<int *>(sb + MS_SRC)[threadIdx.x] = src[threadIdx.x];
+    forward_first(A, src, M.w1b + SL * j * FP, M.w + OFF_B1, j, sb, xs);
+}
+
+// Hidden layer L (2 or 3) of a step.
+template <int L>
+__global__ __launch_bounds__(TRAIN_THREADS) void train_fwd_kernel(TrainArgs A) {
+    const long long g = take_step(A, L == 2 ? K_F2 : K_F3);
+    const int j = blockIdx.x, mem = A.member + (int)blockIdx.y;
+    const MemberW M = member_weights(A.W, mem);
+    const BfView B = bf_view(A.W, mem, A.grad != nullptr ? 0 : (int)(g & 1));
+    unsigned char *sb = member_scratch(A);
+    fwd_slice<H>(S_A(L - 2), H, (L == 2 ? B.w2b : B.w3b) + SL * j * H, M.w + (L == 2 ? OFF_B2 : OFF_B3), j,
+                 S_A(L - 1), S_AT(L - 1), S_D(L - 1));
+}
+
+// Output layer, loss, output-layer weight columns, layer-3 gradient and weight rows.
+__global__ __launch_bounds__(TRAIN_THREADS) void train_b3_kernel(TrainArgs A) {
+    __shared__ __attribute__((aligned(16))) uint16_t g4[NB * G4S];    // [NB][G4S] output gradient
+    __shared__ __attribute__((aligned(16))) uint16_t g4t[OP * GTS];   // [OP][GTS]; then layer-3 gradient [SL][GTS]
+    __shared__ double s_loss;
+    const long long g = take_step(A, K_B3);
+    const int j = blockIdx.x, mem = A.member + (int)blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const MemberW M = member_weights(A.W, mem);
+    const bool upd = A.grad == nullptr;
+    const int set = upd ? (int)(g & 1) : 0;
+    const BfView B = bf_view(A.W, mem, set), N = bf_view(A.W, mem, set ^ 1);
+    unsigned char *sb = member_scratch(A);
+    RowState st = load_row_state(A, M, OFF_W3, j);
+    const StepPos c = step_pos(A, g);
+    const AdamC ac = adam_constants(A, c);
+    const int *srcs = reinterpret_cast<const int *>(sb + MS_SRC) + (g & 1) * NB;
+    if (tid == 0) s_loss = 0.0;
+    __syncthreads();
+    // ---- output layer over all rows (every workgroup), loss, output gradient
+    {
+        const int m0 = 32 * wave;
+        const float scale = 2.0f / (float)((upd ? (double)c.nbe : (double)A.n) * NO);
+        f32x4 acc[2][4];
+        zero_acc(acc);
+        wave_mma<2, 4, H, true>(S_A(2) + m0 * H, H, B.w4b, H, acc);
+        double ls = 0.0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row0 = m0 + 16 * i + 4 * (lane >> 4);
+            int src[4];
+            float t[4][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) src[q] = srcs[row0 + q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int col = 16 * jj + (lane & 15);
+                    t[q][jj] = (col < NO && src[q] >= 0) ? A.tn[(long long)src[q] * NO + col] : 0.f;
+                }
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int col = 16 * jj + (lane & 15);
                 uint16_t h[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    float g = 0.f;
-                    if (col < NO && row0 + q < nbe) {
-                        const float y = acc[i][j][q] + M.w[OFF_B4 + col];
-                        const float diff = y - S_TB[(row0 + q) * NO + col];
+                    float gv = 0.f;
+                    if (col < NO && src[q] >= 0) {
+                        const float y = acc[i][jj][q] + M.w[OFF_B4 + col];
+                        const float diff = y - t[q][jj];
                         ls += (double)diff * (double)diff;
-                        g = diff * scale;
+                        gv = diff * scale;
                     }
-                    h[q] = to_bf16(g);
-                    S_G4[(row0 + q) * OP + col] = h[q];
+                    h[q] = to_bf16(gv);
+                    g4[(row0 + q) * G4S + col] = h[q];
                 }
                 uint2 pk;
                 pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
                 pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-                *reinterpret_cast<uint2 *>(S_G4T + col * NB + row0) = pk;
+                *reinterpret_cast<uint2 *>(g4t + col * GTS + row0) = pk;
             }
+        }
         for (int off = 32; off > 0; off >>= 1) ls += __shfl_xor(ls, off);
-        if (lane == 0) atomicAdd(s_loss, ls);
+        if (lane == 0) atomicAdd(&s_loss, ls);
     }
     __syncthreads();
-    // ---- backward
-    AdamC c;
-    {
-        const long long t = A.step0 + gstep + 1;
-        const double frac = total > 1 ? (double)gstep / (double)(total - 1) : 1.0;
-        const double lr = A.lr1 + 0.5 * (A.lr0 - A.lr1) * (1.0 + cos(3.14159265358979323846 * frac));
-        c.lr = (float)lr;
-        c.b1 = A.beta1;
-        c.b2 = A.beta2;
-        c.eps = A.eps;
-        c.bc1 = (float)(1.0 - pow((double)A.beta1, (double)t));
-        c.bc2 = (float)(1.0 - pow((double)A.beta2, (double)t));
+    if (j == 0) {
+        if (tid < NO) S_B4G[tid] = row_sum(g4t + tid * GTS);   // applied by the next kernel
+        if (tid == 0) {
+            double *acc_loss = S_LOSS;
+            const double L = *acc_loss + s_loss;
+            const bool epoch_end = c.st == c.steps - 1;
+            if (upd && epoch_end) {
+                if (A.loss_hist != nullptr) A.loss_hist[(size_t)blockIdx.y * A.epochs + c.ep] = (float)(L / ((double)A.n * NO));
+                if (A.loss_out != nullptr && blockIdx.y == 0 && c.g == c.total - 1) *A.loss_out = L / ((double)A.n * NO);
+                *acc_loss = 0.0;
+            } else {
+                *acc_loss = L;
+                if (!upd && c.g == c.total - 1 && A.loss_out != nullptr) *A.loss_out = L / ((double)A.n * NO);
+            }
+        }
     }
-    bwd_data<OP>(S_G4, M.w4t, S_D(2), S_G(2), S_GT(2));
+    // ---- output-layer weight columns [SL j, SL j + SL): dW4[o][i] = sum_r g4t[o][r] A3t[i][r],
+    // one 16 x 16 tile per wave (three output tiles, two column tiles)
+    if (wave < 6) {
+        const int ot = wave % 3, it = wave / 3;
+        f32x4 acc[1][1];
+        zero_acc(acc);
+        wave_mma<1, 1, NB, true>(g4t + 16 * ot * GTS, GTS, S_AT(2) + (SL * j + 16 * it) * NB, NB, acc);
+        const int in = SL * j + 16 * it + (lane & 15);
+        int off[4];
+        float gv[4], w[4];
+        bool on[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = 16 * ot + 4 * (lane >> 4) + q;
+            on[q] = o < NO;
+            off[q] = OFF_W4 + min(o, NO - 1) * H + in;
+            gv[q] = acc[0][0][q];
+        }
+        apply_grads<4>(A, M, off, gv, on, ac, w);
+        if (upd) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int o = 16 * ot + 4 * (lane >> 4) + q;
+                if (o >= NO) continue;
+                const uint16_t h = to_bf16(w[q]);
+                N.w4b[o * H + in] = h;
+                N.w4t[in * OP + o] = h;
+            }
+        }
+    }
+    // ---- layer-3 gradient columns (into g4t's memory after the barrier inside)
+    bwd_slice<OP>(g4, G4S, B.w4t, S_D(2), j, S_G(0), g4t);
     __syncthreads();
-    wgrad_out(M, A.grad, S_G4T, S_AT(2), c);
-    if (tid < NO) bias_grad(M, A.grad, S_G4T + tid * NB, OFF_B4 + tid, c);
-    bwd_data<H>(S_G(2), M.w3t, S_D(1), S_G(1), S_GT(1));
-    __syncthreads();
-    wgrad_hidden(M, A.grad, S_GT(2), S_AT(1), OFF_W3, M.w3b, M.w3t, c);
-    if (tid < H) bias_grad(M, A.grad, S_GT(2) + tid * NB, OFF_B3 + tid, c);
-    bwd_data<H>(S_G(1), M.w2t, S_D(0), nullptr, S_GT(0));
-    __syncthreads();
-    wgrad_hidden(M, A.grad, S_GT(1), S_AT(0), OFF_W2, M.w2b, M.w2t, c);
-    wgrad_first(M, A.grad, S_GT(0), S_XBT, c);
-    if (tid < H) bias_grad(M, A.grad, S_GT(1) + tid * NB, OFF_B2 + tid, c);
-    else bias_grad(M, A.grad, S_GT(0) + (tid - H) * NB, OFF_B1 + (tid - H), c);
-    __syncthreads();
+    wgrad_rows(A, M, ac, st, g4t, S_AT(1), j, OFF_W3, OFF_B3, N.w3b, N.w3t);
 }
 
-__global__ __launch_bounds__(TRAIN_THREADS) void train_kernel(TrainArgs A) {
-    const int mem = A.grad != nullptr ? A.member : A.member + (int)blockIdx.x;
+// Output bias, layer-2 gradient and weight rows.
+__global__ __launch_bounds__(TRAIN_THREADS) void train_b2_kernel(TrainArgs A) {
+    __shared__ __attribute__((aligned(16))) uint16_t gt[SL * GTS];
+    const long long g = take_step(A, K_B2);
+    const int j = blockIdx.x, mem = A.member + (int)blockIdx.y;
     const MemberW M = member_weights(A.W, mem);
-    unsigned char *sb = A.scratch + (A.grad != nullptr ? 0 : (size_t)blockIdx.x * SCRATCH_BYTES);
-    const int tid = threadIdx.x;
-    __shared__ double s_loss;
-    __shared__ long long s_pa, s_pb;
-    const long long n = A.n;
-    const long long steps = (n + A.nb - 1) / A.nb;
-    const long long total = steps * (long long)A.epochs;
-    long long gstep = 0;
-    if (tid == 0) s_loss = 0.0;
-    for (int ep = 0; ep < A.epochs; ++ep) {
-        if (tid == 0) {
-            if (A.grad != nullptr || n == 1) {
-                s_pa = 1;
-                s_pb = 0;
-            } else {
-                const uint64_t key = (A.seed << 32) + ((uint64_t)mem << 20) + (uint64_t)(A.epoch0 + ep);
-                long long a = 1 + (long long)(splitmix(key) % (uint64_t)(n - 1));
-                while (gcd_ll(a, n) != 1) a = a % (n - 1) + 1;      // ends: a = 1 is coprime
-                s_pa = a;
-                s_pb = (long long)(splitmix(key ^ 0x5DEECE66Dull) % (uint64_t)n);
-            }
-            if (A.grad == nullptr) s_loss = 0.0;
-        }
-        __syncthreads();
-        const long long pa = s_pa, pb = s_pb;
-        for (long long st = 0; st < steps; ++st, ++gstep) {
-            train_step(A, M, sb, st, total, gstep, pa, pb, &s_loss);
-        }
-        if (tid == 0 && A.loss_hist != nullptr && A.grad == nullptr)
-            A.loss_hist[(size_t)(mem - A.member) * A.epochs + ep] = (float)(s_loss / ((double)n * NO));
+    const bool upd = A.grad == nullptr;
+    const int set = upd ? (int)(g & 1) : 0;
+    const BfView B = bf_view(A.W, mem, set), N = bf_view(A.W, mem, set ^ 1);
+    unsigned char *sb = member_scratch(A);
+    RowState st = load_row_state(A, M, OFF_W2, j);
+    const StepPos c = step_pos(A, g);
+    const AdamC ac = adam_constants(A, c);
+    if (j == 0 && threadIdx.x < NO) apply_grad1(A, M, OFF_B4 + threadIdx.x, S_B4G[threadIdx.x], ac);
+    bwd_slice<H>(S_G(0), H, B.w3t, S_D(1), j, S_G(1), gt);
+    __syncthreads();
+    wgrad_rows(A, M, ac, st, gt, S_AT(0), j, OFF_W2, OFF_B2, N.w2b, N.w2t);
+}
+
+// Layer-1 gradient and weight rows, then layer 1 of the next step.
+__global__ __launch_bounds__(TRAIN_THREADS) void train_b1_kernel(TrainArgs A) {
+    __shared__ __attribute__((aligned(16))) uint16_t gt[SL * GTS];
+    __shared__ __attribute__((aligned(16))) uint16_t xt[FP * GTS];  // this step's features, transposed
+    __shared__ __attribute__((aligned(16))) uint16_t xs[NB * X1S];  // the next step's features
+    __shared__ __attribute__((aligned(16))) uint16_t w1s[SL * FP];  // the updated weight rows
+    __shared__ int src[NB];
+    const long long g = take_step(A, K_B1);
+    const int j = blockIdx.x, mem = A.member + (int)blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const MemberW M = member_weights(A.W, mem);
+    const bool upd = A.grad == nullptr;
+    const int set = upd ? (int)(g & 1) : 0;
+    const BfView B = bf_view(A.W, mem, set), N = bf_view(A.W, mem, set ^ 1);
+    unsigned char *sb = member_scratch(A);
+    const StepPos c = step_pos(A, g);
+    const AdamC ac = adam_constants(A, c);
+    const int *srcs = reinterpret_cast<const int *>(sb + MS_SRC) + (g & 1) * NB;
+    for (int e = tid; e < NB * FP / 8; e += TRAIN_THREADS) {
+        const int r = e / (FP / 8), k8 = (e % (FP / 8)) * 8;
+        const int sr = srcs[r];
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (sr >= 0) v = *reinterpret_cast<const uint4 *>(A.xn + (long long)sr * FP + k8);
+        const uint16_t *h = reinterpret_cast<const uint16_t *>(&v);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) xt[(k8 + k) * GTS + r] = h[k];
     }
-    if (tid == 0 && A.loss_out != nullptr) *A.loss_out = s_loss / ((double)n * NO);
+    for (int e = tid; e < SL * FP; e += TRAIN_THREADS) w1s[e] = B.w1b[SL * j * FP + e];
+    bwd_slice<H>(S_G(1), H, B.w2t, S_D(0), j, nullptr, gt);
+    __syncthreads();
+    // ---- weight rows of layer 1: dW1[o][k] = sum_r gt[o][r] xt[k][r], k < NF
+    if (wave < 2) {
+        f32x4 acc[1][1];
+        zero_acc(acc);
+        wave_mma<1, 1, NB, true>(gt + 16 * wave * GTS, GTS, xt, GTS, acc);
+        const int k = lane & 15;
+        int off[4];
+        float gv[4], w[4];
+        bool on[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = SL * j + 16 * wave + 4 * (lane >> 4) + q;
+            on[q] = k < NF;
+            off[q] = OFF_W1 + o * NF + min(k, NF - 1);
+            gv[q] = acc[0][0][q];
+        }
+        apply_grads<4>(A, M, off, gv, on, ac, w);
+        if (upd && k < NF) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ol = 16 * wave + 4 * (lane >> 4) + q;
+                const uint16_t h = to_bf16(w[q]);
+                N.w1b[(SL * j + ol) * FP + k] = h;
+                w1s[ol * FP + k] = h;
+            }
+        }
+    }
+    if (tid < SL) apply_grad1(A, M, OFF_B1 + SL * j + tid, row_sum(gt + tid * GTS), ac);
+    if (g + 1 >= c.total) return;
+    // ---- layer 1 of the next step (step_rows begins with a barrier)
+    const StepPos cn = step_pos(A, g + 1);
+    step_rows(A, mem, cn, sb, src);
+    if (j == 0 && tid < NB) reinterpret_cast<int *>(sb + MS_SRC)[((g + 1) & 1) * NB + tid] = src[tid];
+    forward_first(A, src, w1s, M.w + OFF_B1, j, sb, xs);
 }
 
 // ------------------------------------------------------------------ inference
@@ -904,9 +1159,43 @@ hipError_t launch_prepare(const double *params, const double *C, const double *K
     return hipGetLastError();
 }
 
-hipError_t launch_train(const TrainArgs &a, int blocks, hipStream_t s) {
-    train_kernel<<<blocks, TRAIN_THREADS, 0, s>>>(a);
+static hipError_t enqueue_train_steps(const TrainArgs &a, dim3 grid, long long steps, hipStream_t s) {
+    for (long long i = 0; i < steps; ++i) {
+        train_fwd_kernel<2><<<grid, TRAIN_THREADS, 0, s>>>(a);
+        train_fwd_kernel<3><<<grid, TRAIN_THREADS, 0, s>>>(a);
+        train_b3_kernel<<<grid, TRAIN_THREADS, 0, s>>>(a);
+        train_b2_kernel<<<grid, TRAIN_THREADS, 0, s>>>(a);
+        train_b1_kernel<<<grid, TRAIN_THREADS, 0, s>>>(a);
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_train(const TrainArgs &a, int members, hipStream_t s, hipStream_t cap) {
+    const dim3 grid(NSL, members);
+    const long long total = (a.n + a.nb - 1) / a.nb * (long long)a.epochs;
+    train_init_kernel<<<1, 256, 0, s>>>(a.scratch, members);
+    train_f1_kernel<<<grid, TRAIN_THREADS, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    constexpr long long G = 64;   // steps per captured graph
+    long long done = 0;
+    if (cap != nullptr && total >= 2 * G) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        const hipError_t le = enqueue_train_steps(a, grid, G, cap);
+        e = hipStreamEndCapture(cap, &graph);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        for (; e == hipSuccess && done + G <= total; done += G) e = hipGraphLaunch(exec, s);
+        const hipError_t se = hipStreamSynchronize(s);   // the graph is destroyed below
+        if (exec != nullptr) (void)hipGraphExecDestroy(exec);
+        if (graph != nullptr) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        if (se != hipSuccess) return se;
+    }
+    return enqueue_train_steps(a, grid, total - done, s);
 }
 
 hipError_t launch_predict(const PredictArgs &a, hipStream_t s) {

@@ -21,7 +21,7 @@ struct chom_mlp {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     DevBuf<float> master, adam_m, adam_v, grad, loss_hist;
-    DevBuf<uint16_t> w1b, w2b, w3b, w4b, w2t, w3t, w4t;
+    DevBuf<uint16_t> w1b, w2b, w3b, w4b, w2t, w3t, w4t, alt;
     DevBuf<double> norm, loss;
     bool has_norm = false;
     long long step = 0;           // Adam steps taken (shared by the members)
@@ -33,7 +33,9 @@ struct chom_mlp {
     DevBuf<double> out_c, out_k, out_d, out_dis;   // device results when the caller's are on the host
     DevBuf<double> fb_p, fb_c, fb_k, fb_d;         // compact fallback records / results
     DevBuf<int> flag, idx, count;
+    hipStream_t capture = nullptr;   // training graphs are captured here
     ~chom_mlp() {
+        if (capture) (void)hipStreamDestroy(capture);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
     M_::Weights weights() const {
@@ -48,6 +50,7 @@ struct chom_mlp {
         W.w2t = w2t.p;
         W.w3t = w3t.p;
         W.w4t = w4t.p;
+        W.alt = alt.p;
         return W;
     }
 };
@@ -178,7 +181,7 @@ int mlp_loss_grad_ws(chom_mlp *m, int member, const double *p, const double *c, 
     a.loss_out = loss;
     a.W = m->weights();
     a.scratch = tr;
-    CHOM_HIP(M_::launch_train(a, 1, m->stream));
+    CHOM_HIP(M_::launch_train(a, 1, m->stream, nullptr));
     int bad = 0;
     CHOM_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, m->stream));
     CHOM_HIP(hipStreamSynchronize(m->stream));
@@ -260,7 +263,7 @@ int chom_mlp_create(const chom_mlp_options *opt_in, chom_mlp **out) {
     CHOM_HIP(m->w4t.ensure(M * M_::H * M_::OP));
     CHOM_HIP(m->norm.ensure(M_::NORM_LEN));
     CHOM_HIP(m->loss.ensure(1));
-    CHOM_HIP(m->scratch.ensure(M * (size_t)M_::SCRATCH_BYTES));
+    CHOM_HIP(m->scratch.ensure((size_t)M_::train_scratch_bytes(M)));
     CHOM_HIP(hipMemsetAsync(m->adam_m.p, 0, sizeof(float) * M * P, m->stream));
     CHOM_HIP(hipMemsetAsync(m->adam_v.p, 0, sizeof(float) * M * P, m->stream));
     std::vector<float> w;
@@ -360,6 +363,11 @@ int chom_mlp_train(chom_mlp *m, const chom_params *params, const double *C, cons
     CHOM_TRY(stage_in(m, m->in_d, D, (size_t)n * 6, &d));
     CHOM_TRY(prepare_rows(m, p, c, k, d, n, o.refit_normalisation != 0 || !m->has_norm, "chom_mlp_train"));
     CHOM_HIP(m->loss_hist.ensure((size_t)m->members * o.epochs));
+    // second set of bfloat16 copies (steps alternate between the sets); the
+    // padding rows and columns, which no step writes, stay zero
+    CHOM_HIP(m->alt.ensure((size_t)m->members * M_::BF_PER_MEMBER));
+    CHOM_HIP(hipMemsetAsync(m->alt.p, 0, sizeof(uint16_t) * m->alt.n, m->stream));
+    if (m->capture == nullptr) CHOM_HIP(hipStreamCreateWithFlags(&m->capture, hipStreamNonBlocking));
     M_::TrainArgs a;
     std::memset(&a, 0, sizeof(a));
     a.xn = m->xn.p;
@@ -381,7 +389,8 @@ int chom_mlp_train(chom_mlp *m, const chom_params *params, const double *C, cons
     a.loss_out = m->loss.p;
     a.W = m->weights();
     a.scratch = m->scratch.p;
-    CHOM_HIP(M_::launch_train(a, m->members, m->stream));
+    CHOM_HIP(M_::launch_train(a, m->members, m->stream, m->capture));
+    CHOM_TRY(sync_copies(m));   // the last step's copies may be in the second set
     CHOM_HIP(hipStreamSynchronize(m->stream));
     m->step += ((n + o.batch - 1) / o.batch) * (long long)o.epochs;
     m->epochs_done += o.epochs;
@@ -426,7 +435,7 @@ int chom_mlp_loss_grad(chom_mlp *m, int32_t member, const chom_params *params, c
     a.loss_out = m->loss.p;
     a.W = m->weights();
     a.scratch = m->scratch.p;
-    CHOM_HIP(M_::launch_train(a, 1, m->stream));
+    CHOM_HIP(M_::launch_train(a, 1, m->stream, nullptr));
     CHOM_HIP(hipMemcpyAsync(grad, m->grad.p, sizeof(float) * M_::NPARAM, hipMemcpyDeviceToHost, m->stream));
     CHOM_HIP(hipMemcpyAsync(loss, m->loss.p, sizeof(double), hipMemcpyDeviceToHost, m->stream));
     CHOM_HIP(hipStreamSynchronize(m->stream));
