@@ -208,25 +208,80 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *__restrict__ 
     }
 }
 
+// Sum of the tile-box copies of lattice point (X, Y, Z) for load cases c0 ..
+// c0 + KG - 1, which lie in one operator group (boxes [tile][group][case in
+// group][box point][C], rg cases per group, ng groups), in the vector precision.
+// Every copy of every case is loaded before any is summed.
+template <typename T, int C, int KG>
+__device__ inline void gather_tiles_grp(const Geo &G, const T *qt, int ng, int rg, int c0, int X, int Y, int Z,
+                                        T out[KG][C]) {
+    const int grp = c0 / rg, rr0 = c0 - grp * rg;
+    const bool per = (G.bc == 1);
+    const int m2 = G.L;
+    int tx[2], ty[2], tz[2], lx[2], ly[2], lz[2];
+    const int nx = tile_cands(X, G.p * G.tcx, G.tiles_x, m2, per, tx, lx);
+    const int ny = tile_cands(Y, G.p * G.tcy, G.tiles_y, m2, per, ty, ly);
+    const int nz = tile_cands(Z, G.p * G.tcz, G.tiles_z, m2, per, tz, lz);
+    T cp[8][KG][C];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+            for (int v = 0; v < C; ++v) cp[k][kk][v] = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (a < nx && b < ny && c < nz) {
+                    // 32-bit: one problem's tile boxes hold fewer than 2^31 values (checked at setup)
+                    const int tile = tx[a] + G.tiles_x * (ty[b] + G.tiles_y * tz[c]);
+                    const int off = (((tile * ng + grp) * rg + rr0) * G.boxpts + lx[a] + G.bx * (ly[b] + G.by * lz[c])) * C;
+#pragma unroll
+                    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+                        for (int v = 0; v < C; ++v) cp[4 * a + 2 * b + c][kk][v] = qt[off + kk * G.boxpts * C + v];
+                }
+            }
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+        for (int v = 0; v < C; ++v) {
+            T sum = T(0);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sum += cp[k][kk][v];
+            out[kk][v] = sum;
+        }
+}
+
 // r -= alpha q (q gathered from the operator's tile boxes) ; partial sums of r
 // and z0 = M^-1 r (z0 itself is formed again by the direction kernel, which
 // reads r anyway; x += alpha p is deferred to the next direction kernel).
-template <typename T, int C, int R, int NR>
-__global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *__restrict__ geos, const Prob *__restrict__ probs, int rg, T *r,
-                                                           const T *q, const T *minv,
-                                                           const ColState *cols, double *accbuf,
-                                                           const int *prob_active) {
+// Wave g takes load cases KG g .. KG g + KG - 1 (KG divides the operator's
+// load cases per group, rg), so a point's lattice position, tile-box addresses,
+// inverse block and constraint rows are found once for all of them.
+template <typename T, int C, int R, int NR, int KG>
+__global__ __launch_bounds__(64 * (R / KG)) void cg_update_kernel(const Geo *__restrict__ geos,
+                                                                  const Prob *__restrict__ probs, int rg, T *r,
+                                                                  const T *q, const T *minv, const ColState *cols,
+                                                                  double *accbuf, const int *prob_active) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int REC = 2 + C * NR;
     const int prob = blockIdx.y;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double acc[REC];
+    const int grp = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double acc[KG][REC];
 #pragma unroll
-    for (int k = 0; k < REC; ++k) acc[k] = 0.0;
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+        for (int k = 0; k < REC; ++k) acc[kk][k] = 0.0;
     if (prob_active[prob] == 0) return;
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
-    const T al = (T)cols[prob * R + w].alpha;
+    T al[KG];
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) al[kk] = (T)cols[prob * R + grp * KG + kk].alpha;
     const T *Mp = minv + P.doff * MS;
     const T *qt = q + P.qoff;
     const long long nblk = (G.npts + 63) / 64;
@@ -234,38 +289,46 @@ __global__ __launch_bounds__(64 * R) void cg_update_kernel(const Geo *__restrict
         const long long pt = blk * 64 + lane;
         if (pt >= G.npts) continue;
         // the point's own loads first, then the gather: all in flight together
-        const long long o = P.voff + (w * G.npts + pt) * C;
-        T Mi[MS], rv[C], zv[C];
+        T Mi[MS], rv[KG][C], qv[KG][C];
 #pragma unroll
         for (int k = 0; k < MS; ++k) Mi[k] = Mp[pt * MS + k];
 #pragma unroll
-        for (int c = 0; c < C; ++c) rv[c] = r[o + c];
+        for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+            for (int c = 0; c < C; ++c) rv[kk][c] = r[P.voff + ((grp * KG + kk) * G.npts + pt) * C + c];
         double row[4];
         load_rows<NR>(G, pt, row);
         int X, Y, Z;
         lattice_xyz(G, pt, X, Y, Z);
-        double qv[C];
         if (dirichlet_boundary(G, X, Y, Z)) {
 #pragma unroll
-            for (int c = 0; c < C; ++c) qv[c] = 0.0;
+            for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+                for (int c = 0; c < C; ++c) qv[kk][c] = T(0);
         } else {
-            gather_tiles_col<T, C, R>(G, qt, rg, X, Y, Z, w, qv);
+            gather_tiles_grp<T, C, KG>(G, qt, R / rg, rg, grp * KG, X, Y, Z, qv);
         }
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            rv[c] = rv[c] - al * (T)qv[c];
-            r[o + c] = rv[c];
-        }
-        minv_apply<T, C>(Mi, rv, zv);
+        for (int kk = 0; kk < KG; ++kk) {
+            const long long o = P.voff + ((grp * KG + kk) * G.npts + pt) * C;
+            T zv[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            acc[0] += (double)rv[c] * (double)zv[c];
-            acc[1] += (double)rv[c] * (double)rv[c];
+            for (int c = 0; c < C; ++c) {
+                rv[kk][c] = rv[kk][c] - al[kk] * qv[kk][c];
+                r[o + c] = rv[kk][c];
+            }
+            minv_apply<T, C>(Mi, rv[kk], zv);
 #pragma unroll
-            for (int a = 0; a < NR; ++a) acc[2 + c * NR + a] += row[a] * (double)zv[c];
+            for (int c = 0; c < C; ++c) {
+                acc[kk][0] += (double)rv[kk][c] * (double)zv[c];
+                acc[kk][1] += (double)rv[kk][c] * (double)rv[kk][c];
+#pragma unroll
+                for (int a = 0; a < NR; ++a) acc[kk][2 + c * NR + a] += row[a] * (double)zv[c];
+            }
         }
     }
-    wave_accum<C, REC>(acc, accbuf, prob, R, w);
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) wave_accum<C, REC>(acc[kk], accbuf, prob, R, grp * KG + kk);
 }
 
 // x += alpha p with the pending step length of each column (after the last CG
@@ -532,7 +595,20 @@ hipError_t launch_cg_update(const Launch &L, T *r, const T *q, const void *minv,
                             double *accbuf, const int *prob_active, hipStream_t s) {
     dim3 grid(L.nwg, L.nprob);
     const T *M = (const T *)minv;
-    CHOM_NR_DISPATCH(L.nr, (cg_update_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, L.rg, r, q, M, cols, accbuf, prob_active)));
+    // each wave takes KG load cases of one operator group: KG = 3 or 2 when it
+    // divides the group size L.rg, else 1
+    if (L.rg % 3 == 0 && R % 3 == 0) {
+        constexpr int KG = R % 3 == 0 ? 3 : 1;
+        CHOM_NR_DISPATCH(L.nr, (cg_update_kernel<T, C, R, NR, KG><<<grid, 64 * (R / KG), 0, s>>>(
+                                   L.geos, L.probs, L.rg, r, q, M, cols, accbuf, prob_active)));
+    } else if (L.rg % 2 == 0 && R % 2 == 0) {
+        constexpr int KG = R % 2 == 0 ? 2 : 1;
+        CHOM_NR_DISPATCH(L.nr, (cg_update_kernel<T, C, R, NR, KG><<<grid, 64 * (R / KG), 0, s>>>(
+                                   L.geos, L.probs, L.rg, r, q, M, cols, accbuf, prob_active)));
+    } else {
+        CHOM_NR_DISPATCH(L.nr, (cg_update_kernel<T, C, R, NR, 1><<<grid, 64 * R, 0, s>>>(
+                                   L.geos, L.probs, L.rg, r, q, M, cols, accbuf, prob_active)));
+    }
     return hipGetLastError();
 }
 
