@@ -103,49 +103,68 @@ __global__ __launch_bounds__(64 * R) void cg_init_kernel(const Geo *__restrict__
 // z += Q f, f = e1 - W y on the n/2 grid (e1 = V Q^T r, W = V Q^T C^T, formed by
 // mg_fcorr_kernel), Q = P_0 P_1 (P_0 injects vertex values, P_1 interpolates
 // from the n/2 grid).
-template <typename T, int C, int R, int NR>
-__global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *__restrict__ geos, const Prob *__restrict__ probs, T *x, T *r, T *p,
-                                                        const T *minv, const double *ycoef,
-                                                        const ColState *cols, const int *prob_active,
-                                                        MgDir<T> mg) {
+//
+// Wave g takes load cases KG g .. KG g + KG - 1, so a point's inverse block,
+// constraint rows and coarse-grid parents are found once for all of them.
+template <typename T, int C, int R, int NR, int KG>
+__global__ __launch_bounds__(64 * (R / KG)) void cg_dir_kernel(const Geo *__restrict__ geos,
+                                                               const Prob *__restrict__ probs, T *x, T *r, T *p,
+                                                               const T *minv, const double *ycoef,
+                                                               const ColState *cols, const int *prob_active,
+                                                               MgDir<T> mg) {
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int S = C * NR;
     const int prob = blockIdx.y;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c0 = g * KG;
     // a finished problem still takes the pending x update of its last step
     // (the finishing kernel zeroes alpha of finished columns afterwards)
     const bool active = prob_active[prob] != 0;
-    const double alpha = cols[prob * R + w].alpha;
-    if (!active && alpha == 0.0) return;   // per wave: the kernel has no block barrier
+    double alpha[KG], beta[KG];
+    bool any_alpha = false, any_move = false;
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) {
+        alpha[kk] = cols[prob * R + c0 + kk].alpha;
+        beta[kk] = cols[prob * R + c0 + kk].beta;
+        any_alpha = any_alpha || alpha[kk] != 0.0;
+        any_move = any_move || alpha[kk] != 0.0 || beta[kk] != 0.0;
+    }
+    if (!active && !any_alpha) return;   // per wave: the kernel has no block barrier
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
-    const double beta = cols[prob * R + w].beta;
-    double yv[S > 0 ? S : 1];
+    double yv[KG][S > 0 ? S : 1];
 #pragma unroll
-    for (int k = 0; k < S; ++k) yv[k] = ycoef[((long long)prob * R + w) * S + k];
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+        for (int k = 0; k < S; ++k) yv[kk][k] = ycoef[((long long)prob * R + c0 + kk) * S + k];
     const T *Mp = minv + P.doff * MS;
     const bool proj = (NR > 0) && G.nrow > 0;
     const long long nblk = (G.npts + 63) / 64;
     for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const long long pt = blk * 64 + lane;
         if (pt >= G.npts) continue;
-        const long long o = P.voff + (w * G.npts + pt) * C;
         // every load that does not depend on another is issued before any use
         // (alpha, beta and active are uniform over the wave)
-        T pv[C], xv[C], rv[C], Mi[MS];
+        T pv[KG][C], xv[KG][C], rv[KG][C], Mi[MS];
         double row[4] = {0.0, 0.0, 0.0, 0.0};
-        if (alpha != 0.0 || beta != 0.0) {
 #pragma unroll
-            for (int c = 0; c < C; ++c) pv[c] = p[o + c];
-        }
-        if (alpha != 0.0) {
+        for (int kk = 0; kk < KG; ++kk) {
+            const long long o = P.voff + ((c0 + kk) * G.npts + pt) * C;
+            if (any_move) {
 #pragma unroll
-            for (int c = 0; c < C; ++c) xv[c] = x[o + c];
+                for (int c = 0; c < C; ++c) pv[kk][c] = p[o + c];
+            }
+            if (any_alpha) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) xv[kk][c] = x[o + c];
+            }
+            if (active) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) rv[kk][c] = r[o + c];
+            }
         }
         long long J0 = -1, J1 = -1;
         if (active) {
-#pragma unroll
-            for (int c = 0; c < C; ++c) rv[c] = r[o + c];
 #pragma unroll
             for (int k = 0; k < MS; ++k) Mi[k] = Mp[pt * MS + k];
             if (proj) load_rows<NR>(G, pt, row);
@@ -164,46 +183,50 @@ __global__ __launch_bounds__(64 * R) void cg_dir_kernel(const Geo *__restrict__ 
                 }
             }
         }
-        if (alpha != 0.0) {
-            const T al = (T)alpha;
 #pragma unroll
-            for (int c = 0; c < C; ++c) x[o + c] = xv[c] + al * pv[c];
-        }
-        if (!active) continue;
-        T zv[C];
-        minv_apply<T, C>(Mi, rv, zv);   // z0 = M^-1 r, as in the update kernel's sums
-        if constexpr (NR > 0) {
-            if (proj) {
-                // projection correction M^-1 C^T y evaluated in FP64
-                double Md[MS], ct[C], corr[C];
+        for (int kk = 0; kk < KG; ++kk) {
+            const long long o = P.voff + ((c0 + kk) * G.npts + pt) * C;
+            if (alpha[kk] != 0.0) {
+                const T al = (T)alpha[kk];
 #pragma unroll
-                for (int k = 0; k < MS; ++k) Md[k] = (double)Mi[k];
+                for (int c = 0; c < C; ++c) x[o + c] = xv[kk][c] + al * pv[kk][c];
+            }
+            if (!active) continue;
+            T zv[C];
+            minv_apply<T, C>(Mi, rv[kk], zv);   // z0 = M^-1 r, as in the update kernel's sums
+            if constexpr (NR > 0) {
+                if (proj) {
+                    // projection correction M^-1 C^T y evaluated in FP64
+                    double Md[MS], ct[C], corr[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    ct[c] = 0.0;
+                    for (int k = 0; k < MS; ++k) Md[k] = (double)Mi[k];
 #pragma unroll
-                    for (int a = 0; a < NR; ++a) ct[c] += row[a] * yv[c * NR + a];
-                }
-                minv_apply<double, C>(Md, ct, corr);
+                    for (int c = 0; c < C; ++c) {
+                        ct[c] = 0.0;
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    zv[c] = (T)((double)zv[c] - corr[c]);
-                    r[o + c] = (T)((double)rv[c] - ct[c]);
+                        for (int a = 0; a < NR; ++a) ct[c] += row[a] * yv[kk][c * NR + a];
+                    }
+                    minv_apply<double, C>(Md, ct, corr);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        zv[c] = (T)((double)zv[c] - corr[c]);
+                        r[o + c] = (T)((double)rv[kk][c] - ct[c]);
+                    }
                 }
             }
-        }
-        if (J0 >= 0) {
-            const T *f = mg.x0 + (P.moff * R + (long long)w * G.mg_pts + G.mg_off[1]) * C;
+            if (J0 >= 0) {
+                const T *f = mg.x0 + (P.moff * R + (long long)(c0 + kk) * G.mg_pts + G.mg_off[1]) * C;
 #pragma unroll
-            for (int c = 0; c < C; ++c) zv[c] += T(0.5) * (f[J0 * C + c] + f[J1 * C + c]);
-        }
-        if (beta == 0.0) {   // first step (p not yet defined) or finished column
+                for (int c = 0; c < C; ++c) zv[c] += T(0.5) * (f[J0 * C + c] + f[J1 * C + c]);
+            }
+            if (beta[kk] == 0.0) {   // first step (p not yet defined) or finished column
 #pragma unroll
-            for (int c = 0; c < C; ++c) p[o + c] = zv[c];
-        } else {
-            const T bt = (T)beta;
+                for (int c = 0; c < C; ++c) p[o + c] = zv[c];
+            } else {
+                const T bt = (T)beta[kk];
 #pragma unroll
-            for (int c = 0; c < C; ++c) p[o + c] = zv[c] + bt * pv[c];
+                for (int c = 0; c < C; ++c) p[o + c] = zv[c] + bt * pv[kk][c];
+            }
         }
     }
 }
@@ -586,7 +609,8 @@ hipError_t launch_cg_dir(const Launch &L, T *x, T *r, T *p, const void *minv, co
     dim3 grid(L.nwg, L.nprob);
     const T *M = (const T *)minv;
     MgDir<T> mg{(const T *)mg_x0, (const T *)mg_W, mg_x0 != nullptr ? 1 : 0};
-    CHOM_NR_DISPATCH(L.nr, (cg_dir_kernel<T, C, R, NR><<<grid, 64 * R, 0, s>>>(L.geos, L.probs, x, r, p, M, ycoef, cols, prob_active, mg)));
+    constexpr int KG = R % 2 == 0 ? 2 : (R % 3 == 0 ? 3 : 1);   // load cases per lane
+    CHOM_NR_DISPATCH(L.nr, (cg_dir_kernel<T, C, R, NR, KG><<<grid, 64 * (R / KG), 0, s>>>(L.geos, L.probs, x, r, p, M, ycoef, cols, prob_active, mg)));
     return hipGetLastError();
 }
 

@@ -61,7 +61,11 @@ def test_compaction_keeps_results_and_iterations(precision, chains):
     assert all(r["status"] == 0 for r in ra + rb)
     assert e <= 1e-10
     # the FP64 sums are atomic, so their order (and a column sitting at the
-    # threshold) can move a stop by a step or two between any two runs; the
-    # refined form adds such moves over its FP32 passes
+    # threshold) can move a stop by a step or two between any two runs; in the
+    # refined form an FP32 pass that reaches its attainable accuracy near the
+    # inner tolerance can run ~4% longer or shorter from such a difference
+    # (measured: 522, 523, 524 and 542 steps for the 12^3 periodic item in four
+    # runs, two of them uncompacted, all within 1.4e-16 of each other)
+    slack = 0.03 if precision == "fp64" else 0.06
     for x, y in zip(its_a, its_b):
-        assert max(abs(u - v) for u, v in zip(x, y)) <= 3 + 0.03 * max(y)
+        assert max(abs(u - v) for u, v in zip(x, y)) <= 3 + slack * max(y)
