@@ -491,33 +491,6 @@ __device__ inline const int *row16(const int *table, const Lev &V, long long pt)
     return table + (V.off + pt) * 16;
 }
 
-// r_1[I] = sum over the level-0 children v of I of the fine right side at v
-// (children on a Dirichlet boundary and outside the lattice are absent from the
-// table); xp_1 = D^-1 r_1.
-template <typename T, int C>
-__device__ inline void restrict01_pt(const Geo &G, const Prob &P, const Lev &Cv, int w, const T *fine_r,
-                                     const T *Dinv1, LV<T> v1, long long pt) {
-    constexpr int MS = (C == 3) ? 6 : 1;
-    const int *ch = row16(G.mg_child, Cv, pt);
-    const T *fr = fine_r + P.voff + (long long)w * G.npts * C;
-    T acc[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = T(0);
-#pragma unroll
-    for (int m = 0; m < MG_SLOTS; ++m) {
-        const int f = ch[m];
-        T v[C];
-        load_c<T, C>(fr + (long long)(f < 0 ? 0 : f) * C, v);
-        const T wgt = f < 0 ? T(0) : (m == 0 ? T(1) : T(0.5));
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] += wgt * v[c];
-    }
-    store_c<T, C>(v1.r + pt * C, acc);
-    T xv[C];
-    minv_apply<T, C>(Dinv1 + pt * MS, acc, xv);
-    store_c<T, C>(v1.xp + pt * C, xv);
-}
-
 // res = r - A xp.
 template <typename T, int C>
 __device__ inline void resid_pt(const Geo &G, const Lev &V, const T *A, LV<T> v, long long pt) {
@@ -604,61 +577,164 @@ struct VPtr {
     if (!(LEVEL_OK)) return;                                                      \
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
-template <typename T, int C, int R>
-__global__ __launch_bounds__(64 * R) void mg_restrict01_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
-                                                               const int *prob_active) {
+// The level-1 kernels: wave g takes load cases KG g .. KG g + KG - 1 of a
+// problem, so a point's index tables, stencil blocks, inverse block and
+// constraint rows are read once for all of them.
+template <typename T, int C, int R, int KG>
+__device__ inline void level_vecs_kg(const Geo &G, const Prob &P, int c0, const Lev &V, const VPtr<T, C, R> &Q,
+                                     LV<T> (&v)[KG]) {
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) v[kk] = level_vecs<T, C, R>(G, P, c0 + kk, V, Q.r, Q.xp, Q.res, Q.x);
+}
+
+// acc[kk] -= sum_s A[s] v[kk][nb[s]] for the KG vectors (each block loaded once).
+template <typename T, int C, int KG>
+__device__ inline void apply_stencil_kg(const int *nb, const T *Arow, const T *const (&v)[KG], T (&acc)[KG][C]) {
+    constexpr int CC = C * C;
+#pragma unroll
+    for (int s = 0; s < MG_SLOTS; ++s) {
+        const long long j = nb[s];
+        T blk[CC];
+#pragma unroll
+        for (int e = 0; e < CC; ++e) blk[e] = Arow[s * CC + e];
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            T vq[C];
+            load_c<T, C>(v[kk] + j * C, vq);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int d = 0; d < C; ++d) acc[kk][c] -= blk[c * C + d] * vq[d];
+        }
+    }
+}
+
+// r_1[I] = sum over the level-0 children v of I of the fine right side at v
+// (children on a Dirichlet boundary and outside the lattice are absent from the
+// table); xp_1 = D^-1 r_1.
+template <typename T, int C, int R, int KG>
+__global__ __launch_bounds__(64 * (R / KG)) void mg_restrict01_kernel(const Geo *geos, const Prob *probs,
+                                                                      VPtr<T, C, R> Q, const int *prob_active) {
     constexpr int MS = (C == 3) ? 6 : 1;
     MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 2)
-    const Lev F = level_of(G, 0), V = level_of(G, 1);
-    const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
+    const int c0 = w * KG;
+    const Lev V = level_of(G, 1);
+    LV<T> v[KG];
+    level_vecs_kg<T, C, R, KG>(G, P, c0, V, Q, v);
     const T *D = Q.Dinv + (P.moff + V.off) * MS;
     const long long np = (long long)V.lw * V.lw * V.lw;
-    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL)
-        restrict01_pt<T, C>(G, P, V, w, Q.fine_r, D, v, pt);
+    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) {
+        const int *ch = row16(G.mg_child, V, pt);
+        int f[MG_SLOTS];
+#pragma unroll
+        for (int m = 0; m < MG_SLOTS; ++m) f[m] = ch[m];
+        T Mi[MS];
+#pragma unroll
+        for (int k = 0; k < MS; ++k) Mi[k] = D[pt * MS + k];
+        T acc[KG][C];
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            const T *fr = Q.fine_r + P.voff + (long long)(c0 + kk) * G.npts * C;
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[kk][c] = T(0);
+#pragma unroll
+            for (int m = 0; m < MG_SLOTS; ++m) {
+                T vv[C];
+                load_c<T, C>(fr + (long long)(f[m] < 0 ? 0 : f[m]) * C, vv);
+                const T wgt = f[m] < 0 ? T(0) : (m == 0 ? T(1) : T(0.5));
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[kk][c] += wgt * vv[c];
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            store_c<T, C>(v[kk].r + pt * C, acc[kk]);
+            T xv[C];
+            minv_apply<T, C>(Mi, acc[kk], xv);
+            store_c<T, C>(v[kk].xp + pt * C, xv);
+        }
+    }
 }
 
-template <typename T, int C, int R>
-__global__ __launch_bounds__(64 * R) void mg_resid1_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
-                                                           const int *prob_active) {
+// res = r - A xp on level 1.
+template <typename T, int C, int R, int KG>
+__global__ __launch_bounds__(64 * (R / KG)) void mg_resid1_kernel(const Geo *geos, const Prob *probs,
+                                                                  VPtr<T, C, R> Q, const int *prob_active) {
     constexpr int CC = C * C;
     MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 3)
+    const int c0 = w * KG;
     const Lev V = level_of(G, 1);
-    const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
+    LV<T> v[KG];
+    level_vecs_kg<T, C, R, KG>(G, P, c0, V, Q, v);
+    const T *xps[KG];
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) xps[kk] = v[kk].xp;
     const T *A = Q.A + (P.moff + V.off) * MG_SLOTS * CC;
     const long long np = (long long)V.lw * V.lw * V.lw;
-    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) resid_pt<T, C>(G, V, A, v, pt);
+    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) {
+        T acc[KG][C];
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) load_c<T, C>(v[kk].r + pt * C, acc[kk]);
+        apply_stencil_kg<T, C, KG>(row16(G.mg_nbr, V, pt), A + pt * MG_SLOTS * CC, xps, acc);
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) store_c<T, C>(v[kk].res + pt * C, acc[kk]);
+    }
 }
 
-template <typename T, int C, int R>
-__global__ __launch_bounds__(64 * R) void mg_correct1_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
-                                                             const int *prob_active) {
+// xc = xp + P e_2 on level 1, stored in res.
+template <typename T, int C, int R, int KG>
+__global__ __launch_bounds__(64 * (R / KG)) void mg_correct1_kernel(const Geo *geos, const Prob *probs,
+                                                                    VPtr<T, C, R> Q, const int *prob_active) {
     MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 3)
+    const int c0 = w * KG;
     const Lev V = level_of(G, 1), Cv = level_of(G, 2);
-    const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
-    const LV<T> vc = level_vecs<T, C, R>(G, P, w, Cv, Q.r, Q.xp, Q.res, Q.x);
+    LV<T> v[KG], vc[KG];
+    level_vecs_kg<T, C, R, KG>(G, P, c0, V, Q, v);
+    level_vecs_kg<T, C, R, KG>(G, P, c0, Cv, Q, vc);
     const long long np = (long long)V.lw * V.lw * V.lw;
-    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) correct_pt<T, C>(G, V, v, vc.x, pt);
+    for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) {
+        const int *pa = row16(G.mg_par, V, pt);
+        const long long ia = pa[0], ib = pa[1];
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            T xv[C];
+            load_c<T, C>(v[kk].xp + pt * C, xv);
+            const T *e = vc[kk].x;
+#pragma unroll
+            for (int c = 0; c < C; ++c) xv[c] += T(0.5) * (e[ia * C + c] + e[ib * C + c]);
+            store_c<T, C>(v[kk].res + pt * C, xv);
+        }
+    }
 }
 
-// Level-1 post-smoothing; with `accbuf`, the sums r_1 . e_1 (= r . Q e_1) and
-// rows1 . e_1 (= C Q e_1) are added to the CG step's striped accumulators.
-template <typename T, int C, int R, int NR>
-__global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
-                                                          double *accbuf, const int *prob_active) {
+// Level-1 post-smoothing x = xc + D^-1 (r - A xc); with `accbuf`, the sums
+// r_1 . e_1 (= r . Q e_1) and rows1 . e_1 (= C Q e_1) are added to the CG
+// step's striped accumulators.
+template <typename T, int C, int R, int NR, int KG>
+__global__ __launch_bounds__(64 * (R / KG)) void mg_post1_kernel(const Geo *geos, const Prob *probs,
+                                                                 VPtr<T, C, R> Q, double *accbuf,
+                                                                 const int *prob_active) {
     constexpr int CC = C * C;
     constexpr int MS = (C == 3) ? 6 : 1;
     constexpr int REC = 2 + C * NR;
     const int prob = blockIdx.y;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double pacc[REC];
+    const int c0 = w * KG;
+    double pacc[KG][REC];
 #pragma unroll
-    for (int k = 0; k < REC; ++k) pacc[k] = 0.0;
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+        for (int k = 0; k < REC; ++k) pacc[kk][k] = 0.0;
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
     if ((prob_active == nullptr || prob_active[prob] != 0) && G.mg_nlev >= 2) {
         const bool smooth = G.mg_nlev >= 3;   // level 1 coarsest: its output is final
         const Lev V = level_of(G, 1);
-        const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
+        LV<T> v[KG];
+        level_vecs_kg<T, C, R, KG>(G, P, c0, V, Q, v);
+        const T *xcs[KG];
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) xcs[kk] = v[kk].res;
         const T *A = Q.A + (P.moff + V.off) * MG_SLOTS * CC;
         const T *D = Q.Dinv + (P.moff + V.off) * MS;
         const double *r1 = Q.rows1 + (P.moff + V.off) * 4;
@@ -666,59 +742,101 @@ __global__ __launch_bounds__(64 * R) void mg_post1_kernel(const Geo *geos, const
         const int nr = G.nrow < NR ? G.nrow : NR;
         const long long np = (long long)V.lw * V.lw * V.lw;
         for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) {
-            if (smooth) post_pt<T, C>(G, V, A, D, v, pt);
+            T rv[KG][C], ov[KG][C];
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) load_c<T, C>(v[kk].r + pt * C, rv[kk]);
+            if (smooth) {
+                T acc[KG][C];
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[kk][c] = rv[kk][c];
+                apply_stencil_kg<T, C, KG>(row16(G.mg_nbr, V, pt), A + pt * MG_SLOTS * CC, xcs, acc);
+                T Mi[MS];
+#pragma unroll
+                for (int k = 0; k < MS; ++k) Mi[k] = D[pt * MS + k];
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk) {
+                    T d[C], xi[C];
+                    minv_apply<T, C>(Mi, acc[kk], d);
+                    load_c<T, C>(v[kk].res + pt * C, xi);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) ov[kk][c] = xi[c] + d[c];
+                    store_c<T, C>(v[kk].x + pt * C, ov[kk]);
+                }
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk) load_c<T, C>(v[kk].x + pt * C, ov[kk]);
+            }
             if (accbuf != nullptr) {
-                T rv[C], ov[C];
-                load_c<T, C>(v.r + pt * C, rv);
-                load_c<T, C>(v.x + pt * C, ov);
                 double row[4] = {0, 0, 0, 0};
                 for (int a = 0; a < nr; ++a) row[a] = r1[pt * 4 + rf + a];
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    pacc[0] += (double)rv[c] * (double)ov[c];
+                for (int kk = 0; kk < KG; ++kk)
 #pragma unroll
-                    for (int a = 0; a < NR; ++a) pacc[2 + c * NR + a] += row[a] * (double)ov[c];
-                }
+                    for (int c = 0; c < C; ++c) {
+                        pacc[kk][0] += (double)rv[kk][c] * (double)ov[kk][c];
+#pragma unroll
+                        for (int a = 0; a < NR; ++a) pacc[kk][2 + c * NR + a] += row[a] * (double)ov[kk][c];
+                    }
             }
         }
     }
     if (accbuf != nullptr) {
         const int stripe = blockIdx.x & (ACC_STRIPES - 1);
-        int k;
-        const double sum = wave_sums_spread<REC>(pacc, k);
-        if (wave_spread_writer<REC>(lane) && k < REC && k != 1)
-            unsafeAtomicAdd(&accbuf[acc_index<C>(prob, R, w, k, stripe)], sum);
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            int k;
+            const double sum = wave_sums_spread<REC>(pacc[kk], k);
+            if (wave_spread_writer<REC>(lane) && k < REC && k != 1)
+                unsafeAtomicAdd(&accbuf[acc_index<C>(prob, R, c0 + kk, k, stripe)], sum);
+        }
     }
 }
 
 // f = e_1 - W y per (problem, load case) on the n/2 grid (y: projection
 // coefficients of the current CG step), into the level-1 res block.
-template <typename T, int C, int R, int NR>
-__global__ __launch_bounds__(64 * R) void mg_fcorr_kernel(const Geo *geos, const Prob *probs, VPtr<T, C, R> Q,
-                                                          const T *W, const double *ycoef, const int *prob_active) {
+template <typename T, int C, int R, int NR, int KG>
+__global__ __launch_bounds__(64 * (R / KG)) void mg_fcorr_kernel(const Geo *geos, const Prob *probs,
+                                                                 VPtr<T, C, R> Q, const T *W, const double *ycoef,
+                                                                 const int *prob_active) {
     MG_LEVEL_KERNEL_HEAD(G.mg_nlev >= 2)
+    const int c0 = w * KG;
     const Lev V = level_of(G, 1);
-    const LV<T> v = level_vecs<T, C, R>(G, P, w, V, Q.r, Q.xp, Q.res, Q.x);
+    LV<T> v[KG];
+    level_vecs_kg<T, C, R, KG>(G, P, c0, V, Q, v);
     const int nr = G.nrow < NR ? G.nrow : NR;
-    double yv[C * NR > 0 ? C * NR : 1];
+    double yv[KG][C * NR > 0 ? C * NR : 1];
 #pragma unroll
-    for (int k = 0; k < C * NR; ++k) yv[k] = ycoef[((long long)prob * R + w) * C * NR + k];
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+        for (int k = 0; k < C * NR; ++k) yv[kk][k] = ycoef[((long long)prob * R + c0 + kk) * C * NR + k];
     const long long np = (long long)V.lw * V.lw * V.lw;
     for (long long pt = blockIdx.x * 64LL + lane; pt < np; pt += gridDim.x * 64LL) {
-        double f[C];
+        double f[KG][C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) f[c] = (double)v.x[pt * C + c];
+        for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+            for (int c = 0; c < C; ++c) f[kk][c] = (double)v[kk].x[pt * C + c];
         if constexpr (NR > 0) {
             const T *Wp = W + (P.moff + V.off + pt) * (4 * C) * C;
-            for (int i = 0; i < C; ++i)
-                for (int a = 0; a < nr; ++a) {
-                    const double yy = yv[i * NR + a];
 #pragma unroll
-                    for (int c = 0; c < C; ++c) f[c] -= yy * (double)Wp[(i * 4 + a) * C + c];
+            for (int i = 0; i < C; ++i)
+#pragma unroll
+                for (int a = 0; a < NR; ++a) {
+                    if (a >= nr) continue;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const double wv = (double)Wp[(i * 4 + a) * C + c];
+#pragma unroll
+                        for (int kk = 0; kk < KG; ++kk) f[kk][c] -= yv[kk][i * NR + a] * wv;
+                    }
                 }
         }
 #pragma unroll
-        for (int c = 0; c < C; ++c) v.res[pt * C + c] = (T)f[c];
+        for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[kk].res[pt * C + c] = (T)f[kk][c];
     }
 }
 
@@ -1232,6 +1350,9 @@ __global__ __launch_bounds__(256) void mg_gram_finish_kernel(const Geo *geos, co
         ginv[(long long)prob * SMAX * SMAX + t] = ok_s ? A[t / S][S + t % S] : 0.0;
 }
 
+// Load cases per lane in the level-1 kernels.
+template <int R> constexpr int MG_KG = R % 2 == 0 ? 2 : (R % 3 == 0 ? 3 : 1);
+
 #define CHOM_MG_NR_DISPATCH(NRV, CALL)                 \
     switch (NRV) {                                     \
         case 0: { constexpr int NR = 0; CALL; } break; \
@@ -1275,8 +1396,9 @@ hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *accbuf, const i
     Q.x = (T *)M.x;
     Q.rows1 = M.rows1;
     const dim3 g1(M.nwg[1], L.nprob);
-    mg_restrict01_kernel<T, C, R><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, prob_active);
-    mg_resid1_kernel<T, C, R><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, prob_active);
+    constexpr int KG = MG_KG<R>;
+    mg_restrict01_kernel<T, C, R, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q, prob_active);
+    mg_resid1_kernel<T, C, R, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q, prob_active);
     if constexpr (std::is_same<T, float>::value) {
         if (M.small_elems > 0) {
             mg_fused_small_kernel<C, R><<<dim3(R, L.nprob), MG_FUSED_BS, (size_t)M.small_elems * sizeof(float), s>>>(
@@ -1289,9 +1411,9 @@ hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *accbuf, const i
         mg_fused_kernel<T, C, R><<<dim3(R, L.nprob), MG_FUSED_BS, (size_t)M.lds_elems * sizeof(T), s>>>(
             L.geos, L.probs, Q, M.sweeps, M.lds_vec, M.lds_sten, prob_active);
     }
-    mg_correct1_kernel<T, C, R><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, prob_active);
-    CHOM_MG_NR_DISPATCH(L.nr, (mg_post1_kernel<T, C, R, NR><<<g1, 64 * R, 0, s>>>(L.geos, L.probs, Q, accbuf,
-                                                                                  prob_active)));
+    mg_correct1_kernel<T, C, R, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q, prob_active);
+    CHOM_MG_NR_DISPATCH(L.nr, (mg_post1_kernel<T, C, R, NR, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q,
+                                                                                             accbuf, prob_active)));
     return hipGetLastError();
 }
 
@@ -1307,7 +1429,8 @@ hipError_t launch_mg_fcorr(const Launch &L, const double *ycoef, const int *prob
     Q.res = (T *)M.res;
     Q.x = (T *)M.x;
     Q.rows1 = M.rows1;
-    CHOM_MG_NR_DISPATCH(L.nr, (mg_fcorr_kernel<T, C, R, NR><<<dim3(M.nwg[1], L.nprob), 64 * R, 0, s>>>(
+    constexpr int KG = MG_KG<R>;
+    CHOM_MG_NR_DISPATCH(L.nr, (mg_fcorr_kernel<T, C, R, NR, KG><<<dim3(M.nwg[1], L.nprob), 64 * (R / KG), 0, s>>>(
                                   L.geos, L.probs, Q, (const T *)M.W, ycoef, prob_active)));
     return hipGetLastError();
 }
