@@ -98,7 +98,14 @@ struct TrainArgs {
     unsigned char *scratch;      // train_scratch_bytes(members)
 };
 
+// Inference GELU table: the standard normal distribution function Phi on
+// GELU_TAB_N equal intervals of [-GELU_TAB_Z, GELU_TAB_Z], as (Phi(z_i),
+// Phi(z_{i+1}) - Phi(z_i)) pairs.
+constexpr int GELU_TAB_N = 4096;
+constexpr float GELU_TAB_Z = 8.0f;
+
 struct PredictArgs {
+    const float2 *gelu_tab;      // GELU_TAB_N entries (launch_gelu_table)
     const double *params;        // [n][11]
     long long n;
     double c_sat;
@@ -120,6 +127,7 @@ hipError_t launch_prepare(const double *params, const double *C, const double *K
 // that it then replays on s (null: the kernels are launched one by one).
 hipError_t launch_train(const TrainArgs &a, int members, hipStream_t s, hipStream_t cap);
 hipError_t launch_predict(const PredictArgs &a, hipStream_t s);
+hipError_t launch_gelu_table(float2 *tab, hipStream_t s);
 hipError_t launch_select(const double *dis, long long n, double thresh, int *idx, int *count, unsigned char *flag,
                          hipStream_t s);
 hipError_t launch_gather(const double *params, const int *idx, int m, double *out, hipStream_t s);

@@ -944,9 +944,33 @@ constexpr int XS = FP + 8;      // LDS row strides (bfloat16 elements), padded a
 constexpr int HS = H + 8;
 constexpr int PTILES = PT / 16;
 
+// GELU of the inference epilogue: z Phi(z) with Phi linearly interpolated in
+// the LDS table (interval 16/4096: interpolation error below 5e-7 in Phi, far
+// under the bfloat16 rounding the activation takes next; Phi = 0 below -8 and
+// 1 above 8 to the same accuracy).  A table lookup and two FMAs replace the
+// quarter-rate exponential and reciprocal of the closed form, which made the
+// epilogue, not the matrix cores, the bound of the inference kernel.
+__device__ __forceinline__ float gelu_lut(float z, const float2 *tab) {
+    constexpr float scale = GELU_TAB_N / (2.0f * GELU_TAB_Z);
+    const float u = fminf(fmaxf(fmaf(z, scale, GELU_TAB_Z * scale), 0.0f), (float)GELU_TAB_N - 0.5f);
+    const int i = (int)u;
+    const float2 e = tab[i];
+    return z * fmaf(u - (float)i, e.y, e.x);
+}
+
+// Phi(z_i) and its increment on each table interval, from the FP64 erfc.
+__global__ void gelu_table_kernel(float2 *tab) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= GELU_TAB_N) return;
+    const double h = 2.0 * (double)GELU_TAB_Z / GELU_TAB_N;
+    const double z0 = -(double)GELU_TAB_Z + h * i, z1 = z0 + h;
+    const double p0 = 0.5 * erfc(-z0 * 0.70710678118654752440), p1 = 0.5 * erfc(-z1 * 0.70710678118654752440);
+    tab[i] = make_float2((float)p0, (float)(p1 - p0));
+}
+
 template <int K>
 __device__ __forceinline__ void infer_hidden(const uint16_t *A, int lda, const uint16_t *Wb, const float *bias,
-                                             uint16_t *out) {
+                                             const float2 *tab, uint16_t *out) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n0 = 64 * wave;
     f32x4 acc[PTILES][4];
@@ -961,7 +985,7 @@ __device__ __forceinline__ void infer_hidden(const uint16_t *A, int lda, const u
         for (int i = 0; i < PTILES; ++i) {
             const int row0 = 16 * i + 4 * (lane >> 4);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) out[(row0 + q) * HS + col] = to_bf16_hw(gelu(acc[i][j][q] + b));
+            for (int q = 0; q < 4; ++q) out[(row0 + q) * HS + col] = to_bf16_hw(gelu_lut(acc[i][j][q] + b, tab));
         }
     }
 }
@@ -970,6 +994,8 @@ __global__ __launch_bounds__(256) void predict_kernel(PredictArgs P) {
     __shared__ __attribute__((aligned(16))) uint16_t xs[PT * XS];
     __shared__ __attribute__((aligned(16))) uint16_t hb[PT * HS];
     __shared__ float s_ymu[NO], s_ysd[NO];
+    __shared__ float2 tab[GELU_TAB_N];
+    for (int e = threadIdx.x; e < GELU_TAB_N; e += blockDim.x) tab[e] = P.gelu_tab[e];
     static_assert(2 * PT * NO * sizeof(float) <= PT * HS * sizeof(uint16_t), "statistics reuse the activations");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long p0 = (long long)blockIdx.x * PT;
@@ -1004,11 +1030,11 @@ __global__ __launch_bounds__(256) void predict_kernel(PredictArgs P) {
 #pragma unroll 1
     for (int mem = 0; mem < P.members; ++mem) {
         const MemberW M = member_weights(P.W, mem);
-        infer_hidden<FP>(xs, XS, M.w1b, M.w + OFF_B1, hb);
+        infer_hidden<FP>(xs, XS, M.w1b, M.w + OFF_B1, tab, hb);
         __syncthreads();
-        infer_hidden<H>(hb, HS, M.w2b, M.w + OFF_B2, hb);
+        infer_hidden<H>(hb, HS, M.w2b, M.w + OFF_B2, tab, hb);
         __syncthreads();
-        infer_hidden<H>(hb, HS, M.w3b, M.w + OFF_B3, hb);
+        infer_hidden<H>(hb, HS, M.w3b, M.w + OFF_B3, tab, hb);
         __syncthreads();
         {
             f32x4 acc[OT][3];
@@ -1201,6 +1227,11 @@ hipError_t launch_train(const TrainArgs &a, int members, hipStream_t s, hipStrea
 hipError_t launch_predict(const PredictArgs &a, hipStream_t s) {
     const long long blocks = (a.n + PT - 1) / PT;
     predict_kernel<<<(unsigned)blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gelu_table(float2 *tab, hipStream_t s) {
+    gelu_table_kernel<<<(GELU_TAB_N + 255) / 256, 256, 0, s>>>(tab);
     return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ struct chom_mlp {
     DevBuf<double> out_c, out_k, out_d, out_dis;   // device results when the caller's are on the host
     DevBuf<double> fb_p, fb_c, fb_k, fb_d;         // compact fallback records / results
     DevBuf<int> flag, idx, count;
+    DevBuf<float2> gelu_tab;       // inference GELU table (filled at creation)
     hipStream_t capture = nullptr;   // training graphs are captured here
     ~chom_mlp() {
         if (capture) (void)hipStreamDestroy(capture);
@@ -128,6 +129,7 @@ int predict_device(chom_mlp *m, const double *p, long long n, double *C, double 
     CHOM_HIP(m->flag.ensure(1));
     CHOM_HIP(hipMemsetAsync(m->flag.p, 0, sizeof(int), m->stream));
     M_::PredictArgs a;
+    a.gelu_tab = m->gelu_tab.p;
     a.params = p;
     a.n = n;
     a.c_sat = m->opt.c_sat;
@@ -261,6 +263,7 @@ int chom_mlp_create(const chom_mlp_options *opt_in, chom_mlp **out) {
     CHOM_HIP(m->w2t.ensure(M * M_::H * M_::H));
     CHOM_HIP(m->w3t.ensure(M * M_::H * M_::H));
     CHOM_HIP(m->w4t.ensure(M * M_::H * M_::OP));
+    CHOM_HIP(m->gelu_tab.ensure(M_::GELU_TAB_N));
     CHOM_HIP(m->norm.ensure(M_::NORM_LEN));
     CHOM_HIP(m->loss.ensure(1));
     CHOM_HIP(m->scratch.ensure((size_t)M_::train_scratch_bytes(M)));
@@ -274,6 +277,7 @@ int chom_mlp_create(const chom_mlp_options *opt_in, chom_mlp **out) {
         CHOM_HIP(hipStreamSynchronize(m->stream));
     }
     CHOM_TRY(sync_copies(m.get()));
+    CHOM_HIP(M_::launch_gelu_table(m->gelu_tab.p, m->stream));
     CHOM_HIP(hipStreamSynchronize(m->stream));
     *out = m.release();
     return CHOM_OK;
