@@ -693,7 +693,10 @@ def main():
                     help="stopping tolerance of each load case (relative to its own energy, in the metric of "
                          "the preconditioner); the errors against the FP64 path and the oracle are measured "
                          "and reported each run")
-    ap.add_argument("--inner-rtol", type=float, default=3e-5, help="FP32 inner solve tolerance per refinement pass")
+    ap.add_argument("--inner-rtol", type=float, default=2e-5,
+                    help="FP32 inner solve tolerance per refinement pass (2/3 of rtol: an inner pass that stops "
+                         "exactly at rtol misses the FP64 check by a hair on about 30%% of the mixed batch's "
+                         "items and pays a restarted second pass)")
     ap.add_argument("--train", type=int, default=20000, help="surrogate: training solves")
     ap.add_argument("--epochs", type=int, default=300, help="surrogate: training epochs")
     ap.add_argument("--points", type=int, default=1_000_000, help="surrogate: evaluation points")

@@ -2,7 +2,7 @@
 
 The benchmark runs the FP32 operator with FP64 refinement, the two-level
 preconditioner (in FP32 the small-grid coarse-level kernel), stopping tolerances
-rtol = inner_rtol = 3e-5 with the energy form of the averages, and launch shapes
+rtol = 3e-5 and inner_rtol = 2e-5 with the energy form of the averages, and launch shapes
 picked by the autotuner.  The same configuration is compared with the oracle:
 
 * n = 8 (hierarchy 8 -> 4, a level-1 coarsest grid), linear Dirichlet, periodic
@@ -33,7 +33,7 @@ pytestmark = pytest.mark.gpu
 
 BCS = ["dirichlet", "periodic", "neumann"]
 BC_ID = {"dirichlet": ofem.BC_DIRICHLET, "periodic": ofem.BC_PERIODIC, "neumann": ofem.BC_NEUMANN}
-BENCH = dict(precision="fp32_refined", precond="two_level", rtol=3e-5, inner_rtol=3e-5, max_iter=50000)
+BENCH = dict(precision="fp32_refined", precond="two_level", rtol=3e-5, inner_rtol=2e-5, max_iter=50000)
 FP64 = dict(precision="fp64", precond="two_level", rtol=1e-12, max_iter=50000)
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "surrogate_heldout_n12_periodic.txt")
 _CACHE = {}
