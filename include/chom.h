@@ -237,6 +237,64 @@ int chom_damage_history(int64_t n, int32_t m, const double *T_celsius, const dou
                         const double *keep0, const double *factors, double c_sat, int32_t device_ptrs,
                         void *hip_stream, double *keep, chom_params *params_out);
 
+/* Fully nested multi-scale run (FE^2, paper Sec. 3 and Sec. 5): a synthetic
+ * macro box [0, lx] x [0, ly] x [0, lz] on an nx x ny x nz Kuhn lattice of
+ * linear (P1) tets, one Gauss point (its centroid) per tet.  Per time step:
+ *  - macro heat and moisture transport (Eq. Eq_field, discretised as in
+ *    Eq. Eq_field_disc: capacity (consistent P1 mass) and conductivity
+ *    matrices, implicit Euler in time): heat_capacity * dT/dt = div(K_T grad T),
+ *    dc/dt = div(D_c grad c), with K_T, D_c the RVE's homogenised conductivity
+ *    and diffusivity of the undegraded record (homogenised once: they do not
+ *    depend on the damage), T = T_top and c = c_top on the face z = lz, no flux
+ *    elsewhere, T = T0 and c = c0 at t = 0; time in years, lengths in the units
+ *    the homogenised coefficients are taken in (a synthetic setting: the paper's
+ *    macro geometry and loads are not specified);
+ *  - at every Gauss point the damage of the matrix by the rate form of Sec. 4
+ *    (Eq. Eq_Model_RateForm), implicit Euler with the step's end values of T
+ *    and c (the mean of the tet's vertex values), as chom_damage_history with
+ *    the RVE's c_sat;
+ *  - at every Gauss point the mechanical RVE solve with that damage (the RVE
+ *    handle `rve`, one batched chom_homogenise call per step) giving C_bar;
+ *  - macro linear elasticity with these C_bar: u_x = 0 on x = 0, u_x =
+ *    strain_x * lx on x = lx, u_y = 0 on y = 0, u_z = 0 on z = 0, other faces
+ *    free; out->reaction[step] is the x-force on the face x = lx.
+ * Macro systems: FP64, Jacobi-preconditioned CG (one workgroup per system) to
+ * r.z <= macro_rtol^2 r0.z0.  factors [8] (nullable: all 1) scale the RVE's
+ * properties at every Gauss point (as in chom_params).  Outputs (host memory,
+ * each nullable): T, c [steps + 1][nv] vertex fields (nv = (nx+1)(ny+1)(nz+1),
+ * x fastest), keep [steps][ngp] (ngp = 6 nx ny nz, tet order of
+ * chom_generate_plain_weave's lattice), reaction [steps], u [nv][3] and
+ * C_bar [ngp][21] of the last step.  The RVE's own options (precision,
+ * tolerances, host or device pointers) apply to its solves.
+ * Errors: CHOM_EINVAL (arguments; also T0 or T_top at or above the law's glass
+ * transition T_g = 126 C, negative c0 or c_top, or a Gauss-point exposure that
+ * leaves the law's domain), CHOM_ENOCONV (a macro solve or an RVE solve did not
+ * converge; outputs written), CHOM_EMATERIAL, CHOM_EDEVICE, CHOM_ENOMEM. */
+typedef struct {
+    int32_t nx, ny, nz;          /* macro cells along x, y, z (>= 1)                          */
+    double lx, ly, lz;           /* box edge lengths (> 0)                                      */
+    double heat_capacity;        /* rho c_p (> 0)                                               */
+    double T0, c0;               /* initial temperature (Celsius) and moisture (wt%)            */
+    double T_top, c_top;         /* exposure on z = lz                                          */
+    double dt_years;             /* time step (> 0)                                             */
+    int32_t steps;               /* time steps (>= 1)                                           */
+    double strain_x;             /* macro stretch of the uniaxial test                          */
+    double macro_rtol;           /* macro CG tolerance (e.g. 1e-10)                             */
+    int32_t macro_max_iter;      /* macro CG step cap                                           */
+    const double *factors;       /* [8] or NULL                                                 */
+} chom_fe2_problem;
+
+typedef struct {
+    double *T, *c;               /* [steps + 1][nv]                                             */
+    double *keep;                /* [steps][ngp]                                                */
+    double *reaction;            /* [steps]                                                     */
+    double *u;                   /* [nv][3], last step                                          */
+    double *C_bar;               /* [ngp][21], last step                                        */
+    int32_t macro_iters[3];      /* largest CG step count of the heat, moisture, mechanics solves */
+} chom_fe2_output;
+
+int chom_fe2_run(chom_rve *rve, const chom_fe2_problem *prob, chom_fe2_output *out);
+
 /* Homogenise the RVE for `batch` parameter records: 6 mechanical + 3 thermal
  * + 3 moisture load cases each.  Outputs: C_hom [batch][21], K_hom [batch][6],
  * D_hom [batch][6], rep [batch] (rep may be NULL; rep is always host memory).

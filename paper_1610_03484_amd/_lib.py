@@ -61,6 +61,19 @@ class ChomMlpTrainOptions(ct.Structure):
                 ("refit_normalisation", ct.c_int32)]
 
 
+class ChomFe2Problem(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32), ("lx", ct.c_double),
+                ("ly", ct.c_double), ("lz", ct.c_double), ("heat_capacity", ct.c_double), ("T0", ct.c_double),
+                ("c0", ct.c_double), ("T_top", ct.c_double), ("c_top", ct.c_double), ("dt_years", ct.c_double),
+                ("steps", ct.c_int32), ("strain_x", ct.c_double), ("macro_rtol", ct.c_double),
+                ("macro_max_iter", ct.c_int32), ("factors", ct.c_void_p)]
+
+
+class ChomFe2Output(ct.Structure):
+    _fields_ = [("T", ct.c_void_p), ("c", ct.c_void_p), ("keep", ct.c_void_p), ("reaction", ct.c_void_p),
+                ("u", ct.c_void_p), ("C_bar", ct.c_void_p), ("macro_iters", ct.c_int32 * 3)]
+
+
 # every exported symbol of include/chom.h with its ctypes signature
 SIGNATURES = {
     "chom_default_options": (ct.c_int, [ct.POINTER(ChomOptions)]),
@@ -77,6 +90,7 @@ SIGNATURES = {
     "chom_damage_history": (ct.c_int, [ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                        ct.c_void_p, ct.c_double, ct.c_int32, ct.c_void_p, ct.c_void_p,
                                        ct.c_void_p]),
+    "chom_fe2_run": (ct.c_int, [ct.c_void_p, ct.POINTER(ChomFe2Problem), ct.POINTER(ChomFe2Output)]),
     "chom_last_error": (ct.c_char_p, []),
     "chom_material_constants": (ct.c_int, [ct.POINTER(ChomMaterials), ct.POINTER(ChomParams), ct.c_double,
                                            ct.c_int32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),

@@ -36,7 +36,8 @@ def test_struct_layouts_match_c_compiler(L, tmp_path):
     """ctypes structs of the binding have the layout gcc gives the header's structs."""
     structs = {"chom_mesh": L.ChomMesh, "chom_materials": L.ChomMaterials, "chom_params": L.ChomParams,
                "chom_options": L.ChomOptions, "chom_report": L.ChomReport,
-               "chom_mlp_options": L.ChomMlpOptions, "chom_mlp_train_options": L.ChomMlpTrainOptions}
+               "chom_mlp_options": L.ChomMlpOptions, "chom_mlp_train_options": L.ChomMlpTrainOptions,
+               "chom_fe2_problem": L.ChomFe2Problem, "chom_fe2_output": L.ChomFe2Output}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "chom.h"', 'int main(void){']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
