@@ -27,6 +27,8 @@ Also measured, outside the timed region, into `config`:
     100 steps, against the HBM peak;
   * the potential-flow yarn directions of the 24^3 RVE: time per call and the
     change of C_bar against the analytic centreline tangent;
+  * the FE^2 outer loop on an 8 x 8 x 2 macro box (768 Gauss points, an 8^3
+    RVE solve at each per step): time per macro step;
   * roofline of the dominant kernel (the FP32 mechanical operator on the batch),
     from HIP events on the library's stream.
 `cpu_baseline`: the oracle on host cores, on the 8^3 records of the batch.
@@ -371,6 +373,34 @@ def yarn_directions_leg(args, torch):
                 note="host-timed call: stencil assembly, one CG workgroup per yarn, per-tet gradients")
 
 
+def fe2_leg(args, torch):
+    """The FE^2 outer loop on an 8 x 8 x 2 macro box (768 Gauss points, one 8^3 periodic
+    RVE solve each per step, FP32 operator + FP64 refinement), four implicit steps of
+    0.25 years with the top face at 60 C and 1.5 wt%: time per macro step (transport,
+    damage, 768 RVE solves, macro elasticity)."""
+    import chom_inputs as ci
+    from paper_1610_03484_amd import RVE, fe2_run, generate_plain_weave
+    rve = RVE(*generate_plain_weave(8, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic",
+              **bench_opts(args, "fp32_refined"))
+    box = dict(nx=8, ny=8, nz=2, lx=1.0, ly=1.0, lz=0.25, T0=20.0, c0=0.0, T_top=60.0, c_top=1.5,
+               dt_years=0.25, strain_x=1e-3, macro_rtol=1e-10)
+    fe2_run(rve, steps=1, **box)
+    torch.cuda.synchronize()
+    steps = 4
+    t0 = time.perf_counter()
+    g = fe2_run(rve, steps=steps, **box)
+    dt = time.perf_counter() - t0
+    rve.close()
+    ngp = 6 * box["nx"] * box["ny"] * box["nz"]
+    return dict(box="8x8x2 cells, 768 Gauss points (P1 Kuhn tets), 1.0 x 1.0 x 0.25",
+                rve="8^3 plain weave, p=2, periodic, FP32 operator + FP64 refinement", steps=steps,
+                dt_years=box["dt_years"], ms_per_macro_step=dt / steps * 1e3,
+                rve_solves_per_s=ngp * steps / dt, macro_cg_iters=[int(v) for v in g["macro_iters"]],
+                keep_range_last_step=[float(g["keep"][-1].min()), float(g["keep"][-1].max())],
+                reaction=[float(v) for v in g["reaction"]],
+                note="host-timed chom_fe2_run call (outputs copied to the host each step)")
+
+
 def c0_plain(args, torch):
     """C0: 8^3 linear-Dirichlet FP64, one record per call; error against a fresh oracle solve."""
     import chom_inputs as ci
@@ -536,6 +566,12 @@ def run_c2(args, torch):
         log(f"yarn directions 24^3: {flow['ms_per_call']:.2f} ms per call, mean angle to the tangent "
             f"{flow['mean_angle_to_tangent_deg']:.1f} deg, C_bar change {flow['c_hom_change_vs_tangent']}")
 
+    # ---- FE^2 outer loop
+    fe2 = None if args.no_fe2 else fe2_leg(args, torch)
+    if fe2:
+        log(f"FE^2 8x8x2 box, 768 Gauss points: {fe2['ms_per_macro_step']:.1f} ms per macro step "
+            f"({fe2['rve_solves_per_s']:.0f} RVE solves/s), macro CG steps {fe2['macro_cg_iters']}")
+
     # ---- surrogate
     sur = None
     if not args.no_surrogate:
@@ -588,7 +624,8 @@ def run_c2(args, torch):
                    "accuracy": acc, "c0_plain_fp64_8cubed": c0,
                    "surrogate": sur,
                    "speedup_surrogate_over_plain": (sur["speedup_vs_plain_12cubed"] if sur else None),
-                   "damage_history_kernel": dmg, "yarn_directions_potential_flow": flow},
+                   "damage_history_kernel": dmg, "yarn_directions_potential_flow": flow,
+                   "fe2_outer_loop": fe2},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -683,6 +720,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="c2: skip the one-record-per-call leg")
     ap.add_argument("--no-damage", action="store_true", help="c2: skip the damage-history kernel leg")
     ap.add_argument("--no-flow", action="store_true", help="c2: skip the potential-flow yarn-direction leg")
+    ap.add_argument("--no-fe2", action="store_true", help="c2: skip the FE^2 outer-loop leg")
     ap.add_argument("--items", type=int, default=512, help="items of the c2 batch (c3: 64 unless set)")
     ap.add_argument("--precond", default="two_level", choices=["block_jacobi", "two_level"],
                     help="CG preconditioner (two_level: block Jacobi plus a P1 multigrid coarse correction)")
