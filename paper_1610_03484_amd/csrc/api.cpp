@@ -487,6 +487,7 @@ template <int C, int R> struct PcgChain {
     int *h_active = nullptr;   // this chain's slice of the class's pinned poll buffer
     int max_iter = 0;          // CG steps per solve and column (0: no cap)
     ColState *cols_scratch = nullptr;   // this chain's slice of a scratch column buffer (compaction)
+    double loose = 0.0;        // inner refinement passes: attainable-accuracy factor of the stopping test
 };
 
 template <int C, int R>
@@ -531,7 +532,7 @@ static hipError_t cg_iteration(const PcgChain<C, R> &K, T *x, T *r, T *p, T *q, 
     if ((e = launch_cg_update<T, C, R>(L, r, q, minv, K.cols, K.acc, K.active, s)) != hipSuccess) return e;
     if (mg && (e = launch_mg_vcycle<T, C, R>(L, r, K.acc, K.active, s)) != hipSuccess) return e;
     return launch_finish_beta<C, R>(L, K.acc, K.ginv, K.ycoef, K.cols, K.active, 0, rtol2, use_init, nullptr, s,
-                                    K.max_iter);
+                                    K.max_iter, nullptr, K.loose);
 }
 
 // Slot state of a chain that compaction permutes: problem table, column
@@ -657,7 +658,7 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, PcgChain<C, R> &K, const T *b, T
     CHOM_HIP((launch_cg_init<T, C, R>(L, b, x, r, minv, K.acc, s)));
     if (mg) CHOM_HIP((launch_mg_vcycle<T, C, R>(L, r, K.acc, nullptr, s)));
     CHOM_HIP((launch_finish_beta<C, R>(L, K.acc, K.ginv, K.ycoef, K.cols, K.active, 1, rtol2,
-                                       K.mask ? 1 : use_init, K.mask, s)));
+                                       K.mask ? 1 : use_init, K.mask, s, 0, nullptr, K.loose)));
     const int max_iter = B->opt.max_iter;
     const int chunk = 8;
     const bool use_graph = std::getenv("CHOM_NO_GRAPH") == nullptr;
@@ -727,7 +728,8 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, PcgChain<C, R> &K, const T *b, T
 // three-BC 24^3 batch: -8% with two).  CHOM_PCG_CHAINS=1 or 2 forces the count.
 template <typename T, int C, int R>
 static int pcg_class(chom_batch *B, ClassWS<C, R> &W, bool fp64, const T *b, T *x, T *r, T *p, T *q,
-                     const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask) {
+                     const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask,
+                     double loose = 0.0) {
     const int nprob = W.L.nprob;
     const char *ev = std::getenv("CHOM_PCG_CHAINS");
     const int want = ev ? std::atoi(ev) : (nprob >= 16 ? 2 : 1);
@@ -735,11 +737,13 @@ static int pcg_class(chom_batch *B, ClassWS<C, R> &W, bool fp64, const T *b, T *
     GraphCache *ga = fp64 ? &W.graph64 : &W.graph32, *gb = fp64 ? &W.graph64b : &W.graph32b;
     if (nch == 1) {
         PcgChain<C, R> K = make_chain<C, R>(W, 0, nprob, ginv, mask, W.stream, ga);
+        K.loose = loose;
         return pcg<T, C, R>(B, W, K, b, x, r, p, q, minv, rtol2, use_init);
     }
     const int h = (nprob + 1) / 2;
     PcgChain<C, R> KA = make_chain<C, R>(W, 0, h, ginv, mask, W.stream, ga);
     PcgChain<C, R> KB = make_chain<C, R>(W, h, nprob - h, ginv, mask, W.stream_b, gb);
+    KA.loose = KB.loose = loose;
     hipEvent_t e0, e1;
     CHOM_HIP(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
     CHOM_HIP(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
@@ -817,6 +821,13 @@ static int refine_class(chom_batch *B, ClassWS<C, R> &W, const double *ginv_inne
     hipStream_t s = W.stream;
     const double irtol2 = B->opt.inner_rtol * B->opt.inner_rtol;
     const bool force_fb = std::getenv("CHOM_FORCE_FP64_FALLBACK") != nullptr;
+    // An FP32 inner pass cannot resolve a column below about u32 * eref / E of
+    // its own energy E (eref: the linear-field energy): the rounding of the
+    // stiff phase's element contributions swamps the soft phase's where the
+    // matrix is degraded.  Its stopping test is relaxed to that level (factor 6,
+    // measured on the mixed batch between 1.5 and 100), so such a column stops
+    // where FP32 stalls and the FP64 refinement continues from there.
+    const double loose = 6.0 * 0x1p-24;
     CHOM_HIP(hipMemsetAsync(W.x64.p, 0, sizeof(double) * W.total_vals, s));
     CHOM_HIP((launch_residual64<C, R>(L, W.b.p, nullptr, W.r64.p, W.r32.p, s)));
     CHOM_HIP(hipMemcpyAsync(W.cols_outer.p, W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToDevice, s));
@@ -908,7 +919,7 @@ static int refine_class(chom_batch *B, ClassWS<C, R> &W, const double *ginv_inne
         }
         const ColState *mask32 = any_stalled ? W.cols_fb.p : W.cols_outer.p;
         CHOM_TRY((pcg_class<float, C, R>(B, W, false, W.r32.p, W.xf.p, W.rf.p, W.pf.p, W.qf.p, W.minv32.p,
-                                         ginv_inner32, irtol2, 1, mask32)));
+                                         ginv_inner32, irtol2, 1, mask32, loose)));
         CHOM_HIP(launch_axpy_x64(W.total_vals, W.x64.p, W.xf.p, s));
         CHOM_HIP((launch_operator<double, C, R>(L, nprob, L.rg, W.x64.p, W.q64.p, W.accpq.p, nullptr, s)));
         CHOM_HIP((launch_residual64<C, R>(L, W.b.p, W.q64.p, W.r64.p, W.r32.p, s)));

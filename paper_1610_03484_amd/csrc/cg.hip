@@ -495,12 +495,16 @@ __global__ __launch_bounds__(256) void finish_alpha_kernel(double *acc_pq, ColSt
 // energy eref, at least 1e-6 eref): rz <= rtol2 E, or with use_init
 // rz <= rtol2 min(rz_init, E).  Relative to E, the error of the energy-form
 // average stays small against the homogenised value itself, also in the soft
-// directions of a degraded matrix, where E is far below eref.
+// directions of a degraded matrix, where E is far below eref.  With loose > 0
+// (inner FP32 passes of a refinement) the relative tolerance is raised to
+// loose * eref / E where that is larger (at most 0.05): the accuracy an FP32
+// operator can reach for the column.
 template <int C, int R>
 __global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const Prob *probs, int NR, double *accbuf,
                                                          const double *ginv, double *ycoef, ColState *cols,
                                                          int *prob_active, int first, double rtol2, int use_init,
-                                                         const ColState *mask, int max_iter, const ColState *esrc) {
+                                                         const ColState *mask, int max_iter, const ColState *esrc,
+                                                         double loose) {
     constexpr int SMAX = C * 4;
     constexpr int RECMAX = ACC_RECMAX<C>;
     const int prob = blockIdx.x;
@@ -568,8 +572,13 @@ __global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const
         if (!(en > 0.0)) en = cs.eref;
         en = fmin(fmax(en, 1e-6 * cs.eref), cs.eref);
         const double ref = use_init ? fmin(cs.rz_init, en) : en;
+        double tol2 = rtol2;
+        if (use_init && loose > 0.0) {
+            const double t = fmin(loose * cs.eref / en, 0.05);
+            tol2 = fmax(tol2, t * t);
+        }
         if (!cs.done && !isfinite(rz)) cs.done = COL_NONFINITE;
-        if (!cs.done && rz <= rtol2 * ref) cs.done = COL_CONVERGED;
+        if (!cs.done && rz <= tol2 * ref) cs.done = COL_CONVERGED;
         if (!cs.done && !first && max_iter > 0 && cs.iters - cs.iters0 >= max_iter) cs.done = COL_CAPPED;
         if (cs.done) cs.beta = 0.0;
         sdone[lane] = cs.done;
@@ -659,9 +668,9 @@ hipError_t launch_finish_alpha(const Launch &L, double *acc_pq, ColState *cols, 
 template <int C, int R>
 hipError_t launch_finish_beta(const Launch &L, double *accbuf, const double *ginv, double *ycoef, ColState *cols,
                               int *prob_active, int first, double rtol2, int use_init, const ColState *mask,
-                              hipStream_t s, int max_iter, const ColState *esrc) {
+                              hipStream_t s, int max_iter, const ColState *esrc, double loose) {
     finish_beta_kernel<C, R><<<L.nprob, 512, 0, s>>>(L.geos, L.probs, L.nr, accbuf, ginv, ycoef, cols, prob_active,
-                                                    first, rtol2, use_init, mask, max_iter, esrc);
+                                                    first, rtol2, use_init, mask, max_iter, esrc, loose);
     return hipGetLastError();
 }
 
@@ -847,7 +856,7 @@ CHOM_INST(float, 1, 3)
     template hipError_t launch_finish_alpha<C, R>(const Launch &, double *, ColState *, hipStream_t);            \
     template hipError_t launch_finish_beta<C, R>(const Launch &, double *, const double *, double *, ColState *, \
                                                  int *, int, double, int, const ColState *, hipStream_t, int,    \
-                                                 const ColState *);                                              \
+                                                 const ColState *, double);                                      \
     template hipError_t launch_proj_resid<C, R>(const Launch &, double *, float *, const double *,               \
                                                 const double *, double *, hipStream_t);                          \
     template hipError_t launch_residual64<C, R>(const Launch &, const double *, const double *, double *, float *, \

@@ -109,7 +109,7 @@ hipError_t launch_finish_alpha(const Launch &L, double *acc_pq, ColState *cols, 
 template <int C, int R>
 hipError_t launch_finish_beta(const Launch &L, double *accbuf, const double *ginv, double *ycoef, ColState *cols,
                               int *prob_active, int first, double rtol2, int use_init, const ColState *mask,
-                              hipStream_t s, int max_iter = 0, const ColState *esrc = nullptr);
+                              hipStream_t s, int max_iter = 0, const ColState *esrc = nullptr, double loose = 0.0);
 template <int C, int R>
 hipError_t launch_proj_resid(const Launch &L, double *r64, float *r32, const double *minv64,
                              const double *ycoef, double *partial, hipStream_t s);
