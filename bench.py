@@ -401,6 +401,30 @@ def fe2_leg(args, torch):
                 note="host-timed chom_fe2_run call (outputs copied to the host each step)")
 
 
+def fe2_surrogate(rve, sur, torch):
+    """The FE^2 box of the FE^2 leg on the 12^3 RVE: four macro steps with an RVE solve
+    at every Gauss point, then with the trained ensemble (fallback threshold 1e-2)."""
+    from paper_1610_03484_amd import fe2_run
+    box = dict(nx=8, ny=8, nz=2, lx=1.0, ly=1.0, lz=0.25, T0=20.0, c0=0.0, T_top=60.0, c_top=1.5,
+               dt_years=0.25, strain_x=1e-3, macro_rtol=1e-10)
+    steps = 4
+    out = {}
+    for name, kw in (("rve", {}), ("surrogate", dict(surrogate=sur, surrogate_thresh=1e-2))):
+        fe2_run(rve, steps=1, **box, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = fe2_run(rve, steps=steps, **box, **kw)
+        out[name] = (time.perf_counter() - t0) / steps * 1e3, g
+    (t_rve, g_rve), (t_sur, g_sur) = out["rve"], out["surrogate"]
+    rdiff = float(np.abs(g_sur["reaction"] / g_rve["reaction"] - 1.0).max())
+    log(f"FE^2 12^3 RVE, 768 Gauss points: {t_rve:.1f} ms per macro step with RVE solves, {t_sur:.1f} ms with the "
+        f"surrogate ({g_sur['n_fallback']} fallbacks), reactions {rdiff:.1e} apart")
+    return dict(box="8x8x2 cells, 768 Gauss points", rve="12^3 plain weave, p=2, periodic, FP32 + FP64 refinement",
+                steps=steps, ms_per_macro_step_rve=t_rve, ms_per_macro_step_surrogate=t_sur,
+                speedup=t_rve / t_sur, fallbacks=int(g_sur["n_fallback"]), reaction_rel_diff=rdiff,
+                note="host-timed chom_fe2_run calls")
+
+
 def c0_plain(args, torch):
     """C0: 8^3 linear-Dirichlet FP64, one record per call; error against a fresh oracle solve."""
     import chom_inputs as ci
@@ -486,6 +510,7 @@ def surrogate_leg(args, torch, plain12_rate=None):
     raw = block_errors(_stack(Cp.cpu().numpy(), Kp.cpu().numpy(), Dp.cpu().numpy()), truth)
     log(f"surrogate: {args.points} points in {dt:.2f} s ({rate:.3g}/s), {nfb} fallbacks; held-out max error "
         f"{err.max():.2e} (network alone {raw.max():.2e})")
+    fe2 = None if args.no_fe2 else fe2_surrogate(rve, sur, torch)
     out = dict(rate=rate, points=args.points, fallbacks=int(nfb), training_solves=args.train,
                training_solve_s=t_solve, training_s=t_train, epochs=args.epochs,
                batched_rate_12cubed=batched12, plain_rate_12cubed=plain12_rate,
@@ -494,7 +519,8 @@ def surrogate_leg(args, torch, plain12_rate=None):
                heldout_max_err=float(err.max()), heldout_max_err_network_alone=float(raw.max()),
                heldout_fallbacks=int(nfbh),
                predict_kernel=dict(avg_launch_us=t_pred * 1e6, achieved_TFLOPs=flops / t_pred / 1e12,
-                                   frac_bf16_peak=flops / t_pred / 2.5e15))
+                                   frac_bf16_peak=flops / t_pred / 2.5e15),
+               fe2_outer_loop=fe2)
     sur.close()
     rve.close()
     return out
@@ -720,7 +746,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="c2: skip the one-record-per-call leg")
     ap.add_argument("--no-damage", action="store_true", help="c2: skip the damage-history kernel leg")
     ap.add_argument("--no-flow", action="store_true", help="c2: skip the potential-flow yarn-direction leg")
-    ap.add_argument("--no-fe2", action="store_true", help="c2: skip the FE^2 outer-loop leg")
+    ap.add_argument("--no-fe2", action="store_true", help="skip the FE^2 outer-loop legs")
     ap.add_argument("--items", type=int, default=512, help="items of the c2 batch (c3: 64 unless set)")
     ap.add_argument("--precond", default="two_level", choices=["block_jacobi", "two_level"],
                     help="CG preconditioner (two_level: block Jacobi plus a P1 multigrid coarse correction)")

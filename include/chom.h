@@ -67,6 +67,7 @@ enum { CHOM_PRECOND_BLOCK_JACOBI = 0, CHOM_PRECOND_TWO_LEVEL = 1 };
 
 typedef struct chom_rve chom_rve;
 typedef struct chom_batch chom_batch;
+typedef struct chom_mlp chom_mlp;   /* learned surrogate ensemble (below) */
 
 /* RVE mesh.  Supported meshes: the Kuhn split of an n x n x n cell grid of the
  * box [lo, hi] -- (n+1)^3 vertices numbered i + (n+1)(j + (n+1)k), 6 n^3 tets,
@@ -265,7 +266,12 @@ int chom_damage_history(int64_t n, int32_t m, const double *T_celsius, const dou
  * x fastest), keep [steps][ngp] (ngp = 6 nx ny nz, tet order of
  * chom_generate_plain_weave's lattice), reaction [steps], u [nv][3] and
  * C_bar [ngp][21] of the last step.  The RVE's own options (precision,
- * tolerances, host or device pointers) apply to its solves.
+ * tolerances, host or device pointers) apply to its solves.  With `surrogate`
+ * set (a trained ensemble with the RVE's c_sat and at least two members), the
+ * Gauss points' C_bar come from chom_homogenise_surrogate with this RVE as the
+ * fallback for records whose disagreement exceeds surrogate_thresh (the
+ * transport coefficients still come from one RVE solve); out->n_fallback
+ * counts the fallback solves over all steps.
  * Errors: CHOM_EINVAL (arguments; also T0 or T_top at or above the law's glass
  * transition T_g = 126 C, negative c0 or c_top, or a Gauss-point exposure that
  * leaves the law's domain), CHOM_ENOCONV (a macro solve or an RVE solve did not
@@ -282,6 +288,8 @@ typedef struct {
     double macro_rtol;           /* macro CG tolerance (e.g. 1e-10)                             */
     int32_t macro_max_iter;      /* macro CG step cap                                           */
     const double *factors;       /* [8] or NULL                                                 */
+    chom_mlp *surrogate;         /* NULL: an RVE solve at every Gauss point                     */
+    double surrogate_thresh;     /* fallback threshold on the ensemble disagreement             */
 } chom_fe2_problem;
 
 typedef struct {
@@ -291,6 +299,7 @@ typedef struct {
     double *u;                   /* [nv][3], last step                                          */
     double *C_bar;               /* [ngp][21], last step                                        */
     int32_t macro_iters[3];      /* largest CG step count of the heat, moisture, mechanics solves */
+    int64_t n_fallback;          /* RVE fallback solves of the surrogate, all steps             */
 } chom_fe2_output;
 
 int chom_fe2_run(chom_rve *rve, const chom_fe2_problem *prob, chom_fe2_output *out);
@@ -391,7 +400,6 @@ void chom_batch_destroy(chom_batch *batch);
  * disagreement [n] and used_fallback [n] are device pointers when
  * chom_mlp_options.device_ptrs is set, else host pointers.  Weight and
  * standardisation arrays are always host pointers. */
-typedef struct chom_mlp chom_mlp;
 
 typedef struct {
     int32_t members;        /* ensemble size, 1..8 (default 5)                           */

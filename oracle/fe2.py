@@ -126,9 +126,12 @@ def solve_dirichlet(A, b, fixed, values):
 
 
 def run(rve, nx, ny, nz, lx=1.0, ly=1.0, lz=0.25, heat_capacity=1.0, T0=20.0, c0=0.0, T_top=60.0, c_top=1.5,
-        dt_years=10.0 / 365.25, steps=10, strain_x=1e-3, factors=None, c_sat=1.5):
+        dt_years=10.0 / 365.25, steps=10, strain_x=1e-3, factors=None, c_sat=1.5, gauss=None):
     """FE^2 steps; returns T, c [steps + 1, nv], keep [steps, ngp], reaction [steps],
-    u [nv, 3] and C_bar [ngp, 6, 6] of the last step."""
+    u [nv, 3] and C_bar [ngp, 6, 6] of the last step.  `gauss` (default: rve)
+    gives C_bar at the Gauss points, e.g. a surrogate model; the transport
+    coefficients always come from rve."""
+    gauss = rve if gauss is None else gauss
     fac = np.ones(8) if factors is None else np.asarray(factors, float)
     coords, tets = box_mesh(nx, ny, nz, lx, ly, lz)
     nv, ne = len(coords), len(tets)
@@ -161,7 +164,7 @@ def run(rve, nx, ny, nz, lx=1.0, ly=1.0, lz=0.25, heat_capacity=1.0, T0=20.0, c0
         keep = materials.damage_history(Tg[None, :], cg[None, :], [dt_years], keep0=keep, c_sat=c_sat)[0]
         keeps.append(keep.copy())
         t_eq = materials.equivalent_exposure_years(keep)
-        Cs = np.array([rve(np.r_[60.0, c_sat, t_eq[e], fac])["C"] for e in range(ne)])
+        Cs = np.array([gauss(np.r_[60.0, c_sat, t_eq[e], fac])["C"] for e in range(ne)])
         Ku = elastic_matrix(coords, tets, Cs)
         u = solve_dirichlet(Ku, np.zeros(3 * nv), fixed_u, val_u)
         reactions.append(float((Ku @ u)[3 * np.flatnonzero(on_x1)].sum()))

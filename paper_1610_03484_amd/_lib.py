@@ -66,12 +66,14 @@ class ChomFe2Problem(ct.Structure):
                 ("ly", ct.c_double), ("lz", ct.c_double), ("heat_capacity", ct.c_double), ("T0", ct.c_double),
                 ("c0", ct.c_double), ("T_top", ct.c_double), ("c_top", ct.c_double), ("dt_years", ct.c_double),
                 ("steps", ct.c_int32), ("strain_x", ct.c_double), ("macro_rtol", ct.c_double),
-                ("macro_max_iter", ct.c_int32), ("factors", ct.c_void_p)]
+                ("macro_max_iter", ct.c_int32), ("factors", ct.c_void_p), ("surrogate", ct.c_void_p),
+                ("surrogate_thresh", ct.c_double)]
 
 
 class ChomFe2Output(ct.Structure):
     _fields_ = [("T", ct.c_void_p), ("c", ct.c_void_p), ("keep", ct.c_void_p), ("reaction", ct.c_void_p),
-                ("u", ct.c_void_p), ("C_bar", ct.c_void_p), ("macro_iters", ct.c_int32 * 3)]
+                ("u", ct.c_void_p), ("C_bar", ct.c_void_p), ("macro_iters", ct.c_int32 * 3),
+                ("n_fallback", ct.c_int64)]
 
 
 # every exported symbol of include/chom.h with its ctypes signature

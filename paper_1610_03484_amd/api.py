@@ -137,15 +137,18 @@ def damage_history(T_celsius, c_wt, dt_years, keep0=None, factors=None, c_sat=1.
 
 def fe2_run(rve, nx, ny, nz, lx=1.0, ly=1.0, lz=0.25, heat_capacity=1.0, T0=20.0, c0=0.0, T_top=60.0,
             c_top=1.5, dt_years=10.0 / 365.25, steps=10, strain_x=1e-3, macro_rtol=1e-10, macro_max_iter=20000,
-            factors=None, allow_noconv=False):
-    """chom_fe2_run on an RVE handle.  Returns a dict of numpy arrays: T, c
-    [steps + 1, nv], keep [steps, ngp], reaction [steps], u [nv, 3] and C_bar
-    [ngp, 21] of the last step, macro_iters [3], status."""
+            factors=None, surrogate=None, surrogate_thresh=1e-2, allow_noconv=False):
+    """chom_fe2_run on an RVE handle (with `surrogate`, a Surrogate whose
+    predictions replace the RVE solves, the RVE as fallback).  Returns a dict of
+    numpy arrays: T, c [steps + 1, nv], keep [steps, ngp], reaction [steps],
+    u [nv, 3] and C_bar [ngp, 21] of the last step, macro_iters [3],
+    n_fallback, status."""
     nv = (nx + 1) * (ny + 1) * (nz + 1)
     ngp = 6 * nx * ny * nz
     fac = None if factors is None else np.ascontiguousarray(np.asarray(factors, dtype=np.float64).reshape(8))
     P = L.ChomFe2Problem(nx, ny, nz, lx, ly, lz, heat_capacity, T0, c0, T_top, c_top, dt_years, steps, strain_x,
-                         macro_rtol, macro_max_iter, _ptr(fac))
+                         macro_rtol, macro_max_iter, _ptr(fac), surrogate._h if surrogate is not None else None,
+                         surrogate_thresh)
     res = dict(T=np.zeros((steps + 1, nv)), c=np.zeros((steps + 1, nv)), keep=np.zeros((steps, ngp)),
                reaction=np.zeros(steps), u=np.zeros((nv, 3)), C_bar=np.zeros((ngp, 21)))
     O = L.ChomFe2Output(*(_ptr(res[k]) for k in ("T", "c", "keep", "reaction", "u", "C_bar")))
@@ -153,6 +156,7 @@ def fe2_run(rve, nx, ny, nz, lx=1.0, ly=1.0, lz=0.25, heat_capacity=1.0, T0=20.0
     if not (st == L.CHOM_OK or (allow_noconv and st == L.CHOM_ENOCONV)):
         L.check(st, "chom_fe2_run")
     res["macro_iters"] = list(O.macro_iters)
+    res["n_fallback"] = int(O.n_fallback)
     res["status"] = st
     return res
 

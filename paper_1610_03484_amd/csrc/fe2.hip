@@ -348,6 +348,8 @@ using namespace chom;
 
 extern "C" int chom_fe2_run(chom_rve *rve, const chom_fe2_problem *P, chom_fe2_output *out) {
     if (!rve || !P) return fe2_fail("null handle or problem", CHOM_EINVAL);
+    if (P->surrogate && !(P->surrogate_thresh >= 0))
+        return fe2_fail("the surrogate's fallback threshold must be >= 0", CHOM_EINVAL);
     if (P->nx < 1 || P->ny < 1 || P->nz < 1 || P->nx > 256 || P->ny > 256 || P->nz > 256 || !(P->lx > 0) ||
         !(P->ly > 0) || !(P->lz > 0) || !(P->heat_capacity > 0) || !(P->dt_years > 0) || P->steps < 1 ||
         !(P->macro_rtol > 0) || P->macro_max_iter < 1 || !std::isfinite(P->strain_x) || !std::isfinite(P->T0) ||
@@ -454,7 +456,20 @@ extern "C" int chom_fe2_run(chom_rve *rve, const chom_fe2_problem *P, chom_fe2_o
     CHOM_HIP(hipGetLastError());
     if (out && out->T) std::memcpy(out->T, hT.data(), sizeof(double) * nv);
     if (out && out->c) std::memcpy(out->c, hc.data(), sizeof(double) * nv);
-    if (out) out->macro_iters[0] = out->macro_iters[1] = out->macro_iters[2] = 0;
+    if (out) {
+        out->macro_iters[0] = out->macro_iters[1] = out->macro_iters[2] = 0;
+        out->n_fallback = 0;
+    }
+    // with a surrogate whose arrays live on the device, the Gauss-point records
+    // and results pass through device buffers
+    const bool sur_dev = P->surrogate && mlp_device_ptrs(P->surrogate);
+    DevBuf<double> sp, sC, sK, sD;
+    if (sur_dev) {
+        CHOM_HIP(sp.ensure((size_t)ngp * 11));
+        CHOM_HIP(sC.ensure((size_t)ngp * 21));
+        CHOM_HIP(sK.ensure((size_t)ngp * 6));
+        CHOM_HIP(sD.ensure((size_t)ngp * 6));
+    }
 
     std::vector<double> hkeep(ngp, 1.0), hTg(ngp), hcg(ngp), hfac(ngp * 8), hC(ngp * 21), hK(ngp * 6), hD(ngp * 6);
     std::vector<chom_params> hpar(ngp);
@@ -494,8 +509,26 @@ extern "C" int chom_fe2_run(chom_rve *rve, const chom_fe2_problem *P, chom_fe2_o
                                  knew.data(), hpar.data());
         if (st != CHOM_OK) return st;
         hkeep = knew;
-        // ---- the RVE at every Gauss point
-        st = rve_homogenise_host(rve, hpar.data(), (int)ngp, hC.data(), hK.data(), hD.data(), hrep.data());
+        // ---- the RVE (or the surrogate with the RVE as fallback) at every Gauss point
+        if (P->surrogate) {
+            int64_t nfb = 0;
+            if (sur_dev) {
+                CHOM_HIP(hipMemcpy(sp.p, hpar.data(), sizeof(double) * ngp * 11, hipMemcpyHostToDevice));
+                st = chom_homogenise_surrogate(P->surrogate, rve, reinterpret_cast<const chom_params *>(sp.p), ngp,
+                                               P->surrogate_thresh, 0, sC.p, sK.p, sD.p, nullptr, nullptr, &nfb);
+                if (st == CHOM_OK || st == CHOM_ENOCONV) {
+                    CHOM_HIP(hipMemcpy(hC.data(), sC.p, sizeof(double) * ngp * 21, hipMemcpyDeviceToHost));
+                    CHOM_HIP(hipMemcpy(hK.data(), sK.p, sizeof(double) * ngp * 6, hipMemcpyDeviceToHost));
+                    CHOM_HIP(hipMemcpy(hD.data(), sD.p, sizeof(double) * ngp * 6, hipMemcpyDeviceToHost));
+                }
+            } else {
+                st = chom_homogenise_surrogate(P->surrogate, rve, hpar.data(), ngp, P->surrogate_thresh, 0, hC.data(),
+                                               hK.data(), hD.data(), nullptr, nullptr, &nfb);
+            }
+            if (out) out->n_fallback += nfb;
+        } else {
+            st = rve_homogenise_host(rve, hpar.data(), (int)ngp, hC.data(), hK.data(), hD.data(), hrep.data());
+        }
         if (st == CHOM_ENOCONV) status = CHOM_ENOCONV;
         else if (st != CHOM_OK) return st;
         // ---- macro elasticity

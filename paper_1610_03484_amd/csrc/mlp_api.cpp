@@ -196,6 +196,8 @@ int mlp_loss_grad_ws(chom_mlp *m, int member, const double *p, const double *c, 
 
 bool mlp_ready(const chom_mlp *m, int member) { return m && m->has_norm && member >= 0 && member < m->members; }
 
+int mlp_device_ptrs(const chom_mlp *m) { return m->opt.device_ptrs != 0; }
+
 }  // namespace chom
 
 extern "C" {
