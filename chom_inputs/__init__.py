@@ -2,8 +2,9 @@
 
 This package holds no arithmetic of the homogenisation method: it only draws the
 random workload parameters (temperature, moisture, exposure time and the eight
-property factors of each macro Gauss point) and states the base material
-constants of the plain-weave workload.  Everything downstream (degradation law,
+property factors of each macro Gauss point), states the base material
+constants of the plain-weave workload and builds seeded unstructured box
+meshes (geometry only).  Everything downstream (degradation law,
 stiffness tensors, meshes, solves) is implemented separately by the oracle and by
 the HIP library.
 """
@@ -17,3 +18,4 @@ from .params import (  # noqa: F401
     batch_sizes_c2,
     uniform_block,
 )
+from .umesh import unstructured_box  # noqa: F401

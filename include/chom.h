@@ -331,6 +331,54 @@ int chom_time_operator(chom_rve *rve, int32_t physics, int32_t reps, double *ms_
  * destroyed first. */
 void chom_rve_destroy(chom_rve *rve);
 
+/* ---------------------------------------------------------------- general tet meshes
+ * RVEs on any conforming tet mesh of the box [lo, hi] (the paper's RVE is an
+ * unstructured mesh of its spline yarn geometry, Sec. 1, Table 1; the lattice
+ * handles above need the Kuhn lattice).  Order-2 hierarchic elements on the
+ * mesh's vertices and edges (numbered by the library), the element operator
+ * of the lattice path applied one thread per tet with FP64 atomic assembly,
+ * point-block Jacobi PCG in FP64 per load case with the energy-relative
+ * stopping test of chom_options.rtol (Sec. 2, Eqs. eq_RVE_disc_Eqs,
+ * Eq_C_stress, eq_homo_flux: the same 6 + 3 + 3 load cases and energy-form
+ * averages as chom_homogenise).
+ * bc: CHOM_BC_DIRICHLET (linear displacement / temperature / concentration on
+ * every boundary vertex and boundary edge) or CHOM_BC_PERIODIC (the faces
+ * x_d = hi_d must match x_d = lo_d vertex for vertex and edge for edge; the
+ * class of the corner lo is pinned, which fixes the translations and leaves
+ * C_bar unchanged); uniform traction is not offered on general meshes.
+ * opt: precision must be CHOM_FP64 (precond is ignored: point-block Jacobi);
+ * rtol, max_iter, c_sat, degrade_yarn, device_ptrs (params and outputs of
+ * chom_urve_homogenise) and hip_stream are used.  The mesh arrays are copied.
+ * Errors: CHOM_EINVAL (arguments, options), CHOM_EMESH (vertex outside the box,
+ * vertex id out of range, degenerate tet, tets not filling the box, phase out
+ * of 0..4, non-unit yarn axis, periodic faces that do not match, no vertex at
+ * the corner lo), CHOM_EMATERIAL, CHOM_EDEVICE, CHOM_ENOMEM. */
+typedef struct chom_urve chom_urve;
+int chom_urve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc, const chom_options *opt,
+                     chom_urve **out);
+
+/* P2 nodes (vertices + edges) and free unknowns (per component) of a handle. */
+int chom_urve_sizes(const chom_urve *u, int64_t *n_nodes, int64_t *n_unknowns);
+
+/* Homogenise `batch` parameter records one after the other: outputs and report
+ * as for chom_homogenise (refine_steps and fp64_fallback are 0; the
+ * Hill-Mandel gap compares the energy form with the volume average of stress
+ * and flux).  Errors: CHOM_ENOCONV (results written), CHOM_EINVAL (records
+ * outside the degradation law), CHOM_EDEVICE, CHOM_ENOMEM. */
+int chom_urve_homogenise(chom_urve *u, const chom_params *params, int32_t batch, double *C_hom, double *K_hom,
+                         double *D_hom, chom_report *rep);
+
+/* Release a general-mesh handle (NULL is ignored). */
+void chom_urve_destroy(chom_urve *u);
+
+/* Yarn tags of any tet mesh of the unit cube by the synthetic weave of
+ * chom_generate_plain_weave (the same centroid test and tangent): phase [n_tets]
+ * and fibre_axis [n_tets][3] out; coords [n_vertices][3], tets [n_tets][4] in.
+ * device_ptrs: 1 if all four arrays are device memory.  Runs on the GPU.
+ * Errors: CHOM_EINVAL, CHOM_EMESH (vertex id out of range), CHOM_EDEVICE. */
+int chom_tag_plain_weave(const double *coords, int64_t n_vertices, const int32_t *tets, int64_t n_tets,
+                         int32_t device_ptrs, int8_t *phase, double *fibre_axis);
+
 /* ---------------------------------------------------------------- batches
  * One macro Gauss point per item (the FE^2 setting of Sec. 5, where every macro
  * Gauss point carries its own RVE): item i is homogenised on RVE rves[i] with

@@ -87,6 +87,14 @@ SIGNATURES = {
     "chom_homogenise": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                    ct.POINTER(ChomReport)]),
     "chom_rve_destroy": (None, [ct.c_void_p]),
+    "chom_urve_create": (ct.c_int, [ct.POINTER(ChomMesh), ct.POINTER(ChomMaterials), ct.c_int32,
+                                    ct.POINTER(ChomOptions), ct.POINTER(ct.c_void_p)]),
+    "chom_urve_sizes": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64)]),
+    "chom_urve_homogenise": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                        ct.c_void_p, ct.POINTER(ChomReport)]),
+    "chom_urve_destroy": (None, [ct.c_void_p]),
+    "chom_tag_plain_weave": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p,
+                                        ct.c_void_p]),
     "chom_yarn_directions": (ct.c_int, [ct.POINTER(ChomMesh), ct.c_int32, ct.c_void_p, ct.c_double, ct.c_int32,
                                         ct.c_void_p, ct.c_void_p]),
     "chom_damage_history": (ct.c_int, [ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,

@@ -231,6 +231,71 @@ class RVE:
             pass
 
 
+class URVE:
+    """Handle of chom_urve_create (any conforming tet mesh of the box [lo, hi]);
+    homogenise() wraps chom_urve_homogenise.  Host (numpy) mesh arrays."""
+
+    def __init__(self, coords, tets, phase, axis, materials: dict, bc="periodic", lo=(0.0, 0.0, 0.0),
+                 hi=(1.0, 1.0, 1.0), **options):
+        self._h = ct.c_void_p()
+        options.setdefault("precision", "fp64")
+        self.options = default_options(**options)
+        arrs = [np.ascontiguousarray(coords, np.float64), np.ascontiguousarray(tets, np.int32),
+                np.ascontiguousarray(phase, np.int8), np.ascontiguousarray(axis, np.float64)]
+        mesh = L.ChomMesh()
+        mesh.on_device = 0
+        mesh.n_vertices, mesh.n_tets = arrs[0].shape[0], arrs[1].shape[0]
+        mesh.coords, mesh.tets, mesh.phase, mesh.fibre_axis = [a.ctypes.data for a in arrs]
+        mesh.lo[:] = lo
+        mesh.hi[:] = hi
+        self.bc = L.BC[bc] if isinstance(bc, str) else int(bc)
+        st = L.lib().chom_urve_create(ct.byref(mesh), ct.byref(materials_struct(materials)), self.bc,
+                                      ct.byref(self.options), ct.byref(self._h))
+        del arrs
+        L.check(st, "chom_urve_create")
+
+    def sizes(self):
+        nn, nu = ct.c_int64(), ct.c_int64()
+        L.check(L.lib().chom_urve_sizes(self._h, ct.byref(nn), ct.byref(nu)), "chom_urve_sizes")
+        return nn.value, nu.value
+
+    def homogenise(self, params, allow_noconv=False):
+        """params [B, 11] -> (C21 [B,21], K6 [B,6], D6 [B,6], reports list)."""
+        p = np.asarray(params, dtype=np.float64).reshape(-1, 11)
+        B = len(p)
+        C = np.zeros((B, 21))
+        K = np.zeros((B, 6))
+        D = np.zeros((B, 6))
+        reps = (L.ChomReport * B)()
+        st = L.lib().chom_urve_homogenise(self._h, params_array(p), B, ct.c_void_p(C.ctypes.data),
+                                          ct.c_void_p(K.ctypes.data), ct.c_void_p(D.ctypes.data), reps)
+        if not (st == L.CHOM_OK or (allow_noconv and st == L.CHOM_ENOCONV)):
+            L.check(st, "chom_urve_homogenise")
+        return C, K, D, [report_dict(r) for r in reps]
+
+    def close(self):
+        if self._h:
+            L.lib().chom_urve_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tag_plain_weave(coords, tets):
+    """chom_tag_plain_weave on host arrays: (phase [nt] int8, fibre_axis [nt, 3])."""
+    c = np.ascontiguousarray(coords, np.float64)
+    t = np.ascontiguousarray(tets, np.int32)
+    ph = np.zeros(len(t), np.int8)
+    ax = np.zeros((len(t), 3))
+    L.check(L.lib().chom_tag_plain_weave(c.ctypes.data, len(c), t.ctypes.data, len(t), 0, ph.ctypes.data,
+                                         ax.ctypes.data), "chom_tag_plain_weave")
+    return ph, ax
+
+
 def report_dict(r: L.ChomReport) -> dict:
     return dict(iters=list(r.iters), refine_steps=list(r.refine_steps), status=r.status,
                 resid=list(r.resid), asym=r.asym, omega_keep=r.omega_keep, fail=list(r.fail),

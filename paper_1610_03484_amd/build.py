@@ -22,7 +22,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-a
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include")]
 SOURCES = ["mesh.hip", "setup.hip", "operator.hip", "cg.hip", "mg.hip", "hom.hip", "mlp.hip", "api.cpp", "mlp_api.cpp", "hp_tables.cpp", "hp.hip",
-           "mlp_noalloc.hip", "degrade.hip", "flow.hip", "fe2.hip"]
+           "mlp_noalloc.hip", "degrade.hip", "flow.hip", "fe2.hip", "umesh.hip"]
 
 
 def _compile(src: str) -> str:

@@ -176,6 +176,9 @@ void rve_settings(const chom_rve *rve, double *c_sat, int *degrade_yarn);
 int mlp_loss_grad_ws(chom_mlp *m, int member, const double *p, const double *c, const double *k, const double *d,
                      long long n, double *loss, float *grad, unsigned char *ws, long long max_rows);
 bool mlp_ready(const chom_mlp *m, int member);
+// Yarn tags of any tet mesh of the unit cube (mesh.hip).
+hipError_t launch_tag(long long nt, const double *coords, const int32_t *tets, int8_t *phase, double *axis,
+                      hipStream_t s);
 // 1 if the ensemble's bulk arrays are device pointers (chom_mlp_options.device_ptrs).
 int mlp_device_ptrs(const chom_mlp *m);
 

@@ -93,6 +93,44 @@ __global__ void gen_tets_kernel(int n, int32_t *tets, int8_t *phase, double *axi
     }
 }
 
+// Tags of any tet mesh of the unit cube: the same yarn test at the centroid
+// (summed in vertex order, then scaled by 1/4) as the lattice generator.
+__global__ void tag_tets_kernel(long long nt, const double *coords, const int32_t *tets, int8_t *phase, double *axis) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nt;
+         e += (long long)gridDim.x * blockDim.x) {
+        double cen[3];
+        for (int d = 0; d < 3; ++d) {
+            const double x0 = coords[3LL * tets[4 * e] + d], x1 = coords[3LL * tets[4 * e + 1] + d];
+            const double x2 = coords[3LL * tets[4 * e + 2] + d], x3 = coords[3LL * tets[4 * e + 3] + d];
+            cen[d] = __dmul_rn(__dadd_rn(__dadd_rn(__dadd_rn(x0, x1), x2), x3), 0.25);
+        }
+        int ph = 0;
+        double ax[3] = {0.0, 0.0, 0.0};
+        for (int y = 0; y < 4 && ph == 0; ++y) {
+            double tang[3];
+            const double f = yarn_f(y, cen, tang);
+            if (f <= 1.0) {
+                ph = y + 1;
+                const double nr = sqrt(tang[0] * tang[0] + tang[1] * tang[1] + tang[2] * tang[2]);
+                ax[0] = tang[0] / nr;
+                ax[1] = tang[1] / nr;
+                ax[2] = tang[2] / nr;
+            }
+        }
+        phase[e] = (int8_t)ph;
+        axis[3 * e + 0] = ax[0];
+        axis[3 * e + 1] = ax[1];
+        axis[3 * e + 2] = ax[2];
+    }
+}
+
+hipError_t launch_tag(long long nt, const double *coords, const int32_t *tets, int8_t *phase, double *axis,
+                      hipStream_t s) {
+    const long long g = (nt + 255) / 256;
+    tag_tets_kernel<<<(int)(g < 65535 ? (g < 1 ? 1 : g) : 65535), 256, 0, s>>>(nt, coords, tets, phase, axis);
+    return hipGetLastError();
+}
+
 hipError_t launch_generate(int n, double *coords, int32_t *tets, int8_t *phase, double *axis,
                            hipStream_t s) {
     const long long nv = (long long)(n + 1) * (n + 1) * (n + 1);

@@ -1,0 +1,937 @@
+// RVE homogenisation on a general conforming tet mesh of the box (order-2
+// hierarchic elements, Sec. 2, Eqs. eq_RVE_disc_Eqs, Eq_C_stress and
+// eq_homo_flux; the paper's own RVE is an unstructured mesh of the spline yarn
+// geometry, Sec. 1 and Table 1).
+//
+// The lattice path exploits the Kuhn lattice (implicit numbering, tile boxes,
+// nested coarse grids).  Here nothing is assumed about the connectivity: the
+// P2 unknowns are the mesh vertices and edges (numbered on the host), the
+// operator runs one thread per tet -- gather of its ten nodes, the same closed-
+// form element kernel as the lattice path (p2_apply), FP64 atomic scatter --
+// and PCG with the point-block Jacobi preconditioner runs in FP64 on the free
+// unknowns.  Linear Dirichlet: the boundary vertices and edges carry the linear
+// field (the fluctuation is zero there).  Periodic: the vertices and edges of
+// the faces x_d = hi_d are identified with their images on x_d = lo_d (the mesh
+// must have matching faces), and the class of the corner lo is pinned (the
+// translations; C_bar does not depend on the pin).  The homogenised matrices
+// are the energy form (1/V) (x_i + u_i)^T K (x_k + u_k); the plain volume
+// average of stress or flux, (1/V) x_i^T K (x_k + u_k), gives the Hill-Mandel
+// gap of the report.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+
+struct chom_urve {
+    int bc = 0;
+    chom_materials mat{};
+    chom_options opt{};
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, volume = 0.0;
+    long long nv = 0, nt = 0, nnode = 0, nslot = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    chom::DevBuf<int> conn;       // [nt][10] node ids (vertices, then edges in edge_verts order)
+    chom::DevBuf<int> smap;       // [nnode] unknown slot of the node (its master's), -1 if fixed
+    chom::DevBuf<double> geo;     // [nt][10] gradients of lambda_1..3 (rows) and |tet|
+    chom::DevBuf<double4> elem;   // [nt] fibre axis, phase
+    chom::DevBuf<double> vco;     // [nv][3] vertex coordinates relative to lo
+    // solve workspace (largest physics: 6 load cases x 3 components)
+    chom::DevBuf<double> x, r, z, p, q, b, minv, dg, vfull, wfull, acc;
+    chom::DevBuf<int> active;
+    ~chom_urve() {
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace chom {
+namespace {
+
+constexpr int UB = 128;   // threads per block of the tet and vector kernels
+
+struct UMat {
+    double m[2][5];   // [matrix, yarn][invariants of the transversely isotropic law]
+};
+
+// Per load case state of the PCG.
+struct UCol {
+    double rz, rz_new, pq, alpha, beta, eref, energy;
+    int done, iters;
+};
+
+// Linear field of load case r at a vertex (coordinates relative to lo): the
+// unit macro strain of Voigt entry r (engineering shear 1), or the unit
+// gradient along axis r for the scalar fields.
+template <int C>
+__device__ inline void lin_field(int r, const double y[3], double u[C]) {
+    if constexpr (C == 3) {
+        u[0] = u[1] = u[2] = 0.0;
+        if (r < 3) {
+            u[r] = y[r];
+        } else {
+            const int i = r == 3 ? 0 : (r == 4 ? 1 : 2), j = r == 3 ? 1 : (r == 4 ? 2 : 0);
+            u[i] = 0.5 * y[j];
+            u[j] = 0.5 * y[i];
+        }
+    } else {
+        u[0] = y[r];
+    }
+}
+
+__device__ inline double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+    return s;
+}
+
+// MODE 0: y[slots] += K x[slots] (CG operator; load cases with active[r] == 0
+// skipped).  MODE 1: y[slots] -= K x_lin (the right side of the fluctuation
+// problem; x_lin the linear field of the load case at the vertices, zero edge
+// coefficients) and energy[r] += x_lin.K x_lin.
+// MODE 2: y[nodes] += K x[nodes] (every node, for the averages).
+template <int C, int R, int MODE>
+__global__ __launch_bounds__(UB) void uop_kernel(long long nt, long long nnode, long long nv, long long nslot,
+                                                 const int *__restrict__ conn, const int *__restrict__ smap,
+                                                 const double *__restrict__ geo, const double4 *__restrict__ elem,
+                                                 const double *__restrict__ vco, UMat mat, const int *active,
+                                                 const double *__restrict__ x, double *y, double *energy) {
+    __shared__ double red[UB / 64];
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const bool live = e < nt;
+    int nd[10];
+    double g[4][3], vol = 0.0, a[3] = {0, 0, 0}, mloc[5] = {0, 0, 0, 0, 0};
+    if (live) {
+        for (int k = 0; k < 10; ++k) nd[k] = conn[e * 10 + k];
+        const double *gp = geo + e * 10;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) g[i + 1][j] = gp[3 * i + j];
+        for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
+        vol = gp[9];
+        const double4 ev = elem[e];
+        a[0] = ev.x;
+        a[1] = ev.y;
+        a[2] = ev.z;
+        const int ph = ev.w > 0.5 ? 1 : 0;
+        for (int k = 0; k < 5; ++k) mloc[k] = mat.m[ph][k];
+    }
+#pragma unroll 1
+    for (int r = 0; r < R; ++r) {
+        if (MODE == 0 && active != nullptr && active[r] == 0) continue;   // uniform over the grid
+        double en = 0.0;
+        if (live) {
+            double u[10][C], yv[10][C];
+            for (int k = 0; k < 10; ++k) {
+                if constexpr (MODE == 0) {
+                    const int s = smap[nd[k]];
+                    for (int c = 0; c < C; ++c) u[k][c] = s >= 0 ? x[((long long)r * nslot + s) * C + c] : 0.0;
+                } else if constexpr (MODE == 1) {
+                    if (nd[k] < nv) {
+                        const double yy[3] = {vco[3LL * nd[k]], vco[3LL * nd[k] + 1], vco[3LL * nd[k] + 2]};
+                        lin_field<C>(r, yy, u[k]);
+                    } else {
+                        for (int c = 0; c < C; ++c) u[k][c] = 0.0;
+                    }
+                } else {
+                    for (int c = 0; c < C; ++c) u[k][c] = x[((long long)r * nnode + nd[k]) * C + c];
+                }
+            }
+            p2_apply<double, C>(g, vol, a, mloc, u, yv);
+            for (int k = 0; k < 10; ++k) {
+                if constexpr (MODE == 2) {
+                    for (int c = 0; c < C; ++c) atomicAdd(&y[((long long)r * nnode + nd[k]) * C + c], yv[k][c]);
+                } else {
+                    const int s = smap[nd[k]];
+                    const double sg = MODE == 1 ? -1.0 : 1.0;
+                    if (s >= 0)
+                        for (int c = 0; c < C; ++c) atomicAdd(&y[((long long)r * nslot + s) * C + c], sg * yv[k][c]);
+                }
+                if constexpr (MODE == 1)
+                    for (int c = 0; c < C; ++c) en += u[k][c] * yv[k][c];
+            }
+        }
+        if constexpr (MODE == 1) {
+            const double s = block_sum(en, red);
+            if (threadIdx.x == 0) atomicAdd(&energy[r], s);
+        }
+    }
+}
+
+// Point blocks of diag(K) (packed xx yy zz xy yz xz for elasticity) of every
+// free unknown: vertex a: |e| Q(g_a); edge (a, b): (4/5)|e| [Q(g_a + g_b) +
+// Q(g_a) + Q(g_b)], Q(w) the element's quadratic form for a gradient w (the
+// integrals of the hierarchic basis products).
+template <int C>
+__global__ __launch_bounds__(UB) void udiag_kernel(long long nt, const int *__restrict__ conn,
+                                                   const int *__restrict__ smap, const double *__restrict__ geo,
+                                                   const double4 *__restrict__ elem, UMat mat, double *dg) {
+    constexpr int MS = C == 3 ? 6 : 1;
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= nt) return;
+    double g[4][3];
+    const double *gp = geo + e * 10;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) g[i + 1][j] = gp[3 * i + j];
+    for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
+    const double vol = gp[9];
+    const double4 ev = elem[e];
+    const double a[3] = {ev.x, ev.y, ev.z};
+    const int ph = ev.w > 0.5 ? 1 : 0;
+    double mloc[5];
+    for (int k = 0; k < 5; ++k) mloc[k] = mat.m[ph][k];
+    for (int k = 0; k < 10; ++k) {
+        const int s = smap[conn[e * 10 + k]];
+        if (s < 0) continue;
+        double ws[3][3], cs;
+        int nw;
+        if (k < 4) {
+            nw = 1;
+            for (int d = 0; d < 3; ++d) ws[0][d] = g[k][d];
+            cs = vol;
+        } else {
+            int a2, b2;
+            edge_verts(k - 4, a2, b2);
+            nw = 3;
+            for (int d = 0; d < 3; ++d) {
+                ws[0][d] = g[a2][d] + g[b2][d];
+                ws[1][d] = g[a2][d];
+                ws[2][d] = g[b2][d];
+            }
+            cs = 0.8 * vol;
+        }
+        if constexpr (C == 3) {
+            double acc[6] = {0, 0, 0, 0, 0, 0};
+            for (int q = 0; q < nw; ++q) {
+                double Q[3][3];
+                acoustic(ws[q], a, mloc, Q);
+                acc[0] += cs * Q[0][0];
+                acc[1] += cs * Q[1][1];
+                acc[2] += cs * Q[2][2];
+                acc[3] += cs * Q[0][1];
+                acc[4] += cs * Q[1][2];
+                acc[5] += cs * Q[0][2];
+            }
+            for (int v = 0; v < MS; ++v) atomicAdd(&dg[(long long)s * MS + v], acc[v]);
+        } else {
+            double acc = 0.0;
+            for (int q = 0; q < nw; ++q) {
+                double fl[3];
+                flux_ti<double>(ws[q], a, mloc, fl);
+                acc += cs * (fl[0] * ws[q][0] + fl[1] * ws[q][1] + fl[2] * ws[q][2]);
+            }
+            atomicAdd(&dg[s], acc);
+        }
+    }
+}
+
+// Inverses of the point blocks (symmetric 3 x 3 packed, or scalars).
+template <int C>
+__global__ __launch_bounds__(UB) void uinv_kernel(long long nslot, const double *dg, double *minv) {
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= nslot) return;
+    if constexpr (C == 3) {
+        const double *D = dg + s * 6;
+        const double a = D[0], b = D[1], c = D[2], xy = D[3], yz = D[4], xz = D[5];
+        const double c00 = b * c - yz * yz, c11 = a * c - xz * xz, c22 = a * b - xy * xy;
+        const double c01 = xz * yz - xy * c, c12 = xy * xz - a * yz, c02 = xy * yz - b * xz;
+        const double det = a * c00 + xy * c01 + xz * c02;
+        const double id = det > 0.0 ? 1.0 / det : 0.0;
+        double *M = minv + s * 6;
+        M[0] = c00 * id;
+        M[1] = c11 * id;
+        M[2] = c22 * id;
+        M[3] = c01 * id;
+        M[4] = c12 * id;
+        M[5] = c02 * id;
+    } else {
+        minv[s] = dg[s] > 0.0 ? 1.0 / dg[s] : 0.0;
+    }
+}
+
+template <int C>
+__device__ inline void apply_minv(const double *M, const double rv[C], double zv[C]) {
+    if constexpr (C == 3) {
+        zv[0] = M[0] * rv[0] + M[3] * rv[1] + M[5] * rv[2];
+        zv[1] = M[3] * rv[0] + M[1] * rv[1] + M[4] * rv[2];
+        zv[2] = M[5] * rv[0] + M[4] * rv[1] + M[2] * rv[2];
+    } else {
+        zv[0] = M[0] * rv[0];
+    }
+}
+
+// PCG vector kernels: grid (blocks over the slots, load case).  acc layout per
+// load case: [0] r.z, [1] p.q.
+template <int C>
+__global__ __launch_bounds__(UB) void ucg_init_kernel(long long nslot, const double *b, const double *minv, double *x,
+                                                      double *r, double *z, double *p, double *acc) {
+    __shared__ double red[UB / 64];
+    constexpr int MS = C == 3 ? 6 : 1;
+    const int lc = blockIdx.y;
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    double loc = 0.0;
+    if (s < nslot) {
+        const long long o = ((long long)lc * nslot + s) * C;
+        double rv[C], zv[C];
+        for (int c = 0; c < C; ++c) rv[c] = b[o + c];
+        apply_minv<C>(minv + s * MS, rv, zv);
+        for (int c = 0; c < C; ++c) {
+            x[o + c] = 0.0;
+            r[o + c] = rv[c];
+            z[o + c] = zv[c];
+            p[o + c] = zv[c];
+            loc += rv[c] * zv[c];
+        }
+    }
+    const double t = block_sum(loc, red);
+    if (threadIdx.x == 0) atomicAdd(&acc[2 * lc], t);
+}
+
+template <int C>
+__global__ __launch_bounds__(UB) void ucg_pq_kernel(long long nslot, const double *p, const double *q, const UCol *cols,
+                                                    double *acc) {
+    __shared__ double red[UB / 64];
+    const int lc = blockIdx.y;
+    if (cols[lc].done) return;   // uniform over the block
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    double loc = 0.0;
+    if (s < nslot) {
+        const long long o = ((long long)lc * nslot + s) * C;
+        for (int c = 0; c < C; ++c) loc += p[o + c] * q[o + c];
+    }
+    const double t = block_sum(loc, red);
+    if (threadIdx.x == 0) atomicAdd(&acc[2 * lc + 1], t);
+}
+
+template <int C>
+__global__ __launch_bounds__(UB) void ucg_update_kernel(long long nslot, const double *minv, const double *p,
+                                                        const double *q, const UCol *cols, double *x, double *r,
+                                                        double *z, double *acc) {
+    __shared__ double red[UB / 64];
+    constexpr int MS = C == 3 ? 6 : 1;
+    const int lc = blockIdx.y;
+    if (cols[lc].done) return;
+    const double al = cols[lc].alpha;
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    double loc = 0.0;
+    if (s < nslot) {
+        const long long o = ((long long)lc * nslot + s) * C;
+        double rv[C], zv[C];
+        for (int c = 0; c < C; ++c) {
+            x[o + c] += al * p[o + c];
+            rv[c] = r[o + c] - al * q[o + c];
+            r[o + c] = rv[c];
+        }
+        apply_minv<C>(minv + s * MS, rv, zv);
+        for (int c = 0; c < C; ++c) {
+            z[o + c] = zv[c];
+            loc += rv[c] * zv[c];
+        }
+    }
+    const double t = block_sum(loc, red);
+    if (threadIdx.x == 0) atomicAdd(&acc[2 * lc], t);
+}
+
+template <int C>
+__global__ __launch_bounds__(UB) void ucg_dir_kernel(long long nslot, const double *z, const UCol *cols, double *p) {
+    const int lc = blockIdx.y;
+    if (cols[lc].done) return;
+    const double be = cols[lc].beta;
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= nslot) return;
+    const long long o = ((long long)lc * nslot + s) * C;
+    for (int c = 0; c < C; ++c) p[o + c] = z[o + c] + be * p[o + c];
+}
+
+// Step length (phase 0) or new direction coefficient and the stopping test
+// (phase 1): r.z <= rtol^2 E, E the column's energy estimate (the linear-field
+// energy minus alpha r.z of every step, kept in [1e-6, 1] of the linear-field
+// energy).  One thread per load case; the sums are cleared for the next step.
+__global__ void ucg_finish_kernel(int R, int phase, double rtol2, int max_iter, UCol *cols, double *acc, int *active) {
+    const int lc = threadIdx.x;
+    if (lc >= R) return;
+    UCol &cs = cols[lc];
+    if (phase == 2) {   // start: r.z of the initial residual
+        cs.rz = acc[2 * lc];
+        acc[2 * lc] = 0.0;
+        cs.energy = cs.eref;
+        cs.iters = 0;
+        cs.done = (cs.rz <= rtol2 * cs.eref || !(cs.eref > 0.0)) ? 1 : 0;
+        if (!isfinite(cs.rz)) cs.done = 3;
+        active[lc] = cs.done ? 0 : 1;
+        return;
+    }
+    if (cs.done) {
+        acc[2 * lc] = acc[2 * lc + 1] = 0.0;
+        active[lc] = 0;
+        return;
+    }
+    if (phase == 0) {
+        cs.pq = acc[2 * lc + 1];
+        acc[2 * lc + 1] = 0.0;
+        if (!(cs.pq > 0.0) || !isfinite(cs.pq)) {
+            cs.done = isfinite(cs.pq) ? 2 : 3;   // breakdown / non-finite
+            cs.alpha = 0.0;
+            active[lc] = 0;
+        } else {
+            cs.alpha = cs.rz / cs.pq;
+        }
+        return;
+    }
+    const double rzn = acc[2 * lc];
+    acc[2 * lc] = 0.0;
+    cs.energy -= cs.alpha * cs.rz;
+    cs.iters += 1;
+    const double en = fmin(fmax(cs.energy, 1e-6 * cs.eref), cs.eref);
+    cs.beta = rzn / cs.rz;
+    cs.rz = rzn;
+    if (!isfinite(rzn)) cs.done = 3;
+    else if (rzn <= rtol2 * en) cs.done = 1;
+    else if (cs.iters >= max_iter) cs.done = 4;
+    active[lc] = cs.done ? 0 : 1;
+}
+
+// v = x_lin + u on every node (u read through the slot map; fixed nodes 0).
+template <int C, int R>
+__global__ __launch_bounds__(UB) void uexpand_kernel(long long nnode, long long nv, long long nslot,
+                                                     const int *smap, const double *vco, const double *x, double *v) {
+    const long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (nd >= nnode) return;
+    const int s = smap[nd];
+    for (int r = 0; r < R; ++r) {
+        double u[C];
+        if (nd < nv) {
+            const double yy[3] = {vco[3 * nd], vco[3 * nd + 1], vco[3 * nd + 2]};
+            lin_field<C>(r, yy, u);
+        } else {
+            for (int c = 0; c < C; ++c) u[c] = 0.0;
+        }
+        for (int c = 0; c < C; ++c)
+            v[((long long)r * nnode + nd) * C + c] = u[c] + (s >= 0 ? x[((long long)r * nslot + s) * C + c] : 0.0);
+    }
+}
+
+// out[i][k][0] += v_i . w_k (energy form), out[i][k][1] += x_lin,i . w_k (volume
+// average), w_k = K v_k on every node.
+template <int C, int R>
+__global__ __launch_bounds__(UB) void uavg_kernel(long long nnode, long long nv, const double *vco, const double *v,
+                                                  const double *w, double *out) {
+    __shared__ double red[UB / 64];
+    const long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    double vi[R][C], xl[R][C], wk[R][C];
+    for (int r = 0; r < R; ++r)
+        for (int c = 0; c < C; ++c) vi[r][c] = xl[r][c] = wk[r][c] = 0.0;
+    if (nd < nnode) {
+        for (int r = 0; r < R; ++r) {
+            for (int c = 0; c < C; ++c) {
+                vi[r][c] = v[((long long)r * nnode + nd) * C + c];
+                wk[r][c] = w[((long long)r * nnode + nd) * C + c];
+            }
+            if (nd < nv) {
+                const double yy[3] = {vco[3 * nd], vco[3 * nd + 1], vco[3 * nd + 2]};
+                lin_field<C>(r, yy, xl[r]);
+            }
+        }
+    }
+    for (int i = 0; i < R; ++i)
+        for (int k = 0; k < R; ++k) {
+            double e0 = 0.0, e1 = 0.0;
+            for (int c = 0; c < C; ++c) {
+                e0 += vi[i][c] * wk[k][c];
+                e1 += xl[i][c] * wk[k][c];
+            }
+            const double s0 = block_sum(e0, red);
+            const double s1 = block_sum(e1, red);
+            if (threadIdx.x == 0) {
+                atomicAdd(&out[(i * R + k) * 2], s0);
+                atomicAdd(&out[(i * R + k) * 2 + 1], s1);
+            }
+        }
+}
+
+int ufail(const std::string &msg, int code) {
+    set_error(msg);
+    return code;
+}
+
+int grid_of(long long n) { return (int)std::max<long long>(1, (n + UB - 1) / UB); }
+
+// One physics (C components, R load cases) for one record: PCG per load case,
+// then the energy-form matrix A [R][R] and the volume average Aavg.
+template <int C, int R>
+int usolve(chom_urve *U, const UMat &mat, double rtol, int max_iter, double *A, double *Aavg, int *iters,
+           double *resid, int *fail) {
+    hipStream_t s = U->stream;
+    const long long ns = U->nslot, nn = U->nnode, nt = U->nt, nv = U->nv;
+    constexpr int MS = C == 3 ? 6 : 1;
+    const size_t nvec = (size_t)R * ns * C;
+    DevBuf<UCol> cols;
+    CHOM_HIP(cols.ensure(R));
+    CHOM_HIP(hipMemsetAsync(cols.p, 0, sizeof(UCol) * R, s));
+    CHOM_HIP(hipMemsetAsync(U->acc.p, 0, sizeof(double) * U->acc.n, s));
+    // right sides b = -K x_lin (the fluctuation problems) and the linear-field energies
+    CHOM_HIP(hipMemsetAsync(U->b.p, 0, sizeof(double) * nvec, s));
+    double *eacc = U->acc.p + 2 * 6;   // after the CG sums
+    uop_kernel<C, R, 1><<<grid_of(nt), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
+                                                   U->vco.p, mat, nullptr, nullptr, U->b.p, eacc);
+    CHOM_HIP(hipGetLastError());
+    // point-block Jacobi
+    CHOM_HIP(hipMemsetAsync(U->dg.p, 0, sizeof(double) * ns * MS, s));
+    udiag_kernel<C><<<grid_of(nt), UB, 0, s>>>(nt, U->conn.p, U->smap.p, U->geo.p, U->elem.p, mat, U->dg.p);
+    uinv_kernel<C><<<grid_of(ns), UB, 0, s>>>(ns, U->dg.p, U->minv.p);
+    CHOM_HIP(hipGetLastError());
+    std::vector<double> heref(R);
+    CHOM_HIP(hipMemcpyAsync(heref.data(), eacc, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipStreamSynchronize(s));
+    std::vector<UCol> hc(R);
+    for (int k = 0; k < R; ++k) {
+        std::memset(&hc[k], 0, sizeof(UCol));
+        hc[k].eref = heref[k];
+    }
+    CHOM_HIP(hipMemcpyAsync(cols.p, hc.data(), sizeof(UCol) * R, hipMemcpyHostToDevice, s));
+    const dim3 gv(grid_of(ns), R);
+    const double rtol2 = rtol * rtol;
+    ucg_init_kernel<C><<<gv, UB, 0, s>>>(ns, U->b.p, U->minv.p, U->x.p, U->r.p, U->z.p, U->p.p, U->acc.p);
+    ucg_finish_kernel<<<1, 64, 0, s>>>(R, 2, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
+    CHOM_HIP(hipGetLastError());
+    std::vector<int> hact(R);
+    for (int it = 0; it < max_iter; it += 8) {
+        CHOM_HIP(hipMemcpyAsync(hact.data(), U->active.p, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+        CHOM_HIP(hipStreamSynchronize(s));
+        int any = 0;
+        for (int k = 0; k < R; ++k) any |= hact[k];
+        if (!any) break;
+        for (int j = 0; j < 8; ++j) {
+            CHOM_HIP(hipMemsetAsync(U->q.p, 0, sizeof(double) * nvec, s));
+            uop_kernel<C, R, 0><<<grid_of(nt), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
+                                                           U->vco.p, mat, U->active.p, U->p.p, U->q.p, nullptr);
+            ucg_pq_kernel<C><<<gv, UB, 0, s>>>(ns, U->p.p, U->q.p, cols.p, U->acc.p);
+            ucg_finish_kernel<<<1, 64, 0, s>>>(R, 0, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
+            ucg_update_kernel<C><<<gv, UB, 0, s>>>(ns, U->minv.p, U->p.p, U->q.p, cols.p, U->x.p, U->r.p, U->z.p,
+                                                   U->acc.p);
+            ucg_finish_kernel<<<1, 64, 0, s>>>(R, 1, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
+            ucg_dir_kernel<C><<<gv, UB, 0, s>>>(ns, U->z.p, cols.p, U->p.p);
+            CHOM_HIP(hipGetLastError());
+        }
+    }
+    CHOM_HIP(hipMemcpyAsync(hc.data(), cols.p, sizeof(UCol) * R, hipMemcpyDeviceToHost, s));
+    // averages: v = x_lin + u on every node, w = K v, A = v.w / V, Aavg = x_lin.w / V
+    const size_t nfull = (size_t)R * nn * C;
+    CHOM_HIP(hipMemsetAsync(U->wfull.p, 0, sizeof(double) * nfull, s));
+    uexpand_kernel<C, R><<<grid_of(nn), UB, 0, s>>>(nn, nv, ns, U->smap.p, U->vco.p, U->x.p, U->vfull.p);
+    uop_kernel<C, R, 2><<<grid_of(nt), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
+                                                   U->vco.p, mat, nullptr, U->vfull.p, U->wfull.p, nullptr);
+    double *aout = U->acc.p + 2 * 6 + 6;
+    CHOM_HIP(hipMemsetAsync(aout, 0, sizeof(double) * R * R * 2, s));
+    uavg_kernel<C, R><<<grid_of(nn), UB, 0, s>>>(nn, nv, U->vco.p, U->vfull.p, U->wfull.p, aout);
+    CHOM_HIP(hipGetLastError());
+    std::vector<double> ha(R * R * 2);
+    CHOM_HIP(hipMemcpyAsync(ha.data(), aout, sizeof(double) * R * R * 2, hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipStreamSynchronize(s));
+    int status = CHOM_OK;
+    for (int k = 0; k < R; ++k) {
+        iters[k] = hc[k].iters;
+        resid[k] = hc[k].eref > 0.0 ? std::sqrt(std::max(hc[k].rz, 0.0) / hc[k].eref) : 0.0;
+        fail[k] = hc[k].done == 1 ? CHOM_FAIL_NONE
+                : hc[k].done == 2 ? CHOM_FAIL_BREAKDOWN
+                : hc[k].done == 3 ? CHOM_FAIL_NONFINITE
+                                  : CHOM_FAIL_CAP;
+        if (hc[k].done != 1) status = CHOM_ENOCONV;
+    }
+    for (int i = 0; i < R * R; ++i) {
+        A[i] = ha[2 * i] / U->volume;
+        Aavg[i] = ha[2 * i + 1] / U->volume;
+    }
+    return status;
+}
+
+bool cholesky_ok(const double *A, int n) {
+    double L[6][6] = {};
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = 0.5 * (A[i * n + j] + A[j * n + i]);
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                L[i][i] = std::sqrt(s);
+            } else {
+                L[i][j] = s / L[j][j];
+            }
+        }
+    return true;
+}
+
+}  // namespace
+}  // namespace chom
+
+using namespace chom;
+
+extern "C" int chom_urve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t bc, const chom_options *opt,
+                                chom_urve **out) {
+    if (!mesh || !mat || !out) return ufail("chom_urve_create: null argument", CHOM_EINVAL);
+    *out = nullptr;
+    if (bc != CHOM_BC_DIRICHLET && bc != CHOM_BC_PERIODIC)
+        return ufail("chom_urve_create: general meshes take linear Dirichlet (0) or periodic (1) conditions",
+                     CHOM_EINVAL);
+    chom_options o;
+    chom_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision != CHOM_FP64 || !(o.rtol > 0) || o.max_iter < 1 || !(o.c_sat > 0))
+        return ufail("chom_urve_create: FP64 precision, rtol > 0, max_iter >= 1 and c_sat > 0 required", CHOM_EINVAL);
+    const long long nv = mesh->n_vertices, nt = mesh->n_tets;
+    if (nv < 4 || nt < 1 || !mesh->coords || !mesh->tets || !mesh->phase || !mesh->fibre_axis)
+        return ufail("chom_urve_create: empty mesh or null mesh array", CHOM_EINVAL);
+    for (int d = 0; d < 3; ++d)
+        if (!(mesh->hi[d] > mesh->lo[d])) return ufail("chom_urve_create: box must have hi > lo", CHOM_EMESH);
+    std::vector<double> hc(3 * nv), hax(3 * nt);
+    std::vector<int32_t> ht(4 * nt);
+    std::vector<int8_t> hph(nt);
+    if (mesh->on_device) {
+        CHOM_HIP(hipMemcpy(hc.data(), mesh->coords, sizeof(double) * 3 * nv, hipMemcpyDeviceToHost));
+        CHOM_HIP(hipMemcpy(ht.data(), mesh->tets, sizeof(int32_t) * 4 * nt, hipMemcpyDeviceToHost));
+        CHOM_HIP(hipMemcpy(hph.data(), mesh->phase, nt, hipMemcpyDeviceToHost));
+        CHOM_HIP(hipMemcpy(hax.data(), mesh->fibre_axis, sizeof(double) * 3 * nt, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(hc.data(), mesh->coords, sizeof(double) * 3 * nv);
+        std::memcpy(ht.data(), mesh->tets, sizeof(int32_t) * 4 * nt);
+        std::memcpy(hph.data(), mesh->phase, nt);
+        std::memcpy(hax.data(), mesh->fibre_axis, sizeof(double) * 3 * nt);
+    }
+    const double ext[3] = {mesh->hi[0] - mesh->lo[0], mesh->hi[1] - mesh->lo[1], mesh->hi[2] - mesh->lo[2]};
+    const double scale = std::max(ext[0], std::max(ext[1], ext[2]));
+    const double tol = 1e-9 * scale;
+    for (long long v = 0; v < nv; ++v)
+        for (int d = 0; d < 3; ++d)
+            if (!(hc[3 * v + d] >= mesh->lo[d] - tol && hc[3 * v + d] <= mesh->hi[d] + tol))
+                return ufail("chom_urve_create: vertex " + std::to_string(v) + " outside the box", CHOM_EMESH);
+    // geometry per tet, tags
+    std::vector<double> hgeo(10 * nt);
+    std::vector<double4> hel(nt);
+    double vsum = 0.0;
+    for (long long e = 0; e < nt; ++e) {
+        int v[4];
+        for (int a = 0; a < 4; ++a) {
+            v[a] = ht[4 * e + a];
+            if (v[a] < 0 || v[a] >= nv)
+                return ufail("chom_urve_create: tet " + std::to_string(e) + " has a vertex out of range", CHOM_EMESH);
+        }
+        double J[3][3];   // columns: edges from vertex 0
+        for (int d = 0; d < 3; ++d)
+            for (int k = 0; k < 3; ++k) J[d][k] = hc[3 * v[k + 1] + d] - hc[3 * v[0] + d];
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(std::fabs(det) > 1e-14 * scale * scale * scale))
+            return ufail("chom_urve_create: tet " + std::to_string(e) + " is degenerate", CHOM_EMESH);
+        const double id = 1.0 / det;
+        const double Ji[3][3] = {
+            {(J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id, (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id,
+             (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id},
+            {(J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id, (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id,
+             (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id},
+            {(J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id, (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id,
+             (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id}};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) hgeo[10 * e + 3 * i + j] = Ji[i][j];
+        hgeo[10 * e + 9] = std::fabs(det) / 6.0;
+        vsum += std::fabs(det) / 6.0;
+        if (hph[e] < 0 || hph[e] > 4) return ufail("chom_urve_create: phase must be in 0..4", CHOM_EMESH);
+        if (hph[e] > 0) {
+            const double nr = std::sqrt(hax[3 * e] * hax[3 * e] + hax[3 * e + 1] * hax[3 * e + 1] +
+                                        hax[3 * e + 2] * hax[3 * e + 2]);
+            if (!(std::fabs(nr - 1.0) < 1e-6))
+                return ufail("chom_urve_create: yarn fibre axis must be a unit vector", CHOM_EMESH);
+        }
+        hel[e] = make_double4(hax[3 * e], hax[3 * e + 1], hax[3 * e + 2], (double)hph[e]);
+    }
+    const double vbox = ext[0] * ext[1] * ext[2];
+    if (std::fabs(vsum - vbox) > 1e-9 * vbox)
+        return ufail("chom_urve_create: the tets do not fill the box (volume sum differs from the box volume)",
+                     CHOM_EMESH);
+    // P2 nodes: vertices, then the distinct edges
+    std::vector<std::tuple<int, int, long long>> ek;   // (min, max, tet*6 + local edge)
+    ek.reserve(6 * nt);
+    for (long long e = 0; e < nt; ++e)
+        for (int le = 0; le < 6; ++le) {
+            int a, b;
+            edge_verts(le, a, b);
+            const int va = ht[4 * e + a], vb = ht[4 * e + b];
+            ek.emplace_back(std::min(va, vb), std::max(va, vb), e * 6 + le);
+        }
+    std::sort(ek.begin(), ek.end());
+    std::vector<int> hconn(10 * nt);
+    std::vector<std::pair<int, int>> edges;
+    for (size_t i = 0; i < ek.size(); ++i) {
+        if (i == 0 || std::get<0>(ek[i]) != std::get<0>(ek[i - 1]) || std::get<1>(ek[i]) != std::get<1>(ek[i - 1]))
+            edges.emplace_back(std::get<0>(ek[i]), std::get<1>(ek[i]));
+        const long long key = std::get<2>(ek[i]);
+        hconn[10 * (key / 6) + 4 + key % 6] = (int)(nv + (long long)edges.size() - 1);
+    }
+    for (long long e = 0; e < nt; ++e)
+        for (int a = 0; a < 4; ++a) hconn[10 * e + a] = ht[4 * e + a];
+    const long long ne = (long long)edges.size(), nnode = nv + ne;
+    if (nnode * 18 >= (1LL << 31)) return ufail("chom_urve_create: mesh too large (limit 2^31 values)", CHOM_EINVAL);
+    // face membership of the vertices: bit 2d (lo face of axis d), bit 2d+1 (hi face)
+    std::vector<int> face(nv, 0);
+    for (long long v = 0; v < nv; ++v)
+        for (int d = 0; d < 3; ++d) {
+            if (std::fabs(hc[3 * v + d] - mesh->lo[d]) <= tol) face[v] |= 1 << (2 * d);
+            if (std::fabs(hc[3 * v + d] - mesh->hi[d]) <= tol) face[v] |= 1 << (2 * d + 1);
+        }
+    std::vector<long long> master(nnode);
+    for (long long i = 0; i < nnode; ++i) master[i] = i;
+    std::vector<char> fixed(nnode, 0);
+    if (bc == CHOM_BC_DIRICHLET) {
+        for (long long v = 0; v < nv; ++v) fixed[v] = face[v] != 0;
+        for (long long k = 0; k < ne; ++k)
+            fixed[nv + k] = (face[edges[k].first] & face[edges[k].second]) != 0;   // both ends on one face
+    } else {
+        // vertex images: every coordinate on a hi face moved to lo
+        std::map<std::tuple<long long, long long, long long>, long long> at;
+        // coordinates quantised to 1e-6 of the box (absorbs rounding)
+        const double qt = 1e-6 * scale;
+        auto qkey = [&](const double x[3]) {
+            return std::make_tuple(std::llround((x[0] - mesh->lo[0]) / qt), std::llround((x[1] - mesh->lo[1]) / qt),
+                                   std::llround((x[2] - mesh->lo[2]) / qt));
+        };
+        for (long long v = 0; v < nv; ++v) at[qkey(&hc[3 * v])] = v;
+        // the vertex at v moved to lo along the axes of `mask` (bit 2d + 1: hi face of axis d)
+        auto shifted = [&](long long v, int mask) -> long long {
+            double x[3] = {hc[3 * v], hc[3 * v + 1], hc[3 * v + 2]};
+            for (int d = 0; d < 3; ++d)
+                if ((mask >> (2 * d + 1)) & 1) x[d] = mesh->lo[d];
+            auto it = at.find(qkey(x));
+            return it == at.end() ? -1 : it->second;
+        };
+        const int HI = (1 << 1) | (1 << 3) | (1 << 5);
+        for (long long v = 0; v < nv; ++v) {
+            if (!(face[v] & HI)) continue;
+            master[v] = shifted(v, face[v] & HI);
+            if (master[v] < 0)
+                return ufail("chom_urve_create: periodic faces do not match (vertex " + std::to_string(v) +
+                                 " has no image)",
+                             CHOM_EMESH);
+        }
+        // an edge lying in hi faces is the image of the edge moved to lo along those
+        // faces' axes; every other edge (an edge into the interior included) is its own
+        std::map<std::pair<long long, long long>, long long> emap;
+        for (long long k = 0; k < ne; ++k) emap[{edges[k].first, edges[k].second}] = nv + k;
+        for (long long k = 0; k < ne; ++k) {
+            const int mask = face[edges[k].first] & face[edges[k].second] & HI;
+            if (!mask) continue;
+            const long long a = shifted(edges[k].first, mask), b = shifted(edges[k].second, mask);
+            auto it = (a < 0 || b < 0) ? emap.end() : emap.find({std::min(a, b), std::max(a, b)});
+            if (it == emap.end())
+                return ufail("chom_urve_create: periodic faces do not match (an edge has no image)", CHOM_EMESH);
+            master[nv + k] = it->second;
+        }
+        // pin the class of the corner lo
+        long long corner = -1;
+        for (long long v = 0; v < nv; ++v)
+            if ((face[v] & 0x15) == 0x15) corner = v;
+        if (corner < 0) return ufail("chom_urve_create: no vertex at the corner lo", CHOM_EMESH);
+        fixed[master[corner]] = 1;
+    }
+    std::vector<int> hsmap(nnode, -1);
+    long long ns = 0;
+    for (long long i = 0; i < nnode; ++i)
+        if (master[i] == i && !fixed[i]) hsmap[i] = (int)ns++;
+    for (long long i = 0; i < nnode; ++i)
+        if (master[i] != i) hsmap[i] = hsmap[master[i]];
+    if (ns < 1) return ufail("chom_urve_create: no free unknowns", CHOM_EMESH);
+    {
+        double m10[10], t4[4], d4[4];
+        if (chom_material_constants(mat, nullptr, o.c_sat, o.degrade_yarn, m10, t4, d4, nullptr) != CHOM_OK)
+            return CHOM_EMATERIAL;
+    }
+    std::unique_ptr<chom_urve> U(new chom_urve());
+    U->bc = bc;
+    U->mat = *mat;
+    U->opt = o;
+    for (int d = 0; d < 3; ++d) {
+        U->lo[d] = mesh->lo[d];
+        U->hi[d] = mesh->hi[d];
+    }
+    U->volume = vbox;
+    U->nv = nv;
+    U->nt = nt;
+    U->nnode = nnode;
+    U->nslot = ns;
+    if (o.hip_stream) {
+        U->stream = (hipStream_t)o.hip_stream;
+    } else {
+        CHOM_HIP(hipStreamCreateWithFlags(&U->stream, hipStreamNonBlocking));
+        U->own_stream = true;
+    }
+    std::vector<double> hv(3 * nv);
+    for (long long v = 0; v < nv; ++v)
+        for (int d = 0; d < 3; ++d) hv[3 * v + d] = hc[3 * v + d] - mesh->lo[d];
+    CHOM_HIP(U->conn.ensure(10 * nt));
+    CHOM_HIP(U->smap.ensure(nnode));
+    CHOM_HIP(U->geo.ensure(10 * nt));
+    CHOM_HIP(U->elem.ensure(nt));
+    CHOM_HIP(U->vco.ensure(3 * nv));
+    const size_t nvec = (size_t)6 * ns * 3, nfull = (size_t)6 * nnode * 3;
+    for (DevBuf<double> *b : {&U->x, &U->r, &U->z, &U->p, &U->q, &U->b}) CHOM_HIP(b->ensure(nvec));
+    CHOM_HIP(U->minv.ensure((size_t)ns * 6));
+    CHOM_HIP(U->dg.ensure((size_t)ns * 6));
+    CHOM_HIP(U->vfull.ensure(nfull));
+    CHOM_HIP(U->wfull.ensure(nfull));
+    CHOM_HIP(U->acc.ensure(2 * 6 + 6 + 6 * 6 * 2));
+    CHOM_HIP(U->active.ensure(6));
+    hipStream_t s = U->stream;
+    CHOM_HIP(hipMemcpyAsync(U->conn.p, hconn.data(), sizeof(int) * 10 * nt, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipMemcpyAsync(U->smap.p, hsmap.data(), sizeof(int) * nnode, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipMemcpyAsync(U->geo.p, hgeo.data(), sizeof(double) * 10 * nt, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipMemcpyAsync(U->elem.p, hel.data(), sizeof(double4) * nt, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipMemcpyAsync(U->vco.p, hv.data(), sizeof(double) * 3 * nv, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipStreamSynchronize(s));
+    *out = U.release();
+    return CHOM_OK;
+}
+
+extern "C" int chom_urve_sizes(const chom_urve *u, int64_t *n_nodes, int64_t *n_unknowns) {
+    if (!u) return ufail("chom_urve_sizes: null handle", CHOM_EINVAL);
+    if (n_nodes) *n_nodes = u->nnode;
+    if (n_unknowns) *n_unknowns = u->nslot;
+    return CHOM_OK;
+}
+
+extern "C" int chom_urve_homogenise(chom_urve *u, const chom_params *params, int32_t batch, double *C_hom,
+                                    double *K_hom, double *D_hom, chom_report *rep) {
+    if (!u || !params || batch < 1 || !C_hom || !K_hom || !D_hom)
+        return ufail("chom_urve_homogenise: null argument or batch < 1", CHOM_EINVAL);
+    const bool dev = u->opt.device_ptrs != 0;
+    std::vector<chom_params> hp(batch);
+    if (dev)
+        CHOM_HIP(hipMemcpy(hp.data(), params, sizeof(chom_params) * batch, hipMemcpyDeviceToHost));
+    else
+        std::memcpy(hp.data(), params, sizeof(chom_params) * batch);
+    std::vector<double> hC((size_t)batch * 21), hK((size_t)batch * 6), hD((size_t)batch * 6);
+    int status = CHOM_OK;
+    for (int i = 0; i < batch; ++i) {
+        double m10[10], t4[4], d4[4], keep = 1.0;
+        const int st = chom_material_constants(&u->mat, &hp[i], u->opt.c_sat, u->opt.degrade_yarn, m10, t4, d4, &keep);
+        if (st != CHOM_OK) return ufail("chom_urve_homogenise: record " + std::to_string(i) + ": " +
+                                            chom_last_error(), st);
+        UMat mm{}, mt{}, md{};
+        for (int ph = 0; ph < 2; ++ph) {
+            for (int k = 0; k < 5; ++k) mm.m[ph][k] = m10[5 * ph + k];
+            for (int k = 0; k < 2; ++k) {
+                mt.m[ph][k] = t4[2 * ph + k];
+                md.m[ph][k] = d4[2 * ph + k];
+            }
+        }
+        chom_report r;
+        std::memset(&r, 0, sizeof(r));
+        r.omega_keep = keep;
+        double A6[36], A6v[36], A3[9], A3v[9], B3[9], B3v[9];
+        int s1 = usolve<3, 6>(u, mm, u->opt.rtol, u->opt.max_iter, A6, A6v, r.iters, r.resid, r.fail);
+        if (s1 != CHOM_OK && s1 != CHOM_ENOCONV) return s1;
+        int s2 = usolve<1, 3>(u, mt, u->opt.rtol, u->opt.max_iter, A3, A3v, r.iters + 6, r.resid + 6, r.fail + 6);
+        if (s2 != CHOM_OK && s2 != CHOM_ENOCONV) return s2;
+        int s3 = usolve<1, 3>(u, md, u->opt.rtol, u->opt.max_iter, B3, B3v, r.iters + 9, r.resid + 9, r.fail + 9);
+        if (s3 != CHOM_OK && s3 != CHOM_ENOCONV) return s3;
+        r.status = (s1 == CHOM_OK && s2 == CHOM_OK && s3 == CHOM_OK) ? CHOM_OK : CHOM_ENOCONV;
+        if (r.status != CHOM_OK) status = CHOM_ENOCONV;
+        // symmetric parts, asymmetry, Hill-Mandel gap, SPD test
+        auto fro = [](const double *M, int n) {
+            double t = 0.0;
+            for (int q = 0; q < n * n; ++q) t += M[q] * M[q];
+            return std::sqrt(t);
+        };
+        double asym = 0.0, gap = 0.0;
+        for (auto blk : {std::make_tuple(A6, A6v, 6), std::make_tuple(A3, A3v, 3), std::make_tuple(B3, B3v, 3)}) {
+            double *M = std::get<0>(blk), *Mv = std::get<1>(blk);
+            const int n = std::get<2>(blk);
+            double da = 0.0, dg = 0.0;
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) {
+                    da += (M[a * n + b] - M[b * n + a]) * (M[a * n + b] - M[b * n + a]);
+                    dg += (M[a * n + b] - Mv[a * n + b]) * (M[a * n + b] - Mv[a * n + b]);
+                }
+            const double nm = fro(M, n);
+            if (n == 6) asym = std::sqrt(da) / nm;
+            gap = std::max(gap, std::sqrt(dg) / nm);
+            for (int a = 0; a < n; ++a)
+                for (int b = a + 1; b < n; ++b) M[a * n + b] = M[b * n + a] = 0.5 * (M[a * n + b] + M[b * n + a]);
+        }
+        r.asym = asym;
+        r.hill_mandel_gap = gap;
+        r.spd = (cholesky_ok(A6, 6) && cholesky_ok(A3, 3) && cholesky_ok(B3, 3)) ? 1 : 0;
+        for (int a = 0, q = 0; a < 6; ++a)
+            for (int b = a; b < 6; ++b, ++q) hC[(size_t)i * 21 + q] = A6[a * 6 + b];
+        const int id[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {1, 2}, {0, 2}};
+        for (int q = 0; q < 6; ++q) {
+            hK[(size_t)i * 6 + q] = A3[id[q][0] * 3 + id[q][1]];
+            hD[(size_t)i * 6 + q] = B3[id[q][0] * 3 + id[q][1]];
+        }
+        if (rep) rep[i] = r;
+    }
+    if (dev) {
+        CHOM_HIP(hipMemcpy(C_hom, hC.data(), sizeof(double) * hC.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(K_hom, hK.data(), sizeof(double) * hK.size(), hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(D_hom, hD.data(), sizeof(double) * hD.size(), hipMemcpyHostToDevice));
+    } else {
+        std::memcpy(C_hom, hC.data(), sizeof(double) * hC.size());
+        std::memcpy(K_hom, hK.data(), sizeof(double) * hK.size());
+        std::memcpy(D_hom, hD.data(), sizeof(double) * hD.size());
+    }
+    if (status != CHOM_OK) set_error("chom_urve_homogenise: a load case did not converge (results written)");
+    return status;
+}
+
+extern "C" void chom_urve_destroy(chom_urve *u) { delete u; }
+
+extern "C" int chom_tag_plain_weave(const double *coords, int64_t n_vertices, const int32_t *tets, int64_t n_tets,
+                                    int32_t device_ptrs, int8_t *phase, double *fibre_axis) {
+    if (!coords || !tets || !phase || !fibre_axis || n_vertices < 4 || n_tets < 1)
+        return ufail("chom_tag_plain_weave: null array or empty mesh", CHOM_EINVAL);
+    std::vector<int32_t> ht;
+    const int32_t *tt = tets;
+    if (!device_ptrs) {
+        ht.assign(tets, tets + 4 * n_tets);
+    } else {
+        ht.resize(4 * n_tets);
+        CHOM_HIP(hipMemcpy(ht.data(), tets, sizeof(int32_t) * 4 * n_tets, hipMemcpyDeviceToHost));
+    }
+    for (int64_t i = 0; i < 4 * n_tets; ++i)
+        if (ht[i] < 0 || ht[i] >= n_vertices) return ufail("chom_tag_plain_weave: vertex id out of range", CHOM_EMESH);
+    DevBuf<double> dc, da;
+    DevBuf<int32_t> dt;
+    DevBuf<int8_t> dp;
+    const double *c = coords;
+    double *ax = fibre_axis;
+    int8_t *ph = phase;
+    if (!device_ptrs) {
+        CHOM_HIP(dc.ensure(3 * n_vertices));
+        CHOM_HIP(dt.ensure(4 * n_tets));
+        CHOM_HIP(dp.ensure(n_tets));
+        CHOM_HIP(da.ensure(3 * n_tets));
+        CHOM_HIP(hipMemcpy(dc.p, coords, sizeof(double) * 3 * n_vertices, hipMemcpyHostToDevice));
+        CHOM_HIP(hipMemcpy(dt.p, ht.data(), sizeof(int32_t) * 4 * n_tets, hipMemcpyHostToDevice));
+        c = dc.p;
+        tt = dt.p;
+        ph = dp.p;
+        ax = da.p;
+    }
+    CHOM_HIP(launch_tag(n_tets, c, tt, ph, ax, nullptr));
+    CHOM_HIP(hipDeviceSynchronize());
+    if (!device_ptrs) {
+        CHOM_HIP(hipMemcpy(phase, dp.p, n_tets, hipMemcpyDeviceToHost));
+        CHOM_HIP(hipMemcpy(fibre_axis, da.p, sizeof(double) * 3 * n_tets, hipMemcpyDeviceToHost));
+    }
+    return CHOM_OK;
+}

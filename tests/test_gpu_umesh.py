@@ -1,0 +1,122 @@
+"""RVEs on general (unstructured) tet meshes on the GPU against the oracle.
+
+The meshes are seeded unstructured boxes (chom_inputs.unstructured_box: an
+extra vertex per cell, face diagonals by periodic id, jittered vertices) tagged
+by the synthetic weave.  The oracle solves the same discrete problem (Lagrange
+P2 on the same tets, sparse direct), so the FP64 GPU path at rtol 1e-12 meets
+it to 1e-9 in the three measures of the other parity tests.
+"""
+import numpy as np
+import pytest
+
+import chom_inputs as ci
+from gpu_util import banner, require_gpu, result_errors, upper21, upper6
+from oracle import fem, materials as M, mesh as omesh
+
+pytestmark = pytest.mark.gpu
+BC = {"dirichlet": fem.BC_DIRICHLET, "periodic": fem.BC_PERIODIC}
+
+
+def _weave(nc, seed):
+    coords, tets = ci.unstructured_box(nc, seed=seed)
+    c = omesh.centroids(coords, tets)
+    phase, axis = omesh.yarn_test(c[:, 0], c[:, 1], c[:, 2])
+    return coords, tets, phase, axis
+
+
+def _urve(coords, tets, phase, axis, bc, **kw):
+    from paper_1610_03484_amd import URVE
+    return URVE(coords, tets, phase, axis, ci.BASE_MATERIALS, bc=bc, rtol=1e-12, max_iter=20000, **kw)
+
+
+def test_tagger_on_an_unstructured_mesh_matches_oracle():
+    require_gpu()
+    from paper_1610_03484_amd import tag_plain_weave
+    coords, tets = ci.unstructured_box(6, seed=7)
+    ph, ax = tag_plain_weave(coords, tets)
+    c = omesh.centroids(coords, tets)
+    ph_o, ax_o = omesh.yarn_test(c[:, 0], c[:, 1], c[:, 2])
+    ties = omesh.yarn_margin(c[:, 0], c[:, 1], c[:, 2]) < 1e-12
+    banner(f"tagger: {len(tets)} tets, {(ph_o > 0).sum()} yarn tets, {ties.sum()} exact ties excluded")
+    assert ties.sum() <= 0.01 * len(tets)
+    assert np.array_equal(ph[~ties], ph_o[~ties])
+    assert np.abs(ax[~ties] - ax_o[~ties]).max() <= 1e-14
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic"])
+def test_unstructured_rve_matches_oracle(bc):
+    require_gpu()
+    coords, tets, phase, axis = _weave(3, seed=5)
+    params = ci.draw_params(11, 2)
+    u = _urve(coords, tets, phase, axis, bc)
+    nn, nu = u.sizes()
+    C, K, D, rep = u.homogenise(params)
+    u.close()
+    banner(f"unstructured {bc}: {len(tets)} tets, {nn} P2 nodes, {nu} free nodes; CG steps "
+           f"{[r['iters'] for r in rep]}")
+    d = fem.Discretisation(coords, tets, 2)
+    for i, p in enumerate(params):
+        ref = fem.homogenise(coords, tets, phase, axis, 2, BC[bc], ci.BASE_MATERIALS, p, disc=d)
+        e = result_errors(C[i], K[i], D[i], upper21(ref["C"]), upper6(ref["K"]), upper6(ref["D"]))
+        banner(f"  record {i}: keep {rep[i]['omega_keep']:.3e} errors {e}, Hill-Mandel gap "
+               f"{rep[i]['hill_mandel_gap']:.1e}")
+        assert max(e) <= 1e-9
+        assert rep[i]["status"] == 0 and rep[i]["spd"] == 1
+        assert rep[i]["hill_mandel_gap"] <= 1e-8 and rep[i]["asym"] <= 1e-9
+        assert abs(rep[i]["omega_keep"] - ref["omega_keep"]) <= 1e-14
+
+
+def test_unstructured_periodic_larger_mesh_matches_oracle():
+    require_gpu()
+    coords, tets, phase, axis = _weave(5, seed=6)
+    params = ci.draw_params(12, 1)
+    u = _urve(coords, tets, phase, axis, "periodic")
+    C, K, D, rep = u.homogenise(params)
+    u.close()
+    ref = fem.homogenise(coords, tets, phase, axis, 2, fem.BC_PERIODIC, ci.BASE_MATERIALS, params[0],
+                         method="substitution")
+    e = result_errors(C[0], K[0], D[0], upper21(ref["C"]), upper6(ref["K"]), upper6(ref["D"]))
+    banner(f"unstructured periodic {len(tets)} tets: errors {e}, CG steps {rep[0]['iters']}")
+    assert max(e) <= 1e-9
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic"])
+def test_homogeneous_unstructured_rve_returns_its_material(bc):
+    require_gpu()
+    coords, tets = ci.unstructured_box(3, seed=8)
+    phase = np.zeros(len(tets), np.int8)
+    axis = np.zeros((len(tets), 3))
+    rec = ci.draw_params(13, 1)
+    u = _urve(coords, tets, phase, axis, bc)
+    C, K, D, _ = u.homogenise(rec)
+    u.close()
+    m, _, _ = M.phase_materials(ci.BASE_MATERIALS, rec[0])
+    Cm = M.isotropic_stiffness(m["E"], m["nu"])
+    assert np.abs(C[0] - upper21(Cm)).max() <= 1e-10 * np.abs(Cm).max()
+    assert np.abs(K[0] - m["k"] * np.array([1, 1, 1, 0, 0, 0])).max() <= 1e-10 * m["k"]
+    assert np.abs(D[0] - m["D"] * np.array([1, 1, 1, 0, 0, 0])).max() <= 1e-10 * m["D"]
+
+
+def test_unstructured_rve_rejects_bad_meshes_and_options():
+    require_gpu()
+    from paper_1610_03484_amd import _lib as L
+    coords, tets, phase, axis = _weave(2, seed=9)
+    for kw, bc in ((dict(precision="fp32_refined"), "periodic"), ({}, "neumann")):
+        with pytest.raises(L.ChomError) as ei:
+            _urve(coords, tets, phase, axis, bc, **kw)
+        assert ei.value.status == L.CHOM_EINVAL
+    bad = coords.copy()
+    onface = np.flatnonzero(np.isclose(bad[:, 0], 1.0) & (bad[:, 1] > 0.01) & (bad[:, 1] < 0.99)
+                            & (bad[:, 2] > 0.01) & (bad[:, 2] < 0.99))
+    bad[onface[0], 1] += 0.01                       # a hi-face vertex without its image
+    with pytest.raises(L.ChomError) as ei:
+        _urve(bad, tets, phase, axis, "periodic")
+    assert ei.value.status == L.CHOM_EMESH
+    with pytest.raises(L.ChomError) as ei:
+        _urve(coords, tets[:-1], phase[:-1], axis[:-1], "dirichlet")   # a hole: the tets do not fill the box
+    assert ei.value.status == L.CHOM_EMESH
+    t2 = tets.copy()
+    t2[0, 1] = t2[0, 0]                              # degenerate tet
+    with pytest.raises(L.ChomError) as ei:
+        _urve(coords, t2, phase, axis, "dirichlet")
+    assert ei.value.status == L.CHOM_EMESH
