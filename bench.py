@@ -29,6 +29,8 @@ Also measured, outside the timed region, into `config`:
     change of C_bar against the analytic centreline tangent;
   * the FE^2 outer loop on an 8 x 8 x 2 macro box (768 Gauss points, an 8^3
     RVE solve at each per step): time per macro step;
+  * an RVE on a general (unstructured) tet mesh of 8,748 tets: time per
+    homogenisation against the lattice path's 12^3 RVE;
   * roofline of the dominant kernel (the FP32 mechanical operator on the batch),
     from HIP events on the library's stream.
 `cpu_baseline`: the oracle on host cores, on the 8^3 records of the batch.
@@ -425,6 +427,46 @@ def fe2_surrogate(rve, sur, torch):
                 note="host-timed chom_fe2_run calls")
 
 
+def unstructured_leg(args, torch):
+    """A general (unstructured) tet mesh of the paper's RVE size class: the 9 x 9 x 9
+    cell box with a vertex per cell (8,748 tets, chom_inputs.unstructured_box), tagged
+    by the synthetic weave on the GPU, periodic, FP64 PCG (point-block Jacobi) on the
+    element-batched operator; time per homogenisation (12 load cases) over four
+    degraded records, against the lattice path's 12^3 RVE (10,368 tets) in FP64 with
+    the same preconditioner and tolerance."""
+    import chom_inputs as ci
+    from paper_1610_03484_amd import RVE, URVE, generate_plain_weave, tag_plain_weave
+    coords, tets = ci.unstructured_box(9, seed=0)
+    phase, axis = tag_plain_weave(coords, tets)
+    params = ci.draw_params(0, 4)
+    u = URVE(coords, tets, phase, axis, ci.BASE_MATERIALS, bc="periodic", rtol=args.rtol, max_iter=50000)
+    nn, nu = u.sizes()
+    u.homogenise(params[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, rep = u.homogenise(params)
+    dt = (time.perf_counter() - t0) / len(params)
+    u.close()
+    lat = RVE(*generate_plain_weave(12, device="cuda:0"), ci.BASE_MATERIALS, bc="periodic", precision="fp64",
+              precond="block_jacobi", rtol=args.rtol, max_iter=50000)
+    lat.homogenise(params[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, rep_l = lat.homogenise(params)
+    dt_l = (time.perf_counter() - t0) / len(params)
+    lat.close()
+    its = [max(r["iters"][:6]) for r in rep]
+    log(f"unstructured 8,748-tet periodic RVE: {dt * 1e3:.1f} ms per homogenisation (max mechanical CG steps "
+        f"{max(its)}); lattice 12^3 FP64 block Jacobi {dt_l * 1e3:.1f} ms")
+    return dict(mesh="unstructured box, 9^3 cells + a vertex per cell, 8,748 tets (seed 0), synthetic weave tags",
+                p2_nodes=int(nn), free_nodes=int(nu), bc="periodic", precision="fp64", precond="block_jacobi",
+                rtol=args.rtol, ms_per_homogenisation=dt * 1e3, rate=1.0 / dt, max_mech_cg_steps=int(max(its)),
+                hill_mandel_gap_max=float(max(r["hill_mandel_gap"] for r in rep)),
+                lattice_12cubed_fp64_block_jacobi_ms=dt_l * 1e3,
+                lattice_12cubed_max_mech_cg_steps=int(max(max(r["iters"][:6]) for r in rep_l)),
+                note="host-timed chom_urve_homogenise, records one after the other")
+
+
 def c0_plain(args, torch):
     """C0: 8^3 linear-Dirichlet FP64, one record per call; error against a fresh oracle solve."""
     import chom_inputs as ci
@@ -592,6 +634,9 @@ def run_c2(args, torch):
         log(f"yarn directions 24^3: {flow['ms_per_call']:.2f} ms per call, mean angle to the tangent "
             f"{flow['mean_angle_to_tangent_deg']:.1f} deg, C_bar change {flow['c_hom_change_vs_tangent']}")
 
+    # ---- general (unstructured) mesh
+    umesh = None if args.no_umesh else unstructured_leg(args, torch)
+
     # ---- FE^2 outer loop
     fe2 = None if args.no_fe2 else fe2_leg(args, torch)
     if fe2:
@@ -651,7 +696,7 @@ def run_c2(args, torch):
                    "surrogate": sur,
                    "speedup_surrogate_over_plain": (sur["speedup_vs_plain_12cubed"] if sur else None),
                    "damage_history_kernel": dmg, "yarn_directions_potential_flow": flow,
-                   "fe2_outer_loop": fe2},
+                   "fe2_outer_loop": fe2, "unstructured_rve": umesh},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -747,6 +792,7 @@ def main():
     ap.add_argument("--no-damage", action="store_true", help="c2: skip the damage-history kernel leg")
     ap.add_argument("--no-flow", action="store_true", help="c2: skip the potential-flow yarn-direction leg")
     ap.add_argument("--no-fe2", action="store_true", help="skip the FE^2 outer-loop legs")
+    ap.add_argument("--no-umesh", action="store_true", help="c2: skip the unstructured-mesh leg")
     ap.add_argument("--items", type=int, default=512, help="items of the c2 batch (c3: 64 unless set)")
     ap.add_argument("--precond", default="two_level", choices=["block_jacobi", "two_level"],
                     help="CG preconditioner (two_level: block Jacobi plus a P1 multigrid coarse correction)")
