@@ -103,6 +103,7 @@ __device__ inline double block_sum(double v, double *red) {
 // problem; x_lin the linear field of the load case at the vertices, zero edge
 // coefficients) and energy[r] += x_lin.K x_lin.
 // MODE 2: y[nodes] += K x[nodes] (every node, for the averages).
+// Grid: (blocks over the tets, load cases), one thread per (tet, load case).
 template <int C, int R, int MODE>
 __global__ __launch_bounds__(UB) void uop_kernel(long long nt, long long nnode, long long nv, long long nslot,
                                                  const int *__restrict__ conn, const int *__restrict__ smap,
@@ -110,6 +111,8 @@ __global__ __launch_bounds__(UB) void uop_kernel(long long nt, long long nnode, 
                                                  const double *__restrict__ vco, UMat mat, const int *active,
                                                  const double *__restrict__ x, double *y, double *energy) {
     __shared__ double red[UB / 64];
+    const int r = blockIdx.y;
+    if (MODE == 0 && active != nullptr && active[r] == 0) return;   // uniform over the block
     const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const bool live = e < nt;
     int nd[10];
@@ -128,9 +131,7 @@ __global__ __launch_bounds__(UB) void uop_kernel(long long nt, long long nnode, 
         const int ph = ev.w > 0.5 ? 1 : 0;
         for (int k = 0; k < 5; ++k) mloc[k] = mat.m[ph][k];
     }
-#pragma unroll 1
-    for (int r = 0; r < R; ++r) {
-        if (MODE == 0 && active != nullptr && active[r] == 0) continue;   // uniform over the grid
+    {
         double en = 0.0;
         if (live) {
             double u[10][C], yv[10][C];
@@ -484,7 +485,7 @@ int usolve(chom_urve *U, const UMat &mat, double rtol, int max_iter, double *A, 
     // right sides b = -K x_lin (the fluctuation problems) and the linear-field energies
     CHOM_HIP(hipMemsetAsync(U->b.p, 0, sizeof(double) * nvec, s));
     double *eacc = U->acc.p + 2 * 6;   // after the CG sums
-    uop_kernel<C, R, 1><<<grid_of(nt), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
+    uop_kernel<C, R, 1><<<dim3(grid_of(nt), R), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
                                                    U->vco.p, mat, nullptr, nullptr, U->b.p, eacc);
     CHOM_HIP(hipGetLastError());
     // point-block Jacobi
@@ -515,7 +516,7 @@ int usolve(chom_urve *U, const UMat &mat, double rtol, int max_iter, double *A, 
         if (!any) break;
         for (int j = 0; j < 8; ++j) {
             CHOM_HIP(hipMemsetAsync(U->q.p, 0, sizeof(double) * nvec, s));
-            uop_kernel<C, R, 0><<<grid_of(nt), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
+            uop_kernel<C, R, 0><<<dim3(grid_of(nt), R), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
                                                            U->vco.p, mat, U->active.p, U->p.p, U->q.p, nullptr);
             ucg_pq_kernel<C><<<gv, UB, 0, s>>>(ns, U->p.p, U->q.p, cols.p, U->acc.p);
             ucg_finish_kernel<<<1, 64, 0, s>>>(R, 0, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
@@ -531,7 +532,7 @@ int usolve(chom_urve *U, const UMat &mat, double rtol, int max_iter, double *A, 
     const size_t nfull = (size_t)R * nn * C;
     CHOM_HIP(hipMemsetAsync(U->wfull.p, 0, sizeof(double) * nfull, s));
     uexpand_kernel<C, R><<<grid_of(nn), UB, 0, s>>>(nn, nv, ns, U->smap.p, U->vco.p, U->x.p, U->vfull.p);
-    uop_kernel<C, R, 2><<<grid_of(nt), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
+    uop_kernel<C, R, 2><<<dim3(grid_of(nt), R), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
                                                    U->vco.p, mat, nullptr, U->vfull.p, U->wfull.p, nullptr);
     double *aout = U->acc.p + 2 * 6 + 6;
     CHOM_HIP(hipMemsetAsync(aout, 0, sizeof(double) * R * R * 2, s));
