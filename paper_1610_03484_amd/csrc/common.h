@@ -99,7 +99,7 @@ struct Prob {
     long long eoff;       // orders 3, 4: offset of its element factors (values)
     long long moff;       // offset of its coarse-hierarchy points (two-level preconditioner)
     int geo;              // index of its RVE geometry
-    int pad_;
+    int mg_sweeps;        // coarsest-level sweeps of the two-level preconditioner (0: the class's count)
 };
 
 // First constraint row used by a BC: periodic uses only int(phi) (row 3).

@@ -860,6 +860,7 @@ __global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_kernel(const Geo *geos, 
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
     if (G.mg_nlev < 2) return;
+    if (P.mg_sweeps > 0) sweeps = P.mg_sweeps;
     const int lc = G.mg_nlev - 1;   // 1: the n/2 grid itself is the coarsest
     const int tid = threadIdx.x, nt = blockDim.x;
     T *smem = (T *)mg_smem;
@@ -1007,6 +1008,7 @@ __global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_small_kernel(const Geo *
     const Prob &P = probs[prob];
     const Geo &G = geos[P.geo];
     if (G.mg_nlev < 2) return;
+    if (P.mg_sweeps > 0) sweeps = P.mg_sweeps;
     const int lc = G.mg_nlev - 1;   // 1, 2 or 3 (checked on the host)
     const int tid = threadIdx.x;
     const Lev V1 = level_of(G, 1);
