@@ -115,6 +115,12 @@ OP_TRAFFIC_BYTES = {
     "c2": {1: 7952610802, 2: 8208382168, 3: 7050862621},
 }
 
+# VALU wave-instructions of one all-active launch of op_p2_kernel<float,3,6,2> on the
+# mixed batch (rocprofv3 SQ_INSTS_VALU, profiles/op_p2_mech_fp32_512_mixed_valu.md);
+# re-measure (or remove) whenever that kernel changes.
+OP_VALU_INSTS = {"c2": {2: 1.71849e9}}
+SIMDS, CLOCK_HZ = 1024, 2.4e9
+
 CAL_BYTES = 256 << 20
 
 
@@ -313,6 +319,13 @@ def roofline_mech(batch, sizes_or_n, nprob_items, fp32, args, workload, order=2)
         kname = f"op_p2_kernel<{'float' if fp32 else 'double'},3,6,{rg}>"
     roof.update(kernel=kname, avg_launch_us=ms * 1e3, algorithmic_bytes=bytes_, algorithmic_flops=flops,
                 hbm_frac=(bytes_ / t) / HBM_PEAK, problems_per_launch=nprob)
+    valu = OP_VALU_INSTS.get(workload, {}).get(rg) if (fp32 and order == 2) else None
+    if valu:
+        # measured issue: a wave64 VALU instruction holds a SIMD for 4 cycles
+        roof.update(valu_issue_frac=valu * 4 / (t * CLOCK_HZ * SIMDS),
+                    valu_note="measured VALU issue against 1,024 SIMDs at 2.4 GHz; the kernel is issue bound, "
+                              "the gap to frac 0.5 of the packed-FP32 peak is the dense-element flop count's "
+                              "(packed FP32 is disabled at compile time)")
     log(f"operator: {ms * 1e3:.1f} us/launch, {bytes_ / t / 1e9:.0f} GB/s algorithmic, "
         f"{flops / t / 1e12:.2f} TFLOP/s algorithmic")
     return roof
