@@ -35,7 +35,7 @@ Also measured, outside the timed region, into `config`:
     from HIP events on the library's stream.
 `cpu_baseline`: the oracle on host cores, on the 8^3 records of the batch.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c0|c3|c4]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c0|c3|c4|umesh|fe2]
 """
 from __future__ import annotations
 
@@ -73,6 +73,12 @@ WORKLOADS = {
                     "FP32 accumulate) trained on 12^3 plain-weave RVE solves (p=2, periodic, degraded records "
                     "as in the batched workload), evaluated on 1,000,000 records with RVE fallback where the "
                     "ensemble disagreement exceeds 1e-2"),
+    "umesh": dict(n=None, bcs=("periodic",), precision="fp64",
+                  desc="general (unstructured) tet mesh: 9^3-cell box with a vertex per cell, 8,748 tets, synthetic "
+                       "weave tags, periodic, FP64 PCG with point-block Jacobi, 12 load cases, four degraded records"),
+    "fe2": dict(n=8, bcs=("periodic",), precision="fp32_refined",
+                desc="FE^2 outer loop: 8 x 8 x 2 macro box (768 Gauss points), 8^3 periodic RVE solve per Gauss point "
+                     "and step (FP32 operator + FP64 refinement), four implicit steps of 0.25 years"),
     "c3": dict(n=16, bcs=("periodic",), precision="fp32_refined",
                desc="p-refinement: batch of 16^3 Kuhn plain-weave RVEs (24,576 tets each) at order p (3: 352,947, "
                     "4: 823,875 elastic DOFs), periodic, degraded records as in the batched workload, element "
@@ -790,6 +796,23 @@ def run_c4(args, torch):
     print(json.dumps(line))
 
 
+def run_leg(args, torch):
+    """--workload umesh | fe2: the unstructured-mesh or FE^2 leg of the default line on its own."""
+    if args.workload == "umesh":
+        leg = unstructured_leg(args, torch)
+        value, unit, metric = leg["rate"], "homogenisations/s", "RVE homogenisations/s (12 load cases), general tet mesh"
+        ms = leg["ms_per_homogenisation"]
+    else:
+        leg = fe2_leg(args, torch)
+        value, unit, metric = 1e3 / leg["ms_per_macro_step"], "macro steps/s", "FE^2 macro steps/s (768 Gauss points)"
+        ms = leg["ms_per_macro_step"]
+    line = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if args.workload == "umesh" else "f32+f64", "data": "synthetic",
+            "config": {"workload": WORKLOADS[args.workload]["desc"], **leg}, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -838,6 +861,8 @@ def main():
         run_c2(args, torch)
     elif args.workload == "c4":
         run_c4(args, torch)
+    elif args.workload in ("umesh", "fe2"):
+        run_leg(args, torch)
     else:
         run_single(args, WORKLOADS[args.workload], torch)
 
