@@ -45,7 +45,7 @@ struct chom_urve {
     chom::DevBuf<double> geo;     // [nt][10] gradients of lambda_1..3 (rows) and |tet|
     chom::DevBuf<double4> elem;   // [nt] fibre axis, phase
     chom::DevBuf<double> vco;     // [nv][3] vertex coordinates relative to lo
-    // solve workspace (largest physics: 6 load cases x 3 components)
+    // solve workspace, sized on first use for the largest chunk of records
     chom::DevBuf<double> x, r, z, p, q, b, minv, dg, vfull, wfull, acc;
     chom::DevBuf<int> active;
     ~chom_urve() {
@@ -56,7 +56,8 @@ struct chom_urve {
 namespace chom {
 namespace {
 
-constexpr int UB = 128;   // threads per block of the tet and vector kernels
+constexpr int UB = 128;          // threads per block of the tet and vector kernels
+constexpr int URVE_CHUNK = 16;   // records per solve (their load cases share every launch)
 
 struct UMat {
     double m[2][5];   // [matrix, yarn][invariants of the transversely isotropic law]
@@ -98,88 +99,91 @@ __device__ inline double block_sum(double v, double *red) {
     return s;
 }
 
-// MODE 0: y[slots] += K x[slots] (CG operator; load cases with active[r] == 0
+// Columns: (record, load case) pairs, column = record * R + load case; every
+// vector is [column][slot or node][component] and each record has its own
+// materials (mats[record]).
+// MODE 0: y[slots] += K x[slots] (CG operator; columns with active[col] == 0
 // skipped).  MODE 1: y[slots] -= K x_lin (the right side of the fluctuation
 // problem; x_lin the linear field of the load case at the vertices, zero edge
-// coefficients) and energy[r] += x_lin.K x_lin.
+// coefficients) and energy[col] += x_lin.K x_lin.
 // MODE 2: y[nodes] += K x[nodes] (every node, for the averages).
-// Grid: (blocks over the tets, load cases), one thread per (tet, load case).
+// Grid: (blocks over the tets, columns), one thread per (tet, column).
 template <int C, int R, int MODE>
 __global__ __launch_bounds__(UB) void uop_kernel(long long nt, long long nnode, long long nv, long long nslot,
                                                  const int *__restrict__ conn, const int *__restrict__ smap,
                                                  const double *__restrict__ geo, const double4 *__restrict__ elem,
-                                                 const double *__restrict__ vco, UMat mat, const int *active,
-                                                 const double *__restrict__ x, double *y, double *energy) {
+                                                 const double *__restrict__ vco, const UMat *__restrict__ mats,
+                                                 const int *active, const double *__restrict__ x, double *y,
+                                                 double *energy) {
     __shared__ double red[UB / 64];
-    const int r = blockIdx.y;
-    if (MODE == 0 && active != nullptr && active[r] == 0) return;   // uniform over the block
+    const int col = blockIdx.y, r = col % R, rec = col / R;
+    if (MODE == 0 && active != nullptr && active[col] == 0) return;   // uniform over the block
     const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const bool live = e < nt;
-    int nd[10];
-    double g[4][3], vol = 0.0, a[3] = {0, 0, 0}, mloc[5] = {0, 0, 0, 0, 0};
+    double en = 0.0;
     if (live) {
+        int nd[10];
+        double g[4][3], a[3], mloc[5];
         for (int k = 0; k < 10; ++k) nd[k] = conn[e * 10 + k];
         const double *gp = geo + e * 10;
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) g[i + 1][j] = gp[3 * i + j];
         for (int j = 0; j < 3; ++j) g[0][j] = -(g[1][j] + g[2][j] + g[3][j]);
-        vol = gp[9];
+        const double vol = gp[9];
         const double4 ev = elem[e];
         a[0] = ev.x;
         a[1] = ev.y;
         a[2] = ev.z;
         const int ph = ev.w > 0.5 ? 1 : 0;
-        for (int k = 0; k < 5; ++k) mloc[k] = mat.m[ph][k];
+        for (int k = 0; k < 5; ++k) mloc[k] = mats[rec].m[ph][k];
+        double u[10][C], yv[10][C];
+        for (int k = 0; k < 10; ++k) {
+            if constexpr (MODE == 0) {
+                const int sl = smap[nd[k]];
+                for (int c = 0; c < C; ++c) u[k][c] = sl >= 0 ? x[((long long)col * nslot + sl) * C + c] : 0.0;
+            } else if constexpr (MODE == 1) {
+                if (nd[k] < nv) {
+                    const double yy[3] = {vco[3LL * nd[k]], vco[3LL * nd[k] + 1], vco[3LL * nd[k] + 2]};
+                    lin_field<C>(r, yy, u[k]);
+                } else {
+                    for (int c = 0; c < C; ++c) u[k][c] = 0.0;
+                }
+            } else {
+                for (int c = 0; c < C; ++c) u[k][c] = x[((long long)col * nnode + nd[k]) * C + c];
+            }
+        }
+        p2_apply<double, C>(g, vol, a, mloc, u, yv);
+        for (int k = 0; k < 10; ++k) {
+            if constexpr (MODE == 2) {
+                for (int c = 0; c < C; ++c) atomicAdd(&y[((long long)col * nnode + nd[k]) * C + c], yv[k][c]);
+            } else {
+                const int sl = smap[nd[k]];
+                const double sg = MODE == 1 ? -1.0 : 1.0;
+                if (sl >= 0)
+                    for (int c = 0; c < C; ++c) atomicAdd(&y[((long long)col * nslot + sl) * C + c], sg * yv[k][c]);
+            }
+            if constexpr (MODE == 1)
+                for (int c = 0; c < C; ++c) en += u[k][c] * yv[k][c];
+        }
     }
-    {
-        double en = 0.0;
-        if (live) {
-            double u[10][C], yv[10][C];
-            for (int k = 0; k < 10; ++k) {
-                if constexpr (MODE == 0) {
-                    const int s = smap[nd[k]];
-                    for (int c = 0; c < C; ++c) u[k][c] = s >= 0 ? x[((long long)r * nslot + s) * C + c] : 0.0;
-                } else if constexpr (MODE == 1) {
-                    if (nd[k] < nv) {
-                        const double yy[3] = {vco[3LL * nd[k]], vco[3LL * nd[k] + 1], vco[3LL * nd[k] + 2]};
-                        lin_field<C>(r, yy, u[k]);
-                    } else {
-                        for (int c = 0; c < C; ++c) u[k][c] = 0.0;
-                    }
-                } else {
-                    for (int c = 0; c < C; ++c) u[k][c] = x[((long long)r * nnode + nd[k]) * C + c];
-                }
-            }
-            p2_apply<double, C>(g, vol, a, mloc, u, yv);
-            for (int k = 0; k < 10; ++k) {
-                if constexpr (MODE == 2) {
-                    for (int c = 0; c < C; ++c) atomicAdd(&y[((long long)r * nnode + nd[k]) * C + c], yv[k][c]);
-                } else {
-                    const int s = smap[nd[k]];
-                    const double sg = MODE == 1 ? -1.0 : 1.0;
-                    if (s >= 0)
-                        for (int c = 0; c < C; ++c) atomicAdd(&y[((long long)r * nslot + s) * C + c], sg * yv[k][c]);
-                }
-                if constexpr (MODE == 1)
-                    for (int c = 0; c < C; ++c) en += u[k][c] * yv[k][c];
-            }
-        }
-        if constexpr (MODE == 1) {
-            const double s = block_sum(en, red);
-            if (threadIdx.x == 0) atomicAdd(&energy[r], s);
-        }
+    if constexpr (MODE == 1) {
+        const double t = block_sum(en, red);
+        if (threadIdx.x == 0) atomicAdd(&energy[col], t);
     }
 }
 
 // Point blocks of diag(K) (packed xx yy zz xy yz xz for elasticity) of every
-// free unknown: vertex a: |e| Q(g_a); edge (a, b): (4/5)|e| [Q(g_a + g_b) +
-// Q(g_a) + Q(g_b)], Q(w) the element's quadratic form for a gradient w (the
-// integrals of the hierarchic basis products).
+// free unknown, per record (grid: blocks over the tets, records): vertex a:
+// |e| Q(g_a); edge (a, b): (4/5)|e| [Q(g_a + g_b) + Q(g_a) + Q(g_b)], Q(w) the
+// element's quadratic form for a gradient w (the integrals of the hierarchic
+// basis products).
 template <int C>
-__global__ __launch_bounds__(UB) void udiag_kernel(long long nt, const int *__restrict__ conn,
+__global__ __launch_bounds__(UB) void udiag_kernel(long long nt, long long nslot, const int *__restrict__ conn,
                                                    const int *__restrict__ smap, const double *__restrict__ geo,
-                                                   const double4 *__restrict__ elem, UMat mat, double *dg) {
+                                                   const double4 *__restrict__ elem, const UMat *__restrict__ mats,
+                                                   double *dg) {
     constexpr int MS = C == 3 ? 6 : 1;
+    const int rec = blockIdx.y;
     const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (e >= nt) return;
     double g[4][3];
@@ -192,10 +196,11 @@ __global__ __launch_bounds__(UB) void udiag_kernel(long long nt, const int *__re
     const double a[3] = {ev.x, ev.y, ev.z};
     const int ph = ev.w > 0.5 ? 1 : 0;
     double mloc[5];
-    for (int k = 0; k < 5; ++k) mloc[k] = mat.m[ph][k];
+    for (int k = 0; k < 5; ++k) mloc[k] = mats[rec].m[ph][k];
+    double *dr = dg + (long long)rec * nslot * MS;
     for (int k = 0; k < 10; ++k) {
-        const int s = smap[conn[e * 10 + k]];
-        if (s < 0) continue;
+        const int sl = smap[conn[e * 10 + k]];
+        if (sl < 0) continue;
         double ws[3][3], cs;
         int nw;
         if (k < 4) {
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(UB) void udiag_kernel(long long nt, const int *__re
                 acc[4] += cs * Q[1][2];
                 acc[5] += cs * Q[0][2];
             }
-            for (int v = 0; v < MS; ++v) atomicAdd(&dg[(long long)s * MS + v], acc[v]);
+            for (int v = 0; v < MS; ++v) atomicAdd(&dr[(long long)sl * MS + v], acc[v]);
         } else {
             double acc = 0.0;
             for (int q = 0; q < nw; ++q) {
@@ -233,16 +238,16 @@ __global__ __launch_bounds__(UB) void udiag_kernel(long long nt, const int *__re
                 flux_ti<double>(ws[q], a, mloc, fl);
                 acc += cs * (fl[0] * ws[q][0] + fl[1] * ws[q][1] + fl[2] * ws[q][2]);
             }
-            atomicAdd(&dg[s], acc);
+            atomicAdd(&dr[sl], acc);
         }
     }
 }
 
-// Inverses of the point blocks (symmetric 3 x 3 packed, or scalars).
+// Inverses of the point blocks (symmetric 3 x 3 packed, or scalars), n = records x slots.
 template <int C>
-__global__ __launch_bounds__(UB) void uinv_kernel(long long nslot, const double *dg, double *minv) {
+__global__ __launch_bounds__(UB) void uinv_kernel(long long n, const double *dg, double *minv) {
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (s >= nslot) return;
+    if (s >= n) return;
     if constexpr (C == 3) {
         const double *D = dg + s * 6;
         const double a = D[0], b = D[1], c = D[2], xy = D[3], yz = D[4], xz = D[5];
@@ -273,21 +278,22 @@ __device__ inline void apply_minv(const double *M, const double rv[C], double zv
     }
 }
 
-// PCG vector kernels: grid (blocks over the slots, load case).  acc layout per
-// load case: [0] r.z, [1] p.q.
-template <int C>
+// PCG vector kernels: grid (blocks over the slots, columns); the column's record
+// is column / R (its preconditioner blocks).  acc layout per column: [0] r.z,
+// [1] p.q.
+template <int C, int R>
 __global__ __launch_bounds__(UB) void ucg_init_kernel(long long nslot, const double *b, const double *minv, double *x,
                                                       double *r, double *z, double *p, double *acc) {
     __shared__ double red[UB / 64];
     constexpr int MS = C == 3 ? 6 : 1;
-    const int lc = blockIdx.y;
+    const int lc = blockIdx.y, rec = lc / R;
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     double loc = 0.0;
     if (s < nslot) {
         const long long o = ((long long)lc * nslot + s) * C;
         double rv[C], zv[C];
         for (int c = 0; c < C; ++c) rv[c] = b[o + c];
-        apply_minv<C>(minv + s * MS, rv, zv);
+        apply_minv<C>(minv + ((long long)rec * nslot + s) * MS, rv, zv);
         for (int c = 0; c < C; ++c) {
             x[o + c] = 0.0;
             r[o + c] = rv[c];
@@ -316,13 +322,13 @@ __global__ __launch_bounds__(UB) void ucg_pq_kernel(long long nslot, const doubl
     if (threadIdx.x == 0) atomicAdd(&acc[2 * lc + 1], t);
 }
 
-template <int C>
+template <int C, int R>
 __global__ __launch_bounds__(UB) void ucg_update_kernel(long long nslot, const double *minv, const double *p,
                                                         const double *q, const UCol *cols, double *x, double *r,
                                                         double *z, double *acc) {
     __shared__ double red[UB / 64];
     constexpr int MS = C == 3 ? 6 : 1;
-    const int lc = blockIdx.y;
+    const int lc = blockIdx.y, rec = lc / R;
     if (cols[lc].done) return;
     const double al = cols[lc].alpha;
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -335,7 +341,7 @@ __global__ __launch_bounds__(UB) void ucg_update_kernel(long long nslot, const d
             rv[c] = r[o + c] - al * q[o + c];
             r[o + c] = rv[c];
         }
-        apply_minv<C>(minv + s * MS, rv, zv);
+        apply_minv<C>(minv + ((long long)rec * nslot + s) * MS, rv, zv);
         for (int c = 0; c < C; ++c) {
             z[o + c] = zv[c];
             loc += rv[c] * zv[c];
@@ -359,10 +365,11 @@ __global__ __launch_bounds__(UB) void ucg_dir_kernel(long long nslot, const doub
 // Step length (phase 0) or new direction coefficient and the stopping test
 // (phase 1): r.z <= rtol^2 E, E the column's energy estimate (the linear-field
 // energy minus alpha r.z of every step, kept in [1e-6, 1] of the linear-field
-// energy).  One thread per load case; the sums are cleared for the next step.
-__global__ void ucg_finish_kernel(int R, int phase, double rtol2, int max_iter, UCol *cols, double *acc, int *active) {
-    const int lc = threadIdx.x;
-    if (lc >= R) return;
+// energy).  One thread per column; the sums are cleared for the next step.
+__global__ __launch_bounds__(UB) void ucg_finish_kernel(int ncol, int phase, double rtol2, int max_iter, UCol *cols,
+                                                        double *acc, int *active) {
+    const int lc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (lc >= ncol) return;
     UCol &cs = cols[lc];
     if (phase == 2) {   // start: r.z of the initial residual
         cs.rz = acc[2 * lc];
@@ -404,41 +411,43 @@ __global__ void ucg_finish_kernel(int R, int phase, double rtol2, int max_iter, 
     active[lc] = cs.done ? 0 : 1;
 }
 
-// v = x_lin + u on every node (u read through the slot map; fixed nodes 0).
+// v = x_lin + u on every node for column blockIdx.y (u read through the slot
+// map; fixed nodes 0).
 template <int C, int R>
 __global__ __launch_bounds__(UB) void uexpand_kernel(long long nnode, long long nv, long long nslot,
                                                      const int *smap, const double *vco, const double *x, double *v) {
+    const int col = blockIdx.y, r = col % R;
     const long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (nd >= nnode) return;
     const int s = smap[nd];
-    for (int r = 0; r < R; ++r) {
-        double u[C];
-        if (nd < nv) {
-            const double yy[3] = {vco[3 * nd], vco[3 * nd + 1], vco[3 * nd + 2]};
-            lin_field<C>(r, yy, u);
-        } else {
-            for (int c = 0; c < C; ++c) u[c] = 0.0;
-        }
-        for (int c = 0; c < C; ++c)
-            v[((long long)r * nnode + nd) * C + c] = u[c] + (s >= 0 ? x[((long long)r * nslot + s) * C + c] : 0.0);
+    double u[C];
+    if (nd < nv) {
+        const double yy[3] = {vco[3 * nd], vco[3 * nd + 1], vco[3 * nd + 2]};
+        lin_field<C>(r, yy, u);
+    } else {
+        for (int c = 0; c < C; ++c) u[c] = 0.0;
     }
+    for (int c = 0; c < C; ++c)
+        v[((long long)col * nnode + nd) * C + c] = u[c] + (s >= 0 ? x[((long long)col * nslot + s) * C + c] : 0.0);
 }
 
-// out[i][k][0] += v_i . w_k (energy form), out[i][k][1] += x_lin,i . w_k (volume
-// average), w_k = K v_k on every node.
+// Per record (blockIdx.y): out[rec][i][k][0] += v_i . w_k (energy form),
+// out[rec][i][k][1] += x_lin,i . w_k (volume average), w_k = K v_k on every node.
 template <int C, int R>
 __global__ __launch_bounds__(UB) void uavg_kernel(long long nnode, long long nv, const double *vco, const double *v,
                                                   const double *w, double *out) {
     __shared__ double red[UB / 64];
+    const int rec = blockIdx.y;
     const long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     double vi[R][C], xl[R][C], wk[R][C];
     for (int r = 0; r < R; ++r)
         for (int c = 0; c < C; ++c) vi[r][c] = xl[r][c] = wk[r][c] = 0.0;
     if (nd < nnode) {
         for (int r = 0; r < R; ++r) {
+            const long long o = ((long long)(rec * R + r) * nnode + nd) * C;
             for (int c = 0; c < C; ++c) {
-                vi[r][c] = v[((long long)r * nnode + nd) * C + c];
-                wk[r][c] = w[((long long)r * nnode + nd) * C + c];
+                vi[r][c] = v[o + c];
+                wk[r][c] = w[o + c];
             }
             if (nd < nv) {
                 const double yy[3] = {vco[3 * nd], vco[3 * nd + 1], vco[3 * nd + 2]};
@@ -446,6 +455,7 @@ __global__ __launch_bounds__(UB) void uavg_kernel(long long nnode, long long nv,
             }
         }
     }
+    double *orec = out + (long long)rec * R * R * 2;
     for (int i = 0; i < R; ++i)
         for (int k = 0; k < R; ++k) {
             double e0 = 0.0, e1 = 0.0;
@@ -456,8 +466,8 @@ __global__ __launch_bounds__(UB) void uavg_kernel(long long nnode, long long nv,
             const double s0 = block_sum(e0, red);
             const double s1 = block_sum(e1, red);
             if (threadIdx.x == 0) {
-                atomicAdd(&out[(i * R + k) * 2], s0);
-                atomicAdd(&out[(i * R + k) * 2 + 1], s1);
+                atomicAdd(&orec[(i * R + k) * 2], s0);
+                atomicAdd(&orec[(i * R + k) * 2 + 1], s1);
             }
         }
 }
@@ -469,80 +479,96 @@ int ufail(const std::string &msg, int code) {
 
 int grid_of(long long n) { return (int)std::max<long long>(1, (n + UB - 1) / UB); }
 
-// One physics (C components, R load cases) for one record: PCG per load case,
-// then the energy-form matrix A [R][R] and the volume average Aavg.
+// One physics (C components, R load cases) for nb records at once (column =
+// record * R + load case): PCG per column, then per record the energy-form
+// matrix A [R][R] and the volume average Aavg (outputs [nb][R][R]; iters,
+// resid, fail [nb][R]).
 template <int C, int R>
-int usolve(chom_urve *U, const UMat &mat, double rtol, int max_iter, double *A, double *Aavg, int *iters,
+int usolve(chom_urve *U, const UMat *hmats, int nb, double rtol, int max_iter, double *A, double *Aavg, int *iters,
            double *resid, int *fail) {
     hipStream_t s = U->stream;
     const long long ns = U->nslot, nn = U->nnode, nt = U->nt, nv = U->nv;
     constexpr int MS = C == 3 ? 6 : 1;
-    const size_t nvec = (size_t)R * ns * C;
+    const int ncol = nb * R;
+    const size_t nvec = (size_t)ncol * ns * C, nfull = (size_t)ncol * nn * C;
+    for (DevBuf<double> *b : {&U->x, &U->r, &U->z, &U->p, &U->q, &U->b}) CHOM_HIP(b->ensure(nvec));
+    CHOM_HIP(U->minv.ensure((size_t)nb * ns * MS));
+    CHOM_HIP(U->dg.ensure((size_t)nb * ns * MS));
+    CHOM_HIP(U->vfull.ensure(nfull));
+    CHOM_HIP(U->wfull.ensure(nfull));
+    const size_t nacc = (size_t)3 * ncol + (size_t)nb * R * R * 2;
+    CHOM_HIP(U->acc.ensure(nacc));
+    CHOM_HIP(U->active.ensure(ncol));
     DevBuf<UCol> cols;
-    CHOM_HIP(cols.ensure(R));
-    CHOM_HIP(hipMemsetAsync(cols.p, 0, sizeof(UCol) * R, s));
-    CHOM_HIP(hipMemsetAsync(U->acc.p, 0, sizeof(double) * U->acc.n, s));
+    DevBuf<UMat> mats;
+    CHOM_HIP(cols.ensure(ncol));
+    CHOM_HIP(mats.ensure(nb));
+    CHOM_HIP(hipMemcpyAsync(mats.p, hmats, sizeof(UMat) * nb, hipMemcpyHostToDevice, s));
+    CHOM_HIP(hipMemsetAsync(U->acc.p, 0, sizeof(double) * nacc, s));
     // right sides b = -K x_lin (the fluctuation problems) and the linear-field energies
     CHOM_HIP(hipMemsetAsync(U->b.p, 0, sizeof(double) * nvec, s));
-    double *eacc = U->acc.p + 2 * 6;   // after the CG sums
-    uop_kernel<C, R, 1><<<dim3(grid_of(nt), R), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
-                                                   U->vco.p, mat, nullptr, nullptr, U->b.p, eacc);
+    double *eacc = U->acc.p + 2 * ncol;   // after the CG sums
+    uop_kernel<C, R, 1><<<dim3(grid_of(nt), ncol), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p,
+                                                               U->elem.p, U->vco.p, mats.p, nullptr, nullptr, U->b.p,
+                                                               eacc);
     CHOM_HIP(hipGetLastError());
-    // point-block Jacobi
-    CHOM_HIP(hipMemsetAsync(U->dg.p, 0, sizeof(double) * ns * MS, s));
-    udiag_kernel<C><<<grid_of(nt), UB, 0, s>>>(nt, U->conn.p, U->smap.p, U->geo.p, U->elem.p, mat, U->dg.p);
-    uinv_kernel<C><<<grid_of(ns), UB, 0, s>>>(ns, U->dg.p, U->minv.p);
+    // point-block Jacobi per record
+    CHOM_HIP(hipMemsetAsync(U->dg.p, 0, sizeof(double) * nb * ns * MS, s));
+    udiag_kernel<C><<<dim3(grid_of(nt), nb), UB, 0, s>>>(nt, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p, mats.p,
+                                                         U->dg.p);
+    uinv_kernel<C><<<grid_of((long long)nb * ns), UB, 0, s>>>((long long)nb * ns, U->dg.p, U->minv.p);
     CHOM_HIP(hipGetLastError());
-    std::vector<double> heref(R);
-    CHOM_HIP(hipMemcpyAsync(heref.data(), eacc, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    std::vector<double> heref(ncol);
+    CHOM_HIP(hipMemcpyAsync(heref.data(), eacc, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
     CHOM_HIP(hipStreamSynchronize(s));
-    std::vector<UCol> hc(R);
-    for (int k = 0; k < R; ++k) {
+    std::vector<UCol> hc(ncol);
+    for (int k = 0; k < ncol; ++k) {
         std::memset(&hc[k], 0, sizeof(UCol));
         hc[k].eref = heref[k];
     }
-    CHOM_HIP(hipMemcpyAsync(cols.p, hc.data(), sizeof(UCol) * R, hipMemcpyHostToDevice, s));
-    const dim3 gv(grid_of(ns), R);
+    CHOM_HIP(hipMemcpyAsync(cols.p, hc.data(), sizeof(UCol) * ncol, hipMemcpyHostToDevice, s));
+    const dim3 gv(grid_of(ns), ncol);
+    const int gf = (ncol + UB - 1) / UB;
     const double rtol2 = rtol * rtol;
-    ucg_init_kernel<C><<<gv, UB, 0, s>>>(ns, U->b.p, U->minv.p, U->x.p, U->r.p, U->z.p, U->p.p, U->acc.p);
-    ucg_finish_kernel<<<1, 64, 0, s>>>(R, 2, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
+    ucg_init_kernel<C, R><<<gv, UB, 0, s>>>(ns, U->b.p, U->minv.p, U->x.p, U->r.p, U->z.p, U->p.p, U->acc.p);
+    ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 2, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
     CHOM_HIP(hipGetLastError());
-    std::vector<int> hact(R);
+    std::vector<int> hact(ncol);
     for (int it = 0; it < max_iter; it += 8) {
-        CHOM_HIP(hipMemcpyAsync(hact.data(), U->active.p, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+        CHOM_HIP(hipMemcpyAsync(hact.data(), U->active.p, sizeof(int) * ncol, hipMemcpyDeviceToHost, s));
         CHOM_HIP(hipStreamSynchronize(s));
         int any = 0;
-        for (int k = 0; k < R; ++k) any |= hact[k];
+        for (int k = 0; k < ncol; ++k) any |= hact[k];
         if (!any) break;
         for (int j = 0; j < 8; ++j) {
             CHOM_HIP(hipMemsetAsync(U->q.p, 0, sizeof(double) * nvec, s));
-            uop_kernel<C, R, 0><<<dim3(grid_of(nt), R), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
-                                                           U->vco.p, mat, U->active.p, U->p.p, U->q.p, nullptr);
+            uop_kernel<C, R, 0><<<dim3(grid_of(nt), ncol), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p,
+                                                                       U->geo.p, U->elem.p, U->vco.p, mats.p,
+                                                                       U->active.p, U->p.p, U->q.p, nullptr);
             ucg_pq_kernel<C><<<gv, UB, 0, s>>>(ns, U->p.p, U->q.p, cols.p, U->acc.p);
-            ucg_finish_kernel<<<1, 64, 0, s>>>(R, 0, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
-            ucg_update_kernel<C><<<gv, UB, 0, s>>>(ns, U->minv.p, U->p.p, U->q.p, cols.p, U->x.p, U->r.p, U->z.p,
-                                                   U->acc.p);
-            ucg_finish_kernel<<<1, 64, 0, s>>>(R, 1, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
+            ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 0, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
+            ucg_update_kernel<C, R><<<gv, UB, 0, s>>>(ns, U->minv.p, U->p.p, U->q.p, cols.p, U->x.p, U->r.p, U->z.p,
+                                                      U->acc.p);
+            ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 1, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
             ucg_dir_kernel<C><<<gv, UB, 0, s>>>(ns, U->z.p, cols.p, U->p.p);
             CHOM_HIP(hipGetLastError());
         }
     }
-    CHOM_HIP(hipMemcpyAsync(hc.data(), cols.p, sizeof(UCol) * R, hipMemcpyDeviceToHost, s));
+    CHOM_HIP(hipMemcpyAsync(hc.data(), cols.p, sizeof(UCol) * ncol, hipMemcpyDeviceToHost, s));
     // averages: v = x_lin + u on every node, w = K v, A = v.w / V, Aavg = x_lin.w / V
-    const size_t nfull = (size_t)R * nn * C;
     CHOM_HIP(hipMemsetAsync(U->wfull.p, 0, sizeof(double) * nfull, s));
-    uexpand_kernel<C, R><<<grid_of(nn), UB, 0, s>>>(nn, nv, ns, U->smap.p, U->vco.p, U->x.p, U->vfull.p);
-    uop_kernel<C, R, 2><<<dim3(grid_of(nt), R), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p, U->elem.p,
-                                                   U->vco.p, mat, nullptr, U->vfull.p, U->wfull.p, nullptr);
-    double *aout = U->acc.p + 2 * 6 + 6;
-    CHOM_HIP(hipMemsetAsync(aout, 0, sizeof(double) * R * R * 2, s));
-    uavg_kernel<C, R><<<grid_of(nn), UB, 0, s>>>(nn, nv, U->vco.p, U->vfull.p, U->wfull.p, aout);
+    uexpand_kernel<C, R><<<dim3(grid_of(nn), ncol), UB, 0, s>>>(nn, nv, ns, U->smap.p, U->vco.p, U->x.p, U->vfull.p);
+    uop_kernel<C, R, 2><<<dim3(grid_of(nt), ncol), UB, 0, s>>>(nt, nn, nv, ns, U->conn.p, U->smap.p, U->geo.p,
+                                                               U->elem.p, U->vco.p, mats.p, nullptr, U->vfull.p,
+                                                               U->wfull.p, nullptr);
+    double *aout = U->acc.p + 3 * ncol;
+    uavg_kernel<C, R><<<dim3(grid_of(nn), nb), UB, 0, s>>>(nn, nv, U->vco.p, U->vfull.p, U->wfull.p, aout);
     CHOM_HIP(hipGetLastError());
-    std::vector<double> ha(R * R * 2);
-    CHOM_HIP(hipMemcpyAsync(ha.data(), aout, sizeof(double) * R * R * 2, hipMemcpyDeviceToHost, s));
+    std::vector<double> ha((size_t)nb * R * R * 2);
+    CHOM_HIP(hipMemcpyAsync(ha.data(), aout, sizeof(double) * ha.size(), hipMemcpyDeviceToHost, s));
     CHOM_HIP(hipStreamSynchronize(s));
     int status = CHOM_OK;
-    for (int k = 0; k < R; ++k) {
+    for (int k = 0; k < ncol; ++k) {
         iters[k] = hc[k].iters;
         resid[k] = hc[k].eref > 0.0 ? std::sqrt(std::max(hc[k].rz, 0.0) / hc[k].eref) : 0.0;
         fail[k] = hc[k].done == 1 ? CHOM_FAIL_NONE
@@ -551,7 +577,7 @@ int usolve(chom_urve *U, const UMat &mat, double rtol, int max_iter, double *A, 
                                   : CHOM_FAIL_CAP;
         if (hc[k].done != 1) status = CHOM_ENOCONV;
     }
-    for (int i = 0; i < R * R; ++i) {
+    for (size_t i = 0; i < (size_t)nb * R * R; ++i) {
         A[i] = ha[2 * i] / U->volume;
         Aavg[i] = ha[2 * i + 1] / U->volume;
     }
@@ -784,14 +810,6 @@ extern "C" int chom_urve_create(const chom_mesh *mesh, const chom_materials *mat
     CHOM_HIP(U->geo.ensure(10 * nt));
     CHOM_HIP(U->elem.ensure(nt));
     CHOM_HIP(U->vco.ensure(3 * nv));
-    const size_t nvec = (size_t)6 * ns * 3, nfull = (size_t)6 * nnode * 3;
-    for (DevBuf<double> *b : {&U->x, &U->r, &U->z, &U->p, &U->q, &U->b}) CHOM_HIP(b->ensure(nvec));
-    CHOM_HIP(U->minv.ensure((size_t)ns * 6));
-    CHOM_HIP(U->dg.ensure((size_t)ns * 6));
-    CHOM_HIP(U->vfull.ensure(nfull));
-    CHOM_HIP(U->wfull.ensure(nfull));
-    CHOM_HIP(U->acc.ensure(2 * 6 + 6 + 6 * 6 * 2));
-    CHOM_HIP(U->active.ensure(6));
     hipStream_t s = U->stream;
     CHOM_HIP(hipMemcpyAsync(U->conn.p, hconn.data(), sizeof(int) * 10 * nt, hipMemcpyHostToDevice, s));
     CHOM_HIP(hipMemcpyAsync(U->smap.p, hsmap.data(), sizeof(int) * nnode, hipMemcpyHostToDevice, s));
@@ -822,64 +840,97 @@ extern "C" int chom_urve_homogenise(chom_urve *u, const chom_params *params, int
         std::memcpy(hp.data(), params, sizeof(chom_params) * batch);
     std::vector<double> hC((size_t)batch * 21), hK((size_t)batch * 6), hD((size_t)batch * 6);
     int status = CHOM_OK;
-    for (int i = 0; i < batch; ++i) {
-        double m10[10], t4[4], d4[4], keep = 1.0;
-        const int st = chom_material_constants(&u->mat, &hp[i], u->opt.c_sat, u->opt.degrade_yarn, m10, t4, d4, &keep);
-        if (st != CHOM_OK) return ufail("chom_urve_homogenise: record " + std::to_string(i) + ": " +
-                                            chom_last_error(), st);
-        UMat mm{}, mt{}, md{};
-        for (int ph = 0; ph < 2; ++ph) {
-            for (int k = 0; k < 5; ++k) mm.m[ph][k] = m10[5 * ph + k];
-            for (int k = 0; k < 2; ++k) {
-                mt.m[ph][k] = t4[2 * ph + k];
-                md.m[ph][k] = d4[2 * ph + k];
+    // records in chunks sharing every launch (columns = record x load case)
+    const long long per_rec = 18LL * u->nnode;   // values of one record's widest vector (6 load cases x 3)
+    const int chunk = (int)std::max<long long>(
+        1, std::min<long long>(std::min(batch, URVE_CHUNK), (64LL << 20) / per_rec));
+    std::vector<UMat> mm(chunk), mt(chunk), md(chunk);
+    std::vector<double> keep(chunk), A6((size_t)chunk * 36), A6v((size_t)chunk * 36), A3((size_t)chunk * 9),
+        A3v((size_t)chunk * 9), B3((size_t)chunk * 9), B3v((size_t)chunk * 9), res6((size_t)chunk * 6),
+        res3a((size_t)chunk * 3), res3b((size_t)chunk * 3);
+    std::vector<int> it6((size_t)chunk * 6), it3a((size_t)chunk * 3), it3b((size_t)chunk * 3), f6((size_t)chunk * 6),
+        f3a((size_t)chunk * 3), f3b((size_t)chunk * 3);
+    for (int i0 = 0; i0 < batch; i0 += chunk) {
+        const int nb = std::min(chunk, batch - i0);
+        for (int j = 0; j < nb; ++j) {
+            double m10[10], t4[4], d4[4];
+            keep[j] = 1.0;
+            const int st = chom_material_constants(&u->mat, &hp[i0 + j], u->opt.c_sat, u->opt.degrade_yarn, m10,
+                                                   t4, d4, &keep[j]);
+            if (st != CHOM_OK)
+                return ufail("chom_urve_homogenise: record " + std::to_string(i0 + j) + ": " + chom_last_error(), st);
+            for (int ph = 0; ph < 2; ++ph) {
+                for (int k = 0; k < 5; ++k) mm[j].m[ph][k] = m10[5 * ph + k];
+                for (int k = 0; k < 5; ++k) mt[j].m[ph][k] = md[j].m[ph][k] = 0.0;
+                for (int k = 0; k < 2; ++k) {
+                    mt[j].m[ph][k] = t4[2 * ph + k];
+                    md[j].m[ph][k] = d4[2 * ph + k];
+                }
             }
         }
-        chom_report r;
-        std::memset(&r, 0, sizeof(r));
-        r.omega_keep = keep;
-        double A6[36], A6v[36], A3[9], A3v[9], B3[9], B3v[9];
-        int s1 = usolve<3, 6>(u, mm, u->opt.rtol, u->opt.max_iter, A6, A6v, r.iters, r.resid, r.fail);
+        const int s1 = usolve<3, 6>(u, mm.data(), nb, u->opt.rtol, u->opt.max_iter, A6.data(), A6v.data(), it6.data(),
+                                    res6.data(), f6.data());
         if (s1 != CHOM_OK && s1 != CHOM_ENOCONV) return s1;
-        int s2 = usolve<1, 3>(u, mt, u->opt.rtol, u->opt.max_iter, A3, A3v, r.iters + 6, r.resid + 6, r.fail + 6);
+        const int s2 = usolve<1, 3>(u, mt.data(), nb, u->opt.rtol, u->opt.max_iter, A3.data(), A3v.data(),
+                                    it3a.data(), res3a.data(), f3a.data());
         if (s2 != CHOM_OK && s2 != CHOM_ENOCONV) return s2;
-        int s3 = usolve<1, 3>(u, md, u->opt.rtol, u->opt.max_iter, B3, B3v, r.iters + 9, r.resid + 9, r.fail + 9);
+        const int s3 = usolve<1, 3>(u, md.data(), nb, u->opt.rtol, u->opt.max_iter, B3.data(), B3v.data(),
+                                    it3b.data(), res3b.data(), f3b.data());
         if (s3 != CHOM_OK && s3 != CHOM_ENOCONV) return s3;
-        r.status = (s1 == CHOM_OK && s2 == CHOM_OK && s3 == CHOM_OK) ? CHOM_OK : CHOM_ENOCONV;
-        if (r.status != CHOM_OK) status = CHOM_ENOCONV;
-        // symmetric parts, asymmetry, Hill-Mandel gap, SPD test
-        auto fro = [](const double *M, int n) {
-            double t = 0.0;
-            for (int q = 0; q < n * n; ++q) t += M[q] * M[q];
-            return std::sqrt(t);
-        };
-        double asym = 0.0, gap = 0.0;
-        for (auto blk : {std::make_tuple(A6, A6v, 6), std::make_tuple(A3, A3v, 3), std::make_tuple(B3, B3v, 3)}) {
-            double *M = std::get<0>(blk), *Mv = std::get<1>(blk);
-            const int n = std::get<2>(blk);
-            double da = 0.0, dg = 0.0;
-            for (int a = 0; a < n; ++a)
-                for (int b = 0; b < n; ++b) {
-                    da += (M[a * n + b] - M[b * n + a]) * (M[a * n + b] - M[b * n + a]);
-                    dg += (M[a * n + b] - Mv[a * n + b]) * (M[a * n + b] - Mv[a * n + b]);
-                }
-            const double nm = fro(M, n);
-            if (n == 6) asym = std::sqrt(da) / nm;
-            gap = std::max(gap, std::sqrt(dg) / nm);
-            for (int a = 0; a < n; ++a)
-                for (int b = a + 1; b < n; ++b) M[a * n + b] = M[b * n + a] = 0.5 * (M[a * n + b] + M[b * n + a]);
+        for (int j = 0; j < nb; ++j) {
+            const int i = i0 + j;
+            chom_report r;
+            std::memset(&r, 0, sizeof(r));
+            r.omega_keep = keep[j];
+            int conv = 1;
+            for (int k = 0; k < 6; ++k) {
+                r.iters[k] = it6[j * 6 + k];
+                r.resid[k] = res6[j * 6 + k];
+                r.fail[k] = f6[j * 6 + k];
+            }
+            for (int k = 0; k < 3; ++k) {
+                r.iters[6 + k] = it3a[j * 3 + k];
+                r.resid[6 + k] = res3a[j * 3 + k];
+                r.fail[6 + k] = f3a[j * 3 + k];
+                r.iters[9 + k] = it3b[j * 3 + k];
+                r.resid[9 + k] = res3b[j * 3 + k];
+                r.fail[9 + k] = f3b[j * 3 + k];
+            }
+            for (int k = 0; k < 12; ++k) conv &= r.fail[k] == CHOM_FAIL_NONE;
+            r.status = conv ? CHOM_OK : CHOM_ENOCONV;
+            if (!conv) status = CHOM_ENOCONV;
+            // symmetric parts, asymmetry, Hill-Mandel gap, SPD test
+            double *a6 = &A6[(size_t)j * 36], *a6v = &A6v[(size_t)j * 36], *a3 = &A3[(size_t)j * 9],
+                   *a3v = &A3v[(size_t)j * 9], *b3 = &B3[(size_t)j * 9], *b3v = &B3v[(size_t)j * 9];
+            double asym = 0.0, gap = 0.0;
+            for (auto blk : {std::make_tuple(a6, a6v, 6), std::make_tuple(a3, a3v, 3), std::make_tuple(b3, b3v, 3)}) {
+                double *M = std::get<0>(blk), *Mv = std::get<1>(blk);
+                const int n = std::get<2>(blk);
+                double da = 0.0, dgp = 0.0, nm = 0.0;
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b) {
+                        da += (M[a * n + b] - M[b * n + a]) * (M[a * n + b] - M[b * n + a]);
+                        dgp += (M[a * n + b] - Mv[a * n + b]) * (M[a * n + b] - Mv[a * n + b]);
+                        nm += M[a * n + b] * M[a * n + b];
+                    }
+                nm = std::sqrt(nm);
+                if (n == 6) asym = std::sqrt(da) / nm;
+                gap = std::max(gap, std::sqrt(dgp) / nm);
+                for (int a = 0; a < n; ++a)
+                    for (int b = a + 1; b < n; ++b) M[a * n + b] = M[b * n + a] = 0.5 * (M[a * n + b] + M[b * n + a]);
+            }
+            r.asym = asym;
+            r.hill_mandel_gap = gap;
+            r.spd = (cholesky_ok(a6, 6) && cholesky_ok(a3, 3) && cholesky_ok(b3, 3)) ? 1 : 0;
+            for (int a = 0, q = 0; a < 6; ++a)
+                for (int b = a; b < 6; ++b, ++q) hC[(size_t)i * 21 + q] = a6[a * 6 + b];
+            const int id[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {1, 2}, {0, 2}};
+            for (int q = 0; q < 6; ++q) {
+                hK[(size_t)i * 6 + q] = a3[id[q][0] * 3 + id[q][1]];
+                hD[(size_t)i * 6 + q] = b3[id[q][0] * 3 + id[q][1]];
+            }
+            if (rep) rep[i] = r;
         }
-        r.asym = asym;
-        r.hill_mandel_gap = gap;
-        r.spd = (cholesky_ok(A6, 6) && cholesky_ok(A3, 3) && cholesky_ok(B3, 3)) ? 1 : 0;
-        for (int a = 0, q = 0; a < 6; ++a)
-            for (int b = a; b < 6; ++b, ++q) hC[(size_t)i * 21 + q] = A6[a * 6 + b];
-        const int id[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {1, 2}, {0, 2}};
-        for (int q = 0; q < 6; ++q) {
-            hK[(size_t)i * 6 + q] = A3[id[q][0] * 3 + id[q][1]];
-            hD[(size_t)i * 6 + q] = B3[id[q][0] * 3 + id[q][1]];
-        }
-        if (rep) rep[i] = r;
     }
     if (dev) {
         CHOM_HIP(hipMemcpy(C_hom, hC.data(), sizeof(double) * hC.size(), hipMemcpyHostToDevice));
