@@ -360,7 +360,8 @@ int chom_urve_create(const chom_mesh *mesh, const chom_materials *mat, int32_t b
 /* P2 nodes (vertices + edges) and free unknowns (per component) of a handle. */
 int chom_urve_sizes(const chom_urve *u, int64_t *n_nodes, int64_t *n_unknowns);
 
-/* Homogenise `batch` parameter records one after the other: outputs and report
+/* Homogenise `batch` parameter records (in chunks of up to 16 whose load cases
+ * share every launch; fewer on very large meshes): outputs and report
  * as for chom_homogenise (refine_steps and fp64_fallback are 0; the
  * Hill-Mandel gap compares the energy form with the volume average of stress
  * and flux).  Errors: CHOM_ENOCONV (results written), CHOM_EINVAL (records
