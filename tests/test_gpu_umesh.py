@@ -80,6 +80,26 @@ def test_unstructured_periodic_larger_mesh_matches_oracle():
     assert max(e) <= 1e-9
 
 
+def test_unstructured_records_in_chunks_equal_single_solves():
+    """18 records in one call run as a chunk of 16 and a chunk of 2 (their load
+    cases share every launch); each equals its own one-record call."""
+    require_gpu()
+    coords, tets, phase, axis = _weave(3, seed=10)
+    params = ci.draw_params(14, 18)
+    u = _urve(coords, tets, phase, axis, "periodic")
+    C, K, D, rep = u.homogenise(params)
+    worst = 0.0
+    for i in (0, 7, 15, 16, 17):
+        c1, k1, d1, r1 = u.homogenise(params[i:i + 1])
+        e = result_errors(C[i], K[i], D[i], c1[0], k1[0], d1[0])
+        worst = max(worst, max(e))
+        assert rep[i]["iters"] == r1[0]["iters"] or max(e) <= 1e-9
+    u.close()
+    banner(f"unstructured chunks: largest difference to single-record calls {worst:.1e}")
+    assert worst <= 1e-9
+    assert all(r["status"] == 0 for r in rep)
+
+
 @pytest.mark.parametrize("bc", ["dirichlet", "periodic"])
 def test_homogeneous_unstructured_rve_returns_its_material(bc):
     require_gpu()
