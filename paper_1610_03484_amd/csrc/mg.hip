@@ -169,6 +169,48 @@ __device__ inline void lev_xyz(const Lev &V, long long pt, int &i, int &j, int &
 }
 
 // ------------------------------------------------------------------ setup (FP64)
+// The tets that hold both a vertex I and its Kuhn neighbour J = I + offset(s)
+// are the same for every I: tet t of the cell whose corner d (bits x, y, z) is
+// I, with I and J its vertices va and vb.  Tabulated at compile time per slot
+// (24 pairs for I itself, 84 over the 15 slots).
+struct Asm0Table {
+    int start[MG_SLOTS + 1];
+    int code[MG_SLOTS * 48];   // d | t << 3 | va << 6 | vb << 8
+};
+constexpr Asm0Table make_asm0_table() {
+    Asm0Table T{};
+    constexpr int ox[8] = {0, 1, 0, 0, 1, 1, 0, 1}, oy[8] = {0, 0, 1, 0, 1, 0, 1, 1}, oz[8] = {0, 0, 0, 1, 0, 1, 1, 1};
+    constexpr int pa[6] = {0, 0, 1, 1, 2, 2}, pb[6] = {1, 2, 0, 2, 0, 1};   // the Kuhn permutations
+    int n = 0;
+    for (int s = 0; s < MG_SLOTS; ++s) {
+        T.start[s] = n;
+        const int b0 = s < 8 ? s : s - 7, sg = s < 8 ? 1 : -1;
+        const int dx = sg * ox[b0], dy = sg * oy[b0], dz = sg * oz[b0];
+        for (int d = 0; d < 8; ++d) {
+            const int ax = d & 1, ay = (d >> 1) & 1, az = (d >> 2) & 1;
+            const int bx = ax + dx, by = ay + dy, bz = az + dz;
+            if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+            for (int t = 0; t < 6; ++t) {
+                int va = -1, vb = -1;
+                for (int q = 0; q < 4; ++q) {
+                    int c3[3] = {0, 0, 0};
+                    if (q >= 1) c3[pa[t]] = 1;
+                    if (q >= 2) c3[pb[t]] = 1;
+                    if (q == 3) c3[0] = c3[1] = c3[2] = 1;
+                    if (c3[0] == ax && c3[1] == ay && c3[2] == az) va = q;
+                    if (c3[0] == bx && c3[1] == by && c3[2] == bz) vb = q;
+                }
+                if (va < 0 || vb < 0) continue;
+                T.code[n++] = d | t << 3 | va << 6 | vb << 8;
+            }
+        }
+    }
+    T.start[MG_SLOTS] = n;
+    return T;
+}
+__constant__ Asm0Table c_asm0 = make_asm0_table();
+static_assert(make_asm0_table().start[1] == 24, "every cube corner lies in the tets of the Kuhn split");
+
 // Level 0: A_0[I][s] = sum over tets holding I and J = I + offset(s) of
 // |e| (grad lam_J . C . grad lam_I) (mechanics: the C x C block with
 // entry [c][d] = |e| sum_j sigma(sym(e_d x g_J))[c][j] g_I[j]).
@@ -184,8 +226,9 @@ __global__ void mg_assemble0_kernel(const Geo *geos, const Prob *probs, double *
     double *Ap = A64 + (P.moff + V.off) * MG_SLOTS * CC;
     for (long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x; u < np * MG_SLOTS;
          u += (long long)gridDim.x * blockDim.x) {
-        const long long pt = u / MG_SLOTS;
-        const int s = (int)(u - pt * MG_SLOTS);
+        // slot-major: the threads of a wave share a slot (and so the table's loop)
+        const int s = (int)(u / np);
+        const long long pt = u - (long long)s * np;
         int i, j, k, dx, dy, dz;
         lev_xyz(V, pt, i, j, k);
         kuhn_offset(s, dx, dy, dz);
@@ -194,10 +237,10 @@ __global__ void mg_assemble0_kernel(const Geo *geos, const Prob *probs, double *
         for (int q = 0; q < CC; ++q) acc[q] = 0.0;
         const bool inside = V.per || (i + dx >= 0 && j + dy >= 0 && k + dz >= 0 && i + dx <= n && j + dy <= n && k + dz <= n);
         if (inside && !lev_boundary(V, i, j, k) && !lev_boundary(V, i + dx, j + dy, k + dz)) {
-            for (int d = 0; d < 8; ++d) {
+            for (int e = c_asm0.start[s]; e < c_asm0.start[s + 1]; ++e) {
+                const int code = c_asm0.code[e];
+                const int d = code & 7, t = (code >> 3) & 7, va = (code >> 6) & 3, vb = (code >> 8) & 3;
                 const int ax = d & 1, ay = (d >> 1) & 1, az = (d >> 2) & 1;   // I's corner in the cell
-                const int bx = ax + dx, by = ay + dy, bz = az + dz;            // J's corner
-                if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
                 int cx = i - ax, cy = j - ay, cz = k - az;
                 if (V.per) {
                     cx = wrap(cx, n);
@@ -206,20 +249,7 @@ __global__ void mg_assemble0_kernel(const Geo *geos, const Prob *probs, double *
                 } else if (cx < 0 || cy < 0 || cz < 0 || cx >= n || cy >= n || cz >= n) {
                     continue;
                 }
-                for (int t = 0; t < 6; ++t) {
-                    int p0, p1;
-                    kuhn_perm(t, p0, p1);
-                    // chain of the tet: 000, e_p0, e_p0 + e_p1, 111
-                    int va = -1, vb = -1;
-                    for (int q = 0; q < 4; ++q) {
-                        int c3[3] = {0, 0, 0};
-                        if (q >= 1) c3[p0] = 1;
-                        if (q >= 2) c3[p1] = 1;
-                        if (q == 3) c3[0] = c3[1] = c3[2] = 1;
-                        if (c3[0] == ax && c3[1] == ay && c3[2] == az) va = q;
-                        if (c3[0] == bx && c3[1] == by && c3[2] == bz) vb = q;
-                    }
-                    if (va < 0 || vb < 0) continue;
+                {
                     const long long tet = ((long long)cx + (long long)n * ((long long)cy + (long long)n * cz)) * 6 + t;
                     double g[4][3], vol, a[3];
                     int ph;
