@@ -24,7 +24,10 @@ namespace chom {
 
 using hp::Shape;
 
-constexpr int HP_THREADS = 256;
+// Threads of an operator workgroup: 128 at order 3 (smaller per-cell work: more
+// workgroups per CU hide the staging and barrier latency; 5.01 -> 4.65 ms per
+// launch of 64 16^3 RVEs), 256 at order 4 (128: 12.6 -> 15.4 ms).
+template <int P> constexpr int hp_threads() { return P == 3 ? 128 : 256; }
 
 static inline int hp_grid(long long work, int bs, int cap = 16384) {
     long long g = (work + bs - 1) / bs;
@@ -388,7 +391,7 @@ template hipError_t launch_factors_hp<1>(const Launch &, double *, float *, hipS
 // that is written, contiguous, to the cell's slot of the tile-box output
 // (consumers sum the copies of points shared by neighbouring cells).
 template <typename T, int P, int C, int R>
-__global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, const Prob *probs, int max_tiles,
+__global__ __launch_bounds__(hp_threads<P>()) void hp_op_kernel(const Geo *geos, const Prob *probs, int max_tiles,
                                                           const T *__restrict__ x, T *__restrict__ y,
                                                           const T *__restrict__ ef, double *acc_pq,
                                                           const int *prob_active) {
@@ -401,6 +404,7 @@ __global__ __launch_bounds__(HP_THREADS) void hp_op_kernel(const Geo *geos, cons
     constexpr int NC = EB * RC;              // columns: tet x load case x component
     constexpr int NT = (NC + 15) / 16;
     constexpr int NCP = NT * 16;
+    constexpr int HP_THREADS = hp_threads<P>();
     constexpr int NW = HP_THREADS / 64;
     using V4 = typename Mfma<T>::v4;
     // LDS shared by phases: X (xs) is dead once G is formed, so the output box
@@ -595,7 +599,7 @@ static hipError_t launch_hp(const Launch &L, int nprob, const T *x, T *y, double
                             hipStream_t s) {
     dim3 grid(L.max_tiles, nprob);
     const T *ef = std::is_same<T, double>::value ? (const T *)L.ef64 : (const T *)L.ef32;
-    hp_op_kernel<T, P, C, R><<<grid, HP_THREADS, 0, s>>>(L.geos, L.probs, L.max_tiles, x, y, ef, acc_pq,
+    hp_op_kernel<T, P, C, R><<<grid, hp_threads<P>(), 0, s>>>(L.geos, L.probs, L.max_tiles, x, y, ef, acc_pq,
                                                          prob_active);
     return hipGetLastError();
 }
