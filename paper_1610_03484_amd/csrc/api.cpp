@@ -720,30 +720,24 @@ static int pcg(chom_batch *B, ClassWS<C, R> &W, PcgChain<C, R> &K, const T *b, T
     return CHOM_OK;
 }
 
-// PCG on all problems of a class.  Large classes (at least 16 problems) split
-// into two chains of contiguous ranges, the second run from its own host thread
+// CG chains of a class.  Large classes (at least 16 problems) split into two
+// chains of contiguous problem ranges, the second run from its own host thread
 // on the class's second stream, so that the latency-bound kernels of one chain
-// (coarse levels, finishing kernels) overlap the bandwidth- and ALU-bound ones
-// of the other (512-record mixed batch: +4%); small classes keep one chain (the
-// three-BC 24^3 batch: -8% with two).  CHOM_PCG_CHAINS=1 or 2 forces the count.
-template <typename T, int C, int R>
-static int pcg_class(chom_batch *B, ClassWS<C, R> &W, bool fp64, const T *b, T *x, T *r, T *p, T *q,
-                     const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask,
-                     double loose = 0.0) {
-    const int nprob = W.L.nprob;
+// (coarse levels, finishing kernels, host polls) overlap the bandwidth- and
+// ALU-bound ones of the other (512-record mixed batch: +4%); small classes keep
+// one chain (the three-BC 24^3 batch: -8% with two).  CHOM_PCG_CHAINS=1 or 2
+// forces the count.
+static int chain_count(int nprob) {
     const char *ev = std::getenv("CHOM_PCG_CHAINS");
     const int want = ev ? std::atoi(ev) : (nprob >= 16 ? 2 : 1);
-    const int nch = (nprob >= 2 && want == 2) ? 2 : 1;
-    GraphCache *ga = fp64 ? &W.graph64 : &W.graph32, *gb = fp64 ? &W.graph64b : &W.graph32b;
-    if (nch == 1) {
-        PcgChain<C, R> K = make_chain<C, R>(W, 0, nprob, ginv, mask, W.stream, ga);
-        K.loose = loose;
-        return pcg<T, C, R>(B, W, K, b, x, r, p, q, minv, rtol2, use_init);
-    }
-    const int h = (nprob + 1) / 2;
-    PcgChain<C, R> KA = make_chain<C, R>(W, 0, h, ginv, mask, W.stream, ga);
-    PcgChain<C, R> KB = make_chain<C, R>(W, h, nprob - h, ginv, mask, W.stream_b, gb);
-    KA.loose = KB.loose = loose;
+    return (nprob >= 2 && want == 2) ? 2 : 1;
+}
+
+// Runs fa() on the class's stream from this thread and fb() on its second
+// stream from a host thread of its own.  The second stream first waits for the
+// work already queued on the first; at the end the first waits for the second.
+template <int C, int R, typename FA, typename FB>
+static int fork_chains(ClassWS<C, R> &W, FA &&fa, FB &&fb) {
     hipEvent_t e0, e1;
     CHOM_HIP(hipEventCreateWithFlags(&e0, hipEventDisableTiming));
     CHOM_HIP(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
@@ -759,10 +753,10 @@ static int pcg_class(chom_batch *B, ClassWS<C, R> &W, bool fp64, const T *b, T *
             errb = "hipSetDevice failed in a CG chain thread";
             return;
         }
-        stb = pcg<T, C, R>(B, W, KB, b, x, r, p, q, minv, rtol2, use_init);
+        stb = fb();
         if (stb != CHOM_OK) errb = g_last_error;
     });
-    const int sta = pcg<T, C, R>(B, W, KA, b, x, r, p, q, minv, rtol2, use_init);
+    const int sta = fa();
     th.join();
     hipError_t he = hipEventRecord(e1, W.stream_b);
     if (he == hipSuccess) he = hipStreamWaitEvent(W.stream, e1, 0);
@@ -777,48 +771,98 @@ static int pcg_class(chom_batch *B, ClassWS<C, R> &W, bool fp64, const T *b, T *
     return CHOM_OK;
 }
 
-// FP64 correction solve of the refinement for the problems flagged in `which`
-// (the others are masked out): K d = r64 with the FP64 operator and block-Jacobi
-// preconditioning to a tenth of the outer tolerance, then x64 += d.  Used when
-// the FP32 inner solves stop contracting the FP64 residual.  The FP64 vectors
-// are allocated on first use.
+// PCG on all problems of a class, in one or two chains (chain_count).
+template <typename T, int C, int R>
+static int pcg_class(chom_batch *B, ClassWS<C, R> &W, bool fp64, const T *b, T *x, T *r, T *p, T *q,
+                     const void *minv, const double *ginv, double rtol2, int use_init, const ColState *mask) {
+    const int nprob = W.L.nprob;
+    GraphCache *ga = fp64 ? &W.graph64 : &W.graph32, *gb = fp64 ? &W.graph64b : &W.graph32b;
+    if (chain_count(nprob) == 1) {
+        PcgChain<C, R> K = make_chain<C, R>(W, 0, nprob, ginv, mask, W.stream, ga);
+        return pcg<T, C, R>(B, W, K, b, x, r, p, q, minv, rtol2, use_init);
+    }
+    const int h = (nprob + 1) / 2;
+    PcgChain<C, R> KA = make_chain<C, R>(W, 0, h, ginv, mask, W.stream, ga);
+    PcgChain<C, R> KB = make_chain<C, R>(W, h, nprob - h, ginv, mask, W.stream_b, gb);
+    return fork_chains<C, R>(
+        W, [&]() { return pcg<T, C, R>(B, W, KA, b, x, r, p, q, minv, rtol2, use_init); },
+        [&]() { return pcg<T, C, R>(B, W, KB, b, x, r, p, q, minv, rtol2, use_init); });
+}
+
+// One CG chain's share of the FP32-operator / FP64-refinement solve: problems
+// [p0, p0 + cnt), whose vector values are [v0, v1), on stream s with the
+// chain's graph caches.  Each chain refines on its own, so neither waits for
+// the other at a refinement step and one chain's FP64 residual and host checks
+// overlap the other's CG.
+template <int C, int R> struct RefineRange {
+    int p0 = 0, cnt = 0;
+    long long v0 = 0, v1 = 0;
+    hipStream_t s = nullptr;
+    GraphCache *g32 = nullptr, *g64 = nullptr;
+};
+
+// FP64 correction solve of the refinement for the problems of the range
+// flagged in `which` (the others are masked out): K d = r64 with the FP64
+// operator and block-Jacobi preconditioning to a tenth of the outer tolerance,
+// then x64 += d.  Used when the FP32 inner solves stop contracting the FP64
+// residual.  The FP64 vectors are allocated on first use (under alloc_mu: both
+// chains may get here).
 template <int C, int R>
-static int fp64_correction(chom_batch *B, ClassWS<C, R> &W, const std::vector<int> &which, double rtol2) {
-    const Launch saved = W.L;
-    const int nprob = saved.nprob;
-    hipStream_t s = W.stream;
-    const size_t nv = (size_t)W.total_vals, nq = (size_t)W.total_q;
-    CHOM_HIP(W.xd.ensure(nv));
-    CHOM_HIP(W.rd.ensure(nv));
-    CHOM_HIP(W.pd.ensure(nv));
-    CHOM_HIP(W.qd.ensure(nq));
-    CHOM_HIP(W.cols_fb.ensure((size_t)R * nprob));
-    std::vector<ColState> mask(W.h_cols_outer);
-    for (int i = 0; i < nprob; ++i)
+static int fp64_correction(chom_batch *B, ClassWS<C, R> &W, const RefineRange<C, R> &G, const std::vector<int> &which,
+                           double rtol2, std::mutex &alloc_mu) {
+    const int nprob = W.L.nprob;
+    const size_t c0 = (size_t)G.p0 * R, nc = (size_t)G.cnt * R;
+    {
+        std::lock_guard<std::mutex> lk(alloc_mu);
+        const size_t nv = (size_t)W.total_vals, nq = (size_t)W.total_q;
+        CHOM_HIP(W.xd.ensure(nv));
+        CHOM_HIP(W.rd.ensure(nv));
+        CHOM_HIP(W.pd.ensure(nv));
+        CHOM_HIP(W.qd.ensure(nq));
+        CHOM_HIP(W.cols_fb.ensure((size_t)R * nprob));
+    }
+    std::vector<ColState> mask(W.h_cols_outer.begin() + c0, W.h_cols_outer.begin() + c0 + nc);
+    for (int i = 0; i < G.cnt; ++i)
         if (!which[i])
             for (int r = 0; r < R; ++r) mask[(size_t)i * R + r].done = COL_CONVERGED;
-    CHOM_HIP(hipMemcpyAsync(W.cols_fb.p, mask.data(), sizeof(ColState) * R * nprob, hipMemcpyHostToDevice, s));
-    W.L.mg.on = 0;   // the coarse levels hold FP32 data in this mode: block Jacobi alone
-    ++W.gen;
-    const int st = pcg_class<double, C, R>(B, W, true, W.r64.p, W.xd.p, W.rd.p, W.pd.p, W.qd.p, W.minv64.p,
-                                           W.ginv64.p, 0.01 * rtol2, 0, W.cols_fb.p);
-    W.L = saved;
-    ++W.gen;
+    CHOM_HIP(hipMemcpyAsync(W.cols_fb.p + c0, mask.data(), sizeof(ColState) * nc, hipMemcpyHostToDevice, G.s));
+    PcgChain<C, R> K = make_chain<C, R>(W, G.p0, G.cnt, W.ginv64.p, W.cols_fb.p, G.s, G.g64);
+    K.L.mg.on = 0;   // the coarse levels hold FP32 data in this mode: block Jacobi alone
+    G.g64->reset();
+    const int st = pcg<double, C, R>(B, W, K, W.r64.p, W.xd.p, W.rd.p, W.pd.p, W.qd.p, W.minv64.p, 0.01 * rtol2, 0);
+    G.g64->reset();
     CHOM_TRY(st);
-    CHOM_HIP(launch_axpy64(W.total_vals, W.x64.p, W.xd.p, s));
+    CHOM_HIP(launch_axpy64(G.v1 - G.v0, W.x64.p + G.v0, W.xd.p + G.v0, G.s));
+    CHOM_HIP(hipStreamSynchronize(G.s));   // mask dies here
     return CHOM_OK;
 }
 
-// FP32 operator with FP64 refinement: x64 += PCG_32(r64), r64 = b - K_64 x64,
-// until the projected FP64 residual meets rtol.  A problem whose FP64 residual
-// norm contracts by less than a half per step over three steps is finished by
-// an FP64 correction solve (CHOM_FORCE_FP64_FALLBACK forces that from the second
-// step on, for tests).
+// FP32 operator with FP64 refinement on one range: x64 += PCG_32(r64),
+// r64 = b - K_64 x64, until the projected FP64 residual meets rtol.  A problem
+// whose FP64 residual norm contracts by less than a half per step over three
+// steps is finished by an FP64 correction solve (CHOM_FORCE_FP64_FALLBACK
+// forces that from the second step on, for tests).
 template <int C, int R>
-static int refine_class(chom_batch *B, ClassWS<C, R> &W, const double *ginv_inner32, double rtol2) {
-    const Launch &L = W.L;
-    const int nprob = L.nprob;
-    hipStream_t s = W.stream;
+static int refine_range(chom_batch *B, ClassWS<C, R> &W, const RefineRange<C, R> &G, const double *ginv_inner32,
+                        double rtol2, std::mutex &alloc_mu) {
+    constexpr int SMAX = C * 4;
+    const int p0 = G.p0, cnt = G.cnt;
+    const size_t c0 = (size_t)p0 * R, nc = (size_t)cnt * R;
+    hipStream_t s = G.s;
+    Launch L = W.L;
+    L.probs = W.L.probs + p0;
+    L.nprob = cnt;
+    const long long accs = (long long)R * ACC_RECMAX<C> * ACC_STRIPES;
+    double *acc = W.acc.p + p0 * accs;
+    const long long acc_n = cnt * accs;
+    double *accpq = W.accpq.p + p0 * (long long)R * ACC_STRIPES;
+    double *ycoef = W.ycoef.p + (size_t)p0 * R * C * L.nr;
+    const double *ginv64 = W.ginv64.p + (size_t)p0 * SMAX * SMAX;
+    const double *ginv32 = ginv_inner32 + (size_t)p0 * SMAX * SMAX;
+    ColState *cols = W.cols.p + c0, *cols_outer = W.cols_outer.p + c0, *cols_tmp = W.cols_tmp.p + c0;
+    int *active_outer = W.active_outer.p + p0, *active_tmp = W.active_tmp.p + p0;
+    ColState *h_outer = W.h_cols_outer.data() + c0;
+    const ColState *h_tmp = W.h_cols_tmp.data() + c0;
     const double irtol2 = B->opt.inner_rtol * B->opt.inner_rtol;
     const bool force_fb = std::getenv("CHOM_FORCE_FP64_FALLBACK") != nullptr;
     // An FP32 inner pass cannot resolve a column below about u32 * eref / E of
@@ -828,47 +872,43 @@ static int refine_class(chom_batch *B, ClassWS<C, R> &W, const double *ginv_inne
     // measured on the mixed batch between 1.5 and 100), so such a column stops
     // where FP32 stalls and the FP64 refinement continues from there.
     const double loose = 6.0 * 0x1p-24;
-    CHOM_HIP(hipMemsetAsync(W.x64.p, 0, sizeof(double) * W.total_vals, s));
-    CHOM_HIP((launch_residual64<C, R>(L, W.b.p, nullptr, W.r64.p, W.r32.p, s)));
-    CHOM_HIP(hipMemcpyAsync(W.cols_outer.p, W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToDevice, s));
-    std::vector<double> prev_rz((size_t)R * nprob, 0.0);
-    std::vector<int> slow((size_t)R * nprob, 0);
+    const bool mg = L.mg.on != 0;
+    std::vector<double> prev_rz(nc, 0.0);
+    std::vector<int> slow(nc, 0);
+    std::vector<ColState> fbmask;
     for (int step = 0; step <= B->opt.max_refine; ++step) {
         // outer residual: project r64 (FP64), then measure it in the metric of the
         // solver's preconditioner (r.M^-1 r, or r.B r with the two-level one, from
         // the FP32 copy with FP64 sums) against the column's energy
-        CHOM_HIP(launch_zero(W.acc.p, (long long)W.acc.n, s));
-        CHOM_HIP((launch_cg_init<double, C, R>(L, W.r64.p, nullptr, nullptr, W.minv64.p, W.acc.p, s)));
-        CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p, W.active_outer.p, 1,
-                                           rtol2, 0, nullptr, s, 0, W.cols.p)));
+        CHOM_HIP(launch_zero(acc, acc_n, s));
+        CHOM_HIP((launch_cg_init<double, C, R>(L, W.r64.p, nullptr, nullptr, W.minv64.p, acc, s)));
+        CHOM_HIP((launch_finish_beta<C, R>(L, acc, ginv64, ycoef, cols_outer, active_outer, 1, rtol2, 0, nullptr, s,
+                                           0, cols)));
         if (L.nr > 0) {
-            CHOM_HIP((launch_proj_resid<C, R>(L, W.r64.p, W.r32.p, W.minv64.p, W.ycoef.p, W.acc.p, s)));
-            CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, W.ginv64.p, W.ycoef.p, W.cols_outer.p, W.active_outer.p,
-                                               1, rtol2, 0, nullptr, s, 0, W.cols.p)));
+            CHOM_HIP((launch_proj_resid<C, R>(L, W.r64.p, W.r32.p, W.minv64.p, ycoef, acc, s)));
+            CHOM_HIP((launch_finish_beta<C, R>(L, acc, ginv64, ycoef, cols_outer, active_outer, 1, rtol2, 0, nullptr,
+                                               s, 0, cols)));
         }
-        const bool mg = L.mg.on != 0;
         if (mg) {   // the two-level metric, into cols_tmp (merged on the host below)
-            CHOM_HIP(hipMemcpyAsync(W.cols_tmp.p, W.cols_outer.p, sizeof(ColState) * R * nprob,
-                                    hipMemcpyDeviceToDevice, s));
-            CHOM_HIP(launch_zero(W.acc.p, (long long)W.acc.n, s));
-            CHOM_HIP((launch_cg_init<float, C, R>(L, W.r32.p, nullptr, nullptr, W.minv32.p, W.acc.p, s)));
-            CHOM_HIP((launch_mg_vcycle<float, C, R>(L, W.r32.p, W.acc.p, nullptr, s)));
-            CHOM_HIP((launch_finish_beta<C, R>(L, W.acc.p, ginv_inner32, W.ycoef.p, W.cols_tmp.p, W.active_tmp.p,
-                                               1, rtol2, 0, nullptr, s, 0, W.cols.p)));
-            CHOM_HIP(hipMemcpyAsync(W.h_cols_tmp.data(), W.cols_tmp.p, sizeof(ColState) * R * nprob,
-                                    hipMemcpyDeviceToHost, s));
+            CHOM_HIP(hipMemcpyAsync(cols_tmp, cols_outer, sizeof(ColState) * nc, hipMemcpyDeviceToDevice, s));
+            CHOM_HIP(launch_zero(acc, acc_n, s));
+            CHOM_HIP((launch_cg_init<float, C, R>(L, W.r32.p, nullptr, nullptr, W.minv32.p, acc, s)));
+            CHOM_HIP((launch_mg_vcycle<float, C, R>(L, W.r32.p, acc, nullptr, s)));
+            CHOM_HIP((launch_finish_beta<C, R>(L, acc, ginv32, ycoef, cols_tmp, active_tmp, 1, rtol2, 0, nullptr, s,
+                                               0, cols)));
+            CHOM_HIP(hipMemcpyAsync(W.h_cols_tmp.data() + c0, cols_tmp, sizeof(ColState) * nc, hipMemcpyDeviceToHost,
+                                    s));
         }
-        CHOM_HIP(hipMemcpyAsync(W.h_cols_outer.data(), W.cols_outer.p, sizeof(ColState) * R * nprob,
-                                hipMemcpyDeviceToHost, s));
+        CHOM_HIP(hipMemcpyAsync(h_outer, cols_outer, sizeof(ColState) * nc, hipMemcpyDeviceToHost, s));
         CHOM_HIP(hipStreamSynchronize(s));
         // merge: the two-level measurement where it is finite; where the FP32
         // coarse levels overflow, the FP64 block-Jacobi one stands and an active
         // column goes to the FP64 correction solve
-        std::vector<int> fp32_failed(nprob, 0);
+        std::vector<int> fp32_failed(cnt, 0);
         if (mg) {
-            for (size_t k = 0; k < (size_t)R * nprob; ++k) {
-                ColState &h = W.h_cols_outer[k];
-                const ColState &t = W.h_cols_tmp[k];
+            for (size_t k = 0; k < nc; ++k) {
+                ColState &h = h_outer[k];
+                const ColState &t = h_tmp[k];
                 if (std::isfinite(t.rz)) {
                     if (h.done != COL_NONFINITE) {
                         h.rz = t.rz;
@@ -879,22 +919,21 @@ static int refine_class(chom_batch *B, ClassWS<C, R> &W, const double *ginv_inne
                     fp32_failed[k / R] = 1;
                 }
             }
-            CHOM_HIP(hipMemcpyAsync(W.cols_outer.p, W.h_cols_outer.data(), sizeof(ColState) * R * nprob,
-                                    hipMemcpyHostToDevice, s));
+            CHOM_HIP(hipMemcpyAsync(cols_outer, h_outer, sizeof(ColState) * nc, hipMemcpyHostToDevice, s));
         }
         int act = 0;
-        std::vector<int> stalled(nprob, 0);
+        std::vector<int> stalled(cnt, 0);
         bool any_stalled = false;
-        for (int i = 0; i < nprob; ++i) {
+        for (int i = 0; i < cnt; ++i) {
             int active = 0;
-            for (int r = 0; r < R; ++r) active += W.h_cols_outer[(size_t)i * R + r].done == COL_ACTIVE;
+            for (int r = 0; r < R; ++r) active += h_outer[(size_t)i * R + r].done == COL_ACTIVE;
             act += active;
             if (!active) continue;
-            W.refine_steps[i] = step;
+            W.refine_steps[p0 + i] = step;
             if (fp32_failed[i]) stalled[i] = 1;
             for (int r = 0; r < R; ++r) {
                 const size_t k = (size_t)i * R + r;
-                const ColState &cs = W.h_cols_outer[k];
+                const ColState &cs = h_outer[k];
                 if (cs.done) continue;
                 const bool contracted = step > 0 && cs.rz <= 0.25 * prev_rz[k];
                 slow[k] = (step > 0 && !contracted) ? slow[k] + 1 : 0;
@@ -903,28 +942,53 @@ static int refine_class(chom_batch *B, ClassWS<C, R> &W, const double *ginv_inne
             }
             if (stalled[i]) {
                 any_stalled = true;
-                W.fallback[i] = 1;
+                W.fallback[p0 + i] = 1;
                 for (int r = 0; r < R; ++r) slow[(size_t)i * R + r] = 0;
             }
         }
         if (act == 0 || step == B->opt.max_refine) break;
         if (any_stalled) {
-            CHOM_TRY((fp64_correction<C, R>(B, W, stalled, rtol2)));
+            CHOM_TRY((fp64_correction<C, R>(B, W, G, stalled, rtol2, alloc_mu)));
             // the other active problems still take their FP32 correction this step
-            for (int i = 0; i < nprob; ++i)
+            fbmask.assign(h_outer, h_outer + nc);
+            for (int i = 0; i < cnt; ++i)
                 if (stalled[i])
-                    for (int r = 0; r < R; ++r) W.h_cols_outer[(size_t)i * R + r].done = COL_CONVERGED;
-            CHOM_HIP(hipMemcpyAsync(W.cols_fb.p, W.h_cols_outer.data(), sizeof(ColState) * R * nprob,
-                                    hipMemcpyHostToDevice, s));
+                    for (int r = 0; r < R; ++r) fbmask[(size_t)i * R + r].done = COL_CONVERGED;
+            CHOM_HIP(hipMemcpyAsync(W.cols_fb.p + c0, fbmask.data(), sizeof(ColState) * nc, hipMemcpyHostToDevice, s));
         }
-        const ColState *mask32 = any_stalled ? W.cols_fb.p : W.cols_outer.p;
-        CHOM_TRY((pcg_class<float, C, R>(B, W, false, W.r32.p, W.xf.p, W.rf.p, W.pf.p, W.qf.p, W.minv32.p,
-                                         ginv_inner32, irtol2, 1, mask32, loose)));
-        CHOM_HIP(launch_axpy_x64(W.total_vals, W.x64.p, W.xf.p, s));
-        CHOM_HIP((launch_operator<double, C, R>(L, nprob, L.rg, W.x64.p, W.q64.p, W.accpq.p, nullptr, s)));
+        PcgChain<C, R> K = make_chain<C, R>(W, p0, cnt, ginv_inner32, any_stalled ? W.cols_fb.p : W.cols_outer.p, s,
+                                            G.g32);
+        K.loose = loose;
+        CHOM_TRY((pcg<float, C, R>(B, W, K, W.r32.p, W.xf.p, W.rf.p, W.pf.p, W.qf.p, W.minv32.p, irtol2, 1)));
+        CHOM_HIP(launch_axpy_x64(G.v1 - G.v0, W.x64.p + G.v0, W.xf.p + G.v0, s));
+        CHOM_HIP((launch_operator<double, C, R>(L, cnt, L.rg, W.x64.p, W.q64.p, accpq, nullptr, s)));
         CHOM_HIP((launch_residual64<C, R>(L, W.b.p, W.q64.p, W.r64.p, W.r32.p, s)));
     }
     return CHOM_OK;
+}
+
+// FP32 operator with FP64 refinement for a class: x64 = 0, r64 = b, then the
+// refinement per CG chain (chain_count), each chain on its own problem range.
+template <int C, int R>
+static int refine_class(chom_batch *B, ClassWS<C, R> &W, const std::vector<Prob> &hprobs,
+                        const double *ginv_inner32, double rtol2) {
+    const int nprob = W.L.nprob;
+    hipStream_t s = W.stream;
+    CHOM_HIP(hipMemsetAsync(W.x64.p, 0, sizeof(double) * W.total_vals, s));
+    CHOM_HIP((launch_residual64<C, R>(W.L, W.b.p, nullptr, W.r64.p, W.r32.p, s)));
+    CHOM_HIP(hipMemcpyAsync(W.cols_outer.p, W.cols.p, sizeof(ColState) * R * nprob, hipMemcpyDeviceToDevice, s));
+    std::mutex alloc_mu;
+    if (chain_count(nprob) == 1) {
+        const RefineRange<C, R> G{0, nprob, 0, W.total_vals, s, &W.graph32, &W.graph64};
+        return refine_range<C, R>(B, W, G, ginv_inner32, rtol2, alloc_mu);
+    }
+    const int h = (nprob + 1) / 2;
+    const long long vh = hprobs[h].voff;
+    const RefineRange<C, R> GA{0, h, 0, vh, s, &W.graph32, &W.graph64};
+    const RefineRange<C, R> GB{h, nprob - h, vh, W.total_vals, W.stream_b, &W.graph32b, &W.graph64b};
+    return fork_chains<C, R>(
+        W, [&]() { return refine_range<C, R>(B, W, GA, ginv_inner32, rtol2, alloc_mu); },
+        [&]() { return refine_range<C, R>(B, W, GB, ginv_inner32, rtol2, alloc_mu); });
 }
 
 // Solve one class (mechanical or scalar) for all its problems.  Result: W.avg_out.
@@ -966,7 +1030,7 @@ static int run_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hprobs,
                                           ginv_inner64, rtol2, 0, nullptr)));
         x64 = W.xd.p;
     } else {
-        CHOM_TRY((refine_class<C, R>(B, W, ginv_inner32, rtol2)));
+        CHOM_TRY((refine_class<C, R>(B, W, hprobs, ginv_inner32, rtol2)));
         x64 = W.x64.p;
     }
     CHOM_HIP((launch_project<C, R>(L, x64, W.minv64.p, W.ginv64.p, W.partial.p, s)));
