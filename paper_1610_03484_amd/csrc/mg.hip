@@ -13,9 +13,10 @@
 // of a coarse Kuhn edge -- so P_l is linear interpolation and the coarse matrices
 // are the Galerkin products A_{l+1} = P_l^T A_l P_l, each a 15-point stencil of
 // C x C blocks.  V is one symmetric V(1,1) cycle from level 1 (the n/2 grid)
-// down; the vertex grid itself is not smoothed (a sweep there would cost two
-// stencil applications on a grid an eighth the size of the fine lattice per
-// CG step, for 20-28% fewer steps in a CPU prototype).  Smoother: l1
+// down; the vertex grid itself is not smoothed: its l1 block Jacobi would repeat
+// the point-block Jacobi of M at the vertices (whose diagonal blocks are those
+// of A_0), and a V-cycle from level 0 measured the same CG step counts at
+// 40% more time per step.  Smoother: l1
 // block Jacobi (the diagonal block plus the absolute off-block row sums on its
 // diagonal), convergent with no damping parameter; the coarsest level takes a
 // fixed number of such sweeps.  V is therefore a fixed symmetric positive
