@@ -379,8 +379,9 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
         // the up-front-load kernel (LDS: 3 level-2 vectors, 2 level-3 vectors, level-3 stencils and
         // inverses; on a level-1 coarsest the two iterates)
         M.small_elems = 0;
+        M.small_bs = 512;
         if (fp32 && !std::getenv("CHOM_MG_GENERIC")) {
-            long long need = 0;
+            long long need = 0, own = 0;
             bool ok = true;
             for (auto &P : hp) {
                 const Geo &G = B->distinct[P.geo]->geo;
@@ -390,14 +391,18 @@ static int setup_class(chom_batch *B, ClassWS<C, R> &W, std::vector<Prob> &hp, i
                     const long long n1 = (long long)G.mg_lw[1] * G.mg_lw[1] * G.mg_lw[1];
                     if (n1 > 512) ok = false;
                     need = std::max(need, 2 * n1 * C);
+                    own = std::max(own, n1);
                     continue;
                 }
                 const long long n2 = (long long)G.mg_lw[2] * G.mg_lw[2] * G.mg_lw[2];
                 const long long n3 = lc == 3 ? (long long)G.mg_lw[3] * G.mg_lw[3] * G.mg_lw[3] : 0;
                 if (lc > 3 || n2 > 512 || n3 > 512) ok = false;
                 need = std::max(need, 3 * (n2 + 1) * C + 2 * (n3 + 1) * C + n3 * MG_SLOTS * CC + n3 * MS);
+                own = std::max(own, std::max(n2, n3));
             }
             if (ok && need * (long long)sizeof(float) <= 64 * 1024) M.small_elems = need;
+            const char *bs = std::getenv("CHOM_MG_SMALL_BS");
+            M.small_bs = (own <= 256 && !(bs && std::atoi(bs) == 512)) ? 256 : 512;
         }
         const size_t np = (size_t)moff;
         CHOM_HIP(W.mgA64.ensure(np * MG_SLOTS * CC));

@@ -55,6 +55,7 @@ struct Launch {
         long long lds_elems;       // LDS of the fused kernel (elements of the solve precision)
         int lds_vec, lds_sten;     // levels >= 2 vectors / coarsest stencils in LDS
         long long small_elems;     // > 0: FP32 levels >= 2 small enough for mg_fused_small_kernel (its LDS, floats)
+        int small_bs;              // its threads (256 or 512: at least the points of the largest owned level)
         void *W;                   // coarse part of B C^T [moff + vertex][4C][C]
     } mg;
 };

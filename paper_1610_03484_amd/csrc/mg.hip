@@ -1027,8 +1027,8 @@ __global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_kernel(const Geo *geos, 
 // stencil row, l1 inverse and neighbour indices in registers; level-3 stencils,
 // inverses and all level >= 2 vectors sit in LDS -- so the kernel waits on
 // memory about once instead of once per stage.
-template <int C, int R>
-__global__ __launch_bounds__(MG_FUSED_BS) void mg_fused_small_kernel(const Geo *geos, const Prob *probs,
+template <int C, int R, int BS>
+__global__ __launch_bounds__(BS) void mg_fused_small_kernel(const Geo *geos, const Prob *probs,
                                                                      VPtr<float, C, R> Q, int sweeps,
                                                                      const int *prob_active) {
     using T = float;
@@ -1435,8 +1435,15 @@ hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *accbuf, const i
     mg_resid1_kernel<T, C, R, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q, prob_active);
     if constexpr (std::is_same<T, float>::value) {
         if (M.small_elems > 0) {
-            mg_fused_small_kernel<C, R><<<dim3(R, L.nprob), MG_FUSED_BS, (size_t)M.small_elems * sizeof(float), s>>>(
-                L.geos, L.probs, Q, M.sweeps, prob_active);
+            // thread t owns point t of the level-1 (coarsest) or level-2 grid: 256 threads
+            // when every owned level has at most 256 points, else 512
+            if (M.small_bs == 256)
+                mg_fused_small_kernel<C, R, 256><<<dim3(R, L.nprob), 256, (size_t)M.small_elems * sizeof(float), s>>>(
+                    L.geos, L.probs, Q, M.sweeps, prob_active);
+            else
+                mg_fused_small_kernel<C, R, MG_FUSED_BS><<<dim3(R, L.nprob), MG_FUSED_BS,
+                                                           (size_t)M.small_elems * sizeof(float), s>>>(
+                    L.geos, L.probs, Q, M.sweeps, prob_active);
         } else {
             mg_fused_kernel<T, C, R><<<dim3(R, L.nprob), MG_FUSED_BS, (size_t)M.lds_elems * sizeof(T), s>>>(
                 L.geos, L.probs, Q, M.sweeps, M.lds_vec, M.lds_sten, prob_active);
