@@ -579,7 +579,7 @@ def surrogate_leg(args, torch, plain12_rate=None):
                training_solve_s=t_solve, training_s=t_train, epochs=args.epochs,
                batched_rate_12cubed=batched12, plain_rate_12cubed=plain12_rate,
                speedup_vs_plain_12cubed=rate / plain12_rate, speedup_vs_batched_12cubed=rate / batched12,
-               heldout_points=len(hp), heldout_judge="CPU FP64 oracle (stored)",
+               heldout_points=len(hp), heldout_reference="CPU FP64 oracle (stored)",
                heldout_max_err=float(err.max()), heldout_max_err_network_alone=float(raw.max()),
                heldout_fallbacks=int(nfbh),
                predict_kernel=dict(avg_launch_us=t_pred * 1e6, achieved_TFLOPs=flops / t_pred / 1e12,
@@ -633,7 +633,7 @@ def run_c2(args, torch):
                                     fro=float(e64[:, 0].max()), elem=float(e64[:, 1].max()),
                                     energy=float(e64[:, 2].max()), plain_path_fro=float(ep[:, 0].max()),
                                     plain_path_energy=float(ep[:, 2].max()),
-                                    judge="FP64 GPU path at rtol 1e-12 (oracle-matched at 8^3 and 12^3 by tests)"))
+                                    reference="FP64 GPU path at rtol 1e-12 (oracle-matched at 8^3 and 12^3 by tests)"))
         rb.close()
         for r in refs:
             r.close()
@@ -682,7 +682,7 @@ def run_c2(args, torch):
         eo = np.array([result_errors(got[i], res[j]) for j, i in enumerate(idx8)])
         acc["vs_oracle"] = dict(items=idx8, size=8, fro=float(eo[:, 0].max()), elem=float(eo[:, 1].max()),
                                 energy=float(eo[:, 2].max()),
-                                judge="CPU FP64 oracle, solved in this run (substitution route)")
+                                reference="CPU FP64 oracle, solved in this run (substitution route)")
         log(f"batch vs oracle (8^3 items): fro {eo[:, 0].max():.2e} energy {eo[:, 2].max():.2e}")
         cpu = dict(value=len(idx8) / wall, unit="homogenisations/s", cores=len(idx8), kind="oracle",
                    sample=(f"CPU FP64 oracle (Lagrange P2, SuperLU, constraints by substitution) on the "
@@ -763,7 +763,7 @@ def run_single(args, wl, torch):
         got, ref = _stack(C, K, D), _stack(Cr, Kr, Dr)
         e = np.array([result_errors(got[i], ref[j]) for j, i in enumerate(acc_items)])
         err = dict(fro=float(e[:, 0].max()), elem=float(e[:, 1].max()), energy=float(e[:, 2].max()),
-                   judge="FP64 GPU path at rtol 1e-12")
+                   reference="FP64 GPU path at rtol 1e-12")
         rb.close()
     fp32 = wl["precision"] != "fp64"
     if args.workload == "c3":

@@ -345,8 +345,8 @@ template <> struct Mfma<double> {
 
 // ------------------------------------------------------------------ element factors
 // Q_e of every tet of every problem, packed: upper triangle (row-major) of the
-// symmetric (3C) x (3C) matrix with index (k, c) = k C + c (the survey's 45 / 6
-// numbers per element), FP64 master and FP32 copy.
+// symmetric (3C) x (3C) matrix with index (k, c) = k C + c (45 numbers per element for
+// the mechanics, 6 for a scalar field), FP64 master and FP32 copy.
 template <int C>
 __global__ __launch_bounds__(256) void hp_factor_kernel(const Geo *geos, const Prob *probs, double *ef64, float *ef32) {
     constexpr int NQ = (3 * C) * (3 * C + 1) / 2;
