@@ -345,7 +345,10 @@ void chom_rve_destroy(chom_rve *rve);
  * every boundary vertex and boundary edge) or CHOM_BC_PERIODIC (the faces
  * x_d = hi_d must match x_d = lo_d vertex for vertex and edge for edge; the
  * class of the corner lo is pinned, which fixes the translations and leaves
- * C_bar unchanged); uniform traction is not offered on general meshes.
+ * C_bar unchanged) or CHOM_BC_NEUMANN (uniform traction, Sec. 2 item 3: the
+ * fluctuation is held to zero surface moments int u_i n_j dS and zero mean
+ * int u_i dV, and PCG runs on that subspace with the projection
+ * z = M^-1 (r - C^T y), y = (C M^-1 C^T)^-1 C M^-1 r).
  * opt: precision must be CHOM_FP64 (precond is ignored: point-block Jacobi);
  * rtol, max_iter, c_sat, degrade_yarn, device_ptrs (params and outputs of
  * chom_urve_homogenise) and hip_stream are used.  The mesh arrays are copied.

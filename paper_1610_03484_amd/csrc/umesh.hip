@@ -48,6 +48,12 @@ struct chom_urve {
     // solve workspace, sized on first use for the largest chunk of records
     chom::DevBuf<double> x, r, z, p, q, b, minv, dg, vfull, wfull, acc;
     chom::DevBuf<int> active;
+    // uniform traction: constraint rows per slot [nslot][4] (surface moments
+    // int phi n_x, n_y, n_z dS and the volume weight int phi dV), their host copy,
+    // and per chunk the inverse Gram matrices [record][S][S], the sums C M^-1 r
+    // and the projection coefficients [column][S] (S = 4 C)
+    chom::DevBuf<double> crow, ginv, wacc, ycol;
+    std::vector<double> hrow;
     ~chom_urve() {
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -280,15 +286,51 @@ __device__ inline void apply_minv(const double *M, const double rv[C], double zv
 
 // PCG vector kernels: grid (blocks over the slots, columns); the column's record
 // is column / R (its preconditioner blocks).  acc layout per column: [0] r.z,
-// [1] p.q.
-template <int C, int R>
+// [1] p.q.  With PROJ (uniform traction: the fluctuation is constrained to
+// C u = 0, the rows of Sec. 2 item 3), the kernels also sum w = C M^-1 r into
+// wacc [column][S] (row (i, a): component i against constraint row a of crow).
+
+// Sums v[0..NS) over the block, added to dst[k * stride] (wave sums, then one
+// exchange through LDS).
+template <int NS>
+__device__ inline void block_sums_add(double (&v)[NS], double *dst, int stride) {
+    __shared__ double red[NS][UB / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NS; ++k) red[k][w] = v[k];
+    __syncthreads();
+    if (threadIdx.x < NS) {
+        double t = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[threadIdx.x][q];
+        atomicAdd(&dst[threadIdx.x * stride], t);
+    }
+}
+
+// r.M^-1 r of one slot's residual into rz and (PROJ) its C M^-1 r terms into wl.
+template <int C, bool PROJ>
+__device__ inline void rz_terms(const double rv[C], const double zv[C], const double *crow, long long s, double &rz,
+                                double (&wl)[4 * C]) {
+    for (int c = 0; c < C; ++c) rz += rv[c] * zv[c];
+    if constexpr (PROJ) {
+        double row[4];
+        for (int a = 0; a < 4; ++a) row[a] = crow[s * 4 + a];
+        for (int i = 0; i < C; ++i)
+            for (int a = 0; a < 4; ++a) wl[i * 4 + a] += row[a] * zv[i];
+    }
+}
+
+template <int C, int R, bool PROJ>
 __global__ __launch_bounds__(UB) void ucg_init_kernel(long long nslot, const double *b, const double *minv, double *x,
-                                                      double *r, double *z, double *p, double *acc) {
-    __shared__ double red[UB / 64];
+                                                      double *r, double *z, double *p, double *acc,
+                                                      const double *crow, double *wacc) {
     constexpr int MS = C == 3 ? 6 : 1;
     const int lc = blockIdx.y, rec = lc / R;
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    double loc = 0.0;
+    double rz = 0.0, wl[4 * C];
+    for (int k = 0; k < 4 * C; ++k) wl[k] = 0.0;
     if (s < nslot) {
         const long long o = ((long long)lc * nslot + s) * C;
         double rv[C], zv[C];
@@ -299,11 +341,16 @@ __global__ __launch_bounds__(UB) void ucg_init_kernel(long long nslot, const dou
             r[o + c] = rv[c];
             z[o + c] = zv[c];
             p[o + c] = zv[c];
-            loc += rv[c] * zv[c];
         }
+        rz_terms<C, PROJ>(rv, zv, crow, s, rz, wl);
     }
-    const double t = block_sum(loc, red);
-    if (threadIdx.x == 0) atomicAdd(&acc[2 * lc], t);
+    if constexpr (PROJ) {
+        block_sums_add<4 * C>(wl, wacc + (long long)lc * 4 * C, 1);   // r.z follows from ucg_proj_kernel
+    } else {
+        __shared__ double red[UB / 64];
+        const double t0 = block_sum(rz, red);
+        if (threadIdx.x == 0) atomicAdd(&acc[2 * lc], t0);
+    }
 }
 
 template <int C>
@@ -322,17 +369,17 @@ __global__ __launch_bounds__(UB) void ucg_pq_kernel(long long nslot, const doubl
     if (threadIdx.x == 0) atomicAdd(&acc[2 * lc + 1], t);
 }
 
-template <int C, int R>
+template <int C, int R, bool PROJ>
 __global__ __launch_bounds__(UB) void ucg_update_kernel(long long nslot, const double *minv, const double *p,
                                                         const double *q, const UCol *cols, double *x, double *r,
-                                                        double *z, double *acc) {
-    __shared__ double red[UB / 64];
+                                                        double *z, double *acc, const double *crow, double *wacc) {
     constexpr int MS = C == 3 ? 6 : 1;
     const int lc = blockIdx.y, rec = lc / R;
     if (cols[lc].done) return;
     const double al = cols[lc].alpha;
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    double loc = 0.0;
+    double rz = 0.0, wl[4 * C];
+    for (int k = 0; k < 4 * C; ++k) wl[k] = 0.0;
     if (s < nslot) {
         const long long o = ((long long)lc * nslot + s) * C;
         double rv[C], zv[C];
@@ -342,13 +389,17 @@ __global__ __launch_bounds__(UB) void ucg_update_kernel(long long nslot, const d
             r[o + c] = rv[c];
         }
         apply_minv<C>(minv + ((long long)rec * nslot + s) * MS, rv, zv);
-        for (int c = 0; c < C; ++c) {
-            z[o + c] = zv[c];
-            loc += rv[c] * zv[c];
-        }
+        if constexpr (!PROJ)
+            for (int c = 0; c < C; ++c) z[o + c] = zv[c];
+        rz_terms<C, PROJ>(rv, zv, crow, s, rz, wl);
     }
-    const double t = block_sum(loc, red);
-    if (threadIdx.x == 0) atomicAdd(&acc[2 * lc], t);
+    if constexpr (PROJ) {
+        block_sums_add<4 * C>(wl, wacc + (long long)lc * 4 * C, 1);   // r.z follows from ucg_proj_kernel
+    } else {
+        __shared__ double red[UB / 64];
+        const double t0 = block_sum(rz, red);
+        if (threadIdx.x == 0) atomicAdd(&acc[2 * lc], t0);
+    }
 }
 
 template <int C>
@@ -362,15 +413,65 @@ __global__ __launch_bounds__(UB) void ucg_dir_kernel(long long nslot, const doub
     for (int c = 0; c < C; ++c) p[o + c] = z[o + c] + be * p[o + c];
 }
 
+// Uniform traction: r <- r - C^T y and z = M^-1 r (so C z = 0), with r.z summed
+// from the projected vectors themselves (no cancellation against C M^-1 r).
+template <int C, int R>
+__global__ __launch_bounds__(UB) void ucg_proj_kernel(long long nslot, const double *minv, const double *crow,
+                                                      const double *ycol, const UCol *cols, double *r, double *z,
+                                                      double *acc) {
+    __shared__ double red[UB / 64];
+    constexpr int MS = C == 3 ? 6 : 1;
+    const int lc = blockIdx.y, rec = lc / R;
+    if (cols[lc].done) return;   // uniform over the block
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    double loc = 0.0;
+    if (s < nslot) {
+        const long long o = ((long long)lc * nslot + s) * C;
+        const double *y = ycol + (long long)lc * 4 * C;
+        double row[4], rv[C], zv[C];
+        for (int a = 0; a < 4; ++a) row[a] = crow[s * 4 + a];
+        for (int i = 0; i < C; ++i) {
+            double ct = 0.0;
+            for (int a = 0; a < 4; ++a) ct += row[a] * y[i * 4 + a];
+            rv[i] = r[o + i] - ct;
+            r[o + i] = rv[i];
+        }
+        apply_minv<C>(minv + ((long long)rec * nslot + s) * MS, rv, zv);
+        for (int c = 0; c < C; ++c) {
+            z[o + c] = zv[c];
+            loc += rv[c] * zv[c];
+        }
+    }
+    const double t = block_sum(loc, red);
+    if (threadIdx.x == 0) atomicAdd(&acc[2 * lc], t);
+}
+
 // Step length (phase 0) or new direction coefficient and the stopping test
 // (phase 1): r.z <= rtol^2 E, E the column's energy estimate (the linear-field
 // energy minus alpha r.z of every step, kept in [1e-6, 1] of the linear-field
 // energy).  One thread per column; the sums are cleared for the next step.
+// Phase 3 (uniform traction, S = 4 C > 0): the projection coefficients
+// y = G^-1 w of the column (G = C M^-1 C^T of its record, w = C M^-1 r summed by
+// the update or init kernel), before ucg_proj_kernel.
 __global__ __launch_bounds__(UB) void ucg_finish_kernel(int ncol, int phase, double rtol2, int max_iter, UCol *cols,
-                                                        double *acc, int *active) {
+                                                        double *acc, int *active, int S, int R, const double *ginv,
+                                                        double *wacc, double *ycol) {
     const int lc = blockIdx.x * blockDim.x + threadIdx.x;
     if (lc >= ncol) return;
     UCol &cs = cols[lc];
+    if (phase == 3) {
+        double *w = wacc + (long long)lc * S, *y = ycol + (long long)lc * S;
+        if (cs.done == 0) {
+            const double *Gi = ginv + (long long)(lc / R) * S * S;
+            for (int i = 0; i < S; ++i) {
+                double t = 0.0;
+                for (int j = 0; j < S; ++j) t += Gi[i * S + j] * w[j];
+                y[i] = t;
+            }
+        }
+        for (int i = 0; i < S; ++i) w[i] = 0.0;
+        return;
+    }
     if (phase == 2) {   // start: r.z of the initial residual
         cs.rz = acc[2 * lc];
         acc[2 * lc] = 0.0;
@@ -479,6 +580,8 @@ int ufail(const std::string &msg, int code) {
 
 int grid_of(long long n) { return (int)std::max<long long>(1, (n + UB - 1) / UB); }
 
+bool invert_small(const double *A, int n, double *out);
+
 // One physics (C components, R load cases) for nb records at once (column =
 // record * R + load case): PCG per column, then per record the energy-form
 // matrix A [R][R] and the volume average Aavg (outputs [nb][R][R]; iters,
@@ -505,6 +608,15 @@ int usolve(chom_urve *U, const UMat *hmats, int nb, double rtol, int max_iter, d
     CHOM_HIP(mats.ensure(nb));
     CHOM_HIP(hipMemcpyAsync(mats.p, hmats, sizeof(UMat) * nb, hipMemcpyHostToDevice, s));
     CHOM_HIP(hipMemsetAsync(U->acc.p, 0, sizeof(double) * nacc, s));
+    // uniform traction: PCG on C u = 0 (projected directions, Gram inverses per record)
+    const bool proj = U->bc == CHOM_BC_NEUMANN;
+    constexpr int S = 4 * C;
+    if (proj) {
+        CHOM_HIP(U->wacc.ensure((size_t)ncol * S));
+        CHOM_HIP(U->ycol.ensure((size_t)ncol * S));
+        CHOM_HIP(U->ginv.ensure((size_t)nb * S * S));
+        CHOM_HIP(hipMemsetAsync(U->wacc.p, 0, sizeof(double) * ncol * S, s));
+    }
     // right sides b = -K x_lin (the fluctuation problems) and the linear-field energies
     CHOM_HIP(hipMemsetAsync(U->b.p, 0, sizeof(double) * nvec, s));
     double *eacc = U->acc.p + 2 * ncol;   // after the CG sums
@@ -518,6 +630,38 @@ int usolve(chom_urve *U, const UMat *hmats, int nb, double rtol, int max_iter, d
                                                          U->dg.p);
     uinv_kernel<C><<<grid_of((long long)nb * ns), UB, 0, s>>>((long long)nb * ns, U->dg.p, U->minv.p);
     CHOM_HIP(hipGetLastError());
+    if (proj) {   // G = C M^-1 C^T per record (FP64, on the host), inverted
+        std::vector<double> hm((size_t)nb * ns * MS), hg((size_t)nb * S * S);
+        CHOM_HIP(hipMemcpyAsync(hm.data(), U->minv.p, sizeof(double) * hm.size(), hipMemcpyDeviceToHost, s));
+        CHOM_HIP(hipStreamSynchronize(s));
+        for (int rec = 0; rec < nb; ++rec) {
+            std::vector<double> G((size_t)S * S, 0.0);
+            for (long long sl = 0; sl < ns; ++sl) {
+                const double *Mi = &hm[((size_t)rec * ns + sl) * MS];
+                double M[C][C];
+                if constexpr (C == 3) {
+                    M[0][0] = Mi[0]; M[1][1] = Mi[1]; M[2][2] = Mi[2];
+                    M[0][1] = M[1][0] = Mi[3]; M[1][2] = M[2][1] = Mi[4]; M[0][2] = M[2][0] = Mi[5];
+                } else {
+                    M[0][0] = Mi[0];
+                }
+                const double *row = &U->hrow[(size_t)sl * 4];
+                for (int i = 0; i < C; ++i)
+                    for (int j = 0; j < C; ++j)
+                        for (int a = 0; a < 4; ++a) {
+                            const double t = row[a] * M[i][j];
+                            for (int b2 = 0; b2 < 4; ++b2) G[(size_t)(i * 4 + a) * S + j * 4 + b2] += t * row[b2];
+                        }
+            }
+            if (!invert_small(G.data(), S, &hg[(size_t)rec * S * S]))
+                return ufail("chom_urve_homogenise: constraint Gram matrix singular (uniform traction)", CHOM_EDEVICE);
+        }
+        CHOM_HIP(hipMemcpyAsync(U->ginv.p, hg.data(), sizeof(double) * hg.size(), hipMemcpyHostToDevice, s));
+        CHOM_HIP(hipStreamSynchronize(s));   // hg dies here
+    }
+    const int Sp = proj ? S : 0;
+    double *wacc = proj ? U->wacc.p : nullptr, *ycol = proj ? U->ycol.p : nullptr;
+    const double *ginv = proj ? U->ginv.p : nullptr, *crow = proj ? U->crow.p : nullptr;
     std::vector<double> heref(ncol);
     CHOM_HIP(hipMemcpyAsync(heref.data(), eacc, sizeof(double) * ncol, hipMemcpyDeviceToHost, s));
     CHOM_HIP(hipStreamSynchronize(s));
@@ -530,8 +674,20 @@ int usolve(chom_urve *U, const UMat *hmats, int nb, double rtol, int max_iter, d
     const dim3 gv(grid_of(ns), ncol);
     const int gf = (ncol + UB - 1) / UB;
     const double rtol2 = rtol * rtol;
-    ucg_init_kernel<C, R><<<gv, UB, 0, s>>>(ns, U->b.p, U->minv.p, U->x.p, U->r.p, U->z.p, U->p.p, U->acc.p);
-    ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 2, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
+    if (proj)
+        ucg_init_kernel<C, R, true><<<gv, UB, 0, s>>>(ns, U->b.p, U->minv.p, U->x.p, U->r.p, U->z.p, U->p.p,
+                                                      U->acc.p, crow, wacc);
+    else
+        ucg_init_kernel<C, R, false><<<gv, UB, 0, s>>>(ns, U->b.p, U->minv.p, U->x.p, U->r.p, U->z.p, U->p.p,
+                                                       U->acc.p, nullptr, nullptr);
+    if (proj) {   // the projected residual and its z (first direction: beta = 0)
+        ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 3, rtol2, max_iter, cols.p, U->acc.p, U->active.p, Sp, R, ginv,
+                                            wacc, ycol);
+        ucg_proj_kernel<C, R><<<gv, UB, 0, s>>>(ns, U->minv.p, crow, ycol, cols.p, U->r.p, U->z.p, U->acc.p);
+    }
+    ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 2, rtol2, max_iter, cols.p, U->acc.p, U->active.p, Sp, R, ginv, wacc,
+                                        ycol);
+    if (proj) ucg_dir_kernel<C><<<gv, UB, 0, s>>>(ns, U->z.p, cols.p, U->p.p);
     CHOM_HIP(hipGetLastError());
     std::vector<int> hact(ncol);
     for (int it = 0; it < max_iter; it += 8) {
@@ -546,10 +702,21 @@ int usolve(chom_urve *U, const UMat *hmats, int nb, double rtol, int max_iter, d
                                                                        U->geo.p, U->elem.p, U->vco.p, mats.p,
                                                                        U->active.p, U->p.p, U->q.p, nullptr);
             ucg_pq_kernel<C><<<gv, UB, 0, s>>>(ns, U->p.p, U->q.p, cols.p, U->acc.p);
-            ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 0, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
-            ucg_update_kernel<C, R><<<gv, UB, 0, s>>>(ns, U->minv.p, U->p.p, U->q.p, cols.p, U->x.p, U->r.p, U->z.p,
-                                                      U->acc.p);
-            ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 1, rtol2, max_iter, cols.p, U->acc.p, U->active.p);
+            ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 0, rtol2, max_iter, cols.p, U->acc.p, U->active.p, Sp, R, ginv,
+                                                wacc, ycol);
+            if (proj)
+                ucg_update_kernel<C, R, true><<<gv, UB, 0, s>>>(ns, U->minv.p, U->p.p, U->q.p, cols.p, U->x.p,
+                                                                U->r.p, U->z.p, U->acc.p, crow, wacc);
+            else
+                ucg_update_kernel<C, R, false><<<gv, UB, 0, s>>>(ns, U->minv.p, U->p.p, U->q.p, cols.p, U->x.p,
+                                                                 U->r.p, U->z.p, U->acc.p, nullptr, nullptr);
+            if (proj) {
+                ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 3, rtol2, max_iter, cols.p, U->acc.p, U->active.p, Sp, R,
+                                                    ginv, wacc, ycol);
+                ucg_proj_kernel<C, R><<<gv, UB, 0, s>>>(ns, U->minv.p, crow, ycol, cols.p, U->r.p, U->z.p, U->acc.p);
+            }
+            ucg_finish_kernel<<<gf, UB, 0, s>>>(ncol, 1, rtol2, max_iter, cols.p, U->acc.p, U->active.p, Sp, R, ginv,
+                                                wacc, ycol);
             ucg_dir_kernel<C><<<gv, UB, 0, s>>>(ns, U->z.p, cols.p, U->p.p);
             CHOM_HIP(hipGetLastError());
         }
@@ -584,6 +751,37 @@ int usolve(chom_urve *U, const UMat *hmats, int nb, double rtol, int max_iter, d
     return status;
 }
 
+// Inverse of a small dense matrix (Gauss-Jordan, partial pivoting); false when a
+// pivot falls below 1e-13 of the largest diagonal entry.
+bool invert_small(const double *A, int n, double *out) {
+    std::vector<double> M((size_t)n * 2 * n, 0.0);
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) M[(size_t)i * 2 * n + j] = A[(size_t)i * n + j];
+        M[(size_t)i * 2 * n + n + i] = 1.0;
+        dmax = std::max(dmax, std::fabs(A[(size_t)i * n + i]));
+    }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < n; ++i)
+            if (std::fabs(M[(size_t)i * 2 * n + c]) > std::fabs(M[(size_t)piv * 2 * n + c])) piv = i;
+        if (!(std::fabs(M[(size_t)piv * 2 * n + c]) > 1e-13 * dmax)) return false;
+        if (piv != c)
+            for (int j = 0; j < 2 * n; ++j) std::swap(M[(size_t)c * 2 * n + j], M[(size_t)piv * 2 * n + j]);
+        const double d = 1.0 / M[(size_t)c * 2 * n + c];
+        for (int j = 0; j < 2 * n; ++j) M[(size_t)c * 2 * n + j] *= d;
+        for (int i = 0; i < n; ++i) {
+            if (i == c) continue;
+            const double f = M[(size_t)i * 2 * n + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < 2 * n; ++j) M[(size_t)i * 2 * n + j] -= f * M[(size_t)c * 2 * n + j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) out[(size_t)i * n + j] = M[(size_t)i * 2 * n + n + j];
+    return true;
+}
+
 bool cholesky_ok(const double *A, int n) {
     double L[6][6] = {};
     for (int i = 0; i < n; ++i)
@@ -609,8 +807,8 @@ extern "C" int chom_urve_create(const chom_mesh *mesh, const chom_materials *mat
                                 chom_urve **out) {
     if (!mesh || !mat || !out) return ufail("chom_urve_create: null argument", CHOM_EINVAL);
     *out = nullptr;
-    if (bc != CHOM_BC_DIRICHLET && bc != CHOM_BC_PERIODIC)
-        return ufail("chom_urve_create: general meshes take linear Dirichlet (0) or periodic (1) conditions",
+    if (bc != CHOM_BC_DIRICHLET && bc != CHOM_BC_PERIODIC && bc != CHOM_BC_NEUMANN)
+        return ufail("chom_urve_create: bc must be linear Dirichlet (0), periodic (1) or uniform traction (2)",
                      CHOM_EINVAL);
     chom_options o;
     chom_default_options(&o);
@@ -724,7 +922,7 @@ extern "C" int chom_urve_create(const chom_mesh *mesh, const chom_materials *mat
         for (long long v = 0; v < nv; ++v) fixed[v] = face[v] != 0;
         for (long long k = 0; k < ne; ++k)
             fixed[nv + k] = (face[edges[k].first] & face[edges[k].second]) != 0;   // both ends on one face
-    } else {
+    } else if (bc == CHOM_BC_PERIODIC) {
         // vertex images: every coordinate on a hi face moved to lo
         std::map<std::tuple<long long, long long, long long>, long long> at;
         // coordinates quantised to 1e-6 of the box (absorbs rounding)
@@ -778,6 +976,48 @@ extern "C" int chom_urve_create(const chom_mesh *mesh, const chom_materials *mat
     for (long long i = 0; i < nnode; ++i)
         if (master[i] != i) hsmap[i] = hsmap[master[i]];
     if (ns < 1) return ufail("chom_urve_create: no free unknowns", CHOM_EMESH);
+    // Uniform traction (every node free, slot = node): the constraint rows of
+    // Sec. 2 item 3 on the fluctuation, int_dOmega u_i n_j dS = 0 and
+    // int_Omega u_i dV = 0, per node as [int phi n_x, n_y, n_z dS, int phi dV].
+    // A hat integrates to A/3 over a boundary triangle and |e|/4 over a tet; an
+    // edge function 4 lam_a lam_b to A/3 and |e|/5.  A boundary triangle is a
+    // tet face whose three vertices lie on one box face (outward normal +-e_d).
+    std::vector<double> hrow;
+    if (bc == CHOM_BC_NEUMANN) {
+        hrow.assign((size_t)ns * 4, 0.0);
+        for (long long e = 0; e < nt; ++e) {
+            const double ve = hgeo[10 * e + 9];
+            for (int a = 0; a < 4; ++a) hrow[(size_t)hsmap[hconn[10 * e + a]] * 4 + 3] += ve / 4.0;
+            for (int le = 0; le < 6; ++le) hrow[(size_t)hsmap[hconn[10 * e + 4 + le]] * 4 + 3] += ve / 5.0;
+            for (int o = 0; o < 4; ++o) {   // the face opposite local vertex o
+                int fv[3], k = 0;
+                for (int a = 0; a < 4; ++a)
+                    if (a != o) fv[k++] = a;
+                const int ga = ht[4 * e + fv[0]], gb = ht[4 * e + fv[1]], gc = ht[4 * e + fv[2]];
+                const int common = face[ga] & face[gb] & face[gc];
+                if (!common) continue;
+                int bit = 0;
+                while (!((common >> bit) & 1)) ++bit;
+                const int d = bit / 2;
+                const double sgn = (bit & 1) ? 1.0 : -1.0;
+                double u[3], w[3];
+                for (int q = 0; q < 3; ++q) {
+                    u[q] = hc[3 * gb + q] - hc[3 * ga + q];
+                    w[q] = hc[3 * gc + q] - hc[3 * ga + q];
+                }
+                const double cx = u[1] * w[2] - u[2] * w[1], cy = u[2] * w[0] - u[0] * w[2],
+                             cz = u[0] * w[1] - u[1] * w[0];
+                const double third = sgn * 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz) / 3.0;
+                for (int q = 0; q < 3; ++q) hrow[(size_t)hsmap[ht[4 * e + fv[q]]] * 4 + d] += third;
+                for (int le = 0; le < 6; ++le) {
+                    int a, b;
+                    edge_verts(le, a, b);
+                    if (a == o || b == o) continue;
+                    hrow[(size_t)hsmap[hconn[10 * e + 4 + le]] * 4 + d] += third;
+                }
+            }
+        }
+    }
     {
         double m10[10], t4[4], d4[4];
         if (chom_material_constants(mat, nullptr, o.c_sat, o.degrade_yarn, m10, t4, d4, nullptr) != CHOM_OK)
@@ -810,6 +1050,11 @@ extern "C" int chom_urve_create(const chom_mesh *mesh, const chom_materials *mat
     CHOM_HIP(U->geo.ensure(10 * nt));
     CHOM_HIP(U->elem.ensure(nt));
     CHOM_HIP(U->vco.ensure(3 * nv));
+    if (bc == CHOM_BC_NEUMANN) {
+        CHOM_HIP(U->crow.ensure(hrow.size()));
+        CHOM_HIP(hipMemcpy(U->crow.p, hrow.data(), sizeof(double) * hrow.size(), hipMemcpyHostToDevice));
+        U->hrow.swap(hrow);
+    }
     hipStream_t s = U->stream;
     CHOM_HIP(hipMemcpyAsync(U->conn.p, hconn.data(), sizeof(int) * 10 * nt, hipMemcpyHostToDevice, s));
     CHOM_HIP(hipMemcpyAsync(U->smap.p, hsmap.data(), sizeof(int) * nnode, hipMemcpyHostToDevice, s));

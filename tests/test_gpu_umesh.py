@@ -4,7 +4,10 @@ The meshes are seeded unstructured boxes (chom_inputs.unstructured_box: an
 extra vertex per cell, face diagonals by periodic id, jittered vertices) tagged
 by the synthetic weave.  The oracle solves the same discrete problem (Lagrange
 P2 on the same tets, sparse direct), so the FP64 GPU path at rtol 1e-12 meets
-it to 1e-9 in the three measures of the other parity tests.
+it to 1e-9 in the three measures of the other parity tests.  Uniform traction
+(CHOM_BC_NEUMANN) runs PCG on the constrained subspace (the library's rows are
+the hierarchic-basis integrals, the oracle's the Lagrange ones: the same
+constraint set).
 """
 import numpy as np
 import pytest
@@ -14,7 +17,7 @@ from gpu_util import banner, require_gpu, result_errors, upper21, upper6
 from oracle import fem, materials as M, mesh as omesh
 
 pytestmark = pytest.mark.gpu
-BC = {"dirichlet": fem.BC_DIRICHLET, "periodic": fem.BC_PERIODIC}
+BC = {"dirichlet": fem.BC_DIRICHLET, "periodic": fem.BC_PERIODIC, "neumann": fem.BC_NEUMANN}
 
 
 def _weave(nc, seed):
@@ -43,7 +46,7 @@ def test_tagger_on_an_unstructured_mesh_matches_oracle():
     assert np.abs(ax[~ties] - ax_o[~ties]).max() <= 1e-14
 
 
-@pytest.mark.parametrize("bc", ["dirichlet", "periodic"])
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic", "neumann"])
 def test_unstructured_rve_matches_oracle(bc):
     require_gpu()
     coords, tets, phase, axis = _weave(3, seed=5)
@@ -100,7 +103,7 @@ def test_unstructured_records_in_chunks_equal_single_solves():
     assert all(r["status"] == 0 for r in rep)
 
 
-@pytest.mark.parametrize("bc", ["dirichlet", "periodic"])
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic", "neumann"])
 def test_homogeneous_unstructured_rve_returns_its_material(bc):
     require_gpu()
     coords, tets = ci.unstructured_box(3, seed=8)
@@ -121,7 +124,7 @@ def test_unstructured_rve_rejects_bad_meshes_and_options():
     require_gpu()
     from paper_1610_03484_amd import _lib as L
     coords, tets, phase, axis = _weave(2, seed=9)
-    for kw, bc in ((dict(precision="fp32_refined"), "periodic"), ({}, "neumann")):
+    for kw, bc in ((dict(precision="fp32_refined"), "periodic"), ({}, 3)):   # 3: no such condition
         with pytest.raises(L.ChomError) as ei:
             _urve(coords, tets, phase, axis, bc, **kw)
         assert ei.value.status == L.CHOM_EINVAL
