@@ -550,6 +550,11 @@ __global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const
             double cy = 0.0;
             for (int I = 0; I < S; ++I) cy += rec[2 + (I / nrow) * NR + (I % nrow)] * sy[lane * SMAX + I];
             rz -= cy;
+            // r.Br - (CBr).y cancels: a projected part at the rounding level of
+            // the sums cannot be resolved further (a homogeneous RVE under
+            // uniform traction starts there: its right side lies in the range of
+            // C^T), so the column counts as converged instead of iterating on noise
+            if (rz <= 1e-13 * fabs(rec[0])) rz = 0.0;
         }
         if (rz < 0.0) rz = 0.0;
         const bool was_active = !cs.done;

@@ -126,3 +126,29 @@ def test_batch_equals_single_calls():
         # independent CG solves stopped at rtol = 1e-12 (FP64 atomic sums vary in order
         # between runs): each within ~2 n rtol of the discrete solution
         assert rel(Cb[i], C[0]) < 1e-10 and rel(Kb[i], K[0]) < 1e-10 and rel(Db[i], D[0]) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+@pytest.mark.parametrize("bc", BCS)
+def test_homogeneous_lattice_rve_returns_its_material(bc, precision):
+    """Every tet matrix: the exact fluctuation is zero for every condition, so
+    C_bar, K_bar, D_bar are the matrix's own tensors (isotropic stiffness, k I,
+    D I) -- with uniform traction the right side lies entirely in the range of
+    the constraint rows, so the projected residual starts at rounding level."""
+    require_gpu()
+    from oracle import materials as M
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    coords, tets, phase, axis = generate_plain_weave(8, device="cuda")
+    phase = phase * 0
+    rec = ci.draw_params(13, 1)
+    r = RVE(coords, tets, phase, axis, ci.BASE_MATERIALS, bc=bc, precision=precision, rtol=1e-10, max_iter=20000)
+    C, K, D, rep = r.homogenise(rec)
+    r.close()
+    m, _, _ = M.phase_materials(ci.BASE_MATERIALS, rec[0])
+    Cm = M.isotropic_stiffness(m["E"], m["nu"])
+    e = (np.abs(C[0] - upper21(Cm)).max() / np.abs(Cm).max(),
+         np.abs(K[0] - m["k"] * np.array([1, 1, 1, 0, 0, 0])).max() / m["k"],
+         np.abs(D[0] - m["D"] * np.array([1, 1, 1, 0, 0, 0])).max() / m["D"])
+    banner(f"homogeneous 8^3 {bc} {precision}: errors {e}, status {rep[0]['status']}, CG steps {rep[0]['iters']}")
+    assert rep[0]["status"] == 0
+    assert max(e) <= 1e-9
