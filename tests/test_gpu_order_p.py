@@ -119,3 +119,27 @@ def test_distorted_mesh_matches_oracle(p, bc):
     banner(f"  errors C={eC:.2e} K={eK:.2e} D={eD:.2e}")
     assert rep[0]["status"] == 0
     assert max(eC, eK, eD) < 1e-9
+
+
+@pytest.mark.parametrize("p", [3, 4])
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic", "neumann"])
+def test_homogeneous_rve_returns_its_material_at_order_p(bc, p):
+    """Every tet matrix: the exact fluctuation is zero at any order and for every
+    condition, so the homogenised tensors are the matrix's own."""
+    require_gpu()
+    from oracle import materials as M
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    coords, tets, phase, axis = generate_plain_weave(4, device="cuda")
+    rec = ci.draw_params(14, 1)
+    r = RVE(coords, tets, phase * 0, axis, ci.BASE_MATERIALS, bc=bc, order=p, precision="fp32_refined",
+            rtol=1e-10, max_iter=20000)
+    C, K, D, rep = r.homogenise(rec)
+    r.close()
+    m, _, _ = M.phase_materials(ci.BASE_MATERIALS, rec[0])
+    Cm = M.isotropic_stiffness(m["E"], m["nu"])
+    e = (np.abs(C[0] - upper21(Cm)).max() / np.abs(Cm).max(),
+         np.abs(K[0] - m["k"] * np.array([1, 1, 1, 0, 0, 0])).max() / m["k"],
+         np.abs(D[0] - m["D"] * np.array([1, 1, 1, 0, 0, 0])).max() / m["D"])
+    banner(f"homogeneous 4^3 order {p} {bc}: errors {e}, status {rep[0]['status']}")
+    assert rep[0]["status"] == 0
+    assert max(e) <= 1e-9
