@@ -152,3 +152,27 @@ def test_homogeneous_lattice_rve_returns_its_material(bc, precision):
     banner(f"homogeneous 8^3 {bc} {precision}: errors {e}, status {rep[0]['status']}, CG steps {rep[0]['iters']}")
     assert rep[0]["status"] == 0
     assert max(e) <= 1e-9
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_scaled_and_shifted_box_gives_the_same_tensors(bc):
+    """Homogenisation does not see the RVE's size or position: the same weave on
+    the box [lo, lo + 2.5] gives the C_bar, K_bar, D_bar of the unit box."""
+    require_gpu()
+    import torch
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    coords, tets, phase, axis = generate_plain_weave(6, device="cuda")
+    lo = torch.tensor([1.0, -2.0, 0.5], dtype=coords.dtype, device=coords.device)
+    rec = ci.draw_params(15, 2)
+    out = []
+    for c, a, b in ((coords, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)),
+                    (lo + 2.5 * coords, tuple(lo.tolist()), tuple((lo + 2.5).tolist()))):
+        r = RVE(c.contiguous(), tets, phase, axis, ci.BASE_MATERIALS, bc=bc, lo=a, hi=b, precision="fp64",
+                rtol=1e-11, max_iter=20000)
+        C, K, D, rep = r.homogenise(rec)
+        r.close()
+        assert all(x["status"] == 0 for x in rep)
+        out.append(np.concatenate([C, K, D], axis=1))
+    e = float(np.abs(out[0] - out[1]).max() / np.abs(out[0]).max())
+    banner(f"scaled and shifted box, 6^3 {bc}: max rel diff {e:.1e}")
+    assert e <= 1e-9

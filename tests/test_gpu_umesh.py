@@ -143,3 +143,21 @@ def test_unstructured_rve_rejects_bad_meshes_and_options():
     with pytest.raises(L.ChomError) as ei:
         _urve(coords, t2, phase, axis, "dirichlet")
     assert ei.value.status == L.CHOM_EMESH
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic", "neumann"])
+def test_unstructured_scaled_and_shifted_box_gives_the_same_tensors(bc):
+    require_gpu()
+    coords, tets, phase, axis = _weave(3, seed=5)
+    lo = np.array([1.0, -2.0, 0.5])
+    rec = ci.draw_params(16, 2)
+    out = []
+    for c, a, b in ((coords, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)), (lo + 2.5 * coords, tuple(lo), tuple(lo + 2.5))):
+        u = _urve(c, tets, phase, axis, bc, lo=a, hi=b)
+        C, K, D, rep = u.homogenise(rec)
+        u.close()
+        assert all(x["status"] == 0 for x in rep)
+        out.append(np.concatenate([C, K, D], axis=1))
+    e = float(np.abs(out[0] - out[1]).max() / np.abs(out[0]).max())
+    banner(f"unstructured scaled and shifted box, {bc}: max rel diff {e:.1e}")
+    assert e <= 1e-9
