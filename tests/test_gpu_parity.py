@@ -11,7 +11,7 @@ import pytest
 import chom_inputs as ci
 from oracle import fem as ofem, mesh as omesh
 
-from gpu_util import banner, rel, require_gpu, upper21, upper6
+from gpu_util import banner, full3, full6, rel, require_gpu, upper21, upper6
 
 pytestmark = pytest.mark.gpu
 
@@ -176,3 +176,25 @@ def test_scaled_and_shifted_box_gives_the_same_tensors(bc):
     e = float(np.abs(out[0] - out[1]).max() / np.abs(out[0]).max())
     banner(f"scaled and shifted box, 6^3 {bc}: max rel diff {e:.1e}")
     assert e <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_boundary_conditions_bound_each_other(precision):
+    """Kinematic conditions stiffen, static ones soften: C_bar(linear Dirichlet) >=
+    C_bar(periodic) >= C_bar(uniform traction) in the Loewner order, and the same
+    for K_bar and D_bar (the minimum principles over nested admissible sets)."""
+    require_gpu()
+    rec = ci.draw_params(17, 2)
+    res = {}
+    for bc in BCS:
+        r = gpu_rve(6, bc, precision=precision, rtol=1e-10, max_iter=20000)
+        res[bc] = r.homogenise(rec)
+        r.close()
+    for i in range(len(rec)):
+        for k, full in ((0, full6), (1, full3), (2, full3)):
+            d, p, n = (full(res[bc][k][i]) for bc in BCS)
+            scale = np.abs(d).max()
+            lo1 = np.linalg.eigvalsh(d - p).min() / scale
+            lo2 = np.linalg.eigvalsh(p - n).min() / scale
+            banner(f"bounds record {i} tensor {k} {precision}: min eig D-P {lo1:.2e}, P-N {lo2:.2e}")
+            assert lo1 >= -1e-9 and lo2 >= -1e-9
