@@ -64,3 +64,17 @@ def result_errors(C21, K6, D6, refC21, refK6, refD6):
     for g, r in ((full6(C21), full6(refC21)), (full3(K6), full3(refK6)), (full3(D6), full3(refD6))):
         out = np.maximum(out, block_errors(g, r))
     return tuple(float(v) for v in out)
+
+
+def rotate_voigt(C, Q):
+    """C_bar (6x6 Voigt, [11, 22, 33, 12, 23, 31], engineering shear) of the
+    rotated material: C'_ijkl = Q_ip Q_jq Q_kr Q_ls C_pqrs."""
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (2, 0)]
+    T = np.zeros((3, 3, 3, 3))
+    for I, (i, j) in enumerate(pairs):
+        for J, (k, l) in enumerate(pairs):
+            for a, b in {(i, j), (j, i)}:
+                for c, d in {(k, l), (l, k)}:
+                    T[a, b, c, d] = C[I, J]
+    Tr = np.einsum("ip,jq,kr,ls,pqrs->ijkl", Q, Q, Q, Q, T)
+    return np.array([[Tr[i, j, k, l] for (k, l) in pairs] for (i, j) in pairs])

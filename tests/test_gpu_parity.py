@@ -229,3 +229,55 @@ def test_extreme_degradation():
     banner(f"(1 - omega) = 1e-8, 6^3 periodic: FP64 vs oracle {e64}, FP32 refined vs FP64 {e32}")
     assert e64[0] <= 1e-9 and e64[1] <= 1e-9 and e64[2] <= 1e-5
     assert max(e32) <= 1e-5
+
+
+def _permuted_lattice(coords, tets, phase, axis, n, perm):
+    """The lattice mesh with axis perm[d] renamed d, in the canonical vertex and
+    tet order: canonical vertex (i, j, k) takes the coordinates of the old
+    vertex at the position whose axis perm[d] coordinate is the new d one, and
+    each canonical tet takes the tags of the old tet on the same vertices."""
+    n1 = n + 1
+    idx = np.arange(n1 ** 3)
+    pos = np.stack([idx % n1, (idx // n1) % n1, idx // (n1 * n1)], axis=1)   # new (i, j, k)
+    old = np.zeros_like(pos)
+    old[:, perm] = pos                                                       # old position
+    vold = old[:, 0] + n1 * (old[:, 1] + n1 * old[:, 2])
+    new_coords = coords[vold][:, perm]
+    lookup = {tuple(sorted(t)): e for e, t in enumerate(tets.tolist())}
+    src = np.array([lookup[tuple(sorted(vold[t]))] for t in tets.tolist()])
+    return new_coords, tets, phase[src], axis[src][:, perm]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32_refined", 1e-7)])
+@pytest.mark.parametrize("bc", BCS)
+def test_permuted_axes_give_the_permuted_tensors(bc, precision, tol):
+    """The lattice weave with its axes renamed, (x, y, z) -> (y, z, x) (the
+    Kuhn split is invariant under axis permutations, so it stays a lattice),
+    fibre axes renamed with it: C_bar, K_bar, D_bar transform as tensors --
+    each axis's tiles, strides and stress-law terms enter differently."""
+    require_gpu()
+    import torch
+    from gpu_util import full3, full6, rotate_voigt
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    n = 6
+    coords, tets, phase, axis = (x.cpu().numpy() for x in generate_plain_weave(n, device="cuda"))
+    perm = [1, 2, 0]
+    Q = np.eye(3)[perm]
+    rec = ci.draw_params(19, 2)
+    res = []
+    for mesh in ((coords, tets, phase, axis), _permuted_lattice(coords, tets, phase, axis, n, perm)):
+        dev = [torch.as_tensor(np.ascontiguousarray(x), device="cuda") for x in mesh]
+        r = RVE(*dev, ci.BASE_MATERIALS, bc=bc, precision=precision, rtol=1e-11 if precision == "fp64" else 1e-9,
+                max_iter=20000)
+        res.append(r.homogenise(rec))
+        r.close()
+    (C, K, D, _), (Cp, Kp, Dp, _) = res
+    err = 0.0
+    for i in range(len(rec)):
+        exp_c = rotate_voigt(full6(C[i]), Q)
+        err = max(err, np.abs(full6(Cp[i]) - exp_c).max() / np.abs(exp_c).max())
+        for got, ref in ((Kp[i], K[i]), (Dp[i], D[i])):
+            e3 = Q @ full3(ref) @ Q.T
+            err = max(err, np.abs(full3(got) - e3).max() / np.abs(e3).max())
+    banner(f"permuted axes 6^3 {bc} {precision}: max rel diff {err:.1e}")
+    assert err <= tol

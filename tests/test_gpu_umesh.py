@@ -163,27 +163,13 @@ def test_unstructured_scaled_and_shifted_box_gives_the_same_tensors(bc):
     assert e <= 1e-9
 
 
-def _rotate_voigt(C, Q):
-    """C_bar (6x6 Voigt, [11, 22, 33, 12, 23, 31], engineering shear) of the
-    rotated material: C'_ijkl = Q_ip Q_jq Q_kr Q_ls C_pqrs."""
-    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (1, 2), (2, 0)]
-    T = np.zeros((3, 3, 3, 3))
-    for I, (i, j) in enumerate(pairs):
-        for J, (k, l) in enumerate(pairs):
-            for a, b in {(i, j), (j, i)}:
-                for c, d in {(k, l), (l, k)}:
-                    T[a, b, c, d] = C[I, J]
-    Tr = np.einsum("ip,jq,kr,ls,pqrs->ijkl", Q, Q, Q, Q, T)
-    return np.array([[Tr[i, j, k, l] for (k, l) in pairs] for (i, j) in pairs])
-
-
 @pytest.mark.parametrize("bc", ["dirichlet", "periodic", "neumann"])
 def test_rotated_mesh_gives_the_rotated_tensors(bc):
     """The same weave turned a quarter turn about z, (x, y, z) -> (1 - y, x, z),
     fibre axes turned with it: C_bar, K_bar, D_bar turn as tensors (the Voigt
     and shear conventions of the stress law and the averages enter here)."""
     require_gpu()
-    from gpu_util import full3, full6
+    from gpu_util import full3, full6, rotate_voigt
     coords, tets, phase, axis = _weave(3, seed=5)
     Q = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
     rc = coords @ Q.T + np.array([1.0, 0.0, 0.0])
@@ -197,7 +183,7 @@ def test_rotated_mesh_gives_the_rotated_tensors(bc):
     u.close()
     err = 0.0
     for i in range(len(rec)):
-        exp_c = _rotate_voigt(full6(C[i]), Q)
+        exp_c = rotate_voigt(full6(C[i]), Q)
         err = max(err, np.abs(full6(Cr[i]) - exp_c).max() / np.abs(exp_c).max())
         for got, ref in ((Kr[i], K[i]), (Dr[i], D[i])):
             e3 = Q @ full3(ref) @ Q.T
