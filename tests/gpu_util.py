@@ -1,4 +1,4 @@
-"""Helpers shared by the GPU tests (no arithmetic of the method here)."""
+"""Helpers shared by the tests (no arithmetic of the method here)."""
 import numpy as np
 import pytest
 
@@ -78,3 +78,20 @@ def rotate_voigt(C, Q):
                     T[a, b, c, d] = C[I, J]
     Tr = np.einsum("ip,jq,kr,ls,pqrs->ijkl", Q, Q, Q, Q, T)
     return np.array([[Tr[i, j, k, l] for (k, l) in pairs] for (i, j) in pairs])
+
+
+def permuted_lattice(coords, tets, phase, axis, n, perm):
+    """The lattice mesh with axis perm[d] renamed d, in the canonical vertex and
+    tet order: canonical vertex (i, j, k) takes the coordinates of the old
+    vertex at the position whose axis perm[d] coordinate is the new d one, and
+    each canonical tet takes the tags of the old tet on the same vertices."""
+    n1 = n + 1
+    idx = np.arange(n1 ** 3)
+    pos = np.stack([idx % n1, (idx // n1) % n1, idx // (n1 * n1)], axis=1)   # new (i, j, k)
+    old = np.zeros_like(pos)
+    old[:, perm] = pos                                                       # old position
+    vold = old[:, 0] + n1 * (old[:, 1] + n1 * old[:, 2])
+    new_coords = coords[vold][:, perm]
+    lookup = {tuple(sorted(t)): e for e, t in enumerate(tets.tolist())}
+    src = np.array([lookup[tuple(sorted(vold[t]))] for t in tets.tolist()])
+    return new_coords, tets, phase[src], axis[src][:, perm]

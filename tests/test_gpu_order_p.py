@@ -143,3 +143,33 @@ def test_homogeneous_rve_returns_its_material_at_order_p(bc, p):
     banner(f"homogeneous 4^3 order {p} {bc}: errors {e}, status {rep[0]['status']}")
     assert rep[0]["status"] == 0
     assert max(e) <= 1e-9
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_permuted_axes_give_the_permuted_tensors_at_order_p(p):
+    """Orders 3 and 4 (element factors per tet type, basis tables, matrix-core
+    products): renamed axes (x, y, z) -> (y, z, x) give the permuted tensors."""
+    require_gpu()
+    import torch
+    from gpu_util import full3, full6, permuted_lattice, rotate_voigt
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    n = 4
+    coords, tets, phase, axis = (x.cpu().numpy() for x in generate_plain_weave(n, device="cuda"))
+    perm = [1, 2, 0]
+    Q = np.eye(3)[perm]
+    rec = ci.draw_params(20, 1)
+    res = []
+    for mesh in ((coords, tets, phase, axis), permuted_lattice(coords, tets, phase, axis, n, perm)):
+        dev = [torch.as_tensor(np.ascontiguousarray(x), device="cuda") for x in mesh]
+        r = RVE(*dev, ci.BASE_MATERIALS, bc="periodic", order=p, precision="fp32_refined", rtol=1e-9,
+                max_iter=20000)
+        res.append(r.homogenise(rec))
+        r.close()
+    (C, K, D, _), (Cp, Kp, Dp, _) = res
+    exp_c = rotate_voigt(full6(C[0]), Q)
+    err = np.abs(full6(Cp[0]) - exp_c).max() / np.abs(exp_c).max()
+    for got, ref in ((Kp[0], K[0]), (Dp[0], D[0])):
+        e3 = Q @ full3(ref) @ Q.T
+        err = max(err, np.abs(full3(got) - e3).max() / np.abs(e3).max())
+    banner(f"permuted axes 4^3 order {p}: max rel diff {err:.1e}")
+    assert err <= 1e-7

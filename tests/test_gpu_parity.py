@@ -231,23 +231,6 @@ def test_extreme_degradation():
     assert max(e32) <= 1e-5
 
 
-def _permuted_lattice(coords, tets, phase, axis, n, perm):
-    """The lattice mesh with axis perm[d] renamed d, in the canonical vertex and
-    tet order: canonical vertex (i, j, k) takes the coordinates of the old
-    vertex at the position whose axis perm[d] coordinate is the new d one, and
-    each canonical tet takes the tags of the old tet on the same vertices."""
-    n1 = n + 1
-    idx = np.arange(n1 ** 3)
-    pos = np.stack([idx % n1, (idx // n1) % n1, idx // (n1 * n1)], axis=1)   # new (i, j, k)
-    old = np.zeros_like(pos)
-    old[:, perm] = pos                                                       # old position
-    vold = old[:, 0] + n1 * (old[:, 1] + n1 * old[:, 2])
-    new_coords = coords[vold][:, perm]
-    lookup = {tuple(sorted(t)): e for e, t in enumerate(tets.tolist())}
-    src = np.array([lookup[tuple(sorted(vold[t]))] for t in tets.tolist()])
-    return new_coords, tets, phase[src], axis[src][:, perm]
-
-
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32_refined", 1e-7)])
 @pytest.mark.parametrize("bc", BCS)
 def test_permuted_axes_give_the_permuted_tensors(bc, precision, tol):
@@ -257,7 +240,7 @@ def test_permuted_axes_give_the_permuted_tensors(bc, precision, tol):
     each axis's tiles, strides and stress-law terms enter differently."""
     require_gpu()
     import torch
-    from gpu_util import full3, full6, rotate_voigt
+    from gpu_util import full3, full6, permuted_lattice, rotate_voigt
     from paper_1610_03484_amd import RVE, generate_plain_weave
     n = 6
     coords, tets, phase, axis = (x.cpu().numpy() for x in generate_plain_weave(n, device="cuda"))
@@ -265,7 +248,7 @@ def test_permuted_axes_give_the_permuted_tensors(bc, precision, tol):
     Q = np.eye(3)[perm]
     rec = ci.draw_params(19, 2)
     res = []
-    for mesh in ((coords, tets, phase, axis), _permuted_lattice(coords, tets, phase, axis, n, perm)):
+    for mesh in ((coords, tets, phase, axis), permuted_lattice(coords, tets, phase, axis, n, perm)):
         dev = [torch.as_tensor(np.ascontiguousarray(x), device="cuda") for x in mesh]
         r = RVE(*dev, ci.BASE_MATERIALS, bc=bc, precision=precision, rtol=1e-11 if precision == "fp64" else 1e-9,
                 max_iter=20000)

@@ -262,3 +262,26 @@ def test_nested_dissection_is_a_permutation():
     E2 = sp.csr_matrix((np.ones(T * nn), (np.repeat(np.arange(T), nn), disc.e2n.ravel())), shape=(T, N))
     order = fem.nested_dissection(disc.nodes, (E2.T @ E2).tocsr(), leaf=8)
     np.testing.assert_array_equal(np.sort(order), np.arange(N))
+
+
+@pytest.mark.parametrize("bc", [fem.BC_PERIODIC, fem.BC_NEUMANN])
+def test_permuted_axes_give_the_permuted_tensors(bc):
+    """Renaming the axes (x, y, z) -> (y, z, x) of the lattice weave (tags and
+    fibre axes with it) turns C_bar, K_bar, D_bar as tensors: pins the Voigt
+    order, the engineering shear and the rotated transversely isotropic law
+    against a transposed or mislabelled index anywhere in them."""
+    from gpu_util import permuted_lattice, rotate_voigt
+    n = 4
+    c, t, ph, ax = mesh.plain_weave(n)
+    c, t, ph, ax = (np.asarray(v) for v in (c, t, ph, ax))
+    perm = [1, 2, 0]
+    Q = np.eye(3)[perm]
+    prm = np.r_[45.0, 1.0, 3.0, np.ones(8)]
+    a = fem.homogenise(c, t, ph, ax, 2, bc, ci.BASE_MATERIALS, prm)
+    b = fem.homogenise(*permuted_lattice(c, t, ph, ax, n, perm), 2, bc, ci.BASE_MATERIALS, prm)
+    rc = rotate_voigt(a["C"], Q)
+    assert np.abs(b["C"] - rc).max() <= 1e-12 * np.abs(rc).max()
+    for k in ("K", "D"):
+        r3 = Q @ a[k] @ Q.T
+        assert np.abs(b[k] - r3).max() <= 1e-12 * np.abs(r3).max()
+    assert np.abs(rc - a["C"]).max() > 1e-2 * np.abs(rc).max()   # the weave is not symmetric under it
