@@ -93,3 +93,36 @@ def test_caller_stream_gives_the_same_results():
             float(np.abs(Da - Db).max() / np.abs(Da).max()))
     banner(f"caller's stream vs the library's own: max rel diff {e:.1e}")
     assert e <= 1e-12
+
+
+def test_general_mesh_device_pointers_equal_host_pointers():
+    require_gpu()
+    import torch
+    from paper_1610_03484_amd import URVE, _lib as L
+    from oracle import mesh as om
+    coords, tets = ci.unstructured_box(3, seed=5)
+    c = om.centroids(coords, tets)
+    phase, axis = om.yarn_test(c[:, 0], c[:, 1], c[:, 2])
+    params = ci.draw_params(25, 2)
+    host = URVE(coords, tets, phase, axis, ci.BASE_MATERIALS, bc="neumann", rtol=1e-10, max_iter=20000)
+    Ch, Kh, Dh, _ = host.homogenise(params)
+    host.close()
+    dev = URVE(coords, tets, phase, axis, ci.BASE_MATERIALS, bc="neumann", rtol=1e-10, max_iter=20000,
+               device_ptrs=1)
+    B = len(params)
+    p = torch.as_tensor(np.ascontiguousarray(params), dtype=torch.float64, device="cuda")
+    C = torch.full((B, 21), float("nan"), dtype=torch.float64, device="cuda")
+    K = torch.full((B, 6), float("nan"), dtype=torch.float64, device="cuda")
+    D = torch.full((B, 6), float("nan"), dtype=torch.float64, device="cuda")
+    reps = (L.ChomReport * B)()
+    torch.cuda.synchronize()
+    st = L.lib().chom_urve_homogenise(dev._h, ct.c_void_p(p.data_ptr()), B, ct.c_void_p(C.data_ptr()),
+                                      ct.c_void_p(K.data_ptr()), ct.c_void_p(D.data_ptr()), reps)
+    torch.cuda.synchronize()
+    dev.close()
+    L.check(st, "chom_urve_homogenise")
+    e = max(float(np.abs(C.cpu().numpy() - Ch).max() / np.abs(Ch).max()),
+            float(np.abs(K.cpu().numpy() - Kh).max() / np.abs(Kh).max()),
+            float(np.abs(D.cpu().numpy() - Dh).max() / np.abs(Dh).max()))
+    banner(f"general mesh, device pointers vs host pointers: max rel diff {e:.1e}")
+    assert e <= 1e-12
