@@ -1384,10 +1384,23 @@ __global__ __launch_bounds__(256) void mg_gram_finish_kernel(const Geo *geos, co
         ginv[(long long)prob * SMAX * SMAX + t] = ok_s ? A[t / S][S + t % S] : 0.0;
 }
 
-// Load cases per lane in the level-1 kernels: three where they divide the
-// cases (fewer waves reload each stencil block; mechanics 6 cases: 475 -> 477
-// homogenisations/s on the mixed batch against two).
-template <int R> constexpr int MG_KG = R % 3 == 0 ? 3 : (R % 2 == 0 ? 2 : 1);
+// Load cases per lane in the level-1 kernels: for launches over many problems
+// three where they divide the cases (fewer waves reload each stencil block;
+// mechanics 6 cases: 475 -> 477 homogenisations/s on the 512-record mixed
+// batch against two), for a few problems two (more waves per problem: the
+// three-problem 24^3 batch 192 -> 197/s against three).
+template <int R> constexpr int MG_KG_MANY = R % 3 == 0 ? 3 : (R % 2 == 0 ? 2 : 1);
+template <int R> constexpr int MG_KG_FEW = R % 2 == 0 ? 2 : (R % 3 == 0 ? 3 : 1);
+constexpr int MG_MANY_PROBLEMS = 16;
+
+// Calls f with std::integral_constant<int, KG> for the launch's problem count.
+template <int R, typename F>
+static void with_mg_kg(int nprob, F &&f) {
+    if (nprob >= MG_MANY_PROBLEMS)
+        f(std::integral_constant<int, MG_KG_MANY<R>>{});
+    else
+        f(std::integral_constant<int, MG_KG_FEW<R>>{});
+}
 
 #define CHOM_MG_NR_DISPATCH(NRV, CALL)                 \
     switch (NRV) {                                     \
@@ -1432,9 +1445,11 @@ hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *accbuf, const i
     Q.x = (T *)M.x;
     Q.rows1 = M.rows1;
     const dim3 g1(M.nwg[1], L.nprob);
-    constexpr int KG = MG_KG<R>;
-    mg_restrict01_kernel<T, C, R, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q, prob_active);
-    mg_resid1_kernel<T, C, R, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q, prob_active);
+    with_mg_kg<R>(L.nprob, [&](auto kg) {
+        constexpr int KG = decltype(kg)::value;
+        mg_restrict01_kernel<T, C, R, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q, prob_active);
+        mg_resid1_kernel<T, C, R, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q, prob_active);
+    });
     if constexpr (std::is_same<T, float>::value) {
         if (M.small_elems > 0) {
             // thread t owns point t of the level-1 (coarsest) or level-2 grid: 256 threads
@@ -1454,9 +1469,12 @@ hipError_t launch_mg_vcycle(const Launch &L, const T *r, double *accbuf, const i
         mg_fused_kernel<T, C, R><<<dim3(R, L.nprob), MG_FUSED_BS, (size_t)M.lds_elems * sizeof(T), s>>>(
             L.geos, L.probs, Q, M.sweeps, M.lds_vec, M.lds_sten, prob_active);
     }
-    mg_correct1_kernel<T, C, R, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q, prob_active);
-    CHOM_MG_NR_DISPATCH(L.nr, (mg_post1_kernel<T, C, R, NR, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q,
-                                                                                             accbuf, prob_active)));
+    with_mg_kg<R>(L.nprob, [&](auto kg) {
+        constexpr int KG = decltype(kg)::value;
+        mg_correct1_kernel<T, C, R, KG><<<g1, 64 * (R / KG), 0, s>>>(L.geos, L.probs, Q, prob_active);
+        CHOM_MG_NR_DISPATCH(L.nr, (mg_post1_kernel<T, C, R, NR, KG><<<g1, 64 * (R / KG), 0, s>>>(
+                                      L.geos, L.probs, Q, accbuf, prob_active)));
+    });
     return hipGetLastError();
 }
 
@@ -1472,9 +1490,11 @@ hipError_t launch_mg_fcorr(const Launch &L, const double *ycoef, const int *prob
     Q.res = (T *)M.res;
     Q.x = (T *)M.x;
     Q.rows1 = M.rows1;
-    constexpr int KG = MG_KG<R>;
-    CHOM_MG_NR_DISPATCH(L.nr, (mg_fcorr_kernel<T, C, R, NR, KG><<<dim3(M.nwg[1], L.nprob), 64 * (R / KG), 0, s>>>(
-                                  L.geos, L.probs, Q, (const T *)M.W, ycoef, prob_active)));
+    with_mg_kg<R>(L.nprob, [&](auto kg) {
+        constexpr int KG = decltype(kg)::value;
+        CHOM_MG_NR_DISPATCH(L.nr, (mg_fcorr_kernel<T, C, R, NR, KG><<<dim3(M.nwg[1], L.nprob), 64 * (R / KG), 0, s>>>(
+                                      L.geos, L.probs, Q, (const T *)M.W, ycoef, prob_active)));
+    });
     return hipGetLastError();
 }
 
