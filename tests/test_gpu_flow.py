@@ -102,3 +102,18 @@ def test_potential_flow_directions_drive_the_rve_solve():
     banner(f"  errors against the oracle {e}")
     assert rep[0]["status"] == 0
     assert max(e) <= 1e-9
+
+
+def test_directions_ignore_the_box_size_and_position():
+    """The potential of each yarn is fixed by its end faces, so scaling and
+    shifting the box leaves every unit direction unchanged."""
+    torch = require_gpu()
+    from paper_1610_03484_amd import generate_plain_weave, yarn_directions
+    coords, tets, phase, _ = generate_plain_weave(8, device="cuda")
+    a = yarn_directions(coords, tets, phase, AXES, rtol=1e-13).cpu().numpy()
+    lo = torch.tensor([2.0, -1.0, 0.5], dtype=coords.dtype, device=coords.device)
+    b = yarn_directions((lo + 3.0 * coords).contiguous(), tets, phase, AXES, rtol=1e-13,
+                        lo=tuple(lo.tolist()), hi=tuple((lo + 3.0).tolist())).cpu().numpy()
+    err = float(np.abs(a - b).max())
+    banner(f"directions on a scaled and shifted box: max difference {err:.1e}")
+    assert err <= 1e-9
