@@ -210,3 +210,22 @@ def test_fe2_rejects_bad_arguments():
     g = fe2_run(rve, **dict(CASE, steps=1))
     assert np.isfinite(g["reaction"]).all()
     rve.close()
+
+
+def test_reaction_is_linear_in_the_applied_strain():
+    """The macro problem is linear elasticity at the step's damage, and the
+    damage does not depend on the load: doubling the prescribed strain doubles
+    the reaction and the displacement and leaves T, c, (1 - omega) and C_bar
+    unchanged (to the run-to-run rounding of atomic sums)."""
+    require_gpu()
+    from paper_1610_03484_amd import fe2_run
+    rve, _ = _rve_pair()
+    a = fe2_run(rve, macro_rtol=1e-13, **CASE)
+    b = fe2_run(rve, macro_rtol=1e-13, **dict(CASE, strain_x=2 * CASE["strain_x"]))
+    rve.close()
+    eR = np.abs(b["reaction"] / (2 * a["reaction"]) - 1.0).max()
+    eu = np.abs(b["u"] - 2 * a["u"]).max() / np.abs(2 * a["u"]).max()
+    banner(f"FE^2 strain doubled: reaction {eR:.1e}, displacement {eu:.1e}")
+    assert eR <= 1e-9 and eu <= 1e-9
+    for k in ("T", "c", "keep", "C_bar"):   # equal up to the order of the solvers' FP64 atomic sums
+        assert np.abs(a[k] - b[k]).max() <= 1e-12 * np.abs(a[k]).max(), k
