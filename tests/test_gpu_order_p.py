@@ -173,3 +173,27 @@ def test_permuted_axes_give_the_permuted_tensors_at_order_p(p):
         err = max(err, np.abs(full3(got) - e3).max() / np.abs(e3).max())
     banner(f"permuted axes 4^3 order {p}: max rel diff {err:.1e}")
     assert err <= 1e-7
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_scaled_and_shifted_box_at_order_p(p):
+    """Element factors and basis tables see the tet sizes: the weave on
+    [lo, lo + 2.5] gives the tensors of the unit box at orders 3 and 4."""
+    require_gpu()
+    import torch
+    from paper_1610_03484_amd import RVE, generate_plain_weave
+    coords, tets, phase, axis = generate_plain_weave(4, device="cuda")
+    lo = torch.tensor([1.0, -2.0, 0.5], dtype=coords.dtype, device=coords.device)
+    rec = ci.draw_params(26, 1)
+    out = []
+    for c, a, b in ((coords, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)),
+                    ((lo + 2.5 * coords).contiguous(), tuple(lo.tolist()), tuple((lo + 2.5).tolist()))):
+        r = RVE(c, tets, phase, axis, ci.BASE_MATERIALS, bc="neumann", order=p, lo=a, hi=b,
+                precision="fp64", rtol=1e-11, max_iter=20000)
+        C, K, D, rep = r.homogenise(rec)
+        r.close()
+        assert rep[0]["status"] == 0
+        out.append(np.concatenate([C, K, D], axis=1))
+    e = float(np.abs(out[0] - out[1]).max() / np.abs(out[0]).max())
+    banner(f"scaled and shifted box, 4^3 order {p} neumann: max rel diff {e:.1e}")
+    assert e <= 1e-9
