@@ -93,3 +93,19 @@ def test_two_level_mixed_batch_fp32_refined():
         assert e <= 1e-8
     for r in rves:
         r.close()
+
+
+def test_fp32_small_grid_kernel_with_512_threads():
+    """24^3 linear Dirichlet keeps 7^3 = 343 points on its level-2 grid, more than
+    256, so the FP32 small-grid coarse kernel runs 512 threads (the periodic
+    benchmark records all fit 256); the two-level FP32-refined solve equals the
+    FP64 block-Jacobi one to the solver tolerance."""
+    require_gpu()
+    p = ci.draw_params(27, 1)
+    a, ra = _solve(24, "dirichlet", "two_level", precision="fp32_refined", rtol=1e-10, params=p)
+    b, rb = _solve(24, "dirichlet", "block_jacobi", precision="fp64", rtol=1e-10, params=p)
+    e = _rel(a, b)
+    banner(f"24^3 Dirichlet, FP32 two-level (512-thread coarse kernel) vs FP64 block Jacobi: {e:.1e}, "
+           f"steps {max(ra[0]['iters'])} vs {max(rb[0]['iters'])}")
+    assert ra[0]["status"] == 0 and rb[0]["status"] == 0
+    assert e <= 1e-8
