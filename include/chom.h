@@ -125,7 +125,11 @@ typedef struct {
                               CG steps and kept within [1e-6, 1] x the linear-field
                               energy x_lin^T K x_lin.  Relative to E, the energy-form
                               averages are accurate against the homogenised value itself,
-                              also in the soft directions of a degraded matrix         */
+                              also in the soft directions of a degraded matrix: at rtol
+                              3e-5 the energy-weighted error of C_bar is 8e-9 at
+                              (1 - omega) = 1e-3 and 8e-8 at 1e-6, but 0.1 at 1e-8,
+                              where the yarn/matrix contrast needs a tighter rtol
+                              (1e-6 gives 6e-7)                                          */
     double inner_rtol;     /* FP32 inner solves: stop when r.B r falls below
                               inner_rtol^2 times the smaller of its initial value and E */
     double c_sat;          /* moisture content (wt%) with gamma = 1                    */
@@ -147,7 +151,8 @@ typedef struct {
     int32_t refine_steps[3];  /* refinement steps (mech, thermal, moisture)                 */
     int32_t status;           /* CHOM_OK or CHOM_ENOCONV                                    */
     double resid[12];         /* final sqrt(r.P r / linear-field energy) per load case (P as
-                                 for chom_options.rtol)                                      */
+                                 for chom_options.rtol; 0 when the projected r.P r fell to
+                                 the rounding level of the unprojected one)                  */
     double asym;              /* ||C - C^T||_F / ||C||_F of the unsymmetrised C_bar           */
     double omega_keep;        /* (1 - omega) applied to the matrix modulus                   */
     int32_t fail[12];         /* CHOM_FAIL_* per load case                                   */
