@@ -1312,10 +1312,14 @@ static int batch_homogenise(chom_batch *B, const chom_params *params, double *C_
         // overrides both).  Measured on the mixed batch: 416 -> 459
         // homogenisations/s, the undegraded 24^3 batch unchanged; thresholds 10 to
         // 100 and 32 to 64 sweeps within 0.5%.
-        if (!sweeps_env) {
-            const double ratio = m10[6] / std::max(m10[1], 1e-300);
-            pm[i].mg_sweeps = ratio > 10.0 ? 32 : 0;
-        }
+        const double ratio = m10[6] / std::max(m10[1], 1e-300);
+        if (!sweeps_env) pm[i].mg_sweeps = ratio > 10.0 ? 32 : 0;
+        // The per-column energy test bounds each column's error, not C_bar's softest
+        // directions, whose share of a stiff column's energy falls with the
+        // yarn/matrix contrast: past a shear-modulus ratio of 3e4 ((1 - omega) below
+        // about 1e-4) the mechanical stopping tests tighten rtol^2 by 3e4 / ratio
+        // (the benchmark's records stay below that ratio and are untouched).
+        pm[i].rtol2_scale = ratio > 3e4 ? 3e4 / ratio : 1.0;
     }
     if (!B->tuned && std::getenv("CHOM_AUTOTUNE")) {
         CHOM_TRY((autotune_class<3, 6>(B, B->mech, pm, tune_key(B, 0), &B->rg_mech, &B->nwg_mech)));

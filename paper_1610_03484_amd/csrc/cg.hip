@@ -577,7 +577,8 @@ __global__ __launch_bounds__(512) void finish_beta_kernel(const Geo *geos, const
         if (!(en > 0.0)) en = cs.eref;
         en = fmin(fmax(en, 1e-6 * cs.eref), cs.eref);
         const double ref = use_init ? fmin(cs.rz_init, en) : en;
-        double tol2 = rtol2;
+        const double rs = probs[prob].rtol2_scale;
+        double tol2 = rs > 0.0 ? rtol2 * rs : rtol2;
         if (use_init && loose > 0.0) {
             const double t = fmin(loose * cs.eref / en, 0.05);
             tol2 = fmax(tol2, t * t);

@@ -100,6 +100,7 @@ struct Prob {
     long long moff;       // offset of its coarse-hierarchy points (two-level preconditioner)
     int geo;              // index of its RVE geometry
     int mg_sweeps;        // coarsest-level sweeps of the two-level preconditioner (0: the class's count)
+    double rtol2_scale;   // factor on every rtol^2 of the problem's stopping tests (0: 1)
 };
 
 // First constraint row used by a BC: periodic uses only int(phi) (row 3).
