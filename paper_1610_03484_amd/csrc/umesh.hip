@@ -72,6 +72,7 @@ struct UMat {
 // Per load case state of the PCG.
 struct UCol {
     double rz, rz_new, pq, alpha, beta, eref, energy;
+    double tol_scale;   // factor on rtol^2 for this column (0: 1)
     int done, iters;
 };
 
@@ -477,6 +478,7 @@ __global__ __launch_bounds__(UB) void ucg_finish_kernel(int ncol, int phase, dou
         acc[2 * lc] = 0.0;
         cs.energy = cs.eref;
         cs.iters = 0;
+        if (cs.tol_scale > 0.0) rtol2 *= cs.tol_scale;
         cs.done = (cs.rz <= rtol2 * cs.eref || !(cs.eref > 0.0)) ? 1 : 0;
         if (!isfinite(cs.rz)) cs.done = 3;
         active[lc] = cs.done ? 0 : 1;
@@ -507,7 +509,7 @@ __global__ __launch_bounds__(UB) void ucg_finish_kernel(int ncol, int phase, dou
     cs.beta = rzn / cs.rz;
     cs.rz = rzn;
     if (!isfinite(rzn)) cs.done = 3;
-    else if (rzn <= rtol2 * en) cs.done = 1;
+    else if (rzn <= (cs.tol_scale > 0.0 ? rtol2 * cs.tol_scale : rtol2) * en) cs.done = 1;
     else if (cs.iters >= max_iter) cs.done = 4;
     active[lc] = cs.done ? 0 : 1;
 }
@@ -669,6 +671,17 @@ int usolve(chom_urve *U, const UMat *hmats, int nb, double rtol, int max_iter, d
     for (int k = 0; k < ncol; ++k) {
         std::memset(&hc[k], 0, sizeof(UCol));
         hc[k].eref = heref[k];
+        // The per-column energy test bounds each column's error, not C_bar's softest
+        // directions, whose share of a stiff column's energy falls with the
+        // yarn/matrix contrast: the mechanical columns use rtol^2 x 100 / ratio past
+        // a shear-modulus ratio of 100.  (This FP64 CG stops right at its test; the
+        // lattice path's refined FP32 passes overshoot theirs, so it starts at 3e4.)
+        // (1 - omega) = 1e-8 at rtol 3e-5: energy-weighted error 2.4e-4 with the
+        // lattice threshold, 1.9e-6 with this one (the 8,748-tet periodic mesh: 10.8 -> 11.3 ms).
+        if constexpr (C == 3) {
+            const double ratio = hmats[k / R].m[1][1] / std::max(hmats[k / R].m[0][1], 1e-300);
+            hc[k].tol_scale = ratio > 100.0 ? 100.0 / ratio : 1.0;
+        }
     }
     CHOM_HIP(hipMemcpyAsync(cols.p, hc.data(), sizeof(UCol) * ncol, hipMemcpyHostToDevice, s));
     const dim3 gv(grid_of(ns), ncol);

@@ -190,3 +190,25 @@ def test_rotated_mesh_gives_the_rotated_tensors(bc):
             err = max(err, np.abs(full3(got) - e3).max() / np.abs(e3).max())
     banner(f"unstructured quarter turn, {bc}: max rel diff {err:.1e}")
     assert err <= 1e-9
+
+
+def test_unstructured_extreme_degradation_at_the_default_tolerance():
+    """(1 - omega) = 1e-8: the contrast rule tightens the mechanical stopping
+    test, so rtol 3e-5 still gives C_bar's soft directions (energy-weighted
+    error against rtol 1e-13 within 1e-5; without the rule about 0.1)."""
+    require_gpu()
+    from gpu_util import result_errors
+    coords, tets, phase, axis = _weave(3, seed=5)
+    ty = -np.log(1e-8) / (M.alpha_of_T(60.0) * M.DAYS_PER_YEAR)
+    prm = np.r_[60.0, 1.5, ty, np.ones(8)][None]
+    out = []
+    from paper_1610_03484_amd import URVE
+    for rt in (1e-13, 3e-5):
+        u = URVE(coords, tets, phase, axis, ci.BASE_MATERIALS, bc="periodic", rtol=rt, max_iter=50000)
+        C, K, D, rep = u.homogenise(prm)
+        u.close()
+        assert rep[0]["status"] == 0
+        out.append((C[0], K[0], D[0]))
+    e = result_errors(*out[1], *out[0])
+    banner(f"unstructured (1 - omega) = 1e-8 at rtol 3e-5 vs 1e-13: errors {e}")
+    assert max(e) <= 1e-5
